@@ -1,0 +1,322 @@
+"""Plain FP64 CPU oracle for the QTT matrix-by-full-vector product.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path imports this module:
+only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may call it.  It shares no code with the HIP library.
+
+Every function is written for a reader holding the paper
+(Corona, Rahimian, Zorin, "A Tensor-Train accelerated solver for integral
+equations in complex geometries", arXiv:1511.06029):
+
+* index convention -- section 2.1 (Nomenclature): multi-indices are flattened
+  in Matlab order, so ``i = i_1 + m_1*(i_2 + m_2*(i_3 + ...))``; the first
+  index is the fastest.  Core 1 is the finest tree level (section 2.3,
+  hierarchical tensorization: levels are numbered from the finest).
+* TT format -- section 2.2, Definition of the TT decomposition (eq. TTdeccores),
+  with dummy ranks r_0 = r_d = 1.
+* QTT matrix over the product tree -- section 3 (tensorized matrix
+  A_T(b_1..b_d) with b_k = (i_k, j_k)); a core is G_k(a_{k-1}, i_k, j_k, a_k).
+* matrix by full vector -- section 4.2, Algorithm 2 (alg:TT-matvec).
+* TT-SVD -- section 2.2, Algorithm 1 (alg:TT-dec).
+
+Array conventions used throughout: a QTT matrix is a list of FP64 numpy arrays
+``cores[k]`` of shape ``(r_{k-1}, m_k, n_k, r_k)``; a block of vectors is an
+``(N, K)`` array whose columns are the right-hand sides.
+
+Everything is FP64.  Reshapes that the paper writes in Matlab notation use
+``order='F'`` so that they read the same way.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+__all__ = [
+    "qtt_shapes", "qtt_entry", "qtt_to_dense", "qtt_apply_alg2",
+    "alg2_flops", "tt_svd", "qtt_matrix_from_dense", "morton_points",
+    "volume_self_term", "volume_matrix", "volume_apply_direct",
+    "richardson_solve",
+]
+
+
+# --------------------------------------------------------------------------
+# shapes and the plain definition
+# --------------------------------------------------------------------------
+
+def qtt_shapes(cores):
+    """Return (ranks, m, n) of a QTT matrix, checking r_0 = r_d = 1 and that
+    neighbouring cores agree on their shared rank (TT definition, sec. 2.2)."""
+    d = len(cores)
+    if d < 1:
+        raise ValueError("a QTT matrix needs at least one core")
+    ranks = [int(cores[0].shape[0])]
+    m, n = [], []
+    for k, G in enumerate(cores):
+        if G.ndim != 4:
+            raise ValueError(f"core {k} must be 4-D (r_prev, m, n, r_next)")
+        if G.shape[0] != ranks[-1]:
+            raise ValueError(f"rank mismatch entering core {k}")
+        m.append(int(G.shape[1]))
+        n.append(int(G.shape[2]))
+        ranks.append(int(G.shape[3]))
+    if ranks[0] != 1 or ranks[-1] != 1:
+        raise ValueError("boundary ranks r_0 and r_d must be 1")
+    return ranks, m, n
+
+
+def _digits(index, modes):
+    """Split a flat index into digits, first digit fastest (sec. 2.1)."""
+    out = []
+    for size in modes:
+        out.append(index % size)
+        index //= size
+    return out
+
+
+def qtt_entry(cores, i, j):
+    """One matrix entry A(i, j) straight from the TT definition (eq. TTdeccores
+    applied to the product-tree tensor of sec. 3): the product of the
+    r_{k-1} x r_k matrices G_k(:, i_k, j_k, :) over k, a 1 x 1 result."""
+    _, m, n = qtt_shapes(cores)
+    idig = _digits(int(i), m)
+    jdig = _digits(int(j), n)
+    v = np.ones((1, 1))
+    for G, ik, jk in zip(cores, idig, jdig):
+        v = v @ G[:, ik, jk, :]
+    return float(v[0, 0])
+
+
+def qtt_to_dense(cores):
+    """Dense M x N matrix represented by the cores (sec. 3, tensorized matrix
+    A_T(b_1, ..., b_d) = A(overline{i_1..i_d}, overline{j_1..j_d})).
+
+    The chain of cores is contracted over the rank indices, giving an array
+    with axes (i_1, j_1, i_2, j_2, ..., i_d, j_d); the i axes and j axes are
+    then flattened with the first digit fastest."""
+    _, m, n = qtt_shapes(cores)
+    d = len(cores)
+    T = cores[0]
+    for G in cores[1:]:
+        T = np.tensordot(T, G, axes=([T.ndim - 1], [0]))
+    T = T.reshape(T.shape[1:-1])                      # (m1, n1, ..., md, nd)
+    perm = [2 * k for k in range(d)] + [2 * k + 1 for k in range(d)]
+    T = T.transpose(perm)                             # (m1..md, n1..nd)
+    return T.reshape(int(np.prod(m)), int(np.prod(n)), order="F")
+
+
+# --------------------------------------------------------------------------
+# Algorithm 2: QTT matrix by uncompressed vector
+# --------------------------------------------------------------------------
+
+def _alg2_one(cores, b):
+    """Algorithm 2 (sec. 4.2) for one vector b of length N."""
+    y = b.reshape(1, -1)                              # y_0 = b^T
+    for G in cores:
+        r_prev, m_k, n_k, r_k = G.shape
+        # M_k(overline{a_k i_k}, overline{a_{k-1} j_k}) = G_k(a_{k-1}, overline{i_k j_k}, a_k)
+        M = G.transpose(3, 1, 0, 2).reshape(r_k * m_k, r_prev * n_k, order="F")
+        cols = y.shape[1] // n_k
+        # b_k(overline{a_{k-1} j_k}, overline{J^BOX_k I^LCL_{k-1}}) = y_{k-1}(a_{k-1}, overline{J^BOX_{k-1} I^LCL_{k-1}})
+        bk = y.reshape(r_prev * n_k, cols, order="F")
+        phi = M @ bk
+        # y_k(a_k, overline{J^BOX_k I^LCL_k}) = phi_k(overline{a_k i_k}, overline{J^BOX_k I^LCL_{k-1}}),
+        # with I^LCL_k = overline{I^LCL_{k-1} i_k}: i_k becomes the slowest column digit.
+        y = phi.reshape(r_k, m_k, cols, order="F").transpose(0, 2, 1)
+        y = y.reshape(r_k, cols * m_k, order="F")
+    return y.reshape(-1, order="F")                   # y = y_d^T
+
+
+def qtt_apply_alg2(cores, X):
+    """Y = A X for a block of vectors, one Algorithm-2 sweep per column.
+
+    X: (N,) or (N, K) FP64.  Returns an array of shape (M,) or (M, K)."""
+    _, m, n = qtt_shapes(cores)
+    X = np.asarray(X, dtype=np.float64)
+    N = int(np.prod(n))
+    if X.shape[0] != N:
+        raise ValueError(f"X has {X.shape[0]} rows, the operator has {N} columns")
+    if X.ndim == 1:
+        return _alg2_one(cores, X)
+    Y = np.empty((int(np.prod(m)), X.shape[1]))
+    for c in range(X.shape[1]):
+        Y[:, c] = _alg2_one(cores, X[:, c])
+    return Y
+
+
+def alg2_flops(ranks, m, n):
+    """Floating-point operations of one Algorithm-2 sweep for one vector.
+
+    Core k multiplies an (r_k m_k) x (r_{k-1} n_k) matrix by a matrix with
+    C_k = prod_{l<k} m_l * prod_{l>k} n_l columns: 2 * r_k m_k r_{k-1} n_k C_k
+    flops.  For square modes this is 2 m_k r_{k-1} r_k N, the count given after
+    Algorithm 2 once its rank subscripts are read as those of M_k's size."""
+    d = len(m)
+    total = 0
+    for k in range(d):
+        cols = int(np.prod(m[:k], dtype=np.int64) * np.prod(n[k + 1:], dtype=np.int64))
+        total += 2 * ranks[k + 1] * m[k] * ranks[k] * n[k] * cols
+    return int(total)
+
+
+# --------------------------------------------------------------------------
+# Algorithm 1: TT-SVD, and the QTT matrix of a dense matrix
+# --------------------------------------------------------------------------
+
+def tt_svd(tensor, eps):
+    """Algorithm 1 (sec. 2.2) with a truncated SVD as the low-rank routine.
+
+    The per-unfolding threshold is delta = eps * ||A||_F / sqrt(d-1); the rank
+    kept is the smallest r >= 1 whose discarded singular values have
+    sum of squares <= delta^2.  Singular values go into the right factor.
+
+    Returns (cores, tails) where cores[k] has shape (r_{k-1}, n_k, r_k) and
+    tails[k] is the Frobenius norm discarded at unfolding k+1."""
+    A = np.asarray(tensor, dtype=np.float64)
+    d = A.ndim
+    n = A.shape
+    if d == 1:
+        return [A.reshape(1, n[0], 1).copy()], []
+    delta = eps * np.linalg.norm(A) / np.sqrt(d - 1)
+    Mk = A.reshape(n[0], -1, order="F")               # first unfolding matrix
+    r_prev = 1
+    cores, tails = [], []
+    for k in range(d - 1):
+        U, s, Vt = np.linalg.svd(Mk, full_matrices=False)
+        # discarded[r] = sqrt(sum_{t >= r} s_t^2) for r = 0..len(s)
+        discarded = np.sqrt(np.append(np.cumsum((s ** 2)[::-1])[::-1], 0.0))
+        r = 1
+        while r < len(s) and discarded[r] > delta:
+            r += 1
+        tails.append(float(discarded[r]))
+        cores.append(U[:, :r].reshape(r_prev, n[k], r, order="F"))
+        V = s[:r, None] * Vt[:r]
+        Mk = V.reshape(r * n[k + 1], -1, order="F")
+        r_prev = r
+    cores.append(Mk.reshape(r_prev, n[d - 1], 1, order="F"))
+    return cores, tails
+
+
+def qtt_matrix_from_dense(A, m, n, eps):
+    """QTT matrix of a dense M x N matrix (sec. 3 tensorization + Algorithm 1).
+
+    The matrix is viewed as the d-dimensional tensor over the product tree,
+    A_T(b_1..b_d) with b_k = overline{i_k j_k} (i_k fastest), then compressed.
+    Returns (cores, tails) with cores[k] of shape (r_{k-1}, m_k, n_k, r_k)."""
+    d = len(m)
+    A = np.asarray(A, dtype=np.float64)
+    T = A.reshape(tuple(m) + tuple(n), order="F")     # axes (i_1..i_d, j_1..j_d)
+    perm = []
+    for k in range(d):
+        perm += [k, d + k]
+    T = T.transpose(perm)                             # (i_1, j_1, ..., i_d, j_d)
+    T = T.reshape(tuple(m[k] * n[k] for k in range(d)), order="F")
+    tt, tails = tt_svd(T, eps)
+    cores = [G.reshape(G.shape[0], m[k], n[k], G.shape[2], order="F")
+             for k, G in enumerate(tt)]
+    return cores, tails
+
+
+# --------------------------------------------------------------------------
+# the volume operator of the numerical experiments (sec. 5.1)
+# --------------------------------------------------------------------------
+
+def morton_points(L):
+    """Integer cell coordinates (ix, iy, iz) of a (2^L)^3 grid listed in
+    octree (Morton) order: point index i = sum_k i_k 8^{k-1}, where the level-k
+    octant digit is i_k = 4 z_bit + 2 y_bit + x_bit of bit k-1 of each
+    coordinate (level 1 = finest, sec. 2.3; ordering of sec. 5.1)."""
+    side = 1 << L
+    N = side ** 3
+    idx = np.arange(N, dtype=np.int64)
+    ix = np.zeros(N, dtype=np.int64)
+    iy = np.zeros(N, dtype=np.int64)
+    iz = np.zeros(N, dtype=np.int64)
+    for k in range(L):
+        digit = (idx >> (3 * k)) & 7
+        ix |= (digit & 1) << k
+        iy |= ((digit >> 1) & 1) << k
+        iz |= ((digit >> 2) & 1) << k
+    return np.stack([ix, iy, iz], axis=1)
+
+
+def volume_self_term(h, sub=8):
+    """Diagonal self term: midpoint rule with sub^3 sub-cells for the integral
+    of 1/(4 pi |x - y|) over the cell centred at x (no sub-cell midpoint hits
+    the singularity).  Used in place of the punctured trapezoid of sec. 5.1."""
+    t = (np.arange(sub) + 0.5) / sub - 0.5
+    u = np.stack(np.meshgrid(t, t, t, indexing="ij"), axis=-1).reshape(-1, 3)
+    return float(np.sum((h / sub) ** 3 / (4.0 * np.pi * h * np.linalg.norm(u, axis=1))))
+
+
+def volume_matrix(L):
+    """Nystrom matrix A = I + K W (eq. nystrom with a = 1, b = c = 1, w = h^3)
+    of the Laplace single-layer kernel 1/(4 pi r) on the cell centres of a
+    (2^L)^3 grid on [0,1]^3 in Morton order; diagonal 1 + self term."""
+    side = 1 << L
+    h = 1.0 / side
+    P = (morton_points(L) + 0.5) * h
+    diff = P[:, None, :] - P[None, :, :]
+    dist = np.sqrt(np.sum(diff * diff, axis=-1))
+    np.fill_diagonal(dist, 1.0)
+    A = h ** 3 / (4.0 * np.pi * dist)
+    np.fill_diagonal(A, 1.0 + volume_self_term(h))
+    return A
+
+
+def volume_apply_direct(L, X):
+    """y = A x for the volume operator by direct summation over grid
+    coordinates, y_i = (1 + s) x_i + sum_{j != i} h^3 / (4 pi |p_i - p_j|) x_j,
+    evaluated in natural (x fastest) grid order as a zero-padded 3-D
+    convolution with scipy's FFT, then listed in Morton order.  It never forms
+    the matrix and never uses the octree digits except to reorder."""
+    from scipy.signal import fftconvolve
+    side = 1 << L
+    h = 1.0 / side
+    s = volume_self_term(h)
+    off = np.arange(-(side - 1), side)
+    dz, dy, dx = np.meshgrid(off, off, off, indexing="ij")
+    r = h * np.sqrt(dx * dx + dy * dy + dz * dz)
+    r[side - 1, side - 1, side - 1] = 1.0
+    kern = h ** 3 / (4.0 * np.pi * r)
+    kern[side - 1, side - 1, side - 1] = 0.0
+    pts = morton_points(L)
+    X = np.asarray(X, dtype=np.float64)
+    one = X.ndim == 1
+    X2 = X[:, None] if one else X
+    Y = np.empty_like(X2)
+    for c in range(X2.shape[1]):
+        grid = np.zeros((side, side, side))
+        grid[pts[:, 2], pts[:, 1], pts[:, 0]] = X2[:, c]
+        conv = fftconvolve(grid, kern, mode="full")
+        conv = conv[side - 1:2 * side - 1, side - 1:2 * side - 1, side - 1:2 * side - 1]
+        Y[:, c] = conv[pts[:, 2], pts[:, 1], pts[:, 0]] + (1.0 + s) * X2[:, c]
+    return Y[:, 0] if one else Y
+
+
+# --------------------------------------------------------------------------
+# the solve: direct inverse apply plus iterative refinement
+# --------------------------------------------------------------------------
+
+def richardson_solve(A_cores, Ainv_cores, F, rtol=1e-8, max_iter=50):
+    """sigma with A sigma = F by refinement with the compressed inverse:
+    x = 0, r = F; repeat { x += Ainv r ; r = F - A x } until
+    ||r_c|| <= rtol ||F_c|| for every column c.  The first pass is the paper's
+    direct solve sigma = Ainv f (sec. 5); the later passes correct it.
+
+    Returns (X, history) where history[t] holds the per-column relative
+    residuals after pass t+1."""
+    F = np.asarray(F, dtype=np.float64)
+    one = F.ndim == 1
+    F2 = F[:, None] if one else F
+    fn = np.linalg.norm(F2, axis=0)
+    fn[fn == 0] = 1.0
+    X = np.zeros_like(F2)
+    R = F2.copy()
+    history = []
+    for _ in range(max_iter):
+        X = X + qtt_apply_alg2(Ainv_cores, R)
+        R = F2 - qtt_apply_alg2(A_cores, X)
+        rel = np.linalg.norm(R, axis=0) / fn
+        history.append(rel)
+        if np.all(rel <= rtol):
+            break
+    return (X[:, 0] if one else X), history

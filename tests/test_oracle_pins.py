@@ -1,0 +1,287 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle.
+
+Each test names the passage of the paper (or the textbook identity) that fixes
+the expected value.  A plausible slip in the oracle -- a transposed core, a
+swapped digit order, a wrong rank index, a dropped term -- fails at least one
+of them.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import qtt_oracle as O
+from paper_1511_06029_amd import inputs as I
+import qtt_structures as S
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+# ---------------------------------------------------------------- definition
+
+def test_dense_matches_entrywise_definition():
+    """qtt_to_dense against the literal product of r x r matrices (TT
+    definition), on heterogeneous modes and ranks."""
+    cores = I.gaussian_qtt([1, 3, 5, 2, 1], [2, 3, 4, 2], [3, 2, 2, 4], seed=1)
+    A = O.qtt_to_dense(cores)
+    assert A.shape == (48, 48)
+    g = I.rng(7)
+    for _ in range(60):
+        i, j = int(g.integers(48)), int(g.integers(48))
+        assert A[i, j] == pytest.approx(O.qtt_entry(cores, i, j), rel=1e-13, abs=1e-15)
+
+
+def test_kronecker_dense_digit_order():
+    """Rank-1 cores give A = A_d (x) ... (x) A_1 (first digit fastest, sec. 2.1;
+    core 1 = finest level).  np.kron is the independent reference."""
+    g = I.rng(3)
+    mats = [g.standard_normal((2, 3)), g.standard_normal((4, 2)), g.standard_normal((3, 3))]
+    A = O.qtt_to_dense(S.kron_cores(mats))
+    ref = np.kron(mats[2], np.kron(mats[1], mats[0]))
+    assert np.abs(A - ref).max() < 1e-14
+
+
+def test_diag_unfolding_matches_paper_pattern():
+    """The proof of the corollary on non-translation-invariant kernels prints
+    the first unfolding of the tensorized diag(b) (binary trees) as a 4 x 2
+    0/1 pattern times the first unfolding of b."""
+    rows = [ln.split() for ln in open(os.path.join(GOLDEN, "diag_unfolding.txt"))
+            if ln.strip() and not ln.startswith("#")]
+    P = np.array([[float(x) for x in r] for r in rows])
+    d = 3
+    b = I.rng(5).standard_normal(2 ** d)
+    B = np.diag(b)
+    # tensorize as in sec. 3 (b_k = overline{i_k j_k}, i_k fastest) via the
+    # oracle's compression at eps = 0, then rebuild the unfolding from it
+    cores, _ = O.qtt_matrix_from_dense(B, [2] * d, [2] * d, 0.0)
+    A_T = O.qtt_to_dense(cores)
+    assert np.abs(A_T - B).max() < 1e-13
+    T = B.reshape((2,) * (2 * d), order="F").transpose(0, 3, 1, 4, 2, 5)
+    T = T.reshape((4,) * d, order="F")
+    unf = T.reshape(4, -1, order="F")
+    nz = np.abs(unf).sum(axis=0) > 0
+    b1 = b.reshape(2, -1, order="F")
+    assert np.abs(unf[:, nz] - P @ b1).max() == 0.0
+    assert b1[0, 1] == b[2] and b1[1, 0] == b[1]   # columns b(x_1), b(x_3), ... in 1-based terms
+
+
+# ---------------------------------------------------------------- Algorithm 2
+
+@pytest.mark.parametrize("ranks,m,n", [
+    ([1, 3, 5, 2, 1], [2, 3, 4, 2], [3, 2, 2, 4]),          # rectangular, uneven
+    ([1, 4, 4, 1], [4, 2, 2], [4, 2, 2]),                   # the d=3 (4x4, 2x2, 2x2) N=16 shape example
+    ([1, 7, 9, 6, 1], [8, 8, 8, 8], [8, 8, 8, 8]),          # L=4 octree digits
+    ([1, 1], [5], [3]),                                     # single core
+    ([1, 2, 1], [1, 4], [3, 1]),                            # unit modes
+])
+def test_alg2_matches_dense(ranks, m, n):
+    cores = I.gaussian_qtt(ranks, m, n, seed=11)
+    A = O.qtt_to_dense(cores)
+    X = I.rhs(A.shape[1], 3, seed=12)
+    Y = O.qtt_apply_alg2(cores, X)
+    assert _rel(Y, A @ X) < 1e-13
+    y1 = O.qtt_apply_alg2(cores, X[:, 1])
+    assert np.array_equal(y1, Y[:, 1])
+
+
+@pytest.mark.parametrize("L", [1, 3, 6])
+def test_alg2_identity_bitwise(L):
+    X = I.rhs(8 ** L, 2, seed=L)
+    Y = O.qtt_apply_alg2(I.identity_qtt([8] * L), X)
+    assert np.array_equal(Y, X)
+
+
+def test_alg2_permutation_bitwise():
+    """Permutation cores give a permutation of X, exactly."""
+    g = I.rng(9)
+    perms = [g.permutation(8) for _ in range(4)]
+    mats = [np.eye(8)[p] for p in perms]
+    X = I.rhs(8 ** 4, 2, seed=3)
+    Y = O.qtt_apply_alg2(S.kron_cores(mats), X)
+    assert np.array_equal(Y, S.modewise_apply(mats, X))
+    assert np.array_equal(np.sort(Y[:, 0]), np.sort(X[:, 0]))
+
+
+def test_alg2_kronecker_modewise():
+    g = I.rng(4)
+    mats = [g.standard_normal((8, 8)) / 3 for _ in range(5)]
+    X = I.rhs(8 ** 5, 2, seed=5)
+    Y = O.qtt_apply_alg2(S.kron_cores(mats), X)
+    assert _rel(Y, S.modewise_apply(mats, X)) < 1e-14
+
+
+@pytest.mark.slow
+def test_alg2_gauge_sum_full_rank():
+    """Rank-R sum of Kronecker terms in block form, then a random orthogonal
+    gauge so every core is dense; the reference is the sum of mode-wise
+    applies of the terms.  L=6, R=32: every rank channel is exercised."""
+    L, R = 6, 32
+    g = I.rng(21)
+    terms = [[g.standard_normal((8, 8)) / 8 for _ in range(L)] for _ in range(R)]
+    cores = S.gauge(S.block_sum_cores(terms), g)
+    assert all(np.count_nonzero(G) == G.size for G in cores)
+    X = I.rhs(8 ** L, 2, seed=22)
+    ref = sum(S.modewise_apply(t, X) for t in terms)
+    assert _rel(O.qtt_apply_alg2(cores, X), ref) < 1e-12
+
+
+def test_alg2_diagonal():
+    """QTT of diag(b) built from the TT of b (same ranks) applies as b * x."""
+    g = I.rng(31)
+    vr = [1, 3, 4, 2, 1]
+    vcores = [g.standard_normal((vr[k], 8, vr[k + 1])) for k in range(4)]
+    b = S.vector_tt_full(vcores)
+    X = I.rhs(8 ** 4, 2, seed=32)
+    Y = O.qtt_apply_alg2(S.diag_cores(vcores), X)
+    assert _rel(Y, b[:, None] * X) < 1e-13
+
+
+def test_alg2_product_chain():
+    """Cores of A B (ranks multiply) apply as A (B X)."""
+    A = I.gaussian_qtt([1, 3, 4, 2, 1], [8] * 4, seed=41)
+    B = I.gaussian_qtt([1, 2, 3, 2, 1], [8] * 4, seed=42)
+    C = S.product_cores(A, B)
+    assert [G.shape[3] for G in C] == [6, 12, 4, 1]
+    X = I.rhs(8 ** 4, 2, seed=43)
+    assert _rel(O.qtt_apply_alg2(C, X), O.qtt_apply_alg2(A, O.qtt_apply_alg2(B, X))) < 1e-13
+
+
+def test_alg2_linearity():
+    cores = I.gaussian_qtt([1, 5, 6, 5, 1], [8] * 4, seed=51)
+    X = I.rhs(4096, 1, 1)[:, 0]
+    Z = I.rhs(4096, 1, 2)[:, 0]
+    lhs = O.qtt_apply_alg2(cores, 2.5 * X - 0.75 * Z)
+    rhs = 2.5 * O.qtt_apply_alg2(cores, X) - 0.75 * O.qtt_apply_alg2(cores, Z)
+    assert _rel(lhs, rhs) < 1e-14
+
+
+def test_flop_count():
+    """Work of Algorithm 2: 2 m_k r_{k-1} r_k N per core for square modes."""
+    ranks = [1, 24, 32, 32, 32, 32, 24, 1]
+    N = 8 ** 7
+    closed = sum(2 * 8 * ranks[k] * ranks[k + 1] * N for k in range(7))
+    assert O.alg2_flops(ranks, [8] * 7, [8] * 7) == closed == 74496 * N
+    # rectangular: core k has (r_k m_k) x (r_{k-1} n_k) times prod_{l<k} m_l prod_{l>k} n_l columns
+    assert O.alg2_flops([1, 2, 1], [3, 5], [4, 2]) == 2 * (2 * 3 * 1 * 4 * 2 + 1 * 5 * 2 * 2 * 3)
+
+
+# ---------------------------------------------------------------- Algorithm 1
+
+def test_ttsvd_two_dims_is_truncated_svd():
+    """For d = 2 Algorithm 1 is one truncated SVD: the error equals the
+    Eckart-Young tail, and the rank is the smallest meeting the threshold."""
+    g = I.rng(61)
+    A = g.standard_normal((40, 8)) @ np.diag(2.0 ** -np.arange(8)) @ g.standard_normal((8, 30))
+    eps = 1e-2
+    cores, tails = O.tt_svd(A, eps)
+    s = np.linalg.svd(A, compute_uv=False)
+    delta = eps * np.linalg.norm(A)
+    r = cores[0].shape[2]
+    assert np.sqrt(np.sum(s[r:] ** 2)) <= delta < np.sqrt(np.sum(s[r - 1:] ** 2))
+    Ar = cores[0].reshape(40, r) @ cores[1].reshape(r, 30)
+    assert abs(np.linalg.norm(A - Ar) - np.sqrt(np.sum(s[r:] ** 2))) < 1e-12 * np.linalg.norm(A)
+
+
+def test_ttsvd_bounds_and_exact_ranks():
+    """Error bound ||A - A_TT||_F^2 <= sum eps_k^2 <= eps^2 ||A||_F^2, and a
+    tensor of exact TT rank is recovered exactly with no larger ranks."""
+    g = I.rng(62)
+    true = [g.standard_normal(s) for s in [(1, 4, 3), (3, 5, 2), (2, 3, 4), (4, 4, 1)]]
+    T = S.vector_tt_full(true).reshape((4, 5, 3, 4), order="F")
+    cores, tails = O.tt_svd(T, 1e-12)
+    assert [c.shape[2] for c in cores][:-1] == [3, 2, 4]
+    R = S.vector_tt_full(cores).reshape(T.shape, order="F")
+    assert _rel(R, T) < 1e-13
+    cores0, tails0 = O.tt_svd(T, 0.0)          # eps = 0 keeps every nonzero direction
+    assert _rel(S.vector_tt_full(cores0).reshape(T.shape, order="F"), T) < 1e-13
+    noisy = T + 1e-3 * g.standard_normal(T.shape)
+    for eps in (1e-1, 1e-2, 1e-3):
+        cores, tails = O.tt_svd(noisy, eps)
+        R = S.vector_tt_full(cores).reshape(T.shape, order="F")
+        err = np.linalg.norm(R - noisy)
+        assert err <= np.sqrt(np.sum(np.square(tails))) * (1 + 1e-10)
+        assert np.sqrt(np.sum(np.square(tails))) <= eps * np.linalg.norm(noisy) * (1 + 1e-12)
+
+
+# ---------------------------------------------------------------- volume operator
+
+def test_self_term_quadrature():
+    """The midpoint rule for the cell integral of 1/(4 pi |x - y|) converges
+    to the closed form (3 ln(2 + sqrt 3) - pi/2) h^2 / (4 pi)."""
+    exact = (3 * math.log(2 + math.sqrt(3)) - math.pi / 2) / (4 * math.pi)
+    e8 = abs(O.volume_self_term(1.0, 8) - exact)
+    e32 = abs(O.volume_self_term(1.0, 32) - exact)
+    assert e8 < 2e-3 * exact and e32 < e8 / 3
+    assert O.volume_self_term(0.25, 8) == pytest.approx(0.0625 * O.volume_self_term(1.0, 8), rel=1e-14)
+
+
+def test_morton_order():
+    pts = O.morton_points(2)
+    assert len({tuple(p) for p in pts}) == 64
+    assert list(pts[1]) == [1, 0, 0] and list(pts[2]) == [0, 1, 0] and list(pts[4]) == [0, 0, 1]
+    assert list(pts[8]) == [2, 0, 0] and list(pts[63]) == [3, 3, 3]
+
+
+def test_volume_matrix_vs_direct_summation():
+    A = O.volume_matrix(2)
+    X = I.rhs(64, 2, seed=71)
+    assert _rel(A @ X, O.volume_apply_direct(2, X)) < 1e-14
+
+
+@pytest.fixture(scope="session")
+def volume_L4():
+    A = O.volume_matrix(4)
+    cores, tails = O.qtt_matrix_from_dense(A, [8] * 4, [8] * 4, 1e-10)
+    return A, cores, tails
+
+
+@pytest.mark.slow
+def test_volume_L4_qtt_apply_vs_direct(volume_L4):
+    """QTT apply of the compressed volume operator against direct summation
+    from coordinates, within the TT-SVD truncation bound."""
+    A, cores, tails = volume_L4
+    bound = np.sqrt(np.sum(np.square(tails)))
+    assert bound <= 1e-10 * np.linalg.norm(A)
+    assert [G.shape[3] for G in cores] == [27, 173, 27, 1]
+    X = I.rhs(4096, 2, seed=72)
+    Y = O.qtt_apply_alg2(cores, X)
+    D = O.volume_apply_direct(4, X)
+    for c in range(2):
+        assert np.linalg.norm(Y[:, c] - D[:, c]) <= bound * np.linalg.norm(X[:, c]) * 1.01 + 1e-13
+
+
+# ---------------------------------------------------------------- solve
+
+def test_richardson_vs_dense_solve_synthetic():
+    """Refinement with the same-rank approximate inverse reaches 1e-8 and
+    agrees with a dense LU solve (forward error <= cond * residual)."""
+    ranks = [1, 6, 8, 6, 1]
+    A, Ainv = I.perturbed_identity_pair(ranks, [8] * 4, seed=81)
+    F = I.rhs(4096, 2, seed=82)
+    X, hist = O.richardson_solve(A, Ainv, F, rtol=1e-8)
+    Ad = O.qtt_to_dense(A)
+    ref = np.linalg.solve(Ad, F)
+    assert np.all(hist[-1] <= 1e-8) and len(hist) <= 12
+    cond = np.linalg.cond(Ad)
+    assert cond < 3
+    assert _rel(X, ref) <= cond * 1e-8
+    # contraction per pass is about ||I - Ainv A||
+    rho = np.linalg.norm(np.eye(4096) - O.qtt_to_dense(Ainv) @ Ad, 2)
+    assert rho < 0.2
+    assert hist[1][0] <= 1.5 * rho * hist[0][0]
+
+
+@pytest.mark.slow
+def test_richardson_volume_L4(volume_L4):
+    A, A_cores, _ = volume_L4
+    Ainv_cores, _ = O.qtt_matrix_from_dense(np.linalg.inv(A), [8] * 4, [8] * 4, 1e-6)
+    F = I.rhs(4096, 1, seed=91)
+    X, hist = O.richardson_solve(A_cores, Ainv_cores, F, rtol=1e-8)
+    ref = np.linalg.solve(A, F)
+    assert hist[-1][0] <= 1e-8
+    assert _rel(X, ref) < 1e-8
