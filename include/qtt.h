@@ -1,0 +1,179 @@
+/*
+ * qtt.h -- C ABI of libqtt: QTT matrix by full-vector products and a
+ * refined solve on AMD Instinct MI355X (gfx950).
+ *
+ * The operation is the QTT matrix-vector product of section 4.2 of
+ * Corona, Rahimian, Zorin, "A Tensor-Train accelerated solver for integral
+ * equations in complex geometries" (arXiv:1511.06029), Algorithm 2
+ * (matrix by uncompressed vector), applied to a block of right-hand sides.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * A QTT matrix with d cores has ranks r_0..r_d (r_0 = r_d = 1), row mode
+ * sizes m_1..m_d and column mode sizes n_1..n_d (section 3: the matrix
+ * tensorized over the product of a target and a source tree).  Its entries
+ * are (TT definition, section 2.2)
+ *     A(i, j) = G_1(:, i_1, j_1, :) G_2(:, i_2, j_2, :) ... G_d(:, i_d, j_d, :)
+ * with the flat indices built first digit fastest (section 2.1, Matlab
+ * order; core 1 is the finest tree level):
+ *     i = i_1 + m_1 (i_2 + m_2 (i_3 + ...)),  j = j_1 + n_1 (j_2 + ...).
+ * A has M = prod m_k rows and N = prod n_k columns.
+ *
+ * Vectors are FP64 and live in device memory.  A block of K vectors is
+ * column-major: column c starts at ptr + c * ld, ld >= length.
+ *
+ * Streams are hipStream_t values passed as void* (NULL: the null stream).
+ * Enqueueing entry points return after enqueueing; device faults surface at
+ * the caller's next synchronisation.  Argument and shape errors are detected
+ * before anything is enqueued and leave outputs untouched.
+ *
+ * Handles are immutable after qtt_matrix_load and may be used concurrently
+ * from several host threads and streams, provided the workspaces differ.
+ *
+ * Every function returns QTT_OK or an error code; qtt_last_error() gives a
+ * message for the calling thread's last failure.
+ */
+#ifndef QTT_H
+#define QTT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qtt_matrix_s* qtt_matrix_t;
+
+/* Arithmetic of a sweep.  FP64: FP64 cores, intermediates and accumulation.
+ * FP32: FP32 cores and intermediates, FP32 accumulation.  BF16: BF16 cores
+ * and intermediates, FP32 accumulation.  Inputs are read as FP64 and
+ * converted when the first core loads them; the last core writes FP64.
+ * Values are bit flags so that qtt_matrix_load can take several. */
+typedef enum {
+  QTT_FP64 = 1,
+  QTT_FP32 = 2,
+  QTT_BF16 = 4
+} qtt_dtype_t;
+
+typedef enum {
+  QTT_OK = 0,
+  QTT_ERR_INVALID_ARG = 1,   /* null or overlapping pointers, bad flags, bad counts */
+  QTT_ERR_SHAPE = 2,         /* ranks or modes inconsistent, solve with non-square modes */
+  QTT_ERR_OUT_OF_MEMORY = 3, /* device allocation failed in qtt_matrix_load */
+  QTT_ERR_DEVICE = 4,        /* a HIP call failed */
+  QTT_ERR_NOT_CONVERGED = 5, /* qtt_solve reached max_iter above rtol */
+  QTT_ERR_NONFINITE = 6,     /* qtt_solve met a NaN or Inf residual */
+  QTT_ERR_WORKSPACE = 7,     /* workspace smaller than the one-vector minimum */
+  QTT_ERR_DTYPE = 8          /* the handle holds no device copy in this dtype */
+} qtt_status_t;
+
+/* Load a QTT matrix onto the current HIP device.
+ *   d       number of cores, 1 <= d <= 64.
+ *   ranks   d+1 values, ranks[0] = ranks[d] = 1, all >= 1.
+ *   m, n    d row and d column mode sizes, all >= 1.
+ *   cores   d host pointers; cores[k] is a dense FP64 array of shape
+ *           [r_k][m_{k+1}][n_{k+1}][r_{k+1}] (0-based k, C row-major, last
+ *           index fastest), i.e. G_{k+1}(a, i, j, b) at ((a*m + i)*n + j)*r + b.
+ *   dtypes  OR of qtt_dtype_t: device copies to build.  Each core is stored
+ *           as the matrix M_k(a_k + r_k i_k, a_{k-1} + r_{k-1} j_k) of
+ *           Algorithm 2 (size r_k m_k x r_{k-1} n_k), rounded to nearest-even
+ *           for FP32 and BF16, in the fragment order the kernels read.
+ *   out     receives the handle.  The library owns it; free with
+ *           qtt_matrix_free.  The host arrays are not retained. */
+qtt_status_t qtt_matrix_load(int32_t d, const int64_t* ranks, const int64_t* m,
+                             const int64_t* n, const double* const* cores,
+                             uint32_t dtypes, qtt_matrix_t* out);
+
+qtt_status_t qtt_matrix_free(qtt_matrix_t A);
+
+/* Shape of a loaded matrix; any output pointer may be NULL. */
+qtt_status_t qtt_matrix_info(qtt_matrix_t A, int32_t* d, int64_t* rows, int64_t* cols,
+                             int64_t* max_rank, uint32_t* dtypes);
+
+/* Device bytes of workspace that let qtt_apply / qtt_apply_batched run nrhs
+ * vectors in one sweep: two ping-pong buffers of the largest intermediate
+ * (r_k x prod_{l<=k} m_l x prod_{l>k} n_l values per vector, Algorithm 2's
+ * y_k) in the compute dtype, plus alignment.  A smaller workspace (at least
+ * the value for nrhs = 1) makes the library process the vectors in waves. */
+qtt_status_t qtt_workspace_bytes(qtt_matrix_t A, qtt_dtype_t compute, int64_t nrhs,
+                                 size_t* bytes);
+
+/* Y = A X (Algorithm 2 on every column).
+ *   X    device FP64, N x nrhs, column stride ldx >= N.
+ *   Y    device FP64, M x nrhs, column stride ldy >= M; must not overlap X.
+ *   ws   device workspace of ws_bytes (see qtt_workspace_bytes); the caller
+ *        owns it and must not use it concurrently for another call.
+ * nrhs = 0 is a no-op. */
+qtt_status_t qtt_apply(qtt_matrix_t A, qtt_dtype_t compute, int64_t nrhs,
+                       const double* X, int64_t ldx, double* Y, int64_t ldy,
+                       void* ws, size_t ws_bytes, void* stream);
+
+/* Uneven blocks: block b has widths[b] vectors at X[b] (stride ldx[b]) and
+ * writes A X[b] to Y[b] (stride ldy[b]).  All blocks go through the same
+ * sweep: each core is one persistent launch over the tiles of every vector
+ * that fits the workspace.  Blocks of width 0 are skipped.  No Y[b] may
+ * overlap any X[b']. */
+qtt_status_t qtt_apply_batched(qtt_matrix_t A, qtt_dtype_t compute, int32_t nblocks,
+                               const int64_t* widths, const double* const* X,
+                               const int64_t* ldx, double* const* Y, const int64_t* ldy,
+                               void* ws, size_t ws_bytes, void* stream);
+
+/* Tune tile shapes for this matrix, dtype and vector count: every candidate
+ * kernel configuration is timed on each core (outputs written to scratch in
+ * ws), and the fastest is kept in the handle and in a process-wide table
+ * keyed by (dtype, core shape, column count).  X/Y are used as in qtt_apply
+ * and hold A X on return.  Synchronises the stream. */
+qtt_status_t qtt_autotune(qtt_matrix_t A, qtt_dtype_t compute, int64_t nrhs,
+                          const double* X, int64_t ldx, double* Y, int64_t ldy,
+                          void* ws, size_t ws_bytes, void* stream);
+
+typedef struct {
+  int32_t iters;         /* passes of x += Ainv r done for this column */
+  double rel_residual;   /* ||F_c - A x_c||_2 / ||F_c||_2 after the last pass */
+} qtt_solve_col_t;
+
+/* Device bytes of workspace for qtt_solve: the apply workspace for nrhs
+ * vectors plus the N x nrhs FP64 residual and the norm buffers. */
+qtt_status_t qtt_solve_workspace_bytes(qtt_matrix_t A, qtt_matrix_t Ainv, qtt_dtype_t inv_compute,
+                                       int64_t nrhs, size_t* bytes);
+
+/* Solve A sigma = F with the compressed inverse and iterative refinement:
+ * sigma = 0, r = F; repeat { sigma += Ainv r ; r = F - A sigma } until
+ * ||r_c|| <= rtol ||F_c|| for every column, or max_iter passes.  The first
+ * pass is the direct solve sigma = Ainv F of section 5.  A is applied in
+ * FP64 (the residual, fused into its last core, stays FP64); Ainv is applied
+ * in inv_compute (FP64, FP32 or BF16), and the update is accumulated in FP64.
+ *   A, Ainv   square modes, identical mode sizes.
+ *   F         device FP64, N x nrhs, stride ldf.  Sigma: device FP64, stride lds.
+ *   info      host array of nrhs entries (may be NULL).
+ * Synchronises the stream once per pass to read the nrhs residual norms.
+ * Returns QTT_ERR_NOT_CONVERGED (Sigma holds the last iterate) or
+ * QTT_ERR_NONFINITE when a residual norm is not finite. */
+qtt_status_t qtt_solve(qtt_matrix_t A, qtt_matrix_t Ainv, qtt_dtype_t inv_compute, int64_t nrhs,
+                       const double* F, int64_t ldf, double* Sigma, int64_t lds,
+                       double rtol, int32_t max_iter, void* ws, size_t ws_bytes,
+                       void* stream, qtt_solve_col_t* info);
+
+const char* qtt_status_string(qtt_status_t s);
+const char* qtt_last_error(void);
+
+/* Per-launch device timing of the core-step kernels, for roofline figures.
+ * When enabled, every core-step launch on the calling thread is bracketed by
+ * HIP events recorded on the stream it is launched on.  qtt_timing_read
+ * synchronises on the recorded events and reports, for one compute dtype
+ * and one core position (0 = interior cores, 1 = first core, 2 = last core,
+ * 3 = single-core matrices), the number of launches, their summed device
+ * time, and their summed algorithmic flops (2 x rows x cols x columns of
+ * each core's product) and bytes (input read once, output written once).
+ * qtt_timing_reset drops what was recorded. */
+qtt_status_t qtt_timing_enable(int32_t on);
+qtt_status_t qtt_timing_reset(void);
+qtt_status_t qtt_timing_read(qtt_dtype_t compute, int32_t position, int64_t* launches,
+                             double* milliseconds, double* flops, double* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QTT_H */

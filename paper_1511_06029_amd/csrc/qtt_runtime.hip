@@ -1,0 +1,859 @@
+// libqtt host runtime: the C ABI declared in include/qtt.h.
+//
+// Responsibilities: validate and re-lay out QTT cores into the fragment
+// order of the core-step kernels (one device copy per requested dtype),
+// drive Algorithm 2 core by core over ping-pong workspace buffers (in waves
+// when the workspace is smaller than the batch), pick a kernel configuration
+// per core (heuristic or autotuned), run the refined solve, and optionally
+// time launches with HIP events.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "qtt.h"
+#include "qtt_kernels.hpp"
+
+using namespace qtt;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_last_error;
+
+static qtt_status_t fail(qtt_status_t s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      return fail(QTT_ERR_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// dtype helpers
+// ---------------------------------------------------------------------------
+static int dt_index(qtt_dtype_t t) {
+  switch (t) {
+    case QTT_FP64: return 0;
+    case QTT_FP32: return 1;
+    case QTT_BF16: return 2;
+  }
+  return -1;
+}
+static const int kKstep[3] = {4, 4, 32};
+static const int kElemBytes[3] = {8, 4, 2};
+static const int kFragE[3] = {1, 1, 8};
+
+// ---------------------------------------------------------------------------
+// kernel registry
+// ---------------------------------------------------------------------------
+typedef void (*step_fn)(const StepArgs);
+
+struct KernelCfg {
+  int dt;          // 0 fp64, 1 fp32, 2 bf16
+  bool in_f64;     // reads FP64 input (first core)
+  bool vec;        // 16-byte input loads
+  int TR, TC, KC, NT;
+  int id;          // configuration id within the dtype (tile shape)
+  const void* fn;  // kernel symbol
+  int occ;         // resident blocks per CU, 0 = not yet queried
+};
+
+template <class Tc, class Tin, int WRW, int WCW, int WR, int WC, int KC, bool ROL, bool VEC>
+static KernelCfg make_cfg(int dt, bool in_f64, int id) {
+  KernelCfg k;
+  k.dt = dt;
+  k.in_f64 = in_f64;
+  k.vec = VEC;
+  k.TR = 16 * WR * WRW;
+  k.TC = 16 * WC * WCW;
+  k.KC = KC;
+  k.NT = 64 * WRW * WCW;
+  k.id = id;
+  k.fn = reinterpret_cast<const void*>(&core_step_kernel<Tc, Tin, WRW, WCW, WR, WC, KC, ROL, VEC>);
+  k.occ = 0;
+  return k;
+}
+
+// tile shapes: (waves along rows, waves along columns, row blocks per wave,
+// column blocks per wave, rows on lanes)
+#define QTT_SHAPES(X)        \
+  X(0, 4, 1, 4, 4, true)     \
+  X(1, 4, 1, 3, 4, true)     \
+  X(2, 1, 4, 1, 4, false)    \
+  X(3, 2, 2, 4, 4, true)     \
+  X(4, 4, 1, 2, 4, true)     \
+  X(5, 4, 1, 4, 2, true)     \
+  X(6, 2, 2, 2, 2, true)     \
+  X(7, 1, 4, 1, 2, false)
+static const int kNumShapes = 8;
+static const int kGenericShape = 6;
+
+template <class Tc, class Tin, int KC>
+static void add_family(std::vector<KernelCfg>& v, int dt, bool in_f64) {
+#define QTT_ADD(id, a, b, c, d, rol) v.push_back(make_cfg<Tc, Tin, a, b, c, d, KC, rol, true>(dt, in_f64, id));
+  QTT_SHAPES(QTT_ADD)
+#undef QTT_ADD
+  // scalar-load fallback for shapes whose columns are not 16-byte aligned
+  v.push_back(make_cfg<Tc, Tin, 2, 2, 2, 2, KC, true, false>(dt, in_f64, kGenericShape));
+}
+
+static std::vector<KernelCfg>& registry() {
+  static std::vector<KernelCfg> reg = [] {
+    std::vector<KernelCfg> v;
+    add_family<double, double, 32>(v, 0, true);
+    add_family<float, float, 32>(v, 1, false);
+    add_family<float, double, 32>(v, 1, true);
+    add_family<bf16_tag, uint16_t, 128>(v, 2, false);
+    add_family<bf16_tag, double, 128>(v, 2, true);
+    return v;
+  }();
+  return reg;
+}
+
+static KernelCfg* find_cfg(int dt, bool in_f64, bool vec, int id) {
+  for (auto& k : registry())
+    if (k.dt == dt && k.in_f64 == in_f64 && k.vec == vec && k.id == id) return &k;
+  return nullptr;
+}
+
+static int num_cus() {
+  static int n = [] {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 256;
+    return cus > 0 ? cus : 256;
+  }();
+  return n;
+}
+
+static std::mutex g_occ_mu;
+static int occupancy(KernelCfg* k) {
+  std::lock_guard<std::mutex> lk(g_occ_mu);
+  if (k->occ == 0) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k->fn, k->NT, 0) != hipSuccess || nb < 1) nb = 1;
+    k->occ = nb;
+  }
+  return k->occ;
+}
+
+// ---------------------------------------------------------------------------
+// the matrix handle
+// ---------------------------------------------------------------------------
+struct CoreDev {
+  int r_in, r_out, m, n;
+  int R_out, K_in;
+  int64_t C;          // columns of b_k per vector
+  int64_t out_len;    // elements of y_k per vector
+  int nRB;
+  int Ksteps[3];
+  void* frag[3];
+  int tuned[3];       // tuned shape id per dtype, -1 = heuristic
+};
+
+struct qtt_matrix_s {
+  int d = 0;
+  std::vector<int64_t> ranks, m, n;
+  int64_t rows = 0, cols = 0, max_rank = 0;
+  uint32_t dtypes = 0;
+  int device = 0;
+  std::vector<CoreDev> core;
+  int64_t max_inter = 0;  // largest y_k (k < d) per vector, elements
+};
+
+static bool valid_handle(qtt_matrix_t A) { return A != nullptr && A->d > 0; }
+
+// Process-wide table of tuned shapes, keyed by (dtype, R_out, K_in, r_out, C, nrhs bucket).
+static std::mutex g_tune_mu;
+static std::map<std::tuple<int, int, int, int, int64_t, int>, int> g_tuned;
+
+static int nrhs_bucket(int64_t nrhs) {
+  int b = 0;
+  while ((1LL << b) < nrhs && b < 40) ++b;
+  return b;
+}
+
+static int heuristic_shape(int R_out) {
+  if (R_out <= 16) return 2;
+  if (R_out <= 64) return kGenericShape;
+  if (R_out <= 128) return 4;
+  if (R_out <= 192) return 1;
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// timing
+// ---------------------------------------------------------------------------
+struct TimedLaunch {
+  hipEvent_t a, b;
+  int dt, pos;
+  double flops, bytes;
+};
+static thread_local bool g_timing = false;
+static thread_local std::vector<TimedLaunch> g_timed;
+static std::atomic<int> g_timing_env{-1};
+
+static bool timing_on() {
+  if (g_timing) return true;
+  int e = g_timing_env.load();
+  if (e < 0) {
+    const char* s = getenv("QTT_TIMING");
+    e = (s && s[0] == '1') ? 1 : 0;
+    g_timing_env.store(e);
+  }
+  return e == 1;
+}
+
+// ---------------------------------------------------------------------------
+// launching one core step
+// ---------------------------------------------------------------------------
+static qtt_status_t launch_step(const qtt_matrix_s* A, int k, int dt, int64_t nrhs,
+                                const Segment* segs, int nseg, const void* in_packed,
+                                void* out_packed, double alpha, hipStream_t st) {
+  const CoreDev& c = A->core[k];
+  const bool first = (k == 0), last = (k == A->d - 1);
+  const bool in_f64 = first || dt == 0;
+  const int in_bytes = in_f64 ? 8 : kElemBytes[dt];
+  const int ve = 16 / in_bytes;
+
+  // 16-byte loads need every column start aligned
+  bool vec = (c.K_in % ve) == 0;
+  if (first) {
+    for (int s = 0; s < nseg && vec; ++s)
+      vec = (reinterpret_cast<uintptr_t>(segs[s].x) % 16 == 0) && (segs[s].ldx % ve == 0);
+  } else {
+    vec = vec && (reinterpret_cast<uintptr_t>(in_packed) % 16 == 0);
+  }
+  int shape = c.tuned[dt];
+  if (shape < 0) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(std::make_tuple(dt, c.R_out, c.K_in, c.r_out, c.C, nrhs_bucket(nrhs)));
+    shape = (it != g_tuned.end()) ? it->second : heuristic_shape(c.R_out);
+  }
+  KernelCfg* kc = vec ? find_cfg(dt, in_f64, true, shape) : find_cfg(dt, in_f64, false, kGenericShape);
+  if (!kc) return fail(QTT_ERR_DEVICE, "no kernel for dtype %d shape %d", dt, shape);
+
+  StepArgs a;
+  memset(&a, 0, sizeof(a));
+  a.M = c.frag[dt];
+  a.in = in_packed;
+  a.out = out_packed;
+  a.C = c.C;
+  a.in_stride = c.C * c.K_in;
+  a.out_stride = c.out_len;
+  a.ncols = c.C * nrhs;
+  a.R_out = c.R_out;
+  a.K_in = c.K_in;
+  a.r_out = c.r_out;
+  a.Ksteps = c.Ksteps[dt];
+  a.nRB = c.nRB;
+  a.n_row_tiles = (c.R_out + kc->TR - 1) / kc->TR;
+  const int64_t col_tiles = (a.ncols + kc->TC - 1) / kc->TC;
+  a.n_tiles = col_tiles * a.n_row_tiles;
+  a.in_table = first ? 1 : 0;
+  a.out_table = last ? 1 : 0;
+  a.nseg = nseg;
+  a.alpha = alpha;
+  for (int s = 0; s < nseg; ++s) a.seg[s] = segs[s];
+
+  const int64_t resident = (int64_t)occupancy(kc) * num_cus();
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(a.n_tiles, resident));
+
+  TimedLaunch tl;
+  const bool timed = timing_on();
+  if (timed) {
+    HIP_TRY(hipEventCreate(&tl.a));
+    HIP_TRY(hipEventCreate(&tl.b));
+    HIP_TRY(hipEventRecord(tl.a, st));
+  }
+  void* args[] = {&a};
+  HIP_TRY(hipLaunchKernel(kc->fn, dim3(grid), dim3(kc->NT), args, 0, st));
+  if (timed) {
+    HIP_TRY(hipEventRecord(tl.b, st));
+    tl.dt = dt;
+    tl.pos = (A->d == 1) ? 3 : (first ? 1 : (last ? 2 : 0));
+    const double colsd = (double)a.ncols;
+    tl.flops = 2.0 * c.R_out * c.K_in * colsd;
+    const double ib = first ? 8.0 : kElemBytes[dt];
+    const double ob = last ? 8.0 : kElemBytes[dt];
+    tl.bytes = colsd * (c.K_in * ib + (double)c.R_out * ob);
+    if (last) {
+      bool z = false;
+      for (int s = 0; s < nseg; ++s) z = z || segs[s].z != nullptr;
+      if (z) tl.bytes += colsd * c.R_out * 8.0;
+    }
+    g_timed.push_back(tl);
+  }
+  return QTT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// one sweep over a wave of vectors described by segments
+// ---------------------------------------------------------------------------
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static size_t wave_buffer_bytes(const qtt_matrix_s* A, int dt, int64_t nrhs) {
+  return align256((size_t)A->max_inter * kElemBytes[dt] * (size_t)nrhs);
+}
+
+static int64_t wave_capacity(const qtt_matrix_s* A, int dt, size_t ws_bytes) {
+  if (A->d == 1) return INT64_MAX;
+  const size_t per = (size_t)A->max_inter * kElemBytes[dt];
+  if (per == 0) return INT64_MAX;
+  // two buffers, each 256-byte aligned
+  if (ws_bytes < 2 * align256(per)) return 0;
+  int64_t w = (int64_t)(ws_bytes / (2 * per));
+  while (w > 0 && 2 * wave_buffer_bytes(A, dt, w) > ws_bytes) --w;
+  return w;
+}
+
+static qtt_status_t sweep(const qtt_matrix_s* A, int dt, int64_t nrhs, const Segment* segs, int nseg,
+                          void* ws, double alpha, hipStream_t st) {
+  void* buf[2] = {ws, nullptr};
+  if (A->d > 1) buf[1] = static_cast<char*>(ws) + wave_buffer_bytes(A, dt, nrhs);
+  for (int k = 0; k < A->d; ++k) {
+    const void* in = (k == 0) ? nullptr : buf[(k - 1) & 1];
+    void* out = (k == A->d - 1) ? nullptr : buf[k & 1];
+    qtt_status_t s = launch_step(A, k, dt, nrhs, segs, nseg, in, out, alpha, st);
+    if (s != QTT_OK) return s;
+  }
+  return QTT_OK;
+}
+
+// A block of vectors before splitting into waves.
+struct Block {
+  const double* x;
+  double* y;
+  const double* z;
+  int64_t ldx, ldy, ldz, width;
+};
+
+// Run y = z + alpha * A x over blocks, in waves bounded by the workspace and
+// by the segment-table size.
+static qtt_status_t run_blocks(const qtt_matrix_s* A, int dt, const std::vector<Block>& blocks,
+                               void* ws, size_t ws_bytes, double alpha, hipStream_t st) {
+  int64_t total = 0;
+  for (auto& b : blocks) total += b.width;
+  if (total == 0) return QTT_OK;
+  const int64_t cap = wave_capacity(A, dt, ws_bytes);
+  if (cap < 1) {
+    size_t need = 2 * wave_buffer_bytes(A, dt, 1);
+    return fail(QTT_ERR_WORKSPACE, "workspace of %zu bytes is below the one-vector minimum %zu", ws_bytes, need);
+  }
+  std::vector<Segment> segs;
+  int64_t in_wave = 0;
+  auto flush = [&]() -> qtt_status_t {
+    if (in_wave == 0) return QTT_OK;
+    qtt_status_t s = sweep(A, dt, in_wave, segs.data(), (int)segs.size(), ws, alpha, st);
+    segs.clear();
+    in_wave = 0;
+    return s;
+  };
+  for (auto& b : blocks) {
+    int64_t done = 0;
+    while (done < b.width) {
+      if (in_wave == cap || (int)segs.size() == kMaxSeg) {
+        qtt_status_t s = flush();
+        if (s != QTT_OK) return s;
+      }
+      const int64_t take = std::min(b.width - done, cap - in_wave);
+      Segment sg;
+      sg.x = b.x + done * b.ldx;
+      sg.y = b.y + done * b.ldy;
+      sg.z = b.z ? b.z + done * b.ldz : nullptr;
+      sg.ldx = b.ldx;
+      sg.ldy = b.ldy;
+      sg.ldz = b.ldz;
+      sg.rhs_begin = in_wave;
+      segs.push_back(sg);
+      in_wave += take;
+      done += take;
+    }
+  }
+  return flush();
+}
+
+static bool overlaps(const void* a, size_t an, const void* b, size_t bn) {
+  const char* pa = static_cast<const char*>(a);
+  const char* pb = static_cast<const char*>(b);
+  return pa < pb + bn && pb < pa + an;
+}
+
+static qtt_status_t check_dtype(const qtt_matrix_s* A, qtt_dtype_t t, int* dt) {
+  *dt = dt_index(t);
+  if (*dt < 0) return fail(QTT_ERR_INVALID_ARG, "unknown compute dtype %d", (int)t);
+  if (!(A->dtypes & (uint32_t)t)) return fail(QTT_ERR_DTYPE, "matrix was not loaded with dtype %d", (int)t);
+  return QTT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* qtt_status_string(qtt_status_t s) {
+  switch (s) {
+    case QTT_OK: return "ok";
+    case QTT_ERR_INVALID_ARG: return "invalid argument";
+    case QTT_ERR_SHAPE: return "inconsistent shape";
+    case QTT_ERR_OUT_OF_MEMORY: return "out of device memory";
+    case QTT_ERR_DEVICE: return "HIP error";
+    case QTT_ERR_NOT_CONVERGED: return "not converged";
+    case QTT_ERR_NONFINITE: return "non-finite residual";
+    case QTT_ERR_WORKSPACE: return "workspace too small";
+    case QTT_ERR_DTYPE: return "dtype not loaded";
+  }
+  return "unknown status";
+}
+
+const char* qtt_last_error(void) { return g_last_error.c_str(); }
+
+qtt_status_t qtt_matrix_load(int32_t d, const int64_t* ranks, const int64_t* m, const int64_t* n,
+                             const double* const* cores, uint32_t dtypes, qtt_matrix_t* out) {
+  if (out == nullptr) return fail(QTT_ERR_INVALID_ARG, "out is null");
+  *out = nullptr;
+  if (d < 1 || d > 64) return fail(QTT_ERR_INVALID_ARG, "d = %d outside [1, 64]", d);
+  if (!ranks || !m || !n || !cores) return fail(QTT_ERR_INVALID_ARG, "null shape or core array");
+  if (dtypes == 0 || (dtypes & ~7u)) return fail(QTT_ERR_INVALID_ARG, "dtypes must be a non-empty OR of QTT_FP64/FP32/BF16");
+  if (ranks[0] != 1 || ranks[d] != 1) return fail(QTT_ERR_SHAPE, "boundary ranks must be 1");
+  for (int k = 0; k < d; ++k) {
+    if (ranks[k + 1] < 1 || m[k] < 1 || n[k] < 1) return fail(QTT_ERR_SHAPE, "core %d: ranks and modes must be >= 1", k);
+    if (!cores[k]) return fail(QTT_ERR_INVALID_ARG, "core %d pointer is null", k);
+    if (ranks[k] * m[k] > (1 << 20) || ranks[k] * n[k] > (1 << 20) || ranks[k + 1] * m[k] > (1 << 20))
+      return fail(QTT_ERR_SHAPE, "core %d too large", k);
+  }
+  // vector lengths (guard overflow)
+  double rows = 1, cols = 1;
+  for (int k = 0; k < d; ++k) { rows *= (double)m[k]; cols *= (double)n[k]; }
+  if (rows > 4e15 || cols > 4e15) return fail(QTT_ERR_SHAPE, "vector length overflows");
+
+  qtt_matrix_s* A = new qtt_matrix_s();
+  A->d = d;
+  A->ranks.assign(ranks, ranks + d + 1);
+  A->m.assign(m, m + d);
+  A->n.assign(n, n + d);
+  A->rows = 1;
+  A->cols = 1;
+  for (int k = 0; k < d; ++k) { A->rows *= m[k]; A->cols *= n[k]; }
+  A->max_rank = *std::max_element(ranks, ranks + d + 1);
+  A->dtypes = dtypes;
+  (void)hipGetDevice(&A->device);
+  A->core.resize(d);
+
+  for (int k = 0; k < d; ++k) {
+    CoreDev& c = A->core[k];
+    c.r_in = (int)ranks[k];
+    c.r_out = (int)ranks[k + 1];
+    c.m = (int)m[k];
+    c.n = (int)n[k];
+    c.R_out = c.r_out * c.m;
+    c.K_in = c.r_in * c.n;
+    int64_t lo = 1, hi = 1;
+    for (int l = 0; l < k; ++l) lo *= m[l];
+    for (int l = k + 1; l < d; ++l) hi *= n[l];
+    c.C = lo * hi;
+    c.out_len = (int64_t)c.r_out * c.C * c.m;
+    c.nRB = (c.R_out + 15) / 16;
+    for (int t = 0; t < 3; ++t) { c.frag[t] = nullptr; c.Ksteps[t] = 0; c.tuned[t] = -1; }
+    if (k < d - 1) A->max_inter = std::max(A->max_inter, c.out_len);
+  }
+
+  // re-layout: fragment (row block rb, step s, lane l, element e) holds
+  // M_k(16 rb + l mod 16, KSTEP s + E (l div 16) + e), zero outside the matrix.
+  for (int k = 0; k < d; ++k) {
+    CoreDev& c = A->core[k];
+    const double* G = cores[k];
+    for (int t = 0; t < 3; ++t) {
+      if (!(dtypes & (1u << t))) continue;
+      const int KS = kKstep[t], E = kFragE[t];
+      const int Ksteps = (c.K_in + KS - 1) / KS;
+      c.Ksteps[t] = Ksteps;
+      const size_t nel = (size_t)c.nRB * Ksteps * 64 * E;
+      std::vector<double> h(nel, 0.0);
+      for (int rb = 0; rb < c.nRB; ++rb)
+        for (int s = 0; s < Ksteps; ++s)
+          for (int l = 0; l < 64; ++l)
+            for (int e = 0; e < E; ++e) {
+              const int row = 16 * rb + (l & 15);
+              const int kap = KS * s + E * (l >> 4) + e;
+              if (row >= c.R_out || kap >= c.K_in) continue;
+              const int ak = row % c.r_out, ik = row / c.r_out;   // row = a_k + r_k i_k
+              const int ap = kap % c.r_in, jk = kap / c.r_in;     // kap = a_{k-1} + r_{k-1} j_k
+              h[(((size_t)rb * Ksteps + s) * 64 + l) * E + e] =
+                  G[(((size_t)ap * c.m + ik) * c.n + jk) * c.r_out + ak];
+            }
+      const size_t bytes = nel * kElemBytes[t];
+      void* dptr = nullptr;
+      if (hipMalloc(&dptr, std::max<size_t>(bytes, 256)) != hipSuccess) {
+        qtt_matrix_free(A);
+        return fail(QTT_ERR_OUT_OF_MEMORY, "hipMalloc of %zu bytes for core %d failed", bytes, k);
+      }
+      c.frag[t] = dptr;
+      hipError_t e;
+      if (t == 0) {
+        e = hipMemcpy(dptr, h.data(), bytes, hipMemcpyHostToDevice);
+      } else if (t == 1) {
+        std::vector<float> f(nel);
+        for (size_t i = 0; i < nel; ++i) f[i] = (float)h[i];
+        e = hipMemcpy(dptr, f.data(), bytes, hipMemcpyHostToDevice);
+      } else {
+        std::vector<uint16_t> b(nel);
+        for (size_t i = 0; i < nel; ++i) b[i] = f32_to_bf16_rne((float)h[i]);
+        e = hipMemcpy(dptr, b.data(), bytes, hipMemcpyHostToDevice);
+      }
+      if (e != hipSuccess) {
+        qtt_matrix_free(A);
+        return fail(QTT_ERR_DEVICE, "hipMemcpy of core %d failed: %s", k, hipGetErrorString(e));
+      }
+    }
+  }
+  *out = A;
+  return QTT_OK;
+}
+
+qtt_status_t qtt_matrix_free(qtt_matrix_t A) {
+  if (A == nullptr) return QTT_OK;
+  for (auto& c : A->core)
+    for (int t = 0; t < 3; ++t)
+      if (c.frag[t]) (void)hipFree(c.frag[t]);
+  delete A;
+  return QTT_OK;
+}
+
+qtt_status_t qtt_matrix_info(qtt_matrix_t A, int32_t* d, int64_t* rows, int64_t* cols,
+                             int64_t* max_rank, uint32_t* dtypes) {
+  if (!valid_handle(A)) return fail(QTT_ERR_INVALID_ARG, "null handle");
+  if (d) *d = A->d;
+  if (rows) *rows = A->rows;
+  if (cols) *cols = A->cols;
+  if (max_rank) *max_rank = A->max_rank;
+  if (dtypes) *dtypes = A->dtypes;
+  return QTT_OK;
+}
+
+qtt_status_t qtt_workspace_bytes(qtt_matrix_t A, qtt_dtype_t compute, int64_t nrhs, size_t* bytes) {
+  if (!valid_handle(A) || !bytes) return fail(QTT_ERR_INVALID_ARG, "null handle or output");
+  if (nrhs < 0) return fail(QTT_ERR_INVALID_ARG, "nrhs < 0");
+  int dt;
+  qtt_status_t s = check_dtype(A, compute, &dt);
+  if (s != QTT_OK) return s;
+  *bytes = (A->d == 1) ? 0 : 2 * wave_buffer_bytes(A, dt, std::max<int64_t>(nrhs, 1));
+  return QTT_OK;
+}
+
+qtt_status_t qtt_apply(qtt_matrix_t A, qtt_dtype_t compute, int64_t nrhs, const double* X, int64_t ldx,
+                       double* Y, int64_t ldy, void* ws, size_t ws_bytes, void* stream) {
+  if (!valid_handle(A)) return fail(QTT_ERR_INVALID_ARG, "null handle");
+  int dt;
+  qtt_status_t s = check_dtype(A, compute, &dt);
+  if (s != QTT_OK) return s;
+  if (nrhs < 0) return fail(QTT_ERR_INVALID_ARG, "nrhs < 0");
+  if (nrhs == 0) return QTT_OK;
+  if (!X || !Y) return fail(QTT_ERR_INVALID_ARG, "X or Y is null");
+  if (ldx < A->cols || ldy < A->rows) return fail(QTT_ERR_INVALID_ARG, "ldx < N or ldy < M");
+  if (A->d > 1 && !ws) return fail(QTT_ERR_INVALID_ARG, "workspace is null");
+  const size_t xb = ((size_t)(nrhs - 1) * ldx + A->cols) * 8, yb = ((size_t)(nrhs - 1) * ldy + A->rows) * 8;
+  if (overlaps(X, xb, Y, yb)) return fail(QTT_ERR_INVALID_ARG, "X and Y overlap");
+  if (ws && (overlaps(ws, ws_bytes, X, xb) || overlaps(ws, ws_bytes, Y, yb)))
+    return fail(QTT_ERR_INVALID_ARG, "workspace overlaps X or Y");
+  std::vector<Block> blocks{{X, Y, nullptr, ldx, ldy, 0, nrhs}};
+  return run_blocks(A, dt, blocks, ws, ws_bytes, 1.0, static_cast<hipStream_t>(stream));
+}
+
+qtt_status_t qtt_apply_batched(qtt_matrix_t A, qtt_dtype_t compute, int32_t nblocks, const int64_t* widths,
+                               const double* const* X, const int64_t* ldx, double* const* Y,
+                               const int64_t* ldy, void* ws, size_t ws_bytes, void* stream) {
+  if (!valid_handle(A)) return fail(QTT_ERR_INVALID_ARG, "null handle");
+  int dt;
+  qtt_status_t s = check_dtype(A, compute, &dt);
+  if (s != QTT_OK) return s;
+  if (nblocks < 0) return fail(QTT_ERR_INVALID_ARG, "nblocks < 0");
+  if (nblocks == 0) return QTT_OK;
+  if (!widths || !X || !ldx || !Y || !ldy) return fail(QTT_ERR_INVALID_ARG, "null block array");
+  if (A->d > 1 && !ws) return fail(QTT_ERR_INVALID_ARG, "workspace is null");
+  std::vector<Block> blocks;
+  std::vector<std::pair<const void*, size_t>> xs, ys;
+  for (int b = 0; b < nblocks; ++b) {
+    if (widths[b] < 0) return fail(QTT_ERR_INVALID_ARG, "block %d has negative width", b);
+    if (widths[b] == 0) continue;
+    if (!X[b] || !Y[b]) return fail(QTT_ERR_INVALID_ARG, "block %d has a null pointer", b);
+    if (ldx[b] < A->cols || ldy[b] < A->rows) return fail(QTT_ERR_INVALID_ARG, "block %d: ld too small", b);
+    blocks.push_back({X[b], Y[b], nullptr, ldx[b], ldy[b], 0, widths[b]});
+    xs.push_back({X[b], ((size_t)(widths[b] - 1) * ldx[b] + A->cols) * 8});
+    ys.push_back({Y[b], ((size_t)(widths[b] - 1) * ldy[b] + A->rows) * 8});
+  }
+  for (auto& y : ys) {
+    for (auto& x : xs)
+      if (overlaps(y.first, y.second, x.first, x.second)) return fail(QTT_ERR_INVALID_ARG, "an output block overlaps an input block");
+    if (ws && overlaps(ws, ws_bytes, y.first, y.second)) return fail(QTT_ERR_INVALID_ARG, "workspace overlaps an output block");
+  }
+  return run_blocks(A, dt, blocks, ws, ws_bytes, 1.0, static_cast<hipStream_t>(stream));
+}
+
+qtt_status_t qtt_autotune(qtt_matrix_t A, qtt_dtype_t compute, int64_t nrhs, const double* X, int64_t ldx,
+                          double* Y, int64_t ldy, void* ws, size_t ws_bytes, void* stream) {
+  qtt_status_t s = qtt_apply(A, compute, nrhs, X, ldx, Y, ldy, ws, ws_bytes, stream);  // validates, warms up
+  if (s != QTT_OK) return s;
+  int dt = dt_index(compute);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int64_t cap = wave_capacity(A, dt, ws_bytes);
+  const int64_t w = std::min<int64_t>(nrhs, cap);
+  Segment sg;
+  sg.x = X; sg.y = Y; sg.z = nullptr; sg.ldx = ldx; sg.ldy = ldy; sg.ldz = 0; sg.rhs_begin = 0;
+  void* buf[2] = {ws, (A->d > 1) ? static_cast<char*>(ws) + wave_buffer_bytes(A, dt, w) : nullptr};
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  const bool was_timing = g_timing;
+  g_timing = false;
+  for (int k = 0; k < A->d; ++k) {
+    CoreDev& c = A->core[k];
+    const void* in = (k == 0) ? nullptr : buf[(k - 1) & 1];
+    void* out = (k == A->d - 1) ? nullptr : buf[k & 1];
+    float best = 1e30f;
+    int best_id = -1;
+    for (int id = 0; id < kNumShapes; ++id) {
+      c.tuned[dt] = id;
+      for (int rep = 0; rep < 2; ++rep) {           // warm-up + timed
+        HIP_TRY(hipEventRecord(e0, st));
+        for (int it = 0; it < 3; ++it) {
+          s = launch_step(A, k, dt, w, &sg, 1, in, out, 1.0, st);
+          if (s != QTT_OK) { g_timing = was_timing; return s; }
+        }
+        HIP_TRY(hipEventRecord(e1, st));
+      }
+      HIP_TRY(hipEventSynchronize(e1));
+      float ms = 0;
+      HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best) { best = ms; best_id = id; }
+    }
+    c.tuned[dt] = best_id;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned[std::make_tuple(dt, c.R_out, c.K_in, c.r_out, c.C, nrhs_bucket(nrhs))] = best_id;
+  }
+  g_timing = was_timing;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  // leave Y = A X computed with the tuned shapes
+  s = qtt_apply(A, compute, nrhs, X, ldx, Y, ldy, ws, ws_bytes, stream);
+  if (s != QTT_OK) return s;
+  HIP_TRY(hipStreamSynchronize(st));
+  return QTT_OK;
+}
+
+// --------------------------------------------------------------------------- solve
+
+static size_t solve_extra_bytes(const qtt_matrix_s* A, int64_t nrhs) {
+  return align256((size_t)A->rows * nrhs * 8)                 // residual R
+         + align256((size_t)nrhs * kNormBlocks * 8)            // norm partials
+         + align256((size_t)nrhs * 8);                         // norms
+}
+
+qtt_status_t qtt_solve_workspace_bytes(qtt_matrix_t A, qtt_matrix_t Ainv, qtt_dtype_t inv_compute,
+                                       int64_t nrhs, size_t* bytes) {
+  if (!valid_handle(A) || !valid_handle(Ainv) || !bytes) return fail(QTT_ERR_INVALID_ARG, "null handle or output");
+  int dt;
+  qtt_status_t s = check_dtype(Ainv, inv_compute, &dt);
+  if (s != QTT_OK) return s;
+  s = check_dtype(A, QTT_FP64, &dt);
+  if (s != QTT_OK) return s;
+  const int64_t k = std::max<int64_t>(nrhs, 1);
+  size_t wa = 0, wi = 0;
+  qtt_workspace_bytes(A, QTT_FP64, k, &wa);
+  qtt_workspace_bytes(Ainv, inv_compute, k, &wi);
+  *bytes = std::max(wa, wi) + solve_extra_bytes(A, k);
+  return QTT_OK;
+}
+
+static qtt_status_t column_norms(const std::vector<const double*>& cols, const std::vector<int64_t>& lds_,
+                                 int64_t N, double* partial, double* dnorm, std::vector<double>& host,
+                                 hipStream_t st) {
+  // one launch per kMaxSeg columns (each column is its own segment)
+  const int ncol = (int)cols.size();
+  host.assign(ncol, 0.0);
+  for (int c0 = 0; c0 < ncol; c0 += kMaxSeg) {
+    NormArgs na;
+    memset(&na, 0, sizeof(na));
+    const int nc = std::min(kMaxSeg, ncol - c0);
+    for (int t = 0; t < nc; ++t) {
+      na.R[t] = cols[c0 + t];
+      na.ld[t] = lds_[c0 + t];
+      na.col_begin[t] = t;
+    }
+    na.nseg = nc;
+    na.ncol = nc;
+    na.N = N;
+    na.partial = partial;
+    void* args[] = {&na};
+    HIP_TRY(hipLaunchKernel(reinterpret_cast<const void*>(&colnorm_partial_kernel), dim3(kNormBlocks, nc),
+                            dim3(kNormThreads), args, 0, st));
+    const double* pp = partial;
+    int ncv = nc;
+    double* dn = dnorm;
+    void* args2[] = {&pp, &ncv, &dn};
+    HIP_TRY(hipLaunchKernel(reinterpret_cast<const void*>(&colnorm_final_kernel), dim3((nc + 63) / 64), dim3(64),
+                            args2, 0, st));
+    HIP_TRY(hipMemcpyAsync(host.data() + c0, dnorm, nc * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+  }
+  return QTT_OK;
+}
+
+qtt_status_t qtt_solve(qtt_matrix_t A, qtt_matrix_t Ainv, qtt_dtype_t inv_compute, int64_t nrhs,
+                       const double* F, int64_t ldf, double* Sigma, int64_t lds, double rtol,
+                       int32_t max_iter, void* ws, size_t ws_bytes, void* stream, qtt_solve_col_t* info) {
+  if (!valid_handle(A) || !valid_handle(Ainv)) return fail(QTT_ERR_INVALID_ARG, "null handle");
+  int dti, dta;
+  qtt_status_t s = check_dtype(Ainv, inv_compute, &dti);
+  if (s != QTT_OK) return s;
+  s = check_dtype(A, QTT_FP64, &dta);
+  if (s != QTT_OK) return s;
+  if (A->d != Ainv->d) return fail(QTT_ERR_SHAPE, "A and Ainv have different core counts");
+  for (int k = 0; k < A->d; ++k)
+    if (A->m[k] != A->n[k] || Ainv->m[k] != A->m[k] || Ainv->n[k] != A->n[k])
+      return fail(QTT_ERR_SHAPE, "solve needs square, identical modes (core %d)", k);
+  if (nrhs < 0 || max_iter < 1 || !(rtol >= 0)) return fail(QTT_ERR_INVALID_ARG, "bad nrhs, max_iter or rtol");
+  if (nrhs == 0) return QTT_OK;
+  if (!F || !Sigma || !ws) return fail(QTT_ERR_INVALID_ARG, "null F, Sigma or workspace");
+  const int64_t N = A->rows;
+  if (ldf < N || lds < N) return fail(QTT_ERR_INVALID_ARG, "ldf or lds < N");
+  const size_t fb = ((size_t)(nrhs - 1) * ldf + N) * 8, sb = ((size_t)(nrhs - 1) * lds + N) * 8;
+  if (overlaps(F, fb, Sigma, sb)) return fail(QTT_ERR_INVALID_ARG, "F and Sigma overlap");
+  // carve the workspace: [R | partial | norms | apply workspace]
+  const size_t extra = solve_extra_bytes(A, nrhs);
+  size_t need1 = 0, tmp = 0;
+  qtt_workspace_bytes(A, QTT_FP64, 1, &need1);
+  qtt_workspace_bytes(Ainv, inv_compute, 1, &tmp);
+  need1 = std::max(need1, tmp);
+  if (ws_bytes < extra + need1)
+    return fail(QTT_ERR_WORKSPACE, "solve workspace %zu < minimum %zu", ws_bytes, extra + need1);
+  if (overlaps(ws, ws_bytes, F, fb) || overlaps(ws, ws_bytes, Sigma, sb))
+    return fail(QTT_ERR_INVALID_ARG, "workspace overlaps F or Sigma");
+  char* p = static_cast<char*>(ws);
+  double* R = reinterpret_cast<double*>(p);
+  p += align256((size_t)N * nrhs * 8);
+  double* partial = reinterpret_cast<double*>(p);
+  p += align256((size_t)nrhs * kNormBlocks * 8);
+  double* dnorm = reinterpret_cast<double*>(p);
+  p += align256((size_t)nrhs * 8);
+  void* aws = p;
+  const size_t aws_bytes = ws_bytes - extra;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+
+  std::vector<const double*> fcols(nrhs);
+  std::vector<int64_t> fld(nrhs, ldf);
+  for (int64_t c = 0; c < nrhs; ++c) fcols[c] = F + c * ldf;
+  std::vector<double> fn, rn;
+  s = column_norms(fcols, fld, N, partial, dnorm, fn, st);
+  if (s != QTT_OK) return s;
+  for (int64_t c = 0; c < nrhs; ++c) {
+    if (!std::isfinite(fn[c])) return fail(QTT_ERR_NONFINITE, "column %lld of F is not finite", (long long)c);
+    if (info) { info[c].iters = 0; info[c].rel_residual = (fn[c] > 0) ? 1.0 : 0.0; }
+  }
+  // columns still iterating; a converged column is frozen
+  std::vector<char> active(nrhs, 1);
+  int64_t n_active = nrhs;
+  std::vector<int> iters(nrhs, 0);
+  for (int it = 1; it <= max_iter && n_active > 0; ++it) {
+    // runs of consecutive active columns
+    std::vector<std::pair<int64_t, int64_t>> runs;
+    for (int64_t c = 0; c < nrhs;) {
+      if (!active[c]) { ++c; continue; }
+      int64_t e = c;
+      while (e < nrhs && active[e]) ++e;
+      runs.push_back({c, e - c});
+      c = e;
+    }
+    // sigma += Ainv r  (first pass: sigma = Ainv F)
+    std::vector<Block> bi, ba;
+    for (auto& r : runs) {
+      if (it == 1) bi.push_back({F + r.first * ldf, Sigma + r.first * lds, nullptr, ldf, lds, 0, r.second});
+      else bi.push_back({R + r.first * N, Sigma + r.first * lds, Sigma + r.first * lds, N, lds, lds, r.second});
+      // r = F - A sigma, residual fused into A's last core
+      ba.push_back({Sigma + r.first * lds, R + r.first * N, F + r.first * ldf, lds, N, ldf, r.second});
+    }
+    s = run_blocks(Ainv, dti, bi, aws, aws_bytes, 1.0, st);
+    if (s != QTT_OK) return s;
+    s = run_blocks(A, dta, ba, aws, aws_bytes, -1.0, st);
+    if (s != QTT_OK) return s;
+    std::vector<const double*> rc;
+    std::vector<int64_t> rld;
+    std::vector<int64_t> idx;
+    for (int64_t c = 0; c < nrhs; ++c)
+      if (active[c]) { rc.push_back(R + c * N); rld.push_back(N); idx.push_back(c); }
+    s = column_norms(rc, rld, N, partial, dnorm, rn, st);
+    if (s != QTT_OK) return s;
+    for (size_t t = 0; t < idx.size(); ++t) {
+      const int64_t c = idx[t];
+      iters[c] = it;
+      const double rel = (fn[c] > 0) ? rn[t] / fn[c] : rn[t];
+      if (info) { info[c].iters = it; info[c].rel_residual = rel; }
+      if (!std::isfinite(rel)) return fail(QTT_ERR_NONFINITE, "residual of column %lld is not finite", (long long)c);
+      if (rel <= rtol) { active[c] = 0; --n_active; }
+    }
+  }
+  if (n_active > 0) return fail(QTT_ERR_NOT_CONVERGED, "%lld columns above rtol after %d passes", (long long)n_active, max_iter);
+  return QTT_OK;
+}
+
+// --------------------------------------------------------------------------- timing
+
+qtt_status_t qtt_timing_enable(int32_t on) {
+  g_timing = on != 0;
+  return QTT_OK;
+}
+
+qtt_status_t qtt_timing_reset(void) {
+  for (auto& t : g_timed) {
+    (void)hipEventDestroy(t.a);
+    (void)hipEventDestroy(t.b);
+  }
+  g_timed.clear();
+  return QTT_OK;
+}
+
+qtt_status_t qtt_timing_read(qtt_dtype_t compute, int32_t position, int64_t* launches, double* milliseconds,
+                             double* flops, double* bytes) {
+  const int dt = dt_index(compute);
+  if (dt < 0 || position < 0 || position > 3) return fail(QTT_ERR_INVALID_ARG, "bad dtype or position");
+  int64_t n = 0;
+  double ms = 0, fl = 0, by = 0;
+  for (auto& t : g_timed) {
+    if (t.dt != dt || t.pos != position) continue;
+    HIP_TRY(hipEventSynchronize(t.b));
+    float e = 0;
+    HIP_TRY(hipEventElapsedTime(&e, t.a, t.b));
+    ++n;
+    ms += e;
+    fl += t.flops;
+    by += t.bytes;
+  }
+  if (launches) *launches = n;
+  if (milliseconds) *milliseconds = ms;
+  if (flops) *flops = fl;
+  if (bytes) *bytes = by;
+  return QTT_OK;
+}
+
+}  // extern "C"

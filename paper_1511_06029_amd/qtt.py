@@ -1,0 +1,285 @@
+"""Python binding of libqtt (ctypes).  Argument marshalling only: every step of
+the apply and of the solve runs in the HIP library.  PyTorch supplies device
+memory and streams.
+
+Vectors are FP64 CUDA tensors.  A block of K vectors of length N is an
+(N, K) tensor in column-major layout (``stride(0) == 1``, column stride
+``stride(1) >= N``), e.g. ``empty_block(N, K)``; a single vector may be 1-D.
+
+Importing this module loads ``libqtt.so`` from the package directory and
+raises if it has not been built (``python -m paper_1511_06029_amd.build_lib``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libqtt.so")
+
+QTT_FP64, QTT_FP32, QTT_BF16 = 1, 2, 4
+DTYPES = {"fp64": QTT_FP64, "fp32": QTT_FP32, "bf16": QTT_BF16}
+
+QTT_OK = 0
+QTT_ERR_NOT_CONVERGED = 5
+QTT_ERR_NONFINITE = 6
+
+
+class QttError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"libqtt error {status}: {message}")
+        self.status = status
+
+
+class _SolveCol(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("rel_residual", ctypes.c_double)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_1511_06029_amd.build_lib` (hipcc, gfx950)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, U32, SZ, D = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
+                               ctypes.c_uint32, ctypes.c_size_t, ctypes.c_double)
+    PP = ctypes.POINTER(ctypes.c_void_p)
+    PI64 = ctypes.POINTER(ctypes.c_int64)
+    sig = {
+        "qtt_matrix_load": [I32, PI64, PI64, PI64, PP, U32, PP],
+        "qtt_matrix_free": [P],
+        "qtt_matrix_info": [P, ctypes.POINTER(I32), PI64, PI64, PI64, ctypes.POINTER(U32)],
+        "qtt_workspace_bytes": [P, I32, I64, ctypes.POINTER(SZ)],
+        "qtt_apply": [P, I32, I64, P, I64, P, I64, P, SZ, P],
+        "qtt_apply_batched": [P, I32, I32, PI64, PP, PI64, PP, PI64, P, SZ, P],
+        "qtt_autotune": [P, I32, I64, P, I64, P, I64, P, SZ, P],
+        "qtt_solve_workspace_bytes": [P, P, I32, I64, ctypes.POINTER(SZ)],
+        "qtt_solve": [P, P, I32, I64, P, I64, P, I64, D, I32, P, SZ, P, ctypes.POINTER(_SolveCol)],
+        "qtt_timing_enable": [I32],
+        "qtt_timing_reset": [],
+        "qtt_timing_read": [I32, I32, PI64, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(D)],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    lib.qtt_status_string.argtypes = [ctypes.c_int]
+    lib.qtt_status_string.restype = ctypes.c_char_p
+    lib.qtt_last_error.argtypes = []
+    lib.qtt_last_error.restype = ctypes.c_char_p
+    return lib
+
+
+_lib = _load()
+# Names the C ABI exports (include/qtt.h); the tests check each is present.
+EXPORTED = ["qtt_matrix_load", "qtt_matrix_free", "qtt_matrix_info", "qtt_workspace_bytes",
+            "qtt_apply", "qtt_apply_batched", "qtt_autotune", "qtt_solve_workspace_bytes",
+            "qtt_solve", "qtt_status_string", "qtt_last_error", "qtt_timing_enable",
+            "qtt_timing_reset", "qtt_timing_read"]
+
+
+def lib():
+    return _lib
+
+
+def _check(status, allow=()):
+    if status != QTT_OK and status not in allow:
+        raise QttError(status, _lib.qtt_last_error().decode())
+    return status
+
+
+def _dtype(compute):
+    if isinstance(compute, str):
+        return DTYPES[compute]
+    return int(compute)
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _col_major(T, name):
+    """(ptr, rows, ncols, ld) of an FP64 CUDA tensor in column-major layout."""
+    if not isinstance(T, torch.Tensor) or not T.is_cuda or T.dtype != torch.float64:
+        raise TypeError(f"{name} must be an FP64 CUDA tensor")
+    if T.dim() == 1:
+        if T.stride(0) != 1:
+            raise ValueError(f"{name} must be contiguous")
+        return T.data_ptr(), T.shape[0], 1, T.shape[0]
+    if T.dim() != 2 or (T.stride(0) != 1 and T.shape[0] > 1):
+        raise ValueError(f"{name} must be an (N, K) column-major tensor (stride(0) == 1)")
+    ld = T.stride(1) if T.shape[1] > 1 else T.shape[0]
+    return T.data_ptr(), T.shape[0], T.shape[1], max(ld, T.shape[0])
+
+
+def empty_block(N, K, device="cuda"):
+    """Uninitialised (N, K) FP64 column-major tensor."""
+    return torch.empty((K, N), dtype=torch.float64, device=device).t()
+
+
+def to_block(X_np, device="cuda"):
+    """Column-major device copy of a host (N,) or (N, K) array."""
+    X_np = np.asarray(X_np, dtype=np.float64)
+    if X_np.ndim == 1:
+        return torch.from_numpy(X_np.copy()).to(device)
+    return torch.from_numpy(np.ascontiguousarray(X_np.T)).to(device).t()
+
+
+class QttMatrix:
+    """A QTT matrix resident on the current device (handle from qtt_matrix_load)."""
+
+    def __init__(self, handle, cores_shape):
+        self._h = handle
+        self.ranks, self.m, self.n = cores_shape
+        self.d = len(self.m)
+        self.rows = int(np.prod(self.m))
+        self.cols = int(np.prod(self.n))
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("matrix was freed")
+        return self._h
+
+    def free(self):
+        if self._h is not None:
+            _check(_lib.qtt_matrix_free(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def qtt_matrix_load(cores, dtypes=("fp64",)):
+    """Load host FP64 cores (each of shape (r_prev, m, n, r_next)) onto the device."""
+    cores = [np.ascontiguousarray(np.asarray(G, dtype=np.float64)) for G in cores]
+    d = len(cores)
+    ranks = [cores[0].shape[0]] + [G.shape[3] for G in cores]
+    m = [G.shape[1] for G in cores]
+    n = [G.shape[2] for G in cores]
+    if isinstance(dtypes, (str, int)):
+        dtypes = (dtypes,)
+    flags = 0
+    for t in dtypes:
+        flags |= _dtype(t)
+    r = (ctypes.c_int64 * (d + 1))(*ranks)
+    mm = (ctypes.c_int64 * d)(*m)
+    nn = (ctypes.c_int64 * d)(*n)
+    ptrs = (ctypes.c_void_p * d)(*[G.ctypes.data for G in cores])
+    h = ctypes.c_void_p()
+    _check(_lib.qtt_matrix_load(d, r, mm, nn, ptrs, flags, ctypes.byref(h)))
+    return QttMatrix(h, (ranks, m, n))
+
+
+def qtt_matrix_info(A):
+    d, rows, cols, mr, dt = (ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64(),
+                             ctypes.c_int64(), ctypes.c_uint32())
+    _check(_lib.qtt_matrix_info(A.handle, ctypes.byref(d), ctypes.byref(rows), ctypes.byref(cols),
+                                ctypes.byref(mr), ctypes.byref(dt)))
+    return {"d": d.value, "rows": rows.value, "cols": cols.value, "max_rank": mr.value,
+            "dtypes": dt.value}
+
+
+def qtt_workspace_bytes(A, compute, nrhs):
+    b = ctypes.c_size_t()
+    _check(_lib.qtt_workspace_bytes(A.handle, _dtype(compute), int(nrhs), ctypes.byref(b)))
+    return b.value
+
+
+def qtt_solve_workspace_bytes(A, Ainv, inv_compute, nrhs):
+    b = ctypes.c_size_t()
+    _check(_lib.qtt_solve_workspace_bytes(A.handle, Ainv.handle, _dtype(inv_compute), int(nrhs),
+                                          ctypes.byref(b)))
+    return b.value
+
+
+def workspace(nbytes, device="cuda"):
+    """Device workspace tensor of at least nbytes (256-byte aligned by the allocator)."""
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def qtt_apply(A, compute, X, Y=None, ws=None, stream=None):
+    """Y = A X; returns Y (allocated column-major when not given)."""
+    xp, n, k, ldx = _col_major(X, "X")
+    if Y is None:
+        Y = empty_block(A.rows, k, X.device) if X.dim() == 2 else torch.empty(A.rows, dtype=torch.float64, device=X.device)
+    yp, m, ky, ldy = _col_major(Y, "Y")
+    if n != A.cols or m != A.rows or ky != k:
+        raise ValueError(f"shape mismatch: A is {A.rows}x{A.cols}, X {n}x{k}, Y {m}x{ky}")
+    if ws is None:
+        ws = workspace(qtt_workspace_bytes(A, compute, k), X.device)
+    _check(_lib.qtt_apply(A.handle, _dtype(compute), k, xp, ldx, yp, ldy, ws.data_ptr(),
+                          ws.numel() * ws.element_size(), _stream(stream)))
+    return Y
+
+
+def qtt_apply_batched(A, compute, Xs, Ys=None, ws=None, stream=None):
+    """Y_b = A X_b for a list of uneven column-major blocks; returns the list Ys."""
+    nb = len(Xs)
+    if Ys is None:
+        Ys = [empty_block(A.rows, _col_major(X, "X")[2], X.device) for X in Xs]
+    xs = [_col_major(X, "X") for X in Xs]
+    ys = [_col_major(Y, "Y") for Y in Ys]
+    for (xp, n, k, _), (yp, m, ky, _) in zip(xs, ys):
+        if n != A.cols or m != A.rows or k != ky:
+            raise ValueError("block shape mismatch")
+    widths = (ctypes.c_int64 * nb)(*[x[2] for x in xs])
+    xptr = (ctypes.c_void_p * nb)(*[x[0] for x in xs])
+    ldx = (ctypes.c_int64 * nb)(*[x[3] for x in xs])
+    yptr = (ctypes.c_void_p * nb)(*[y[0] for y in ys])
+    ldy = (ctypes.c_int64 * nb)(*[y[3] for y in ys])
+    if ws is None:
+        ws = workspace(qtt_workspace_bytes(A, compute, sum(x[2] for x in xs)), Xs[0].device)
+    _check(_lib.qtt_apply_batched(A.handle, _dtype(compute), nb, widths, xptr, ldx, yptr, ldy,
+                                  ws.data_ptr(), ws.numel() * ws.element_size(), _stream(stream)))
+    return Ys
+
+
+def qtt_autotune(A, compute, X, Y, ws, stream=None):
+    xp, n, k, ldx = _col_major(X, "X")
+    yp, m, _, ldy = _col_major(Y, "Y")
+    _check(_lib.qtt_autotune(A.handle, _dtype(compute), k, xp, ldx, yp, ldy, ws.data_ptr(),
+                             ws.numel() * ws.element_size(), _stream(stream)))
+
+
+def qtt_solve(A, Ainv, inv_compute, F, Sigma=None, rtol=1e-8, max_iter=50, ws=None, stream=None,
+              raise_on_fail=True):
+    """Refined solve A Sigma = F; returns (Sigma, info, status) with info a list of
+    (iters, rel_residual) per column."""
+    fp, n, k, ldf = _col_major(F, "F")
+    if Sigma is None:
+        Sigma = empty_block(n, k, F.device) if F.dim() == 2 else torch.empty(n, dtype=torch.float64, device=F.device)
+    sp, _, _, lds = _col_major(Sigma, "Sigma")
+    if ws is None:
+        ws = workspace(qtt_solve_workspace_bytes(A, Ainv, inv_compute, k), F.device)
+    info = (_SolveCol * k)()
+    st = _lib.qtt_solve(A.handle, Ainv.handle, _dtype(inv_compute), k, fp, ldf, sp, lds, float(rtol),
+                        int(max_iter), ws.data_ptr(), ws.numel() * ws.element_size(), _stream(stream), info)
+    if raise_on_fail:
+        _check(st)
+    else:
+        _check(st, allow=(QTT_ERR_NOT_CONVERGED, QTT_ERR_NONFINITE))
+    return Sigma, [(c.iters, c.rel_residual) for c in info], st
+
+
+def qtt_timing_enable(on=True):
+    _check(_lib.qtt_timing_enable(1 if on else 0))
+
+
+def qtt_timing_reset():
+    _check(_lib.qtt_timing_reset())
+
+
+def qtt_timing_read(compute, position):
+    n = ctypes.c_int64()
+    ms, fl, by = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _check(_lib.qtt_timing_read(_dtype(compute), int(position), ctypes.byref(n), ctypes.byref(ms),
+                                ctypes.byref(fl), ctypes.byref(by)))
+    return {"launches": n.value, "ms": ms.value, "flops": fl.value, "bytes": by.value}

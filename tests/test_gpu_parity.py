@@ -1,0 +1,268 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances (normwise per column, worst column):
+  FP64 sweep  1e-12, and elementwise |y - y_ref| <= 1e-12 max|y_ref|
+  FP32 sweep  1e-5
+  BF16 sweep  3e-2 for the Gaussian-core operators (8 significant bits:
+              unit roundoff 2^-8; d roundings of cores and intermediates of
+              random sign add up to about sqrt(2d/3) 2^-8 ~ 0.01 at d = 7);
+              the refined solve then restores 1e-8.
+  refined solve: relative residual <= 1e-8 recomputed by the oracle.
+Integer-exact cases (identity, permutation cores) are bitwise.
+"""
+import numpy as np
+import pytest
+
+from oracle import qtt_oracle as O
+from paper_1511_06029_amd import inputs as I
+import qtt_structures as S
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32": 1e-5, "bf16": 3e-2}
+
+
+@pytest.fixture(scope="module")
+def Q():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    from paper_1511_06029_amd import qtt
+    return qtt
+
+
+def colrel(Y, R):
+    Y = np.asarray(Y).reshape(R.shape[0], -1)
+    R = R.reshape(R.shape[0], -1)
+    return max(np.linalg.norm(Y[:, c] - R[:, c]) / max(np.linalg.norm(R[:, c]), 1e-300)
+               for c in range(R.shape[1]))
+
+
+def elementwise_ok(Y, R, tol):
+    Y = np.asarray(Y).reshape(R.shape[0], -1)
+    R = R.reshape(R.shape[0], -1)
+    scale = np.abs(R).max(axis=0)
+    return np.all(np.abs(Y - R) <= tol * scale[None, :])
+
+
+def gpu_apply(Q, cores, X, dtype, ws_nrhs=None):
+    A = Q.qtt_matrix_load(cores, dtypes=(dtype,))
+    Xd = Q.to_block(X)
+    ws = None
+    if ws_nrhs is not None:
+        ws = Q.workspace(Q.qtt_workspace_bytes(A, dtype, ws_nrhs))
+    Y = Q.qtt_apply(A, dtype, Xd, ws=ws)
+    torch.cuda.synchronize()
+    out = Y.cpu().numpy()
+    A.free()
+    return out
+
+
+# ------------------------------------------------------------------ exact cases
+
+@pytest.mark.parametrize("dtype", ["fp64", "fp32", "bf16"])
+def test_identity_bitwise(Q, dtype):
+    X = I.rhs(8 ** 3, 3, seed=1)
+    if dtype != "fp64":   # values exactly representable in the compute type
+        X = np.round(X * 8) / 8
+    Y = gpu_apply(Q, I.identity_qtt([8] * 3), X, dtype)
+    assert np.array_equal(Y, X)
+
+
+def test_permutation_bitwise_fp64(Q):
+    g = I.rng(9)
+    mats = [np.eye(8)[g.permutation(8)] for _ in range(4)]
+    X = I.rhs(8 ** 4, 2, seed=3)
+    Y = gpu_apply(Q, S.kron_cores(mats), X, "fp64")
+    assert np.array_equal(Y, S.modewise_apply(mats, X))
+
+
+# ------------------------------------------------------------------ random operators
+
+SHAPES = [
+    ("octree_L4", [1, 7, 9, 6, 1], [8] * 4, [8] * 4),
+    ("rect_uneven", [1, 3, 5, 2, 1], [2, 3, 4, 2], [3, 2, 2, 4]),
+    ("single_core", [1, 1], [5], [3]),
+    ("unit_modes", [1, 2, 1], [1, 4], [3, 1]),
+    ("shape_example", [1, 4, 4, 1], [4, 2, 2], [4, 2, 2]),
+    ("rank40_L3", [1, 40, 40, 1], [8] * 3, [8] * 3),
+    ("L2_small_C", [1, 16, 1], [8, 8], [8, 8]),
+]
+
+
+@pytest.mark.parametrize("dtype", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("name,ranks,m,n", SHAPES, ids=[s[0] for s in SHAPES])
+def test_random_shapes(Q, name, ranks, m, n, dtype):
+    cores = I.gaussian_qtt(ranks, m, n, seed=11)
+    N = int(np.prod(n))
+    X = I.rhs(N, 3, seed=12)
+    ref = O.qtt_apply_alg2(cores, X)
+    Y = gpu_apply(Q, cores, X, dtype)
+    err = colrel(Y, ref)
+    print(f"{name} {dtype} rel err {err:.3e}")
+    assert err <= TOL[dtype]
+    if dtype == "fp64":
+        assert elementwise_ok(Y, ref, 1e-12)
+
+
+@pytest.mark.parametrize("K", [1, 16])
+@pytest.mark.parametrize("dtype", ["fp64", "fp32", "bf16"])
+def test_synthetic_L6(Q, K, dtype):
+    """L=6 (N=262144), ranks [1,16,32,32,32,16,1], Gaussian cores scaled
+    1/sqrt(8 r_{k-1}), K=1 and K=16 seeded N(0,1) right-hand sides."""
+    w = I.WORKLOADS["synthetic_L6"]
+    cores = I.gaussian_qtt(w["ranks"], [8] * 6, seed=w["core_seed"])
+    X = I.rhs(8 ** 6, K, seed=w["rhs_seed"])
+    ref = O.qtt_apply_alg2(cores, X)
+    Y = gpu_apply(Q, cores, X, dtype)
+    err = colrel(Y, ref)
+    print(f"L6 K={K} {dtype} rel err {err:.3e}")
+    assert err <= TOL[dtype]
+    if dtype == "fp64":
+        assert elementwise_ok(Y, ref, 1e-12)
+
+
+def test_volume_L4_fp64(Q):
+    """Volume operator on the 16^3 grid (Morton order, octree digits), TT-SVD at
+    1e-10: ranks [1,27,173,27,1] (non-power-of-two rank, several row tiles)."""
+    A = O.volume_matrix(4)
+    cores, _ = O.qtt_matrix_from_dense(A, [8] * 4, [8] * 4, 1e-10)
+    assert [G.shape[3] for G in cores] == [27, 173, 27, 1]
+    X = I.rhs(4096, 1, seed=I.WORKLOADS["volume_L4"]["rhs_seed"])
+    ref = O.qtt_apply_alg2(cores, X)
+    Y = gpu_apply(Q, cores, X, "fp64")
+    assert colrel(Y, ref) <= 1e-12 and elementwise_ok(Y, ref, 1e-12)
+    assert colrel(Y, A @ X) <= 1e-9      # within the compression error of A itself
+
+
+# ------------------------------------------------------------------ layouts, waves, batching
+
+def test_padded_ld_and_waves(Q):
+    cores = I.gaussian_qtt([1, 6, 12, 5, 1], [8] * 4, seed=21)
+    X = I.rhs(4096, 5, seed=22)
+    ref = O.qtt_apply_alg2(cores, X)
+    A = Q.qtt_matrix_load(cores, dtypes=("fp64",))
+    Xp = torch.zeros((5, 4100), dtype=torch.float64, device="cuda")
+    Xp[:, :4096] = torch.from_numpy(X.T.copy()).cuda()
+    Xv = Xp.t()[:4096]                       # ld = 4100
+    Yp = torch.full((5, 4098), 7.0, dtype=torch.float64, device="cuda")
+    Yv = Yp.t()[:4096]                       # ld = 4098
+    ws = Q.workspace(Q.qtt_workspace_bytes(A, "fp64", 1))   # one vector per wave
+    Q.qtt_apply(A, "fp64", Xv, Yv, ws=ws)
+    torch.cuda.synchronize()
+    Yh = Yp.cpu().numpy()
+    assert np.all(Yh[:, 4096:] == 7.0)       # padding untouched
+    assert colrel(Yh[:, :4096].T, ref) <= 1e-12
+    A.free()
+
+
+@pytest.mark.parametrize("dtype", ["fp64", "fp32"])
+def test_batched_uneven(Q, dtype):
+    cores = I.gaussian_qtt([1, 8, 16, 8, 1], [8] * 4, seed=31)
+    widths = [1, 4, 2, 0, 7, 1, 3]
+    A = Q.qtt_matrix_load(cores, dtypes=(dtype,))
+    Xs_h = [I.rhs(4096, w, seed=40 + b) for b, w in enumerate(widths)]
+    Xs = [Q.to_block(x) if x.shape[1] else Q.empty_block(4096, 0) for x in Xs_h]
+    total = sum(widths)
+    for ws_n in (total, 3):                  # one wave, then several waves
+        ws = Q.workspace(Q.qtt_workspace_bytes(A, dtype, ws_n))
+        Ys = Q.qtt_apply_batched(A, dtype, Xs, ws=ws)
+        torch.cuda.synchronize()
+        for x, y in zip(Xs_h, Ys):
+            if x.shape[1]:
+                assert colrel(y.cpu().numpy(), O.qtt_apply_alg2(cores, x)) <= TOL[dtype]
+    A.free()
+
+
+def test_batched_matches_single_bitwise(Q):
+    """Batch invariance: a vector's result does not depend on its batch."""
+    cores = I.gaussian_qtt([1, 8, 16, 8, 1], [8] * 4, seed=33)
+    A = Q.qtt_matrix_load(cores, dtypes=("fp64", "bf16"))
+    X = I.rhs(4096, 6, seed=34)
+    for dt in ("fp64", "bf16"):
+        alone = [Q.qtt_apply(A, dt, Q.to_block(X[:, c])).cpu().numpy() for c in range(6)]
+        Ys = Q.qtt_apply_batched(A, dt, [Q.to_block(X[:, :2]), Q.to_block(X[:, 2:])])
+        mixed = np.concatenate([y.cpu().numpy() for y in Ys], axis=1)
+        for c in range(6):
+            assert np.array_equal(mixed[:, c], alone[c])
+    A.free()
+
+
+# ------------------------------------------------------------------ solve
+
+@pytest.mark.parametrize("inv", ["fp64", "fp32", "bf16"])
+def test_solve_L4_vs_dense(Q, inv):
+    ranks = [1, 6, 8, 6, 1]
+    Ac, Aic = I.perturbed_identity_pair(ranks, [8] * 4, seed=81)
+    F = I.rhs(4096, 3, seed=82)
+    A = Q.qtt_matrix_load(Ac, dtypes=("fp64",))
+    Ai = Q.qtt_matrix_load(Aic, dtypes=(inv,))
+    Sig, info, st = Q.qtt_solve(A, Ai, inv, Q.to_block(F), rtol=1e-8)
+    Sh = Sig.cpu().numpy()
+    ref = np.linalg.solve(O.qtt_to_dense(Ac), F)
+    res = F - O.qtt_apply_alg2(Ac, Sh)
+    for c in range(3):
+        assert np.linalg.norm(res[:, c]) <= 1e-8 * np.linalg.norm(F[:, c]) * 1.0001
+        assert info[c][1] <= 1e-8
+    assert colrel(Sh, ref) <= 3e-8
+    A.free()
+    Ai.free()
+
+
+def test_solve_iterations_match_oracle_fp64(Q):
+    ranks = [1, 6, 8, 6, 1]
+    Ac, Aic = I.perturbed_identity_pair(ranks, [8] * 4, seed=83)
+    F = I.rhs(4096, 2, seed=84)
+    Xo, hist = O.richardson_solve(Ac, Aic, F, rtol=1e-8)
+    A = Q.qtt_matrix_load(Ac, dtypes=("fp64",))
+    Ai = Q.qtt_matrix_load(Aic, dtypes=("fp64",))
+    Sig, info, st = Q.qtt_solve(A, Ai, "fp64", Q.to_block(F), rtol=1e-8)
+    assert [c[0] for c in info] == [len(hist)] * 2
+    assert colrel(Sig.cpu().numpy(), Xo) <= 1e-12
+    A.free()
+    Ai.free()
+
+
+@pytest.mark.slow
+def test_refine_L7_full_size(Q):
+    """The refined solve at full size: L=7 (N=2,097,152), ranks
+    [1,24,32,32,32,32,24,1], K=8; the oracle recomputes the relative residual of
+    two sampled columns, and checks one FP64 A apply elementwise."""
+    w = I.WORKLOADS["refine_L7"]
+    Ac, Aic = I.perturbed_identity_pair(w["ranks"], [8] * 7, seed=w["core_seed"], eps=w["eps"])
+    F = I.rhs(8 ** 7, w["K"], seed=w["rhs_seed"])
+    A = Q.qtt_matrix_load(Ac, dtypes=("fp64",))
+    Ai = Q.qtt_matrix_load(Aic, dtypes=("bf16", "fp64"))
+    Fd = Q.to_block(F)
+    Sig, info, st = Q.qtt_solve(A, Ai, "bf16", Fd, rtol=w["rtol"])
+    Sh = Sig.cpu().numpy()
+    for c in (0, w["K"] - 1):
+        r = F[:, c] - O.qtt_apply_alg2(Ac, Sh[:, c])
+        assert np.linalg.norm(r) <= 1e-8 * np.linalg.norm(F[:, c]) * 1.0001
+    Y = Q.qtt_apply(A, "fp64", Q.to_block(F[:, :1]))
+    ref = O.qtt_apply_alg2(Ac, F[:, :1])
+    assert colrel(Y.cpu().numpy(), ref) <= 1e-12 and elementwise_ok(Y.cpu().numpy(), ref, 1e-12)
+    A.free()
+    Ai.free()
+
+
+# ------------------------------------------------------------------ errors
+
+def test_error_paths(Q):
+    cores = I.gaussian_qtt([1, 3, 1], [8, 8], seed=5)
+    A = Q.qtt_matrix_load(cores, dtypes=("fp64",))
+    X = Q.to_block(I.rhs(64, 2, seed=1))
+    with pytest.raises(Q.QttError) as e:
+        Q.qtt_apply(A, "bf16", X)            # dtype not loaded
+    assert e.value.status == 8
+    with pytest.raises(Q.QttError) as e:
+        Q.qtt_apply(A, "fp64", X, X)         # output overlaps input
+    assert e.value.status == 1
+    with pytest.raises(Q.QttError) as e:
+        Q.qtt_apply(A, "fp64", X, ws=Q.workspace(16))
+    assert e.value.status == 7
+    Ai = Q.qtt_matrix_load([-G for G in cores], dtypes=("fp64",))
+    Sig, info, st = Q.qtt_solve(A, Ai, "fp64", X, max_iter=3, raise_on_fail=False)
+    assert st == 5                            # not a contraction: not converged
+    A.free()
+    Ai.free()
