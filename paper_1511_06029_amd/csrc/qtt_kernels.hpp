@@ -16,8 +16,10 @@
 // v_mfma_{f64_16x16x4f64, f32_16x16x4f32, f32_16x16x32_bf16}.  An operand
 // fragment holds a 16 x KSTEP slice; lane l carries line (l mod 16) and the
 // contraction indices KSTEP-slot group (l div 16), E consecutive values each.
-// The accumulator of lane l, register v is element (4 (l div 16) + v, l mod 16)
-// of the 16x16 block (first index from operand a, second from operand b).
+// The accumulator of lane l, register v is element (acc_line(l, v), l mod 16)
+// of the 16x16 block (first index from operand a, second from operand b), with
+// acc_line = 4 (l div 16) + v for the FP32 and BF16 instructions and
+// (l div 16) + 4 v for the FP64 one (measured lane by lane on gfx950).
 // The same lane mapping is used for the core fragments (stored in this order
 // by the loader) and for the input fragments (written in this order into LDS),
 // so the contraction index assignment inside a step is immaterial.
@@ -60,6 +62,7 @@ template <> struct Mfma<double> {
   __device__ static acc mma(frag a, frag b, acc c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
+  __device__ static int acc_line(int lane, int v) { return (lane >> 4) + 4 * v; }
   __device__ static frag load_frag(const elem* p) { return *p; }
   __device__ static frag zero_frag() { return 0.0; }
   __device__ static elem from_double(double x) { return x; }
@@ -75,6 +78,7 @@ template <> struct Mfma<float> {
   __device__ static acc mma(frag a, frag b, acc c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
+  __device__ static int acc_line(int lane, int v) { return 4 * (lane >> 4) + v; }
   __device__ static frag load_frag(const elem* p) { return *p; }
   __device__ static frag zero_frag() { return 0.0f; }
   __device__ static elem from_double(double x) { return (float)x; }
@@ -90,6 +94,7 @@ template <> struct Mfma<bf16_tag> {
   __device__ static acc mma(frag a, frag b, acc c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
   }
+  __device__ static int acc_line(int lane, int v) { return 4 * (lane >> 4) + v; }
   __device__ static frag load_frag(const elem* p) {
     return __builtin_bit_cast(v8bf, *reinterpret_cast<const v4u*>(p));
   }
@@ -297,10 +302,10 @@ core_step_kernel(const StepArgs args) {
         for (int v = 0; v < 4; ++v) {
           int row, cit;
           if (ROWS_ON_LANES) {
-            cit = (wc * WC + j) * 16 + 4 * (lane >> 4) + v;
+            cit = (wc * WC + j) * 16 + MF::acc_line(lane, v);
             row = rt * TR + (wr * WR + i) * 16 + (lane & 15);
           } else {
-            row = rt * TR + (wr * WR + i) * 16 + 4 * (lane >> 4) + v;
+            row = rt * TR + (wr * WR + i) * 16 + MF::acc_line(lane, v);
             cit = (wc * WC + j) * 16 + (lane & 15);
           }
           const int64_t g = col0 + cit;
