@@ -122,7 +122,7 @@ qtt_status_t qtt_apply_batched(qtt_matrix_t A, qtt_dtype_t compute, int32_t nblo
 /* Tune tile shapes for this matrix, dtype and vector count: every candidate
  * kernel configuration is timed on each core (outputs written to scratch in
  * ws), and the fastest is kept in the handle and in a process-wide table
- * keyed by (dtype, core shape, column count).  X/Y are used as in qtt_apply
+ * keyed by (dtype, core shape).  X/Y are used as in qtt_apply
  * and hold A X on return.  Synchronises the stream. */
 qtt_status_t qtt_autotune(qtt_matrix_t A, qtt_dtype_t compute, int64_t nrhs,
                           const double* X, int64_t ldx, double* Y, int64_t ldy,

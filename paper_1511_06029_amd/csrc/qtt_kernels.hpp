@@ -145,7 +145,8 @@ __device__ inline const T& kernarg() {
   return *(const T*)(__builtin_amdgcn_kernarg_segment_ptr());
 }
 
-__device__ inline int find_seg(const StepArgs& a, int64_t rhs) {
+template <class Args>
+__device__ inline int find_seg(const Args& a, int64_t rhs) {
   int s = 0;
   for (int t = 1; t < a.nseg; ++t) s = (a.seg[t].rhs_begin <= rhs) ? t : s;
   return s;
@@ -332,6 +333,597 @@ core_step_kernel(const StepArgs args) {
           } else {
             reinterpret_cast<elem*>(a.out)[rhs * a.out_stride + off] = MF::from_acc(val);
           }
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Pipelined core step: both operands staged in LDS.
+//
+// The workgroup streams (tile, chunk) pairs: a chunk is KC contraction
+// indices of the input columns of one tile plus the matching KC columns of
+// the tile's core rows.  Global loads run two chunks ahead of the matrix
+// cores (into registers), each chunk is written to one of two LDS stages,
+// and one barrier per chunk separates reuse of a stage.  Fragments for step
+// s+1 are read from LDS while step s runs on the matrix cores.  The core
+// fragments are copied unchanged (the loader already stores them in
+// fragment order), so every LDS read is 64 lanes x E contiguous elements.
+// ---------------------------------------------------------------------------
+template <class Tc, class Tin, int WAVES_R, int WAVES_C, int WR, int WC, int KC,
+          bool ROWS_ON_LANES, bool VEC>
+__global__ void __launch_bounds__(64 * WAVES_R * WAVES_C)
+core_step_pipe_kernel(const StepArgs args) {
+  (void)args;
+  const StepArgs& a = kernarg<StepArgs>();
+  using MF = Mfma<Tc>;
+  using elem = typename MF::elem;
+  using frag = typename MF::frag;
+  using acc_t = typename MF::acc;
+  constexpr int NT = 64 * WAVES_R * WAVES_C;
+  constexpr int TC = 16 * WC * WAVES_C;
+  constexpr int TR = 16 * WR * WAVES_R;
+  constexpr int E = MF::E, KSTEP = MF::KSTEP;
+  constexpr int SPC = KC / KSTEP;
+  static_assert(KC % KSTEP == 0, "chunk must hold whole steps");
+  constexpr int VE = VEC ? (int)(16 / sizeof(Tin)) : 1;
+  static_assert(KC % VE == 0, "chunk must hold whole loads");
+  constexpr int VPC = KC / VE;
+  constexpr int NLA = (TC * VPC + NT - 1) / NT;                  // input loads per thread
+  constexpr int BV_PER_RB = SPC * 64 * E * (int)sizeof(elem) / 16;   // 16-byte core loads per row block
+  constexpr int NLB = ((TR / 16) * BV_PER_RB + NT - 1) / NT;     // core loads per thread
+  constexpr int A_ELEMS = (TC / 16) * SPC * 64 * E;
+  constexpr int B_ELEMS = (TR / 16) * SPC * 64 * E;
+  constexpr int STAGE = A_ELEMS + B_ELEMS;
+  using ld_t = typename std::conditional<VEC, v4u, Tin>::type;
+
+  __shared__ __attribute__((aligned(16))) elem lds[2 * STAGE];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wr = wave % WAVES_R;
+  const int wc = wave / WAVES_R;
+  const elem* __restrict__ Mf = reinterpret_cast<const elem*>(a.M);
+  const int Kpad = a.Ksteps * KSTEP;
+  const int nch = (Kpad + KC - 1) / KC;
+
+  const int64_t my_tiles = (a.n_tiles > (int64_t)blockIdx.x)
+                               ? (a.n_tiles - 1 - (int64_t)blockIdx.x) / gridDim.x + 1 : 0;
+  const int64_t total_it = my_tiles * nch;
+  if (total_it == 0) return;
+
+  ld_t sa[NLA];
+  v4u sb[NLB];
+
+  // ---- global -> registers for iteration it ----
+  auto gload = [&](int64_t it) {
+    const int64_t tile = blockIdx.x + (it / nch) * (int64_t)gridDim.x;
+    const int ch = (int)(it % nch);
+    const int kc0 = ch * KC;
+    const int rt = (int)(tile % a.n_row_tiles);
+    const int64_t col0 = (tile / a.n_row_tiles) * (int64_t)TC;
+#pragma unroll
+    for (int t = 0; t < NLA; ++t) {
+      const int idx = tid + t * NT;
+      const int c = idx / VPC;
+      const int kap = kc0 + (idx % VPC) * VE;
+      const int64_t g = col0 + c;
+      sa[t] = ld_t{};
+      if (idx < TC * VPC && g < a.ncols && kap < a.K_in) {
+        const int64_t rhs = g / a.C;
+        const int64_t q = g - rhs * a.C;
+        const Tin* p;
+        if (a.in_table) {
+          const Segment& sg = a.seg[find_seg(a, rhs)];
+          p = reinterpret_cast<const Tin*>(sg.x) + (rhs - sg.rhs_begin) * sg.ldx + q * a.K_in;
+        } else {
+          p = reinterpret_cast<const Tin*>(a.in) + rhs * a.in_stride + q * a.K_in;
+        }
+        sa[t] = *reinterpret_cast<const ld_t*>(p + kap);
+      }
+    }
+    const int s0 = kc0 / KSTEP;
+    const int nsteps = min(SPC, a.Ksteps - s0);
+    const int valid_v = nsteps * 64 * E * (int)sizeof(elem) / 16;   // loads per row block holding real steps
+#pragma unroll
+    for (int t = 0; t < NLB; ++t) {
+      const int idx = tid + t * NT;
+      const int rb = idx / BV_PER_RB;
+      const int v = idx % BV_PER_RB;
+      const int rbg = rt * (TR / 16) + rb;
+      sb[t] = v4u{0u, 0u, 0u, 0u};
+      if (idx < (TR / 16) * BV_PER_RB && rbg < a.nRB && v < valid_v) {
+        const elem* p = Mf + ((int64_t)rbg * a.Ksteps + s0) * 64 * E;
+        sb[t] = reinterpret_cast<const v4u*>(p)[v];
+      }
+    }
+  };
+  // ---- registers -> LDS stage ----
+  auto lstore = [&](int stage, int64_t it) {
+    const int ch = (int)(it % nch);
+    const int kc0 = ch * KC;
+    elem* A = lds + stage * STAGE;
+    elem* B = A + A_ELEMS;
+#pragma unroll
+    for (int t = 0; t < NLA; ++t) {
+      const int idx = tid + t * NT;
+      if (idx < TC * VPC) {
+        const int c = idx / VPC;
+        const int kl0 = (idx % VPC) * VE;
+        const int cb = c >> 4, cl = c & 15;
+        const Tin* v = reinterpret_cast<const Tin*>(&sa[t]);
+        if constexpr (VE == E && std::is_same<Tin, elem>::value) {
+          // one 16-byte fragment slot
+          const int s = kl0 / KSTEP, gq = (kl0 % KSTEP) / E;
+          *reinterpret_cast<ld_t*>(&A[((cb * SPC + s) * 64 + cl + 16 * gq) * E]) = sa[t];
+        } else {
+#pragma unroll
+          for (int e = 0; e < VE; ++e) {
+            const int kl = kl0 + e;
+            const int s = kl / KSTEP, gq = (kl % KSTEP) / E, ee = kl % E;
+            elem val;
+            if constexpr (std::is_same<Tin, double>::value) val = MF::from_double(v[e]);
+            else val = *reinterpret_cast<const elem*>(&v[e]);
+            A[((cb * SPC + s) * 64 + cl + 16 * gq) * E + ee] = val;
+          }
+        }
+      }
+    }
+    (void)kc0;
+#pragma unroll
+    for (int t = 0; t < NLB; ++t) {
+      const int idx = tid + t * NT;
+      if (idx < (TR / 16) * BV_PER_RB) {
+        const int rb = idx / BV_PER_RB;
+        const int v = idx % BV_PER_RB;
+        reinterpret_cast<v4u*>(B + rb * SPC * 64 * E)[v] = sb[t];
+      }
+    }
+  };
+
+  acc_t acc[WR][WC];
+  gload(0);
+  lstore(0, 0);
+  __syncthreads();
+  if (total_it > 1) gload(1);
+
+  for (int64_t it = 0; it < total_it; ++it) {
+    const int ch = (int)(it % nch);
+    if (ch == 0) {
+#pragma unroll
+      for (int i = 0; i < WR; ++i)
+#pragma unroll
+        for (int j = 0; j < WC; ++j) acc[i][j] = acc_t{};
+    }
+    const elem* A = lds + (it & 1) * STAGE;
+    const elem* B = A + A_ELEMS;
+    const int nsteps = min(SPC, a.Ksteps - ch * SPC);
+    auto step = [&](int s) {
+      frag bf[WR], af[WC];
+#pragma unroll
+      for (int i = 0; i < WR; ++i)
+        bf[i] = MF::load_frag(&B[(((wr * WR + i) * SPC + s) * 64 + lane) * E]);
+#pragma unroll
+      for (int j = 0; j < WC; ++j)
+        af[j] = MF::load_frag(&A[(((wc * WC + j) * SPC + s) * 64 + lane) * E]);
+#pragma unroll
+      for (int i = 0; i < WR; ++i)
+#pragma unroll
+        for (int j = 0; j < WC; ++j)
+          acc[i][j] = ROWS_ON_LANES ? MF::mma(af[j], bf[i], acc[i][j])
+                                    : MF::mma(bf[i], af[j], acc[i][j]);
+    };
+    if (nsteps == SPC) {
+#pragma unroll
+      for (int s = 0; s < SPC; ++s) step(s);
+    } else {
+      for (int s = 0; s < nsteps; ++s) step(s);
+    }
+
+    if (ch == nch - 1) {
+      // ---- epilogue of this tile ----
+      const int64_t tile = blockIdx.x + (it / nch) * (int64_t)gridDim.x;
+      const int rt = (int)(tile % a.n_row_tiles);
+      const int64_t col0 = (tile / a.n_row_tiles) * (int64_t)TC;
+      const int64_t rhs0 = col0 / a.C;
+      const int64_t q0 = col0 - rhs0 * a.C;
+      const bool one_rhs = (q0 + TC <= a.C);
+      const Segment* s0p = a.out_table ? &a.seg[find_seg(a, rhs0)] : nullptr;
+#pragma unroll
+      for (int i = 0; i < WR; ++i) {
+#pragma unroll
+        for (int j = 0; j < WC; ++j) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            int row, cit;
+            if (ROWS_ON_LANES) {
+              cit = (wc * WC + j) * 16 + MF::acc_line(lane, v);
+              row = rt * TR + (wr * WR + i) * 16 + (lane & 15);
+            } else {
+              row = rt * TR + (wr * WR + i) * 16 + MF::acc_line(lane, v);
+              cit = (wc * WC + j) * 16 + (lane & 15);
+            }
+            const int64_t g = col0 + cit;
+            if (g >= a.ncols || row >= a.R_out) continue;
+            int64_t rhs, q;
+            const Segment* sp = s0p;
+            if (one_rhs) {
+              rhs = rhs0;
+              q = q0 + cit;
+            } else {
+              rhs = g / a.C;
+              q = g - rhs * a.C;
+              if (a.out_table) sp = &a.seg[find_seg(a, rhs)];
+            }
+            const int ar = row % a.r_out;
+            const int ir = row / a.r_out;
+            const int64_t off = ar + (int64_t)a.r_out * (q + a.C * ir);
+            const auto val = acc[i][j][v];
+            if (a.out_table) {
+              const int64_t vr = rhs - sp->rhs_begin;
+              double res = a.alpha * (double)val;
+              if (sp->z != nullptr) res += sp->z[vr * sp->ldz + off];
+              sp->y[vr * sp->ldy + off] = res;
+            } else {
+              reinterpret_cast<elem*>(a.out)[rhs * a.out_stride + off] = MF::from_acc(val);
+            }
+          }
+        }
+      }
+    }
+    if (it + 1 < total_it) lstore((int)((it + 1) & 1), it + 1);
+    __syncthreads();
+    if (it + 2 < total_it) gload(it + 2);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Streamed core step: input in LDS, core fragments straight from L2.
+//
+// The workgroup walks its (tile, chunk) pairs as one stream.  Input columns
+// of a chunk are loaded a chunk ahead into registers, written to one of two
+// LDS stages in fragment order, and read by every wave of the workgroup.
+// Core fragments never touch LDS: each wave reads the fragments of its own
+// row blocks from global memory (they stay L2-resident: one core is at most
+// a few hundred KB) one step ahead of the matrix cores, across chunk and
+// tile boundaries.  The fragment buffer is padded with zero row blocks up to
+// a multiple of 16, so those loads need no bounds test.  One barrier per
+// chunk.
+// ---------------------------------------------------------------------------
+template <class Tc, class Tin, int WAVES_R, int WAVES_C, int WR, int WC, int KC,
+          bool ROWS_ON_LANES, bool VEC>
+__global__ void __launch_bounds__(64 * WAVES_R * WAVES_C)
+core_step_stream_kernel(const StepArgs args) {
+  (void)args;
+  const StepArgs& a = kernarg<StepArgs>();
+  using MF = Mfma<Tc>;
+  using elem = typename MF::elem;
+  using frag = typename MF::frag;
+  using acc_t = typename MF::acc;
+  constexpr int NT = 64 * WAVES_R * WAVES_C;
+  constexpr int TC = 16 * WC * WAVES_C;
+  constexpr int TR = 16 * WR * WAVES_R;
+  constexpr int E = MF::E, KSTEP = MF::KSTEP;
+  constexpr int SPC = KC / KSTEP;
+  static_assert(KC % KSTEP == 0, "chunk must hold whole steps");
+  constexpr int VE = VEC ? (int)(16 / sizeof(Tin)) : 1;
+  static_assert(KC % VE == 0, "chunk must hold whole loads");
+  constexpr int VPC = KC / VE;
+  constexpr int NLA = (TC * VPC + NT - 1) / NT;
+  constexpr int A_ELEMS = (TC / 16) * SPC * 64 * E;
+  using ld_t = typename std::conditional<VEC, v4u, Tin>::type;
+
+  __shared__ __attribute__((aligned(16))) elem lds[2 * A_ELEMS];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wr = wave % WAVES_R;
+  const int wc = wave / WAVES_R;
+  const elem* __restrict__ Mf = reinterpret_cast<const elem*>(a.M);
+  const int Ks = a.Ksteps;
+  const int nch = (Ks * KSTEP + KC - 1) / KC;
+
+  const int64_t my_tiles = (a.n_tiles > (int64_t)blockIdx.x)
+                               ? (a.n_tiles - 1 - (int64_t)blockIdx.x) / gridDim.x + 1 : 0;
+  const int64_t total_it = my_tiles * nch;
+  if (total_it == 0) return;
+
+  ld_t sa[NLA];
+  auto gload = [&](int64_t it) {
+    const int64_t tile = blockIdx.x + (it / nch) * (int64_t)gridDim.x;
+    const int kc0 = (int)(it % nch) * KC;
+    const int64_t col0 = (tile / a.n_row_tiles) * (int64_t)TC;
+#pragma unroll
+    for (int t = 0; t < NLA; ++t) {
+      const int idx = tid + t * NT;
+      const int c = idx / VPC;
+      const int kap = kc0 + (idx % VPC) * VE;
+      const int64_t g = col0 + c;
+      sa[t] = ld_t{};
+      if (idx < TC * VPC && g < a.ncols && kap < a.K_in) {
+        const int64_t rhs = g / a.C;
+        const int64_t q = g - rhs * a.C;
+        const Tin* p;
+        if (a.in_table) {
+          const Segment& sg = a.seg[find_seg(a, rhs)];
+          p = reinterpret_cast<const Tin*>(sg.x) + (rhs - sg.rhs_begin) * sg.ldx + q * a.K_in;
+        } else {
+          p = reinterpret_cast<const Tin*>(a.in) + rhs * a.in_stride + q * a.K_in;
+        }
+        sa[t] = *reinterpret_cast<const ld_t*>(p + kap);
+      }
+    }
+  };
+  auto lstore = [&](int stage) {
+    elem* A = lds + stage * A_ELEMS;
+#pragma unroll
+    for (int t = 0; t < NLA; ++t) {
+      const int idx = tid + t * NT;
+      if (idx < TC * VPC) {
+        const int c = idx / VPC;
+        const int kl0 = (idx % VPC) * VE;
+        const int cb = c >> 4, cl = c & 15;
+        const Tin* v = reinterpret_cast<const Tin*>(&sa[t]);
+        if constexpr (VE == E && std::is_same<Tin, elem>::value) {
+          const int s = kl0 / KSTEP, gq = (kl0 % KSTEP) / E;
+          *reinterpret_cast<ld_t*>(&A[((cb * SPC + s) * 64 + cl + 16 * gq) * E]) = sa[t];
+        } else {
+#pragma unroll
+          for (int e = 0; e < VE; ++e) {
+            const int kl = kl0 + e;
+            const int s = kl / KSTEP, gq = (kl % KSTEP) / E, ee = kl % E;
+            elem val;
+            if constexpr (std::is_same<Tin, double>::value) val = MF::from_double(v[e]);
+            else val = *reinterpret_cast<const elem*>(&v[e]);
+            A[((cb * SPC + s) * 64 + cl + 16 * gq) * E + ee] = val;
+          }
+        }
+      }
+    }
+  };
+  // core fragment of row block (this wave's i-th) at global step gs of tile row-tile rt
+  auto bload = [&](frag (&dst)[WR], int rt, int gs) {
+#pragma unroll
+    for (int i = 0; i < WR; ++i) {
+      const int rbg = rt * (TR / 16) + wr * WR + i;
+      dst[i] = MF::load_frag(Mf + (((int64_t)rbg * Ks + gs) * 64 + lane) * E);
+    }
+  };
+
+  acc_t acc[WR][WC];
+  frag bnext[WR];
+  gload(0);
+  lstore(0);
+  bload(bnext, (int)(((int64_t)blockIdx.x) % a.n_row_tiles), 0);
+  __syncthreads();
+  if (total_it > 1) gload(1);
+
+  for (int64_t it = 0; it < total_it; ++it) {
+    const int ch = (int)(it % nch);
+    const int64_t tile = blockIdx.x + (it / nch) * (int64_t)gridDim.x;
+    const int rt = (int)(tile % a.n_row_tiles);
+    if (ch == 0) {
+#pragma unroll
+      for (int i = 0; i < WR; ++i)
+#pragma unroll
+        for (int j = 0; j < WC; ++j) acc[i][j] = acc_t{};
+    }
+    // where the step after this chunk's last step comes from
+    int next_rt = rt, next_s0 = (ch + 1) * SPC;
+    if (ch == nch - 1) {
+      next_s0 = 0;
+      next_rt = (it + 1 < total_it) ? (int)((tile + gridDim.x) % a.n_row_tiles) : rt;
+    }
+    const elem* A = lds + (it & 1) * A_ELEMS;
+    const int s0 = ch * SPC;
+    const int nsteps = min(SPC, Ks - s0);
+    auto step = [&](int s, bool last) {
+      frag bcur[WR];
+#pragma unroll
+      for (int i = 0; i < WR; ++i) bcur[i] = bnext[i];
+      if (!last) bload(bnext, rt, s0 + s + 1);
+      else bload(bnext, next_rt, (next_s0 < Ks) ? next_s0 : 0);
+      frag af[WC];
+#pragma unroll
+      for (int j = 0; j < WC; ++j)
+        af[j] = MF::load_frag(&A[(((wc * WC + j) * SPC + s) * 64 + lane) * E]);
+#pragma unroll
+      for (int i = 0; i < WR; ++i)
+#pragma unroll
+        for (int j = 0; j < WC; ++j)
+          acc[i][j] = ROWS_ON_LANES ? MF::mma(af[j], bcur[i], acc[i][j])
+                                    : MF::mma(bcur[i], af[j], acc[i][j]);
+    };
+    if (nsteps == SPC) {
+#pragma unroll
+      for (int s = 0; s < SPC; ++s) step(s, s == SPC - 1);
+    } else {
+      for (int s = 0; s < nsteps; ++s) step(s, s == nsteps - 1);
+    }
+
+    if (ch == nch - 1) {
+      const int64_t col0 = (tile / a.n_row_tiles) * (int64_t)TC;
+      const int64_t rhs0 = col0 / a.C;
+      const int64_t q0 = col0 - rhs0 * a.C;
+      const bool one_rhs = (q0 + TC <= a.C);
+      const Segment* s0p = a.out_table ? &a.seg[find_seg(a, rhs0)] : nullptr;
+#pragma unroll
+      for (int i = 0; i < WR; ++i) {
+#pragma unroll
+        for (int j = 0; j < WC; ++j) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            int row, cit;
+            if (ROWS_ON_LANES) {
+              cit = (wc * WC + j) * 16 + MF::acc_line(lane, v);
+              row = rt * TR + (wr * WR + i) * 16 + (lane & 15);
+            } else {
+              row = rt * TR + (wr * WR + i) * 16 + MF::acc_line(lane, v);
+              cit = (wc * WC + j) * 16 + (lane & 15);
+            }
+            const int64_t g = col0 + cit;
+            if (g >= a.ncols || row >= a.R_out) continue;
+            int64_t rhs, q;
+            const Segment* sp = s0p;
+            if (one_rhs) {
+              rhs = rhs0;
+              q = q0 + cit;
+            } else {
+              rhs = g / a.C;
+              q = g - rhs * a.C;
+              if (a.out_table) sp = &a.seg[find_seg(a, rhs)];
+            }
+            const int ar = row % a.r_out;
+            const int ir = row / a.r_out;
+            const int64_t off = ar + (int64_t)a.r_out * (q + a.C * ir);
+            const auto val = acc[i][j][v];
+            if (a.out_table) {
+              const int64_t vr = rhs - sp->rhs_begin;
+              double res = a.alpha * (double)val;
+              if (sp->z != nullptr) res += sp->z[vr * sp->ldz + off];
+              sp->y[vr * sp->ldy + off] = res;
+            } else {
+              reinterpret_cast<elem*>(a.out)[rhs * a.out_stride + off] = MF::from_acc(val);
+            }
+          }
+        }
+      }
+    }
+    if (it + 1 < total_it) lstore((int)((it + 1) & 1));
+    __syncthreads();
+    if (it + 2 < total_it) gload(it + 2);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 core step on the vector ALUs (same intermediate layout as the
+// matrix-core kernels, so the two can be mixed core by core).
+//
+// Lane l owns column q of b_k: its K_in inputs are contiguous, read in groups
+// of G consecutive values (G = 8 when K_in % 8 == 0 and columns are 16-byte
+// aligned, else 1).  The core values are wave-uniform and come through scalar
+// loads as the scalar operand of v_fma_f64 (constant address space).
+// Core order: Mv[(g * Rpad + row) * G + e] = M_k(row, G g + e), rows padded to Rpad.
+// A workgroup has NW waves; wave w computes rows [row0 + w RW, +RW) of 64 x CPL
+// columns (lane l owns columns col0 + l + 64 c).  Output row (a', i) of column
+// q goes to a' + r_k (q + C_k i), the row-separating store of Algorithm 2.
+// These kernels win on the edge cores (r_0 = 1 or r_d = 1), which are bound
+// by memory traffic rather than arithmetic.
+// ---------------------------------------------------------------------------
+typedef __attribute__((address_space(4))) const double cdouble;
+
+struct ValuArgs {
+  const double* M;        // Mv (group size G of the kernel)
+  const double* in;       // packed input (when in_table == 0)
+  double* out;            // packed output (when out_table == 0)
+  int64_t in_stride;      // elements between vectors
+  int64_t out_stride;
+  int64_t C;              // columns per vector
+  int64_t ncols;          // C * nrhs
+  int64_t n_tiles;        // row tiles * column tiles
+  int32_t R_out, Rpad, K_in, r_out;
+  int32_t n_row_tiles;
+  int32_t in_table, out_table, nseg;
+  double alpha;
+  Segment seg[kMaxSeg];
+};
+
+template <int NW, int RW, int CPL, int G>
+__global__ void __launch_bounds__(64 * NW) core_step_valu64_kernel(const ValuArgs args) {
+  (void)args;
+  const ValuArgs& a = kernarg<ValuArgs>();
+  const int lane = threadIdx.x & 63;
+  // wave index made provably uniform, so core addresses go through scalar loads
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  constexpr int TCOL = 64 * CPL;
+  const int ngroups = a.K_in / G;
+  for (int64_t tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
+    const int rt = (int)(tile % a.n_row_tiles);
+    const int64_t col0 = (tile / a.n_row_tiles) * TCOL;
+    const int row0 = rt * NW * RW + wave * RW;          // wave-uniform
+    const double* xin[CPL];
+    double* yout[CPL];
+    const double* zin[CPL];
+    bool ok[CPL];
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+      const int64_t g = col0 + lane + 64 * c;
+      ok[c] = g < a.ncols;
+      const int64_t gg = ok[c] ? g : 0;
+      const int64_t rhs = gg / a.C;
+      const int64_t q = gg - rhs * a.C;
+      if (a.in_table) {
+        const Segment& sg = a.seg[find_seg(a, rhs)];
+        xin[c] = sg.x + (rhs - sg.rhs_begin) * sg.ldx + q * a.K_in;
+      } else {
+        xin[c] = a.in + rhs * a.in_stride + q * a.K_in;
+      }
+      const int64_t qo = (int64_t)a.r_out * q;
+      if (a.out_table) {
+        const Segment& sg = a.seg[find_seg(a, rhs)];
+        yout[c] = sg.y + (rhs - sg.rhs_begin) * sg.ldy + qo;
+        zin[c] = sg.z ? sg.z + (rhs - sg.rhs_begin) * sg.ldz + qo : nullptr;
+      } else {
+        yout[c] = a.out + rhs * a.out_stride + qo;
+        zin[c] = nullptr;
+      }
+    }
+    double acc[RW][CPL];
+#pragma unroll
+    for (int r = 0; r < RW; ++r)
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) acc[r][c] = 0.0;
+
+    double x[CPL][G];
+    auto load_x = [&](int gi) {
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) {
+        const double* p = xin[c] + (int64_t)gi * G;
+        if constexpr (G > 1) p = static_cast<const double*>(__builtin_assume_aligned(p, 16));
+#pragma unroll
+        for (int e = 0; e < G; ++e) x[c][e] = p[e];
+        if (!ok[c]) {
+#pragma unroll
+          for (int e = 0; e < G; ++e) x[c][e] = 0.0;
+        }
+      }
+    };
+    load_x(0);
+    for (int gi = 0; gi < ngroups; ++gi) {
+      double xc[CPL][G];
+#pragma unroll
+      for (int c = 0; c < CPL; ++c)
+#pragma unroll
+        for (int e = 0; e < G; ++e) xc[c][e] = x[c][e];
+      if (gi + 1 < ngroups) load_x(gi + 1);
+      const cdouble* mrow = (const cdouble*)a.M + ((int64_t)gi * a.Rpad + row0) * G;
+#pragma unroll
+      for (int r = 0; r < RW; ++r)
+#pragma unroll
+        for (int e = 0; e < G; ++e) {
+          const double mv = mrow[r * G + e];
+#pragma unroll
+          for (int c = 0; c < CPL; ++c) acc[r][c] = fma(mv, xc[c][e], acc[r][c]);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+      const int row = row0 + r;
+      if (row >= a.R_out) break;
+      const int ap = row % a.r_out, ir = row / a.r_out;
+      const int64_t off = ap + (int64_t)a.r_out * a.C * ir;
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) {
+        if (!ok[c]) continue;
+        if (a.out_table) {
+          double v = a.alpha * acc[r][c];
+          if (zin[c]) v += zin[c][off];
+          yout[c][off] = v;
+        } else {
+          yout[c][off] = acc[r][c];
         }
       }
     }

@@ -79,7 +79,7 @@ struct KernelCfg {
   int occ;         // resident blocks per CU, 0 = not yet queried
 };
 
-template <class Tc, class Tin, int WRW, int WCW, int WR, int WC, int KC, bool ROL, bool VEC>
+template <class Tc, class Tin, int WRW, int WCW, int WR, int WC, int KC, bool ROL, bool VEC, int KIND>
 static KernelCfg make_cfg(int dt, bool in_f64, int id) {
   KernelCfg k;
   k.dt = dt;
@@ -90,42 +90,63 @@ static KernelCfg make_cfg(int dt, bool in_f64, int id) {
   k.KC = KC;
   k.NT = 64 * WRW * WCW;
   k.id = id;
-  k.fn = reinterpret_cast<const void*>(&core_step_kernel<Tc, Tin, WRW, WCW, WR, WC, KC, ROL, VEC>);
+  if constexpr (KIND == 2)
+    k.fn = reinterpret_cast<const void*>(&core_step_stream_kernel<Tc, Tin, WRW, WCW, WR, WC, KC, ROL, VEC>);
+  else if constexpr (KIND == 1)
+    k.fn = reinterpret_cast<const void*>(&core_step_pipe_kernel<Tc, Tin, WRW, WCW, WR, WC, KC, ROL, VEC>);
+  else
+    k.fn = reinterpret_cast<const void*>(&core_step_kernel<Tc, Tin, WRW, WCW, WR, WC, KC, ROL, VEC>);
   k.occ = 0;
   return k;
 }
 
-// tile shapes: (waves along rows, waves along columns, row blocks per wave,
-// column blocks per wave, rows on lanes)
-#define QTT_SHAPES(X)        \
+// Tile shapes: (id, waves along rows, waves along columns, row blocks per
+// wave, column blocks per wave, rows on lanes).  Ids below 10 use the
+// single-operand-LDS kernel, ids from 10 the pipelined two-operand kernel.
+#define QTT_SHAPES_V1(X)     \
   X(0, 4, 1, 4, 4, true)     \
   X(1, 4, 1, 3, 4, true)     \
   X(2, 1, 4, 1, 4, false)    \
-  X(3, 2, 2, 4, 4, true)     \
-  X(4, 4, 1, 2, 4, true)     \
   X(5, 4, 1, 4, 2, true)     \
-  X(6, 2, 2, 2, 2, true)     \
-  X(7, 1, 4, 1, 2, false)
-static const int kNumShapes = 8;
+  X(6, 2, 2, 2, 2, true)
+#define QTT_SHAPES_V2(X)     \
+  X(10, 4, 1, 4, 4, true)    \
+  X(11, 4, 1, 4, 2, true)    \
+  X(13, 1, 4, 1, 4, false)
+#define QTT_SHAPES_V3(X)     \
+  X(20, 4, 1, 4, 4, true)    \
+  X(21, 4, 1, 4, 2, true)    \
+  X(22, 4, 1, 3, 4, true)    \
+  X(23, 1, 4, 1, 4, false)   \
+  X(24, 2, 2, 4, 4, true)    \
+  X(25, 4, 1, 2, 4, true)    \
+  X(26, 4, 1, 4, 1, true)    \
+  X(27, 1, 4, 1, 2, false)
 static const int kGenericShape = 6;
 
-template <class Tc, class Tin, int KC>
+template <class Tc, class Tin, int KC1, int KC2>
 static void add_family(std::vector<KernelCfg>& v, int dt, bool in_f64) {
-#define QTT_ADD(id, a, b, c, d, rol) v.push_back(make_cfg<Tc, Tin, a, b, c, d, KC, rol, true>(dt, in_f64, id));
-  QTT_SHAPES(QTT_ADD)
-#undef QTT_ADD
+#define QTT_ADD1(id, a, b, c, d, rol) v.push_back(make_cfg<Tc, Tin, a, b, c, d, KC1, rol, true, 0>(dt, in_f64, id));
+#define QTT_ADD2(id, a, b, c, d, rol) v.push_back(make_cfg<Tc, Tin, a, b, c, d, KC2, rol, true, 1>(dt, in_f64, id));
+#define QTT_ADD3(id, a, b, c, d, rol) v.push_back(make_cfg<Tc, Tin, a, b, c, d, KC1, rol, true, 2>(dt, in_f64, id));
+  QTT_SHAPES_V1(QTT_ADD1)
+  QTT_SHAPES_V2(QTT_ADD2)
+  QTT_SHAPES_V3(QTT_ADD3)
+#undef QTT_ADD1
+#undef QTT_ADD2
+#undef QTT_ADD3
   // scalar-load fallback for shapes whose columns are not 16-byte aligned
-  v.push_back(make_cfg<Tc, Tin, 2, 2, 2, 2, KC, true, false>(dt, in_f64, kGenericShape));
+  v.push_back(make_cfg<Tc, Tin, 2, 2, 2, 2, KC1, true, false, 0>(dt, in_f64, kGenericShape));
 }
 
 static std::vector<KernelCfg>& registry() {
   static std::vector<KernelCfg> reg = [] {
     std::vector<KernelCfg> v;
-    add_family<double, double, 32>(v, 0, true);
-    add_family<float, float, 32>(v, 1, false);
-    add_family<float, double, 32>(v, 1, true);
-    add_family<bf16_tag, uint16_t, 128>(v, 2, false);
-    add_family<bf16_tag, double, 128>(v, 2, true);
+    add_family<double, double, 32, 16>(v, 0, true);
+    add_family<float, float, 32, 32>(v, 1, false);
+    add_family<float, double, 32, 32>(v, 1, true);
+    add_family<bf16_tag, uint16_t, 128, 64>(v, 2, false);
+    add_family<bf16_tag, double, 32, 64>(v, 2, true);   // first core: K_in = n_1 is small
     return v;
   }();
   return reg;
@@ -135,6 +156,71 @@ static KernelCfg* find_cfg(int dt, bool in_f64, bool vec, int id) {
   for (auto& k : registry())
     if (k.dt == dt && k.in_f64 == in_f64 && k.vec == vec && k.id == id) return &k;
   return nullptr;
+}
+
+// Row blocks to allocate for a core with nRB real ones: the largest
+// ceil(nRB / t) * t over the tile heights t (in row blocks) of the registry.
+static int padded_row_blocks(int nRB) {
+  int pad = nRB;
+  for (auto& k : registry()) {
+    const int t = k.TR / 16;
+    pad = std::max(pad, (nRB + t - 1) / t * t);
+  }
+  return pad;
+}
+
+// Shape ids available for (dtype, input type) with vector loads.
+static std::vector<int> shape_ids(int dt, bool in_f64) {
+  std::vector<int> ids;
+  for (auto& k : registry())
+    if (k.dt == dt && k.in_f64 == in_f64 && k.vec) ids.push_back(k.id);
+  return ids;
+}
+
+// FP64 vector-ALU kernels: (id, waves, rows per wave, columns per lane, input group size).
+struct ValuCfg {
+  int id, NW, RW, CPL, G;
+  const void* fn;
+  int occ;
+};
+#define QTT_VALU_SHAPES(X)   \
+  X(40, 8, 24, 1, 8)         \
+  X(41, 4, 24, 2, 8)         \
+  X(42, 4, 32, 1, 8)         \
+  X(43, 4, 16, 1, 8)         \
+  X(44, 8, 16, 1, 8)         \
+  X(45, 1, 8, 4, 8)          \
+  X(46, 2, 8, 2, 8)          \
+  X(47, 1, 8, 2, 8)          \
+  X(48, 4, 16, 1, 1)
+static const int kValuGeneric = 48;
+
+static std::vector<ValuCfg>& valu_registry() {
+  static std::vector<ValuCfg> reg = [] {
+    std::vector<ValuCfg> v;
+#define QTT_ADDV(id, nw, rw, cpl, nj) \
+    v.push_back({id, nw, rw, cpl, nj, reinterpret_cast<const void*>(&core_step_valu64_kernel<nw, rw, cpl, nj>), 0});
+    QTT_VALU_SHAPES(QTT_ADDV)
+#undef QTT_ADDV
+    return v;
+  }();
+  return reg;
+}
+
+static ValuCfg* find_valu(int id) {
+  for (auto& k : valu_registry())
+    if (k.id == id) return &k;
+  return nullptr;
+}
+
+// Rows of the FP64 vector-ALU core copy: every tile height divides it.
+static int valu_padded_rows(int R_out) {
+  int pad = R_out;
+  for (auto& k : valu_registry()) {
+    const int t = k.NW * k.RW;
+    pad = std::max(pad, (R_out + t - 1) / t * t);
+  }
+  return pad;
 }
 
 static int num_cus() {
@@ -148,6 +234,15 @@ static int num_cus() {
 }
 
 static std::mutex g_occ_mu;
+static int occupancy_fn(const void* fn, int nt, int* cache) {
+  std::lock_guard<std::mutex> lk(g_occ_mu);
+  if (*cache == 0) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, nt, 0) != hipSuccess || nb < 1) nb = 1;
+    *cache = nb;
+  }
+  return *cache;
+}
 static int occupancy(KernelCfg* k) {
   std::lock_guard<std::mutex> lk(g_occ_mu);
   if (k->occ == 0) {
@@ -170,6 +265,9 @@ struct CoreDev {
   int Ksteps[3];
   void* frag[3];
   int tuned[3];       // tuned shape id per dtype, -1 = heuristic
+  double* valu;       // FP64 vector-ALU copy Mv, input groups of 8 (when K_in % 8 == 0)
+  double* valu1;      // FP64 vector-ALU copy Mv, groups of 1
+  int Rpad;           // rows of Mv
 };
 
 struct qtt_matrix_s {
@@ -180,26 +278,50 @@ struct qtt_matrix_s {
   int device = 0;
   std::vector<CoreDev> core;
   int64_t max_inter = 0;  // largest y_k (k < d) per vector, elements
+  // captured sweeps: a sweep with the same dtype, vectors, pointers, workspace
+  // and alpha replays its graph instead of launching d kernels
+  struct Graph {
+    std::string key;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+  };
+  mutable std::mutex graph_mu;
+  mutable std::vector<Graph> graphs;   // most recent last
+  mutable hipStream_t cap_stream = nullptr;
+  mutable uint64_t tune_gen = 0;       // bumped when tile choices change
 };
+
+static const size_t kMaxGraphs = 48;
+
+static void drop_graphs(const qtt_matrix_s* A) {
+  std::lock_guard<std::mutex> lk(A->graph_mu);
+  for (auto& g : A->graphs) {
+    (void)hipGraphExecDestroy(g.exec);
+    (void)hipGraphDestroy(g.graph);
+  }
+  A->graphs.clear();
+  ++A->tune_gen;
+}
 
 static bool valid_handle(qtt_matrix_t A) { return A != nullptr && A->d > 0; }
 
-// Process-wide table of tuned shapes, keyed by (dtype, R_out, K_in, r_out, C, nrhs bucket).
+// Process-wide table of tuned shapes, keyed by (dtype, R_out, K_in, r_out, C).
+// It does not depend on the number of vectors, so a vector's kernels (and
+// hence its bits) are the same whatever batch it is part of.
 static std::mutex g_tune_mu;
-static std::map<std::tuple<int, int, int, int, int64_t, int>, int> g_tuned;
+static std::map<std::tuple<int, int, int, int, int64_t>, int> g_tuned;
 
-static int nrhs_bucket(int64_t nrhs) {
-  int b = 0;
-  while ((1LL << b) < nrhs && b < 40) ++b;
-  return b;
+static bool tune_log() {
+  const char* s = getenv("QTT_TUNE_LOG");
+  return s && s[0] == '1';
 }
 
-static int heuristic_shape(int R_out) {
-  if (R_out <= 16) return 2;
+// Untuned defaults, from tuning runs on MI355X at L = 7, r = 32.
+static int heuristic_shape(int R_out, int K_in, int dt) {
+  if (R_out <= 16) return dt == 0 ? 47 : 2;      // last core (r_d = 1)
+  if (K_in <= 16) return dt == 0 ? 6 : 26;       // first core (r_0 = 1)
   if (R_out <= 64) return kGenericShape;
-  if (R_out <= 128) return 4;
-  if (R_out <= 192) return 1;
-  return 0;
+  return dt == 2 ? 5 : 21;                       // interior cores
 }
 
 // ---------------------------------------------------------------------------
@@ -228,6 +350,86 @@ static bool timing_on() {
 // ---------------------------------------------------------------------------
 // launching one core step
 // ---------------------------------------------------------------------------
+// FP64 vector-ALU shape ids are 40..48; anything else is a matrix-core shape.
+static bool is_valu_shape(int id) { return id >= 40 && id < 50; }
+
+static void record_timing(TimedLaunch& tl, const qtt_matrix_s* A, int k, int dt, int64_t ncols,
+                          const Segment* segs, int nseg);
+
+static qtt_status_t launch_valu(const qtt_matrix_s* A, int k, int64_t nrhs, const Segment* segs, int nseg,
+                                const void* in_packed, void* out_packed, double alpha, int id, hipStream_t st) {
+  const CoreDev& c = A->core[k];
+  const bool first = (k == 0), last = (k == A->d - 1);
+  ValuCfg* vc = find_valu(id);
+  // grouped kernels read each lane's inputs as aligned 16-byte vectors
+  bool aligned = (c.K_in % 8) == 0 && c.valu != nullptr;
+  if (first) {
+    for (int s = 0; s < nseg && aligned; ++s)
+      aligned = (reinterpret_cast<uintptr_t>(segs[s].x) % 16 == 0) && (segs[s].ldx % 2 == 0);
+  } else {
+    aligned = aligned && (reinterpret_cast<uintptr_t>(in_packed) % 16 == 0);
+  }
+  if (!vc || (vc->G == 8 && !aligned)) vc = find_valu(kValuGeneric);
+  ValuArgs a;
+  memset(&a, 0, sizeof(a));
+  a.M = (vc->G == 8) ? c.valu : c.valu1;
+  a.in = static_cast<const double*>(in_packed);
+  a.out = static_cast<double*>(out_packed);
+  a.in_stride = c.C * c.K_in;
+  a.out_stride = c.out_len;
+  a.C = c.C;
+  a.ncols = c.C * nrhs;
+  a.R_out = c.R_out;
+  a.Rpad = c.Rpad;
+  a.K_in = c.K_in;
+  a.r_out = c.r_out;
+  const int trows = vc->NW * vc->RW;
+  a.n_row_tiles = (c.R_out + trows - 1) / trows;
+  const int64_t col_tiles = (a.ncols + 64 * vc->CPL - 1) / (64 * vc->CPL);
+  a.n_tiles = col_tiles * a.n_row_tiles;
+  a.in_table = first ? 1 : 0;
+  a.out_table = last ? 1 : 0;
+  a.nseg = nseg;
+  a.alpha = alpha;
+  for (int s = 0; s < nseg; ++s) a.seg[s] = segs[s];
+  const int nt = 64 * vc->NW;
+  const int64_t resident = (int64_t)occupancy_fn(vc->fn, nt, &vc->occ) * num_cus();
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(a.n_tiles, resident));
+  TimedLaunch tl;
+  const bool timed = timing_on();
+  if (timed) {
+    HIP_TRY(hipEventCreate(&tl.a));
+    HIP_TRY(hipEventCreate(&tl.b));
+    HIP_TRY(hipEventRecord(tl.a, st));
+  }
+  void* args[] = {&a};
+  HIP_TRY(hipLaunchKernel(vc->fn, dim3(grid), dim3(nt), args, 0, st));
+  if (timed) {
+    HIP_TRY(hipEventRecord(tl.b, st));
+    record_timing(tl, A, k, 0, a.ncols, segs, nseg);
+  }
+  return QTT_OK;
+}
+
+static void record_timing(TimedLaunch& tl, const qtt_matrix_s* A, int k, int dt, int64_t ncols,
+                          const Segment* segs, int nseg) {
+  const CoreDev& c = A->core[k];
+  const bool first = (k == 0), last = (k == A->d - 1);
+  tl.dt = dt;
+  tl.pos = (A->d == 1) ? 3 : (first ? 1 : (last ? 2 : 0));
+  const double colsd = (double)ncols;
+  tl.flops = 2.0 * c.R_out * c.K_in * colsd;
+  const double ib = first ? 8.0 : kElemBytes[dt];
+  const double ob = last ? 8.0 : kElemBytes[dt];
+  tl.bytes = colsd * (c.K_in * ib + (double)c.R_out * ob);
+  if (last) {
+    bool z = false;
+    for (int s = 0; s < nseg; ++s) z = z || segs[s].z != nullptr;
+    if (z) tl.bytes += colsd * c.R_out * 8.0;
+  }
+  g_timed.push_back(tl);
+}
+
 static qtt_status_t launch_step(const qtt_matrix_s* A, int k, int dt, int64_t nrhs,
                                 const Segment* segs, int nseg, const void* in_packed,
                                 void* out_packed, double alpha, hipStream_t st) {
@@ -248,9 +450,11 @@ static qtt_status_t launch_step(const qtt_matrix_s* A, int k, int dt, int64_t nr
   int shape = c.tuned[dt];
   if (shape < 0) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    auto it = g_tuned.find(std::make_tuple(dt, c.R_out, c.K_in, c.r_out, c.C, nrhs_bucket(nrhs)));
-    shape = (it != g_tuned.end()) ? it->second : heuristic_shape(c.R_out);
+    auto it = g_tuned.find(std::make_tuple(dt, c.R_out, c.K_in, c.r_out, c.C));
+    shape = (it != g_tuned.end()) ? it->second : heuristic_shape(c.R_out, c.K_in, dt);
   }
+  if (dt == 0 && is_valu_shape(shape))
+    return launch_valu(A, k, nrhs, segs, nseg, in_packed, out_packed, alpha, shape, st);
   KernelCfg* kc = vec ? find_cfg(dt, in_f64, true, shape) : find_cfg(dt, in_f64, false, kGenericShape);
   if (!kc) return fail(QTT_ERR_DEVICE, "no kernel for dtype %d shape %d", dt, shape);
 
@@ -291,19 +495,7 @@ static qtt_status_t launch_step(const qtt_matrix_s* A, int k, int dt, int64_t nr
   HIP_TRY(hipLaunchKernel(kc->fn, dim3(grid), dim3(kc->NT), args, 0, st));
   if (timed) {
     HIP_TRY(hipEventRecord(tl.b, st));
-    tl.dt = dt;
-    tl.pos = (A->d == 1) ? 3 : (first ? 1 : (last ? 2 : 0));
-    const double colsd = (double)a.ncols;
-    tl.flops = 2.0 * c.R_out * c.K_in * colsd;
-    const double ib = first ? 8.0 : kElemBytes[dt];
-    const double ob = last ? 8.0 : kElemBytes[dt];
-    tl.bytes = colsd * (c.K_in * ib + (double)c.R_out * ob);
-    if (last) {
-      bool z = false;
-      for (int s = 0; s < nseg; ++s) z = z || segs[s].z != nullptr;
-      if (z) tl.bytes += colsd * c.R_out * 8.0;
-    }
-    g_timed.push_back(tl);
+    record_timing(tl, A, k, dt, a.ncols, segs, nseg);
   }
   return QTT_OK;
 }
@@ -341,6 +533,68 @@ static qtt_status_t sweep(const qtt_matrix_s* A, int dt, int64_t nrhs, const Seg
   return QTT_OK;
 }
 
+static bool graphs_enabled() {
+  static int on = [] {
+    const char* e = getenv("QTT_GRAPH");
+    return (e && e[0] == '0') ? 0 : 1;
+  }();
+  return on == 1;
+}
+
+// One sweep, captured into a graph on first use and replayed afterwards.
+// Capture runs on the handle's own stream (the caller's stream may be the
+// null stream, which cannot be captured); the graph is launched on the
+// caller's stream.  Timed runs launch directly (per-launch events).
+static qtt_status_t sweep_graph(const qtt_matrix_s* A, int dt, int64_t nrhs, const Segment* segs, int nseg,
+                                void* ws, double alpha, hipStream_t st) {
+  if (!graphs_enabled() || timing_on()) return sweep(A, dt, nrhs, segs, nseg, ws, alpha, st);
+  std::string key;
+  auto put = [&](const void* p, size_t n) { key.append(static_cast<const char*>(p), n); };
+  put(&dt, sizeof dt);
+  put(&nrhs, sizeof nrhs);
+  put(&alpha, sizeof alpha);
+  put(&ws, sizeof ws);
+  put(&A->tune_gen, sizeof A->tune_gen);
+  for (int i = 0; i < nseg; ++i) put(&segs[i], sizeof(Segment));
+  std::lock_guard<std::mutex> lk(A->graph_mu);
+  for (size_t i = 0; i < A->graphs.size(); ++i) {
+    if (A->graphs[i].key == key) {
+      qtt_matrix_s::Graph g = A->graphs[i];
+      A->graphs.erase(A->graphs.begin() + i);
+      A->graphs.push_back(g);
+      HIP_TRY(hipGraphLaunch(g.exec, st));
+      return QTT_OK;
+    }
+  }
+  // first use: run directly (this also settles every lazily queried launch
+  // parameter), then capture the same launches for later calls
+  qtt_status_t s0 = sweep(A, dt, nrhs, segs, nseg, ws, alpha, st);
+  if (s0 != QTT_OK) return s0;
+  if (A->cap_stream == nullptr) HIP_TRY(hipStreamCreateWithFlags(&A->cap_stream, hipStreamNonBlocking));
+  HIP_TRY(hipStreamBeginCapture(A->cap_stream, hipStreamCaptureModeThreadLocal));
+  qtt_status_t s = sweep(A, dt, nrhs, segs, nseg, ws, alpha, A->cap_stream);
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamEndCapture(A->cap_stream, &graph);
+  if (s != QTT_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return s;
+  }
+  if (e != hipSuccess) return fail(QTT_ERR_DEVICE, "hipStreamEndCapture failed: %s", hipGetErrorString(e));
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    return fail(QTT_ERR_DEVICE, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
+  }
+  if (A->graphs.size() >= kMaxGraphs) {
+    (void)hipGraphExecDestroy(A->graphs.front().exec);
+    (void)hipGraphDestroy(A->graphs.front().graph);
+    A->graphs.erase(A->graphs.begin());
+  }
+  A->graphs.push_back({key, graph, exec});
+  return QTT_OK;
+}
+
 // A block of vectors before splitting into waves.
 struct Block {
   const double* x;
@@ -365,7 +619,7 @@ static qtt_status_t run_blocks(const qtt_matrix_s* A, int dt, const std::vector<
   int64_t in_wave = 0;
   auto flush = [&]() -> qtt_status_t {
     if (in_wave == 0) return QTT_OK;
-    qtt_status_t s = sweep(A, dt, in_wave, segs.data(), (int)segs.size(), ws, alpha, st);
+    qtt_status_t s = sweep_graph(A, dt, in_wave, segs.data(), (int)segs.size(), ws, alpha, st);
     segs.clear();
     in_wave = 0;
     return s;
@@ -476,6 +730,9 @@ qtt_status_t qtt_matrix_load(int32_t d, const int64_t* ranks, const int64_t* m, 
     c.out_len = (int64_t)c.r_out * c.C * c.m;
     c.nRB = (c.R_out + 15) / 16;
     for (int t = 0; t < 3; ++t) { c.frag[t] = nullptr; c.Ksteps[t] = 0; c.tuned[t] = -1; }
+    c.valu = nullptr;
+    c.valu1 = nullptr;
+    c.Rpad = 0;
     if (k < d - 1) A->max_inter = std::max(A->max_inter, c.out_len);
   }
 
@@ -489,7 +746,11 @@ qtt_status_t qtt_matrix_load(int32_t d, const int64_t* ranks, const int64_t* m, 
       const int KS = kKstep[t], E = kFragE[t];
       const int Ksteps = (c.K_in + KS - 1) / KS;
       c.Ksteps[t] = Ksteps;
-      const size_t nel = (size_t)c.nRB * Ksteps * 64 * E;
+      // row blocks padded with zeros so that every tile height of the
+      // registry covers a whole number of tiles: kernels may then read the
+      // row blocks of any tile without bounds tests
+      const int nRBpad = padded_row_blocks(c.nRB);
+      const size_t nel = (size_t)nRBpad * Ksteps * 64 * E;
       std::vector<double> h(nel, 0.0);
       for (int rb = 0; rb < c.nRB; ++rb)
         for (int s = 0; s < Ksteps; ++s)
@@ -528,15 +789,51 @@ qtt_status_t qtt_matrix_load(int32_t d, const int64_t* ranks, const int64_t* m, 
       }
     }
   }
+  // FP64 vector-ALU copies: Mv[(g * Rpad + row) * G + e] = M_k(row, G g + e)
+  if (dtypes & QTT_FP64) {
+    for (int k = 0; k < d; ++k) {
+      CoreDev& c = A->core[k];
+      const double* G = cores[k];
+      c.Rpad = valu_padded_rows(c.R_out);
+      for (int gs : {8, 1}) {
+        if (c.K_in % gs) continue;
+        const size_t nel = (size_t)c.K_in * c.Rpad;
+        std::vector<double> h(nel, 0.0);
+        for (int row = 0; row < c.R_out; ++row)
+          for (int kap = 0; kap < c.K_in; ++kap) {
+            const int ak = row % c.r_out, ik = row / c.r_out;
+            const int ap = kap % c.r_in, jk = kap / c.r_in;
+            h[((size_t)(kap / gs) * c.Rpad + row) * gs + kap % gs] =
+                G[(((size_t)ap * c.m + ik) * c.n + jk) * c.r_out + ak];
+          }
+        void* dptr = nullptr;
+        if (hipMalloc(&dptr, std::max<size_t>(nel * 8, 256)) != hipSuccess) {
+          qtt_matrix_free(A);
+          return fail(QTT_ERR_OUT_OF_MEMORY, "hipMalloc for the FP64 vector-ALU copy of core %d failed", k);
+        }
+        (gs == 8 ? c.valu : c.valu1) = static_cast<double*>(dptr);
+        hipError_t er = hipMemcpy(dptr, h.data(), nel * 8, hipMemcpyHostToDevice);
+        if (er != hipSuccess) {
+          qtt_matrix_free(A);
+          return fail(QTT_ERR_DEVICE, "hipMemcpy of core %d failed: %s", k, hipGetErrorString(er));
+        }
+      }
+    }
+  }
   *out = A;
   return QTT_OK;
 }
 
 qtt_status_t qtt_matrix_free(qtt_matrix_t A) {
   if (A == nullptr) return QTT_OK;
-  for (auto& c : A->core)
+  drop_graphs(A);
+  if (A->cap_stream) (void)hipStreamDestroy(A->cap_stream);
+  for (auto& c : A->core) {
     for (int t = 0; t < 3; ++t)
       if (c.frag[t]) (void)hipFree(c.frag[t]);
+    if (c.valu) (void)hipFree(c.valu);
+    if (c.valu1) (void)hipFree(c.valu1);
+  }
   delete A;
   return QTT_OK;
 }
@@ -615,6 +912,7 @@ qtt_status_t qtt_autotune(qtt_matrix_t A, qtt_dtype_t compute, int64_t nrhs, con
                           double* Y, int64_t ldy, void* ws, size_t ws_bytes, void* stream) {
   qtt_status_t s = qtt_apply(A, compute, nrhs, X, ldx, Y, ldy, ws, ws_bytes, stream);  // validates, warms up
   if (s != QTT_OK) return s;
+  drop_graphs(A);
   int dt = dt_index(compute);
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int64_t cap = wave_capacity(A, dt, ws_bytes);
@@ -633,7 +931,12 @@ qtt_status_t qtt_autotune(qtt_matrix_t A, qtt_dtype_t compute, int64_t nrhs, con
     void* out = (k == A->d - 1) ? nullptr : buf[k & 1];
     float best = 1e30f;
     int best_id = -1;
-    for (int id = 0; id < kNumShapes; ++id) {
+    const bool in_f64 = (k == 0) || dt == 0;
+    std::vector<int> ids = shape_ids(dt, in_f64);
+    if (dt == 0)
+      for (auto& vc : valu_registry())
+        if (vc.G == 1 || c.K_in % vc.G == 0) ids.push_back(vc.id);
+    for (int id : ids) {
       c.tuned[dt] = id;
       for (int rep = 0; rep < 2; ++rep) {           // warm-up + timed
         HIP_TRY(hipEventRecord(e0, st));
@@ -646,13 +949,17 @@ qtt_status_t qtt_autotune(qtt_matrix_t A, qtt_dtype_t compute, int64_t nrhs, con
       HIP_TRY(hipEventSynchronize(e1));
       float ms = 0;
       HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+      if (tune_log())
+        fprintf(stderr, "qtt_autotune dtype %d core %d (%d x %d, %lld cols) shape %d: %.4f ms\n", dt, k,
+                c.R_out, c.K_in, (long long)(c.C * w), id, ms / 3);
       if (ms < best) { best = ms; best_id = id; }
     }
     c.tuned[dt] = best_id;
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tuned[std::make_tuple(dt, c.R_out, c.K_in, c.r_out, c.C, nrhs_bucket(nrhs))] = best_id;
+    g_tuned[std::make_tuple(dt, c.R_out, c.K_in, c.r_out, c.C)] = best_id;
   }
   g_timing = was_timing;
+  drop_graphs(A);
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   // leave Y = A X computed with the tuned shapes

@@ -1,0 +1,292 @@
+"""Continuous-batching solve server over resident QTT operators.
+
+Each operator is a pair (A, Ainv) of QTT matrices held on the device for the
+server's lifetime: A in FP64 for the residual, Ainv in a low-precision dtype
+for the refinement.  Requests (an operator id and a block of right-hand
+sides) arrive over time.  A fixed number of slots, each a host thread with
+its own HIP stream, run refined solves (``qtt_solve``) concurrently, so work
+of different batches overlaps on the device.  Whenever a slot is free, the
+scheduler admits the oldest waiting request's operator and coalesces every
+waiting request for that operator into one batch, as far as the device
+memory budget and the batch width allow; requests that arrive while other
+batches run are admitted as soon as a slot and memory free up.
+
+The per-column arithmetic of the apply and of the solve does not depend on
+the other columns of a batch (no cross-column reductions, a fixed kernel per
+core once an operator is loaded), so a request's result is the same alone
+and in any mix.
+
+All numerics run in libqtt; this module only schedules, copies request
+blocks into batch buffers, and records latencies.
+"""
+from __future__ import annotations
+
+import threading
+import time
+from collections import deque
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import qtt as Q
+
+
+@dataclass
+class Request:
+    rid: int
+    op: str
+    F: torch.Tensor               # (N, k) column-major FP64 on the device
+    arrival: float = 0.0          # seconds on the server clock
+    Sigma: torch.Tensor | None = None
+    info: list = field(default_factory=list)
+    status: int = -1
+    admitted: float = -1.0
+    done: float = -1.0
+    batch_id: int = -1
+    error: str = ""
+
+    @property
+    def k(self):
+        return 1 if self.F.dim() == 1 else self.F.shape[1]
+
+    @property
+    def latency(self):
+        return self.done - self.arrival
+
+
+def choose_batch(pending, in_use, budget, max_rhs, bytes_fn):
+    """Admission policy.  pending: {op: deque of requests in arrival order}
+    (each with .arrival and .k).  Operators are tried in the order of their
+    oldest waiting request; for the first one whose oldest request fits the
+    remaining budget, the waiting requests are taken in arrival order while
+    the batch stays within max_rhs columns and the budget.  Returns
+    (op, requests, columns, bytes) or None when nothing fits now."""
+    heads = sorted((q[0].arrival, op) for op, q in pending.items() if q)
+    for _, op in heads:
+        reqs, k = [], 0
+        for r in pending[op]:
+            if reqs and k + r.k > max_rhs:
+                break
+            if in_use + bytes_fn(op, k + r.k) > budget:
+                break
+            reqs.append(r)
+            k += r.k
+        if reqs:
+            return op, reqs, k, bytes_fn(op, k)
+    return None
+
+
+class SolveServer:
+    """Refined solves for resident operators with continuous batching.
+
+    operators: {name: (A_cores, Ainv_cores)} host FP64 cores.
+    budget_bytes: device memory the batches in flight may hold together
+        (solve workspace + batch right-hand sides + solutions).
+    """
+
+    def __init__(self, operators, inv_dtype="bf16", budget_bytes=200 * 10 ** 9, n_slots=3,
+                 rtol=1e-8, max_iter=50, max_batch_rhs=64, device="cuda"):
+        self.inv_dtype = inv_dtype
+        self.budget = int(budget_bytes)
+        self.rtol = rtol
+        self.max_iter = max_iter
+        self.max_batch_rhs = max_batch_rhs
+        self.device = torch.device(device)
+        self.ops = {}
+        for name, (Ac, Aic) in operators.items():
+            A = Q.qtt_matrix_load(Ac, dtypes=("fp64",))
+            Ai = Q.qtt_matrix_load(Aic, dtypes=(inv_dtype,))
+            self.ops[name] = (A, Ai)
+        self.n_slots = n_slots
+        self._lock = threading.Condition()
+        self._pending = {name: deque() for name in self.ops}
+        self._in_use = 0
+        self._busy = 0
+        self._closed = False
+        self._batches = 0
+        self.t0 = time.perf_counter()
+        self.log = []                 # (batch_id, op, rids, admitted, done)
+        self._workers = [threading.Thread(target=self._worker, args=(i,), daemon=True)
+                         for i in range(n_slots)]
+        for w in self._workers:
+            w.start()
+
+    # ------------------------------------------------------------ memory model
+    def batch_bytes(self, op, k):
+        A, Ai = self.ops[op]
+        ws = Q.qtt_solve_workspace_bytes(A, Ai, self.inv_dtype, k)
+        return ws + 2 * A.rows * k * 8
+
+    def now(self):
+        return time.perf_counter() - self.t0
+
+    # ------------------------------------------------------------ client side
+    def submit(self, req: Request):
+        if req.op not in self.ops:
+            raise KeyError(f"unknown operator {req.op}")
+        A, _ = self.ops[req.op]
+        if req.F.shape[0] != A.rows:
+            raise ValueError("right-hand side length does not match the operator")
+        if self.batch_bytes(req.op, req.k) > self.budget:
+            raise MemoryError(f"request {req.rid} needs more than the whole budget")
+        with self._lock:
+            req.arrival = self.now() if req.arrival <= 0 else req.arrival
+            self._pending[req.op].append(req)
+            self._lock.notify_all()
+
+    def close(self):
+        with self._lock:
+            self._closed = True
+            self._lock.notify_all()
+        for w in self._workers:
+            w.join()
+        for A, Ai in self.ops.values():
+            A.free()
+            Ai.free()
+
+    # ------------------------------------------------------------ scheduling
+    def _take_batch(self):
+        """Called with the lock held: the next batch, or None."""
+        got = choose_batch(self._pending, self._in_use, self.budget, self.max_batch_rhs, self.batch_bytes)
+        if got is None:
+            return None
+        op, reqs, k, nbytes = got
+        for _ in reqs:
+            self._pending[op].popleft()
+        self._in_use += nbytes
+        self._batches += 1
+        return op, reqs, k, nbytes, self._batches
+
+    def _worker(self, slot):
+        stream = torch.cuda.Stream(device=self.device)
+        while True:
+            with self._lock:
+                while True:
+                    if self._closed and not any(self._pending.values()):
+                        return
+                    got = self._take_batch()
+                    if got is not None:
+                        break
+                    self._lock.wait(timeout=0.05)
+                self._busy += 1
+            op, reqs, k, nbytes, bid = got
+            t_adm = self.now()
+            try:
+                self._run(op, reqs, k, stream, bid, t_adm)
+            except Exception as e:          # report the failure on the requests, keep serving
+                t = self.now()
+                for r in reqs:
+                    r.status, r.done, r.admitted, r.batch_id = -2, t, t_adm, bid
+                    r.error = repr(e)
+            finally:
+                with self._lock:
+                    self._in_use -= nbytes
+                    self._busy -= 1
+                    self._lock.notify_all()
+
+    def _run(self, op, reqs, k, stream, bid, t_adm):
+        A, Ai = self.ops[op]
+        N = A.rows
+        stream.wait_stream(torch.cuda.default_stream(self.device))   # request blocks are ready
+        with torch.cuda.stream(stream):
+            Fb = Q.empty_block(N, k, self.device)
+            c = 0
+            for r in reqs:
+                Fb[:, c:c + r.k].copy_(r.F.reshape(N, r.k))
+                c += r.k
+            Sb = Q.empty_block(N, k, self.device)
+            ws = Q.workspace(Q.qtt_solve_workspace_bytes(A, Ai, self.inv_dtype, k), self.device)
+        _, info, st = Q.qtt_solve(A, Ai, self.inv_dtype, Fb, Sb, rtol=self.rtol, max_iter=self.max_iter,
+                                  ws=ws, stream=stream, raise_on_fail=False)
+        stream.synchronize()
+        t_done = self.now()
+        c = 0
+        for r in reqs:
+            r.Sigma = Sb[:, c:c + r.k]
+            r.info = info[c:c + r.k]
+            r.status = st
+            r.admitted = t_adm
+            r.done = t_done
+            r.batch_id = bid
+            c += r.k
+        with self._lock:
+            self.log.append((bid, op, [r.rid for r in reqs], t_adm, t_done))
+
+    # ------------------------------------------------------------ traces
+    def run_trace(self, requests, realtime=True):
+        """Submit requests at their arrival times (seconds from now), wait for
+        all of them, and return summary statistics."""
+        start = self.now()
+        for r in sorted(requests, key=lambda r: r.arrival):
+            if realtime:
+                delay = start + r.arrival - self.now()
+                if delay > 0:
+                    time.sleep(delay)
+            r.arrival = start + r.arrival
+            self.submit(r)
+        while True:
+            with self._lock:
+                if all(r.done >= 0 for r in requests):
+                    break
+                self._lock.wait(timeout=0.05)
+        return summarize(requests)
+
+
+def summarize(requests):
+    lat = np.array([r.latency for r in requests]) * 1e3
+    rhs = sum(r.k for r in requests)
+    t_first = min(r.arrival for r in requests)
+    t_last = max(r.done for r in requests)
+    worst = max((c[1] for r in requests for c in r.info), default=float("nan"))
+    return {"requests": len(requests), "rhs": rhs, "wall_s": t_last - t_first,
+            "rhs_per_s": rhs / (t_last - t_first), "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99)), "max_rel_residual": worst,
+            "batches": len({r.batch_id for r in requests}),
+            "all_converged": all(r.status == 0 for r in requests)}
+
+
+def _main():
+    """Serving benchmark: a seeded Poisson trace over resident operators."""
+    import argparse
+    import json
+    from . import inputs as I
+    p = argparse.ArgumentParser()
+    p.add_argument("--requests", type=int, default=48)
+    p.add_argument("--rate", type=float, default=200.0)
+    p.add_argument("--ops", type=int, default=12)
+    p.add_argument("--levels", default="5,6,7,8")
+    p.add_argument("--slots", type=int, default=3)
+    p.add_argument("--inv", default="bf16")
+    p.add_argument("--budget-gb", type=float, default=200.0)
+    p.add_argument("--seed", type=int, default=51)
+    args = p.parse_args()
+    levels = tuple(int(x) for x in args.levels.split(","))
+    descs = I.serving_operators(args.ops, levels=levels, seed=args.seed)
+    operators = {}
+    for t, dsc in enumerate(descs):
+        A, Ai = I.perturbed_identity_pair(dsc["ranks"], [8] * dsc["L"], seed=dsc["seed"], eps=0.1)
+        operators[f"op{t}"] = (A, Ai)
+    srv = SolveServer(operators, inv_dtype=args.inv, budget_bytes=int(args.budget_gb * 1e9),
+                      n_slots=args.slots)
+    g = I.rng(args.seed + 1)
+    arrivals = I.poisson_arrivals(args.requests, args.rate, seed=args.seed + 2)
+    reqs = []
+    for i in range(args.requests):
+        t = int(g.integers(args.ops))
+        k = int(g.integers(1, 17))
+        N = 8 ** descs[t]["L"]
+        F = Q.to_block(I.rhs(N, k, seed=args.seed * 7919 + i))
+        reqs.append(Request(rid=i, op=f"op{t}", F=F, arrival=float(arrivals[i])))
+    torch.cuda.synchronize()
+    stats = srv.run_trace(reqs)
+    srv.close()
+    stats.update({"workload": "serving: Poisson trace over resident QTT operators",
+                  "operators": [{"L": d["L"], "r": d["ranks"][1]} for d in descs],
+                  "rate_per_s": args.rate, "slots": args.slots, "inverse_dtype": args.inv,
+                  "budget_gb": args.budget_gb})
+    print(json.dumps(stats), flush=True)
+
+
+if __name__ == "__main__":
+    _main()
