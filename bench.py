@@ -41,6 +41,7 @@ def parse():
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-tune", action="store_true")
+    p.add_argument("--no-batched", action="store_true")
     p.add_argument("--variants", default="bf16,fp64,fp32",
                    help="inverse dtypes to time; the first is the reported value")
     return p.parse_args()
@@ -151,6 +152,8 @@ def main():
                    "kernel": f"core_step_kernel<{head}> on the interior cores of the inverse apply",
                    "launches": lo["launches"], "avg_launch_ms": round(lo["ms"] / lo["launches"], 4)}
 
+    batched = None if args.no_batched else batched_run(Q, torch)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(Ac, Aic, F_h[:, :1], r0["passes"])
@@ -175,17 +178,51 @@ def main():
         "latency_ms": {"p50": round(r0["p50_ms"], 3), "p99": round(r0["p99_ms"], 3)},
         "passes": r0["passes"],
         "max_rel_residual": r0["max_rel_residual"],
-        "variants": {v: {k: (round(x, 4) if isinstance(x, float) else x) for k, x in r.items() if k != "kernels"}
+        "variants": {v: {k: (float(f"{x:.5g}") if isinstance(x, float) else x) for k, x in r.items() if k != "kernels"}
                      for v, r in results.items()},
         "speedup_vs_plain_fp64": (round(r0["rhs_per_s"] / results["fp64"]["rhs_per_s"], 3)
                                   if "fp64" in results and head != "fp64" else None),
         "roofline": roof,
         "roofline_inverse": roof_lo,
+        "batched_uneven_L7": batched,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
     A.free()
     Ai.free()
+
+
+def batched_run(Q, torch):
+    """Uneven batching: 64 blocks of widths drawn from {1,...,32} applied to the
+    L=7 operator in FP32 by one qtt_apply_batched call per repetition (each
+    core is one persistent launch per workspace wave, replayed from a graph)."""
+    from paper_1511_06029_amd import inputs as I
+    w = I.WORKLOADS["batched_L7"]
+    Ac, _ = I.perturbed_identity_pair(w["ranks"], [8] * 7, seed=w["core_seed"])
+    widths = I.uneven_widths(w["nblocks"], seed=w["width_seed"])
+    A = Q.qtt_matrix_load(Ac, dtypes=("fp32",))
+    N = 8 ** 7
+    g = torch.Generator(device="cuda").manual_seed(w["rhs_seed"])
+    Xs = [torch.randn((k, N), generator=g, device="cuda", dtype=torch.float64).t() for k in widths]
+    Ys = [Q.empty_block(N, k) for k in widths]
+    total = sum(widths)
+    ws_bytes = min(Q.qtt_workspace_bytes(A, "fp32", total), 96 * 2 ** 30)
+    ws = Q.workspace(ws_bytes)
+    for _ in range(2):
+        Q.qtt_apply_batched(A, "fp32", Xs, Ys, ws=ws)
+    torch.cuda.synchronize()
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        Q.qtt_apply_batched(A, "fp32", Xs, Ys, ws=ws)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    from oracle import qtt_oracle as O
+    flops = O.alg2_flops(w["ranks"], [8] * 7, [8] * 7) * total
+    A.free()
+    return {"blocks": len(widths), "rhs": total, "ms_per_call": round(dt * 1e3, 2),
+            "rhs_per_s": round(total / dt, 1), "tflops": round(flops / dt / 1e12, 2),
+            "workspace_gb": round(ws_bytes / 2 ** 30, 1), "dtype": "fp32"}
 
 
 def cpu_baseline(Ac, Aic, f, passes):

@@ -55,6 +55,53 @@ class Request:
         return self.done - self.arrival
 
 
+class Arena:
+    """First-fit sub-allocator over one device buffer of the whole budget.
+
+    The server's batches take their workspace, right-hand sides and solutions
+    from here, so the budget is the memory actually reserved (no caching
+    allocator fragmentation can make an admitted batch fail)."""
+
+    ALIGN = 256
+
+    def __init__(self, nbytes, device):
+        self.size = int(nbytes) // self.ALIGN * self.ALIGN
+        self.buf = torch.empty(self.size, dtype=torch.uint8, device=device)
+        self.free = [(0, self.size)]          # sorted (offset, length)
+
+    def alloc(self, nbytes):
+        n = (int(nbytes) + self.ALIGN - 1) // self.ALIGN * self.ALIGN
+        for i, (off, ln) in enumerate(self.free):
+            if ln >= n:
+                if ln == n:
+                    self.free.pop(i)
+                else:
+                    self.free[i] = (off + n, ln - n)
+                return off, n
+        return None
+
+    def release(self, off, n):
+        self.free.append((off, n))
+        self.free.sort()
+        merged = []
+        for o, ln in self.free:
+            if merged and merged[-1][0] + merged[-1][1] == o:
+                merged[-1] = (merged[-1][0], merged[-1][1] + ln)
+            else:
+                merged.append((o, ln))
+        self.free = merged
+
+    def largest(self):
+        return max((ln for _, ln in self.free), default=0)
+
+    def block(self, off, N, k):
+        """(N, k) FP64 column-major view at byte offset off."""
+        return self.buf[off:off + N * k * 8].view(torch.float64).view(k, N).t()
+
+    def bytes(self, off, n):
+        return self.buf[off:off + n]
+
+
 def choose_batch(pending, in_use, budget, max_rhs, bytes_fn):
     """Admission policy.  pending: {op: deque of requests in arrival order}
     (each with .arrival and .k).  Operators are tried in the order of their
@@ -99,6 +146,7 @@ class SolveServer:
             Ai = Q.qtt_matrix_load(Aic, dtypes=(inv_dtype,))
             self.ops[name] = (A, Ai)
         self.n_slots = n_slots
+        self.arena = Arena(self.budget, self.device)
         self._lock = threading.Condition()
         self._pending = {name: deque() for name in self.ops}
         self._in_use = 0
@@ -114,9 +162,7 @@ class SolveServer:
 
     # ------------------------------------------------------------ memory model
     def batch_bytes(self, op, k):
-        A, Ai = self.ops[op]
-        ws = Q.qtt_solve_workspace_bytes(A, Ai, self.inv_dtype, k)
-        return ws + 2 * A.rows * k * 8
+        return self._arena_bytes(op, k)
 
     def now(self):
         return time.perf_counter() - self.t0
@@ -148,15 +194,29 @@ class SolveServer:
     # ------------------------------------------------------------ scheduling
     def _take_batch(self):
         """Called with the lock held: the next batch, or None."""
-        got = choose_batch(self._pending, self._in_use, self.budget, self.max_batch_rhs, self.batch_bytes)
+        # the budget seen by the policy is the largest free block of the arena
+        free = self.arena.largest()
+        got = choose_batch(self._pending, self.budget - free, self.budget, self.max_batch_rhs,
+                           self._arena_bytes)
         if got is None:
             return None
-        op, reqs, k, nbytes = got
+        op, reqs, k, _ = got
+        region = self.arena.alloc(self._arena_bytes(op, k))
+        if region is None:
+            return None
         for _ in reqs:
             self._pending[op].popleft()
-        self._in_use += nbytes
+        self._in_use += region[1]
         self._batches += 1
-        return op, reqs, k, nbytes, self._batches
+        return op, reqs, k, region, self._batches
+
+    def _arena_bytes(self, op, k):
+        """Bytes of one batch as carved from the arena (each part aligned)."""
+        A, Ai = self.ops[op]
+        al = Arena.ALIGN
+        ws = Q.qtt_solve_workspace_bytes(A, Ai, self.inv_dtype, k)
+        blk = (A.rows * k * 8 + al - 1) // al * al
+        return (ws + al - 1) // al * al + 2 * blk
 
     def _worker(self, slot):
         stream = torch.cuda.Stream(device=self.device)
@@ -170,10 +230,10 @@ class SolveServer:
                         break
                     self._lock.wait(timeout=0.05)
                 self._busy += 1
-            op, reqs, k, nbytes, bid = got
+            op, reqs, k, region, bid = got
             t_adm = self.now()
             try:
-                self._run(op, reqs, k, stream, bid, t_adm)
+                self._run(op, reqs, k, stream, bid, t_adm, region)
             except Exception as e:          # report the failure on the requests, keep serving
                 t = self.now()
                 for r in reqs:
@@ -181,29 +241,42 @@ class SolveServer:
                     r.error = repr(e)
             finally:
                 with self._lock:
-                    self._in_use -= nbytes
+                    self.arena.release(*region)
+                    self._in_use -= region[1]
                     self._busy -= 1
                     self._lock.notify_all()
 
-    def _run(self, op, reqs, k, stream, bid, t_adm):
+    def _run(self, op, reqs, k, stream, bid, t_adm, region):
         A, Ai = self.ops[op]
         N = A.rows
+        al = Arena.ALIGN
+        off0, _ = region
+        ws_n = (Q.qtt_solve_workspace_bytes(A, Ai, self.inv_dtype, k) + al - 1) // al * al
+        blk = (N * k * 8 + al - 1) // al * al
+        ws = self.arena.bytes(off0, ws_n)
+        Fb = self.arena.block(off0 + ws_n, N, k)
+        Sb = self.arena.block(off0 + ws_n + blk, N, k)
         stream.wait_stream(torch.cuda.default_stream(self.device))   # request blocks are ready
         with torch.cuda.stream(stream):
-            Fb = Q.empty_block(N, k, self.device)
             c = 0
             for r in reqs:
                 Fb[:, c:c + r.k].copy_(r.F.reshape(N, r.k))
                 c += r.k
-            Sb = Q.empty_block(N, k, self.device)
-            ws = Q.workspace(Q.qtt_solve_workspace_bytes(A, Ai, self.inv_dtype, k), self.device)
         _, info, st = Q.qtt_solve(A, Ai, self.inv_dtype, Fb, Sb, rtol=self.rtol, max_iter=self.max_iter,
                                   ws=ws, stream=stream, raise_on_fail=False)
+        with torch.cuda.stream(stream):
+            outs = []
+            c = 0
+            for r in reqs:        # results leave the arena before the region is reused
+                o = Q.empty_block(N, r.k, self.device)
+                o.copy_(Sb[:, c:c + r.k])
+                outs.append(o)
+                c += r.k
         stream.synchronize()
         t_done = self.now()
         c = 0
-        for r in reqs:
-            r.Sigma = Sb[:, c:c + r.k]
+        for r, o in zip(reqs, outs):
+            r.Sigma = o
             r.info = info[c:c + r.k]
             r.status = st
             r.admitted = t_adm
@@ -243,7 +316,11 @@ def summarize(requests):
             "rhs_per_s": rhs / (t_last - t_first), "p50_ms": float(np.percentile(lat, 50)),
             "p99_ms": float(np.percentile(lat, 99)), "max_rel_residual": worst,
             "batches": len({r.batch_id for r in requests}),
-            "all_converged": all(r.status == 0 for r in requests)}
+            "all_converged": all(r.status == 0 for r in requests),
+            "status_counts": {str(s): sum(1 for r in requests if r.status == s)
+                              for s in sorted({r.status for r in requests})},
+            "first_error": next((r.error for r in requests if r.error), ""),
+            "iters_max": max((c[0] for r in requests for c in r.info), default=0)}
 
 
 def _main():
