@@ -42,6 +42,8 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-tune", action="store_true")
     p.add_argument("--no-batched", action="store_true")
+    p.add_argument("--copy-probe", action="store_true",
+                   help="only run a device copy of known size (HBM counter calibration)")
     p.add_argument("--variants", default="bf16,fp64,fp32",
                    help="inverse dtypes to time; the first is the reported value")
     return p.parse_args()
@@ -67,6 +69,9 @@ def main():
         sys.exit(2)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.copy_probe:
+        copy_probe(torch)
+        return
 
     w = I.WORKLOADS["refine_L7"]
     L, ranks, K, rtol = w["L"], w["ranks"], w["K"], w["rtol"]
@@ -190,6 +195,24 @@ def main():
     print(json.dumps(line), flush=True)
     A.free()
     Ai.free()
+
+
+def copy_probe(torch):
+    """A plain device copy of 1 GiB, five times: reads 1 GiB and writes 1 GiB
+    per launch.  Its HBM counters calibrate those of the core-step kernels."""
+    n = 2 ** 30 // 8
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(5):
+        y.copy_(x)
+    ev[1].record()
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / 5
+    print(json.dumps({"copy_bytes_each_way": 2 ** 30, "launches": 5, "ms_per_copy": round(ms, 4),
+                      "GBs_read_plus_write": round(2 * 2 ** 30 / ms * 1e-6, 1)}), flush=True)
 
 
 def batched_run(Q, torch):

@@ -931,6 +931,334 @@ __global__ void __launch_bounds__(64 * NW) core_step_valu64_kernel(const ValuArg
 }
 
 // ---------------------------------------------------------------------------
+// BF16 interior core step with the core resident in registers.
+//
+// For the interior cores of the BF16 sweep (R_out = r_k m_k <= 256 and
+// K_in = r_{k-1} n_k <= 256, both intermediates packed), the whole core is
+// 128 KB: each of the 4 waves keeps the fragments of its 64 rows for every
+// contraction step in registers for the life of the workgroup, so the main
+// loop moves only the streamed intermediate.  Input tiles of 64 columns are
+// contiguous (32 KB at K_in = 256); they are loaded into registers one tile
+// ahead and written to one of two LDS stages in fragment order.  The output
+// tile is converted to BF16 and written to one of two LDS buffers laid out
+// as it lies in memory (for each i_k, the r_k x 64 block a_k + r_k q is
+// contiguous), then copied out with 16-byte stores.
+// Requirements checked by the host: K_in % 8 == 0, C_k % 64 == 0.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) core_step_bf16_resident_kernel(const StepArgs args) {
+  (void)args;
+  const StepArgs& a = kernarg<StepArgs>();
+  using MF = Mfma<bf16_tag>;
+  constexpr int WR = 4;            // row blocks per wave
+  constexpr int TCB = 4;           // column blocks per tile
+  constexpr int TC = 16 * TCB;     // 64 columns
+  constexpr int KS = 8;            // contraction steps held (K_in <= 256)
+  constexpr int NT = 256;
+  constexpr int IN_ELEMS = TCB * KS * 64 * 8;      // one input stage (bf16 elements)
+  constexpr int OUT_ELEMS = TC * 256;              // one output stage
+  constexpr int NSV = (TC * 256 / 8) / NT;         // 16-byte input loads per thread (max)
+  __shared__ __attribute__((aligned(16))) uint16_t lin[2 * IN_ELEMS];
+  __shared__ __attribute__((aligned(16))) uint16_t lout[2 * OUT_ELEMS];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int Ks = a.Ksteps;
+  const int vpc = a.K_in / 8;                      // 16-byte vectors per input column
+  const int spc = Ks * 4;                          // 16-byte slots per column in LDS (K_in padded)
+  const int nslot = TC * spc;                      // per tile
+  const uint16_t* __restrict__ Mf = reinterpret_cast<const uint16_t*>(a.M);
+  const uint16_t* __restrict__ in = reinterpret_cast<const uint16_t*>(a.in);
+  uint16_t* __restrict__ out = reinterpret_cast<uint16_t*>(a.out);
+
+  // resident core fragments
+  v8bf mf[WR][KS];
+#pragma unroll
+  for (int i = 0; i < WR; ++i) {
+    const int rbg = wave * WR + i;
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      mf[i][s] = MF::zero_frag();
+      if (s < Ks && rbg < a.nRB) mf[i][s] = MF::load_frag(Mf + (((int64_t)rbg * Ks + s) * 64 + lane) * 8);
+    }
+  }
+
+  const int64_t ntiles = a.ncols / TC;
+  const int64_t my = (ntiles > (int64_t)blockIdx.x) ? (ntiles - 1 - (int64_t)blockIdx.x) / gridDim.x + 1 : 0;
+  if (my == 0) return;
+
+  v4u st[NSV];
+  auto gload = [&](int64_t t) {
+    const int64_t tile = blockIdx.x + t * (int64_t)gridDim.x;
+    const int64_t col0 = tile * TC;
+    const v4u* src = reinterpret_cast<const v4u*>(in + col0 * a.K_in);   // packed: tile is contiguous
+#pragma unroll
+    for (int u = 0; u < NSV; ++u) {
+      // slot (c, kv): kv < vpc holds data, kv in [vpc, spc) is the zero padding
+      // of the last contraction step (never left stale in LDS)
+      const int idx = tid + u * NT;
+      const int c = idx / spc;
+      const int kv = idx - c * spc;
+      st[u] = (idx < nslot && kv < vpc) ? src[c * vpc + kv] : v4u{0u, 0u, 0u, 0u};
+    }
+  };
+  auto lstore = [&](int stage) {
+    uint16_t* A = lin + stage * IN_ELEMS;
+#pragma unroll
+    for (int u = 0; u < NSV; ++u) {
+      const int idx = tid + u * NT;
+      if (idx < nslot) {
+        const int c = idx / spc;
+        const int kap = (idx - c * spc) * 8;
+        const int s = kap >> 5, g = (kap & 31) >> 3;
+        *reinterpret_cast<v4u*>(&A[(((c >> 4) * KS + s) * 64 + (c & 15) + 16 * g) * 8]) = st[u];
+      }
+    }
+  };
+
+  gload(0);
+  lstore(0);
+  __syncthreads();
+  if (my > 1) gload(1);
+  const int rows_out = a.R_out;
+  const int r = a.r_out;
+  for (int64_t t = 0; t < my; ++t) {
+    const uint16_t* A = lin + (t & 1) * IN_ELEMS;
+    v4f acc[WR][TCB];
+#pragma unroll
+    for (int i = 0; i < WR; ++i)
+#pragma unroll
+      for (int j = 0; j < TCB; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      if (s < Ks) {
+        v8bf af[TCB];
+#pragma unroll
+        for (int j = 0; j < TCB; ++j) af[j] = MF::load_frag(&A[((j * KS + s) * 64 + lane) * 8]);
+#pragma unroll
+        for (int i = 0; i < WR; ++i)
+#pragma unroll
+          for (int j = 0; j < TCB; ++j) acc[i][j] = MF::mma(mf[i][s], af[j], acc[i][j]);
+      }
+    }
+    // accumulators -> BF16 in the output stage: element (row = a' + r i, col q)
+    // sits at i * (r TC) + q r + a'; a lane holds 4 consecutive rows of one column
+    uint16_t* O = lout + (t & 1) * OUT_ELEMS;
+#pragma unroll
+    for (int i = 0; i < WR; ++i) {
+      const int row0 = (wave * WR + i) * 16 + 4 * (lane >> 4);
+#pragma unroll
+      for (int j = 0; j < TCB; ++j) {
+        const int q = j * 16 + (lane & 15);
+        if ((r & 3) == 0 && row0 + 3 < rows_out) {
+          // the 4 rows share i_k and are consecutive a_k: one 8-byte write
+          const int ir = row0 / r, ar = row0 - ir * r;
+          const uint32_t lo = (uint32_t)MF::from_acc(acc[i][j][0]) | ((uint32_t)MF::from_acc(acc[i][j][1]) << 16);
+          const uint32_t hi = (uint32_t)MF::from_acc(acc[i][j][2]) | ((uint32_t)MF::from_acc(acc[i][j][3]) << 16);
+          typedef uint32_t v2u __attribute__((ext_vector_type(2)));
+          *reinterpret_cast<v2u*>(&O[ir * (r * TC) + q * r + ar]) = v2u{lo, hi};
+        } else {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int row = row0 + v;
+            if (row < rows_out) {
+              const int ir = row / r, ar = row - ir * r;
+              O[ir * (r * TC) + q * r + ar] = MF::from_acc(acc[i][j][v]);
+            }
+          }
+        }
+      }
+    }
+    if (t + 1 < my) lstore((int)((t + 1) & 1));
+    __syncthreads();
+    // copy the output stage out: for each i_k a contiguous run of r * TC values
+    {
+      const int64_t tile = blockIdx.x + t * (int64_t)gridDim.x;
+      const int64_t col0 = tile * TC;
+      const int64_t rhs = col0 / a.C;
+      const int64_t q0 = col0 - rhs * a.C;
+      uint16_t* dst = out + rhs * a.out_stride + (int64_t)r * q0;
+      const int m = rows_out / r;
+      const int per_i = r * TC / 8;                 // 16-byte vectors per i_k run
+      for (int idx = tid; idx < m * per_i; idx += NT) {
+        const int ir = idx / per_i;
+        const int v = idx - ir * per_i;
+        reinterpret_cast<v4u*>(dst + (int64_t)r * a.C * ir)[v] =
+            reinterpret_cast<const v4u*>(O + ir * (r * TC))[v];
+      }
+    }
+    if (t + 2 < my) gload(t + 2);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Same computation with the input tiles moved by direct global-to-LDS loads
+// (global_load_lds_dwordx4): one instruction fills one 1 KB fragment, lane l
+// fetching the 16 bytes of fragment slot l (column l mod 16, contraction
+// indices 8 (l div 16) .. +7 of the step).  Three input stages let two tiles
+// be in flight while a third is consumed, without staging registers.  Each
+// wave waits for its own loads of a tile (vector-memory counter) before the
+// barrier that publishes the tile to the other waves.  Slots past K_in (zero
+// core values) read the last real indices of the same column, so they hold
+// finite data of that column only.
+// ---------------------------------------------------------------------------
+typedef __attribute__((address_space(3))) void lds_void;
+
+// s_waitcnt with only the vector-memory count limited to N (gfx9 encoding).
+template <int N>
+__device__ inline void wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | (0x7 << 4) | (0xF << 8) | (((N >> 4) & 3) << 14));
+}
+
+// s_waitcnt needs an immediate: dispatch a wave-uniform count to one.
+template <int I>
+__device__ inline void wait_vmcnt_dispatch(int n) {
+  if constexpr (I == 0) {
+    wait_vmcnt<0>();
+  } else {
+    if (n >= I) wait_vmcnt<I>();
+    else wait_vmcnt_dispatch<I - 1>(n);
+  }
+}
+
+__global__ void __launch_bounds__(256) core_step_bf16_dma_kernel(const StepArgs args) {
+  (void)args;
+  const StepArgs& a = kernarg<StepArgs>();
+  using MF = Mfma<bf16_tag>;
+  constexpr int WR = 4, TCB = 4, TC = 64, KS = 8, NT = 256;
+  constexpr int IN_ELEMS = TCB * KS * 64 * 8;      // 32 KB per stage
+  constexpr int OUT_ELEMS = TC * 256;              // 32 KB
+  constexpr int PER_WAVE = TCB * KS / 4;           // fragment loads per wave per tile (max)
+  __shared__ __attribute__((aligned(1024))) uint16_t lin0[IN_ELEMS];
+  __shared__ __attribute__((aligned(1024))) uint16_t lin1[IN_ELEMS];
+  __shared__ __attribute__((aligned(1024))) uint16_t lin2[IN_ELEMS];
+  __shared__ __attribute__((aligned(16))) uint16_t lout[OUT_ELEMS];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int Ks = a.Ksteps;                         // host guarantees Ks == KS
+  const uint16_t* __restrict__ Mf = reinterpret_cast<const uint16_t*>(a.M);
+  const uint16_t* __restrict__ in = reinterpret_cast<const uint16_t*>(a.in);
+  uint16_t* __restrict__ out = reinterpret_cast<uint16_t*>(a.out);
+
+  v8bf mf[WR][KS];
+#pragma unroll
+  for (int i = 0; i < WR; ++i) {
+    const int rbg = wave * WR + i;
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      mf[i][s] = MF::zero_frag();
+      if (rbg < a.nRB) mf[i][s] = MF::load_frag(Mf + (((int64_t)rbg * Ks + s) * 64 + lane) * 8);
+    }
+  }
+  wait_vmcnt<0>();
+  const int64_t ntiles = a.ncols / TC;
+  const int64_t my = (ntiles > (int64_t)blockIdx.x) ? (ntiles - 1 - (int64_t)blockIdx.x) / gridDim.x + 1 : 0;
+  if (my == 0) return;
+
+  const int kmax = a.K_in - 8;
+  // every wave issues exactly PER_WAVE fragment loads per tile
+  auto dma = [&](int64_t t, uint16_t* stage) {
+    const int64_t col0 = (blockIdx.x + t * (int64_t)gridDim.x) * TC;
+    const uint16_t* base = in + col0 * a.K_in;
+#pragma unroll
+    for (int u = 0; u < PER_WAVE; ++u) {
+      const int f = wave + 4 * u;
+      const int cb = f / KS, s = f % KS;
+      const int col = cb * 16 + (lane & 15);
+      const int kap = min(s * 32 + 8 * (lane >> 4), kmax);
+      __builtin_amdgcn_global_load_lds((const void*)(base + (int64_t)col * a.K_in + kap),
+                                       (lds_void*)(stage + (cb * KS + s) * 64 * 8), 16, 0, 0);
+    }
+  };
+  auto stage_of = [&](int64_t t) -> uint16_t* {
+    const int m3 = (int)(t % 3);
+    return m3 == 0 ? lin0 : (m3 == 1 ? lin1 : lin2);
+  };
+
+  // Issue order: dma(0..2), then per tile t: [wait for dma(t), barrier,
+  // compute, stage output, barrier, stores(t), dma(t+3)].  Vector-memory
+  // operations complete in issue order, so dma(t) has landed once at most the
+  // operations issued after it are outstanding: dma(t+1), dma(t+2) (those that
+  // exist) and the stores of tiles t-2 and t-1.  Every thread issues the same
+  // number of stores per tile (R_out / 32; the host requires R_out % 32 == 0).
+  const int rows_out = a.R_out;
+  const int r = a.r_out;
+  const int spt = rows_out / 32;
+  dma(0, lin0);
+  if (my > 1) dma(1, lin1);
+  if (my > 2) dma(2, lin2);
+  for (int64_t t = 0; t < my; ++t) {
+    const int nd = (int)(min(my - 1, t + 2) - t);
+    const int ns = (int)min(t, (int64_t)2);
+    wait_vmcnt_dispatch<2 * PER_WAVE + 16>(nd * PER_WAVE + ns * spt);
+    __syncthreads();
+    const uint16_t* A = stage_of(t);
+    v4f acc[WR][TCB];
+#pragma unroll
+    for (int i = 0; i < WR; ++i)
+#pragma unroll
+      for (int j = 0; j < TCB; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      v8bf af[TCB];
+#pragma unroll
+      for (int j = 0; j < TCB; ++j) af[j] = MF::load_frag(&A[((j * KS + s) * 64 + lane) * 8]);
+#pragma unroll
+      for (int i = 0; i < WR; ++i)
+#pragma unroll
+        for (int j = 0; j < TCB; ++j) acc[i][j] = MF::mma(mf[i][s], af[j], acc[i][j]);
+    }
+#pragma unroll
+    for (int i = 0; i < WR; ++i) {
+      const int row0 = (wave * WR + i) * 16 + 4 * (lane >> 4);
+#pragma unroll
+      for (int j = 0; j < TCB; ++j) {
+        const int q = j * 16 + (lane & 15);
+        if ((r & 3) == 0 && row0 + 3 < rows_out) {
+          const int ir = row0 / r, ar = row0 - ir * r;
+          const uint32_t lo = (uint32_t)MF::from_acc(acc[i][j][0]) | ((uint32_t)MF::from_acc(acc[i][j][1]) << 16);
+          const uint32_t hi = (uint32_t)MF::from_acc(acc[i][j][2]) | ((uint32_t)MF::from_acc(acc[i][j][3]) << 16);
+          typedef uint32_t v2u __attribute__((ext_vector_type(2)));
+          *reinterpret_cast<v2u*>(&lout[ir * (r * TC) + q * r + ar]) = v2u{lo, hi};
+        } else {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int row = row0 + v;
+            if (row < rows_out) {
+              const int ir = row / r, ar = row - ir * r;
+              lout[ir * (r * TC) + q * r + ar] = MF::from_acc(acc[i][j][v]);
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+    {
+      const int64_t col0 = (blockIdx.x + t * (int64_t)gridDim.x) * TC;
+      const int64_t rhs = col0 / a.C;
+      const int64_t q0 = col0 - rhs * a.C;
+      uint16_t* dst = out + rhs * a.out_stride + (int64_t)r * q0;
+      const int m = rows_out / r;
+      const int per_i = r * TC / 8;
+      for (int idx = tid; idx < m * per_i; idx += NT) {
+        const int ir = idx / per_i;
+        const int v = idx - ir * per_i;
+        reinterpret_cast<v4u*>(dst + (int64_t)r * a.C * ir)[v] =
+            reinterpret_cast<const v4u*>(lout + ir * (r * TC))[v];
+      }
+    }
+    // stage t % 3 was last read by this tile's compute, finished by every
+    // wave before the barrier above
+    if (t + 3 < my) dma(t + 3, stage_of(t + 3));
+    // the stores above read lout; the next tile writes it after the barrier at
+    // the top of the loop, which every thread reaches only after its stores
+  }
+}
+
+// ---------------------------------------------------------------------------
 // column norms: ||R_c||_2 for every column, two deterministic passes (the
 // summation order depends only on the column length, never on the batch).
 // ---------------------------------------------------------------------------

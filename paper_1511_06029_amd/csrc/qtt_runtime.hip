@@ -223,6 +223,39 @@ static int valu_padded_rows(int R_out) {
   return pad;
 }
 
+// BF16 interior kernel with the core resident in registers (shape id 30).
+static const int kBf16Resident = 30;
+static KernelCfg* bf16_resident_cfg() {
+  static KernelCfg k = [] {
+    KernelCfg c;
+    c.dt = 2;
+    c.in_f64 = false;
+    c.vec = true;
+    c.TR = 256;
+    c.TC = 64;
+    c.KC = 256;
+    c.NT = 256;
+    c.id = kBf16Resident;
+    c.fn = reinterpret_cast<const void*>(&core_step_bf16_resident_kernel);
+    c.occ = 0;
+    return c;
+  }();
+  return &k;
+}
+
+// BF16 interior kernel fed by direct global-to-LDS loads (shape id 31).
+static const int kBf16Dma = 31;
+static KernelCfg* bf16_dma_cfg() {
+  static KernelCfg k = [] {
+    KernelCfg c = *bf16_resident_cfg();
+    c.id = kBf16Dma;
+    c.fn = reinterpret_cast<const void*>(&core_step_bf16_dma_kernel);
+    c.occ = 0;
+    return c;
+  }();
+  return &k;
+}
+
 static int num_cus() {
   static int n = [] {
     int dev = 0, cus = 0;
@@ -321,7 +354,7 @@ static int heuristic_shape(int R_out, int K_in, int dt) {
   if (R_out <= 16) return dt == 0 ? 47 : 2;      // last core (r_d = 1)
   if (K_in <= 16) return dt == 0 ? 6 : 26;       // first core (r_0 = 1)
   if (R_out <= 64) return kGenericShape;
-  return dt == 2 ? 5 : 21;                       // interior cores
+  return dt == 2 ? kBf16Dma : 21;                // interior cores (DMA falls back to resident)
 }
 
 // ---------------------------------------------------------------------------
@@ -455,7 +488,16 @@ static qtt_status_t launch_step(const qtt_matrix_s* A, int k, int dt, int64_t nr
   }
   if (dt == 0 && is_valu_shape(shape))
     return launch_valu(A, k, nrhs, segs, nseg, in_packed, out_packed, alpha, shape, st);
-  KernelCfg* kc = vec ? find_cfg(dt, in_f64, true, shape) : find_cfg(dt, in_f64, false, kGenericShape);
+  // the resident BF16 kernel serves interior cores that fit it
+  const bool resident_ok = dt == 2 && !first && !last && c.R_out <= 256 && c.K_in <= 256 &&
+                           c.K_in % 8 == 0 && c.C % 64 == 0 && vec &&
+                           reinterpret_cast<uintptr_t>(out_packed) % 16 == 0;
+  const bool dma_ok = resident_ok && c.Ksteps[2] == 8 && c.R_out % 32 == 0;
+  if (shape == kBf16Dma && !dma_ok) shape = kBf16Resident;
+  if (shape == kBf16Resident && !resident_ok) shape = heuristic_shape(c.R_out, c.K_in, 1);
+  KernelCfg* kc = (shape == kBf16Dma) ? bf16_dma_cfg()
+                  : (shape == kBf16Resident) ? bf16_resident_cfg()
+                  : vec ? find_cfg(dt, in_f64, true, shape) : find_cfg(dt, in_f64, false, kGenericShape);
   if (!kc) return fail(QTT_ERR_DEVICE, "no kernel for dtype %d shape %d", dt, shape);
 
   StepArgs a;
@@ -933,6 +975,10 @@ qtt_status_t qtt_autotune(qtt_matrix_t A, qtt_dtype_t compute, int64_t nrhs, con
     int best_id = -1;
     const bool in_f64 = (k == 0) || dt == 0;
     std::vector<int> ids = shape_ids(dt, in_f64);
+    if (dt == 2 && k > 0 && k < A->d - 1) {
+      ids.push_back(kBf16Resident);
+      ids.push_back(kBf16Dma);
+    }
     if (dt == 0)
       for (auto& vc : valu_registry())
         if (vc.G == 1 || c.K_in % vc.G == 0) ids.push_back(vc.id);
