@@ -128,6 +128,18 @@ qtt_status_t qtt_autotune(qtt_matrix_t A, qtt_dtype_t compute, int64_t nrhs,
                           const double* X, int64_t ldx, double* Y, int64_t ldy,
                           void* ws, size_t ws_bytes, void* stream);
 
+/* Pin the kernel configuration of one core for one compute dtype: shape is a
+ * configuration id (as chosen by qtt_autotune), -1 restores the default
+ * choice.  A configuration that cannot serve the core (wrong dtype, shape
+ * restrictions, misaligned operands) falls back to the default at launch.
+ * Returns QTT_ERR_INVALID_ARG for an unknown id or core index.  Used by the
+ * tests to run every kernel variant, and to replay a tuning result. */
+qtt_status_t qtt_set_shape(qtt_matrix_t A, qtt_dtype_t compute, int32_t core, int32_t shape);
+
+/* Ids of the configurations available for a dtype (up to cap written to
+ * ids); *count receives the total. */
+qtt_status_t qtt_list_shapes(qtt_dtype_t compute, int32_t* ids, int32_t cap, int32_t* count);
+
 typedef struct {
   int32_t iters;         /* passes of x += Ainv r done for this column */
   double rel_residual;   /* ||F_c - A x_c||_2 / ||F_c||_2 after the last pass */

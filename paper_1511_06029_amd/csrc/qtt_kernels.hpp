@@ -1259,6 +1259,148 @@ __global__ void __launch_bounds__(256) core_step_bf16_dma_kernel(const StepArgs 
 }
 
 // ---------------------------------------------------------------------------
+// FP64 interior core step, both operands moved by direct global-to-LDS loads.
+//
+// Tile: 256 rows x 64 columns, 4 waves of 64 x 64 (16 accumulator blocks).
+// The contraction runs in chunks of 16 indices (4 steps).  A chunk's core
+// fragments (16 row blocks x 4 steps, contiguous 2 KB per row block in the
+// fragment-ordered core) are copied with 16-byte loads, 1 KB per instruction;
+// its input fragments with 8-byte loads, one 512-byte fragment per
+// instruction (lane l: column l mod 16, contraction index 4 s + l div 16).
+// Three LDS stages keep two chunks in flight.  Waits count only the copies
+// issued after the awaited chunk: the output stores issued in between make
+// such a wait stricter, never weaker.  Input indices past K_in and columns past
+// the last tile column read finite data of the same operand (their core
+// values, or their outputs, are never used).
+// Requirements checked by the host: interior core (packed input and output),
+// R_out <= 256 with R_out % 64 == 0, C % 64 == 0.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) core_step_f64_dma_kernel(const StepArgs args) {
+  (void)args;
+  const StepArgs& a = kernarg<StepArgs>();
+  using MF = Mfma<double>;
+  constexpr int WR = 4, WC = 4, TR = 256, TC = 64, SPC = 4, KC = 16;
+  constexpr int A_EL = (TC / 16) * SPC * 64;       // 1024 doubles = 8 KB
+  constexpr int B_EL = (TR / 16) * SPC * 64;       // 4096 doubles = 32 KB
+  constexpr int DMA_B = (TR / 16) * SPC * 64 * 8 / 1024 / 4;   // 1 KB copies per wave (8)
+  constexpr int DMA_A = (TC / 16) * SPC * 2 / 4;                // 256 B gathers per wave (8)
+  constexpr int PER = DMA_A + DMA_B;                            // copies per wave per chunk
+  __shared__ __attribute__((aligned(1024))) double sA0[A_EL];
+  __shared__ __attribute__((aligned(1024))) double sA1[A_EL];
+  __shared__ __attribute__((aligned(1024))) double sA2[A_EL];
+  __shared__ __attribute__((aligned(1024))) double sB0[B_EL];
+  __shared__ __attribute__((aligned(1024))) double sB1[B_EL];
+  __shared__ __attribute__((aligned(1024))) double sB2[B_EL];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int Ks = a.Ksteps;
+  const int nch = (Ks + SPC - 1) / SPC;
+  const double* __restrict__ Mf = reinterpret_cast<const double*>(a.M);
+  const double* __restrict__ in = reinterpret_cast<const double*>(a.in);
+  double* __restrict__ out = reinterpret_cast<double*>(a.out);
+  const int64_t ntiles = a.ncols / TC;
+  const int64_t my = (ntiles > (int64_t)blockIdx.x) ? (ntiles - 1 - (int64_t)blockIdx.x) / gridDim.x + 1 : 0;
+  const int64_t total = my * nch;
+  if (total == 0) return;
+
+  auto stageA = [&](int64_t it) -> double* { const int m = (int)(it % 3); return m == 0 ? sA0 : (m == 1 ? sA1 : sA2); };
+  auto stageB = [&](int64_t it) -> double* { const int m = (int)(it % 3); return m == 0 ? sB0 : (m == 1 ? sB1 : sB2); };
+  auto dma = [&](int64_t it) {
+    const int64_t col0 = (blockIdx.x + (it / nch) * (int64_t)gridDim.x) * TC;
+    const int ch = (int)(it % nch);
+    double* A = stageA(it);
+    double* B = stageB(it);
+    // core: row block rb, steps s0..s0+3 are 2 KB contiguous -> two 1 KB copies
+    const int s0 = min(ch * SPC, Ks - SPC >= 0 ? Ks - SPC : 0);
+#pragma unroll
+    for (int u = 0; u < DMA_B; ++u) {
+      const int f = wave * DMA_B + u;                 // 0..31
+      const int rb = f >> 1, half = f & 1;
+      const double* src = Mf + (((int64_t)rb * Ks + s0) * 64) + half * 128 + lane * 2;
+      __builtin_amdgcn_global_load_lds((const void*)src, (lds_void*)(B + rb * SPC * 64 + half * 128), 16, 0, 0);
+    }
+    // input: fragment (cb, s) holds, for MFMA lane d, column col0 + 16 cb + d % 16
+    // and index 4 s + d / 16.  A 4-byte copy fills half a fragment: lane l
+    // fetches half (l % 2) of fragment double 32 h + l / 2.
+#pragma unroll
+    for (int u = 0; u < DMA_A; ++u) {
+      const int f = wave * DMA_A + u;                 // 0..31
+      const int frag_id = f >> 1, h = f & 1;
+      const int cb = frag_id / SPC, s = frag_id % SPC;
+      const int d = 32 * h + (lane >> 1);
+      const int64_t col = col0 + cb * 16 + (d & 15);
+      const int kap = min(ch * KC + 4 * s + (d >> 4), a.K_in - 1);
+      const int64_t rhs = col / a.C;
+      const int64_t q = col - rhs * a.C;
+      const char* src = reinterpret_cast<const char*>(in + rhs * a.in_stride + q * a.K_in + kap) + 4 * (lane & 1);
+      __builtin_amdgcn_global_load_lds((const void*)src, (lds_void*)(A + (cb * SPC + s) * 64 + 32 * h), 4, 0, 0);
+    }
+  };
+
+  dma(0);
+  if (total > 1) dma(1);
+  if (total > 2) dma(2);
+  v4d acc[WR][WC];
+  for (int64_t it = 0; it < total; ++it) {
+    const int ch = (int)(it % nch);
+    const int nd = (int)(min(total - 1, it + 2) - it);   // copies issued after chunk it
+    wait_vmcnt_dispatch<2 * PER>(nd * PER);
+    __syncthreads();
+    if (ch == 0) {
+#pragma unroll
+      for (int i = 0; i < WR; ++i)
+#pragma unroll
+        for (int j = 0; j < WC; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+    }
+    const double* A = stageA(it);
+    const double* B = stageB(it);
+    // the last chunk may start before ch * SPC when Ks is not a multiple of SPC
+    const int s_first = ch * SPC;
+    const int s0 = min(s_first, Ks - SPC >= 0 ? Ks - SPC : 0);
+    const int sk = s_first - s0;                     // steps of this chunk already done
+    const int nsteps = min(SPC, Ks - s_first);
+#pragma unroll
+    for (int s = 0; s < SPC; ++s) {
+      if (s < nsteps) {
+        const int sb = s + sk;
+        double bf[WR], af[WC];
+#pragma unroll
+        for (int i = 0; i < WR; ++i) bf[i] = B[((wave * WR + i) * SPC + sb) * 64 + lane];
+#pragma unroll
+        for (int j = 0; j < WC; ++j) af[j] = A[(j * SPC + s) * 64 + lane];
+#pragma unroll
+        for (int i = 0; i < WR; ++i)
+#pragma unroll
+          for (int j = 0; j < WC; ++j) acc[i][j] = MF::mma(af[j], bf[i], acc[i][j]);
+      }
+    }
+    if (ch == nch - 1 && wave * 64 < a.R_out) {
+      const int64_t col0 = (blockIdx.x + (it / nch) * (int64_t)gridDim.x) * TC;
+      const int64_t rhs = col0 / a.C;
+      const int64_t q0 = col0 - rhs * a.C;
+      double* dst = out + rhs * a.out_stride;
+#pragma unroll
+      for (int i = 0; i < WR; ++i) {
+        const int row = (wave * WR + i) * 16 + (lane & 15);
+        const int ir = row / a.r_out, ar = row - ir * a.r_out;
+        const int64_t rbase = ar + (int64_t)a.r_out * (q0 + a.C * ir);
+#pragma unroll
+        for (int j = 0; j < WC; ++j)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int cit = j * 16 + MF::acc_line(lane, v);
+            dst[rbase + (int64_t)a.r_out * cit] = acc[i][j][v];
+          }
+      }
+    }
+    __syncthreads();                                 // stage it % 3 is free again
+    if (it + 3 < total) dma(it + 3);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // column norms: ||R_c||_2 for every column, two deterministic passes (the
 // summation order depends only on the column length, never on the batch).
 // ---------------------------------------------------------------------------

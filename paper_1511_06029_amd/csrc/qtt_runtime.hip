@@ -256,6 +256,26 @@ static KernelCfg* bf16_dma_cfg() {
   return &k;
 }
 
+// FP64 interior kernel fed by direct global-to-LDS loads (shape id 32).
+static const int kF64Dma = 32;
+static KernelCfg* f64_dma_cfg() {
+  static KernelCfg k = [] {
+    KernelCfg c;
+    c.dt = 0;
+    c.in_f64 = true;
+    c.vec = true;
+    c.TR = 256;
+    c.TC = 64;
+    c.KC = 16;
+    c.NT = 256;
+    c.id = kF64Dma;
+    c.fn = reinterpret_cast<const void*>(&core_step_f64_dma_kernel);
+    c.occ = 0;
+    return c;
+  }();
+  return &k;
+}
+
 static int num_cus() {
   static int n = [] {
     int dev = 0, cus = 0;
@@ -494,8 +514,12 @@ static qtt_status_t launch_step(const qtt_matrix_s* A, int k, int dt, int64_t nr
                            reinterpret_cast<uintptr_t>(out_packed) % 16 == 0;
   const bool dma_ok = resident_ok && c.Ksteps[2] == 8 && c.R_out % 32 == 0;
   if (shape == kBf16Dma && !dma_ok) shape = kBf16Resident;
+  const bool f64dma_ok = dt == 0 && !first && !last && c.R_out <= 256 && c.R_out % 64 == 0 &&
+                         c.C % 64 == 0 && c.Ksteps[0] >= 4;
+  if (shape == kF64Dma && !f64dma_ok) shape = 21;
   if (shape == kBf16Resident && !resident_ok) shape = heuristic_shape(c.R_out, c.K_in, 1);
-  KernelCfg* kc = (shape == kBf16Dma) ? bf16_dma_cfg()
+  KernelCfg* kc = (shape == kF64Dma) ? f64_dma_cfg()
+                  : (shape == kBf16Dma) ? bf16_dma_cfg()
                   : (shape == kBf16Resident) ? bf16_resident_cfg()
                   : vec ? find_cfg(dt, in_f64, true, shape) : find_cfg(dt, in_f64, false, kGenericShape);
   if (!kc) return fail(QTT_ERR_DEVICE, "no kernel for dtype %d shape %d", dt, shape);
@@ -979,6 +1003,7 @@ qtt_status_t qtt_autotune(qtt_matrix_t A, qtt_dtype_t compute, int64_t nrhs, con
       ids.push_back(kBf16Resident);
       ids.push_back(kBf16Dma);
     }
+    if (dt == 0 && k > 0 && k < A->d - 1) ids.push_back(kF64Dma);
     if (dt == 0)
       for (auto& vc : valu_registry())
         if (vc.G == 1 || c.K_in % vc.G == 0) ids.push_back(vc.id);
@@ -1012,6 +1037,38 @@ qtt_status_t qtt_autotune(qtt_matrix_t A, qtt_dtype_t compute, int64_t nrhs, con
   s = qtt_apply(A, compute, nrhs, X, ldx, Y, ldy, ws, ws_bytes, stream);
   if (s != QTT_OK) return s;
   HIP_TRY(hipStreamSynchronize(st));
+  return QTT_OK;
+}
+
+qtt_status_t qtt_list_shapes(qtt_dtype_t compute, int32_t* ids, int32_t cap, int32_t* count) {
+  const int dt = dt_index(compute);
+  if (dt < 0 || !count || (cap > 0 && !ids)) return fail(QTT_ERR_INVALID_ARG, "bad arguments");
+  std::vector<int> v = shape_ids(dt, dt == 0);
+  if (dt == 2) { v.push_back(kBf16Resident); v.push_back(kBf16Dma); }
+  if (dt == 0) {
+    v.push_back(kF64Dma);
+    for (auto& vc : valu_registry()) v.push_back(vc.id);
+  }
+  *count = (int32_t)v.size();
+  for (int i = 0; i < (int)v.size() && i < cap; ++i) ids[i] = v[i];
+  return QTT_OK;
+}
+
+qtt_status_t qtt_set_shape(qtt_matrix_t A, qtt_dtype_t compute, int32_t core, int32_t shape) {
+  if (!valid_handle(A)) return fail(QTT_ERR_INVALID_ARG, "null handle");
+  int dt;
+  qtt_status_t s = check_dtype(A, compute, &dt);
+  if (s != QTT_OK) return s;
+  if (core < 0 || core >= A->d) return fail(QTT_ERR_INVALID_ARG, "core %d out of range", core);
+  if (shape != -1) {
+    int32_t ids[128], n = 0;
+    qtt_list_shapes(compute, ids, 128, &n);
+    bool found = false;
+    for (int i = 0; i < n && i < 128; ++i) found = found || ids[i] == shape;
+    if (!found) return fail(QTT_ERR_INVALID_ARG, "shape %d is not a configuration for dtype %d", shape, (int)compute);
+  }
+  A->core[core].tuned[dt] = shape;
+  drop_graphs(A);
   return QTT_OK;
 }
 

@@ -57,6 +57,8 @@ def _load():
         "qtt_autotune": [P, I32, I64, P, I64, P, I64, P, SZ, P],
         "qtt_solve_workspace_bytes": [P, P, I32, I64, ctypes.POINTER(SZ)],
         "qtt_solve": [P, P, I32, I64, P, I64, P, I64, D, I32, P, SZ, P, ctypes.POINTER(_SolveCol)],
+        "qtt_set_shape": [P, I32, I32, I32],
+        "qtt_list_shapes": [I32, ctypes.POINTER(I32), I32, ctypes.POINTER(I32)],
         "qtt_timing_enable": [I32],
         "qtt_timing_reset": [],
         "qtt_timing_read": [I32, I32, PI64, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(D)],
@@ -76,7 +78,8 @@ _lib = _load()
 # Names the C ABI exports (include/qtt.h); the tests check each is present.
 EXPORTED = ["qtt_matrix_load", "qtt_matrix_free", "qtt_matrix_info", "qtt_workspace_bytes",
             "qtt_apply", "qtt_apply_batched", "qtt_autotune", "qtt_solve_workspace_bytes",
-            "qtt_solve", "qtt_status_string", "qtt_last_error", "qtt_timing_enable",
+            "qtt_solve", "qtt_status_string", "qtt_last_error", "qtt_set_shape", "qtt_list_shapes",
+            "qtt_timing_enable",
             "qtt_timing_reset", "qtt_timing_read"]
 
 
@@ -267,6 +270,17 @@ def qtt_solve(A, Ainv, inv_compute, F, Sigma=None, rtol=1e-8, max_iter=50, ws=No
     else:
         _check(st, allow=(QTT_ERR_NOT_CONVERGED, QTT_ERR_NONFINITE))
     return Sigma, [(c.iters, c.rel_residual) for c in info], st
+
+
+def qtt_set_shape(A, compute, core, shape):
+    _check(_lib.qtt_set_shape(A.handle, _dtype(compute), int(core), int(shape)))
+
+
+def qtt_list_shapes(compute):
+    ids = (ctypes.c_int32 * 128)()
+    n = ctypes.c_int32()
+    _check(_lib.qtt_list_shapes(_dtype(compute), ids, 128, ctypes.byref(n)))
+    return [ids[i] for i in range(min(n.value, 128))]
 
 
 def qtt_timing_enable(on=True):

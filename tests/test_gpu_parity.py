@@ -266,3 +266,29 @@ def test_error_paths(Q):
     assert st == 5                            # not a contraction: not converged
     A.free()
     Ai.free()
+
+
+@pytest.mark.parametrize("dtype", ["fp64", "fp32", "bf16"])
+def test_every_kernel_configuration(Q, dtype):
+    """Pin each kernel configuration on every core in turn (a configuration
+    that cannot serve a core falls back to the default) and compare with the
+    oracle: covers the single-operand, pipelined, streamed, register-resident,
+    direct-to-LDS and vector-ALU variants."""
+    cases = [([1, 24, 32, 32, 24, 1], 3), ([1, 16, 32, 16, 1], 2), ([1, 9, 13, 1], 2)]
+    for ranks, K in cases:
+        L = len(ranks) - 1
+        cores = I.gaussian_qtt(ranks, [8] * L, seed=17 + L)
+        X = I.rhs(8 ** L, K, seed=18 + L)
+        ref = O.qtt_apply_alg2(cores, X)
+        A = Q.qtt_matrix_load(cores, dtypes=(dtype,))
+        Xd = Q.to_block(X)
+        for shape in Q.qtt_list_shapes(dtype):
+            for k in range(L):
+                Q.qtt_set_shape(A, dtype, k, shape)
+            Y = Q.qtt_apply(A, dtype, Xd)
+            torch.cuda.synchronize()
+            err = colrel(Y.cpu().numpy(), ref)
+            assert err <= TOL[dtype], (ranks, shape, err)
+            if dtype == "fp64":
+                assert elementwise_ok(Y.cpu().numpy(), ref, 1e-12), (ranks, shape)
+        A.free()
