@@ -133,3 +133,23 @@ def test_server_budget_serialises_batches(Q):
     spans = sorted((a, d) for _, _, _, a, d in srv.log)
     for (a0, d0), (a1, d1) in zip(spans, spans[1:]):
         assert a1 >= d0 - 1e-6
+
+
+def test_autotune_keeps_parity(Q):
+    """The autotuner times every configuration per core and keeps the fastest;
+    the tuned sweep still matches the oracle, and its choice survives (the
+    next apply is bitwise the autotuner's own result)."""
+    cores = I.gaussian_qtt([1, 16, 32, 32, 16, 1], [8] * 5, seed=61)
+    X = I.rhs(8 ** 5, 4, seed=62)
+    ref = O.qtt_apply_alg2(cores, X)
+    A = Q.qtt_matrix_load(cores, dtypes=("fp64", "bf16"))
+    Xd = Q.to_block(X)
+    for dt, tol in (("fp64", 1e-12), ("bf16", 3e-2)):
+        Y = Q.empty_block(8 ** 5, 4)
+        ws = Q.workspace(Q.qtt_workspace_bytes(A, dt, 4))
+        Q.qtt_autotune(A, dt, Xd, Y, ws)
+        tuned = Y.cpu().numpy()
+        assert rel(tuned, ref) < tol
+        again = Q.qtt_apply(A, dt, Xd, ws=ws).cpu().numpy()
+        assert np.array_equal(again, tuned)
+    A.free()
