@@ -132,8 +132,13 @@ qtt_status_t qtt_autotune(qtt_matrix_t A, qtt_dtype_t compute, int64_t nrhs,
  * configuration id (as chosen by qtt_autotune), -1 restores the default
  * choice.  A configuration that cannot serve the core (wrong dtype, shape
  * restrictions, misaligned operands) falls back to the default at launch.
- * Returns QTT_ERR_INVALID_ARG for an unknown id or core index.  Used by the
- * tests to run every kernel variant, and to replay a tuning result. */
+ * core = -1 selects a whole-sweep mode instead (FP64 only): shape 50 runs
+ * every FP64 sweep on the vector ALUs with the intermediates stored rank
+ * index slowest (needs every mode size 8, else QTT_ERR_SHAPE; ids 50..56
+ * then pick that sweep's per-core configuration), -1 returns to the
+ * standard sweep.  Returns QTT_ERR_INVALID_ARG for an unknown id or core
+ * index.  Used by the tests to run every kernel variant, and to replay a
+ * tuning result. */
 qtt_status_t qtt_set_shape(qtt_matrix_t A, qtt_dtype_t compute, int32_t core, int32_t shape);
 
 /* Ids of the configurations available for a dtype (up to cap written to

@@ -593,8 +593,8 @@ core_step_pipe_kernel(const StepArgs args) {
 // chunk.
 // ---------------------------------------------------------------------------
 template <class Tc, class Tin, int WAVES_R, int WAVES_C, int WR, int WC, int KC,
-          bool ROWS_ON_LANES, bool VEC>
-__global__ void __launch_bounds__(64 * WAVES_R * WAVES_C)
+          bool ROWS_ON_LANES, bool VEC, int MIN_WAVES = 1>
+__global__ void __launch_bounds__(64 * WAVES_R * WAVES_C, MIN_WAVES)
 core_step_stream_kernel(const StepArgs args) {
   (void)args;
   const StepArgs& a = kernarg<StepArgs>();
@@ -1397,6 +1397,144 @@ __global__ void __launch_bounds__(256) core_step_f64_dma_kernel(const StepArgs a
     }
     __syncthreads();                                 // stage it % 3 is free again
     if (it + 3 < total) dma(it + 3);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 sweep on the vector ALUs in the rank-slowest layout.
+//
+// In this mode every intermediate of the FP64 sweep is stored with the rank
+// index slowest: y_k(a, col) at a * ncol_k + col, col = j_{k+1} + n_{k+1} q
+// in Algorithm 2's column order (for r = 1 this is X or Y itself).  Core k then
+// reads, for lane column q and rank a, its n_k values at a * n_k C_k + n_k q
+// + j (16-byte loads, consecutive lanes 64 bytes apart), and writes output
+// row (a', i) of column q at a' * m_k C_k + q + C_k i (consecutive lanes,
+// consecutive addresses).
+// Core values are wave-uniform scalar operands: the rows of rank a are read
+// in groups of two rows (two 64-byte scalar loads), the next group requested
+// before the current one is used; a scheduling barrier keeps the compiler
+// from sinking those loads to the end of the group.
+// Core order: Mt[(a * Rpad + row) * n + j] = M_k(row, a + r_{k-1} j).
+// ---------------------------------------------------------------------------
+template <int NW, int RW, int CPL>
+__global__ void __launch_bounds__(64 * NW) core_step_valu64t_kernel(const ValuArgs args) {
+  (void)args;
+  const ValuArgs& a = kernarg<ValuArgs>();
+  constexpr int NJ = 8;                       // mode size n_k (host checks)
+  static_assert(RW % 2 == 0, "rows in pairs");
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  constexpr int TCOL = 64 * CPL;
+  const int r_in = a.K_in / NJ;
+  const int64_t nC = (int64_t)NJ * a.C;
+  const int m = a.R_out / a.r_out;
+  const int64_t mC = (int64_t)m * a.C;
+  for (int64_t tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
+    const int rt = (int)(tile % a.n_row_tiles);
+    const int64_t col0 = (tile / a.n_row_tiles) * TCOL;
+    const int row0 = rt * NW * RW + wave * RW;
+    const double* xin[CPL];
+    double* yout[CPL];
+    const double* zin[CPL];
+    bool ok[CPL];
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+      const int64_t g = col0 + lane + 64 * c;
+      ok[c] = g < a.ncols;
+      const int64_t gg = ok[c] ? g : 0;
+      const int64_t rhs = gg / a.C;
+      const int64_t q = gg - rhs * a.C;
+      if (a.in_table) {
+        const Segment& sg = a.seg[find_seg(a, rhs)];
+        xin[c] = sg.x + (rhs - sg.rhs_begin) * sg.ldx + (int64_t)NJ * q;
+      } else {
+        xin[c] = a.in + rhs * a.in_stride + (int64_t)NJ * q;
+      }
+      if (a.out_table) {
+        const Segment& sg = a.seg[find_seg(a, rhs)];
+        yout[c] = sg.y + (rhs - sg.rhs_begin) * sg.ldy + q;
+        zin[c] = sg.z ? sg.z + (rhs - sg.rhs_begin) * sg.ldz + q : nullptr;
+      } else {
+        yout[c] = a.out + rhs * a.out_stride + q;
+        zin[c] = nullptr;
+      }
+    }
+    double acc[RW][CPL];
+#pragma unroll
+    for (int r = 0; r < RW; ++r)
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) acc[r][c] = 0.0;
+    double x[CPL][NJ];
+    auto load_x = [&](int al) {
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) {
+        const double* p = static_cast<const double*>(__builtin_assume_aligned(xin[c] + (int64_t)al * nC, 16));
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) x[c][j] = p[j];
+        if (!ok[c]) {
+#pragma unroll
+          for (int j = 0; j < NJ; ++j) x[c][j] = 0.0;
+        }
+      }
+    };
+    load_x(0);
+    for (int al = 0; al < r_in; ++al) {
+      double xc[CPL][NJ];
+#pragma unroll
+      for (int c = 0; c < CPL; ++c)
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) xc[c][j] = x[c][j];
+      if (al + 1 < r_in) load_x(al + 1);
+      const cdouble* mrow = (const cdouble*)a.M + ((int64_t)al * a.Rpad + row0) * NJ;
+      double mc[2][NJ], mn[2][NJ];
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) mc[h][j] = mrow[h * NJ + j];
+#pragma unroll
+      for (int r = 0; r < RW; r += 2) {
+        // scalar loads return out of order, so a wait covers every load in
+        // flight: wait for the current group first, then request the next
+        __builtin_amdgcn_s_waitcnt(0xC07F);        // lgkmcnt(0) only
+        __builtin_amdgcn_sched_barrier(0);
+        if (r + 2 < RW) {
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) mn[h][j] = mrow[(r + 2 + h) * NJ + j];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int j = 0; j < NJ; ++j)
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) acc[r + h][c] = fma(mc[h][j], xc[c][j], acc[r + h][c]);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int j = 0; j < NJ; ++j) mc[h][j] = mn[h][j];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+      const int row = row0 + r;
+      if (row >= a.R_out) break;
+      const int ap = row % a.r_out, ir = row / a.r_out;
+      const int64_t off = (int64_t)ap * mC + (int64_t)a.C * ir;
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) {
+        if (!ok[c]) continue;
+        if (a.out_table) {
+          double v = a.alpha * acc[r][c];
+          if (zin[c]) v += zin[c][off];
+          yout[c][off] = v;
+        } else {
+          yout[c][off] = acc[r][c];
+        }
+      }
+    }
   }
 }
 

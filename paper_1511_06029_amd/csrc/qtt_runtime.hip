@@ -79,7 +79,8 @@ struct KernelCfg {
   int occ;         // resident blocks per CU, 0 = not yet queried
 };
 
-template <class Tc, class Tin, int WRW, int WCW, int WR, int WC, int KC, bool ROL, bool VEC, int KIND>
+template <class Tc, class Tin, int WRW, int WCW, int WR, int WC, int KC, bool ROL, bool VEC, int KIND,
+          int MINW = 1>
 static KernelCfg make_cfg(int dt, bool in_f64, int id) {
   KernelCfg k;
   k.dt = dt;
@@ -91,7 +92,7 @@ static KernelCfg make_cfg(int dt, bool in_f64, int id) {
   k.NT = 64 * WRW * WCW;
   k.id = id;
   if constexpr (KIND == 2)
-    k.fn = reinterpret_cast<const void*>(&core_step_stream_kernel<Tc, Tin, WRW, WCW, WR, WC, KC, ROL, VEC>);
+    k.fn = reinterpret_cast<const void*>(&core_step_stream_kernel<Tc, Tin, WRW, WCW, WR, WC, KC, ROL, VEC, MINW>);
   else if constexpr (KIND == 1)
     k.fn = reinterpret_cast<const void*>(&core_step_pipe_kernel<Tc, Tin, WRW, WCW, WR, WC, KC, ROL, VEC>);
   else
@@ -132,6 +133,9 @@ static void add_family(std::vector<KernelCfg>& v, int dt, bool in_f64) {
   QTT_SHAPES_V1(QTT_ADD1)
   QTT_SHAPES_V2(QTT_ADD2)
   QTT_SHAPES_V3(QTT_ADD3)
+  // streamed shapes held to 3 resident waves per SIMD (fewer registers each)
+  v.push_back(make_cfg<Tc, Tin, 4, 1, 4, 2, KC1, true, true, 2, 3>(dt, in_f64, 28));
+  v.push_back(make_cfg<Tc, Tin, 4, 1, 2, 4, KC1, true, true, 2, 3>(dt, in_f64, 29));
 #undef QTT_ADD1
 #undef QTT_ADD2
 #undef QTT_ADD3
@@ -205,6 +209,42 @@ static std::vector<ValuCfg>& valu_registry() {
     return v;
   }();
   return reg;
+}
+
+// FP64 sweeps in the rank-slowest layout (vector ALUs, n_k = 8): ids 50..
+#define QTT_VALUT_SHAPES(X)  \
+  X(50, 4, 32, 1)            \
+  X(51, 8, 32, 1)            \
+  X(52, 4, 16, 2)            \
+  X(53, 8, 16, 2)            \
+  X(54, 4, 8, 4)             \
+  X(55, 1, 8, 4)             \
+  X(56, 2, 8, 2)
+static std::vector<ValuCfg>& valut_registry() {
+  static std::vector<ValuCfg> reg = [] {
+    std::vector<ValuCfg> v;
+#define QTT_ADDVT(id, nw, rw, cpl) \
+    v.push_back({id, nw, rw, cpl, 8, reinterpret_cast<const void*>(&core_step_valu64t_kernel<nw, rw, cpl>), 0});
+    QTT_VALUT_SHAPES(QTT_ADDVT)
+#undef QTT_ADDVT
+    return v;
+  }();
+  return reg;
+}
+static ValuCfg* find_valut(int id) {
+  for (auto& k : valut_registry())
+    if (k.id == id) return &k;
+  return nullptr;
+}
+
+// Rows of the rank-slowest copy: every tile height of that registry divides it.
+static int valut_padded_rows(int R_out) {
+  int pad = R_out;
+  for (auto& k : valut_registry()) {
+    const int t = k.NW * k.RW;
+    pad = std::max(pad, (R_out + t - 1) / t * t);
+  }
+  return pad;
 }
 
 static ValuCfg* find_valu(int id) {
@@ -320,7 +360,10 @@ struct CoreDev {
   int tuned[3];       // tuned shape id per dtype, -1 = heuristic
   double* valu;       // FP64 vector-ALU copy Mv, input groups of 8 (when K_in % 8 == 0)
   double* valu1;      // FP64 vector-ALU copy Mv, groups of 1
+  double* valut;      // FP64 copy for the rank-slowest sweep (n_k = 8), Mt
   int Rpad;           // rows of Mv
+  int RpadT;          // rows of Mt
+  int tuned_t;        // shape id in the rank-slowest sweep, -1 = heuristic
 };
 
 struct qtt_matrix_s {
@@ -331,6 +374,8 @@ struct qtt_matrix_s {
   int device = 0;
   std::vector<CoreDev> core;
   int64_t max_inter = 0;  // largest y_k (k < d) per vector, elements
+  bool fp64_t = false;    // FP64 sweeps in the rank-slowest layout on the vector ALUs
+  bool fp64_t_ok = false; // every mode size is 8, so the mode is available
   // captured sweeps: a sweep with the same dtype, vectors, pointers, workspace
   // and alpha replays its graph instead of launching d kernels
   struct Graph {
@@ -434,6 +479,61 @@ static qtt_status_t launch_valu(const qtt_matrix_s* A, int k, int64_t nrhs, cons
   a.ncols = c.C * nrhs;
   a.R_out = c.R_out;
   a.Rpad = c.Rpad;
+  a.K_in = c.K_in;
+  a.r_out = c.r_out;
+  const int trows = vc->NW * vc->RW;
+  a.n_row_tiles = (c.R_out + trows - 1) / trows;
+  const int64_t col_tiles = (a.ncols + 64 * vc->CPL - 1) / (64 * vc->CPL);
+  a.n_tiles = col_tiles * a.n_row_tiles;
+  a.in_table = first ? 1 : 0;
+  a.out_table = last ? 1 : 0;
+  a.nseg = nseg;
+  a.alpha = alpha;
+  for (int s = 0; s < nseg; ++s) a.seg[s] = segs[s];
+  const int nt = 64 * vc->NW;
+  const int64_t resident = (int64_t)occupancy_fn(vc->fn, nt, &vc->occ) * num_cus();
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(a.n_tiles, resident));
+  TimedLaunch tl;
+  const bool timed = timing_on();
+  if (timed) {
+    HIP_TRY(hipEventCreate(&tl.a));
+    HIP_TRY(hipEventCreate(&tl.b));
+    HIP_TRY(hipEventRecord(tl.a, st));
+  }
+  void* args[] = {&a};
+  HIP_TRY(hipLaunchKernel(vc->fn, dim3(grid), dim3(nt), args, 0, st));
+  if (timed) {
+    HIP_TRY(hipEventRecord(tl.b, st));
+    record_timing(tl, A, k, 0, a.ncols, segs, nseg);
+  }
+  return QTT_OK;
+}
+
+static int heuristic_valut(const CoreDev& c) {
+  if (c.R_out <= 8) return 55;
+  if (c.R_out <= 16) return 56;
+  if (c.R_out <= 64) return 54;
+  return 52;
+}
+
+// One core of the rank-slowest FP64 sweep.
+static qtt_status_t launch_valut(const qtt_matrix_s* A, int k, int64_t nrhs, const Segment* segs, int nseg,
+                                 const void* in_packed, void* out_packed, double alpha, hipStream_t st) {
+  const CoreDev& c = A->core[k];
+  const bool first = (k == 0), last = (k == A->d - 1);
+  ValuCfg* vc = find_valut(c.tuned_t >= 0 ? c.tuned_t : heuristic_valut(c));
+  if (!vc) vc = find_valut(heuristic_valut(c));
+  ValuArgs a;
+  memset(&a, 0, sizeof(a));
+  a.M = c.valut;
+  a.in = static_cast<const double*>(in_packed);
+  a.out = static_cast<double*>(out_packed);
+  a.in_stride = c.C * c.K_in;
+  a.out_stride = c.out_len;
+  a.C = c.C;
+  a.ncols = c.C * nrhs;
+  a.R_out = c.R_out;
+  a.Rpad = c.RpadT;
   a.K_in = c.K_in;
   a.r_out = c.r_out;
   const int trows = vc->NW * vc->RW;
@@ -586,14 +686,30 @@ static int64_t wave_capacity(const qtt_matrix_s* A, int dt, size_t ws_bytes) {
   return w;
 }
 
+// Whether X allows the rank-slowest sweep (16-byte aligned columns).
+static bool tsweep_usable_mode_free(const qtt_matrix_s* A, const double* X, int64_t ldx) {
+  (void)A;
+  return reinterpret_cast<uintptr_t>(X) % 16 == 0 && ldx % 2 == 0;
+}
+
+// The rank-slowest FP64 sweep reads X with 16-byte loads per lane column.
+static bool tsweep_usable(const qtt_matrix_s* A, int dt, const Segment* segs, int nseg) {
+  if (dt != 0 || !A->fp64_t || !A->fp64_t_ok) return false;
+  for (int s = 0; s < nseg; ++s)
+    if (reinterpret_cast<uintptr_t>(segs[s].x) % 16 != 0 || segs[s].ldx % 2 != 0) return false;
+  return true;
+}
+
 static qtt_status_t sweep(const qtt_matrix_s* A, int dt, int64_t nrhs, const Segment* segs, int nseg,
                           void* ws, double alpha, hipStream_t st) {
   void* buf[2] = {ws, nullptr};
   if (A->d > 1) buf[1] = static_cast<char*>(ws) + wave_buffer_bytes(A, dt, nrhs);
+  const bool tsw = tsweep_usable(A, dt, segs, nseg);
   for (int k = 0; k < A->d; ++k) {
     const void* in = (k == 0) ? nullptr : buf[(k - 1) & 1];
     void* out = (k == A->d - 1) ? nullptr : buf[k & 1];
-    qtt_status_t s = launch_step(A, k, dt, nrhs, segs, nseg, in, out, alpha, st);
+    qtt_status_t s = tsw ? launch_valut(A, k, nrhs, segs, nseg, in, out, alpha, st)
+                         : launch_step(A, k, dt, nrhs, segs, nseg, in, out, alpha, st);
     if (s != QTT_OK) return s;
   }
   return QTT_OK;
@@ -798,7 +914,10 @@ qtt_status_t qtt_matrix_load(int32_t d, const int64_t* ranks, const int64_t* m, 
     for (int t = 0; t < 3; ++t) { c.frag[t] = nullptr; c.Ksteps[t] = 0; c.tuned[t] = -1; }
     c.valu = nullptr;
     c.valu1 = nullptr;
+    c.valut = nullptr;
     c.Rpad = 0;
+    c.RpadT = 0;
+    c.tuned_t = -1;
     if (k < d - 1) A->max_inter = std::max(A->max_inter, c.out_len);
   }
 
@@ -886,6 +1005,36 @@ qtt_status_t qtt_matrix_load(int32_t d, const int64_t* ranks, const int64_t* m, 
       }
     }
   }
+  // FP64 copy for the rank-slowest sweep: Mt[(a * RpadT + row) * 8 + j] = M_k(row, a + r_{k-1} j)
+  if (dtypes & QTT_FP64) {
+    bool ok = true;
+    for (int k = 0; k < d; ++k) ok = ok && m[k] == 8 && n[k] == 8;
+    A->fp64_t_ok = ok;
+    for (int k = 0; k < d && ok; ++k) {
+      CoreDev& c = A->core[k];
+      const double* G = cores[k];
+      c.RpadT = valut_padded_rows(c.R_out);
+      const size_t nel = (size_t)c.r_in * c.RpadT * 8;
+      std::vector<double> h(nel, 0.0);
+      for (int ap = 0; ap < c.r_in; ++ap)
+        for (int row = 0; row < c.R_out; ++row)
+          for (int jk = 0; jk < 8; ++jk) {
+            const int ak = row % c.r_out, ik = row / c.r_out;
+            h[((size_t)ap * c.RpadT + row) * 8 + jk] = G[(((size_t)ap * c.m + ik) * c.n + jk) * c.r_out + ak];
+          }
+      void* dptr = nullptr;
+      if (hipMalloc(&dptr, std::max<size_t>(nel * 8, 256)) != hipSuccess) {
+        qtt_matrix_free(A);
+        return fail(QTT_ERR_OUT_OF_MEMORY, "hipMalloc for the rank-slowest copy of core %d failed", k);
+      }
+      c.valut = static_cast<double*>(dptr);
+      hipError_t er = hipMemcpy(dptr, h.data(), nel * 8, hipMemcpyHostToDevice);
+      if (er != hipSuccess) {
+        qtt_matrix_free(A);
+        return fail(QTT_ERR_DEVICE, "hipMemcpy of core %d failed: %s", k, hipGetErrorString(er));
+      }
+    }
+  }
   *out = A;
   return QTT_OK;
 }
@@ -899,6 +1048,7 @@ qtt_status_t qtt_matrix_free(qtt_matrix_t A) {
       if (c.frag[t]) (void)hipFree(c.frag[t]);
     if (c.valu) (void)hipFree(c.valu);
     if (c.valu1) (void)hipFree(c.valu1);
+    if (c.valut) (void)hipFree(c.valut);
   }
   delete A;
   return QTT_OK;
@@ -1029,6 +1179,55 @@ qtt_status_t qtt_autotune(qtt_matrix_t A, qtt_dtype_t compute, int64_t nrhs, con
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tuned[std::make_tuple(dt, c.R_out, c.K_in, c.r_out, c.C)] = best_id;
   }
+  // FP64: also tune the rank-slowest vector-ALU sweep, then keep whichever
+  // whole sweep is faster
+  if (dt == 0 && A->fp64_t_ok && tsweep_usable_mode_free(A, X, ldx)) {
+    const bool was_t = A->fp64_t;
+    for (int k = 0; k < A->d; ++k) {
+      CoreDev& c = A->core[k];
+      const void* in = (k == 0) ? nullptr : buf[(k - 1) & 1];
+      void* out = (k == A->d - 1) ? nullptr : buf[k & 1];
+      float best = 1e30f;
+      int best_id = -1;
+      for (auto& vc : valut_registry()) {
+        c.tuned_t = vc.id;
+        for (int rep = 0; rep < 2; ++rep) {
+          HIP_TRY(hipEventRecord(e0, st));
+          for (int it = 0; it < 3; ++it) {
+            s = launch_valut(A, k, w, &sg, 1, in, out, 1.0, st);
+            if (s != QTT_OK) { g_timing = was_timing; return s; }
+          }
+          HIP_TRY(hipEventRecord(e1, st));
+        }
+        HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        if (tune_log())
+          fprintf(stderr, "qtt_autotune dtype 0 core %d (%d x %d, %lld cols) shape %d: %.4f ms\n", k,
+                  c.R_out, c.K_in, (long long)(c.C * w), vc.id, ms / 3);
+        if (ms < best) { best = ms; best_id = vc.id; }
+      }
+      c.tuned_t = best_id;
+    }
+    float ms_mode[2] = {0, 0};
+    for (int mode = 0; mode < 2; ++mode) {
+      A->fp64_t = (mode == 1);
+      for (int rep = 0; rep < 2; ++rep) {
+        HIP_TRY(hipEventRecord(e0, st));
+        for (int it = 0; it < 2; ++it) {
+          s = sweep(A, dt, w, &sg, 1, ws, 1.0, st);
+          if (s != QTT_OK) { g_timing = was_timing; A->fp64_t = was_t; return s; }
+        }
+        HIP_TRY(hipEventRecord(e1, st));
+      }
+      HIP_TRY(hipEventSynchronize(e1));
+      HIP_TRY(hipEventElapsedTime(&ms_mode[mode], e0, e1));
+    }
+    A->fp64_t = ms_mode[1] < ms_mode[0];
+    if (tune_log())
+      fprintf(stderr, "qtt_autotune dtype 0 whole sweep: standard %.4f ms, rank-slowest %.4f ms\n",
+              ms_mode[0] / 2, ms_mode[1] / 2);
+  }
   g_timing = was_timing;
   drop_graphs(A);
   (void)hipEventDestroy(e0);
@@ -1040,6 +1239,8 @@ qtt_status_t qtt_autotune(qtt_matrix_t A, qtt_dtype_t compute, int64_t nrhs, con
   return QTT_OK;
 }
 
+static const int kTSweepMode = 50;
+
 qtt_status_t qtt_list_shapes(qtt_dtype_t compute, int32_t* ids, int32_t cap, int32_t* count) {
   const int dt = dt_index(compute);
   if (dt < 0 || !count || (cap > 0 && !ids)) return fail(QTT_ERR_INVALID_ARG, "bad arguments");
@@ -1048,6 +1249,7 @@ qtt_status_t qtt_list_shapes(qtt_dtype_t compute, int32_t* ids, int32_t cap, int
   if (dt == 0) {
     v.push_back(kF64Dma);
     for (auto& vc : valu_registry()) v.push_back(vc.id);
+    for (auto& vc : valut_registry()) v.push_back(vc.id);
   }
   *count = (int32_t)v.size();
   for (int i = 0; i < (int)v.size() && i < cap; ++i) ids[i] = v[i];
@@ -1059,7 +1261,20 @@ qtt_status_t qtt_set_shape(qtt_matrix_t A, qtt_dtype_t compute, int32_t core, in
   int dt;
   qtt_status_t s = check_dtype(A, compute, &dt);
   if (s != QTT_OK) return s;
+  if (core == -1) {               // whole-sweep mode (FP64): rank-slowest layout on/off
+    if (dt != 0 || (shape != -1 && shape != kTSweepMode)) return fail(QTT_ERR_INVALID_ARG, "core -1 takes shape %d or -1 (FP64)", kTSweepMode);
+    if (shape == kTSweepMode && !A->fp64_t_ok) return fail(QTT_ERR_SHAPE, "the rank-slowest sweep needs every mode size to be 8");
+    A->fp64_t = (shape == kTSweepMode);
+    drop_graphs(A);
+    return QTT_OK;
+  }
   if (core < 0 || core >= A->d) return fail(QTT_ERR_INVALID_ARG, "core %d out of range", core);
+  if (dt == 0 && shape >= 50 && shape < 60) {
+    if (!find_valut(shape)) return fail(QTT_ERR_INVALID_ARG, "unknown shape %d", shape);
+    A->core[core].tuned_t = shape;
+    drop_graphs(A);
+    return QTT_OK;
+  }
   if (shape != -1) {
     int32_t ids[128], n = 0;
     qtt_list_shapes(compute, ids, 128, &n);

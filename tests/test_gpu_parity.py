@@ -292,3 +292,44 @@ def test_every_kernel_configuration(Q, dtype):
             if dtype == "fp64":
                 assert elementwise_ok(Y.cpu().numpy(), ref, 1e-12), (ranks, shape)
         A.free()
+
+
+def test_rank_slowest_fp64_sweep(Q):
+    """FP64 sweep on the vector ALUs with rank-slowest intermediates: every
+    per-core configuration, a misaligned input block (falls back to the
+    standard sweep), and a refined solve in that mode."""
+    for ranks, K in (([1, 24, 32, 32, 24, 1], 3), ([1, 7, 13, 1], 2), ([1, 16, 1], 1)):
+        L = len(ranks) - 1
+        cores = I.gaussian_qtt(ranks, [8] * L, seed=27 + L)
+        X = I.rhs(8 ** L, K, seed=28 + L)
+        ref = O.qtt_apply_alg2(cores, X)
+        A = Q.qtt_matrix_load(cores, dtypes=("fp64",))
+        Q.qtt_set_shape(A, "fp64", -1, 50)
+        Xd = Q.to_block(X)
+        for shape in range(50, 57):
+            for k in range(L):
+                Q.qtt_set_shape(A, "fp64", k, shape)
+            Y = Q.qtt_apply(A, "fp64", Xd).cpu().numpy()
+            assert colrel(Y, ref) <= 1e-12 and elementwise_ok(Y, ref, 1e-12), (ranks, shape)
+        # odd leading dimension: 8-byte aligned columns only
+        Xp = torch.zeros((K, 8 ** L + 1), dtype=torch.float64, device="cuda")
+        Xp[:, :8 ** L] = torch.from_numpy(X.T.copy()).cuda()
+        Y = Q.qtt_apply(A, "fp64", Xp.t()[:8 ** L]).cpu().numpy()
+        assert colrel(Y, ref) <= 1e-12
+        A.free()
+    Ac, Aic = I.perturbed_identity_pair([1, 6, 8, 6, 1], [8] * 4, seed=85)
+    F = I.rhs(4096, 2, seed=86)
+    A = Q.qtt_matrix_load(Ac, dtypes=("fp64",))
+    Ai = Q.qtt_matrix_load(Aic, dtypes=("bf16",))
+    Q.qtt_set_shape(A, "fp64", -1, 50)
+    Sig, info, st = Q.qtt_solve(A, Ai, "bf16", Q.to_block(F), rtol=1e-8)
+    res = F - O.qtt_apply_alg2(Ac, Sig.cpu().numpy())
+    assert np.all(np.linalg.norm(res, axis=0) <= 1e-8 * np.linalg.norm(F, axis=0) * 1.0001)
+    with pytest.raises(Q.QttError):
+        B = Q.qtt_matrix_load(I.gaussian_qtt([1, 2, 1], [4, 8], seed=1), dtypes=("fp64",))
+        try:
+            Q.qtt_set_shape(B, "fp64", -1, 50)    # mode sizes other than 8
+        finally:
+            B.free()
+    A.free()
+    Ai.free()
