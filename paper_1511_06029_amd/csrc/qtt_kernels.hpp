@@ -132,7 +132,7 @@ struct StepArgs {
   int32_t in_table;      // input columns come from seg[].x
   int32_t out_table;     // output goes to seg[].y (FP64, with z and alpha)
   int32_t nseg;
-  int32_t pad_;
+  int32_t M_bytes;       // bytes of the fragment array M (range of buffer loads), 0 if not needed
   double alpha;
   Segment seg[kMaxSeg];
 };
@@ -795,6 +795,245 @@ core_step_stream_kernel(const StepArgs args) {
     if (it + 1 < total_it) lstore((int)((it + 1) & 1));
     __syncthreads();
     if (it + 2 < total_it) gload(it + 2);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 core step on the 4x4x4 matrix instruction.
+//
+// v_mfma_f64_4x4x4_4b_f64 computes four independent 4x4 products over a
+// contraction of 4.  Operand lane l carries contraction index l div 16, block
+// (l div 4) mod 4 and line l mod 4; output lane 16 r + 4 b + c holds row r,
+// column c of block b (measured lane by lane on gfx950).  On gfx950 it runs
+// at about twice the FP64 rate of the 16x16x4 form.
+//
+// Here the four blocks are four groups of four core rows.  The core operand
+// is then exactly the 16-row fragment used above (lane 16 k + n holds
+// M(16 rb + n, 4 s + k)).  The input operand carries four columns, each
+// replicated over the four blocks (lane 16 k + 4 b + c holds b_k(4 s + k,
+// column c)), which LDS serves as broadcast reads.  The output of lane l is
+// row 16 rb + (l mod 16) of the core, column l div 16 of the 4-column group,
+// so rows stay on lanes and 16 lanes store 16 consecutive a_k.
+//
+// The streaming scheme is the one of the kernel above: input chunks a chunk
+// ahead in registers, two LDS stages, core fragments from L2 a step ahead.
+// LDS input layout: for 4-column group g and step s, a run of 16 values with
+// (column c, contraction k) at 4 c + k; runs are kQGS values apart, a padding
+// that puts the 16-byte stores of one column's consecutive steps on distinct
+// banks.
+// ---------------------------------------------------------------------------
+static constexpr int kQGS = 20;
+
+// Core fragments come through a buffer resource: the per-lane part of the
+// byte offset (row block, lane) is fixed for the whole launch and the step
+// part is wave-uniform (a scalar offset), so a fragment load costs no vector
+// address arithmetic.  Fragments are prefetched PF steps ahead in a ring of
+// registers.  Vector-memory loads complete in issue order, so the wait for a
+// fragment also waits for every older load; the next chunk's input loads are
+// therefore issued right after the first fragment prefetch of a chunk, which
+// leaves them PF + 1 steps before the first wait that covers them.
+template <int WAVES_R, int WAVES_C, int WR, int WQ, int KC, int PF, int MIN_WAVES = 1>
+__global__ void __launch_bounds__(64 * WAVES_R * WAVES_C, MIN_WAVES)
+core_step_f64q_kernel(const StepArgs args) {
+  (void)args;
+  const StepArgs& a = kernarg<StepArgs>();
+  constexpr int NT = 64 * WAVES_R * WAVES_C;
+  constexpr int TC = 4 * WQ * WAVES_C;
+  constexpr int TR = 16 * WR * WAVES_R;
+  constexpr int SPC = KC / 4;
+  static_assert(KC % 8 == 0, "chunk must hold an even number of steps");
+  static_assert(SPC % PF == 0, "chunk must hold whole prefetch rounds");
+  constexpr int VPC = KC / 2;  // 16-byte loads per column and chunk
+  constexpr int NLA = (TC * VPC + NT - 1) / NT;
+  constexpr int A_ELEMS = (TC / 4) * SPC * kQGS;
+
+  __shared__ __attribute__((aligned(16))) double lds[2 * A_ELEMS];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wr = wave % WAVES_R;
+  const int wc = wave / WAVES_R;
+  const int Ks = a.Ksteps;
+  const int nch = (Ks * 4 + KC - 1) / KC;
+  // this lane's element inside a 16-value run: column lane mod 4, contraction lane div 16
+  const int rd = 4 * (lane & 3) + (lane >> 4);
+
+  const int64_t my_tiles = (a.n_tiles > (int64_t)blockIdx.x)
+                               ? (a.n_tiles - 1 - (int64_t)blockIdx.x) / gridDim.x + 1 : 0;
+  const int64_t total_it = my_tiles * nch;
+  if (total_it == 0) return;
+
+  v4u sa[NLA];
+  auto gload = [&](int64_t it) {
+    const int64_t tile = blockIdx.x + (it / nch) * (int64_t)gridDim.x;
+    const int kc0 = (int)(it % nch) * KC;
+    const int64_t col0 = (tile / a.n_row_tiles) * (int64_t)TC;
+#pragma unroll
+    for (int t = 0; t < NLA; ++t) {
+      const int idx = tid + t * NT;
+      const int c = idx / VPC;
+      const int kap = kc0 + (idx % VPC) * 2;
+      const int64_t g = col0 + c;
+      sa[t] = v4u{};
+      if (idx < TC * VPC && g < a.ncols && kap < a.K_in) {
+        const int64_t rhs = g / a.C;
+        const int64_t q = g - rhs * a.C;
+        const double* p;
+        if (a.in_table) {
+          const Segment& sg = a.seg[find_seg(a, rhs)];
+          p = reinterpret_cast<const double*>(sg.x) + (rhs - sg.rhs_begin) * sg.ldx + q * a.K_in;
+        } else {
+          p = reinterpret_cast<const double*>(a.in) + rhs * a.in_stride + q * a.K_in;
+        }
+        sa[t] = *reinterpret_cast<const v4u*>(p + kap);
+      }
+    }
+  };
+  auto lstore = [&](int stage) {
+    double* A = lds + stage * A_ELEMS;
+#pragma unroll
+    for (int t = 0; t < NLA; ++t) {
+      const int idx = tid + t * NT;
+      if (idx < TC * VPC) {
+        const int c = idx / VPC;
+        const int kl0 = (idx % VPC) * 2;
+        *reinterpret_cast<v4u*>(&A[((c >> 2) * SPC + (kl0 >> 2)) * kQGS + 4 * (c & 3) + (kl0 & 3)]) = sa[t];
+      }
+    }
+  };
+
+  // fragment loads: byte offset ((row block) * Ks + step) * 512 + 8 * lane, the
+  // row block being rt * TR / 16 + wr * WR + i for row tile rt
+  const __amdgpu_buffer_rsrc_t mrs =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(a.M), (short)0, a.M_bytes, 0x00020000);
+  int vo[WR];
+#pragma unroll
+  for (int i = 0; i < WR; ++i) vo[i] = ((wr * WR + i) * Ks * 64 + lane) * 8;
+  const int rt_bytes = (TR / 16) * Ks * 512;
+  // prefetch cursor: step pf_s of the row tile pf_rt (tiles advance by
+  // gridDim.x, so the row tile advances by gridDim.x mod n_row_tiles)
+  const int rt_adv = (int)(gridDim.x % (unsigned)a.n_row_tiles);
+  int pf_s = 0;
+  int pf_rt = (int)(blockIdx.x % (unsigned)a.n_row_tiles);
+  auto bload = [&](double (&dst)[WR]) {
+    const int soff = __builtin_amdgcn_readfirstlane(pf_rt * rt_bytes + pf_s * 512);
+#pragma unroll
+    for (int i = 0; i < WR; ++i)
+      dst[i] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(mrs, vo[i], soff, 0));
+    if (++pf_s == Ks) {
+      pf_s = 0;
+      pf_rt += rt_adv;
+      if (pf_rt >= a.n_row_tiles) pf_rt -= a.n_row_tiles;
+    }
+  };
+
+  double acc[WR][WQ];
+  double ring[PF][WR];
+  gload(0);
+  lstore(0);
+#pragma unroll
+  for (int p = 0; p < PF; ++p) bload(ring[p]);
+  __syncthreads();
+
+  for (int64_t it = 0; it < total_it; ++it) {
+    const int ch = (int)(it % nch);
+    const int64_t tile = blockIdx.x + (it / nch) * (int64_t)gridDim.x;
+    const int rt = (int)(tile % a.n_row_tiles);
+    if (ch == 0) {
+#pragma unroll
+      for (int i = 0; i < WR; ++i)
+#pragma unroll
+        for (int j = 0; j < WQ; ++j) acc[i][j] = 0.0;
+    }
+    const double* A = lds + (it & 1) * A_ELEMS;
+    const int s0 = ch * SPC;
+    const int nsteps = min(SPC, Ks - s0);
+    auto lread = [&](double (&dst)[WQ], int s) {
+#pragma unroll
+      for (int j = 0; j < WQ; ++j) dst[j] = A[((wc * WQ + j) * SPC + s) * kQGS + rd];
+    };
+    auto mma = [&](const double (&af)[WQ], const double (&bc)[WR]) {
+#pragma unroll
+      for (int i = 0; i < WR; ++i)
+#pragma unroll
+        for (int j = 0; j < WQ; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_4x4x4f64(af[j], bc[i], acc[i][j], 0, 0, 0);
+    };
+    if (nsteps == SPC) {
+      // whole chunk: ring slot s mod PF holds step s (the ring is back in
+      // place after the chunk); input fragments read one step ahead
+      double af[2][WQ];
+      lread(af[0], 0);
+#pragma unroll
+      for (int s = 0; s < SPC; ++s) {
+        if (s + 1 < SPC) lread(af[(s + 1) & 1], s + 1);
+        double bc[WR];
+#pragma unroll
+        for (int i = 0; i < WR; ++i) bc[i] = ring[s % PF][i];
+        bload(ring[s % PF]);
+        if (s == 0 && it + 1 < total_it) gload(it + 1);
+        mma(af[s & 1], bc);
+      }
+    } else {
+      // partial chunk (the last of a tile): rotate the ring step by step
+      for (int s = 0; s < nsteps; ++s) {
+        double af[WQ];
+        lread(af, s);
+        double bc[WR];
+#pragma unroll
+        for (int i = 0; i < WR; ++i) bc[i] = ring[0][i];
+#pragma unroll
+        for (int p = 0; p + 1 < PF; ++p)
+#pragma unroll
+          for (int i = 0; i < WR; ++i) ring[p][i] = ring[p + 1][i];
+        bload(ring[PF - 1]);
+        if (s == 0 && it + 1 < total_it) gload(it + 1);
+        mma(af, bc);
+      }
+    }
+
+    if (ch == nch - 1) {
+      const int64_t col0 = (tile / a.n_row_tiles) * (int64_t)TC;
+      const int64_t rhs0 = col0 / a.C;
+      const int64_t q0 = col0 - rhs0 * a.C;
+      const bool one_rhs = (q0 + TC <= a.C);
+      const Segment* s0p = a.out_table ? &a.seg[find_seg(a, rhs0)] : nullptr;
+#pragma unroll
+      for (int i = 0; i < WR; ++i) {
+        const int row = rt * TR + (wr * WR + i) * 16 + (lane & 15);
+        const int ar = row % a.r_out;
+        const int ir = row / a.r_out;
+#pragma unroll
+        for (int j = 0; j < WQ; ++j) {
+          const int cit = (wc * WQ + j) * 4 + (lane >> 4);
+          const int64_t g = col0 + cit;
+          if (g >= a.ncols || row >= a.R_out) continue;
+          int64_t rhs, q;
+          const Segment* sp = s0p;
+          if (one_rhs) {
+            rhs = rhs0;
+            q = q0 + cit;
+          } else {
+            rhs = g / a.C;
+            q = g - rhs * a.C;
+            if (a.out_table) sp = &a.seg[find_seg(a, rhs)];
+          }
+          const int64_t off = ar + (int64_t)a.r_out * (q + a.C * ir);
+          const double val = acc[i][j];
+          if (a.out_table) {
+            const int64_t vr = rhs - sp->rhs_begin;
+            double res = a.alpha * val;
+            if (sp->z != nullptr) res += sp->z[vr * sp->ldz + off];
+            sp->y[vr * sp->ldy + off] = res;
+          } else {
+            reinterpret_cast<double*>(a.out)[rhs * a.out_stride + off] = val;
+          }
+        }
+      }
+    }
+    if (it + 1 < total_it) lstore((int)((it + 1) & 1));
+    __syncthreads();
   }
 }
 

@@ -80,18 +80,22 @@ struct KernelCfg {
 };
 
 template <class Tc, class Tin, int WRW, int WCW, int WR, int WC, int KC, bool ROL, bool VEC, int KIND,
-          int MINW = 1>
+          int MINW = 1, int PF = 1>
 static KernelCfg make_cfg(int dt, bool in_f64, int id) {
   KernelCfg k;
   k.dt = dt;
   k.in_f64 = in_f64;
   k.vec = VEC;
   k.TR = 16 * WR * WRW;
-  k.TC = 16 * WC * WCW;
+  k.TC = (KIND == 3 ? 4 : 16) * WC * WCW;
   k.KC = KC;
   k.NT = 64 * WRW * WCW;
   k.id = id;
-  if constexpr (KIND == 2)
+  if constexpr (KIND == 3) {
+    static_assert(std::is_same<Tc, double>::value && std::is_same<Tin, double>::value,
+                  "the 4x4x4 kernel is FP64 only");
+    k.fn = reinterpret_cast<const void*>(&core_step_f64q_kernel<WRW, WCW, WR, WC, KC, PF, MINW>);
+  } else if constexpr (KIND == 2)
     k.fn = reinterpret_cast<const void*>(&core_step_stream_kernel<Tc, Tin, WRW, WCW, WR, WC, KC, ROL, VEC, MINW>);
   else if constexpr (KIND == 1)
     k.fn = reinterpret_cast<const void*>(&core_step_pipe_kernel<Tc, Tin, WRW, WCW, WR, WC, KC, ROL, VEC>);
@@ -123,6 +127,20 @@ static KernelCfg make_cfg(int dt, bool in_f64, int id) {
   X(25, 4, 1, 2, 4, true)    \
   X(26, 4, 1, 4, 1, true)    \
   X(27, 1, 4, 1, 2, false)
+// FP64 shapes on the 4x4x4 instruction (ids from 60): (id, waves along rows,
+// waves along columns, row blocks per wave, 4-column groups per wave, chunk
+// length KC, core prefetch depth in steps, minimum resident waves per SIMD).
+#define QTT_SHAPES_Q(X)             \
+  X(60, 4, 1, 4, 8, 32, 2, 2)       \
+  X(61, 4, 1, 4, 4, 64, 2, 2)       \
+  X(62, 4, 1, 2, 8, 64, 4, 2)       \
+  X(63, 4, 1, 3, 8, 32, 2, 2)       \
+  X(64, 4, 1, 4, 4, 32, 4, 2)       \
+  X(65, 4, 1, 4, 4, 32, 2, 2)       \
+  X(66, 4, 1, 2, 8, 32, 4, 2)       \
+  X(67, 4, 1, 3, 8, 32, 4, 2)       \
+  X(68, 4, 1, 4, 16, 32, 2, 1)      \
+  X(69, 2, 2, 4, 4, 32, 2, 2)
 static const int kGenericShape = 6;
 
 template <class Tc, class Tin, int KC1, int KC2>
@@ -136,6 +154,12 @@ static void add_family(std::vector<KernelCfg>& v, int dt, bool in_f64) {
   // streamed shapes held to 3 resident waves per SIMD (fewer registers each)
   v.push_back(make_cfg<Tc, Tin, 4, 1, 4, 2, KC1, true, true, 2, 3>(dt, in_f64, 28));
   v.push_back(make_cfg<Tc, Tin, 4, 1, 2, 4, KC1, true, true, 2, 3>(dt, in_f64, 29));
+  if constexpr (std::is_same<Tc, double>::value) {
+#define QTT_ADDQ(id, a, b, c, d, kc, pf, mw) \
+    v.push_back(make_cfg<Tc, Tin, a, b, c, d, kc, true, true, 3, mw, pf>(dt, in_f64, id));
+    QTT_SHAPES_Q(QTT_ADDQ)
+#undef QTT_ADDQ
+  }
 #undef QTT_ADD1
 #undef QTT_ADD2
 #undef QTT_ADD3
@@ -417,6 +441,7 @@ static bool tune_log() {
 // Untuned defaults, from tuning runs on MI355X at L = 7, r = 32.
 static int heuristic_shape(int R_out, int K_in, int dt) {
   if (R_out <= 16) return dt == 0 ? 47 : 2;      // last core (r_d = 1)
+  if (dt == 0 && R_out > 64) return R_out <= 192 ? 63 : 60;   // FP64: 4x4x4 matrix instruction
   if (K_in <= 16) return dt == 0 ? 6 : 26;       // first core (r_0 = 1)
   if (R_out <= 64) return kGenericShape;
   return dt == 2 ? kBf16Dma : 21;                // interior cores (DMA falls back to resident)
@@ -617,6 +642,10 @@ static qtt_status_t launch_step(const qtt_matrix_s* A, int k, int dt, int64_t nr
   const bool f64dma_ok = dt == 0 && !first && !last && c.R_out <= 256 && c.R_out % 64 == 0 &&
                          c.C % 64 == 0 && c.Ksteps[0] >= 4;
   if (shape == kF64Dma && !f64dma_ok) shape = 21;
+  // the 4x4x4 kernels address the fragment array with 32-bit buffer offsets
+  const int64_t m_bytes =
+      (int64_t)padded_row_blocks(c.nRB) * c.Ksteps[dt] * 64 * kFragE[dt] * kElemBytes[dt];
+  if (shape >= 60 && shape < 70 && m_bytes > INT32_MAX) shape = 21;
   if (shape == kBf16Resident && !resident_ok) shape = heuristic_shape(c.R_out, c.K_in, 1);
   KernelCfg* kc = (shape == kF64Dma) ? f64_dma_cfg()
                   : (shape == kBf16Dma) ? bf16_dma_cfg()
@@ -644,6 +673,7 @@ static qtt_status_t launch_step(const qtt_matrix_s* A, int k, int dt, int64_t nr
   a.in_table = first ? 1 : 0;
   a.out_table = last ? 1 : 0;
   a.nseg = nseg;
+  a.M_bytes = (int32_t)std::min<int64_t>(m_bytes, INT32_MAX);
   a.alpha = alpha;
   for (int s = 0; s < nseg; ++s) a.seg[s] = segs[s];
 
