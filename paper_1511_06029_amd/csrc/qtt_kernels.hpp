@@ -832,7 +832,9 @@ static constexpr int kQGS = 20;
 // fragment also waits for every older load; the next chunk's input loads are
 // therefore issued right after the first fragment prefetch of a chunk, which
 // leaves them PF + 1 steps before the first wait that covers them.
-template <int WAVES_R, int WAVES_C, int WR, int WQ, int KC, int PF, int MIN_WAVES = 1>
+// Requires Ksteps to be a multiple of the chunk's KC / 4 steps (checked by the
+// host): chunks are always whole, so the ring indices stay compile-time.
+template <int WAVES_R, int WAVES_C, int WR, int WQ, int KC, int PF, int MIN_WAVES = 1, bool AHEAD = true>
 __global__ void __launch_bounds__(64 * WAVES_R * WAVES_C, MIN_WAVES)
 core_step_f64q_kernel(const StepArgs args) {
   (void)args;
@@ -947,8 +949,6 @@ core_step_f64q_kernel(const StepArgs args) {
         for (int j = 0; j < WQ; ++j) acc[i][j] = 0.0;
     }
     const double* A = lds + (it & 1) * A_ELEMS;
-    const int s0 = ch * SPC;
-    const int nsteps = min(SPC, Ks - s0);
     auto lread = [&](double (&dst)[WQ], int s) {
 #pragma unroll
       for (int j = 0; j < WQ; ++j) dst[j] = A[((wc * WQ + j) * SPC + s) * kQGS + rd];
@@ -960,36 +960,25 @@ core_step_f64q_kernel(const StepArgs args) {
         for (int j = 0; j < WQ; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_4x4x4f64(af[j], bc[i], acc[i][j], 0, 0, 0);
     };
-    if (nsteps == SPC) {
-      // whole chunk: ring slot s mod PF holds step s (the ring is back in
-      // place after the chunk); input fragments read one step ahead
-      double af[2][WQ];
+    {
+      // ring slot s mod PF holds step s (the ring is back in place after the
+      // chunk); with AHEAD, input fragments are read one step ahead (more
+      // registers, less exposed LDS latency)
+      double af[AHEAD ? 2 : 1][WQ];
       lread(af[0], 0);
 #pragma unroll
       for (int s = 0; s < SPC; ++s) {
-        if (s + 1 < SPC) lread(af[(s + 1) & 1], s + 1);
+        if (AHEAD) {
+          if (s + 1 < SPC) lread(af[(s + 1) % (AHEAD ? 2 : 1)], s + 1);
+        } else if (s > 0) {
+          lread(af[0], s);
+        }
         double bc[WR];
 #pragma unroll
         for (int i = 0; i < WR; ++i) bc[i] = ring[s % PF][i];
         bload(ring[s % PF]);
         if (s == 0 && it + 1 < total_it) gload(it + 1);
-        mma(af[s & 1], bc);
-      }
-    } else {
-      // partial chunk (the last of a tile): rotate the ring step by step
-      for (int s = 0; s < nsteps; ++s) {
-        double af[WQ];
-        lread(af, s);
-        double bc[WR];
-#pragma unroll
-        for (int i = 0; i < WR; ++i) bc[i] = ring[0][i];
-#pragma unroll
-        for (int p = 0; p + 1 < PF; ++p)
-#pragma unroll
-          for (int i = 0; i < WR; ++i) ring[p][i] = ring[p + 1][i];
-        bload(ring[PF - 1]);
-        if (s == 0 && it + 1 < total_it) gload(it + 1);
-        mma(af, bc);
+        mma(af[AHEAD ? (s & 1) : 0], bc);
       }
     }
 
@@ -1775,6 +1764,219 @@ __global__ void __launch_bounds__(64 * NW) core_step_valu64t_kernel(const ValuAr
       }
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 core step on the 4x4x4 matrix instruction with both operands in LDS.
+//
+// Same product and operand mapping as core_step_f64q_kernel.  Vector-memory
+// operations complete in issue order, so a kernel that waits on core loads
+// every step also waits on every older input load and output store.  Here
+// every vector-memory wait is at a chunk boundary.
+//  * The core fragments of a chunk (the workgroup's TR / 16 row blocks, SPC
+//    steps) are copied into LDS by direct global-to-LDS loads of 16 bytes per
+//    lane, i.e. two consecutive step fragments of one row block per load.
+//  * The input columns of a chunk are loaded into registers and written to
+//    LDS in the 16-value-run layout (kQGS).
+//  * Both are issued for chunk it + 1 when chunk it starts, into the other of
+//    two LDS stages, and waited for (vmcnt 0) when chunk it ends.
+//  * The output stores of a finished tile are issued after those loads, at
+//    the start of the next chunk, so that a whole chunk of matrix work
+//    separates them from the next wait.
+// Requires an even number of steps Ks (the copies move step pairs).
+// ---------------------------------------------------------------------------
+template <int WR, int WQ, int KC, int MIN_WAVES = 1>
+__global__ void __launch_bounds__(256, MIN_WAVES)
+core_step_f64ql_kernel(const StepArgs args) {
+  (void)args;
+  const StepArgs& a = kernarg<StepArgs>();
+  constexpr int NT = 256;
+  constexpr int TC = 4 * WQ;
+  constexpr int TR = 16 * WR * 4;
+  constexpr int SPC = KC / 4;
+  static_assert(KC % 8 == 0, "chunk must hold an even number of steps");
+  constexpr int VPC = KC / 2;  // 16-byte input loads per column and chunk
+  constexpr int NLA = (TC * VPC + NT - 1) / NT;
+  constexpr int CORE_ELEMS = (TR / 16) * SPC * 64;
+  constexpr int IN_ELEMS = (TC / 4) * SPC * kQGS;
+  constexpr int STAGE = CORE_ELEMS + IN_ELEMS;
+  constexpr int NPAIR = (TR / 16) * (SPC / 2);  // core copies per chunk
+
+  __shared__ __attribute__((aligned(16))) double lds[2 * STAGE];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wr = tid >> 6;
+  const double* __restrict__ Mf = reinterpret_cast<const double*>(a.M);
+  const int Ks = a.Ksteps;
+  const int nch = (Ks * 4 + KC - 1) / KC;
+  const int rd = 4 * (lane & 3) + (lane >> 4);
+
+  const int64_t my_tiles = (a.n_tiles > (int64_t)blockIdx.x)
+                               ? (a.n_tiles - 1 - (int64_t)blockIdx.x) / gridDim.x + 1 : 0;
+  const int64_t total_it = my_tiles * nch;
+  if (total_it == 0) return;
+
+  v4u sa[NLA];
+  auto gload = [&](int64_t it) {
+    const int64_t tile = blockIdx.x + (it / nch) * (int64_t)gridDim.x;
+    const int kc0 = (int)(it % nch) * KC;
+    const int64_t col0 = (tile / a.n_row_tiles) * (int64_t)TC;
+#pragma unroll
+    for (int t = 0; t < NLA; ++t) {
+      const int idx = tid + t * NT;
+      const int c = idx / VPC;
+      const int kap = kc0 + (idx % VPC) * 2;
+      const int64_t g = col0 + c;
+      sa[t] = v4u{};
+      if (idx < TC * VPC && g < a.ncols && kap < a.K_in) {
+        const int64_t rhs = g / a.C;
+        const int64_t q = g - rhs * a.C;
+        const double* p;
+        if (a.in_table) {
+          const Segment& sg = a.seg[find_seg(a, rhs)];
+          p = reinterpret_cast<const double*>(sg.x) + (rhs - sg.rhs_begin) * sg.ldx + q * a.K_in;
+        } else {
+          p = reinterpret_cast<const double*>(a.in) + rhs * a.in_stride + q * a.K_in;
+        }
+        sa[t] = *reinterpret_cast<const v4u*>(p + kap);
+      }
+    }
+  };
+  auto lstore = [&](int stage) {
+    double* A = lds + stage * STAGE + CORE_ELEMS;
+#pragma unroll
+    for (int t = 0; t < NLA; ++t) {
+      const int idx = tid + t * NT;
+      if (idx < TC * VPC) {
+        const int c = idx / VPC;
+        const int kl0 = (idx % VPC) * 2;
+        *reinterpret_cast<v4u*>(&A[((c >> 2) * SPC + (kl0 >> 2)) * kQGS + 4 * (c & 3) + (kl0 & 3)]) = sa[t];
+      }
+    }
+  };
+  // core copies of chunk it: unit u = (row block rbl, step pair p), four waves
+  // share the units; a copy moves fragments (rb, s0 + 2 p) and (rb, s0 + 2 p + 1)
+  auto cload = [&](int64_t it, int stage) {
+    const int64_t tile = blockIdx.x + (it / nch) * (int64_t)gridDim.x;
+    const int rt = (int)(tile % a.n_row_tiles);
+    const int s0 = (int)(it % nch) * SPC;
+    const int ns = min(SPC, Ks - s0);
+    double* B = lds + stage * STAGE;
+#pragma unroll
+    for (int u0 = 0; u0 < NPAIR; u0 += 4) {
+      const int u = u0 + wr;
+      const int rbl = u / (SPC / 2), p = u % (SPC / 2);
+      if (u < NPAIR && 2 * p < ns) {
+        const double* src = Mf + ((int64_t)(rt * (TR / 16) + rbl) * Ks + s0 + 2 * p) * 64 + 2 * lane;
+        __builtin_amdgcn_global_load_lds((const void*)src, (lds_void*)(B + (rbl * SPC + 2 * p) * 64), 16, 0, 0);
+      }
+    }
+  };
+
+  double acc[WR][WQ];
+  auto epilogue = [&](int64_t it) {
+    const int64_t tile = blockIdx.x + (it / nch) * (int64_t)gridDim.x;
+    const int rt = (int)(tile % a.n_row_tiles);
+    const int64_t col0 = (tile / a.n_row_tiles) * (int64_t)TC;
+    const int64_t rhs0 = col0 / a.C;
+    const int64_t q0 = col0 - rhs0 * a.C;
+    const bool one_rhs = (q0 + TC <= a.C);
+    const Segment* s0p = a.out_table ? &a.seg[find_seg(a, rhs0)] : nullptr;
+#pragma unroll
+    for (int i = 0; i < WR; ++i) {
+      const int row = rt * TR + (wr * WR + i) * 16 + (lane & 15);
+      const int ar = row % a.r_out;
+      const int ir = row / a.r_out;
+#pragma unroll
+      for (int j = 0; j < WQ; ++j) {
+        const int cit = j * 4 + (lane >> 4);
+        const int64_t g = col0 + cit;
+        if (g >= a.ncols || row >= a.R_out) continue;
+        int64_t rhs, q;
+        const Segment* sp = s0p;
+        if (one_rhs) {
+          rhs = rhs0;
+          q = q0 + cit;
+        } else {
+          rhs = g / a.C;
+          q = g - rhs * a.C;
+          if (a.out_table) sp = &a.seg[find_seg(a, rhs)];
+        }
+        const int64_t off = ar + (int64_t)a.r_out * (q + a.C * ir);
+        const double val = acc[i][j];
+        if (a.out_table) {
+          const int64_t vr = rhs - sp->rhs_begin;
+          double res = a.alpha * val;
+          if (sp->z != nullptr) res += sp->z[vr * sp->ldz + off];
+          sp->y[vr * sp->ldy + off] = res;
+        } else {
+          reinterpret_cast<double*>(a.out)[rhs * a.out_stride + off] = val;
+        }
+      }
+    }
+  };
+
+  cload(0, 0);
+  gload(0);
+  wait_vmcnt<0>();
+  lstore(0);
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < WR; ++i)
+#pragma unroll
+    for (int j = 0; j < WQ; ++j) acc[i][j] = 0.0;
+
+  for (int64_t it = 0; it < total_it; ++it) {
+    if (it + 1 < total_it) {
+      cload(it + 1, (int)((it + 1) & 1));
+      gload(it + 1);
+    }
+    const int ch = (int)(it % nch);
+    if (it > 0 && ch == 0) {
+      epilogue(it - 1);
+#pragma unroll
+      for (int i = 0; i < WR; ++i)
+#pragma unroll
+        for (int j = 0; j < WQ; ++j) acc[i][j] = 0.0;
+    }
+    const double* S = lds + (it & 1) * STAGE;
+    const int nsteps = min(SPC, Ks - ch * SPC);
+    auto lread = [&](double (&af)[WQ], double (&bc)[WR], int s) {
+#pragma unroll
+      for (int i = 0; i < WR; ++i) bc[i] = S[((wr * WR + i) * SPC + s) * 64 + lane];
+#pragma unroll
+      for (int j = 0; j < WQ; ++j) af[j] = S[CORE_ELEMS + (j * SPC + s) * kQGS + rd];
+    };
+    auto mma = [&](const double (&af)[WQ], const double (&bc)[WR]) {
+#pragma unroll
+      for (int i = 0; i < WR; ++i)
+#pragma unroll
+        for (int j = 0; j < WQ; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_4x4x4f64(af[j], bc[i], acc[i][j], 0, 0, 0);
+    };
+    if (nsteps == SPC) {
+      double af[2][WQ], bc[2][WR];
+      lread(af[0], bc[0], 0);
+#pragma unroll
+      for (int s = 0; s < SPC; ++s) {
+        if (s + 1 < SPC) lread(af[(s + 1) & 1], bc[(s + 1) & 1], s + 1);
+        mma(af[s & 1], bc[s & 1]);
+      }
+    } else {
+      for (int s = 0; s < nsteps; ++s) {
+        double af[WQ], bc[WR];
+        lread(af, bc, s);
+        mma(af, bc);
+      }
+    }
+    if (it + 1 < total_it) {
+      wait_vmcnt<0>();
+      lstore((int)((it + 1) & 1));
+    }
+    __syncthreads();
+  }
+  epilogue(total_it - 1);
 }
 
 // ---------------------------------------------------------------------------

@@ -77,24 +77,30 @@ struct KernelCfg {
   int id;          // configuration id within the dtype (tile shape)
   const void* fn;  // kernel symbol
   int occ;         // resident blocks per CU, 0 = not yet queried
+  int kind;        // 0 single-operand LDS, 1 pipelined, 2 streamed, 3 4x4x4 streamed, 4 4x4x4 LDS-fed
 };
 
 template <class Tc, class Tin, int WRW, int WCW, int WR, int WC, int KC, bool ROL, bool VEC, int KIND,
-          int MINW = 1, int PF = 1>
+          int MINW = 1, int PF = 1, bool AHEAD = true>
 static KernelCfg make_cfg(int dt, bool in_f64, int id) {
   KernelCfg k;
   k.dt = dt;
   k.in_f64 = in_f64;
   k.vec = VEC;
   k.TR = 16 * WR * WRW;
-  k.TC = (KIND == 3 ? 4 : 16) * WC * WCW;
+  k.TC = (KIND >= 3 ? 4 : 16) * WC * WCW;
   k.KC = KC;
   k.NT = 64 * WRW * WCW;
   k.id = id;
-  if constexpr (KIND == 3) {
+  k.kind = KIND;
+  if constexpr (KIND == 4) {
+    static_assert(std::is_same<Tc, double>::value && std::is_same<Tin, double>::value && WRW == 4 && WCW == 1,
+                  "the LDS-fed 4x4x4 kernel is FP64 only, four waves along rows");
+    k.fn = reinterpret_cast<const void*>(&core_step_f64ql_kernel<WR, WC, KC, MINW>);
+  } else if constexpr (KIND == 3) {
     static_assert(std::is_same<Tc, double>::value && std::is_same<Tin, double>::value,
                   "the 4x4x4 kernel is FP64 only");
-    k.fn = reinterpret_cast<const void*>(&core_step_f64q_kernel<WRW, WCW, WR, WC, KC, PF, MINW>);
+    k.fn = reinterpret_cast<const void*>(&core_step_f64q_kernel<WRW, WCW, WR, WC, KC, PF, MINW, AHEAD>);
   } else if constexpr (KIND == 2)
     k.fn = reinterpret_cast<const void*>(&core_step_stream_kernel<Tc, Tin, WRW, WCW, WR, WC, KC, ROL, VEC, MINW>);
   else if constexpr (KIND == 1)
@@ -130,17 +136,34 @@ static KernelCfg make_cfg(int dt, bool in_f64, int id) {
 // FP64 shapes on the 4x4x4 instruction (ids from 60): (id, waves along rows,
 // waves along columns, row blocks per wave, 4-column groups per wave, chunk
 // length KC, core prefetch depth in steps, minimum resident waves per SIMD).
+// They serve a core only when its step count is a multiple of KC / 4.
 #define QTT_SHAPES_Q(X)             \
   X(60, 4, 1, 4, 8, 32, 2, 2)       \
-  X(61, 4, 1, 4, 4, 64, 2, 2)       \
-  X(62, 4, 1, 2, 8, 64, 4, 2)       \
+  X(61, 4, 1, 4, 8, 32, 4, 2)       \
+  X(62, 4, 1, 4, 8, 32, 8, 2)       \
   X(63, 4, 1, 3, 8, 32, 2, 2)       \
-  X(64, 4, 1, 4, 4, 32, 4, 2)       \
-  X(65, 4, 1, 4, 4, 32, 2, 2)       \
-  X(66, 4, 1, 2, 8, 32, 4, 2)       \
-  X(67, 4, 1, 3, 8, 32, 4, 2)       \
-  X(68, 4, 1, 4, 16, 32, 2, 1)      \
-  X(69, 2, 2, 4, 4, 32, 2, 2)
+  X(64, 4, 1, 3, 8, 32, 4, 2)       \
+  X(65, 4, 1, 4, 4, 32, 4, 2)       \
+  X(66, 4, 1, 4, 4, 32, 8, 2)       \
+  X(67, 4, 1, 3, 8, 8, 2, 2)        \
+  X(68, 4, 1, 4, 8, 8, 2, 2)        \
+  X(69, 2, 2, 4, 4, 32, 4, 2)
+// the same without reading input fragments a step ahead (ids from 75)
+#define QTT_SHAPES_QN(X)            \
+  X(75, 4, 1, 4, 8, 32, 4, 2)       \
+  X(76, 4, 1, 4, 8, 32, 8, 2)       \
+  X(77, 4, 1, 3, 8, 32, 4, 2)       \
+  X(78, 4, 1, 4, 6, 32, 4, 2)       \
+  X(79, 4, 1, 4, 6, 32, 8, 2)
+// FP64 shapes on the 4x4x4 instruction with both operands in LDS (ids from
+// 70): (id, row blocks per wave, 4-column groups per wave, chunk length KC,
+// minimum resident waves per SIMD); four waves along rows.
+#define QTT_SHAPES_QL(X)     \
+  X(70, 4, 8, 16, 2)         \
+  X(71, 4, 4, 16, 2)         \
+  X(72, 3, 8, 16, 2)         \
+  X(73, 4, 8, 8, 2)          \
+  X(74, 2, 8, 32, 2)
 static const int kGenericShape = 6;
 
 template <class Tc, class Tin, int KC1, int KC2>
@@ -159,6 +182,14 @@ static void add_family(std::vector<KernelCfg>& v, int dt, bool in_f64) {
     v.push_back(make_cfg<Tc, Tin, a, b, c, d, kc, true, true, 3, mw, pf>(dt, in_f64, id));
     QTT_SHAPES_Q(QTT_ADDQ)
 #undef QTT_ADDQ
+#define QTT_ADDQN(id, a, b, c, d, kc, pf, mw) \
+    v.push_back(make_cfg<Tc, Tin, a, b, c, d, kc, true, true, 3, mw, pf, false>(dt, in_f64, id));
+    QTT_SHAPES_QN(QTT_ADDQN)
+#undef QTT_ADDQN
+#define QTT_ADDQL(id, c, d, kc, mw) \
+    v.push_back(make_cfg<Tc, Tin, 4, 1, c, d, kc, true, true, 4, mw>(dt, in_f64, id));
+    QTT_SHAPES_QL(QTT_ADDQL)
+#undef QTT_ADDQL
   }
 #undef QTT_ADD1
 #undef QTT_ADD2
@@ -302,6 +333,7 @@ static KernelCfg* bf16_resident_cfg() {
     c.id = kBf16Resident;
     c.fn = reinterpret_cast<const void*>(&core_step_bf16_resident_kernel);
     c.occ = 0;
+    c.kind = -1;
     return c;
   }();
   return &k;
@@ -315,6 +347,7 @@ static KernelCfg* bf16_dma_cfg() {
     c.id = kBf16Dma;
     c.fn = reinterpret_cast<const void*>(&core_step_bf16_dma_kernel);
     c.occ = 0;
+    c.kind = -1;
     return c;
   }();
   return &k;
@@ -335,6 +368,7 @@ static KernelCfg* f64_dma_cfg() {
     c.id = kF64Dma;
     c.fn = reinterpret_cast<const void*>(&core_step_f64_dma_kernel);
     c.occ = 0;
+    c.kind = -1;
     return c;
   }();
   return &k;
@@ -441,7 +475,10 @@ static bool tune_log() {
 // Untuned defaults, from tuning runs on MI355X at L = 7, r = 32.
 static int heuristic_shape(int R_out, int K_in, int dt) {
   if (R_out <= 16) return dt == 0 ? 47 : 2;      // last core (r_d = 1)
-  if (dt == 0 && R_out > 64) return R_out <= 192 ? 63 : 60;   // FP64: 4x4x4 matrix instruction
+  if (dt == 0 && R_out > 64) {                   // FP64: 4x4x4 matrix instruction
+    if (K_in <= 16) return 67;                   // short chunks for the first core
+    return R_out <= 192 ? 63 : 60;
+  }
   if (K_in <= 16) return dt == 0 ? 6 : 26;       // first core (r_0 = 1)
   if (R_out <= 64) return kGenericShape;
   return dt == 2 ? kBf16Dma : 21;                // interior cores (DMA falls back to resident)
@@ -645,12 +682,16 @@ static qtt_status_t launch_step(const qtt_matrix_s* A, int k, int dt, int64_t nr
   // the 4x4x4 kernels address the fragment array with 32-bit buffer offsets
   const int64_t m_bytes =
       (int64_t)padded_row_blocks(c.nRB) * c.Ksteps[dt] * 64 * kFragE[dt] * kElemBytes[dt];
-  if (shape >= 60 && shape < 70 && m_bytes > INT32_MAX) shape = 21;
+  if (((shape >= 60 && shape < 70) || (shape >= 75 && shape < 80)) && m_bytes > INT32_MAX) shape = 21;
+  // the LDS-fed ones copy step pairs
+  if (shape >= 70 && shape < 75 && c.Ksteps[dt] % 2 != 0) shape = 60;
   if (shape == kBf16Resident && !resident_ok) shape = heuristic_shape(c.R_out, c.K_in, 1);
   KernelCfg* kc = (shape == kF64Dma) ? f64_dma_cfg()
                   : (shape == kBf16Dma) ? bf16_dma_cfg()
                   : (shape == kBf16Resident) ? bf16_resident_cfg()
                   : vec ? find_cfg(dt, in_f64, true, shape) : find_cfg(dt, in_f64, false, kGenericShape);
+  // the streamed 4x4x4 kernels take whole chunks only
+  if (kc && kc->kind == 3 && c.Ksteps[dt] % (kc->KC / 4) != 0) kc = find_cfg(dt, in_f64, true, 21);
   if (!kc) return fail(QTT_ERR_DEVICE, "no kernel for dtype %d shape %d", dt, shape);
 
   StepArgs a;
