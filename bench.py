@@ -32,6 +32,8 @@ PEAK_FP64_TFLOPS = 78.6      # MI355X dense FP64 (matrix and vector)
 PEAK_FP32_TFLOPS = 157.3
 PEAK_BF16_TFLOPS = 2500.0
 PEAK_HBM_GBS = 8000.0
+# the sources whose hash the committed HBM-traffic figures are tied to
+KERNEL_SOURCES = ("paper_1511_06029_amd/csrc/qtt_kernels.hpp", "paper_1511_06029_amd/csrc/qtt_runtime.hip")
 
 
 def parse():
@@ -125,6 +127,7 @@ def main():
         if timing:
             Q.qtt_timing_enable(False)
             kt = {(dt, pos): Q.qtt_timing_read(dt, pos) for dt in ("fp64", v) for pos in (0, 1, 2)}
+            ks = {(dt, sh): Q.qtt_timing_read_shape(dt, sh) for dt in ("fp64", v) for sh in Q.qtt_list_shapes(dt)}
             Q.qtt_timing_reset()
         elapsed = t1 - t0
         iters = max(c[0] for c in infos[-1])
@@ -134,33 +137,43 @@ def main():
                       "passes": iters, "max_rel_residual": worst}
         if timing:
             results[v]["kernels"] = kt
+            results[v]["shapes"] = ks
 
     head = variants[0]
     r0 = results[head]
-    kt = r0["kernels"]
-    f64 = kt[("fp64", 0)]
-    traffic = measured_traffic("core_step_stream_kernel<double, double, 4, 1, 4, 2, 32, true, true>")
+
+    def dominant(dt):
+        """The kernel configuration that carries the most flops of dtype dt."""
+        cand = [(r["flops"], sh, r) for (d, sh), r in r0["shapes"].items() if d == dt and r["launches"]]
+        return max(cand, key=lambda c: c[0])[1:] if cand else (None, None)
+
+    sh64, f64 = dominant("fp64")
+    traffic, kname = measured_traffic("fp64", sh64)
     roof = None
-    if f64["launches"]:
+    if f64 is not None:
         avg_ms = f64["ms"] / f64["launches"]
         per_launch_flops = f64["flops"] / f64["launches"]
         achieved = per_launch_flops / (avg_ms * 1e-3) / 1e12
         roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
                 "traffic": (None if (traffic is None or args.tune) else traffic),
-                "kernel": "FP64 core step (autotuned configuration, 4x4x4 matrix instruction by default) on the interior cores of the FP64 residual apply",
+                "kernel": (f"FP64 core step, configuration {sh64}" + (f" ({kname})" if kname else "")
+                           + ", the one carrying most of the FP64 residual apply's flops"),
                 "launches": f64["launches"], "avg_launch_ms": round(avg_ms, 4),
                 "flops_per_launch": per_launch_flops,
                 "achieved_hbm_GBs": round(f64["bytes"] / f64["ms"] * 1e-6, 1)}
-    lo = kt.get((head, 0))
     roof_lo = None
-    if head != "fp64" and lo and lo["launches"]:
-        gbs = lo["bytes"] / lo["ms"] * 1e-6
-        tfs = lo["flops"] / lo["ms"] * 1e-9
-        roof_lo = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                   "frac": round(gbs / PEAK_HBM_GBS, 4), "tflops": round(tfs, 2),
-                   "kernel": f"core_step_kernel<{head}> on the interior cores of the inverse apply",
-                   "launches": lo["launches"], "avg_launch_ms": round(lo["ms"] / lo["launches"], 4)}
+    if head != "fp64":
+        shlo, lo = dominant(head)
+        if lo is not None:
+            gbs = lo["bytes"] / lo["ms"] * 1e-6
+            tfs = lo["flops"] / lo["ms"] * 1e-9
+            _, klo = measured_traffic(head, shlo)
+            roof_lo = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                       "frac": round(gbs / PEAK_HBM_GBS, 4), "tflops": round(tfs, 2),
+                       "kernel": (f"{head} core step, configuration {shlo}" + (f" ({klo})" if klo else "")
+                                  + ", the one carrying most of the inverse apply's flops"),
+                       "launches": lo["launches"], "avg_launch_ms": round(lo["ms"] / lo["launches"], 4)}
 
     batched = None if args.no_batched else batched_run(Q, torch)
 
@@ -188,7 +201,8 @@ def main():
         "latency_ms": {"p50": round(r0["p50_ms"], 3), "p99": round(r0["p99_ms"], 3)},
         "passes": r0["passes"],
         "max_rel_residual": r0["max_rel_residual"],
-        "variants": {v: {k: (float(f"{x:.5g}") if isinstance(x, float) else x) for k, x in r.items() if k != "kernels"}
+        "variants": {v: {k: (float(f"{x:.5g}") if isinstance(x, float) else x) for k, x in r.items()
+                         if k not in ("kernels", "shapes")}
                      for v, r in results.items()},
         "speedup_vs_plain_fp64": (round(r0["rhs_per_s"] / results["fp64"]["rhs_per_s"], 3)
                                   if "fp64" in results and head != "fp64" else None),
@@ -202,21 +216,24 @@ def main():
     Ai.free()
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed PMC summary
-    (profiles/hbm_traffic_refine_L7.json: FETCH_SIZE and WRITE_SIZE scaled by
-    the copy calibration), or None when the kernel source changed since."""
+def measured_traffic(dtype, shape):
+    """(HBM bytes per launch, kernel name) of configuration `shape` of `dtype`
+    from the committed PMC summary (profiles/hbm_traffic_refine_L7.json:
+    FETCH_SIZE and WRITE_SIZE scaled by the copy calibration).  The bytes are
+    None when the library sources changed since the counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "hbm_traffic_refine_L7.json")
-    src = os.path.join(ROOT, "paper_1511_06029_amd", "csrc", "qtt_kernels.hpp")
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
     try:
         rec = json.load(open(path))
-        if rec["kernels_source_sha256"] != hashlib.sha256(open(src, "rb").read()).hexdigest():
-            return None
-        b = rec["bytes_per_launch"][kernel]
-        return round(b["fetch"] + b["write"])
+        b = rec["bytes_per_launch"][f"{dtype} shape {shape}"]
     except (OSError, KeyError, ValueError):
-        return None
+        return None, None
+    if rec.get("sources_sha256") != h.hexdigest():
+        return None, b.get("kernel")
+    return round(b["fetch"] + b["write"]), b.get("kernel")
 
 
 def copy_probe(torch):

@@ -490,6 +490,7 @@ static int heuristic_shape(int R_out, int K_in, int dt) {
 struct TimedLaunch {
   hipEvent_t a, b;
   int dt, pos;
+  int shape;  // kernel configuration id
   double flops, bytes;
 };
 static thread_local bool g_timing = false;
@@ -514,7 +515,7 @@ static bool timing_on() {
 static bool is_valu_shape(int id) { return id >= 40 && id < 50; }
 
 static void record_timing(TimedLaunch& tl, const qtt_matrix_s* A, int k, int dt, int64_t ncols,
-                          const Segment* segs, int nseg);
+                          const Segment* segs, int nseg, int shape);
 
 static qtt_status_t launch_valu(const qtt_matrix_s* A, int k, int64_t nrhs, const Segment* segs, int nseg,
                                 const void* in_packed, void* out_packed, double alpha, int id, hipStream_t st) {
@@ -566,7 +567,7 @@ static qtt_status_t launch_valu(const qtt_matrix_s* A, int k, int64_t nrhs, cons
   HIP_TRY(hipLaunchKernel(vc->fn, dim3(grid), dim3(nt), args, 0, st));
   if (timed) {
     HIP_TRY(hipEventRecord(tl.b, st));
-    record_timing(tl, A, k, 0, a.ncols, segs, nseg);
+    record_timing(tl, A, k, 0, a.ncols, segs, nseg, vc->id);
   }
   return QTT_OK;
 }
@@ -621,14 +622,15 @@ static qtt_status_t launch_valut(const qtt_matrix_s* A, int k, int64_t nrhs, con
   HIP_TRY(hipLaunchKernel(vc->fn, dim3(grid), dim3(nt), args, 0, st));
   if (timed) {
     HIP_TRY(hipEventRecord(tl.b, st));
-    record_timing(tl, A, k, 0, a.ncols, segs, nseg);
+    record_timing(tl, A, k, 0, a.ncols, segs, nseg, vc->id);
   }
   return QTT_OK;
 }
 
 static void record_timing(TimedLaunch& tl, const qtt_matrix_s* A, int k, int dt, int64_t ncols,
-                          const Segment* segs, int nseg) {
+                          const Segment* segs, int nseg, int shape) {
   const CoreDev& c = A->core[k];
+  tl.shape = shape;
   const bool first = (k == 0), last = (k == A->d - 1);
   tl.dt = dt;
   tl.pos = (A->d == 1) ? 3 : (first ? 1 : (last ? 2 : 0));
@@ -732,7 +734,7 @@ static qtt_status_t launch_step(const qtt_matrix_s* A, int k, int dt, int64_t nr
   HIP_TRY(hipLaunchKernel(kc->fn, dim3(grid), dim3(kc->NT), args, 0, st));
   if (timed) {
     HIP_TRY(hipEventRecord(tl.b, st));
-    record_timing(tl, A, k, dt, a.ncols, segs, nseg);
+    record_timing(tl, A, k, dt, a.ncols, segs, nseg, kc->id);
   }
   return QTT_OK;
 }
@@ -1529,14 +1531,14 @@ qtt_status_t qtt_timing_reset(void) {
   return QTT_OK;
 }
 
-qtt_status_t qtt_timing_read(qtt_dtype_t compute, int32_t position, int64_t* launches, double* milliseconds,
-                             double* flops, double* bytes) {
-  const int dt = dt_index(compute);
-  if (dt < 0 || position < 0 || position > 3) return fail(QTT_ERR_INVALID_ARG, "bad dtype or position");
+// launches of one dtype selected by core position (by_shape == false) or by
+// kernel configuration id (by_shape == true)
+static qtt_status_t timing_sum(int dt, bool by_shape, int key, int64_t* launches, double* milliseconds,
+                               double* flops, double* bytes) {
   int64_t n = 0;
   double ms = 0, fl = 0, by = 0;
   for (auto& t : g_timed) {
-    if (t.dt != dt || t.pos != position) continue;
+    if (t.dt != dt || (by_shape ? t.shape : t.pos) != key) continue;
     HIP_TRY(hipEventSynchronize(t.b));
     float e = 0;
     HIP_TRY(hipEventElapsedTime(&e, t.a, t.b));
@@ -1550,6 +1552,20 @@ qtt_status_t qtt_timing_read(qtt_dtype_t compute, int32_t position, int64_t* lau
   if (flops) *flops = fl;
   if (bytes) *bytes = by;
   return QTT_OK;
+}
+
+qtt_status_t qtt_timing_read(qtt_dtype_t compute, int32_t position, int64_t* launches, double* milliseconds,
+                             double* flops, double* bytes) {
+  const int dt = dt_index(compute);
+  if (dt < 0 || position < 0 || position > 3) return fail(QTT_ERR_INVALID_ARG, "bad dtype or position");
+  return timing_sum(dt, false, position, launches, milliseconds, flops, bytes);
+}
+
+qtt_status_t qtt_timing_read_shape(qtt_dtype_t compute, int32_t shape, int64_t* launches,
+                                   double* milliseconds, double* flops, double* bytes) {
+  const int dt = dt_index(compute);
+  if (dt < 0) return fail(QTT_ERR_INVALID_ARG, "bad dtype");
+  return timing_sum(dt, true, shape, launches, milliseconds, flops, bytes);
 }
 
 }  // extern "C"

@@ -62,6 +62,7 @@ def _load():
         "qtt_timing_enable": [I32],
         "qtt_timing_reset": [],
         "qtt_timing_read": [I32, I32, PI64, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(D)],
+        "qtt_timing_read_shape": [I32, I32, PI64, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(D)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -80,7 +81,7 @@ EXPORTED = ["qtt_matrix_load", "qtt_matrix_free", "qtt_matrix_info", "qtt_worksp
             "qtt_apply", "qtt_apply_batched", "qtt_autotune", "qtt_solve_workspace_bytes",
             "qtt_solve", "qtt_status_string", "qtt_last_error", "qtt_set_shape", "qtt_list_shapes",
             "qtt_timing_enable",
-            "qtt_timing_reset", "qtt_timing_read"]
+            "qtt_timing_reset", "qtt_timing_read", "qtt_timing_read_shape"]
 
 
 def lib():
@@ -296,4 +297,12 @@ def qtt_timing_read(compute, position):
     ms, fl, by = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
     _check(_lib.qtt_timing_read(_dtype(compute), int(position), ctypes.byref(n), ctypes.byref(ms),
                                 ctypes.byref(fl), ctypes.byref(by)))
+    return {"launches": n.value, "ms": ms.value, "flops": fl.value, "bytes": by.value}
+
+
+def qtt_timing_read_shape(compute, shape):
+    n = ctypes.c_int64()
+    ms, fl, by = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _check(_lib.qtt_timing_read_shape(_dtype(compute), int(shape), ctypes.byref(n), ctypes.byref(ms),
+                                      ctypes.byref(fl), ctypes.byref(by)))
     return {"launches": n.value, "ms": ms.value, "flops": fl.value, "bytes": by.value}
