@@ -1321,6 +1321,9 @@ __global__ void __launch_bounds__(256) core_step_bf16_resident_kernel(const Step
 
 // ---------------------------------------------------------------------------
 // Same computation with the input tiles moved by direct global-to-LDS loads
+// (tiles of 16 TCB columns: TCB = 4 uses 128 KB of LDS, one workgroup per CU;
+// TCB = 2 uses 64 KB, two per CU, so one workgroup's copies and stores
+// overlap the other's matrix work)
 // (global_load_lds_dwordx4): one instruction fills one 1 KB fragment, lane l
 // fetching the 16 bytes of fragment slot l (column l mod 16, contraction
 // indices 8 (l div 16) .. +7 of the step).  Three input stages let two tiles
@@ -1350,13 +1353,14 @@ __device__ inline void wait_vmcnt_dispatch(int n) {
   }
 }
 
-__global__ void __launch_bounds__(256) core_step_bf16_dma_kernel(const StepArgs args) {
+template <int TCB>
+__global__ void __launch_bounds__(256, TCB == 2 ? 2 : 1) core_step_bf16_dma_kernel(const StepArgs args) {
   (void)args;
   const StepArgs& a = kernarg<StepArgs>();
   using MF = Mfma<bf16_tag>;
-  constexpr int WR = 4, TCB = 4, TC = 64, KS = 8, NT = 256;
-  constexpr int IN_ELEMS = TCB * KS * 64 * 8;      // 32 KB per stage
-  constexpr int OUT_ELEMS = TC * 256;              // 32 KB
+  constexpr int WR = 4, TC = 16 * TCB, KS = 8, NT = 256;
+  constexpr int IN_ELEMS = TCB * KS * 64 * 8;      // 8 KB per column block and stage
+  constexpr int OUT_ELEMS = TC * 256;
   constexpr int PER_WAVE = TCB * KS / 4;           // fragment loads per wave per tile (max)
   __shared__ __attribute__((aligned(1024))) uint16_t lin0[IN_ELEMS];
   __shared__ __attribute__((aligned(1024))) uint16_t lin1[IN_ELEMS];
@@ -1366,7 +1370,7 @@ __global__ void __launch_bounds__(256) core_step_bf16_dma_kernel(const StepArgs 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int Ks = a.Ksteps;                         // host guarantees Ks == KS
+  const int Ks = a.Ksteps;                         // host guarantees Ks <= KS
   const uint16_t* __restrict__ Mf = reinterpret_cast<const uint16_t*>(a.M);
   const uint16_t* __restrict__ in = reinterpret_cast<const uint16_t*>(a.in);
   uint16_t* __restrict__ out = reinterpret_cast<uint16_t*>(a.out);
@@ -1378,7 +1382,8 @@ __global__ void __launch_bounds__(256) core_step_bf16_dma_kernel(const StepArgs 
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
       mf[i][s] = MF::zero_frag();
-      if (rbg < a.nRB) mf[i][s] = MF::load_frag(Mf + (((int64_t)rbg * Ks + s) * 64 + lane) * 8);
+      // steps past Ks keep zero core values: their input slots hold clamped data
+      if (rbg < a.nRB && s < Ks) mf[i][s] = MF::load_frag(Mf + (((int64_t)rbg * Ks + s) * 64 + lane) * 8);
     }
   }
   wait_vmcnt<0>();
@@ -1411,10 +1416,20 @@ __global__ void __launch_bounds__(256) core_step_bf16_dma_kernel(const StepArgs 
   // operations complete in issue order, so dma(t) has landed once at most the
   // operations issued after it are outstanding: dma(t+1), dma(t+2) (those that
   // exist) and the stores of tiles t-2 and t-1.  Every thread issues the same
-  // number of stores per tile (R_out / 32; the host requires R_out % 32 == 0).
+  // number of stores per tile (R_out TC / 2048; the host requires R_out to be a
+  // multiple of 32 for TCB = 4 and of 64 for TCB = 2).  Cores with fewer than
+  // KS steps (K_in < 256) copy clamped indices into the unused slots, so the
+  // count per wave stays PER_WAVE.
   const int rows_out = a.R_out;
   const int r = a.r_out;
-  const int spt = rows_out / 32;
+  const int spt = rows_out * TC / (8 * NT);        // 16-byte stores per thread and tile
+  // Output staging is swizzled in 16-byte slots: slot v of an i_k run (slots
+  // per column spq = r / 8) is stored at v ^ ((column >> 1) & (spq - 1)), so
+  // the 8-byte writes of 16 consecutive columns spread over the banks.  Only
+  // for spq in {2, 4, 8}; otherwise unswizzled.
+  const int spq = r / 8;
+  const int swm = (r % 8 == 0 && (spq == 2 || spq == 4 || spq == 8)) ? spq - 1 : 0;
+  auto swz = [&](int e, int q) { return ((((e >> 3) ^ ((q >> 1) & swm)) << 3) | (e & 7)); };
   dma(0, lin0);
   if (my > 1) dma(1, lin1);
   if (my > 2) dma(2, lin2);
@@ -1450,14 +1465,14 @@ __global__ void __launch_bounds__(256) core_step_bf16_dma_kernel(const StepArgs 
           const uint32_t lo = (uint32_t)MF::from_acc(acc[i][j][0]) | ((uint32_t)MF::from_acc(acc[i][j][1]) << 16);
           const uint32_t hi = (uint32_t)MF::from_acc(acc[i][j][2]) | ((uint32_t)MF::from_acc(acc[i][j][3]) << 16);
           typedef uint32_t v2u __attribute__((ext_vector_type(2)));
-          *reinterpret_cast<v2u*>(&lout[ir * (r * TC) + q * r + ar]) = v2u{lo, hi};
+          *reinterpret_cast<v2u*>(&lout[ir * (r * TC) + swz(q * r + ar, q)]) = v2u{lo, hi};
         } else {
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int row = row0 + v;
             if (row < rows_out) {
               const int ir = row / r, ar = row - ir * r;
-              lout[ir * (r * TC) + q * r + ar] = MF::from_acc(acc[i][j][v]);
+              lout[ir * (r * TC) + (swm ? swz(q * r + ar, q) : q * r + ar)] = MF::from_acc(acc[i][j][v]);
             }
           }
         }
@@ -1474,8 +1489,9 @@ __global__ void __launch_bounds__(256) core_step_bf16_dma_kernel(const StepArgs 
       for (int idx = tid; idx < m * per_i; idx += NT) {
         const int ir = idx / per_i;
         const int v = idx - ir * per_i;
+        const int vp = v ^ (((v / (spq > 0 ? spq : 1)) >> 1) & swm);
         reinterpret_cast<v4u*>(dst + (int64_t)r * a.C * ir)[v] =
-            reinterpret_cast<const v4u*>(lout + ir * (r * TC))[v];
+            reinterpret_cast<const v4u*>(lout + ir * (r * TC))[vp];
       }
     }
     // stage t % 3 was last read by this tile's compute, finished by every

@@ -339,13 +339,27 @@ static KernelCfg* bf16_resident_cfg() {
   return &k;
 }
 
-// BF16 interior kernel fed by direct global-to-LDS loads (shape id 31).
+// BF16 interior kernel fed by direct global-to-LDS loads: 64-column tiles
+// (shape id 31, one workgroup per CU) or 32-column tiles (id 33, two).
 static const int kBf16Dma = 31;
+static const int kBf16Dma32 = 33;
 static KernelCfg* bf16_dma_cfg() {
   static KernelCfg k = [] {
     KernelCfg c = *bf16_resident_cfg();
     c.id = kBf16Dma;
-    c.fn = reinterpret_cast<const void*>(&core_step_bf16_dma_kernel);
+    c.fn = reinterpret_cast<const void*>(&core_step_bf16_dma_kernel<4>);
+    c.occ = 0;
+    c.kind = -1;
+    return c;
+  }();
+  return &k;
+}
+static KernelCfg* bf16_dma32_cfg() {
+  static KernelCfg k = [] {
+    KernelCfg c = *bf16_resident_cfg();
+    c.id = kBf16Dma32;
+    c.TC = 32;
+    c.fn = reinterpret_cast<const void*>(&core_step_bf16_dma_kernel<2>);
     c.occ = 0;
     c.kind = -1;
     return c;
@@ -481,7 +495,7 @@ static int heuristic_shape(int R_out, int K_in, int dt) {
   }
   if (K_in <= 16) return dt == 0 ? 6 : 26;       // first core (r_0 = 1)
   if (R_out <= 64) return kGenericShape;
-  return dt == 2 ? kBf16Dma : 21;                // interior cores (DMA falls back to resident)
+  return dt == 2 ? kBf16Dma32 : 21;              // interior cores (falls back to 31, then resident)
 }
 
 // ---------------------------------------------------------------------------
@@ -676,7 +690,8 @@ static qtt_status_t launch_step(const qtt_matrix_s* A, int k, int dt, int64_t nr
   const bool resident_ok = dt == 2 && !first && !last && c.R_out <= 256 && c.K_in <= 256 &&
                            c.K_in % 8 == 0 && c.C % 64 == 0 && vec &&
                            reinterpret_cast<uintptr_t>(out_packed) % 16 == 0;
-  const bool dma_ok = resident_ok && c.Ksteps[2] == 8 && c.R_out % 32 == 0;
+  const bool dma_ok = resident_ok && c.Ksteps[2] <= 8 && c.R_out % 32 == 0;
+  if (shape == kBf16Dma32 && !(dma_ok && c.R_out % 64 == 0)) shape = kBf16Dma;
   if (shape == kBf16Dma && !dma_ok) shape = kBf16Resident;
   const bool f64dma_ok = dt == 0 && !first && !last && c.R_out <= 256 && c.R_out % 64 == 0 &&
                          c.C % 64 == 0 && c.Ksteps[0] >= 4;
@@ -690,6 +705,7 @@ static qtt_status_t launch_step(const qtt_matrix_s* A, int k, int dt, int64_t nr
   if (shape == kBf16Resident && !resident_ok) shape = heuristic_shape(c.R_out, c.K_in, 1);
   KernelCfg* kc = (shape == kF64Dma) ? f64_dma_cfg()
                   : (shape == kBf16Dma) ? bf16_dma_cfg()
+                  : (shape == kBf16Dma32) ? bf16_dma32_cfg()
                   : (shape == kBf16Resident) ? bf16_resident_cfg()
                   : vec ? find_cfg(dt, in_f64, true, shape) : find_cfg(dt, in_f64, false, kGenericShape);
   // the streamed 4x4x4 kernels take whole chunks only
@@ -1225,6 +1241,7 @@ qtt_status_t qtt_autotune(qtt_matrix_t A, qtt_dtype_t compute, int64_t nrhs, con
     if (dt == 2 && k > 0 && k < A->d - 1) {
       ids.push_back(kBf16Resident);
       ids.push_back(kBf16Dma);
+      ids.push_back(kBf16Dma32);
     }
     if (dt == 0 && k > 0 && k < A->d - 1) ids.push_back(kF64Dma);
     if (dt == 0)
@@ -1318,7 +1335,7 @@ qtt_status_t qtt_list_shapes(qtt_dtype_t compute, int32_t* ids, int32_t cap, int
   const int dt = dt_index(compute);
   if (dt < 0 || !count || (cap > 0 && !ids)) return fail(QTT_ERR_INVALID_ARG, "bad arguments");
   std::vector<int> v = shape_ids(dt, dt == 0);
-  if (dt == 2) { v.push_back(kBf16Resident); v.push_back(kBf16Dma); }
+  if (dt == 2) { v.push_back(kBf16Resident); v.push_back(kBf16Dma); v.push_back(kBf16Dma32); }
   if (dt == 0) {
     v.push_back(kF64Dma);
     for (auto& vc : valu_registry()) v.push_back(vc.id);
