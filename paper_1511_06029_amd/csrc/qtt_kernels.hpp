@@ -1996,6 +1996,147 @@ core_step_f64ql_kernel(const StepArgs args) {
 }
 
 // ---------------------------------------------------------------------------
+// First core step with a short contraction (K_in = n_1 <= 16) on the vector
+// ALUs, any compute dtype.
+//
+// The first core's product is R_out x K_in with K_in = n_1 (8 for octree
+// digits): too short a contraction to fill a matrix instruction (the BF16
+// one contracts over 32).  The step is bound by writing R_out values per
+// column.  Here:
+//  * the core, decoded once per workgroup from the dtype's fragment buffer,
+//    sits in LDS as Ms[k][row] in the accumulation type (so the values are
+//    exactly those the matrix-core kernels use);
+//  * a tile of TQ consecutive columns of one vector is read with 16-byte
+//    loads into registers a tile ahead, then into LDS (FP64 input, rounded
+//    to the compute type as the matrix-core kernels do);
+//  * thread t owns column t mod TQ and, in groups of 4 consecutive rows,
+//    the rows assigned to its row group; the core rows are LDS broadcasts;
+//  * results are staged in LDS laid out as in memory (for each i_1, the run
+//    a_1 + r_1 q of r_1 TQ values is contiguous) and leave as 16-byte stores.
+// Requirements checked by the host: first core, not the last, K_in <= 16,
+// R_out <= 256, r_1 % 4 == 0, C_1 % TQ == 0, FP64 input columns 16-byte
+// aligned with an even K_in.
+// ---------------------------------------------------------------------------
+template <class Tc> struct SmallK;
+template <> struct SmallK<double> {
+  using acc = double;
+  using out = double;
+  static constexpr int KS = 4, E = 1, TQ = 8;
+  __device__ static acc load_core(const void* M, int64_t i) { return reinterpret_cast<const double*>(M)[i]; }
+  __device__ static acc round_in(double x) { return x; }
+  __device__ static out to_out(acc v) { return v; }
+};
+template <> struct SmallK<float> {
+  using acc = float;
+  using out = float;
+  static constexpr int KS = 4, E = 1, TQ = 16;
+  __device__ static acc load_core(const void* M, int64_t i) { return reinterpret_cast<const float*>(M)[i]; }
+  __device__ static acc round_in(double x) { return (float)x; }
+  __device__ static out to_out(acc v) { return v; }
+};
+template <> struct SmallK<bf16_tag> {
+  using acc = float;
+  using out = uint16_t;
+  static constexpr int KS = 32, E = 8, TQ = 32;
+  __device__ static float from_bits(uint16_t b) { return __builtin_bit_cast(float, (uint32_t)b << 16); }
+  __device__ static acc load_core(const void* M, int64_t i) { return from_bits(reinterpret_cast<const uint16_t*>(M)[i]); }
+  __device__ static acc round_in(double x) { return from_bits(f32_to_bf16_rne((float)x)); }
+  __device__ static out to_out(acc v) { return f32_to_bf16_rne(v); }
+};
+
+template <class Tc>
+__global__ void __launch_bounds__(256) core_step_smallk_kernel(const StepArgs args) {
+  (void)args;
+  const StepArgs& a = kernarg<StepArgs>();
+  using S = SmallK<Tc>;
+  using acc_t = typename S::acc;
+  using out_t = typename S::out;
+  constexpr int NT = 256, TQ = S::TQ, MAXK = 16, MAXR = 256;
+  constexpr int RG = NT / TQ;                       // row groups
+  constexpr int NLD = (TQ * MAXK / 2 + NT - 1) / NT;  // 16-byte input loads per thread (max)
+  __shared__ __attribute__((aligned(16))) acc_t Ms[MAXK * MAXR];
+  __shared__ __attribute__((aligned(16))) double xs[TQ * MAXK];
+  __shared__ __attribute__((aligned(16))) out_t st[MAXR * TQ];
+
+  const int tid = threadIdx.x;
+  const int K = a.K_in, R = a.R_out, r = a.r_out;
+  const int Ks = a.Ksteps;
+  // core: Ms[k * R + row] = M(row, k), decoded from fragment order
+  for (int idx = tid; idx < K * R; idx += NT) {
+    const int k = idx / R, row = idx - k * R;
+    const int l = (row & 15) + 16 * ((k % S::KS) / S::E);
+    Ms[idx] = S::load_core(a.M, (((int64_t)(row >> 4) * Ks + k / S::KS) * 64 + l) * S::E + k % S::E);
+  }
+  const int64_t ntiles = a.ncols / TQ;
+  const int ql = tid % TQ, rg = tid / TQ;
+  const int nquad = R / 4;                          // groups of 4 consecutive rows
+  const int nvec = TQ * K / 2;
+  // the next tile's input is loaded into registers while this tile computes
+  v4u pre[NLD];
+  auto gload = [&](int64_t tile) {
+    const int64_t col0 = tile * TQ;
+    const int64_t rhs = col0 / a.C;
+    const int64_t q0 = col0 - rhs * a.C;
+    const Segment& sg = a.seg[find_seg(a, rhs)];
+    const v4u* src = reinterpret_cast<const v4u*>(reinterpret_cast<const double*>(sg.x) +
+                                                  (rhs - sg.rhs_begin) * sg.ldx + q0 * K);
+#pragma unroll
+    for (int j = 0; j < NLD; ++j) {
+      const int idx = tid + j * NT;
+      if (idx < nvec) pre[j] = src[idx];
+    }
+  };
+  if ((int64_t)blockIdx.x < ntiles) gload(blockIdx.x);
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int64_t col0 = tile * TQ;
+    const int64_t rhs = col0 / a.C;
+    const int64_t q0 = col0 - rhs * a.C;
+    __syncthreads();                                // previous tile's xs and staging are free
+#pragma unroll
+    for (int j = 0; j < NLD; ++j) {
+      const int idx = tid + j * NT;
+      if (idx < nvec) reinterpret_cast<v4u*>(xs)[idx] = pre[j];
+    }
+    __syncthreads();
+    if (tile + gridDim.x < ntiles) gload(tile + gridDim.x);
+    acc_t x[MAXK];
+#pragma unroll
+    for (int k = 0; k < MAXK; ++k) x[k] = (k < K) ? S::round_in(xs[ql * K + k]) : acc_t(0);
+    for (int g = rg; g < nquad; g += RG) {
+      const int row0 = 4 * g;
+      acc_t v0 = 0, v1 = 0, v2 = 0, v3 = 0;
+#pragma unroll
+      for (int k = 0; k < MAXK; ++k) {
+        if (k < K) {
+          const acc_t* m = &Ms[k * R + row0];
+          v0 = fma(m[0], x[k], v0);
+          v1 = fma(m[1], x[k], v1);
+          v2 = fma(m[2], x[k], v2);
+          v3 = fma(m[3], x[k], v3);
+        }
+      }
+      // rows row0..row0+3 share i_1 (r_1 % 4 == 0)
+      const int ir = row0 / r, ar = row0 - ir * r;
+      out_t* o = &st[ir * (r * TQ) + ql * r + ar];
+      o[0] = S::to_out(v0);
+      o[1] = S::to_out(v1);
+      o[2] = S::to_out(v2);
+      o[3] = S::to_out(v3);
+    }
+    __syncthreads();
+    // for each i_1 a contiguous run of r TQ values at a_1 + r_1 (q + C_1 i_1)
+    out_t* dst = reinterpret_cast<out_t*>(a.out) + rhs * a.out_stride + (int64_t)r * q0;
+    const int m = R / r;
+    constexpr int VE = 16 / (int)sizeof(out_t);
+    const int per_i = r * TQ / VE;
+    for (int idx = tid; idx < m * per_i; idx += NT) {
+      const int ir = idx / per_i, v = idx - ir * per_i;
+      reinterpret_cast<v4u*>(dst + (int64_t)r * a.C * ir)[v] = reinterpret_cast<const v4u*>(st + ir * (r * TQ))[v];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // column norms: ||R_c||_2 for every column, two deterministic passes (the
 // summation order depends only on the column length, never on the batch).
 // ---------------------------------------------------------------------------

@@ -165,6 +165,7 @@ static KernelCfg make_cfg(int dt, bool in_f64, int id) {
   X(73, 4, 8, 8, 2)          \
   X(74, 2, 8, 32, 2)
 static const int kGenericShape = 6;
+static const int kSmallK = 34;   // first core with a short contraction (vector ALUs)
 
 template <class Tc, class Tin, int KC1, int KC2>
 static void add_family(std::vector<KernelCfg>& v, int dt, bool in_f64) {
@@ -367,6 +368,33 @@ static KernelCfg* bf16_dma32_cfg() {
   return &k;
 }
 
+// First core with a short contraction on the vector ALUs (shape id 34), one
+// instantiation per compute dtype.
+static KernelCfg* smallk_cfg(int dt) {
+  static KernelCfg k[3] = {};
+  static std::once_flag once;
+  std::call_once(once, [] {
+    const void* fns[3] = {reinterpret_cast<const void*>(&core_step_smallk_kernel<double>),
+                          reinterpret_cast<const void*>(&core_step_smallk_kernel<float>),
+                          reinterpret_cast<const void*>(&core_step_smallk_kernel<bf16_tag>)};
+    const int tq[3] = {SmallK<double>::TQ, SmallK<float>::TQ, SmallK<bf16_tag>::TQ};
+    for (int t = 0; t < 3; ++t) {
+      k[t].dt = t;
+      k[t].in_f64 = true;
+      k[t].vec = true;
+      k[t].TR = 256;
+      k[t].TC = tq[t];
+      k[t].KC = 16;
+      k[t].NT = 256;
+      k[t].id = kSmallK;
+      k[t].fn = fns[t];
+      k[t].occ = 0;
+      k[t].kind = -1;
+    }
+  });
+  return &k[dt];
+}
+
 // FP64 interior kernel fed by direct global-to-LDS loads (shape id 32).
 static const int kF64Dma = 32;
 static KernelCfg* f64_dma_cfg() {
@@ -491,9 +519,9 @@ static int heuristic_shape(int R_out, int K_in, int dt) {
   if (R_out <= 16) return dt == 0 ? 47 : 2;      // last core (r_d = 1)
   if (dt == 0 && R_out > 64) {                   // FP64: 4x4x4 matrix instruction
     if (K_in <= 16) return 67;                   // short chunks for the first core
-    return R_out <= 192 ? 63 : 60;
+    return R_out <= 192 ? 63 : 75;
   }
-  if (K_in <= 16) return dt == 0 ? 6 : 26;       // first core (r_0 = 1)
+  if (K_in <= 16) return dt == 0 ? 6 : kSmallK; // first core (r_0 = 1; falls back to 26)
   if (R_out <= 64) return kGenericShape;
   return dt == 2 ? kBf16Dma32 : 21;              // interior cores (falls back to 31, then resident)
 }
@@ -703,7 +731,13 @@ static qtt_status_t launch_step(const qtt_matrix_s* A, int k, int dt, int64_t nr
   // the LDS-fed ones copy step pairs
   if (shape >= 70 && shape < 75 && c.Ksteps[dt] % 2 != 0) shape = 60;
   if (shape == kBf16Resident && !resident_ok) shape = heuristic_shape(c.R_out, c.K_in, 1);
-  KernelCfg* kc = (shape == kF64Dma) ? f64_dma_cfg()
+  const int tq = smallk_cfg(dt)->TC;
+  const bool smallk_ok = first && !last && vec && c.K_in <= 16 && c.K_in % 2 == 0 && c.R_out <= 256 &&
+                         c.r_out % 4 == 0 && c.C % tq == 0 && (c.r_out * tq * kElemBytes[dt]) % 16 == 0 &&
+                         reinterpret_cast<uintptr_t>(out_packed) % 16 == 0;
+  if (shape == kSmallK && !smallk_ok) shape = (dt == 0) ? 67 : 26;   // first-core matrix-core kernels
+  KernelCfg* kc = (shape == kSmallK) ? smallk_cfg(dt)
+                  : (shape == kF64Dma) ? f64_dma_cfg()
                   : (shape == kBf16Dma) ? bf16_dma_cfg()
                   : (shape == kBf16Dma32) ? bf16_dma32_cfg()
                   : (shape == kBf16Resident) ? bf16_resident_cfg()
@@ -1244,6 +1278,7 @@ qtt_status_t qtt_autotune(qtt_matrix_t A, qtt_dtype_t compute, int64_t nrhs, con
       ids.push_back(kBf16Dma32);
     }
     if (dt == 0 && k > 0 && k < A->d - 1) ids.push_back(kF64Dma);
+    if (k == 0 && A->d > 1) ids.push_back(kSmallK);
     if (dt == 0)
       for (auto& vc : valu_registry())
         if (vc.G == 1 || c.K_in % vc.G == 0) ids.push_back(vc.id);
@@ -1335,6 +1370,7 @@ qtt_status_t qtt_list_shapes(qtt_dtype_t compute, int32_t* ids, int32_t cap, int
   const int dt = dt_index(compute);
   if (dt < 0 || !count || (cap > 0 && !ids)) return fail(QTT_ERR_INVALID_ARG, "bad arguments");
   std::vector<int> v = shape_ids(dt, dt == 0);
+  v.push_back(kSmallK);
   if (dt == 2) { v.push_back(kBf16Resident); v.push_back(kBf16Dma); v.push_back(kBf16Dma32); }
   if (dt == 0) {
     v.push_back(kF64Dma);
