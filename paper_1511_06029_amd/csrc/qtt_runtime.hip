@@ -1052,7 +1052,12 @@ qtt_status_t qtt_matrix_load(int32_t d, const int64_t* ranks, const int64_t* m, 
     for (int t = 0; t < 3; ++t) {
       if (!(dtypes & (1u << t))) continue;
       const int KS = kKstep[t], E = kFragE[t];
-      const int Ksteps = (c.K_in + KS - 1) / KS;
+      int Ksteps = (c.K_in + KS - 1) / KS;
+      // FP64 cores of more than 8 steps get zero steps up to a multiple of 8,
+      // the chunk of the streamed 4x4x4 kernels (so any rank can use them;
+      // every kernel reads input indices past K_in as zeros or as finite data
+      // multiplied by these zero core values)
+      if (t == 0 && Ksteps > 8) Ksteps = (Ksteps + 7) / 8 * 8;
       c.Ksteps[t] = Ksteps;
       // row blocks padded with zeros so that every tile height of the
       // registry covers a whole number of tiles: kernels may then read the
