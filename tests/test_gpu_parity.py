@@ -333,3 +333,36 @@ def test_rank_slowest_fp64_sweep(Q):
             B.free()
     A.free()
     Ai.free()
+
+
+def test_timing_by_configuration(Q):
+    """Launch timing summed by kernel configuration partitions the sums by
+    core position: same launches, same flops, and the default configurations
+    are the ones recorded (4x4x4 FP64 kernels on cores of more than 64 rows,
+    the first core's short-contraction kernel for BF16)."""
+    ranks = [1, 24, 32, 32, 24, 1]
+    cores = I.gaussian_qtt(ranks, [8] * 5, seed=81)
+    X = I.rhs(8 ** 5, 2, seed=82)
+    A = Q.qtt_matrix_load(cores, dtypes=("fp64", "bf16"))
+    Xd = Q.to_block(X)
+    for dt in ("fp64", "bf16"):
+        Q.qtt_apply(A, dt, Xd)          # first call: direct launches, graph capture
+        torch.cuda.synchronize()
+        Q.qtt_timing_reset()
+        Q.qtt_timing_enable(True)
+        Q.qtt_apply(A, dt, Xd)
+        torch.cuda.synchronize()
+        Q.qtt_timing_enable(False)
+        by_pos = [Q.qtt_timing_read(dt, p) for p in range(4)]
+        by_shape = {sh: Q.qtt_timing_read_shape(dt, sh) for sh in Q.qtt_list_shapes(dt)}
+        Q.qtt_timing_reset()
+        used = {sh: r for sh, r in by_shape.items() if r["launches"]}
+        assert sum(r["launches"] for r in by_pos) == sum(r["launches"] for r in used.values()) == len(ranks) - 1
+        assert np.isclose(sum(r["flops"] for r in by_pos), sum(r["flops"] for r in used.values()))
+        assert all(r["ms"] > 0 for r in used.values())
+        if dt == "fp64":
+            assert set(used) >= {67, 63, 75}, used.keys()    # first core, 192-row and 256-row cores
+        else:
+            assert 34 in used, used.keys()
+    assert Q.qtt_timing_read_shape("fp64", 9999)["launches"] == 0
+    A.free()
