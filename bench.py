@@ -130,6 +130,8 @@ def main():
             ks = {(dt, sh): Q.qtt_timing_read_shape(dt, sh) for dt in ("fp64", v) for sh in Q.qtt_list_shapes(dt)}
             Q.qtt_timing_reset()
         elapsed = t1 - t0
+        if v == variants[0]:
+            sigma0 = Sig[:, 0].cpu().numpy().copy()   # the headline solve's first solution
         iters = max(c[0] for c in infos[-1])
         worst = max(c[1] for inf in infos for c in inf)
         results[v] = {"rhs_per_s": K * args.steps / elapsed, "ms_per_step": 1e3 * elapsed / args.steps,
@@ -179,7 +181,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(Ac, Aic, F_h[:, :1], r0["passes"])
+        cpu = cpu_baseline(Ac, Aic, F_h[:, :1], r0["passes"], sigma0, head)
 
     line = {
         "metric": "QTT-inverse RHS/s at 1e-8 rel residual (refined solve), L=7 r=32, vs plain FP64",
@@ -287,10 +289,12 @@ def batched_run(Q, torch):
             "workspace_gb": round(ws_bytes / 2 ** 30, 1), "dtype": "fp32"}
 
 
-def cpu_baseline(Ac, Aic, f, passes):
+def cpu_baseline(Ac, Aic, f, passes, sigma0, head):
     """Time the FP64 oracle on a bounded sample: one refinement pass (one Ainv
     apply and one A apply) for one right-hand side, scaled to RHS/s with the
-    number of passes the GPU solve needed."""
+    number of passes the GPU solve needed.  Also checks the headline solve's
+    first solution against the oracle: its FP64 residual ||f - A sigma|| / ||f||
+    computed by the oracle's A apply."""
     from oracle import qtt_oracle as O
     threads = None
     try:
@@ -304,11 +308,16 @@ def cpu_baseline(Ac, Aic, f, passes):
     dt = time.perf_counter() - t0
     del r
     per_rhs = dt * passes
+    f0 = f[:, 0]
+    res = f0 - O.qtt_apply_alg2(Ac, sigma0)
+    oracle_rel = float(np.linalg.norm(res) / np.linalg.norm(f0))
     return {"value": round(1.0 / per_rhs, 6), "unit": "RHS/s", "cores": threads or os.cpu_count(),
             "kind": "oracle",
             "sample": f"one refinement pass (Ainv apply + A apply, numpy FP64 Algorithm 2) on 1 RHS at L=7 "
                       f"took {dt:.2f} s; scaled by the {passes} passes the solve needs",
-            "host_cpus": os.cpu_count()}
+            "host_cpus": os.cpu_count(),
+            "oracle_check": {"rhs": 0, "inverse_dtype": head, "rel_residual": oracle_rel,
+                             "what": "||f - A sigma|| / ||f|| of the GPU solution, A applied by the FP64 oracle"}}
 
 
 if __name__ == "__main__":

@@ -727,7 +727,7 @@ static qtt_status_t launch_step(const qtt_matrix_s* A, int k, int dt, int64_t nr
   // the 4x4x4 kernels address the fragment array with 32-bit buffer offsets
   const int64_t m_bytes =
       (int64_t)padded_row_blocks(c.nRB) * c.Ksteps[dt] * 64 * kFragE[dt] * kElemBytes[dt];
-  if (((shape >= 60 && shape < 70) || (shape >= 75 && shape < 80)) && m_bytes > INT32_MAX) shape = 21;
+
   // the LDS-fed ones copy step pairs
   if (shape >= 70 && shape < 75 && c.Ksteps[dt] % 2 != 0) shape = 60;
   if (shape == kBf16Resident && !resident_ok) shape = heuristic_shape(c.R_out, c.K_in, 1);
@@ -742,8 +742,10 @@ static qtt_status_t launch_step(const qtt_matrix_s* A, int k, int dt, int64_t nr
                   : (shape == kBf16Dma32) ? bf16_dma32_cfg()
                   : (shape == kBf16Resident) ? bf16_resident_cfg()
                   : vec ? find_cfg(dt, in_f64, true, shape) : find_cfg(dt, in_f64, false, kGenericShape);
-  // the streamed 4x4x4 kernels take whole chunks only
-  if (kc && kc->kind == 3 && c.Ksteps[dt] % (kc->KC / 4) != 0) kc = find_cfg(dt, in_f64, true, 21);
+  // the streamed 4x4x4 kernels take whole chunks only and address the
+  // fragment array with 32-bit buffer offsets
+  if (kc && kc->kind == 3 && (c.Ksteps[dt] % (kc->KC / 4) != 0 || m_bytes > INT32_MAX))
+    kc = find_cfg(dt, in_f64, true, 21);
   if (!kc) return fail(QTT_ERR_DEVICE, "no kernel for dtype %d shape %d", dt, shape);
 
   StepArgs a;
