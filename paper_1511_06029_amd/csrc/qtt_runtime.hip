@@ -476,6 +476,7 @@ struct qtt_matrix_s {
   int64_t max_inter = 0;  // largest y_k (k < d) per vector, elements
   bool fp64_t = false;    // FP64 sweeps in the rank-slowest layout on the vector ALUs
   bool fp64_t_ok = false; // every mode size is 8, so the mode is available
+  bool fp64_pair = true;  // FP64 sweeps fuse interior core pairs where the pair kernel applies
   // captured sweeps: a sweep with the same dtype, vectors, pointers, workspace
   // and alpha replays its graph instead of launching d kernels
   struct Graph {
@@ -811,6 +812,66 @@ static int64_t wave_capacity(const qtt_matrix_s* A, int dt, size_t ws_bytes) {
   return w;
 }
 
+// Fused FP64 pair (core k, core k + 1), see core_pair_f64q_kernel.
+static const int kPairShape = 90;   // configuration id reported by the launch timing
+static int64_t frag_bytes(const CoreDev& c, int dt) {
+  return (int64_t)padded_row_blocks(c.nRB) * c.Ksteps[dt] * 64 * kFragE[dt] * kElemBytes[dt];
+}
+static bool pair_ok(const qtt_matrix_s* A, int dt, int k) {
+  if (dt != 0 || !A->fp64_pair || k < 1 || k + 1 > A->d - 2) return false;
+  const CoreDev& x = A->core[k];
+  const CoreDev& y = A->core[k + 1];
+  return x.r_out == 32 && x.m == 8 && y.n == 8 && x.R_out == 256 && y.K_in == 256 && y.R_out <= 256 &&
+         x.Ksteps[0] % 8 == 0 && y.Ksteps[0] == 64 && x.C % 32 == 0 && x.C == y.C && x.K_in % 2 == 0 &&
+         frag_bytes(x, 0) <= INT32_MAX && frag_bytes(y, 0) <= INT32_MAX;
+}
+static qtt_status_t launch_pair(const qtt_matrix_s* A, int k, int64_t nrhs, const void* in, void* out,
+                                hipStream_t st) {
+  const CoreDev& x = A->core[k];
+  const CoreDev& y = A->core[k + 1];
+  PairArgs a;
+  memset(&a, 0, sizeof(a));
+  a.MA = x.frag[0];
+  a.MB = y.frag[0];
+  a.in = static_cast<const double*>(in);
+  a.out = static_cast<double*>(out);
+  a.in_stride = x.C * x.K_in;
+  a.out_stride = y.out_len;
+  a.C = x.C;
+  a.ncols = x.C * nrhs;
+  a.n_tiles = a.ncols / 32;
+  a.KsA = x.Ksteps[0];
+  a.KsB = y.Ksteps[0];
+  a.K_inA = x.K_in;
+  a.R_outB = y.R_out;
+  a.r_outB = y.r_out;
+  a.MA_bytes = (int32_t)frag_bytes(x, 0);
+  a.MB_bytes = (int32_t)frag_bytes(y, 0);
+  static int occ = 0;
+  const void* fn = reinterpret_cast<const void*>(&core_pair_f64q_kernel<4>);
+  const int64_t resident = (int64_t)occupancy_fn(fn, 256, &occ) * num_cus();
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(a.n_tiles, resident));
+  TimedLaunch tl;
+  const bool timed = timing_on();
+  if (timed) {
+    HIP_TRY(hipEventCreate(&tl.a));
+    HIP_TRY(hipEventCreate(&tl.b));
+    HIP_TRY(hipEventRecord(tl.a, st));
+  }
+  void* args[] = {&a};
+  HIP_TRY(hipLaunchKernel(fn, dim3(grid), dim3(256), args, 0, st));
+  if (timed) {
+    HIP_TRY(hipEventRecord(tl.b, st));
+    tl.dt = 0;
+    tl.pos = 0;
+    tl.shape = kPairShape;
+    tl.flops = 2.0 * ((double)x.R_out * x.K_in + (double)y.R_out * y.K_in) * (double)a.ncols;
+    tl.bytes = (double)a.ncols * ((double)x.K_in + y.R_out) * 8.0;
+    g_timed.push_back(tl);
+  }
+  return QTT_OK;
+}
+
 // Whether X allows the rank-slowest sweep (16-byte aligned columns).
 static bool tsweep_usable_mode_free(const qtt_matrix_s* A, const double* X, int64_t ldx) {
   (void)A;
@@ -830,12 +891,22 @@ static qtt_status_t sweep(const qtt_matrix_s* A, int dt, int64_t nrhs, const Seg
   void* buf[2] = {ws, nullptr};
   if (A->d > 1) buf[1] = static_cast<char*>(ws) + wave_buffer_bytes(A, dt, nrhs);
   const bool tsw = tsweep_usable(A, dt, segs, nseg);
-  for (int k = 0; k < A->d; ++k) {
-    const void* in = (k == 0) ? nullptr : buf[(k - 1) & 1];
-    void* out = (k == A->d - 1) ? nullptr : buf[k & 1];
+  int cur = 0;  // buffer holding the latest intermediate (core 0 writes buf[0])
+  for (int k = 0; k < A->d;) {
+    const void* in = (k == 0) ? nullptr : buf[cur];
+    if (!tsw && pair_ok(A, dt, k)) {
+      qtt_status_t s = launch_pair(A, k, nrhs, in, buf[cur ^ 1], st);
+      if (s != QTT_OK) return s;
+      cur ^= 1;
+      k += 2;
+      continue;
+    }
+    void* out = (k == A->d - 1) ? nullptr : (k == 0 ? buf[0] : buf[cur ^ 1]);
     qtt_status_t s = tsw ? launch_valut(A, k, nrhs, segs, nseg, in, out, alpha, st)
                          : launch_step(A, k, dt, nrhs, segs, nseg, in, out, alpha, st);
     if (s != QTT_OK) return s;
+    if (k > 0) cur ^= 1;
+    ++k;
   }
   return QTT_OK;
 }
@@ -1341,9 +1412,10 @@ qtt_status_t qtt_autotune(qtt_matrix_t A, qtt_dtype_t compute, int64_t nrhs, con
       }
       c.tuned_t = best_id;
     }
-    float ms_mode[2] = {0, 0};
-    for (int mode = 0; mode < 2; ++mode) {
-      A->fp64_t = (mode == 1);
+    float ms_mode[3] = {0, 0, 0};
+    for (int mode = 0; mode < 3; ++mode) {
+      A->fp64_t = (mode == 2);
+      A->fp64_pair = (mode == 1);
       for (int rep = 0; rep < 2; ++rep) {
         HIP_TRY(hipEventRecord(e0, st));
         for (int it = 0; it < 2; ++it) {
@@ -1355,10 +1427,29 @@ qtt_status_t qtt_autotune(qtt_matrix_t A, qtt_dtype_t compute, int64_t nrhs, con
       HIP_TRY(hipEventSynchronize(e1));
       HIP_TRY(hipEventElapsedTime(&ms_mode[mode], e0, e1));
     }
-    A->fp64_t = ms_mode[1] < ms_mode[0];
+    const int best = (ms_mode[1] < ms_mode[0]) ? (ms_mode[2] < ms_mode[1] ? 2 : 1) : (ms_mode[2] < ms_mode[0] ? 2 : 0);
+    A->fp64_t = (best == 2);
+    A->fp64_pair = (best == 1);
     if (tune_log())
-      fprintf(stderr, "qtt_autotune dtype 0 whole sweep: standard %.4f ms, rank-slowest %.4f ms\n",
-              ms_mode[0] / 2, ms_mode[1] / 2);
+      fprintf(stderr, "qtt_autotune dtype 0 whole sweep: standard %.4f ms, fused pairs %.4f ms, rank-slowest %.4f ms\n",
+              ms_mode[0] / 2, ms_mode[1] / 2, ms_mode[2] / 2);
+  } else if (dt == 0) {
+    // no rank-slowest mode: fused pairs against the standard sweep
+    float ms_mode[2] = {0, 0};
+    for (int mode = 0; mode < 2; ++mode) {
+      A->fp64_pair = (mode == 1);
+      for (int rep = 0; rep < 2; ++rep) {
+        HIP_TRY(hipEventRecord(e0, st));
+        for (int it = 0; it < 2; ++it) {
+          s = sweep(A, dt, w, &sg, 1, ws, 1.0, st);
+          if (s != QTT_OK) { g_timing = was_timing; return s; }
+        }
+        HIP_TRY(hipEventRecord(e1, st));
+      }
+      HIP_TRY(hipEventSynchronize(e1));
+      HIP_TRY(hipEventElapsedTime(&ms_mode[mode], e0, e1));
+    }
+    A->fp64_pair = ms_mode[1] < ms_mode[0];
   }
   g_timing = was_timing;
   drop_graphs(A);
@@ -1394,6 +1485,12 @@ qtt_status_t qtt_set_shape(qtt_matrix_t A, qtt_dtype_t compute, int32_t core, in
   int dt;
   qtt_status_t s = check_dtype(A, compute, &dt);
   if (s != QTT_OK) return s;
+  if (core == -2) {               // fused interior core pairs (FP64) on/off
+    if (dt != 0 || (shape != 0 && shape != 1)) return fail(QTT_ERR_INVALID_ARG, "core -2 takes shape 0 or 1 (FP64)");
+    A->fp64_pair = (shape == 1);
+    drop_graphs(A);
+    return QTT_OK;
+  }
   if (core == -1) {               // whole-sweep mode (FP64): rank-slowest layout on/off
     if (dt != 0 || (shape != -1 && shape != kTSweepMode)) return fail(QTT_ERR_INVALID_ARG, "core -1 takes shape %d or -1 (FP64)", kTSweepMode);
     if (shape == kTSweepMode && !A->fp64_t_ok) return fail(QTT_ERR_SHAPE, "the rank-slowest sweep needs every mode size to be 8");
@@ -1416,6 +1513,8 @@ qtt_status_t qtt_set_shape(qtt_matrix_t A, qtt_dtype_t compute, int32_t core, in
     if (!found) return fail(QTT_ERR_INVALID_ARG, "shape %d is not a configuration for dtype %d", shape, (int)compute);
   }
   A->core[core].tuned[dt] = shape;
+  // a pinned FP64 configuration is what runs: fused pairs would bypass it
+  if (dt == 0 && shape != -1) A->fp64_pair = false;
   drop_graphs(A);
   return QTT_OK;
 }

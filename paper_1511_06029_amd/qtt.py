@@ -23,6 +23,9 @@ LIB_PATH = os.path.join(_PKG, "libqtt.so")
 QTT_FP64, QTT_FP32, QTT_BF16 = 1, 2, 4
 DTYPES = {"fp64": QTT_FP64, "fp32": QTT_FP32, "bf16": QTT_BF16}
 
+# configuration id under which launches of the fused FP64 core pair are timed
+PAIR_SHAPE = 90
+
 QTT_OK = 0
 QTT_ERR_NOT_CONVERGED = 5
 QTT_ERR_NONFINITE = 6

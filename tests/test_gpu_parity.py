@@ -354,15 +354,20 @@ def test_timing_by_configuration(Q):
         torch.cuda.synchronize()
         Q.qtt_timing_enable(False)
         by_pos = [Q.qtt_timing_read(dt, p) for p in range(4)]
-        by_shape = {sh: Q.qtt_timing_read_shape(dt, sh) for sh in Q.qtt_list_shapes(dt)}
+        by_shape = {sh: Q.qtt_timing_read_shape(dt, sh) for sh in Q.qtt_list_shapes(dt) + [Q.PAIR_SHAPE]}
         Q.qtt_timing_reset()
         used = {sh: r for sh, r in by_shape.items() if r["launches"]}
-        assert sum(r["launches"] for r in by_pos) == sum(r["launches"] for r in used.values()) == len(ranks) - 1
+        assert sum(r["launches"] for r in by_pos) == sum(r["launches"] for r in used.values())
+        # 2 R_out K_in flops per column, C_k = 8^4 columns per vector, 2 vectors
+        flops = sum(2.0 * c.shape[0] * c.shape[3] * c.shape[1] * c.shape[2] for c in cores) * 8 ** 4 * 2
         assert np.isclose(sum(r["flops"] for r in by_pos), sum(r["flops"] for r in used.values()))
+        assert np.isclose(sum(r["flops"] for r in used.values()), flops)
         assert all(r["ms"] > 0 for r in used.values())
         if dt == "fp64":
-            assert set(used) >= {67, 63, 75}, used.keys()    # first core, 192-row and 256-row cores
+            # first core, the fused pair (cores 1, 2), the 192-row core, the last core
+            assert set(used) == {67, Q.PAIR_SHAPE, 63, 47}, used.keys()
+            assert sum(r["launches"] for r in used.values()) == len(ranks) - 2
         else:
-            assert 34 in used, used.keys()
+            assert 34 in used and sum(r["launches"] for r in used.values()) == len(ranks) - 1, used.keys()
     assert Q.qtt_timing_read_shape("fp64", 9999)["launches"] == 0
     A.free()
