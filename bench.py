@@ -128,7 +128,7 @@ def main():
             Q.qtt_timing_enable(False)
             kt = {(dt, pos): Q.qtt_timing_read(dt, pos) for dt in ("fp64", v) for pos in (0, 1, 2)}
             ks = {(dt, sh): Q.qtt_timing_read_shape(dt, sh)
-                  for dt in ("fp64", v) for sh in Q.qtt_list_shapes(dt) + [Q.PAIR_SHAPE]}
+                  for dt in ("fp64", v) for sh in Q.qtt_list_shapes(dt) + Q.PAIR_SHAPES}
             Q.qtt_timing_reset()
         elapsed = t1 - t0
         if v == variants[0]:

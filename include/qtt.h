@@ -189,10 +189,12 @@ qtt_status_t qtt_timing_reset(void);
 qtt_status_t qtt_timing_read(qtt_dtype_t compute, int32_t position, int64_t* launches,
                              double* milliseconds, double* flops, double* bytes);
 /* The same sums over the launches of one kernel configuration id (any core
- * position); ids as in qtt_list_shapes, plus 90 for the FP64 kernel that
- * applies two interior cores in one launch (recorded at position 0, with the
- * flops of both cores).  Launches of a configuration id that was never timed
- * give zeros. */
+ * position); ids as in qtt_list_shapes, plus 90..97 for the FP64 kernel
+ * that applies two consecutive cores k, k + 1 in one launch: 90 + 4 (k is
+ * the first core) + 2 (r_k = 32, else 24) + (R_out of core k + 1 above 192).
+ * Such a launch is recorded at the position of core k, with the flops of
+ * both cores.  Launches of a configuration id that was never timed give
+ * zeros. */
 qtt_status_t qtt_timing_read_shape(qtt_dtype_t compute, int32_t shape, int64_t* launches,
                                    double* milliseconds, double* flops, double* bytes);
 

@@ -1030,26 +1030,29 @@ core_step_f64q_kernel(const StepArgs args) {
 // Two consecutive FP64 core steps k, k + 1 in one pass over a column tile,
 // on the 4x4x4 matrix instruction: the tile's intermediate y_k stays on chip.
 //
-// For interior cores with r_k = 32 and m_k = n_{k+1} = 8.  A tile is 32
+// For cores with r_k = RA (24 or 32) and m_k = n_{k+1} = 8.  A tile is 32
 // consecutive columns q = j_{k+1} + 8 Q of b_k, four values of Q.  Step k
-// gives phi_k(a_k + 32 i_k, j_{k+1} + 8 Q) for all 256 rows.  By the row
+// gives phi_k(a_k + RA i_k, j_{k+1} + 8 Q) for all 8 RA rows.  By the row
 // separation of step k and the reshape into b_{k+1} (Algorithm 2), these are
 // exactly the 32 complete columns q' = Q + (C_k / 8) i_k of b_{k+1}, with
-// contraction index a_k + 32 j_{k+1}.  They are written to LDS in the input
-// layout of the 4x4x4 kernels (column c' = (Q - Q0) + 4 i_k, all 64 steps:
-// 80 KB, which still lets two workgroups share a CU), and step k + 1 runs
-// from there with no input traffic and no barriers.  Step k streams its input
-// like core_step_f64q_kernel (chunks of 8 steps, two stages that alias the
-// start of the LDS tile); both steps take core fragments through buffer
-// resources with a ring of PF prefetched steps.
-// Requirements checked by the host: the conditions above, K_in(k + 1) = 256
-// (64 steps), R_out(k + 1) <= 256, both step counts multiples of 8,
-// C_k % 32 == 0, both fragment arrays below 2 GiB.
+// contraction index a_k + RA j_{k+1}.  They are written to LDS in the input
+// layout of the 4x4x4 kernels (column c' = (Q - Q0) + 4 i_k, all 2 RA steps:
+// at most 80 KB, which still lets two workgroups share a CU), and step k + 1
+// runs from there with no input traffic and no barriers.  Step k streams its
+// input like core_step_f64q_kernel (chunks of KCA / 4 steps, two stages that
+// alias the start of the LDS tile), from the packed intermediate or, with
+// FIRST, from the caller's FP64 vectors through the segment table (core 0);
+// both steps take core fragments through buffer resources with a ring of
+// prefetched steps.  Step k + 1 covers 64 WRB rows.
+// Requirements checked by the host: the conditions above, R_out(k + 1) <=
+// 64 WRB, step counts multiples of the chunk (step k) and of 8 (step k + 1),
+// C_k % 32 == 0, K_in(k) even with 16-byte aligned columns, both fragment
+// arrays below 2 GiB, core k + 1 not the last.
 // ---------------------------------------------------------------------------
 struct PairArgs {
-  const void* MA;        // fragment-ordered FP64 core k (256 rows)
-  const void* MB;        // fragment-ordered FP64 core k + 1 (K_in = 256)
-  const double* in;      // packed b_k
+  const void* MA;        // fragment-ordered FP64 core k (8 RA rows)
+  const void* MB;        // fragment-ordered FP64 core k + 1 (K_in = 8 RA)
+  const double* in;      // packed b_k (not FIRST)
   double* out;           // packed y_{k+1}
   int64_t in_stride;     // elements between vectors, input
   int64_t out_stride;    // elements between vectors, output
@@ -1060,18 +1063,24 @@ struct PairArgs {
   int32_t K_inA;         // r_{k-1} n_k
   int32_t R_outB, r_outB;
   int32_t MA_bytes, MB_bytes;
+  int32_t nseg;          // FIRST: input columns come from seg[].x
+  Segment seg[kMaxSeg];
 };
 
-template <int PF>
+template <int RA, int WRB, bool FIRST, int KCA, int PF>
 __global__ void __launch_bounds__(256, 2) core_pair_f64q_kernel(const PairArgs args) {
   (void)args;
   const PairArgs& a = kernarg<PairArgs>();
-  constexpr int NT = 256, WR = 4, WQ = 8, TC = 32, SPC = 8, KC = 32, VPC = KC / 2;
+  constexpr int NT = 256, WQ = 8, TC = 32, SPB = 8;
+  constexpr int WRA = RA / 8;                      // row blocks per wave in step k (8 RA rows)
+  constexpr int SPA = KCA / 4, VPC = KCA / 2;
+  constexpr int PFA = PF < SPA ? PF : SPA;
   constexpr int NLA = (TC * VPC + NT - 1) / NT;
-  constexpr int A_ELEMS = (TC / 4) * SPC * kQGS;   // one staging stage of step k
-  constexpr int KSB = 64;                          // steps of step k + 1
+  constexpr int A_ELEMS = (TC / 4) * SPA * kQGS;   // one staging stage of step k
+  constexpr int KSB = 2 * RA;                      // steps of step k + 1 (K_in = 8 RA)
   constexpr int X_ELEMS = (TC / 4) * KSB * kQGS;   // b_{k+1} tile
-  static_assert(SPC % PF == 0, "chunk must hold whole prefetch rounds");
+  static_assert(RA == 24 || RA == 32, "rank of the fused boundary");
+  static_assert(SPA % PFA == 0 && SPB % PF == 0 && KSB % SPB == 0, "whole prefetch rounds");
   static_assert(2 * A_ELEMS <= X_ELEMS, "stages alias the tile");
   __shared__ __attribute__((aligned(16))) double lds[X_ELEMS];
 
@@ -1079,7 +1088,7 @@ __global__ void __launch_bounds__(256, 2) core_pair_f64q_kernel(const PairArgs a
   const int lane = tid & 63;
   const int wr = tid >> 6;
   const int rd = 4 * (lane & 3) + (lane >> 4);
-  const int nchA = a.KsA / SPC;
+  const int nchA = a.KsA / SPA;
   const int64_t my_tiles = (a.n_tiles > (int64_t)blockIdx.x)
                                ? (a.n_tiles - 1 - (int64_t)blockIdx.x) / gridDim.x + 1 : 0;
   if (my_tiles == 0) return;
@@ -1087,7 +1096,7 @@ __global__ void __launch_bounds__(256, 2) core_pair_f64q_kernel(const PairArgs a
   v4u sa[NLA];
   auto gload = [&](int64_t tile, int ch) {
     const int64_t col0 = tile * TC;
-    const int kc0 = ch * KC;
+    const int kc0 = ch * KCA;
 #pragma unroll
     for (int t = 0; t < NLA; ++t) {
       const int idx = tid + t * NT;
@@ -1098,7 +1107,14 @@ __global__ void __launch_bounds__(256, 2) core_pair_f64q_kernel(const PairArgs a
       if (idx < TC * VPC && g < a.ncols && kap < a.K_inA) {
         const int64_t rhs = g / a.C;
         const int64_t q = g - rhs * a.C;
-        sa[t] = *reinterpret_cast<const v4u*>(a.in + rhs * a.in_stride + q * a.K_inA + kap);
+        const double* p;
+        if constexpr (FIRST) {
+          const Segment& sg = a.seg[find_seg(a, rhs)];
+          p = sg.x + (rhs - sg.rhs_begin) * sg.ldx + q * a.K_inA;
+        } else {
+          p = a.in + rhs * a.in_stride + q * a.K_inA;
+        }
+        sa[t] = *reinterpret_cast<const v4u*>(p + kap);
       }
     }
   };
@@ -1110,7 +1126,7 @@ __global__ void __launch_bounds__(256, 2) core_pair_f64q_kernel(const PairArgs a
       if (idx < TC * VPC) {
         const int c = idx / VPC;
         const int kl0 = (idx % VPC) * 2;
-        *reinterpret_cast<v4u*>(&S[((c >> 2) * SPC + (kl0 >> 2)) * kQGS + 4 * (c & 3) + (kl0 & 3)]) = sa[t];
+        *reinterpret_cast<v4u*>(&S[((c >> 2) * SPA + (kl0 >> 2)) * kQGS + 4 * (c & 3) + (kl0 & 3)]) = sa[t];
       }
     }
   };
@@ -1118,102 +1134,105 @@ __global__ void __launch_bounds__(256, 2) core_pair_f64q_kernel(const PairArgs a
       __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(a.MA), (short)0, a.MA_bytes, 0x00020000);
   const __amdgpu_buffer_rsrc_t rB =
       __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(a.MB), (short)0, a.MB_bytes, 0x00020000);
-  int voA[WR], voB[WR];
+  int voA[WRA], voB[WRB];
 #pragma unroll
-  for (int i = 0; i < WR; ++i) {
-    voA[i] = ((wr * WR + i) * a.KsA * 64 + lane) * 8;
-    voB[i] = ((wr * WR + i) * a.KsB * 64 + lane) * 8;
-  }
-  auto loadA = [&](double (&dst)[WR], int gs) {
+  for (int i = 0; i < WRA; ++i) voA[i] = ((wr * WRA + i) * a.KsA * 64 + lane) * 8;
+#pragma unroll
+  for (int i = 0; i < WRB; ++i) voB[i] = ((wr * WRB + i) * a.KsB * 64 + lane) * 8;
+  auto loadA = [&](double (&dst)[WRA], int gs) {
     const int soff = __builtin_amdgcn_readfirstlane(gs * 512);
 #pragma unroll
-    for (int i = 0; i < WR; ++i)
+    for (int i = 0; i < WRA; ++i)
       dst[i] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rA, voA[i], soff, 0));
   };
-  auto loadB = [&](double (&dst)[WR], int gs) {
+  auto loadB = [&](double (&dst)[WRB], int gs) {
     const int soff = __builtin_amdgcn_readfirstlane(gs * 512);
 #pragma unroll
-    for (int i = 0; i < WR; ++i)
+    for (int i = 0; i < WRB; ++i)
       dst[i] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rB, voB[i], soff, 0));
-  };
-
-  double acc[WR][WQ];
-  double ring[PF][WR];
-  auto mma = [&](const double (&af)[WQ], const double (&bc)[WR]) {
-#pragma unroll
-    for (int i = 0; i < WR; ++i)
-#pragma unroll
-      for (int j = 0; j < WQ; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_f64_4x4x4f64(af[j], bc[i], acc[i][j], 0, 0, 0);
-  };
-  auto zero = [&]() {
-#pragma unroll
-    for (int i = 0; i < WR; ++i)
-#pragma unroll
-      for (int j = 0; j < WQ; ++j) acc[i][j] = 0.0;
   };
 
   gload(blockIdx.x, 0);
   for (int64_t t = 0; t < my_tiles; ++t) {
     const int64_t tile = blockIdx.x + t * (int64_t)gridDim.x;
-    // ---- step k: input streamed in chunks of 8 steps ----
-    __syncthreads();                               // the previous tile's step k + 1 is done with lds
-    lstore(0);
+    // ---- step k: input streamed in chunks of SPA steps ----
+    {
+      double acc[WRA][WQ];
+      double ring[PFA][WRA];
+      __syncthreads();                             // the previous tile's step k + 1 is done with lds
+      lstore(0);
 #pragma unroll
-    for (int p = 0; p < PF; ++p) loadA(ring[p], p);
-    zero();
-    __syncthreads();
-    for (int ch = 0; ch < nchA; ++ch) {
-      const double* S = lds + (ch & 1) * A_ELEMS;
+      for (int p = 0; p < PFA; ++p) loadA(ring[p], p);
 #pragma unroll
-      for (int s = 0; s < SPC; ++s) {
-        double af[WQ];
+      for (int i = 0; i < WRA; ++i)
 #pragma unroll
-        for (int j = 0; j < WQ; ++j) af[j] = S[(j * SPC + s) * kQGS + rd];
-        double bc[WR];
+        for (int j = 0; j < WQ; ++j) acc[i][j] = 0.0;
+      __syncthreads();
+      for (int ch = 0; ch < nchA; ++ch) {
+        const double* S = lds + (ch & 1) * A_ELEMS;
 #pragma unroll
-        for (int i = 0; i < WR; ++i) bc[i] = ring[s % PF][i];
-        const int gs = ch * SPC + s + PF;
-        if (gs < a.KsA) loadA(ring[s % PF], gs);
-        if (s == 0 && ch + 1 < nchA) gload(tile, ch + 1);
-        mma(af, bc);
+        for (int s = 0; s < SPA; ++s) {
+          double af[WQ];
+#pragma unroll
+          for (int j = 0; j < WQ; ++j) af[j] = S[(j * SPA + s) * kQGS + rd];
+          double bc[WRA];
+#pragma unroll
+          for (int i = 0; i < WRA; ++i) bc[i] = ring[s % PFA][i];
+          const int gs = ch * SPA + s + PFA;
+          if (gs < a.KsA) loadA(ring[s % PFA], gs);
+          if (s == 0 && ch + 1 < nchA) gload(tile, ch + 1);
+#pragma unroll
+          for (int i = 0; i < WRA; ++i)
+#pragma unroll
+            for (int j = 0; j < WQ; ++j)
+              acc[i][j] = __builtin_amdgcn_mfma_f64_4x4x4f64(af[j], bc[i], acc[i][j], 0, 0, 0);
+        }
+        if (ch + 1 < nchA) {
+          lstore((ch + 1) & 1);
+          __syncthreads();
+        }
       }
-      if (ch + 1 < nchA) {
-        lstore((ch + 1) & 1);
-        __syncthreads();
+      // ---- phi_k tile -> b_{k+1} tile in LDS ----
+      __syncthreads();                             // every wave is done with the stages
+#pragma unroll
+      for (int i = 0; i < WRA; ++i) {
+        const int row = 16 * (WRA * wr + i) + (lane & 15);   // a_k + RA i_k
+        const int ak = row % RA, ik = row / RA;
+#pragma unroll
+        for (int j = 0; j < WQ; ++j) {
+          const int col = 4 * j + (lane >> 4);               // j_{k+1} + 8 (Q - Q0)
+          const int kap = ak + RA * (col & 7);
+          lds[(ik * KSB + (kap >> 2)) * kQGS + 4 * (col >> 3) + (kap & 3)] = acc[i][j];
+        }
       }
     }
-    // ---- phi_k tile -> b_{k+1} tile in LDS ----
-    __syncthreads();                               // every wave is done with the stages
-#pragma unroll
-    for (int i = 0; i < WR; ++i) {
-      const int row = 16 * (WR * wr + i) + (lane & 15);   // a_k + 32 i_k
-      const int ak = row & 31, ik = row >> 5;
-#pragma unroll
-      for (int j = 0; j < WQ; ++j) {
-        const int col = 4 * j + (lane >> 4);               // j_{k+1} + 8 (Q - Q0)
-        const int kap = ak + 32 * (col & 7);
-        lds[(ik * KSB + (kap >> 2)) * kQGS + 4 * (col >> 3) + (kap & 3)] = acc[i][j];
-      }
-    }
+    // ---- step k + 1 from LDS ----
+    double acc[WRB][WQ];
+    double ring[PF][WRB];
 #pragma unroll
     for (int p = 0; p < PF; ++p) loadB(ring[p], p);
     if (t + 1 < my_tiles) gload(tile + gridDim.x, 0);
-    zero();
-    __syncthreads();
-    // ---- step k + 1 from LDS ----
-    for (int c8 = 0; c8 < KSB / SPC; ++c8) {
 #pragma unroll
-      for (int s = 0; s < SPC; ++s) {
-        const int gs = c8 * SPC + s;
+    for (int i = 0; i < WRB; ++i)
+#pragma unroll
+      for (int j = 0; j < WQ; ++j) acc[i][j] = 0.0;
+    __syncthreads();
+    for (int c8 = 0; c8 < KSB / SPB; ++c8) {
+#pragma unroll
+      for (int s = 0; s < SPB; ++s) {
+        const int gs = c8 * SPB + s;
         double af[WQ];
 #pragma unroll
         for (int j = 0; j < WQ; ++j) af[j] = lds[(j * KSB + gs) * kQGS + rd];
-        double bc[WR];
+        double bc[WRB];
 #pragma unroll
-        for (int i = 0; i < WR; ++i) bc[i] = ring[s % PF][i];
+        for (int i = 0; i < WRB; ++i) bc[i] = ring[s % PF][i];
         if (gs + PF < KSB) loadB(ring[s % PF], gs + PF);
-        mma(af, bc);
+#pragma unroll
+        for (int i = 0; i < WRB; ++i)
+#pragma unroll
+          for (int j = 0; j < WQ; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f64_4x4x4f64(af[j], bc[i], acc[i][j], 0, 0, 0);
       }
     }
     // ---- y_{k+1}(a', q' + C i_{k+1}) with q' = Q + (C / 8) i_k ----
@@ -1222,8 +1241,8 @@ __global__ void __launch_bounds__(256, 2) core_pair_f64q_kernel(const PairArgs a
     const int64_t Q0 = (col0 - rhs * a.C) / 8;
     double* dst = a.out + rhs * a.out_stride;
 #pragma unroll
-    for (int i = 0; i < WR; ++i) {
-      const int row = 16 * (WR * wr + i) + (lane & 15);
+    for (int i = 0; i < WRB; ++i) {
+      const int row = 16 * (WRB * wr + i) + (lane & 15);
       if (row >= a.R_outB) continue;
       const int ar = row % a.r_outB, ir = row / a.r_outB;
 #pragma unroll

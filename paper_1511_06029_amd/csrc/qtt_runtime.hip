@@ -813,22 +813,36 @@ static int64_t wave_capacity(const qtt_matrix_s* A, int dt, size_t ws_bytes) {
 }
 
 // Fused FP64 pair (core k, core k + 1), see core_pair_f64q_kernel.
-static const int kPairShape = 90;   // configuration id reported by the launch timing
+// configuration ids reported by the launch timing: 90 + 4 (first core) +
+// 2 (r_k = 32) + (R_out(k + 1) > 192), one per kernel instantiation
+static const int kPairShape = 90;
 static int64_t frag_bytes(const CoreDev& c, int dt) {
   return (int64_t)padded_row_blocks(c.nRB) * c.Ksteps[dt] * 64 * kFragE[dt] * kElemBytes[dt];
 }
-static bool pair_ok(const qtt_matrix_s* A, int dt, int k) {
-  if (dt != 0 || !A->fp64_pair || k < 1 || k + 1 > A->d - 2) return false;
+static bool pair_ok(const qtt_matrix_s* A, int dt, int k, const Segment* segs, int nseg) {
+  if (dt != 0 || !A->fp64_pair || k + 1 > A->d - 2) return false;   // core k + 1 is not the last
   const CoreDev& x = A->core[k];
   const CoreDev& y = A->core[k + 1];
-  return x.r_out == 32 && x.m == 8 && y.n == 8 && x.R_out == 256 && y.K_in == 256 && y.R_out <= 256 &&
-         x.Ksteps[0] % 8 == 0 && y.Ksteps[0] == 64 && x.C % 32 == 0 && x.C == y.C && x.K_in % 2 == 0 &&
-         frag_bytes(x, 0) <= INT32_MAX && frag_bytes(y, 0) <= INT32_MAX;
+  const bool first = (k == 0);
+  const int ra = x.r_out;
+  if (!((ra == 24 || ra == 32) && x.m == 8 && y.n == 8 && y.K_in == 8 * ra && y.R_out <= 256)) return false;
+  if (x.Ksteps[0] % (first ? 2 : 8) != 0 || y.Ksteps[0] != 2 * ra) return false;
+  if (x.C % 32 != 0 || x.C != y.C || x.K_in % 2 != 0) return false;
+  if (frag_bytes(x, 0) > INT32_MAX || frag_bytes(y, 0) > INT32_MAX) return false;
+  if (first)
+    for (int s = 0; s < nseg; ++s)
+      if (reinterpret_cast<uintptr_t>(segs[s].x) % 16 != 0 || segs[s].ldx % 2 != 0) return false;
+  return true;
 }
-static qtt_status_t launch_pair(const qtt_matrix_s* A, int k, int64_t nrhs, const void* in, void* out,
-                                hipStream_t st) {
+template <int RA, int WRB, bool FIRST>
+static const void* pair_fn() {
+  return reinterpret_cast<const void*>(&core_pair_f64q_kernel<RA, WRB, FIRST, FIRST ? 8 : 32, 4>);
+}
+static qtt_status_t launch_pair(const qtt_matrix_s* A, int k, int64_t nrhs, const Segment* segs, int nseg,
+                                const void* in, void* out, hipStream_t st) {
   const CoreDev& x = A->core[k];
   const CoreDev& y = A->core[k + 1];
+  const bool first = (k == 0);
   PairArgs a;
   memset(&a, 0, sizeof(a));
   a.MA = x.frag[0];
@@ -847,9 +861,15 @@ static qtt_status_t launch_pair(const qtt_matrix_s* A, int k, int64_t nrhs, cons
   a.r_outB = y.r_out;
   a.MA_bytes = (int32_t)frag_bytes(x, 0);
   a.MB_bytes = (int32_t)frag_bytes(y, 0);
-  static int occ = 0;
-  const void* fn = reinterpret_cast<const void*>(&core_pair_f64q_kernel<4>);
-  const int64_t resident = (int64_t)occupancy_fn(fn, 256, &occ) * num_cus();
+  a.nseg = first ? nseg : 0;
+  for (int s = 0; s < a.nseg; ++s) a.seg[s] = segs[s];
+  // instantiation: rank of the fused boundary, rows of step k + 1, first core
+  static int occ[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  static const void* fns[8] = {pair_fn<24, 3, false>(), pair_fn<24, 4, false>(), pair_fn<32, 3, false>(),
+                               pair_fn<32, 4, false>(), pair_fn<24, 3, true>(),  pair_fn<24, 4, true>(),
+                               pair_fn<32, 3, true>(),  pair_fn<32, 4, true>()};
+  const int v = (first ? 4 : 0) + (x.r_out == 32 ? 2 : 0) + (y.R_out > 192 ? 1 : 0);
+  const int64_t resident = (int64_t)occupancy_fn(fns[v], 256, &occ[v]) * num_cus();
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(a.n_tiles, resident));
   TimedLaunch tl;
   const bool timed = timing_on();
@@ -859,12 +879,12 @@ static qtt_status_t launch_pair(const qtt_matrix_s* A, int k, int64_t nrhs, cons
     HIP_TRY(hipEventRecord(tl.a, st));
   }
   void* args[] = {&a};
-  HIP_TRY(hipLaunchKernel(fn, dim3(grid), dim3(256), args, 0, st));
+  HIP_TRY(hipLaunchKernel(fns[v], dim3(grid), dim3(256), args, 0, st));
   if (timed) {
     HIP_TRY(hipEventRecord(tl.b, st));
     tl.dt = 0;
-    tl.pos = 0;
-    tl.shape = kPairShape;
+    tl.pos = first ? 1 : 0;
+    tl.shape = kPairShape + v;
     tl.flops = 2.0 * ((double)x.R_out * x.K_in + (double)y.R_out * y.K_in) * (double)a.ncols;
     tl.bytes = (double)a.ncols * ((double)x.K_in + y.R_out) * 8.0;
     g_timed.push_back(tl);
@@ -894,8 +914,8 @@ static qtt_status_t sweep(const qtt_matrix_s* A, int dt, int64_t nrhs, const Seg
   int cur = 0;  // buffer holding the latest intermediate (core 0 writes buf[0])
   for (int k = 0; k < A->d;) {
     const void* in = (k == 0) ? nullptr : buf[cur];
-    if (!tsw && pair_ok(A, dt, k)) {
-      qtt_status_t s = launch_pair(A, k, nrhs, in, buf[cur ^ 1], st);
+    if (!tsw && pair_ok(A, dt, k, segs, nseg)) {
+      qtt_status_t s = launch_pair(A, k, nrhs, segs, nseg, in, buf[cur ^ 1], st);
       if (s != QTT_OK) return s;
       cur ^= 1;
       k += 2;

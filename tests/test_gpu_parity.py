@@ -338,7 +338,7 @@ def test_rank_slowest_fp64_sweep(Q):
 def test_timing_by_configuration(Q):
     """Launch timing summed by kernel configuration partitions the sums by
     core position: same launches, same flops, and the default configurations
-    are the ones recorded (4x4x4 FP64 kernels on cores of more than 64 rows,
+    are the ones recorded (fused FP64 core pairs, the vector-ALU last core;
     the first core's short-contraction kernel for BF16)."""
     ranks = [1, 24, 32, 32, 24, 1]
     cores = I.gaussian_qtt(ranks, [8] * 5, seed=81)
@@ -354,7 +354,7 @@ def test_timing_by_configuration(Q):
         torch.cuda.synchronize()
         Q.qtt_timing_enable(False)
         by_pos = [Q.qtt_timing_read(dt, p) for p in range(4)]
-        by_shape = {sh: Q.qtt_timing_read_shape(dt, sh) for sh in Q.qtt_list_shapes(dt) + [Q.PAIR_SHAPE]}
+        by_shape = {sh: Q.qtt_timing_read_shape(dt, sh) for sh in Q.qtt_list_shapes(dt) + Q.PAIR_SHAPES}
         Q.qtt_timing_reset()
         used = {sh: r for sh, r in by_shape.items() if r["launches"]}
         assert sum(r["launches"] for r in by_pos) == sum(r["launches"] for r in used.values())
@@ -364,9 +364,10 @@ def test_timing_by_configuration(Q):
         assert np.isclose(sum(r["flops"] for r in used.values()), flops)
         assert all(r["ms"] > 0 for r in used.values())
         if dt == "fp64":
-            # first core, the fused pair (cores 1, 2), the 192-row core, the last core
-            assert set(used) == {67, Q.PAIR_SHAPE, 63, 47}, used.keys()
-            assert sum(r["launches"] for r in used.values()) == len(ranks) - 2
+            # fused pairs (0, 1): first core, r_1 = 24, 256 rows next; (2, 3): r_3 = 32,
+            # 192 rows next; then the last core on the vector ALUs
+            assert set(used) == {90 + 4 + 0 + 1, 90 + 0 + 2 + 0, 47}, used.keys()
+            assert sum(r["launches"] for r in used.values()) == 3
         else:
             assert 34 in used and sum(r["launches"] for r in used.values()) == len(ranks) - 1, used.keys()
     assert Q.qtt_timing_read_shape("fp64", 9999)["launches"] == 0
