@@ -1030,7 +1030,8 @@ core_step_f64q_kernel(const StepArgs args) {
 // Two consecutive FP64 core steps k, k + 1 in one pass over a column tile,
 // on the 4x4x4 matrix instruction: the tile's intermediate y_k stays on chip.
 //
-// For cores with r_k = RA (24 or 32) and m_k = n_{k+1} = 8.  A tile is 32
+// For cores with r_k = RA (24 or 32; the RA = 32 kernels also take any r_k
+// from 17 to 32, padded) and m_k = n_{k+1} = 8.  A tile is 32
 // consecutive columns q = j_{k+1} + 8 Q of b_k, four values of Q.  Step k
 // gives phi_k(a_k + RA i_k, j_{k+1} + 8 Q) for all 8 RA rows.  By the row
 // separation of step k and the reshape into b_{k+1} (Algorithm 2), these are
@@ -1064,6 +1065,7 @@ struct PairArgs {
   int32_t R_outB, r_outB;
   int32_t MA_bytes, MB_bytes;
   int32_t nseg;          // FIRST: input columns come from seg[].x
+  int32_t ra;            // boundary rank r_k (the RA = 32 kernels take 17..32)
   Segment seg[kMaxSeg];
 };
 
@@ -1077,7 +1079,7 @@ __global__ void __launch_bounds__(256, 2) core_pair_f64q_kernel(const PairArgs a
   constexpr int PFA = PF < SPA ? PF : SPA;
   constexpr int NLA = (TC * VPC + NT - 1) / NT;
   constexpr int A_ELEMS = (TC / 4) * SPA * kQGS;   // one staging stage of step k
-  constexpr int KSB = 2 * RA;                      // steps of step k + 1 (K_in = 8 RA)
+  constexpr int KSB = 2 * RA;                      // LDS steps of step k + 1 (K_in <= 8 RA)
   constexpr int X_ELEMS = (TC / 4) * KSB * kQGS;   // b_{k+1} tile
   static_assert(RA == 24 || RA == 32, "rank of the fused boundary");
   static_assert(SPA % PFA == 0 && SPB % PF == 0 && KSB % SPB == 0, "whole prefetch rounds");
@@ -1089,6 +1091,11 @@ __global__ void __launch_bounds__(256, 2) core_pair_f64q_kernel(const PairArgs a
   const int wr = tid >> 6;
   const int rd = 4 * (lane & 3) + (lane >> 4);
   const int nchA = a.KsA / SPA;
+  // the boundary rank: RA itself, or (RA = 32) any ra in 17..32 with step k's
+  // rows padded to 8 RA (zero fragment rows) and step k + 1's contraction to
+  // a.KsB steps (zero core steps past 8 ra, zero LDS values there)
+  const int ra = (RA == 32) ? a.ra : RA;
+  const int kin_b = 8 * ra;
   const int64_t my_tiles = (a.n_tiles > (int64_t)blockIdx.x)
                                ? (a.n_tiles - 1 - (int64_t)blockIdx.x) / gridDim.x + 1 : 0;
   if (my_tiles == 0) return;
@@ -1196,13 +1203,23 @@ __global__ void __launch_bounds__(256, 2) core_pair_f64q_kernel(const PairArgs a
       __syncthreads();                             // every wave is done with the stages
 #pragma unroll
       for (int i = 0; i < WRA; ++i) {
-        const int row = 16 * (WRA * wr + i) + (lane & 15);   // a_k + RA i_k
-        const int ak = row % RA, ik = row / RA;
+        const int row = 16 * (WRA * wr + i) + (lane & 15);   // a_k + ra i_k
+        if (row < kin_b) {
+          const int ak = row % ra, ik = row / ra;
 #pragma unroll
-        for (int j = 0; j < WQ; ++j) {
-          const int col = 4 * j + (lane >> 4);               // j_{k+1} + 8 (Q - Q0)
-          const int kap = ak + RA * (col & 7);
-          lds[(ik * KSB + (kap >> 2)) * kQGS + 4 * (col >> 3) + (kap & 3)] = acc[i][j];
+          for (int j = 0; j < WQ; ++j) {
+            const int col = 4 * j + (lane >> 4);             // j_{k+1} + 8 (Q - Q0)
+            const int kap = ak + ra * (col & 7);
+            lds[(ik * KSB + (kap >> 2)) * kQGS + 4 * (col >> 3) + (kap & 3)] = acc[i][j];
+          }
+        }
+      }
+      // contraction indices 8 ra .. 4 KsB of every column: zeros
+      if (RA == 32 && kin_b < 4 * a.KsB) {
+        const int pad = 4 * a.KsB - kin_b;
+        for (int e = tid; e < TC * pad; e += NT) {
+          const int c = e / pad, kap = kin_b + (e - c * pad);
+          lds[((c >> 2) * KSB + (kap >> 2)) * kQGS + 4 * (c & 3) + (kap & 3)] = 0.0;
         }
       }
     }
@@ -1217,7 +1234,7 @@ __global__ void __launch_bounds__(256, 2) core_pair_f64q_kernel(const PairArgs a
 #pragma unroll
       for (int j = 0; j < WQ; ++j) acc[i][j] = 0.0;
     __syncthreads();
-    for (int c8 = 0; c8 < KSB / SPB; ++c8) {
+    for (int c8 = 0; c8 < a.KsB / SPB; ++c8) {
 #pragma unroll
       for (int s = 0; s < SPB; ++s) {
         const int gs = c8 * SPB + s;
@@ -1227,7 +1244,7 @@ __global__ void __launch_bounds__(256, 2) core_pair_f64q_kernel(const PairArgs a
         double bc[WRB];
 #pragma unroll
         for (int i = 0; i < WRB; ++i) bc[i] = ring[s % PF][i];
-        if (gs + PF < KSB) loadB(ring[s % PF], gs + PF);
+        if (gs + PF < a.KsB) loadB(ring[s % PF], gs + PF);
 #pragma unroll
         for (int i = 0; i < WRB; ++i)
 #pragma unroll

@@ -814,7 +814,8 @@ static int64_t wave_capacity(const qtt_matrix_s* A, int dt, size_t ws_bytes) {
 
 // Fused FP64 pair (core k, core k + 1), see core_pair_f64q_kernel.
 // configuration ids reported by the launch timing: 90 + 4 (first core) +
-// 2 (r_k = 32) + (R_out(k + 1) > 192), one per kernel instantiation
+// 2 (r_k != 24: the padded rank-32 kernel) + (R_out(k + 1) > 192), one per
+// kernel instantiation
 static const int kPairShape = 90;
 static int64_t frag_bytes(const CoreDev& c, int dt) {
   return (int64_t)padded_row_blocks(c.nRB) * c.Ksteps[dt] * 64 * kFragE[dt] * kElemBytes[dt];
@@ -825,8 +826,8 @@ static bool pair_ok(const qtt_matrix_s* A, int dt, int k, const Segment* segs, i
   const CoreDev& y = A->core[k + 1];
   const bool first = (k == 0);
   const int ra = x.r_out;
-  if (!((ra == 24 || ra == 32) && x.m == 8 && y.n == 8 && y.K_in == 8 * ra && y.R_out <= 256)) return false;
-  if (x.Ksteps[0] % (first ? 2 : 8) != 0 || y.Ksteps[0] != 2 * ra) return false;
+  if (!(ra >= 17 && ra <= 32 && x.m == 8 && y.n == 8 && y.K_in == 8 * ra && y.R_out <= 256)) return false;
+  if (x.Ksteps[0] % (first ? 2 : 8) != 0 || y.Ksteps[0] != (2 * ra + 7) / 8 * 8) return false;
   if (x.C % 32 != 0 || x.C != y.C || x.K_in % 2 != 0) return false;
   if (frag_bytes(x, 0) > INT32_MAX || frag_bytes(y, 0) > INT32_MAX) return false;
   if (first)
@@ -862,13 +863,15 @@ static qtt_status_t launch_pair(const qtt_matrix_s* A, int k, int64_t nrhs, cons
   a.MA_bytes = (int32_t)frag_bytes(x, 0);
   a.MB_bytes = (int32_t)frag_bytes(y, 0);
   a.nseg = first ? nseg : 0;
+  a.ra = x.r_out;
   for (int s = 0; s < a.nseg; ++s) a.seg[s] = segs[s];
   // instantiation: rank of the fused boundary, rows of step k + 1, first core
   static int occ[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   static const void* fns[8] = {pair_fn<24, 3, false>(), pair_fn<24, 4, false>(), pair_fn<32, 3, false>(),
                                pair_fn<32, 4, false>(), pair_fn<24, 3, true>(),  pair_fn<24, 4, true>(),
                                pair_fn<32, 3, true>(),  pair_fn<32, 4, true>()};
-  const int v = (first ? 4 : 0) + (x.r_out == 32 ? 2 : 0) + (y.R_out > 192 ? 1 : 0);
+  // exact rank-24 kernels for r_k = 24, the padded rank-32 ones otherwise
+  const int v = (first ? 4 : 0) + (x.r_out != 24 ? 2 : 0) + (y.R_out > 192 ? 1 : 0);
   const int64_t resident = (int64_t)occupancy_fn(fns[v], 256, &occ[v]) * num_cus();
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(a.n_tiles, resident));
   TimedLaunch tl;

@@ -372,3 +372,43 @@ def test_timing_by_configuration(Q):
             assert 34 in used and sum(r["launches"] for r in used.values()) == len(ranks) - 1, used.keys()
     assert Q.qtt_timing_read_shape("fp64", 9999)["launches"] == 0
     A.free()
+
+
+def test_fused_pairs_any_rank(Q):
+    """The fused FP64 pair kernels at boundary ranks other than 24 and 32
+    (padded rows and contraction): the first core with r_1 = 20 and an
+    interior pair with r_3 = 29, against the oracle and against the sweep
+    with pairs switched off; and a refined solve through them."""
+    ranks = [1, 20, 29, 29, 20, 1]
+    cores = I.gaussian_qtt(ranks, [8] * 5, seed=91)
+    X = I.rhs(8 ** 5, 3, seed=92)
+    ref = O.qtt_apply_alg2(cores, X)
+    A = Q.qtt_matrix_load(cores, dtypes=("fp64",))
+    Xd = Q.to_block(X)
+    Q.qtt_timing_reset()
+    Q.qtt_timing_enable(True)
+    Yp = Q.qtt_apply(A, "fp64", Xd).cpu().numpy()
+    torch.cuda.synchronize()
+    Q.qtt_timing_enable(False)
+    used = {sh for sh in Q.PAIR_SHAPES if Q.qtt_timing_read_shape("fp64", sh)["launches"]}
+    Q.qtt_timing_reset()
+    assert used == {90 + 4 + 2 + 1, 90 + 0 + 2 + 0}, used   # (0,1) padded, 232 rows next; (2,3) padded, 160 rows
+    assert colrel(Yp, ref) <= 1e-12 and elementwise_ok(Yp, ref, 1e-12)
+    Q.qtt_set_shape(A, "fp64", -2, 0)
+    Ys = Q.qtt_apply(A, "fp64", Xd).cpu().numpy()
+    assert colrel(Ys, ref) <= 1e-12
+    assert colrel(Yp, Ys) <= 1e-13
+    Q.qtt_set_shape(A, "fp64", -2, 1)
+    A.free()
+    # a refined solve with the fused FP64 residual
+    Ac, Aic = I.perturbed_identity_pair(ranks, [8] * 5, seed=93)
+    A = Q.qtt_matrix_load(Ac, dtypes=("fp64",))
+    Ai = Q.qtt_matrix_load(Aic, dtypes=("bf16",))
+    F = I.rhs(8 ** 5, 2, seed=94)
+    Sig, info, st = Q.qtt_solve(A, Ai, "bf16", Q.to_block(F), rtol=1e-8)
+    assert st == 0 and all(c[1] <= 1e-8 for c in info)
+    S = Sig.cpu().numpy().reshape(F.shape)
+    res = F - O.qtt_apply_alg2(Ac, S)
+    assert np.all(np.linalg.norm(res, axis=0) <= 1e-8 * np.linalg.norm(F, axis=0) * 1.0001)
+    A.free()
+    Ai.free()
