@@ -122,8 +122,10 @@ qtt_status_t qtt_apply_batched(qtt_matrix_t A, qtt_dtype_t compute, int32_t nblo
 /* Tune tile shapes for this matrix, dtype and vector count: every candidate
  * kernel configuration is timed on each core (outputs written to scratch in
  * ws), and the fastest is kept in the handle and in a process-wide table
- * keyed by (dtype, core shape).  X/Y are used as in qtt_apply
- * and hold A X on return.  Synchronises the stream. */
+ * keyed by (dtype, core shape).  For FP64 the whole sweep is then timed
+ * core by core, with fused core pairs and in the rank-slowest mode, and the
+ * fastest of the three is kept.  X/Y are used as in qtt_apply and hold A X
+ * on return.  Synchronises the stream. */
 qtt_status_t qtt_autotune(qtt_matrix_t A, qtt_dtype_t compute, int64_t nrhs,
                           const double* X, int64_t ldx, double* Y, int64_t ldy,
                           void* ws, size_t ws_bytes, void* stream);
@@ -136,9 +138,15 @@ qtt_status_t qtt_autotune(qtt_matrix_t A, qtt_dtype_t compute, int64_t nrhs,
  * every FP64 sweep on the vector ALUs with the intermediates stored rank
  * index slowest (needs every mode size 8, else QTT_ERR_SHAPE; ids 50..56
  * then pick that sweep's per-core configuration), -1 returns to the
- * standard sweep.  Returns QTT_ERR_INVALID_ARG for an unknown id or core
- * index.  Used by the tests to run every kernel variant, and to replay a
- * tuning result. */
+ * standard sweep.  core = -2 (FP64 only) switches fused core pairs off
+ * (shape 0) or on (shape 1): with pairs on, which is the default, two
+ * consecutive cores k, k + 1 with r_k in 17..32 and m_k = n_{k+1} = 8, core
+ * k + 1 not the last, run as one kernel that keeps the tile's intermediate
+ * y_k on chip (Algorithm 2 applied two cores at a time).  Pinning an FP64
+ * configuration on a core (shape != -1) switches pairs off, so that the
+ * pinned configuration is the one that runs.  Returns QTT_ERR_INVALID_ARG
+ * for an unknown id or core index.  Used by the tests to run every kernel
+ * variant, and to replay a tuning result. */
 qtt_status_t qtt_set_shape(qtt_matrix_t A, qtt_dtype_t compute, int32_t core, int32_t shape);
 
 /* Ids of the configurations available for a dtype (up to cap written to
