@@ -138,12 +138,12 @@ qtt_status_t qtt_autotune(qtt_matrix_t A, qtt_dtype_t compute, int64_t nrhs,
  * every FP64 sweep on the vector ALUs with the intermediates stored rank
  * index slowest (needs every mode size 8, else QTT_ERR_SHAPE; ids 50..56
  * then pick that sweep's per-core configuration), -1 returns to the
- * standard sweep.  core = -2 (FP64 only) switches fused core pairs off
+ * standard sweep.  core = -2 (FP64, FP32) switches fused core pairs off
  * (shape 0) or on (shape 1): with pairs on, which is the default, two
  * consecutive cores k, k + 1 with r_k in 17..32 and m_k = n_{k+1} = 8, core
  * k + 1 not the last, run as one kernel that keeps the tile's intermediate
- * y_k on chip (Algorithm 2 applied two cores at a time).  Pinning an FP64
- * configuration on a core (shape != -1) switches pairs off, so that the
+ * y_k on chip (Algorithm 2 applied two cores at a time).  Pinning a
+ * configuration on a core (shape != -1) switches that dtype's pairs off, so that the
  * pinned configuration is the one that runs.  Returns QTT_ERR_INVALID_ARG
  * for an unknown id or core index.  Used by the tests to run every kernel
  * variant, and to replay a tuning result. */
@@ -197,9 +197,10 @@ qtt_status_t qtt_timing_reset(void);
 qtt_status_t qtt_timing_read(qtt_dtype_t compute, int32_t position, int64_t* launches,
                              double* milliseconds, double* flops, double* bytes);
 /* The same sums over the launches of one kernel configuration id (any core
- * position); ids as in qtt_list_shapes, plus 90..97 for the FP64 kernel
- * that applies two consecutive cores k, k + 1 in one launch: 90 + 4 (k is
- * the first core) + 2 (r_k = 32, else 24) + (R_out of core k + 1 above 192).
+ * position); ids as in qtt_list_shapes, plus 90..97 (FP64) and 100..107
+ * (FP32) for the kernels that apply two consecutive cores k, k + 1 in one
+ * launch: base + 4 (k is the first core) + 2 (the padded kernel for any r_k
+ * in 17..32 other than 24) + (R_out of core k + 1 above 192).
  * Such a launch is recorded at the position of core k, with the flops of
  * both cores.  Launches of a configuration id that was never timed give
  * zeros. */

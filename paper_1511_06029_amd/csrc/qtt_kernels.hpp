@@ -815,8 +815,8 @@ core_step_stream_kernel(const StepArgs args) {
 // row 16 rb + (l mod 16) of the core, column l div 16 of the 4-column group,
 // so rows stay on lanes and 16 lanes store 16 consecutive a_k.
 //
-// The streaming scheme is the one of the kernel above: input chunks a chunk
-// ahead in registers, two LDS stages, core fragments from L2 a step ahead.
+// The streaming scheme follows the kernel above: input chunks a chunk ahead
+// in registers, two LDS stages; core fragments come from L2 (below).
 // LDS input layout: for 4-column group g and step s, a run of 16 values with
 // (column c, contraction k) at 4 c + k; runs are kQGS values apart, a padding
 // that puts the 16-byte stores of one column's consecutive steps on distinct
@@ -1266,6 +1266,231 @@ __global__ void __launch_bounds__(256, 2) core_pair_f64q_kernel(const PairArgs a
       for (int j = 0; j < WQ; ++j) {
         const int64_t qp = Q0 + (lane >> 4) + (a.C / 8) * j;    // column c' = (Q - Q0) + 4 i_k, i_k = j
         dst[ar + (int64_t)a.r_outB * (qp + a.C * ir)] = acc[i][j];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The fused pair of core steps k, k + 1 (see core_pair_f64q_kernel) for the
+// FP32 sweep, on v_mfma_f32_16x16x4f32 with FP32 accumulation.
+//
+// Operands as in the streamed FP32 kernels with rows on lanes: the input
+// fragment of column block cb and step s has lane l = (column mod 16) +
+// 16 (contraction index mod 4); the core fragment lane l holds
+// M(16 rb + l mod 16, 4 s + l div 16); accumulator register v of lane l is
+// column 4 (l div 16) + v of the 16-column block, core row l mod 16.  A tile
+// is 32 columns of b_k (two column blocks); the b_{k+1} tile goes to LDS in
+// the same fragment order (column c' = (Q - Q0) + 4 i_k), 32 KB at r_k = 32.
+// Requirements as for the FP64 pair.
+// ---------------------------------------------------------------------------
+template <int RA, int WRB, bool FIRST, int KCA, int PF>
+__global__ void __launch_bounds__(256, 2) core_pair_f32_kernel(const PairArgs args) {
+  (void)args;
+  const PairArgs& a = kernarg<PairArgs>();
+  using Tin = typename std::conditional<FIRST, double, float>::type;
+  constexpr int NT = 256, TC = 32, CB = TC / 16, SPB = 8;
+  constexpr int WRA = RA / 8;
+  constexpr int SPA = KCA / 4;
+  constexpr int VE = 16 / (int)sizeof(Tin);         // values per 16-byte input load
+  constexpr int VPC = KCA / VE;
+  constexpr int PFA = PF < SPA ? PF : SPA;
+  constexpr int NLA = (TC * VPC + NT - 1) / NT;
+  constexpr int A_ELEMS = CB * SPA * 64;            // one staging stage of step k
+  constexpr int KSB = 2 * RA;                       // LDS steps of step k + 1
+  constexpr int X_ELEMS = CB * KSB * 64;            // b_{k+1} tile
+  static_assert(RA == 24 || RA == 32, "rank of the fused boundary");
+  static_assert(SPA % PFA == 0 && SPB % PF == 0 && KSB % SPB == 0, "whole prefetch rounds");
+  static_assert(2 * A_ELEMS <= X_ELEMS, "stages alias the tile");
+  __shared__ __attribute__((aligned(16))) float lds[X_ELEMS];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wr = tid >> 6;
+  const int nchA = a.KsA / SPA;
+  const int ra = (RA == 32) ? a.ra : RA;
+  const int kin_b = 8 * ra;
+  const int64_t my_tiles = (a.n_tiles > (int64_t)blockIdx.x)
+                               ? (a.n_tiles - 1 - (int64_t)blockIdx.x) / gridDim.x + 1 : 0;
+  if (my_tiles == 0) return;
+
+  v4u sa[NLA];
+  auto gload = [&](int64_t tile, int ch) {
+    const int64_t col0 = tile * TC;
+    const int kc0 = ch * KCA;
+#pragma unroll
+    for (int t = 0; t < NLA; ++t) {
+      const int idx = tid + t * NT;
+      const int c = idx / VPC;
+      const int kap = kc0 + (idx % VPC) * VE;
+      const int64_t g = col0 + c;
+      sa[t] = v4u{};
+      if (idx < TC * VPC && g < a.ncols && kap < a.K_inA) {
+        const int64_t rhs = g / a.C;
+        const int64_t q = g - rhs * a.C;
+        const Tin* p;
+        if constexpr (FIRST) {
+          const Segment& sg = a.seg[find_seg(a, rhs)];
+          p = sg.x + (rhs - sg.rhs_begin) * sg.ldx + q * a.K_inA;
+        } else {
+          p = reinterpret_cast<const float*>(a.in) + rhs * a.in_stride + q * a.K_inA;
+        }
+        sa[t] = *reinterpret_cast<const v4u*>(p + kap);
+      }
+    }
+  };
+  auto lstore = [&](int stage) {
+    float* S = lds + stage * A_ELEMS;
+#pragma unroll
+    for (int t = 0; t < NLA; ++t) {
+      const int idx = tid + t * NT;
+      if (idx < TC * VPC) {
+        const int c = idx / VPC;
+        const int kl0 = (idx % VPC) * VE;
+        const Tin* v = reinterpret_cast<const Tin*>(&sa[t]);
+#pragma unroll
+        for (int e = 0; e < VE; ++e) {
+          const int kl = kl0 + e;
+          S[((c >> 4) * SPA + (kl >> 2)) * 64 + (c & 15) + 16 * (kl & 3)] = (float)v[e];
+        }
+      }
+    }
+  };
+  const __amdgpu_buffer_rsrc_t rA =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(a.MA), (short)0, a.MA_bytes, 0x00020000);
+  const __amdgpu_buffer_rsrc_t rB =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(a.MB), (short)0, a.MB_bytes, 0x00020000);
+  int voA[WRA], voB[WRB];
+#pragma unroll
+  for (int i = 0; i < WRA; ++i) voA[i] = ((wr * WRA + i) * a.KsA * 64 + lane) * 4;
+#pragma unroll
+  for (int i = 0; i < WRB; ++i) voB[i] = ((wr * WRB + i) * a.KsB * 64 + lane) * 4;
+  auto loadA = [&](float (&dst)[WRA], int gs) {
+    const int soff = __builtin_amdgcn_readfirstlane(gs * 256);
+#pragma unroll
+    for (int i = 0; i < WRA; ++i)
+      dst[i] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rA, voA[i], soff, 0));
+  };
+  auto loadB = [&](float (&dst)[WRB], int gs) {
+    const int soff = __builtin_amdgcn_readfirstlane(gs * 256);
+#pragma unroll
+    for (int i = 0; i < WRB; ++i)
+      dst[i] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rB, voB[i], soff, 0));
+  };
+
+  gload(blockIdx.x, 0);
+  for (int64_t t = 0; t < my_tiles; ++t) {
+    const int64_t tile = blockIdx.x + t * (int64_t)gridDim.x;
+    // ---- step k ----
+    {
+      v4f acc[WRA][CB];
+      float ring[PFA][WRA];
+      __syncthreads();                             // the previous tile's step k + 1 is done with lds
+      lstore(0);
+#pragma unroll
+      for (int p = 0; p < PFA; ++p) loadA(ring[p], p);
+#pragma unroll
+      for (int i = 0; i < WRA; ++i)
+#pragma unroll
+        for (int j = 0; j < CB; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+      __syncthreads();
+      for (int ch = 0; ch < nchA; ++ch) {
+        const float* S = lds + (ch & 1) * A_ELEMS;
+#pragma unroll
+        for (int s = 0; s < SPA; ++s) {
+          float af[CB];
+#pragma unroll
+          for (int j = 0; j < CB; ++j) af[j] = S[(j * SPA + s) * 64 + lane];
+          float bc[WRA];
+#pragma unroll
+          for (int i = 0; i < WRA; ++i) bc[i] = ring[s % PFA][i];
+          const int gs = ch * SPA + s + PFA;
+          if (gs < a.KsA) loadA(ring[s % PFA], gs);
+          if (s == 0 && ch + 1 < nchA) gload(tile, ch + 1);
+#pragma unroll
+          for (int i = 0; i < WRA; ++i)
+#pragma unroll
+            for (int j = 0; j < CB; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[j], bc[i], acc[i][j], 0, 0, 0);
+        }
+        if (ch + 1 < nchA) {
+          lstore((ch + 1) & 1);
+          __syncthreads();
+        }
+      }
+      // ---- phi_k tile -> b_{k+1} tile in LDS ----
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < WRA; ++i) {
+        const int row = 16 * (WRA * wr + i) + (lane & 15);   // a_k + ra i_k
+        if (row < kin_b) {
+          const int ak = row % ra, ik = row / ra;
+#pragma unroll
+          for (int j = 0; j < CB; ++j) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int col = 16 * j + 4 * (lane >> 4) + v;  // j_{k+1} + 8 (Q - Q0)
+              const int kap = ak + ra * (col & 7);
+              const int cp = (col >> 3) + 4 * ik;            // column of b_{k+1} in the tile
+              lds[((cp >> 4) * KSB + (kap >> 2)) * 64 + (cp & 15) + 16 * (kap & 3)] = acc[i][j][v];
+            }
+          }
+        }
+      }
+      if (RA == 32 && kin_b < 4 * a.KsB) {
+        const int pad = 4 * a.KsB - kin_b;
+        for (int e = tid; e < TC * pad; e += NT) {
+          const int c = e / pad, kap = kin_b + (e - c * pad);
+          lds[((c >> 4) * KSB + (kap >> 2)) * 64 + (c & 15) + 16 * (kap & 3)] = 0.f;
+        }
+      }
+    }
+    // ---- step k + 1 from LDS ----
+    v4f acc[WRB][CB];
+    float ring[PF][WRB];
+#pragma unroll
+    for (int p = 0; p < PF; ++p) loadB(ring[p], p);
+    if (t + 1 < my_tiles) gload(tile + gridDim.x, 0);
+#pragma unroll
+    for (int i = 0; i < WRB; ++i)
+#pragma unroll
+      for (int j = 0; j < CB; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+    __syncthreads();
+    for (int c8 = 0; c8 < a.KsB / SPB; ++c8) {
+#pragma unroll
+      for (int s = 0; s < SPB; ++s) {
+        const int gs = c8 * SPB + s;
+        float af[CB];
+#pragma unroll
+        for (int j = 0; j < CB; ++j) af[j] = lds[(j * KSB + gs) * 64 + lane];
+        float bc[WRB];
+#pragma unroll
+        for (int i = 0; i < WRB; ++i) bc[i] = ring[s % PF][i];
+        if (gs + PF < a.KsB) loadB(ring[s % PF], gs + PF);
+#pragma unroll
+        for (int i = 0; i < WRB; ++i)
+#pragma unroll
+          for (int j = 0; j < CB; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[j], bc[i], acc[i][j], 0, 0, 0);
+      }
+    }
+    // ---- y_{k+1}(a', q' + C i_{k+1}) with q' = Q + (C / 8) i_k ----
+    const int64_t col0 = tile * TC;
+    const int64_t rhs = col0 / a.C;
+    const int64_t Q0 = (col0 - rhs * a.C) / 8;
+    float* dst = reinterpret_cast<float*>(a.out) + rhs * a.out_stride;
+#pragma unroll
+    for (int i = 0; i < WRB; ++i) {
+      const int row = 16 * (WRB * wr + i) + (lane & 15);
+      if (row >= a.R_outB) continue;
+      const int ar = row % a.r_outB, ir = row / a.r_outB;
+#pragma unroll
+      for (int j = 0; j < CB; ++j) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          // column c' = 16 j + 4 (lane div 16) + v = (Q - Q0) + 4 i_k
+          const int cp = 16 * j + 4 * (lane >> 4) + v;
+          const int64_t qp = Q0 + (cp & 3) + (a.C / 8) * (cp >> 2);
+          dst[ar + (int64_t)a.r_outB * (qp + a.C * ir)] = acc[i][j][v];
+        }
       }
     }
   }

@@ -477,6 +477,7 @@ struct qtt_matrix_s {
   bool fp64_t = false;    // FP64 sweeps in the rank-slowest layout on the vector ALUs
   bool fp64_t_ok = false; // every mode size is 8, so the mode is available
   bool fp64_pair = true;  // FP64 sweeps fuse interior core pairs where the pair kernel applies
+  bool fp32_pair = true;  // the same for FP32 sweeps
   // captured sweeps: a sweep with the same dtype, vectors, pointers, workspace
   // and alpha replays its graph instead of launching d kernels
   struct Graph {
@@ -817,19 +818,21 @@ static int64_t wave_capacity(const qtt_matrix_s* A, int dt, size_t ws_bytes) {
 // 2 (r_k != 24: the padded rank-32 kernel) + (R_out(k + 1) > 192), one per
 // kernel instantiation
 static const int kPairShape = 90;
+static const int kPairShape32 = 100;   // the same for the FP32 pair kernels
 static int64_t frag_bytes(const CoreDev& c, int dt) {
   return (int64_t)padded_row_blocks(c.nRB) * c.Ksteps[dt] * 64 * kFragE[dt] * kElemBytes[dt];
 }
 static bool pair_ok(const qtt_matrix_s* A, int dt, int k, const Segment* segs, int nseg) {
-  if (dt != 0 || !A->fp64_pair || k + 1 > A->d - 2) return false;   // core k + 1 is not the last
+  if (!((dt == 0 && A->fp64_pair) || (dt == 1 && A->fp32_pair)) || k + 1 > A->d - 2) return false;
   const CoreDev& x = A->core[k];
   const CoreDev& y = A->core[k + 1];
   const bool first = (k == 0);
   const int ra = x.r_out;
   if (!(ra >= 17 && ra <= 32 && x.m == 8 && y.n == 8 && y.K_in == 8 * ra && y.R_out <= 256)) return false;
-  if (x.Ksteps[0] % (first ? 2 : 8) != 0 || y.Ksteps[0] != (2 * ra + 7) / 8 * 8) return false;
-  if (x.C % 32 != 0 || x.C != y.C || x.K_in % 2 != 0) return false;
-  if (frag_bytes(x, 0) > INT32_MAX || frag_bytes(y, 0) > INT32_MAX) return false;
+  if (x.Ksteps[dt] % (first ? 2 : 8) != 0 || y.Ksteps[dt] != (2 * ra + 7) / 8 * 8) return false;
+  // 16-byte input loads: 2 FP64 or 4 FP32 values
+  if (x.C % 32 != 0 || x.C != y.C || x.K_in % ((first || dt == 0) ? 2 : 4) != 0) return false;
+  if (frag_bytes(x, dt) > INT32_MAX || frag_bytes(y, dt) > INT32_MAX) return false;
   if (first)
     for (int s = 0; s < nseg; ++s)
       if (reinterpret_cast<uintptr_t>(segs[s].x) % 16 != 0 || segs[s].ldx % 2 != 0) return false;
@@ -839,15 +842,19 @@ template <int RA, int WRB, bool FIRST>
 static const void* pair_fn() {
   return reinterpret_cast<const void*>(&core_pair_f64q_kernel<RA, WRB, FIRST, FIRST ? 8 : 32, 4>);
 }
-static qtt_status_t launch_pair(const qtt_matrix_s* A, int k, int64_t nrhs, const Segment* segs, int nseg,
-                                const void* in, void* out, hipStream_t st) {
+template <int RA, int WRB, bool FIRST>
+static const void* pair32_fn() {
+  return reinterpret_cast<const void*>(&core_pair_f32_kernel<RA, WRB, FIRST, FIRST ? 8 : 32, 4>);
+}
+static qtt_status_t launch_pair(const qtt_matrix_s* A, int dt, int k, int64_t nrhs, const Segment* segs,
+                                int nseg, const void* in, void* out, hipStream_t st) {
   const CoreDev& x = A->core[k];
   const CoreDev& y = A->core[k + 1];
   const bool first = (k == 0);
   PairArgs a;
   memset(&a, 0, sizeof(a));
-  a.MA = x.frag[0];
-  a.MB = y.frag[0];
+  a.MA = x.frag[dt];
+  a.MB = y.frag[dt];
   a.in = static_cast<const double*>(in);
   a.out = static_cast<double*>(out);
   a.in_stride = x.C * x.K_in;
@@ -855,24 +862,27 @@ static qtt_status_t launch_pair(const qtt_matrix_s* A, int k, int64_t nrhs, cons
   a.C = x.C;
   a.ncols = x.C * nrhs;
   a.n_tiles = a.ncols / 32;
-  a.KsA = x.Ksteps[0];
-  a.KsB = y.Ksteps[0];
+  a.KsA = x.Ksteps[dt];
+  a.KsB = y.Ksteps[dt];
   a.K_inA = x.K_in;
   a.R_outB = y.R_out;
   a.r_outB = y.r_out;
-  a.MA_bytes = (int32_t)frag_bytes(x, 0);
-  a.MB_bytes = (int32_t)frag_bytes(y, 0);
+  a.MA_bytes = (int32_t)frag_bytes(x, dt);
+  a.MB_bytes = (int32_t)frag_bytes(y, dt);
   a.nseg = first ? nseg : 0;
   a.ra = x.r_out;
   for (int s = 0; s < a.nseg; ++s) a.seg[s] = segs[s];
   // instantiation: rank of the fused boundary, rows of step k + 1, first core
-  static int occ[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  static const void* fns[8] = {pair_fn<24, 3, false>(), pair_fn<24, 4, false>(), pair_fn<32, 3, false>(),
-                               pair_fn<32, 4, false>(), pair_fn<24, 3, true>(),  pair_fn<24, 4, true>(),
-                               pair_fn<32, 3, true>(),  pair_fn<32, 4, true>()};
+  static int occ[16] = {};
+  static const void* fns[16] = {
+      pair_fn<24, 3, false>(),   pair_fn<24, 4, false>(),   pair_fn<32, 3, false>(),   pair_fn<32, 4, false>(),
+      pair_fn<24, 3, true>(),    pair_fn<24, 4, true>(),    pair_fn<32, 3, true>(),    pair_fn<32, 4, true>(),
+      pair32_fn<24, 3, false>(), pair32_fn<24, 4, false>(), pair32_fn<32, 3, false>(), pair32_fn<32, 4, false>(),
+      pair32_fn<24, 3, true>(),  pair32_fn<24, 4, true>(),  pair32_fn<32, 3, true>(),  pair32_fn<32, 4, true>()};
   // exact rank-24 kernels for r_k = 24, the padded rank-32 ones otherwise
   const int v = (first ? 4 : 0) + (x.r_out != 24 ? 2 : 0) + (y.R_out > 192 ? 1 : 0);
-  const int64_t resident = (int64_t)occupancy_fn(fns[v], 256, &occ[v]) * num_cus();
+  const int f = (dt == 1 ? 8 : 0) + v;
+  const int64_t resident = (int64_t)occupancy_fn(fns[f], 256, &occ[f]) * num_cus();
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(a.n_tiles, resident));
   TimedLaunch tl;
   const bool timed = timing_on();
@@ -882,14 +892,14 @@ static qtt_status_t launch_pair(const qtt_matrix_s* A, int k, int64_t nrhs, cons
     HIP_TRY(hipEventRecord(tl.a, st));
   }
   void* args[] = {&a};
-  HIP_TRY(hipLaunchKernel(fns[v], dim3(grid), dim3(256), args, 0, st));
+  HIP_TRY(hipLaunchKernel(fns[f], dim3(grid), dim3(256), args, 0, st));
   if (timed) {
     HIP_TRY(hipEventRecord(tl.b, st));
-    tl.dt = 0;
+    tl.dt = dt;
     tl.pos = first ? 1 : 0;
-    tl.shape = kPairShape + v;
+    tl.shape = (dt == 1 ? kPairShape32 : kPairShape) + v;
     tl.flops = 2.0 * ((double)x.R_out * x.K_in + (double)y.R_out * y.K_in) * (double)a.ncols;
-    tl.bytes = (double)a.ncols * ((double)x.K_in + y.R_out) * 8.0;
+    tl.bytes = (double)a.ncols * ((double)x.K_in * (first ? 8 : kElemBytes[dt]) + (double)y.R_out * kElemBytes[dt]);
     g_timed.push_back(tl);
   }
   return QTT_OK;
@@ -918,7 +928,7 @@ static qtt_status_t sweep(const qtt_matrix_s* A, int dt, int64_t nrhs, const Seg
   for (int k = 0; k < A->d;) {
     const void* in = (k == 0) ? nullptr : buf[cur];
     if (!tsw && pair_ok(A, dt, k, segs, nseg)) {
-      qtt_status_t s = launch_pair(A, k, nrhs, segs, nseg, in, buf[cur ^ 1], st);
+      qtt_status_t s = launch_pair(A, dt, k, nrhs, segs, nseg, in, buf[cur ^ 1], st);
       if (s != QTT_OK) return s;
       cur ^= 1;
       k += 2;
@@ -1149,11 +1159,11 @@ qtt_status_t qtt_matrix_load(int32_t d, const int64_t* ranks, const int64_t* m, 
       if (!(dtypes & (1u << t))) continue;
       const int KS = kKstep[t], E = kFragE[t];
       int Ksteps = (c.K_in + KS - 1) / KS;
-      // FP64 cores of more than 8 steps get zero steps up to a multiple of 8,
+      // FP64 and FP32 cores of more than 8 steps get zero steps up to a multiple of 8,
       // the chunk of the streamed 4x4x4 kernels (so any rank can use them;
       // every kernel reads input indices past K_in as zeros or as finite data
       // multiplied by these zero core values)
-      if (t == 0 && Ksteps > 8) Ksteps = (Ksteps + 7) / 8 * 8;
+      if (t <= 1 && Ksteps > 8) Ksteps = (Ksteps + 7) / 8 * 8;
       c.Ksteps[t] = Ksteps;
       // row blocks padded with zeros so that every tile height of the
       // registry covers a whole number of tiles: kernels may then read the
@@ -1456,11 +1466,12 @@ qtt_status_t qtt_autotune(qtt_matrix_t A, qtt_dtype_t compute, int64_t nrhs, con
     if (tune_log())
       fprintf(stderr, "qtt_autotune dtype 0 whole sweep: standard %.4f ms, fused pairs %.4f ms, rank-slowest %.4f ms\n",
               ms_mode[0] / 2, ms_mode[1] / 2, ms_mode[2] / 2);
-  } else if (dt == 0) {
-    // no rank-slowest mode: fused pairs against the standard sweep
+  } else if (dt <= 1) {
+    // fused pairs against the standard sweep
+    bool& pair = (dt == 0) ? A->fp64_pair : A->fp32_pair;
     float ms_mode[2] = {0, 0};
     for (int mode = 0; mode < 2; ++mode) {
-      A->fp64_pair = (mode == 1);
+      pair = (mode == 1);
       for (int rep = 0; rep < 2; ++rep) {
         HIP_TRY(hipEventRecord(e0, st));
         for (int it = 0; it < 2; ++it) {
@@ -1472,7 +1483,10 @@ qtt_status_t qtt_autotune(qtt_matrix_t A, qtt_dtype_t compute, int64_t nrhs, con
       HIP_TRY(hipEventSynchronize(e1));
       HIP_TRY(hipEventElapsedTime(&ms_mode[mode], e0, e1));
     }
-    A->fp64_pair = ms_mode[1] < ms_mode[0];
+    pair = ms_mode[1] < ms_mode[0];
+    if (tune_log())
+      fprintf(stderr, "qtt_autotune dtype %d whole sweep: standard %.4f ms, fused pairs %.4f ms\n", dt,
+              ms_mode[0] / 2, ms_mode[1] / 2);
   }
   g_timing = was_timing;
   drop_graphs(A);
@@ -1508,9 +1522,9 @@ qtt_status_t qtt_set_shape(qtt_matrix_t A, qtt_dtype_t compute, int32_t core, in
   int dt;
   qtt_status_t s = check_dtype(A, compute, &dt);
   if (s != QTT_OK) return s;
-  if (core == -2) {               // fused interior core pairs (FP64) on/off
-    if (dt != 0 || (shape != 0 && shape != 1)) return fail(QTT_ERR_INVALID_ARG, "core -2 takes shape 0 or 1 (FP64)");
-    A->fp64_pair = (shape == 1);
+  if (core == -2) {               // fused core pairs (FP64, FP32) on/off
+    if (dt == 2 || (shape != 0 && shape != 1)) return fail(QTT_ERR_INVALID_ARG, "core -2 takes shape 0 or 1 (FP64, FP32)");
+    (dt == 0 ? A->fp64_pair : A->fp32_pair) = (shape == 1);
     drop_graphs(A);
     return QTT_OK;
   }
@@ -1536,8 +1550,9 @@ qtt_status_t qtt_set_shape(qtt_matrix_t A, qtt_dtype_t compute, int32_t core, in
     if (!found) return fail(QTT_ERR_INVALID_ARG, "shape %d is not a configuration for dtype %d", shape, (int)compute);
   }
   A->core[core].tuned[dt] = shape;
-  // a pinned FP64 configuration is what runs: fused pairs would bypass it
+  // a pinned configuration is what runs: fused pairs would bypass it
   if (dt == 0 && shape != -1) A->fp64_pair = false;
+  if (dt == 1 && shape != -1) A->fp32_pair = false;
   drop_graphs(A);
   return QTT_OK;
 }

@@ -23,9 +23,10 @@ LIB_PATH = os.path.join(_PKG, "libqtt.so")
 QTT_FP64, QTT_FP32, QTT_BF16 = 1, 2, 4
 DTYPES = {"fp64": QTT_FP64, "fp32": QTT_FP32, "bf16": QTT_BF16}
 
-# configuration ids under which launches of the fused FP64 core pairs are
-# timed (90 + 4 first core + 2 rank 32 + rows of the second core above 192)
-PAIR_SHAPES = list(range(90, 98))
+# configuration ids under which launches of the fused core pairs are timed:
+# FP64 90.., FP32 100.. (+ 4 first core + 2 padded rank-32 kernel + rows of
+# the second core above 192)
+PAIR_SHAPES = list(range(90, 98)) + list(range(100, 108))
 
 QTT_OK = 0
 QTT_ERR_NOT_CONVERGED = 5
