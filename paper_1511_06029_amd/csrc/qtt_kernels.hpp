@@ -2607,6 +2607,93 @@ __global__ void __launch_bounds__(256) core_step_smallk_kernel(const StepArgs ar
 }
 
 // ---------------------------------------------------------------------------
+// Last core step of a BF16 sweep (r_d = 1, R_out = m_d <= 8) on the vector
+// ALUs with FP32 accumulation.
+//
+// The product is at most 8 x K_in with K_in up to 256: too few rows for a
+// matrix instruction, and the step is bound by reading the K_in BF16 values
+// of every column.  Four lanes share a column, each contracting a quarter of
+// it with 16-byte loads (8 BF16 values); the core, decoded once per workgroup
+// from its fragment buffer (the same values as the matrix-core kernels),
+// sits in LDS as Ms[k][row] and is read as two 16-byte broadcasts per
+// contraction index; a butterfly over the four lanes completes the sums, and
+// the four lanes write the FP64 output Y = Z + alpha (A X) (rows h, h + 4 for
+// lane h), which is the step's fused epilogue.
+// Requirements checked by the host: last core of a BF16 sweep (input packed,
+// output through the segment table), R_out <= 8, K_in % 32 == 0, K_in <= 256.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) core_step_lastk_bf16_kernel(const StepArgs args) {
+  (void)args;
+  const StepArgs& a = kernarg<StepArgs>();
+  constexpr int NT = 256, MAXK = 256, RP = 8, CPB = NT / 4;   // columns per workgroup pass
+  __shared__ __attribute__((aligned(16))) float Ms[MAXK * RP];
+  const int tid = threadIdx.x;
+  const int K = a.K_in, R = a.R_out, Ks = a.Ksteps;
+  const uint16_t* __restrict__ Mf = reinterpret_cast<const uint16_t*>(a.M);
+  for (int idx = tid; idx < K * RP; idx += NT) {
+    const int k = idx / RP, row = idx - k * RP;
+    float v = 0.f;
+    if (row < R) {
+      const int l = (row & 15) + 16 * ((k & 31) >> 3);
+      const uint16_t b = Mf[(((int64_t)(row >> 4) * Ks + (k >> 5)) * 64 + l) * 8 + (k & 7)];
+      v = __builtin_bit_cast(float, (uint32_t)b << 16);
+    }
+    Ms[idx] = v;
+  }
+  __syncthreads();
+  const int h = tid & 3;
+  const int kq = K / 4;                            // contraction indices per lane (multiple of 8)
+  const uint16_t* __restrict__ in = reinterpret_cast<const uint16_t*>(a.in);
+  for (int64_t g = (int64_t)blockIdx.x * CPB + (tid >> 2); g < a.ncols; g += (int64_t)gridDim.x * CPB) {
+    const int64_t rhs = g / a.C;
+    const int64_t q = g - rhs * a.C;
+    const v4u* src = reinterpret_cast<const v4u*>(in + rhs * a.in_stride + q * K + h * kq);
+    float acc[RP];
+#pragma unroll
+    for (int r = 0; r < RP; ++r) acc[r] = 0.f;
+    for (int v = 0; v < kq / 8; ++v) {
+      const v4u x8 = src[v];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const uint32_t w = x8[e >> 1];
+        const float xv = __builtin_bit_cast(float, (e & 1) ? (w & 0xffff0000u) : (w << 16));
+        const int k = h * kq + 8 * v + e;
+        const v4f m0 = *reinterpret_cast<const v4f*>(&Ms[k * RP]);
+        const v4f m1 = *reinterpret_cast<const v4f*>(&Ms[k * RP + 4]);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          acc[r] = fmaf(m0[r], xv, acc[r]);
+          acc[r + 4] = fmaf(m1[r], xv, acc[r + 4]);
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < RP; ++r) {
+      acc[r] += __shfl_xor(acc[r], 1);
+      acc[r] += __shfl_xor(acc[r], 2);
+    }
+    // row = i_d (r_d = 1): output q + C_d i_d
+    const Segment& sg = a.seg[find_seg(a, rhs)];
+    const int64_t vr = rhs - sg.rhs_begin;
+    // lane h writes rows h and h + 4 (selected without indexing registers)
+    float sel[2] = {acc[0], acc[4]};
+    if (h == 1) { sel[0] = acc[1]; sel[1] = acc[5]; }
+    if (h == 2) { sel[0] = acc[2]; sel[1] = acc[6]; }
+    if (h == 3) { sel[0] = acc[3]; sel[1] = acc[7]; }
+#pragma unroll
+    for (int r2 = 0; r2 < 2; ++r2) {
+      const int row = h + 4 * r2;
+      if (row < R) {
+        const int64_t off = q + a.C * row;
+        double res = a.alpha * (double)sel[r2];
+        if (sg.z != nullptr) res += sg.z[vr * sg.ldz + off];
+        sg.y[vr * sg.ldy + off] = res;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // column norms: ||R_c||_2 for every column, two deterministic passes (the
 // summation order depends only on the column length, never on the batch).
 // ---------------------------------------------------------------------------

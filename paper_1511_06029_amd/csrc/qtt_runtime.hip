@@ -166,6 +166,7 @@ static KernelCfg make_cfg(int dt, bool in_f64, int id) {
   X(74, 2, 8, 32, 2)
 static const int kGenericShape = 6;
 static const int kSmallK = 34;   // first core with a short contraction (vector ALUs)
+static const int kLastK = 35;    // BF16 last core with at most 8 rows (vector ALUs)
 
 template <class Tc, class Tin, int KC1, int KC2>
 static void add_family(std::vector<KernelCfg>& v, int dt, bool in_f64) {
@@ -393,6 +394,26 @@ static KernelCfg* smallk_cfg(int dt) {
     }
   });
   return &k[dt];
+}
+
+// BF16 last core on the vector ALUs (shape id 35).
+static KernelCfg* lastk_cfg() {
+  static KernelCfg k = [] {
+    KernelCfg c;
+    c.dt = 2;
+    c.in_f64 = false;
+    c.vec = true;
+    c.TR = 256;
+    c.TC = 64;
+    c.KC = 32;
+    c.NT = 256;
+    c.id = kLastK;
+    c.fn = reinterpret_cast<const void*>(&core_step_lastk_bf16_kernel);
+    c.occ = 0;
+    c.kind = -1;
+    return c;
+  }();
+  return &k;
 }
 
 // FP64 interior kernel fed by direct global-to-LDS loads (shape id 32).
@@ -738,7 +759,11 @@ static qtt_status_t launch_step(const qtt_matrix_s* A, int k, int dt, int64_t nr
                          c.r_out % 4 == 0 && c.C % tq == 0 && (c.r_out * tq * kElemBytes[dt]) % 16 == 0 &&
                          reinterpret_cast<uintptr_t>(out_packed) % 16 == 0;
   if (shape == kSmallK && !smallk_ok) shape = (dt == 0) ? 67 : 26;   // first-core matrix-core kernels
+  const bool lastk_ok = dt == 2 && last && !first && c.R_out <= 8 && c.K_in % 32 == 0 && c.K_in <= 256 &&
+                        reinterpret_cast<uintptr_t>(in_packed) % 16 == 0;
+  if (shape == kLastK && !lastk_ok) shape = 2;
   KernelCfg* kc = (shape == kSmallK) ? smallk_cfg(dt)
+                  : (shape == kLastK) ? lastk_cfg()
                   : (shape == kF64Dma) ? f64_dma_cfg()
                   : (shape == kBf16Dma) ? bf16_dma_cfg()
                   : (shape == kBf16Dma32) ? bf16_dma32_cfg()
@@ -1390,6 +1415,7 @@ qtt_status_t qtt_autotune(qtt_matrix_t A, qtt_dtype_t compute, int64_t nrhs, con
     }
     if (dt == 0 && k > 0 && k < A->d - 1) ids.push_back(kF64Dma);
     if (k == 0 && A->d > 1) ids.push_back(kSmallK);
+    if (dt == 2 && k == A->d - 1 && k > 0) ids.push_back(kLastK);
     if (dt == 0)
       for (auto& vc : valu_registry())
         if (vc.G == 1 || c.K_in % vc.G == 0) ids.push_back(vc.id);
@@ -1506,7 +1532,7 @@ qtt_status_t qtt_list_shapes(qtt_dtype_t compute, int32_t* ids, int32_t cap, int
   if (dt < 0 || !count || (cap > 0 && !ids)) return fail(QTT_ERR_INVALID_ARG, "bad arguments");
   std::vector<int> v = shape_ids(dt, dt == 0);
   v.push_back(kSmallK);
-  if (dt == 2) { v.push_back(kBf16Resident); v.push_back(kBf16Dma); v.push_back(kBf16Dma32); }
+  if (dt == 2) { v.push_back(kBf16Resident); v.push_back(kBf16Dma); v.push_back(kBf16Dma32); v.push_back(kLastK); }
   if (dt == 0) {
     v.push_back(kF64Dma);
     for (auto& vc : valu_registry()) v.push_back(vc.id);
