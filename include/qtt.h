@@ -199,8 +199,9 @@ qtt_status_t qtt_timing_read(qtt_dtype_t compute, int32_t position, int64_t* lau
 /* The same sums over the launches of one kernel configuration id (any core
  * position); ids as in qtt_list_shapes, plus 90..97 (FP64) and 100..107
  * (FP32) for the kernels that apply two consecutive cores k, k + 1 in one
- * launch: base + 4 (k is the first core) + 2 (the padded kernel for any r_k
- * in 17..32 other than 24) + (R_out of core k + 1 above 192).
+ * launch: base + 4 (k is the first core) + 2 (r_k other than 24: the
+ * 256-row kernel, exact at r_k = 32, padded for the other ranks in 17..32)
+ * + (R_out of core k + 1 above 192).
  * Such a launch is recorded at the position of core k, with the flops of
  * both cores.  Launches of a configuration id that was never timed give
  * zeros. */

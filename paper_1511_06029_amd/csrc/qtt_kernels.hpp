@@ -1030,8 +1030,8 @@ core_step_f64q_kernel(const StepArgs args) {
 // Two consecutive FP64 core steps k, k + 1 in one pass over a column tile,
 // on the 4x4x4 matrix instruction: the tile's intermediate y_k stays on chip.
 //
-// For cores with r_k = RA (24 or 32; the RA = 32 kernels also take any r_k
-// from 17 to 32, padded) and m_k = n_{k+1} = 8.  A tile is 32
+// For cores with r_k = RA (24 or 32; with PAD, the RA = 32 kernel takes any
+// r_k from 17 to 32, padded) and m_k = n_{k+1} = 8.  A tile is 32
 // consecutive columns q = j_{k+1} + 8 Q of b_k, four values of Q.  Step k
 // gives phi_k(a_k + RA i_k, j_{k+1} + 8 Q) for all 8 RA rows.  By the row
 // separation of step k and the reshape into b_{k+1} (Algorithm 2), these are
@@ -1069,7 +1069,7 @@ struct PairArgs {
   Segment seg[kMaxSeg];
 };
 
-template <int RA, int WRB, bool FIRST, int KCA, int PF>
+template <int RA, int WRB, bool FIRST, int KCA, int PF, bool PAD = false>
 __global__ void __launch_bounds__(256, 2) core_pair_f64q_kernel(const PairArgs args) {
   (void)args;
   const PairArgs& a = kernarg<PairArgs>();
@@ -1082,6 +1082,7 @@ __global__ void __launch_bounds__(256, 2) core_pair_f64q_kernel(const PairArgs a
   constexpr int KSB = 2 * RA;                      // LDS steps of step k + 1 (K_in <= 8 RA)
   constexpr int X_ELEMS = (TC / 4) * KSB * kQGS;   // b_{k+1} tile
   static_assert(RA == 24 || RA == 32, "rank of the fused boundary");
+  static_assert(!PAD || RA == 32, "padded ranks use the 256-row kernel");
   static_assert(SPA % PFA == 0 && SPB % PF == 0 && KSB % SPB == 0, "whole prefetch rounds");
   static_assert(2 * A_ELEMS <= X_ELEMS, "stages alias the tile");
   __shared__ __attribute__((aligned(16))) double lds[X_ELEMS];
@@ -1091,11 +1092,12 @@ __global__ void __launch_bounds__(256, 2) core_pair_f64q_kernel(const PairArgs a
   const int wr = tid >> 6;
   const int rd = 4 * (lane & 3) + (lane >> 4);
   const int nchA = a.KsA / SPA;
-  // the boundary rank: RA itself, or (RA = 32) any ra in 17..32 with step k's
+  // the boundary rank: RA itself, or (PAD) any ra in 17..32 with step k's
   // rows padded to 8 RA (zero fragment rows) and step k + 1's contraction to
   // a.KsB steps (zero core steps past 8 ra, zero LDS values there)
-  const int ra = (RA == 32) ? a.ra : RA;
+  const int ra = PAD ? a.ra : RA;
   const int kin_b = 8 * ra;
+  const int ksb = PAD ? a.KsB : KSB;
   const int64_t my_tiles = (a.n_tiles > (int64_t)blockIdx.x)
                                ? (a.n_tiles - 1 - (int64_t)blockIdx.x) / gridDim.x + 1 : 0;
   if (my_tiles == 0) return;
@@ -1215,7 +1217,7 @@ __global__ void __launch_bounds__(256, 2) core_pair_f64q_kernel(const PairArgs a
         }
       }
       // contraction indices 8 ra .. 4 KsB of every column: zeros
-      if (RA == 32 && kin_b < 4 * a.KsB) {
+      if (PAD && kin_b < 4 * a.KsB) {
         const int pad = 4 * a.KsB - kin_b;
         for (int e = tid; e < TC * pad; e += NT) {
           const int c = e / pad, kap = kin_b + (e - c * pad);
@@ -1234,7 +1236,7 @@ __global__ void __launch_bounds__(256, 2) core_pair_f64q_kernel(const PairArgs a
 #pragma unroll
       for (int j = 0; j < WQ; ++j) acc[i][j] = 0.0;
     __syncthreads();
-    for (int c8 = 0; c8 < a.KsB / SPB; ++c8) {
+    for (int c8 = 0; c8 < ksb / SPB; ++c8) {
 #pragma unroll
       for (int s = 0; s < SPB; ++s) {
         const int gs = c8 * SPB + s;
@@ -1244,7 +1246,7 @@ __global__ void __launch_bounds__(256, 2) core_pair_f64q_kernel(const PairArgs a
         double bc[WRB];
 #pragma unroll
         for (int i = 0; i < WRB; ++i) bc[i] = ring[s % PF][i];
-        if (gs + PF < a.KsB) loadB(ring[s % PF], gs + PF);
+        if (gs + PF < ksb) loadB(ring[s % PF], gs + PF);
 #pragma unroll
         for (int i = 0; i < WRB; ++i)
 #pragma unroll
@@ -1284,7 +1286,7 @@ __global__ void __launch_bounds__(256, 2) core_pair_f64q_kernel(const PairArgs a
 // the same fragment order (column c' = (Q - Q0) + 4 i_k), 32 KB at r_k = 32.
 // Requirements as for the FP64 pair.
 // ---------------------------------------------------------------------------
-template <int RA, int WRB, bool FIRST, int KCA, int PF>
+template <int RA, int WRB, bool FIRST, int KCA, int PF, bool PAD = false>
 __global__ void __launch_bounds__(256, 2) core_pair_f32_kernel(const PairArgs args) {
   (void)args;
   const PairArgs& a = kernarg<PairArgs>();
@@ -1308,8 +1310,10 @@ __global__ void __launch_bounds__(256, 2) core_pair_f32_kernel(const PairArgs ar
   const int lane = tid & 63;
   const int wr = tid >> 6;
   const int nchA = a.KsA / SPA;
-  const int ra = (RA == 32) ? a.ra : RA;
+  static_assert(!PAD || RA == 32, "padded ranks use the 256-row kernel");
+  const int ra = PAD ? a.ra : RA;
   const int kin_b = 8 * ra;
+  const int ksb = PAD ? a.KsB : KSB;
   const int64_t my_tiles = (a.n_tiles > (int64_t)blockIdx.x)
                                ? (a.n_tiles - 1 - (int64_t)blockIdx.x) / gridDim.x + 1 : 0;
   if (my_tiles == 0) return;
@@ -1436,7 +1440,7 @@ __global__ void __launch_bounds__(256, 2) core_pair_f32_kernel(const PairArgs ar
           }
         }
       }
-      if (RA == 32 && kin_b < 4 * a.KsB) {
+      if (PAD && kin_b < 4 * a.KsB) {
         const int pad = 4 * a.KsB - kin_b;
         for (int e = tid; e < TC * pad; e += NT) {
           const int c = e / pad, kap = kin_b + (e - c * pad);
@@ -1455,7 +1459,7 @@ __global__ void __launch_bounds__(256, 2) core_pair_f32_kernel(const PairArgs ar
 #pragma unroll
       for (int j = 0; j < CB; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
     __syncthreads();
-    for (int c8 = 0; c8 < a.KsB / SPB; ++c8) {
+    for (int c8 = 0; c8 < ksb / SPB; ++c8) {
 #pragma unroll
       for (int s = 0; s < SPB; ++s) {
         const int gs = c8 * SPB + s;
@@ -1465,7 +1469,7 @@ __global__ void __launch_bounds__(256, 2) core_pair_f32_kernel(const PairArgs ar
         float bc[WRB];
 #pragma unroll
         for (int i = 0; i < WRB; ++i) bc[i] = ring[s % PF][i];
-        if (gs + PF < a.KsB) loadB(ring[s % PF], gs + PF);
+        if (gs + PF < ksb) loadB(ring[s % PF], gs + PF);
 #pragma unroll
         for (int i = 0; i < WRB; ++i)
 #pragma unroll

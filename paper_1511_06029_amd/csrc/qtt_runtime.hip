@@ -863,13 +863,16 @@ static bool pair_ok(const qtt_matrix_s* A, int dt, int k, const Segment* segs, i
       if (reinterpret_cast<uintptr_t>(segs[s].x) % 16 != 0 || segs[s].ldx % 2 != 0) return false;
   return true;
 }
+// RA = 24 and 32 exact; "RA = 33" stands for the padded 256-row kernel
 template <int RA, int WRB, bool FIRST>
 static const void* pair_fn() {
-  return reinterpret_cast<const void*>(&core_pair_f64q_kernel<RA, WRB, FIRST, FIRST ? 8 : 32, 4>);
+  constexpr int R = RA > 32 ? 32 : RA;
+  return reinterpret_cast<const void*>(&core_pair_f64q_kernel<R, WRB, FIRST, FIRST ? 8 : 32, 4, (RA > 32)>);
 }
 template <int RA, int WRB, bool FIRST>
 static const void* pair32_fn() {
-  return reinterpret_cast<const void*>(&core_pair_f32_kernel<RA, WRB, FIRST, FIRST ? 8 : 32, 4>);
+  constexpr int R = RA > 32 ? 32 : RA;
+  return reinterpret_cast<const void*>(&core_pair_f32_kernel<R, WRB, FIRST, FIRST ? 8 : 32, 4, (RA > 32)>);
 }
 static qtt_status_t launch_pair(const qtt_matrix_s* A, int dt, int k, int64_t nrhs, const Segment* segs,
                                 int nseg, const void* in, void* out, hipStream_t st) {
@@ -898,15 +901,21 @@ static qtt_status_t launch_pair(const qtt_matrix_s* A, int dt, int k, int64_t nr
   a.ra = x.r_out;
   for (int s = 0; s < a.nseg; ++s) a.seg[s] = segs[s];
   // instantiation: rank of the fused boundary, rows of step k + 1, first core
-  static int occ[16] = {};
-  static const void* fns[16] = {
+  // index: 12 dt + 6 first + 2 (0: rank 24, 1: rank 32, 2: padded 17..32) + (rows of core k + 1 > 192)
+  static int occ[24] = {};
+  static const void* fns[24] = {
       pair_fn<24, 3, false>(),   pair_fn<24, 4, false>(),   pair_fn<32, 3, false>(),   pair_fn<32, 4, false>(),
+      pair_fn<33, 3, false>(),   pair_fn<33, 4, false>(),
       pair_fn<24, 3, true>(),    pair_fn<24, 4, true>(),    pair_fn<32, 3, true>(),    pair_fn<32, 4, true>(),
+      pair_fn<33, 3, true>(),    pair_fn<33, 4, true>(),
       pair32_fn<24, 3, false>(), pair32_fn<24, 4, false>(), pair32_fn<32, 3, false>(), pair32_fn<32, 4, false>(),
-      pair32_fn<24, 3, true>(),  pair32_fn<24, 4, true>(),  pair32_fn<32, 3, true>(),  pair32_fn<32, 4, true>()};
-  // exact rank-24 kernels for r_k = 24, the padded rank-32 ones otherwise
+      pair32_fn<33, 3, false>(), pair32_fn<33, 4, false>(),
+      pair32_fn<24, 3, true>(),  pair32_fn<24, 4, true>(),  pair32_fn<32, 3, true>(),  pair32_fn<32, 4, true>(),
+      pair32_fn<33, 3, true>(),  pair32_fn<33, 4, true>()};
+  const int rk = (x.r_out == 24) ? 0 : (x.r_out == 32 ? 1 : 2);
+  const int f = (dt == 1 ? 12 : 0) + (first ? 6 : 0) + 2 * rk + (y.R_out > 192 ? 1 : 0);
+  // timing id: exact rank 24, else the 256-row kernels (exact or padded)
   const int v = (first ? 4 : 0) + (x.r_out != 24 ? 2 : 0) + (y.R_out > 192 ? 1 : 0);
-  const int f = (dt == 1 ? 8 : 0) + v;
   const int64_t resident = (int64_t)occupancy_fn(fns[f], 256, &occ[f]) * num_cus();
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(a.n_tiles, resident));
   TimedLaunch tl;
