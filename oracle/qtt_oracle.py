@@ -18,6 +18,11 @@ equations in complex geometries", arXiv:1511.06029):
   A_T(b_1..b_d) with b_k = (i_k, j_k)); a core is G_k(a_{k-1}, i_k, j_k, a_k).
 * matrix by full vector -- section 4.2, Algorithm 2 (alg:TT-matvec).
 * TT-SVD -- section 2.2, Algorithm 1 (alg:TT-dec).
+* outer Krylov solver -- section 5.2 (boundary integral equations): the
+  compressed approximate inverse preconditions an unrestarted GMRES with a
+  relative-residual tolerance of 1e-8.  Because a low-precision inverse apply
+  is linear only up to rounding, the solver here is the flexible variant
+  (FGMRES, Saad 1993), which keeps the preconditioned directions.
 
 Array conventions used throughout: a QTT matrix is a list of FP64 numpy arrays
 ``cores[k]`` of shape ``(r_{k-1}, m_k, n_k, r_k)``; a block of vectors is an
@@ -28,13 +33,15 @@ Everything is FP64.  Reshapes that the paper writes in Matlab notation use
 """
 from __future__ import annotations
 
+import math
+
 import numpy as np
 
 __all__ = [
     "qtt_shapes", "qtt_entry", "qtt_to_dense", "qtt_apply_alg2",
     "alg2_flops", "tt_svd", "qtt_matrix_from_dense", "morton_points",
     "volume_self_term", "volume_matrix", "volume_apply_direct",
-    "richardson_solve",
+    "richardson_solve", "fgmres_solve",
 ]
 
 
@@ -320,3 +327,83 @@ def richardson_solve(A_cores, Ainv_cores, F, rtol=1e-8, max_iter=50):
         if np.all(rel <= rtol):
             break
     return (X[:, 0] if one else X), history
+
+
+# --------------------------------------------------------------------------
+# the outer Krylov solver: flexible GMRES, right preconditioner (sec. 5.2)
+# --------------------------------------------------------------------------
+
+def fgmres_solve(apply_A, apply_M, F, rtol=1e-8, max_iter=50):
+    """sigma with A sigma = F by unrestarted flexible GMRES, one column at a
+    time, as section 5.2 uses GMRES (no restart, relative-residual tolerance)
+    with the compressed inverse as right preconditioner.
+
+    The steps are Saad's FGMRES (SIAM J. Sci. Comput. 14, 1993), written out
+    plainly: x_0 = 0, v_1 = f / ||f||; for j = 1, 2, ...
+        z_j = M v_j;  w = A z_j;
+        modified Gram-Schmidt: h_ij = <w, v_i>, w -= h_ij v_i  (i = 1..j);
+        h_{j+1,j} = ||w||;  v_{j+1} = w / h_{j+1,j};
+        Givens rotations reduce the (j+1) x j Hessenberg matrix to upper
+        triangular form; the last rotated right-hand-side entry |g_{j+1}| is
+        the residual norm ||f - A x_j||;
+    stop when |g_{j+1}| <= rtol ||f|| (or on breakdown h_{j+1,j} = 0); then
+    x = Z y with R y = g (the stored z_j, not M applied to V y, so M may change
+    from one step to the next).
+
+    apply_A, apply_M: functions of one FP64 vector (N,) returning (N,);
+    apply_M = None means no preconditioner (z_j = v_j).
+    Returns (X, history, iters): history[c][t] = |g_{t+2}| / ||f_c|| after step
+    t+1 of column c, iters[c] = the steps that column took."""
+    F = np.asarray(F, dtype=np.float64)
+    one = F.ndim == 1
+    F2 = F[:, None] if one else F
+    N, K = F2.shape
+    X = np.zeros_like(F2)
+    history, iters = [], []
+    for c in range(K):
+        f = F2[:, c]
+        beta = float(np.linalg.norm(f))
+        hist = []
+        if beta == 0.0:
+            history.append(hist)
+            iters.append(0)
+            continue
+        V = [f / beta]
+        Z = []
+        H = np.zeros((max_iter + 1, max_iter))
+        g = np.zeros(max_iter + 1)
+        g[0] = beta
+        cs = np.zeros(max_iter)
+        sn = np.zeros(max_iter)
+        k = 0
+        for j in range(max_iter):
+            z = V[j] if apply_M is None else np.asarray(apply_M(V[j]), dtype=np.float64)
+            Z.append(z)
+            w = np.asarray(apply_A(z), dtype=np.float64).copy()
+            for i in range(j + 1):
+                H[i, j] = np.dot(w, V[i])
+                w = w - H[i, j] * V[i]
+            hnext = float(np.linalg.norm(w))
+            H[j + 1, j] = hnext
+            for i in range(j):
+                a, b = H[i, j], H[i + 1, j]
+                H[i, j] = cs[i] * a + sn[i] * b
+                H[i + 1, j] = -sn[i] * a + cs[i] * b
+            d = math.hypot(H[j, j], H[j + 1, j])
+            cs[j], sn[j] = H[j, j] / d, H[j + 1, j] / d
+            H[j, j] = d
+            H[j + 1, j] = 0.0
+            g[j + 1] = -sn[j] * g[j]
+            g[j] = cs[j] * g[j]
+            hist.append(abs(g[j + 1]) / beta)
+            k = j + 1
+            if abs(g[j + 1]) <= rtol * beta or hnext == 0.0:
+                break
+            V.append(w / hnext)
+        y = np.zeros(k)
+        for i in range(k - 1, -1, -1):
+            y[i] = (g[i] - np.dot(H[i, i + 1:k], y[i + 1:k])) / H[i, i]
+        X[:, c] = sum(y[i] * Z[i] for i in range(k))
+        history.append(hist)
+        iters.append(k)
+    return (X[:, 0] if one else X), history, iters

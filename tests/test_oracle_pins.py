@@ -285,3 +285,117 @@ def test_richardson_volume_L4(volume_L4):
     ref = np.linalg.solve(A, F)
     assert hist[-1][0] <= 1e-8
     assert _rel(X, ref) < 1e-8
+
+
+# ---------------------------------------------------------------- FGMRES (sec. 5.2)
+
+def _dense_problem(n, seed, shift=3.0):
+    g = I.rng(seed)
+    A = shift * np.eye(n) + g.standard_normal((n, n)) / math.sqrt(n)
+    f = g.standard_normal(n)
+    return A, f
+
+
+def test_fgmres_terminates_in_n_steps():
+    """Unpreconditioned GMRES on an n x n system reaches the exact solution
+    in at most n steps (the Krylov space is the whole space); checked
+    against an LU solve."""
+    A, f = _dense_problem(12, 501, shift=0.5)
+    x, hist, it = O.fgmres_solve(lambda v: A @ v, None, f, rtol=0.0, max_iter=12)
+    assert it[0] <= 12
+    assert _rel(x, np.linalg.solve(A, f)) < 1e-10
+    assert hist[0][-1] < 1e-12
+
+
+def test_fgmres_estimate_is_true_residual():
+    """The Givens-rotated right-hand side gives ||f - A x_k|| exactly (up to
+    rounding) at every k: a wrong rotation sign or index breaks this."""
+    A, f = _dense_problem(40, 502, shift=1.0)
+    Mi = np.linalg.inv(A + 0.3 * I.rng(503).standard_normal((40, 40)) / math.sqrt(40))
+    for k in range(1, 9):
+        x, hist, it = O.fgmres_solve(lambda v: A @ v, lambda v: Mi @ v, f, rtol=0.0, max_iter=k)
+        assert it[0] == k
+        true = np.linalg.norm(f - A @ x) / np.linalg.norm(f)
+        assert hist[0][-1] == pytest.approx(true, rel=1e-9, abs=1e-15)
+
+
+def test_fgmres_minimal_residual_over_krylov_space():
+    """With a fixed linear M, x_k = M u_k with u_k minimising ||f - A M u||
+    over span{f, AMf, ..., (AM)^{k-1} f}; the minimum is computed here by a
+    least-squares solve on the explicit (normalised) Krylov vectors."""
+    A, f = _dense_problem(60, 504, shift=2.0)
+    M = np.eye(60) + 0.2 * I.rng(505).standard_normal((60, 60)) / math.sqrt(60)
+    AM = A @ M
+    for k in range(1, 6):
+        x, hist, _ = O.fgmres_solve(lambda v: A @ v, lambda v: M @ v, f, rtol=0.0, max_iter=k)
+        Kr = [f / np.linalg.norm(f)]
+        for _ in range(k - 1):
+            u = AM @ Kr[-1]
+            Kr.append(u / np.linalg.norm(u))
+        Kr = np.stack(Kr, axis=1)
+        c, *_ = np.linalg.lstsq(AM @ Kr, f, rcond=None)
+        best = np.linalg.norm(f - AM @ (Kr @ c)) / np.linalg.norm(f)
+        assert hist[0][-1] == pytest.approx(best, rel=1e-7)
+        # nonincreasing residuals
+        assert all(b <= a * (1 + 1e-12) for a, b in zip(hist[0], hist[0][1:]))
+
+
+def test_fgmres_scalar_operator_one_step():
+    """A = alpha I: the first direction is exact, x = f / alpha after one
+    step; a zero right-hand side returns zero in no steps."""
+    f = I.rng(506).standard_normal(30)
+    F = np.stack([f, np.zeros(30)], axis=1)
+    X, hist, it = O.fgmres_solve(lambda v: 2.5 * v, None, F, rtol=1e-12, max_iter=5)
+    assert it == [1, 0]
+    np.testing.assert_allclose(X[:, 0], f / 2.5, rtol=1e-14)
+    assert np.all(X[:, 1] == 0)
+
+
+def test_fgmres_flexible_preconditioner():
+    """A preconditioner that changes at every step (FGMRES's reason to keep
+    z_j): the estimate still equals the true residual, and the solve still
+    converges.  Forming x as M (V y) with the last M would not."""
+    A, f = _dense_problem(50, 507, shift=1.5)
+    Ai = np.linalg.inv(A)
+    E = I.rng(508).standard_normal((50, 50)) / math.sqrt(50)
+    step = [0]
+
+    def M(v):
+        step[0] += 1
+        return (Ai + 0.02 * step[0] * E) @ v
+
+    x, hist, it = O.fgmres_solve(lambda v: A @ v, M, f, rtol=1e-10, max_iter=40)
+    true = np.linalg.norm(f - A @ x) / np.linalg.norm(f)
+    assert hist[0][-1] <= 1e-10
+    assert true == pytest.approx(hist[0][-1], rel=1e-6, abs=1e-15)
+
+
+def test_fgmres_qtt_pair_beats_refinement():
+    """On the synthetic QTT pair, each GMRES step is at least as good as the
+    same number of refinement passes (refinement's iterate lies in the same
+    preconditioned Krylov space), and the result agrees with a dense solve;
+    scaling the preconditioner by 2.5 (which makes refinement diverge)
+    changes neither GMRES's steps nor its answer beyond rounding."""
+    ranks = [1, 6, 8, 6, 1]
+    A, Ainv = I.perturbed_identity_pair(ranks, [8] * 4, seed=81)
+    F = I.rhs(4096, 2, seed=83)
+    apA = lambda v: O.qtt_apply_alg2(A, v[:, None])[:, 0]
+    apM = lambda v: O.qtt_apply_alg2(Ainv, v[:, None])[:, 0]
+    X, hist, it = O.fgmres_solve(apA, apM, F, rtol=1e-8, max_iter=20)
+    _, rh = O.richardson_solve(A, Ainv, F, rtol=1e-8)
+    for c in range(2):
+        assert hist[c][-1] <= 1e-8
+        assert it[c] <= len(rh)
+        for t in range(min(len(hist[c]), len(rh))):
+            assert hist[c][t] <= rh[t][c] * (1 + 1e-9)
+    ref = np.linalg.solve(O.qtt_to_dense(A), F)
+    assert _rel(X, ref) < 3e-8
+    # 2.5 x the inverse: refinement contracts by ||I - 2.5 A Ainv|| > 1
+    Ainv_s = [c.copy() for c in Ainv]
+    Ainv_s[0] = 2.5 * Ainv_s[0]
+    _, rh_s = O.richardson_solve(A, Ainv_s, F, rtol=1e-8, max_iter=8)
+    assert np.all(rh_s[-1] > rh_s[0])
+    Xs, hs, its = O.fgmres_solve(apA, lambda v: O.qtt_apply_alg2(Ainv_s, v[:, None])[:, 0], F,
+                                 rtol=1e-8, max_iter=20)
+    assert its == it
+    assert _rel(Xs, X) < 1e-10
