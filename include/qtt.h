@@ -180,6 +180,41 @@ qtt_status_t qtt_solve(qtt_matrix_t A, qtt_matrix_t Ainv, qtt_dtype_t inv_comput
                        double rtol, int32_t max_iter, void* ws, size_t ws_bytes,
                        void* stream, qtt_solve_col_t* info);
 
+/* Device bytes of workspace for qtt_solve_fgmres: max_iter + 1 Krylov blocks
+ * V and, with a preconditioner, max_iter preconditioned blocks Z (each
+ * N x nrhs FP64), small coefficient buffers, and the apply workspace.
+ * Ainv may be NULL (no preconditioner; inv_compute is then ignored). */
+qtt_status_t qtt_fgmres_workspace_bytes(qtt_matrix_t A, qtt_matrix_t Ainv, qtt_dtype_t inv_compute,
+                                        int64_t nrhs, int32_t max_iter, size_t* bytes);
+
+/* Solve A sigma = F by unrestarted flexible GMRES with the compressed
+ * inverse as right preconditioner, as section 5.2 uses GMRES (relative
+ * residual tolerance, no restart) around the QTT approximate inverse.  Each
+ * column c runs its own Krylov space; all active columns share every apply:
+ *   z_j = Ainv v_j (inv_compute), w = A z_j (FP64), two passes of classical
+ *   Gram-Schmidt against v_1..v_j, v_{j+1} = w / ||w||, Givens rotations on
+ *   the host, and sigma_c = Z y once ||F_c - A sigma_c|| <= rtol ||F_c||.
+ * The flexible form keeps the z_j, so a BF16 or FP32 inverse, linear only up
+ * to rounding, is still exact in the minimised residual.  Ainv = NULL runs
+ * plain GMRES (z_j = v_j).  A step costs one Ainv and one A apply, as a pass
+ * of qtt_solve does; scaling Ainv changes no step.
+ *   A, Ainv   square modes, identical mode sizes.
+ *   F, Sigma  device FP64, N x nrhs, strides ldf and lds (no overlap).
+ *   info      host, nrhs entries or NULL: steps taken and the residual
+ *             estimate |g_{k+1}| / ||F_c|| of the rotated Hessenberg system,
+ *             which equals the true relative residual up to FP64 rounding of
+ *             the Arnoldi relation (A applied in FP64).
+ * A zero column of F gives a zero column of Sigma in no steps.  Synchronises
+ * the stream once per step.  Returns QTT_ERR_NOT_CONVERGED after max_iter
+ * steps (Sigma holds each column's minimal-residual iterate),
+ * QTT_ERR_NONFINITE for a non-finite norm or a singular Hessenberg matrix,
+ * QTT_ERR_WORKSPACE below qtt_fgmres_workspace_bytes' fixed part plus the
+ * one-vector apply workspace. */
+qtt_status_t qtt_solve_fgmres(qtt_matrix_t A, qtt_matrix_t Ainv, qtt_dtype_t inv_compute, int64_t nrhs,
+                              const double* F, int64_t ldf, double* Sigma, int64_t lds,
+                              double rtol, int32_t max_iter, void* ws, size_t ws_bytes,
+                              void* stream, qtt_solve_col_t* info);
+
 const char* qtt_status_string(qtt_status_t s);
 const char* qtt_last_error(void);
 

@@ -2747,4 +2747,132 @@ __global__ void colnorm_final_kernel(const double* partial, int ncol, double* ou
   out[c] = sqrt(s);
 }
 
+// ---------------------------------------------------------------------------
+// Vector kernels of the flexible GMRES outer solver (section 5.2 uses the
+// compressed inverse as the preconditioner of an unrestarted GMRES).  Every
+// vector is an FP64 column of N values; column c of basis vector i lies at
+// basis + i * bstride + c * N.  The work per call is a few passes over N x K
+// FP64 values, so these kernels are HBM-bound: coalesced 8-byte loads, a
+// fixed row split and a fixed reduction order (the same result at every
+// call, whatever the other columns hold).
+// ---------------------------------------------------------------------------
+
+constexpr int kKryCols = 32;       // columns per launch
+constexpr int kGramBlocks = 128;   // row chunks per column
+constexpr int kGramNb = 16;        // basis vectors per Gram pass (register accumulators)
+constexpr int kKryThreads = 256;
+constexpr int kKryElems = 4;       // rows per thread per tile
+
+struct GramArgs {
+  const double* basis;   // nb basis vectors, stride bstride
+  int64_t bstride;
+  const double* w;       // w column c at w + c * N
+  int64_t N;
+  int32_t nb;            // <= kGramNb
+  int32_t ncol;          // <= kKryCols
+  int32_t col[kKryCols];
+  double* partial;       // [(i * ncol + s) * kGramBlocks + block]
+};
+
+// partial_i = sum over this block's rows of basis_i * w, for i < nb
+__global__ void __launch_bounds__(kKryThreads) gram_partial_kernel(const GramArgs args) {
+  (void)args;
+  const GramArgs& a = kernarg<GramArgs>();
+  const int s = blockIdx.y;
+  const int64_t c = a.col[s];
+  const int nb = a.nb;
+  const int64_t per = (a.N + kGramBlocks - 1) / kGramBlocks;
+  const int64_t b0 = (int64_t)blockIdx.x * per;
+  const int64_t b1 = min(a.N, b0 + per);
+  const double* w = a.w + c * a.N;
+  const double* B = a.basis + c * a.N;
+  double acc[kGramNb];
+#pragma unroll
+  for (int i = 0; i < kGramNb; ++i) acc[i] = 0.0;
+  constexpr int kTile = kKryThreads * kKryElems;
+  for (int64_t t0 = b0; t0 < b1; t0 += kTile) {
+    double wv[kKryElems];
+#pragma unroll
+    for (int e = 0; e < kKryElems; ++e) {
+      const int64_t r = t0 + e * kKryThreads + threadIdx.x;
+      wv[e] = (r < b1) ? w[r] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < kGramNb; ++i) {
+      if (i < nb) {
+        const double* Bi = B + i * a.bstride;
+#pragma unroll
+        for (int e = 0; e < kKryElems; ++e) {
+          const int64_t r = t0 + e * kKryThreads + threadIdx.x;
+          if (r < b1) acc[i] = fma(Bi[r], wv[e], acc[i]);
+        }
+      }
+    }
+  }
+  // wave sums, then the four waves in order
+  __shared__ double red[kKryThreads / 64][kGramNb];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < kGramNb; ++i) {
+    if (i < nb) {
+      double v = acc[i];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+      if (lane == 0) red[wave][i] = v;
+    }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < nb) {
+    const int i = threadIdx.x;
+    double v = red[0][i];
+#pragma unroll
+    for (int q = 1; q < kKryThreads / 64; ++q) v += red[q][i];
+    a.partial[((int64_t)i * a.ncol + s) * kGramBlocks + blockIdx.x] = v;
+  }
+}
+
+// h[(i0 + i) * ncol + s] = sum over blocks (in order) of the partials
+__global__ void gram_final_kernel(const double* partial, int nb, int ncol, int i0, double* h) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nb * ncol) return;
+  double v = 0.0;
+  for (int b = 0; b < kGramBlocks; ++b) v += partial[(int64_t)t * kGramBlocks + b];
+  const int i = t / ncol, s = t - i * ncol;
+  h[(int64_t)(i0 + i) * ncol + s] = v;
+}
+
+struct CombineArgs {
+  double* out;           // column c at out + c * ldo
+  int64_t ldo;
+  const double* in;      // column c at in + c * ldi; NULL reads as zero
+  int64_t ldi;
+  const double* scale;   // per slot s (NULL = 1): multiplies in
+  const double* basis;   // nb basis vectors, stride bstride, column c at + c * N
+  int64_t bstride;
+  const double* coef;    // coef[i * ncol + s]
+  double sign;           // multiplies the basis sum
+  int64_t N;
+  int32_t nb;
+  int32_t ncol;
+  int32_t col[kKryCols];
+};
+
+// out = scale_s * in + sign * sum_i coef_is * basis_i  (column by column)
+__global__ void __launch_bounds__(kKryThreads) combine_kernel(const CombineArgs args) {
+  (void)args;
+  const CombineArgs& a = kernarg<CombineArgs>();
+  const int s = blockIdx.y;
+  const int64_t c = a.col[s];
+  const double sc = a.scale ? a.scale[s] : 1.0;
+  const double* B = a.basis ? a.basis + c * a.N : nullptr;
+  double* out = a.out + c * a.ldo;
+  const double* in = a.in ? a.in + c * a.ldi : nullptr;
+  const int64_t stride = (int64_t)gridDim.x * kKryThreads;
+  for (int64_t r = (int64_t)blockIdx.x * kKryThreads + threadIdx.x; r < a.N; r += stride) {
+    double v = 0.0;
+    for (int i = 0; i < a.nb; ++i) v = fma(a.coef[(int64_t)i * a.ncol + s], B[i * a.bstride + r], v);
+    out[r] = (in ? sc * in[r] : 0.0) + a.sign * v;
+  }
+}
+
 }  // namespace qtt

@@ -1747,6 +1747,362 @@ qtt_status_t qtt_solve(qtt_matrix_t A, qtt_matrix_t Ainv, qtt_dtype_t inv_comput
   return QTT_OK;
 }
 
+// --------------------------------------------------------------------------- flexible GMRES
+
+// [V: max_iter + 1 blocks | Z: max_iter blocks (with a preconditioner) |
+//  Gram partials | h1 | h2 | coefficients | norm partials | norms | apply ws]
+// where a block is N x nrhs FP64 and the small buffers are sized per chunk
+// of kKryCols columns.
+static size_t fgmres_extra_bytes(const qtt_matrix_s* A, bool precond, int64_t nrhs, int32_t max_iter) {
+  const size_t blk = align256((size_t)A->rows * nrhs * 8);
+  // one chunk more than the columns need: finished and continuing columns
+  // are chunked separately within a step
+  const int64_t chunks = (nrhs + kKryCols - 1) / kKryCols + 1;
+  const size_t hsz = align256((size_t)chunks * (max_iter + 1) * kKryCols * 8);
+  return blk * (max_iter + 1) + (precond ? blk * max_iter : 0)
+         + align256((size_t)kGramNb * kKryCols * kGramBlocks * 8)
+         + 3 * hsz
+         + align256((size_t)nrhs * kNormBlocks * 8) + align256((size_t)nrhs * 8);
+}
+
+qtt_status_t qtt_fgmres_workspace_bytes(qtt_matrix_t A, qtt_matrix_t Ainv, qtt_dtype_t inv_compute,
+                                        int64_t nrhs, int32_t max_iter, size_t* bytes) {
+  if (!valid_handle(A) || (Ainv && !valid_handle(Ainv)) || !bytes)
+    return fail(QTT_ERR_INVALID_ARG, "null handle or output");
+  if (max_iter < 1) return fail(QTT_ERR_INVALID_ARG, "max_iter < 1");
+  int dt;
+  qtt_status_t s = check_dtype(A, QTT_FP64, &dt);
+  if (s != QTT_OK) return s;
+  const int64_t k = std::max<int64_t>(nrhs, 1);
+  size_t wa = 0, wi = 0;
+  qtt_workspace_bytes(A, QTT_FP64, k, &wa);
+  if (Ainv) {
+    s = check_dtype(Ainv, inv_compute, &dt);
+    if (s != QTT_OK) return s;
+    qtt_workspace_bytes(Ainv, inv_compute, k, &wi);
+  }
+  *bytes = std::max(wa, wi) + fgmres_extra_bytes(A, Ainv != nullptr, k, max_iter);
+  return QTT_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// One launch group of at most kKryCols columns.
+struct KryChunk {
+  int ncol = 0;
+  int32_t col[kKryCols];
+};
+
+std::vector<KryChunk> chunk_columns(const std::vector<int64_t>& cols) {
+  std::vector<KryChunk> out;
+  for (size_t t = 0; t < cols.size(); t += kKryCols) {
+    KryChunk ch;
+    ch.ncol = (int)std::min<size_t>(kKryCols, cols.size() - t);
+    for (int q = 0; q < ch.ncol; ++q) ch.col[q] = (int32_t)cols[t + q];
+    out.push_back(ch);
+  }
+  return out;
+}
+
+// h[i * ncol + s] = <basis_i, w> for i < nb, columns of one chunk
+qtt_status_t gram(const KryChunk& ch, const double* basis, int64_t bstride, int nb, const double* w,
+                  int64_t N, double* partial, double* h, hipStream_t st) {
+  for (int i0 = 0; i0 < nb; i0 += kGramNb) {
+    GramArgs ga;
+    memset(&ga, 0, sizeof(ga));
+    ga.basis = basis + i0 * bstride;
+    ga.bstride = bstride;
+    ga.w = w;
+    ga.N = N;
+    ga.nb = std::min(kGramNb, nb - i0);
+    ga.ncol = ch.ncol;
+    memcpy(ga.col, ch.col, sizeof(ga.col));
+    ga.partial = partial;
+    void* args[] = {&ga};
+    HIP_TRY(hipLaunchKernel(reinterpret_cast<const void*>(&gram_partial_kernel), dim3(kGramBlocks, ch.ncol),
+                            dim3(kKryThreads), args, 0, st));
+    const double* pp = partial;
+    int nbv = ga.nb, nc = ch.ncol, i0v = i0;
+    double* hv = h;
+    void* args2[] = {&pp, &nbv, &nc, &i0v, &hv};
+    const int nt = nbv * nc;
+    HIP_TRY(hipLaunchKernel(reinterpret_cast<const void*>(&gram_final_kernel), dim3((nt + 63) / 64), dim3(64),
+                            args2, 0, st));
+  }
+  return QTT_OK;
+}
+
+// out = scale * in + sign * sum_i coef_i basis_i, columns of one chunk
+qtt_status_t combine(const KryChunk& ch, double* out, int64_t ldo, const double* in, int64_t ldi,
+                     const double* scale, const double* basis, int64_t bstride, const double* coef, int nb,
+                     double sign, int64_t N, hipStream_t st) {
+  CombineArgs ca;
+  memset(&ca, 0, sizeof(ca));
+  ca.out = out;
+  ca.ldo = ldo;
+  ca.in = in;
+  ca.ldi = ldi;
+  ca.scale = scale;
+  ca.basis = basis;
+  ca.bstride = bstride;
+  ca.coef = coef;
+  ca.sign = sign;
+  ca.N = N;
+  ca.nb = nb;
+  ca.ncol = ch.ncol;
+  memcpy(ca.col, ch.col, sizeof(ca.col));
+  const int64_t bx = std::min<int64_t>(512, std::max<int64_t>(1, (N + kKryThreads - 1) / kKryThreads));
+  void* args[] = {&ca};
+  HIP_TRY(hipLaunchKernel(reinterpret_cast<const void*>(&combine_kernel), dim3((unsigned)bx, ch.ncol),
+                          dim3(kKryThreads), args, 0, st));
+  return QTT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+qtt_status_t qtt_solve_fgmres(qtt_matrix_t A, qtt_matrix_t Ainv, qtt_dtype_t inv_compute, int64_t nrhs,
+                              const double* F, int64_t ldf, double* Sigma, int64_t lds, double rtol,
+                              int32_t max_iter, void* ws, size_t ws_bytes, void* stream,
+                              qtt_solve_col_t* info) {
+  if (!valid_handle(A) || (Ainv && !valid_handle(Ainv))) return fail(QTT_ERR_INVALID_ARG, "null handle");
+  int dti = -1, dta;
+  qtt_status_t s = check_dtype(A, QTT_FP64, &dta);
+  if (s != QTT_OK) return s;
+  if (Ainv) {
+    s = check_dtype(Ainv, inv_compute, &dti);
+    if (s != QTT_OK) return s;
+    if (A->d != Ainv->d) return fail(QTT_ERR_SHAPE, "A and Ainv have different core counts");
+  }
+  for (int k = 0; k < A->d; ++k)
+    if (A->m[k] != A->n[k] || (Ainv && (Ainv->m[k] != A->m[k] || Ainv->n[k] != A->n[k])))
+      return fail(QTT_ERR_SHAPE, "solve needs square, identical modes (core %d)", k);
+  if (nrhs < 0 || max_iter < 1 || !(rtol >= 0)) return fail(QTT_ERR_INVALID_ARG, "bad nrhs, max_iter or rtol");
+  if (nrhs == 0) return QTT_OK;
+  if (!F || !Sigma || !ws) return fail(QTT_ERR_INVALID_ARG, "null F, Sigma or workspace");
+  const int64_t N = A->rows;
+  if (ldf < N || lds < N) return fail(QTT_ERR_INVALID_ARG, "ldf or lds < N");
+  const size_t fb = ((size_t)(nrhs - 1) * ldf + N) * 8, sb = ((size_t)(nrhs - 1) * lds + N) * 8;
+  if (overlaps(F, fb, Sigma, sb)) return fail(QTT_ERR_INVALID_ARG, "F and Sigma overlap");
+  const bool pre = Ainv != nullptr;
+  const size_t extra = fgmres_extra_bytes(A, pre, nrhs, max_iter);
+  size_t need1 = 0, tmp = 0;
+  qtt_workspace_bytes(A, QTT_FP64, 1, &need1);
+  if (pre) {
+    qtt_workspace_bytes(Ainv, inv_compute, 1, &tmp);
+    need1 = std::max(need1, tmp);
+  }
+  if (ws_bytes < extra + need1)
+    return fail(QTT_ERR_WORKSPACE, "FGMRES workspace %zu < minimum %zu", ws_bytes, extra + need1);
+  if (overlaps(ws, ws_bytes, F, fb) || overlaps(ws, ws_bytes, Sigma, sb))
+    return fail(QTT_ERR_INVALID_ARG, "workspace overlaps F or Sigma");
+
+  // carve the workspace
+  const int64_t bstride = N * nrhs;   // one block: N x nrhs, column c at + c * N
+  const size_t blk = align256((size_t)bstride * 8);
+  const int64_t nchunk = (nrhs + kKryCols - 1) / kKryCols + 1;
+  const int64_t hstride = (int64_t)(max_iter + 1) * kKryCols;   // per chunk
+  const size_t hsz = align256((size_t)nchunk * hstride * 8);
+  char* p = static_cast<char*>(ws);
+  double* V = reinterpret_cast<double*>(p);
+  p += blk * (max_iter + 1);
+  double* Z = V;   // no preconditioner: z_j = v_j
+  if (pre) {
+    Z = reinterpret_cast<double*>(p);
+    p += blk * max_iter;
+  }
+  double* gpart = reinterpret_cast<double*>(p);
+  p += align256((size_t)kGramNb * kKryCols * kGramBlocks * 8);
+  double* h1 = reinterpret_cast<double*>(p);
+  p += hsz;
+  double* h2 = reinterpret_cast<double*>(p);
+  p += hsz;
+  double* cbuf = reinterpret_cast<double*>(p);
+  p += hsz;
+  double* npart = reinterpret_cast<double*>(p);
+  p += align256((size_t)nrhs * kNormBlocks * 8);
+  double* dnorm = reinterpret_cast<double*>(p);
+  p += align256((size_t)nrhs * 8);
+  void* aws = p;
+  const size_t aws_bytes = ws_bytes - extra;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+
+  // ||f_c||
+  std::vector<const double*> fcols(nrhs);
+  std::vector<int64_t> fld(nrhs, ldf);
+  for (int64_t c = 0; c < nrhs; ++c) fcols[c] = F + c * ldf;
+  std::vector<double> beta;
+  s = column_norms(fcols, fld, N, npart, dnorm, beta, st);
+  if (s != QTT_OK) return s;
+  std::vector<int64_t> act, zero;
+  std::vector<double> relv(nrhs, 0.0);
+  for (int64_t c = 0; c < nrhs; ++c) {
+    if (!std::isfinite(beta[c])) return fail(QTT_ERR_NONFINITE, "column %lld of F is not finite", (long long)c);
+    if (info) { info[c].iters = 0; info[c].rel_residual = 0.0; }
+    (beta[c] > 0 ? act : zero).push_back(c);
+  }
+  // zero right-hand sides: sigma = 0
+  for (auto& ch : chunk_columns(zero)) {
+    s = combine(ch, Sigma, lds, nullptr, 0, nullptr, nullptr, 0, nullptr, 0, 1.0, N, st);
+    if (s != QTT_OK) return s;
+  }
+  // host state per column: Hessenberg columns (rotated), rotations, g
+  const int M = max_iter;
+  std::vector<double> H((size_t)nrhs * (M + 1) * M, 0.0), cs((size_t)nrhs * M), sn((size_t)nrhs * M),
+      g((size_t)nrhs * (M + 1), 0.0);
+  auto Hc = [&](int64_t c, int i, int j) -> double& { return H[((size_t)c * M + j) * (M + 1) + i]; };
+  for (int64_t c : act) g[(size_t)c * (M + 1)] = beta[c];
+  // host staging of uploaded coefficients: one region per chunk and purpose,
+  // untouched until the stream has synchronised again
+  std::vector<double> hscale((size_t)nchunk * hstride), hy((size_t)nchunk * hstride);
+  std::vector<double> hh1((size_t)nchunk * hstride), hh2((size_t)nchunk * hstride);
+
+  // v_1 = f / ||f||
+  {
+    auto chs = chunk_columns(act);
+    for (size_t q = 0; q < chs.size(); ++q) {
+      for (int t = 0; t < chs[q].ncol; ++t) hscale[q * hstride + t] = 1.0 / beta[chs[q].col[t]];
+      HIP_TRY(hipMemcpyAsync(cbuf + q * hstride, hscale.data() + q * hstride, chs[q].ncol * 8,
+                             hipMemcpyHostToDevice, st));
+      // F columns are at F + c * ldf; V columns at V + c * N
+      s = combine(chs[q], V, N, F, ldf, cbuf + q * hstride, nullptr, 0, nullptr, 0, 1.0, N, st);
+      if (s != QTT_OK) return s;
+    }
+  }
+
+  // x = Z y for the columns of one chunk after k steps (y solved on the host)
+  auto finish = [&](const std::vector<int64_t>& cols, int k, size_t slot) -> qtt_status_t {
+    auto chs = chunk_columns(cols);
+    for (size_t q = 0; q < chs.size(); ++q) {
+      double* hyq = hy.data() + (slot + q) * hstride;
+      for (int t = 0; t < chs[q].ncol; ++t) {
+        const int64_t c = chs[q].col[t];
+        std::vector<double> y(k);
+        for (int i = k - 1; i >= 0; --i) {
+          double v = g[(size_t)c * (M + 1) + i];
+          for (int l = i + 1; l < k; ++l) v -= Hc(c, i, l) * y[l];
+          y[i] = v / Hc(c, i, i);
+        }
+        for (int i = 0; i < k; ++i) hyq[(size_t)i * chs[q].ncol + t] = y[i];
+      }
+      double* dy = cbuf + (slot + q) * hstride;
+      HIP_TRY(hipMemcpyAsync(dy, hyq, (size_t)k * chs[q].ncol * 8, hipMemcpyHostToDevice, st));
+      qtt_status_t r = combine(chs[q], Sigma, lds, nullptr, 0, nullptr, Z, bstride, dy, k, 1.0, N, st);
+      if (r != QTT_OK) return r;
+    }
+    return QTT_OK;
+  };
+
+  for (int j = 0; j < M && !act.empty(); ++j) {
+    // z_j = Ainv v_j, w = A z_j (w is stored as v_{j+1})
+    std::vector<std::pair<int64_t, int64_t>> runs;
+    for (size_t t = 0; t < act.size();) {
+      size_t e = t + 1;
+      while (e < act.size() && act[e] == act[e - 1] + 1) ++e;
+      runs.push_back({act[t], (int64_t)(e - t)});
+      t = e;
+    }
+    double* Vj = V + j * bstride;
+    double* Zj = Z + j * bstride;
+    double* W = V + (j + 1) * bstride;
+    std::vector<Block> bi, ba;
+    for (auto& r : runs) {
+      bi.push_back({Vj + r.first * N, Zj + r.first * N, nullptr, N, N, 0, r.second});
+      ba.push_back({Zj + r.first * N, W + r.first * N, nullptr, N, N, 0, r.second});
+    }
+    if (pre) {
+      s = run_blocks(Ainv, dti, bi, aws, aws_bytes, 1.0, st);
+      if (s != QTT_OK) return s;
+    }
+    s = run_blocks(A, dta, ba, aws, aws_bytes, 1.0, st);
+    if (s != QTT_OK) return s;
+    // classical Gram-Schmidt, twice: h = V^T w, w -= V h
+    const int nb = j + 1;
+    auto chs = chunk_columns(act);
+    for (size_t q = 0; q < chs.size(); ++q) {
+      double* hq1 = h1 + q * hstride;
+      double* hq2 = h2 + q * hstride;
+      s = gram(chs[q], V, bstride, nb, W, N, gpart, hq1, st);
+      if (s != QTT_OK) return s;
+      s = combine(chs[q], W, N, W, N, nullptr, V, bstride, hq1, nb, -1.0, N, st);
+      if (s != QTT_OK) return s;
+      s = gram(chs[q], V, bstride, nb, W, N, gpart, hq2, st);
+      if (s != QTT_OK) return s;
+      s = combine(chs[q], W, N, W, N, nullptr, V, bstride, hq2, nb, -1.0, N, st);
+      if (s != QTT_OK) return s;
+      HIP_TRY(hipMemcpyAsync(hh1.data() + q * hstride, hq1, (size_t)nb * chs[q].ncol * 8, hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipMemcpyAsync(hh2.data() + q * hstride, hq2, (size_t)nb * chs[q].ncol * 8, hipMemcpyDeviceToHost, st));
+    }
+    std::vector<const double*> wc;
+    std::vector<int64_t> wld(act.size(), N);
+    for (int64_t c : act) wc.push_back(W + c * N);
+    std::vector<double> wn;
+    s = column_norms(wc, wld, N, npart, dnorm, wn, st);   // synchronises the stream
+    if (s != QTT_OK) return s;
+    // Hessenberg column j, rotations, residual estimate
+    std::vector<int64_t> done, keep;
+    std::vector<double> keep_scale;
+    for (size_t q = 0, t = 0; q < chs.size(); ++q) {
+      for (int u = 0; u < chs[q].ncol; ++u, ++t) {
+        const int64_t c = chs[q].col[u];
+        for (int i = 0; i < nb; ++i)
+          Hc(c, i, j) = hh1[q * hstride + (size_t)i * chs[q].ncol + u] + hh2[q * hstride + (size_t)i * chs[q].ncol + u];
+        const double hn = wn[t];
+        Hc(c, j + 1, j) = hn;
+        double* cc = cs.data() + (size_t)c * M;
+        double* ss = sn.data() + (size_t)c * M;
+        for (int i = 0; i < j; ++i) {
+          const double a = Hc(c, i, j), b = Hc(c, i + 1, j);
+          Hc(c, i, j) = cc[i] * a + ss[i] * b;
+          Hc(c, i + 1, j) = -ss[i] * a + cc[i] * b;
+        }
+        const double d = std::hypot(Hc(c, j, j), Hc(c, j + 1, j));
+        if (!std::isfinite(d) || !std::isfinite(hn))
+          return fail(QTT_ERR_NONFINITE, "Arnoldi step %d of column %lld is not finite", j + 1, (long long)c);
+        if (d == 0.0) return fail(QTT_ERR_NONFINITE, "singular Hessenberg at step %d, column %lld", j + 1, (long long)c);
+        cc[j] = Hc(c, j, j) / d;
+        ss[j] = Hc(c, j + 1, j) / d;
+        Hc(c, j, j) = d;
+        Hc(c, j + 1, j) = 0.0;
+        double* gc = g.data() + (size_t)c * (M + 1);
+        gc[j + 1] = -ss[j] * gc[j];
+        gc[j] = cc[j] * gc[j];
+        const double rel = std::fabs(gc[j + 1]) / beta[c];
+        relv[c] = rel;
+        if (info) { info[c].iters = j + 1; info[c].rel_residual = rel; }
+        if (rel <= rtol || hn == 0.0 || j + 1 == M) done.push_back(c);
+        else { keep.push_back(c); keep_scale.push_back(1.0 / hn); }
+      }
+    }
+    // finished columns: sigma = Z y now (their blocks are not touched again)
+    if (!done.empty()) {
+      s = finish(done, j + 1, 0);
+      if (s != QTT_OK) return s;
+    }
+    // the others: v_{j+1} = w / h_{j+1,j}
+    auto kch = chunk_columns(keep);
+    const size_t off = chunk_columns(done).size();
+    for (size_t q = 0, t = 0; q < kch.size(); ++q) {
+      double* hs = hscale.data() + (off + q) * hstride;
+      for (int u = 0; u < kch[q].ncol; ++u, ++t) hs[u] = keep_scale[t];
+      double* ds = cbuf + (off + q) * hstride;
+      HIP_TRY(hipMemcpyAsync(ds, hs, kch[q].ncol * 8, hipMemcpyHostToDevice, st));
+      s = combine(kch[q], W, N, W, N, ds, nullptr, 0, nullptr, 0, 1.0, N, st);
+      if (s != QTT_OK) return s;
+    }
+    act.swap(keep);
+  }
+  // every column is finished here (the last step finishes the rest)
+  int64_t above = 0;
+  for (int64_t c = 0; c < nrhs; ++c) above += (relv[c] > rtol);
+  HIP_TRY(hipStreamSynchronize(st));
+  if (above > 0) return fail(QTT_ERR_NOT_CONVERGED, "%lld columns above rtol after %d steps", (long long)above, M);
+  return QTT_OK;
+}
+
 // --------------------------------------------------------------------------- timing
 
 qtt_status_t qtt_timing_enable(int32_t on) {

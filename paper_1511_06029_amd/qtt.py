@@ -62,6 +62,8 @@ def _load():
         "qtt_autotune": [P, I32, I64, P, I64, P, I64, P, SZ, P],
         "qtt_solve_workspace_bytes": [P, P, I32, I64, ctypes.POINTER(SZ)],
         "qtt_solve": [P, P, I32, I64, P, I64, P, I64, D, I32, P, SZ, P, ctypes.POINTER(_SolveCol)],
+        "qtt_fgmres_workspace_bytes": [P, P, I32, I64, I32, ctypes.POINTER(SZ)],
+        "qtt_solve_fgmres": [P, P, I32, I64, P, I64, P, I64, D, I32, P, SZ, P, ctypes.POINTER(_SolveCol)],
         "qtt_set_shape": [P, I32, I32, I32],
         "qtt_list_shapes": [I32, ctypes.POINTER(I32), I32, ctypes.POINTER(I32)],
         "qtt_timing_enable": [I32],
@@ -84,7 +86,7 @@ _lib = _load()
 # Names the C ABI exports (include/qtt.h); the tests check each is present.
 EXPORTED = ["qtt_matrix_load", "qtt_matrix_free", "qtt_matrix_info", "qtt_workspace_bytes",
             "qtt_apply", "qtt_apply_batched", "qtt_autotune", "qtt_solve_workspace_bytes",
-            "qtt_solve", "qtt_status_string", "qtt_last_error", "qtt_set_shape", "qtt_list_shapes",
+            "qtt_solve", "qtt_fgmres_workspace_bytes", "qtt_solve_fgmres", "qtt_status_string", "qtt_last_error", "qtt_set_shape", "qtt_list_shapes",
             "qtt_timing_enable",
             "qtt_timing_reset", "qtt_timing_read", "qtt_timing_read_shape"]
 
@@ -271,6 +273,35 @@ def qtt_solve(A, Ainv, inv_compute, F, Sigma=None, rtol=1e-8, max_iter=50, ws=No
     info = (_SolveCol * k)()
     st = _lib.qtt_solve(A.handle, Ainv.handle, _dtype(inv_compute), k, fp, ldf, sp, lds, float(rtol),
                         int(max_iter), ws.data_ptr(), ws.numel() * ws.element_size(), _stream(stream), info)
+    if raise_on_fail:
+        _check(st)
+    else:
+        _check(st, allow=(QTT_ERR_NOT_CONVERGED, QTT_ERR_NONFINITE))
+    return Sigma, [(c.iters, c.rel_residual) for c in info], st
+
+
+def qtt_fgmres_workspace_bytes(A, Ainv, inv_compute, nrhs, max_iter):
+    n = ctypes.c_size_t()
+    _check(_lib.qtt_fgmres_workspace_bytes(A.handle, Ainv.handle if Ainv is not None else None,
+                                           _dtype(inv_compute), int(nrhs), int(max_iter), ctypes.byref(n)))
+    return n.value
+
+
+def qtt_solve_fgmres(A, Ainv, inv_compute, F, Sigma=None, rtol=1e-8, max_iter=30, ws=None, stream=None,
+                     raise_on_fail=True):
+    """Flexible GMRES solve A Sigma = F, Ainv (or None) the right
+    preconditioner; returns (Sigma, info, status) with info a list of
+    (steps, relative residual estimate) per column."""
+    fp, n, k, ldf = _col_major(F, "F")
+    if Sigma is None:
+        Sigma = empty_block(n, k, F.device) if F.dim() == 2 else torch.empty(n, dtype=torch.float64, device=F.device)
+    sp, _, _, lds = _col_major(Sigma, "Sigma")
+    if ws is None:
+        ws = workspace(qtt_fgmres_workspace_bytes(A, Ainv, inv_compute, k, max_iter), F.device)
+    info = (_SolveCol * k)()
+    st = _lib.qtt_solve_fgmres(A.handle, Ainv.handle if Ainv is not None else None, _dtype(inv_compute), k,
+                               fp, ldf, sp, lds, float(rtol), int(max_iter), ws.data_ptr(),
+                               ws.numel() * ws.element_size(), _stream(stream), info)
     if raise_on_fail:
         _check(st)
     else:

@@ -1,0 +1,191 @@
+"""GPU parity of the flexible GMRES outer solver (qtt_solve_fgmres) against
+the oracle's FGMRES (section 5.2: GMRES around the compressed inverse,
+relative-residual tolerance, no restart).
+
+With an FP64 preconditioner both sides run the same algorithm in FP64, so the
+steps per column must be equal and the solutions agree to 1e-10 (classical
+Gram-Schmidt twice on the GPU, modified Gram-Schmidt in the oracle: the two
+differ by rounding only).  With FP32 or BF16 inverses the residual the oracle
+recomputes must reach the tolerance.
+"""
+import numpy as np
+import pytest
+
+from oracle import qtt_oracle as O
+from paper_1511_06029_amd import inputs as I
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def Q():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    from paper_1511_06029_amd import qtt
+    return qtt
+
+
+def colrel(Y, R):
+    return max(np.linalg.norm(Y[:, c] - R[:, c]) / max(np.linalg.norm(R[:, c]), 1e-300)
+               for c in range(R.shape[1]))
+
+
+def oracle_fgmres(Ac, Mc, F, rtol, max_iter):
+    apA = lambda v: O.qtt_apply_alg2(Ac, v[:, None])[:, 0]
+    apM = None if Mc is None else (lambda v: O.qtt_apply_alg2(Mc, v[:, None])[:, 0])
+    return O.fgmres_solve(apA, apM, F, rtol=rtol, max_iter=max_iter)
+
+
+def true_rel(Ac, F, S):
+    R = F - O.qtt_apply_alg2(Ac, S)
+    return [np.linalg.norm(R[:, c]) / np.linalg.norm(F[:, c]) for c in range(F.shape[1])]
+
+
+def test_fgmres_fp64_matches_oracle(Q):
+    """FP64 inverse: equal steps, equal residual estimates, equal solutions."""
+    Ac, Aic = I.perturbed_identity_pair([1, 6, 8, 6, 1], [8] * 4, seed=81)
+    F = I.rhs(4096, 3, seed=85)
+    Xo, ho, ito = oracle_fgmres(Ac, Aic, F, 1e-8, 30)
+    A = Q.qtt_matrix_load(Ac, dtypes=("fp64",))
+    Ai = Q.qtt_matrix_load(Aic, dtypes=("fp64",))
+    Sig, info, st = Q.qtt_solve_fgmres(A, Ai, "fp64", Q.to_block(F), rtol=1e-8, max_iter=30)
+    S = Sig.cpu().numpy()
+    assert [c[0] for c in info] == ito
+    for c in range(3):
+        assert info[c][1] == pytest.approx(ho[c][-1], rel=1e-6)
+    assert colrel(S, Xo) <= 1e-10
+    assert max(true_rel(Ac, F, S)) <= 1e-8
+    A.free()
+    Ai.free()
+
+
+def test_fgmres_unpreconditioned_many_steps(Q):
+    """No preconditioner, a harder operator: 27-28 steps (two Gram passes of
+    16 basis vectors), columns finishing at different steps."""
+    Ac, _ = I.perturbed_identity_pair([1, 6, 8, 6, 1], [8] * 4, seed=81, eps=0.3)
+    F = I.rhs(4096, 3, seed=85)
+    Xo, ho, ito = oracle_fgmres(Ac, None, F, 1e-8, 40)
+    assert max(ito) > 16 and len(set(ito)) > 1
+    A = Q.qtt_matrix_load(Ac, dtypes=("fp64",))
+    Sig, info, st = Q.qtt_solve_fgmres(A, None, "fp64", Q.to_block(F), rtol=1e-8, max_iter=40)
+    S = Sig.cpu().numpy()
+    assert [c[0] for c in info] == ito
+    assert colrel(S, Xo) <= 1e-10
+    assert max(true_rel(Ac, F, S)) <= 1e-8
+    A.free()
+
+
+@pytest.mark.parametrize("inv", ["fp32", "bf16"])
+def test_fgmres_low_precision_inverse(Q, inv):
+    """FP32 / BF16 inverse (linear only up to rounding, hence the flexible
+    form): the oracle's residual reaches 1e-8, in no more steps than the
+    refinement passes of qtt_solve with the same inverse."""
+    Ac, Aic = I.perturbed_identity_pair([1, 6, 8, 6, 1], [8] * 4, seed=81)
+    F = I.rhs(4096, 3, seed=86)
+    A = Q.qtt_matrix_load(Ac, dtypes=("fp64",))
+    Ai = Q.qtt_matrix_load(Aic, dtypes=(inv,))
+    Sig, info, st = Q.qtt_solve_fgmres(A, Ai, inv, Q.to_block(F), rtol=1e-8, max_iter=30)
+    S = Sig.cpu().numpy()
+    tr = true_rel(Ac, F, S)
+    for c in range(3):
+        assert tr[c] <= 1e-8 * 1.0001
+        assert info[c][1] == pytest.approx(tr[c], rel=1e-3)
+    _, rinfo, _ = Q.qtt_solve(A, Ai, inv, Q.to_block(F), rtol=1e-8)
+    assert max(c[0] for c in info) <= max(c[0] for c in rinfo)
+    ref = np.linalg.solve(O.qtt_to_dense(Ac), F)
+    assert colrel(S, ref) <= 3e-8
+    A.free()
+    Ai.free()
+
+
+def test_fgmres_scaled_preconditioner(Q):
+    """2.5 x the inverse: refinement diverges (not converged), GMRES takes the
+    same steps and finds the same solution as with the unscaled inverse."""
+    Ac, Aic = I.perturbed_identity_pair([1, 6, 8, 6, 1], [8] * 4, seed=81)
+    As = [c.copy() for c in Aic]
+    As[0] = 2.5 * As[0]
+    F = I.rhs(4096, 2, seed=87)
+    A = Q.qtt_matrix_load(Ac, dtypes=("fp64",))
+    Ai = Q.qtt_matrix_load(Aic, dtypes=("fp64",))
+    Ais = Q.qtt_matrix_load(As, dtypes=("fp64",))
+    _, _, st = Q.qtt_solve(A, Ais, "fp64", Q.to_block(F), rtol=1e-8, max_iter=8, raise_on_fail=False)
+    assert st == Q.QTT_ERR_NOT_CONVERGED
+    S1, i1, _ = Q.qtt_solve_fgmres(A, Ai, "fp64", Q.to_block(F), rtol=1e-8)
+    S2, i2, _ = Q.qtt_solve_fgmres(A, Ais, "fp64", Q.to_block(F), rtol=1e-8)
+    assert [c[0] for c in i1] == [c[0] for c in i2]
+    assert colrel(S2.cpu().numpy(), S1.cpu().numpy()) <= 1e-10
+    for a in (A, Ai, Ais):
+        a.free()
+
+
+def test_fgmres_many_columns_zero_column_and_repeat(Q):
+    """40 columns (two launch chunks of 32), one of them zero (zero solution,
+    no steps), against the oracle column by column; a second call gives the
+    same bits."""
+    Ac, Aic = I.perturbed_identity_pair([1, 4, 4, 1], [8] * 3, seed=86)
+    F = I.rhs(512, 40, seed=87)
+    F[:, 5] = 0.0
+    Xo, ho, ito = oracle_fgmres(Ac, Aic, F, 1e-8, 30)
+    A = Q.qtt_matrix_load(Ac, dtypes=("fp64",))
+    Ai = Q.qtt_matrix_load(Aic, dtypes=("fp64",))
+    Fd = Q.to_block(F)
+    Sig, info, st = Q.qtt_solve_fgmres(A, Ai, "fp64", Fd, rtol=1e-8, max_iter=30)
+    S = Sig.cpu().numpy()
+    assert [c[0] for c in info] == ito
+    assert np.all(S[:, 5] == 0.0) and info[5] == (0, 0.0)
+    nz = [c for c in range(40) if c != 5]
+    assert colrel(S[:, nz], Xo[:, nz]) <= 1e-10
+    Sig2, _, _ = Q.qtt_solve_fgmres(A, Ai, "fp64", Fd, rtol=1e-8, max_iter=30)
+    assert torch.equal(Sig, Sig2)
+    A.free()
+    Ai.free()
+
+
+def test_fgmres_not_converged_and_errors(Q):
+    """max_iter below what is needed: status NOT_CONVERGED, Sigma holds the
+    minimal-residual iterate of that many steps (the oracle's); no columns:
+    OK; a workspace below the minimum: WORKSPACE."""
+    Ac, Aic = I.perturbed_identity_pair([1, 6, 8, 6, 1], [8] * 4, seed=81)
+    F = I.rhs(4096, 2, seed=88)
+    Xo, ho, ito = oracle_fgmres(Ac, Aic, F, 1e-8, 3)
+    A = Q.qtt_matrix_load(Ac, dtypes=("fp64",))
+    Ai = Q.qtt_matrix_load(Aic, dtypes=("fp64",))
+    Sig, info, st = Q.qtt_solve_fgmres(A, Ai, "fp64", Q.to_block(F), rtol=1e-8, max_iter=3,
+                                       raise_on_fail=False)
+    assert st == Q.QTT_ERR_NOT_CONVERGED
+    assert [c[0] for c in info] == [3, 3] == ito
+    assert all(c[1] > 1e-8 for c in info)
+    assert colrel(Sig.cpu().numpy(), Xo) <= 1e-10
+    with pytest.raises(Q.QttError) as e:
+        Q.qtt_solve_fgmres(A, Ai, "fp64", Q.to_block(F), ws=Q.workspace(1024))
+    assert e.value.status == 7
+    E = Q.empty_block(4096, 0)
+    _, info0, st0 = Q.qtt_solve_fgmres(A, Ai, "fp64", E)
+    assert st0 == 0 and info0 == []
+    A.free()
+    Ai.free()
+
+
+@pytest.mark.slow
+def test_fgmres_L7_full_size(Q):
+    """Full size (L=7, ranks [1,24,32,32,32,32,24,1], K=8) with the BF16
+    inverse: converged, the oracle's residual of two sampled columns is below
+    1e-8, and no more steps than refinement's passes."""
+    w = I.WORKLOADS["refine_L7"]
+    Ac, Aic = I.perturbed_identity_pair(w["ranks"], [8] * 7, seed=w["core_seed"], eps=w["eps"])
+    F = I.rhs(8 ** 7, w["K"], seed=w["rhs_seed"])
+    A = Q.qtt_matrix_load(Ac, dtypes=("fp64",))
+    Ai = Q.qtt_matrix_load(Aic, dtypes=("bf16",))
+    Fd = Q.to_block(F)
+    Sig, info, st = Q.qtt_solve_fgmres(A, Ai, "bf16", Fd, rtol=w["rtol"], max_iter=20)
+    S = Sig.cpu().numpy()
+    for c in (0, w["K"] - 1):
+        r = F[:, c] - O.qtt_apply_alg2(Ac, S[:, c])
+        rel = np.linalg.norm(r) / np.linalg.norm(F[:, c])
+        assert rel <= 1e-8 * 1.0001
+        assert info[c][1] == pytest.approx(rel, rel=1e-3)
+    _, rinfo, _ = Q.qtt_solve(A, Ai, "bf16", Fd, rtol=w["rtol"])
+    assert max(c[0] for c in info) <= max(c[0] for c in rinfo)
+    A.free()
+    Ai.free()
