@@ -47,6 +47,8 @@ def parse():
                         "committed profiles measure)")
     p.add_argument("--no-tune", action="store_true", help=argparse.SUPPRESS)
     p.add_argument("--no-batched", action="store_true")
+    p.add_argument("--no-fgmres", action="store_true",
+                   help="skip the flexible-GMRES solve of the same workload")
     p.add_argument("--copy-probe", action="store_true",
                    help="only run a device copy of known size (HBM counter calibration)")
     p.add_argument("--variants", default="bf16,fp64,fp32",
@@ -178,6 +180,8 @@ def main():
                                   + ", the one carrying most of the inverse apply's flops"),
                        "launches": lo["launches"], "avg_launch_ms": round(lo["ms"] / lo["launches"], 4)}
 
+    fg = None if args.no_fgmres else fgmres_run(Q, torch, A, Ai, head, F, K, N, rtol, args)
+
     batched = None if args.no_batched else batched_run(Q, torch)
 
     cpu = None
@@ -211,12 +215,41 @@ def main():
                                   if "fp64" in results and head != "fp64" else None),
         "roofline": roof,
         "roofline_inverse": roof_lo,
+        "fgmres": fg,
         "batched_uneven_L7": batched,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
     A.free()
     Ai.free()
+
+
+def fgmres_run(Q, torch, A, Ai, inv, F, K, N, rtol, args, max_iter=12):
+    """The same solve by flexible GMRES (the compressed inverse as right
+    preconditioner, section 5.2's outer solver): RHS/s, steps, and the true
+    relative residual recomputed by an FP64 apply outside the timed region."""
+    ws = Q.workspace(Q.qtt_fgmres_workspace_bytes(A, Ai, inv, K, max_iter))
+    Sig = Q.empty_block(N, K)
+    stream = torch.cuda.current_stream()
+    for _ in range(max(args.warmup, 1)):
+        Q.qtt_solve_fgmres(A, Ai, inv, F, Sig, rtol=rtol, max_iter=max_iter, ws=ws, stream=stream)
+    torch.cuda.synchronize()
+    lat, info = [], None
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        s0 = time.perf_counter()
+        _, info, _ = Q.qtt_solve_fgmres(A, Ai, inv, F, Sig, rtol=rtol, max_iter=max_iter, ws=ws, stream=stream)
+        lat.append((time.perf_counter() - s0) * 1e3)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    del ws
+    AS = Q.qtt_apply(A, "fp64", Sig)
+    true = ((F - AS).norm(dim=0) / F.norm(dim=0)).max().item()
+    return {"inverse_dtype": inv, "rhs_per_s": round(K * args.steps / el, 3),
+            "ms_per_step": round(1e3 * el / args.steps, 3),
+            "p50_ms": round(percentile(lat, 50), 3), "p99_ms": round(percentile(lat, 99), 3),
+            "steps": max(c[0] for c in info), "max_rel_residual_estimate": max(c[1] for c in info),
+            "max_rel_residual_true": true}
 
 
 def measured_traffic(dtype, shape):
