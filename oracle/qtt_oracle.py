@@ -18,6 +18,9 @@ equations in complex geometries", arXiv:1511.06029):
   A_T(b_1..b_d) with b_k = (i_k, j_k)); a core is G_k(a_{k-1}, i_k, j_k, a_k).
 * matrix by full vector -- section 4.2, Algorithm 2 (alg:TT-matvec).
 * TT-SVD -- section 2.2, Algorithm 1 (alg:TT-dec).
+* non-translation-invariant operators -- section 3, the matrix form of the
+  Nystrom discretisation (eq. nystrom): A = a I + B K W C with B, C, W
+  diagonal (entries b(x_i), c(y_j), w_j).
 * outer Krylov solver -- section 5.2 (boundary integral equations): the
   compressed approximate inverse preconditions an unrestarted GMRES with a
   relative-residual tolerance of 1e-8.  Because a low-precision inverse apply
@@ -41,7 +44,7 @@ __all__ = [
     "qtt_shapes", "qtt_entry", "qtt_to_dense", "qtt_apply_alg2",
     "alg2_flops", "tt_svd", "qtt_matrix_from_dense", "morton_points",
     "volume_self_term", "volume_matrix", "volume_apply_direct",
-    "richardson_solve", "fgmres_solve",
+    "richardson_solve", "fgmres_solve", "nti_apply",
 ]
 
 
@@ -296,6 +299,27 @@ def volume_apply_direct(L, X):
         conv = fftconvolve(grid, kern, mode="full")
         conv = conv[side - 1:2 * side - 1, side - 1:2 * side - 1, side - 1:2 * side - 1]
         Y[:, c] = conv[pts[:, 2], pts[:, 1], pts[:, 0]] + (1.0 + s) * X2[:, c]
+    return Y[:, 0] if one else Y
+
+
+# --------------------------------------------------------------------------
+# non-translation-invariant operators (sec. 3, eq. nystrom)
+# --------------------------------------------------------------------------
+
+def nti_apply(K_cores, a, b, wc, X):
+    """Y = (a I + B K W C) X with K a QTT matrix and B = diag(b), W C =
+    diag(wc) (the Nystrom matrix of section 3, eq. nystrom; wc holds the
+    products w_j c(y_j)).  b or wc = None stands for all ones.  Written as
+    the definition reads: scale the input, apply K by Algorithm 2, scale the
+    output, add a X."""
+    X = np.asarray(X, dtype=np.float64)
+    one = X.ndim == 1
+    X2 = X[:, None] if one else X
+    Xs = X2 if wc is None else np.asarray(wc, dtype=np.float64)[:, None] * X2
+    T = qtt_apply_alg2(K_cores, Xs)
+    if b is not None:
+        T = np.asarray(b, dtype=np.float64)[:, None] * T
+    Y = T + a * X2 if a != 0.0 else T
     return Y[:, 0] if one else Y
 
 

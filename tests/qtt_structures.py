@@ -106,3 +106,26 @@ def product_cores(Acores, Bcores):
         C = np.einsum("aixc,bxjd->abijcd", A, B)
         out.append(C.reshape(ra0 * rb0, m, n, ra1 * rb1))
     return out
+
+
+def sum_cores(Acores, Bcores):
+    """Cores of A + B (TT definition: the sum of two TT products): the first
+    cores side by side, the last stacked, the interior block diagonal, so the
+    ranks add."""
+    d = len(Acores)
+    out = []
+    for k, (A, B) in enumerate(zip(Acores, Bcores)):
+        ra0, m, n, ra1 = A.shape
+        rb0, _, _, rb1 = B.shape
+        if d == 1:
+            out.append(A + B)
+        elif k == 0:
+            out.append(np.concatenate([A, B], axis=3))
+        elif k == d - 1:
+            out.append(np.concatenate([A, B], axis=0))
+        else:
+            G = np.zeros((ra0 + rb0, m, n, ra1 + rb1))
+            G[:ra0, :, :, :ra1] = A
+            G[ra0:, :, :, ra1:] = B
+            out.append(G)
+    return out

@@ -399,3 +399,64 @@ def test_fgmres_qtt_pair_beats_refinement():
                                  rtol=1e-8, max_iter=20)
     assert its == it
     assert _rel(Xs, X) < 1e-10
+
+
+# ---------------------------------------------------------------- NTI operators (sec. 3)
+
+def test_nti_apply_matches_dense_definition():
+    """(a I + B K W C) X against the dense matrix assembled entry by entry
+    from the cores (heterogeneous modes, ragged K)."""
+    K = I.gaussian_qtt([1, 3, 5, 2, 1], [2, 3, 4, 2], seed=601)
+    N = 48
+    g = I.rng(602)
+    b = 1.0 + g.random(N)
+    wc = 0.5 + g.random(N)
+    X = I.rhs(N, 3, seed=603)
+    A = 1.7 * np.eye(N) + np.diag(b) @ O.qtt_to_dense(K) @ np.diag(wc)
+    np.testing.assert_allclose(O.nti_apply(K, 1.7, b, wc, X), A @ X, rtol=1e-13, atol=1e-13)
+    # no diagonals and a = 0 is the plain apply
+    assert np.array_equal(O.nti_apply(K, 0.0, None, None, X), O.qtt_apply_alg2(K, X))
+
+
+def test_nti_apply_matches_assembled_qtt():
+    """Diagonals given in TT form make A = a I + B K W C a QTT matrix (the
+    corollary on non-translation-invariant kernels: diag(b) from b's TT cores,
+    the product rule, and the TT sum).  Its Algorithm-2 apply equals the
+    structured apply."""
+    L = 4
+    K = I.gaussian_qtt([1, 4, 6, 4, 1], [8] * L, seed=611)
+    bt = [I.rng(612 + k).standard_normal((r0, 8, r1)) for k, (r0, r1) in enumerate([(1, 2), (2, 3), (3, 2), (2, 1)])]
+    ct = [I.rng(620 + k).standard_normal((r0, 8, r1)) for k, (r0, r1) in enumerate([(1, 2), (2, 2), (2, 2), (2, 1)])]
+    b = S.vector_tt_full(bt)
+    wc = S.vector_tt_full(ct)
+    eye = S.kron_cores([np.eye(8)] * L)
+    full = S.sum_cores([0.8 * eye[0]] + eye[1:],
+                       S.product_cores(S.product_cores(S.diag_cores(bt), K), S.diag_cores(ct)))
+    assert [G.shape[3] for G in full[:-1]] == [1 + 2 * 4 * 2, 1 + 3 * 6 * 2, 1 + 2 * 4 * 2]
+    X = I.rhs(8 ** L, 2, seed=630)
+    Y = O.nti_apply(K, 0.8, b, wc, X)
+    assert _rel(Y, O.qtt_apply_alg2(full, X)) < 1e-12
+
+
+@pytest.mark.slow
+def test_nti_volume_gaussians_vs_direct(volume_L4):
+    """The non-translation-invariant volume test of section 5.1: b(x) =
+    1 + exp(-|x - x0|^2), c(y) likewise, around the cube centre; the kernel
+    part (A - I of the volume operator, weights included) in QTT.  Against
+    direct summation from the coordinates, within the TT-SVD error bound."""
+    A, _, _ = volume_L4
+    L, N = 4, 4096
+    Kd = A - np.eye(N)
+    Kc, tails = O.qtt_matrix_from_dense(Kd, [8] * L, [8] * L, 1e-10)
+    h = 1.0 / 16
+    P = (O.morton_points(L) + 0.5) * h
+    r2 = ((P - 0.5) ** 2).sum(axis=1)
+    bx = 1.0 + np.exp(-r2)
+    cy = 1.0 + np.exp(-r2)
+    X = I.rhs(N, 2, seed=640)
+    Y = O.nti_apply(Kc, 1.0, bx, cy, X)
+    D = X + bx[:, None] * (O.volume_apply_direct(L, cy[:, None] * X) - cy[:, None] * X)
+    bound = np.sqrt(sum(t * t for t in tails))
+    for c in range(2):
+        # |B (K - K_tt) C x| <= max|b| |K - K_tt|_F max|c| |x|
+        assert np.linalg.norm(Y[:, c] - D[:, c]) <= bound * bx.max() * cy.max() * np.linalg.norm(X[:, c]) * 1.01 + 1e-13
