@@ -47,6 +47,8 @@ def parse():
                         "committed profiles measure)")
     p.add_argument("--no-tune", action="store_true", help=argparse.SUPPRESS)
     p.add_argument("--no-batched", action="store_true")
+    p.add_argument("--no-nti", action="store_true",
+                   help="skip the timing of the operator with diagonals (a I + B K W C)")
     p.add_argument("--no-fgmres", action="store_true",
                    help="skip the flexible-GMRES solve of the same workload")
     p.add_argument("--copy-probe", action="store_true",
@@ -182,6 +184,8 @@ def main():
 
     fg = None if args.no_fgmres else fgmres_run(Q, torch, A, Ai, head, F, K, N, rtol, args)
 
+    nti = None if args.no_nti else nti_run(Q, torch, Ac, F, K, N)
+
     batched = None if args.no_batched else batched_run(Q, torch)
 
     cpu = None
@@ -216,12 +220,42 @@ def main():
         "roofline": roof,
         "roofline_inverse": roof_lo,
         "fgmres": fg,
+        "nti_apply_L7": nti,
         "batched_uneven_L7": batched,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
     A.free()
     Ai.free()
+
+
+def nti_run(Q, torch, Ac, F, K, N, reps=10):
+    """FP64 apply of the L=7 operator as K alone and as a I + B K W C (the
+    non-translation-invariant form of section 3, diagonals as elementwise
+    passes around the sweep): the cost of the diagonals."""
+    from paper_1511_06029_amd import inputs as I
+    g = I.rng(2024)
+    b, wc = 1.0 + g.random(N), 1.0 + g.random(N)
+    A = Q.qtt_matrix_load(Ac, dtypes=("fp64",))
+    out = {}
+    for name, diag in (("plain_ms", None), ("nti_ms", (1.0, b, wc))):
+        if diag:
+            Q.qtt_matrix_set_diagonals(A, *diag)
+        ws = Q.workspace(Q.qtt_workspace_bytes(A, "fp64", K))
+        Y = Q.empty_block(N, K)
+        for _ in range(2):
+            Q.qtt_apply(A, "fp64", F, Y, ws=ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            Q.qtt_apply(A, "fp64", F, Y, ws=ws)
+        torch.cuda.synchronize()
+        out[name] = round(1e3 * (time.perf_counter() - t0) / reps, 3)
+        del ws, Y
+    A.free()
+    out["overhead"] = round(out["nti_ms"] / out["plain_ms"] - 1.0, 4)
+    out["config"] = "L=7, ranks [1,24,32,32,32,32,24,1], K=8 vectors, FP64, a=1, b and wc in [1,2)"
+    return out
 
 
 def fgmres_run(Q, torch, A, Ai, inv, F, K, N, rtol, args, max_iter=12):

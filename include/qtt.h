@@ -87,6 +87,25 @@ qtt_status_t qtt_matrix_load(int32_t d, const int64_t* ranks, const int64_t* m,
 
 qtt_status_t qtt_matrix_free(qtt_matrix_t A);
 
+/* Make A the non-translation-invariant operator of section 3 (the matrix
+ * form of the Nystrom discretisation):
+ *     A = a I + B K W C,   B = diag(b), W C = diag(wc),
+ * with K the QTT matrix the handle was loaded with.  From then on every
+ * apply through A (qtt_apply, qtt_apply_batched, and A or Ainv inside
+ * qtt_solve and qtt_solve_fgmres) computes y = a x + b . K (wc . x): the
+ * diagonals are elementwise passes before and after K's sweep, so the ranks
+ * stay those of K (assembling the diagonals into the cores would multiply
+ * them).
+ *   b   host FP64, rows values, or NULL for ones; wc: host FP64, cols values
+ *       (the products w_j c(y_j)), or NULL for ones.  Both are copied.
+ *   a   needs rows == cols unless 0 (else QTT_ERR_SHAPE).
+ * a = 0 with b = wc = NULL restores the plain K.  The workspace an apply
+ * needs grows by (rows + cols) FP64 values per vector
+ * (qtt_workspace_bytes reports it).  Not to be called while the handle is in
+ * use on a stream.  QTT_ERR_INVALID_ARG for non-finite values,
+ * QTT_ERR_OUT_OF_MEMORY if the copies cannot be allocated. */
+qtt_status_t qtt_matrix_set_diagonals(qtt_matrix_t A, double a, const double* b, const double* wc);
+
 /* Shape of a loaded matrix; any output pointer may be NULL. */
 qtt_status_t qtt_matrix_info(qtt_matrix_t A, int32_t* d, int64_t* rows, int64_t* cols,
                              int64_t* max_rank, uint32_t* dtypes);
@@ -94,8 +113,10 @@ qtt_status_t qtt_matrix_info(qtt_matrix_t A, int32_t* d, int64_t* rows, int64_t*
 /* Device bytes of workspace that let qtt_apply / qtt_apply_batched run nrhs
  * vectors in one sweep: two ping-pong buffers of the largest intermediate
  * (r_k x prod_{l<=k} m_l x prod_{l>k} n_l values per vector, Algorithm 2's
- * y_k) in the compute dtype, plus alignment.  A smaller workspace (at least
- * the value for nrhs = 1) makes the library process the vectors in waves. */
+ * y_k) in the compute dtype, plus alignment; for an operator with
+ * diagonals (qtt_matrix_set_diagonals) also rows + cols FP64 values per
+ * vector.  A smaller workspace (at least the value for nrhs = 1) makes the
+ * library process the vectors in waves. */
 qtt_status_t qtt_workspace_bytes(qtt_matrix_t A, qtt_dtype_t compute, int64_t nrhs,
                                  size_t* bytes);
 

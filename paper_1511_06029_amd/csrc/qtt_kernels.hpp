@@ -2875,4 +2875,61 @@ __global__ void __launch_bounds__(kKryThreads) combine_kernel(const CombineArgs 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Non-translation-invariant operators A = a I + B K W C (section 3, the
+// matrix form of the Nystrom discretisation): B = diag(b), W C = diag(wc),
+// K the QTT matrix.  The diagonals are elementwise passes around K's sweep,
+// each one read and one write of the vectors (HBM-bound):
+//   before: S[:, t] = wc . x_t            (S dense, column t at S + t * rows)
+//   after:  y_t = z_t + alpha (a x_t + b . S[:, t])
+// Vector t of the launch belongs to the segment whose rhs_begin is the
+// largest one <= t.
+// ---------------------------------------------------------------------------
+
+struct DiagArgs {
+  Segment seg[kMaxSeg];
+  int32_t nseg;
+  int64_t ncol;          // vectors in the launch
+  int64_t rows;          // length of the columns handled (N before, M after)
+  const double* d;       // wc before, b after; NULL = ones
+  double* S;             // scratch, column t at S + t * rows
+  double a, alpha;       // after only
+};
+
+__device__ inline int diag_segment(const DiagArgs& a, int64_t t) {
+  int s = 0;
+  for (int q = 1; q < a.nseg; ++q) s = (a.seg[q].rhs_begin <= t) ? q : s;
+  return s;
+}
+
+__global__ void __launch_bounds__(256) diag_in_kernel(const DiagArgs args) {
+  (void)args;
+  const DiagArgs& a = kernarg<DiagArgs>();
+  for (int64_t t = blockIdx.y; t < a.ncol; t += gridDim.y) {
+    const Segment& sg = a.seg[diag_segment(a, t)];
+    const double* x = sg.x + (t - sg.rhs_begin) * sg.ldx;
+    double* out = a.S + t * a.rows;
+    for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < a.rows; r += (int64_t)gridDim.x * 256)
+      out[r] = a.d ? a.d[r] * x[r] : x[r];
+  }
+}
+
+__global__ void __launch_bounds__(256) diag_out_kernel(const DiagArgs args) {
+  (void)args;
+  const DiagArgs& a = kernarg<DiagArgs>();
+  for (int64_t t = blockIdx.y; t < a.ncol; t += gridDim.y) {
+    const Segment& sg = a.seg[diag_segment(a, t)];
+    const int64_t v = t - sg.rhs_begin;
+    const double* x = sg.x + v * sg.ldx;
+    const double* z = sg.z ? sg.z + v * sg.ldz : nullptr;
+    double* y = sg.y + v * sg.ldy;
+    const double* T = a.S + t * a.rows;
+    for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < a.rows; r += (int64_t)gridDim.x * 256) {
+      double u = a.d ? a.d[r] * T[r] : T[r];
+      if (a.a != 0.0) u = fma(a.a, x[r], u);
+      y[r] = z ? fma(a.alpha, u, z[r]) : a.alpha * u;
+    }
+  }
+}
+
 }  // namespace qtt

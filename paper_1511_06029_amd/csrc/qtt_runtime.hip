@@ -499,6 +499,12 @@ struct qtt_matrix_s {
   bool fp64_t_ok = false; // every mode size is 8, so the mode is available
   bool fp64_pair = true;  // FP64 sweeps fuse interior core pairs where the pair kernel applies
   bool fp32_pair = true;  // the same for FP32 sweeps
+  // a I + diag(b) K diag(wc) (non-translation-invariant operator); device
+  // arrays of rows / cols values, NULL = ones
+  bool has_diag = false;
+  double diag_a = 0.0;
+  double* diag_b = nullptr;
+  double* diag_wc = nullptr;
   // captured sweeps: a sweep with the same dtype, vectors, pointers, workspace
   // and alpha replays its graph instead of launching d kernels
   struct Graph {
@@ -827,14 +833,24 @@ static size_t wave_buffer_bytes(const qtt_matrix_s* A, int dt, int64_t nrhs) {
   return align256((size_t)A->max_inter * kElemBytes[dt] * (size_t)nrhs);
 }
 
+// the two dense FP64 blocks around the sweep of an operator with diagonals
+static size_t diag_scratch_bytes(const qtt_matrix_s* A, int64_t nrhs) {
+  if (!A->has_diag) return 0;
+  return align256((size_t)A->cols * 8 * nrhs) + align256((size_t)A->rows * 8 * nrhs);
+}
+
+// workspace of one wave of nrhs vectors: the sweep's two buffers, then the
+// diagonal scratch
+static size_t wave_total_bytes(const qtt_matrix_s* A, int dt, int64_t nrhs) {
+  return (A->d > 1 ? 2 * wave_buffer_bytes(A, dt, nrhs) : 0) + diag_scratch_bytes(A, nrhs);
+}
+
 static int64_t wave_capacity(const qtt_matrix_s* A, int dt, size_t ws_bytes) {
-  if (A->d == 1) return INT64_MAX;
-  const size_t per = (size_t)A->max_inter * kElemBytes[dt];
+  const size_t per = (A->d > 1 ? 2 * (size_t)A->max_inter * kElemBytes[dt] : 0)
+                     + (A->has_diag ? (size_t)(A->rows + A->cols) * 8 : 0);
   if (per == 0) return INT64_MAX;
-  // two buffers, each 256-byte aligned
-  if (ws_bytes < 2 * align256(per)) return 0;
-  int64_t w = (int64_t)(ws_bytes / (2 * per));
-  while (w > 0 && 2 * wave_buffer_bytes(A, dt, w) > ws_bytes) --w;
+  int64_t w = (int64_t)(ws_bytes / per);
+  while (w > 0 && wave_total_bytes(A, dt, w) > ws_bytes) --w;
   return w;
 }
 
@@ -1040,6 +1056,48 @@ static qtt_status_t sweep_graph(const qtt_matrix_s* A, int dt, int64_t nrhs, con
   return QTT_OK;
 }
 
+// y = z + alpha (a x + b . K (wc . x)) for a wave: scale the inputs into the
+// first scratch block, sweep K from it into the second, then the epilogue.
+// The scratch sits after the sweep buffers of a full wave (cap vectors), so
+// it never overlaps the buffers of this wave.
+static qtt_status_t diag_sweep(const qtt_matrix_s* A, int dt, int64_t nrhs, int64_t cap,
+                               const std::vector<Segment>& segs, void* ws, double alpha, hipStream_t st) {
+  char* base = static_cast<char*>(ws) + (A->d > 1 ? 2 * wave_buffer_bytes(A, dt, cap) : 0);
+  double* S1 = reinterpret_cast<double*>(base);
+  double* S2 = reinterpret_cast<double*>(base + align256((size_t)A->cols * 8 * cap));
+  DiagArgs da;
+  memset(&da, 0, sizeof(da));
+  for (size_t i = 0; i < segs.size(); ++i) da.seg[i] = segs[i];
+  da.nseg = (int32_t)segs.size();
+  da.ncol = nrhs;
+  auto grid = [&](int64_t rows) {
+    return dim3((unsigned)std::min<int64_t>(256, std::max<int64_t>(1, (rows + 255) / 256)),
+                (unsigned)std::min<int64_t>(nrhs, 65535));
+  };
+  da.rows = A->cols;
+  da.d = A->diag_wc;
+  da.S = S1;
+  void* args[] = {&da};
+  HIP_TRY(hipLaunchKernel(reinterpret_cast<const void*>(&diag_in_kernel), grid(A->cols), dim3(256), args, 0, st));
+  Segment one;
+  one.x = S1;
+  one.y = S2;
+  one.z = nullptr;
+  one.ldx = A->cols;
+  one.ldy = A->rows;
+  one.ldz = 0;
+  one.rhs_begin = 0;
+  qtt_status_t s = sweep_graph(A, dt, nrhs, &one, 1, ws, 1.0, st);
+  if (s != QTT_OK) return s;
+  da.rows = A->rows;
+  da.d = A->diag_b;
+  da.S = S2;
+  da.a = A->diag_a;
+  da.alpha = alpha;
+  HIP_TRY(hipLaunchKernel(reinterpret_cast<const void*>(&diag_out_kernel), grid(A->rows), dim3(256), args, 0, st));
+  return QTT_OK;
+}
+
 // A block of vectors before splitting into waves.
 struct Block {
   const double* x;
@@ -1057,14 +1115,15 @@ static qtt_status_t run_blocks(const qtt_matrix_s* A, int dt, const std::vector<
   if (total == 0) return QTT_OK;
   const int64_t cap = wave_capacity(A, dt, ws_bytes);
   if (cap < 1) {
-    size_t need = 2 * wave_buffer_bytes(A, dt, 1);
+    size_t need = wave_total_bytes(A, dt, 1);
     return fail(QTT_ERR_WORKSPACE, "workspace of %zu bytes is below the one-vector minimum %zu", ws_bytes, need);
   }
   std::vector<Segment> segs;
   int64_t in_wave = 0;
   auto flush = [&]() -> qtt_status_t {
     if (in_wave == 0) return QTT_OK;
-    qtt_status_t s = sweep_graph(A, dt, in_wave, segs.data(), (int)segs.size(), ws, alpha, st);
+    qtt_status_t s = A->has_diag ? diag_sweep(A, dt, in_wave, cap, segs, ws, alpha, st)
+                                 : sweep_graph(A, dt, in_wave, segs.data(), (int)segs.size(), ws, alpha, st);
     segs.clear();
     in_wave = 0;
     return s;
@@ -1311,6 +1370,8 @@ qtt_status_t qtt_matrix_free(qtt_matrix_t A) {
   if (A == nullptr) return QTT_OK;
   drop_graphs(A);
   if (A->cap_stream) (void)hipStreamDestroy(A->cap_stream);
+  if (A->diag_b) (void)hipFree(A->diag_b);
+  if (A->diag_wc) (void)hipFree(A->diag_wc);
   for (auto& c : A->core) {
     for (int t = 0; t < 3; ++t)
       if (c.frag[t]) (void)hipFree(c.frag[t]);
@@ -1319,6 +1380,41 @@ qtt_status_t qtt_matrix_free(qtt_matrix_t A) {
     if (c.valut) (void)hipFree(c.valut);
   }
   delete A;
+  return QTT_OK;
+}
+
+qtt_status_t qtt_matrix_set_diagonals(qtt_matrix_t A, double a, const double* b, const double* wc) {
+  if (!valid_handle(A)) return fail(QTT_ERR_INVALID_ARG, "null handle");
+  if (!std::isfinite(a)) return fail(QTT_ERR_INVALID_ARG, "a is not finite");
+  if (a != 0.0 && A->rows != A->cols) return fail(QTT_ERR_SHAPE, "a I needs a square matrix");
+  for (int64_t i = 0; b && i < A->rows; ++i)
+    if (!std::isfinite(b[i])) return fail(QTT_ERR_INVALID_ARG, "b[%lld] is not finite", (long long)i);
+  for (int64_t i = 0; wc && i < A->cols; ++i)
+    if (!std::isfinite(wc[i])) return fail(QTT_ERR_INVALID_ARG, "wc[%lld] is not finite", (long long)i);
+  int cur = 0;
+  HIP_TRY(hipGetDevice(&cur));
+  HIP_TRY(hipSetDevice(A->device));
+  auto upload = [&](const double* h, int64_t n, double** dptr) -> qtt_status_t {
+    if (*dptr) (void)hipFree(*dptr);
+    *dptr = nullptr;
+    if (!h) return QTT_OK;
+    if (hipMalloc(reinterpret_cast<void**>(dptr), std::max<size_t>(n * 8, 256)) != hipSuccess) {
+      *dptr = nullptr;
+      return fail(QTT_ERR_OUT_OF_MEMORY, "hipMalloc of %lld diagonal entries failed", (long long)n);
+    }
+    HIP_TRY(hipMemcpy(*dptr, h, n * 8, hipMemcpyHostToDevice));
+    return QTT_OK;
+  };
+  qtt_status_t s = upload(b, A->rows, &A->diag_b);
+  if (s == QTT_OK) s = upload(wc, A->cols, &A->diag_wc);
+  (void)hipSetDevice(cur);
+  if (s != QTT_OK) {
+    A->has_diag = false;
+    return s;
+  }
+  A->diag_a = a;
+  A->has_diag = (a != 0.0) || b || wc;
+  drop_graphs(A);
   return QTT_OK;
 }
 
@@ -1339,7 +1435,7 @@ qtt_status_t qtt_workspace_bytes(qtt_matrix_t A, qtt_dtype_t compute, int64_t nr
   int dt;
   qtt_status_t s = check_dtype(A, compute, &dt);
   if (s != QTT_OK) return s;
-  *bytes = (A->d == 1) ? 0 : 2 * wave_buffer_bytes(A, dt, std::max<int64_t>(nrhs, 1));
+  *bytes = wave_total_bytes(A, dt, std::max<int64_t>(nrhs, 1));
   return QTT_OK;
 }
 
@@ -1353,7 +1449,7 @@ qtt_status_t qtt_apply(qtt_matrix_t A, qtt_dtype_t compute, int64_t nrhs, const 
   if (nrhs == 0) return QTT_OK;
   if (!X || !Y) return fail(QTT_ERR_INVALID_ARG, "X or Y is null");
   if (ldx < A->cols || ldy < A->rows) return fail(QTT_ERR_INVALID_ARG, "ldx < N or ldy < M");
-  if (A->d > 1 && !ws) return fail(QTT_ERR_INVALID_ARG, "workspace is null");
+  if (wave_total_bytes(A, dt, 1) > 0 && !ws) return fail(QTT_ERR_INVALID_ARG, "workspace is null");
   const size_t xb = ((size_t)(nrhs - 1) * ldx + A->cols) * 8, yb = ((size_t)(nrhs - 1) * ldy + A->rows) * 8;
   if (overlaps(X, xb, Y, yb)) return fail(QTT_ERR_INVALID_ARG, "X and Y overlap");
   if (ws && (overlaps(ws, ws_bytes, X, xb) || overlaps(ws, ws_bytes, Y, yb)))
@@ -1372,7 +1468,7 @@ qtt_status_t qtt_apply_batched(qtt_matrix_t A, qtt_dtype_t compute, int32_t nblo
   if (nblocks < 0) return fail(QTT_ERR_INVALID_ARG, "nblocks < 0");
   if (nblocks == 0) return QTT_OK;
   if (!widths || !X || !ldx || !Y || !ldy) return fail(QTT_ERR_INVALID_ARG, "null block array");
-  if (A->d > 1 && !ws) return fail(QTT_ERR_INVALID_ARG, "workspace is null");
+  if (wave_total_bytes(A, dt, 1) > 0 && !ws) return fail(QTT_ERR_INVALID_ARG, "workspace is null");
   std::vector<Block> blocks;
   std::vector<std::pair<const void*, size_t>> xs, ys;
   for (int b = 0; b < nblocks; ++b) {

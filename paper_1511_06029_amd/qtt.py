@@ -55,6 +55,7 @@ def _load():
     sig = {
         "qtt_matrix_load": [I32, PI64, PI64, PI64, PP, U32, PP],
         "qtt_matrix_free": [P],
+        "qtt_matrix_set_diagonals": [P, D, P, P],
         "qtt_matrix_info": [P, ctypes.POINTER(I32), PI64, PI64, PI64, ctypes.POINTER(U32)],
         "qtt_workspace_bytes": [P, I32, I64, ctypes.POINTER(SZ)],
         "qtt_apply": [P, I32, I64, P, I64, P, I64, P, SZ, P],
@@ -84,7 +85,7 @@ def _load():
 
 _lib = _load()
 # Names the C ABI exports (include/qtt.h); the tests check each is present.
-EXPORTED = ["qtt_matrix_load", "qtt_matrix_free", "qtt_matrix_info", "qtt_workspace_bytes",
+EXPORTED = ["qtt_matrix_load", "qtt_matrix_free", "qtt_matrix_set_diagonals", "qtt_matrix_info", "qtt_workspace_bytes",
             "qtt_apply", "qtt_apply_batched", "qtt_autotune", "qtt_solve_workspace_bytes",
             "qtt_solve", "qtt_fgmres_workspace_bytes", "qtt_solve_fgmres", "qtt_status_string", "qtt_last_error", "qtt_set_shape", "qtt_list_shapes",
             "qtt_timing_enable",
@@ -187,6 +188,18 @@ def qtt_matrix_load(cores, dtypes=("fp64",)):
     h = ctypes.c_void_p()
     _check(_lib.qtt_matrix_load(d, r, mm, nn, ptrs, flags, ctypes.byref(h)))
     return QttMatrix(h, (ranks, m, n))
+
+
+def qtt_matrix_set_diagonals(A, a=0.0, b=None, wc=None):
+    """A becomes a I + diag(b) K diag(wc) (b, wc: host FP64 arrays or None)."""
+    def host(v):
+        if v is None:
+            return None, None
+        arr = np.ascontiguousarray(v, dtype=np.float64)
+        return arr, arr.ctypes.data_as(ctypes.c_void_p)
+    bh, bp = host(b)
+    wh, wp = host(wc)
+    _check(_lib.qtt_matrix_set_diagonals(A.handle, float(a), bp, wp))
 
 
 def qtt_matrix_info(A):

@@ -1,0 +1,153 @@
+"""GPU parity of non-translation-invariant operators A = a I + B K W C
+(section 3, Nystrom matrix form) against the oracle's nti_apply.
+
+Tolerances as for the plain apply (normwise per column, worst column): FP64
+1e-12 (and elementwise 1e-12 of the column maximum), FP32 1e-5, BF16 3e-2;
+solves: relative residual <= 1e-8 recomputed by the oracle.
+"""
+import numpy as np
+import pytest
+
+from oracle import qtt_oracle as O
+from paper_1511_06029_amd import inputs as I
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32": 1e-5, "bf16": 3e-2}
+
+
+@pytest.fixture(scope="module")
+def Q():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    from paper_1511_06029_amd import qtt
+    return qtt
+
+
+def colrel(Y, R):
+    Y = np.asarray(Y).reshape(R.shape[0], -1)
+    R = R.reshape(R.shape[0], -1)
+    return max(np.linalg.norm(Y[:, c] - R[:, c]) / max(np.linalg.norm(R[:, c]), 1e-300)
+               for c in range(R.shape[1]))
+
+
+def _diags(N, seed):
+    g = I.rng(seed)
+    return 0.5 + g.random(N), 0.5 + g.random(N)
+
+
+@pytest.mark.parametrize("dtype", ["fp64", "fp32", "bf16"])
+def test_nti_apply(Q, dtype):
+    K = I.gaussian_qtt([1, 6, 8, 6, 1], [8] * 4, seed=701)
+    b, wc = _diags(4096, 702)
+    X = I.rhs(4096, 3, seed=703)
+    A = Q.qtt_matrix_load(K, dtypes=(dtype,))
+    Q.qtt_matrix_set_diagonals(A, 1.3, b, wc)
+    Y = Q.qtt_apply(A, dtype, Q.to_block(X)).cpu().numpy()
+    R = O.nti_apply(K, 1.3, b, wc, X)
+    assert colrel(Y, R) <= TOL[dtype]
+    if dtype == "fp64":
+        assert np.all(np.abs(Y - R) <= 1e-12 * np.abs(R).max(axis=0)[None, :])
+    A.free()
+
+
+def test_nti_partial_diagonals_and_clear(Q):
+    """Only b, only wc, only a; clearing gives back the plain apply bitwise."""
+    K = I.gaussian_qtt([1, 5, 7, 1], [8] * 3, seed=711)
+    b, wc = _diags(512, 712)
+    X = I.rhs(512, 2, seed=713)
+    A = Q.qtt_matrix_load(K, dtypes=("fp64",))
+    Xd = Q.to_block(X)
+    plain = Q.qtt_apply(A, "fp64", Xd).clone()
+    for a_, b_, w_ in ((0.0, b, None), (0.0, None, wc), (2.0, None, None)):
+        Q.qtt_matrix_set_diagonals(A, a_, b_, w_)
+        Y = Q.qtt_apply(A, "fp64", Xd).cpu().numpy()
+        assert colrel(Y, O.nti_apply(K, a_, b_, w_, X)) <= 1e-12
+    Q.qtt_matrix_set_diagonals(A)
+    assert torch.equal(Q.qtt_apply(A, "fp64", Xd), plain)
+    A.free()
+
+
+def test_nti_batched_and_waves(Q):
+    """Uneven blocks in one batched call, and a one-vector workspace (waves
+    of one vector): both equal the oracle, and the waves give the same bits
+    as one full wave."""
+    K = I.gaussian_qtt([1, 6, 8, 6, 1], [8] * 4, seed=721)
+    b, wc = _diags(4096, 722)
+    A = Q.qtt_matrix_load(K, dtypes=("fp64",))
+    Q.qtt_matrix_set_diagonals(A, -0.7, b, wc)
+    widths = [1, 4, 2]
+    Xs = [I.rhs(4096, w, seed=723 + i) for i, w in enumerate(widths)]
+    Ys = Q.qtt_apply_batched(A, "fp64", [Q.to_block(x) for x in Xs])
+    for x, y in zip(Xs, Ys):
+        assert colrel(y.cpu().numpy(), O.nti_apply(K, -0.7, b, wc, x)) <= 1e-12
+    X = Q.to_block(Xs[1])
+    full = Q.qtt_apply(A, "fp64", X)
+    one = Q.qtt_apply(A, "fp64", X, ws=Q.workspace(Q.qtt_workspace_bytes(A, "fp64", 1)))
+    assert torch.equal(full, one)
+    A.free()
+
+
+@pytest.mark.parametrize("solver", ["refine", "fgmres"])
+def test_nti_solve(Q, solver):
+    """A = B A0 C and Ainv = C^-1 A0inv B^-1 (both as operators with
+    diagonals, a = 0): refinement and flexible GMRES reach 1e-8, the residual
+    recomputed by the oracle; BF16 inverse."""
+    A0, A0i = I.perturbed_identity_pair([1, 6, 8, 6, 1], [8] * 4, seed=81)
+    b, c = _diags(4096, 731)
+    F = I.rhs(4096, 3, seed=732)
+    A = Q.qtt_matrix_load(A0, dtypes=("fp64",))
+    Ai = Q.qtt_matrix_load(A0i, dtypes=("bf16",))
+    Q.qtt_matrix_set_diagonals(A, 0.0, b, c)
+    Q.qtt_matrix_set_diagonals(Ai, 0.0, 1.0 / c, 1.0 / b)
+    Fd = Q.to_block(F)
+    if solver == "refine":
+        Sig, info, st = Q.qtt_solve(A, Ai, "bf16", Fd, rtol=1e-8)
+    else:
+        Sig, info, st = Q.qtt_solve_fgmres(A, Ai, "bf16", Fd, rtol=1e-8)
+    S = Sig.cpu().numpy()
+    R = F - O.nti_apply(A0, 0.0, b, c, S)
+    for k in range(3):
+        assert np.linalg.norm(R[:, k]) <= 1e-8 * np.linalg.norm(F[:, k]) * 1.0001
+    assert max(i[0] for i in info) <= 8
+    A.free()
+    Ai.free()
+
+
+def test_nti_volume_gaussians(Q):
+    """The section 5.1 non-translation-invariant volume test: the kernel part
+    of the L=4 volume operator in QTT, b(x) = c(x) = 1 + exp(-|x - x0|^2)
+    around the cube centre, a = 1."""
+    L, N = 4, 4096
+    Kd = O.volume_matrix(L) - np.eye(N)
+    Kc, _ = O.qtt_matrix_from_dense(Kd, [8] * L, [8] * L, 1e-10)
+    P = (O.morton_points(L) + 0.5) / 16
+    g = 1.0 + np.exp(-((P - 0.5) ** 2).sum(axis=1))
+    X = I.rhs(N, 2, seed=741)
+    A = Q.qtt_matrix_load(Kc, dtypes=("fp64",))
+    Q.qtt_matrix_set_diagonals(A, 1.0, g, g)
+    Y = Q.qtt_apply(A, "fp64", Q.to_block(X)).cpu().numpy()
+    assert colrel(Y, O.nti_apply(Kc, 1.0, g, g, X)) <= 1e-12
+    A.free()
+
+
+def test_nti_errors(Q):
+    K = I.gaussian_qtt([1, 3, 1], [4, 8], [8, 8], seed=751)   # 32 x 64
+    A = Q.qtt_matrix_load(K, dtypes=("fp64",))
+    with pytest.raises(Q.QttError) as e:
+        Q.qtt_matrix_set_diagonals(A, 1.0)
+    assert e.value.status == 2
+    bad = np.ones(32)
+    bad[3] = np.nan
+    with pytest.raises(Q.QttError) as e:
+        Q.qtt_matrix_set_diagonals(A, 0.0, bad)
+    assert e.value.status == 1
+    # rectangular with a = 0: fine
+    b = np.linspace(1, 2, 32)
+    wc = np.linspace(0.5, 1, 64)
+    Q.qtt_matrix_set_diagonals(A, 0.0, b, wc)
+    X = I.rhs(64, 2, seed=752)
+    Y = Q.qtt_apply(A, "fp64", Q.to_block(X)).cpu().numpy()
+    assert colrel(Y, O.nti_apply(K, 0.0, b, wc, X)) <= 1e-12
+    A.free()
