@@ -17,6 +17,9 @@ equations in complex geometries", arXiv:1511.06029):
 * QTT matrix over the product tree -- section 3 (tensorized matrix
   A_T(b_1..b_d) with b_k = (i_k, j_k)); a core is G_k(a_{k-1}, i_k, j_k, a_k).
 * matrix by full vector -- section 4.2, Algorithm 2 (alg:TT-matvec).
+* matrix by compressed vector -- section 4.2 (QTT compressed matrix-vector
+  product): the cores of c = A b are the contractions over j_k of A's and
+  b's cores, with the rank pairs merged (ranks multiply).
 * TT-SVD -- section 2.2, Algorithm 1 (alg:TT-dec).
 * non-translation-invariant operators -- section 3, the matrix form of the
   Nystrom discretisation (eq. nystrom): A = a I + B K W C with B, C, W
@@ -44,7 +47,7 @@ __all__ = [
     "qtt_shapes", "qtt_entry", "qtt_to_dense", "qtt_apply_alg2",
     "alg2_flops", "tt_svd", "qtt_matrix_from_dense", "morton_points",
     "volume_self_term", "volume_matrix", "volume_apply_direct",
-    "richardson_solve", "fgmres_solve", "nti_apply",
+    "richardson_solve", "fgmres_solve", "nti_apply", "qtt_matvec_compressed",
 ]
 
 
@@ -150,6 +153,27 @@ def qtt_apply_alg2(cores, X):
     for c in range(X.shape[1]):
         Y[:, c] = _alg2_one(cores, X[:, c])
     return Y
+
+
+def qtt_matvec_compressed(A_cores, b_cores):
+    """Cores of c = A b when b is itself in TT form (section 4.2, compressed
+    matrix-vector product):
+
+        G^c_k(alpha + rA_{k-1} beta, i, alpha' + rA_k beta')
+            = sum_j G^A_k(alpha, i, j, alpha') G^b_k(beta, j, beta')
+
+    The merged rank index puts the matrix's rank first (fastest), the
+    paper's merged-index order.  b_cores[k] has shape (rb_{k-1}, n_k, rb_k);
+    the result has shape (rA_{k-1} rb_{k-1}, m_k, rA_k rb_k)."""
+    out = []
+    for GA, Gb in zip(A_cores, b_cores):
+        ra0, m, n, ra1 = GA.shape
+        rb0, n2, rb1 = Gb.shape
+        if n2 != n:
+            raise ValueError("mode sizes of A and b differ")
+        T = np.einsum("aijc,bjd->baidc", GA, Gb)   # [beta, alpha, i, beta', alpha']
+        out.append(T.reshape(rb0 * ra0, m, rb1 * ra1))
+    return out
 
 
 def alg2_flops(ranks, m, n):

@@ -460,3 +460,35 @@ def test_nti_volume_gaussians_vs_direct(volume_L4):
     for c in range(2):
         # |B (K - K_tt) C x| <= max|b| |K - K_tt|_F max|c| |x|
         assert np.linalg.norm(Y[:, c] - D[:, c]) <= bound * bx.max() * cy.max() * np.linalg.norm(X[:, c]) * 1.01 + 1e-13
+
+
+# ---------------------------------------------------------------- compressed product (sec. 4.2)
+
+def _tt_vector(ranks, n, seed):
+    return [I.rng(seed + k).standard_normal((ranks[k], n[k], ranks[k + 1])) for k in range(len(n))]
+
+
+def test_compressed_matvec_expands_to_dense_product():
+    """The cores of A b, expanded by the TT definition, equal the dense A
+    (entry by entry from the cores) times the expanded b; heterogeneous
+    modes and ranks, ranks multiply."""
+    m, n = [2, 3, 4, 2], [3, 2, 2, 4]
+    A = I.gaussian_qtt([1, 3, 5, 2, 1], m, n, seed=801)
+    b = _tt_vector([1, 2, 3, 2, 1], n, 802)
+    c = O.qtt_matvec_compressed(A, b)
+    assert [G.shape for G in c] == [(1, 2, 6), (6, 3, 15), (15, 4, 4), (4, 2, 1)]
+    full = O.qtt_to_dense(A) @ S.vector_tt_full(b)
+    np.testing.assert_allclose(S.vector_tt_full(c), full, rtol=1e-12, atol=1e-12 * np.abs(full).max())
+
+
+def test_compressed_matvec_identity_and_rank_one():
+    """Identity cores (rank 1) give back b's cores bitwise; rank-1 A and b
+    give the mode-wise products A_k b_k (Kronecker closed form)."""
+    b = _tt_vector([1, 3, 4, 2, 1], [8] * 4, 811)
+    c = O.qtt_matvec_compressed(I.identity_qtt([8] * 4), b)
+    assert all(np.array_equal(x, y) for x, y in zip(c, b))
+    mats = [I.rng(820 + k).standard_normal((4, 4)) for k in range(3)]
+    vecs = [I.rng(830 + k).standard_normal(4) for k in range(3)]
+    c = O.qtt_matvec_compressed(S.kron_cores(mats), [v.reshape(1, 4, 1) for v in vecs])
+    for k in range(3):
+        np.testing.assert_allclose(c[k].reshape(4), mats[k] @ vecs[k], rtol=1e-14)
