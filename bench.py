@@ -47,6 +47,8 @@ def parse():
                         "committed profiles measure)")
     p.add_argument("--no-tune", action="store_true", help=argparse.SUPPRESS)
     p.add_argument("--no-batched", action="store_true")
+    p.add_argument("--no-compressed", action="store_true",
+                   help="skip the compressed matrix-vector product timing")
     p.add_argument("--no-nti", action="store_true",
                    help="skip the timing of the operator with diagonals (a I + B K W C)")
     p.add_argument("--no-fgmres", action="store_true",
@@ -185,6 +187,7 @@ def main():
     fg = None if args.no_fgmres else fgmres_run(Q, torch, A, Ai, head, F, K, N, rtol, args)
 
     nti = None if args.no_nti else nti_run(Q, torch, Ac, F, K, N)
+    cmv = None if args.no_compressed else compressed_run(Q, torch, Ac)
 
     batched = None if args.no_batched else batched_run(Q, torch)
 
@@ -221,12 +224,41 @@ def main():
         "roofline_inverse": roof_lo,
         "fgmres": fg,
         "nti_apply_L7": nti,
+        "compressed_matvec_L7": cmv,
         "batched_uneven_L7": batched,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
     A.free()
     Ai.free()
+
+
+def compressed_run(Q, torch, Ac, nvec=64, rank=8, reps=20):
+    """The compressed matrix-vector product (section 4.2) of the L=7 operator
+    with a batch of TT vectors of rank 8: vectors/s and HBM rate (algorithmic
+    bytes = input and output cores plus the operator's cores, per call)."""
+    from paper_1511_06029_amd import inputs as I
+    d = len(Ac)
+    rb = [1] + [rank] * (d - 1) + [1]
+    g = I.rng(77)
+    B = [torch.from_numpy(g.standard_normal((nvec, rb[k], 8, rb[k + 1]))).cuda() for k in range(d)]
+    A = Q.qtt_matrix_load(Ac, dtypes=("fp64",))
+    C = Q.qtt_matvec_compressed(A, B)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        Q.qtt_matvec_compressed(A, B, C)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    nbytes = sum(x.numel() for x in B) * 8 + sum(x.numel() for x in C) * 8 + sum(G.size for G in Ac) * 8
+    A.free()
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    return {"vectors": nvec, "vector_rank": rank, "ms_per_call": round(ms, 4),
+            "vectors_per_s": round(nvec / (ms * 1e-3), 1), "bytes_per_call": nbytes,
+            "achieved_GBs": round(gbs, 1), "frac_of_hbm_peak": round(gbs / PEAK_HBM_GBS, 4),
+            "config": "L=7 operator, ranks [1,24,32,32,32,32,24,1]; TT vectors of rank 8; FP64"}
 
 
 def nti_run(Q, torch, Ac, F, K, N, reps=10):

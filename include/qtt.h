@@ -236,6 +236,25 @@ qtt_status_t qtt_solve_fgmres(qtt_matrix_t A, qtt_matrix_t Ainv, qtt_dtype_t inv
                               double rtol, int32_t max_iter, void* ws, size_t ws_bytes,
                               void* stream, qtt_solve_col_t* info);
 
+/* Compressed matrix-vector product (section 4.2): for vectors b given in
+ * TT form, the cores of c = A b,
+ *   c_k(alpha + rA_{k-1} beta, i, alpha' + rA_k beta')
+ *       = sum_j G_k(alpha, i, j, alpha') b_k(beta, j, beta'),
+ * for nvec vectors that share the TT ranks rb.  The ranks of c are
+ * rA_k rb_k; nothing is rounded.
+ *   rb   host, d + 1 ranks, rb[0] = rb[d] = 1.
+ *   B    d device pointers; B[k] holds nvec FP64 cores of rb[k] x n_k x
+ *        rb[k+1] values each, vector v's at B[k] + v rb[k] n_k rb[k+1], C
+ *        row-major [beta][j][beta'].
+ *   C    d device pointers; C[k] receives nvec cores of (rA_k rb[k]) x m_k x
+ *        (rA_{k+1} rb[k+1]) values, row-major [beta][alpha][i][beta'][alpha']
+ *        (the merged index alpha + rA beta, matrix rank fastest).
+ * Needs A's FP64 copy (QTT_ERR_DTYPE otherwise) and no diagonals
+ * (QTT_ERR_INVALID_ARG).  Output cores must not overlap each other or the
+ * input cores.  Asynchronous on the stream; allocates nothing. */
+qtt_status_t qtt_matvec_compressed(qtt_matrix_t A, int64_t nvec, const int64_t* rb,
+                                   const double* const* B, double* const* C, void* stream);
+
 const char* qtt_status_string(qtt_status_t s);
 const char* qtt_last_error(void);
 

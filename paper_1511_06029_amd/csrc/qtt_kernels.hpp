@@ -2932,4 +2932,105 @@ __global__ void __launch_bounds__(256) diag_out_kernel(const DiagArgs args) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Compressed matrix-vector product (section 4.2): for b in TT form the cores
+// of c = A b are
+//   c_k[beta][alpha][i][beta'][alpha'] = sum_j G_k[alpha][i][j][alpha'] b_k[beta][j][beta']
+// (merged rank index alpha + rA beta).  An output row (v, beta, alpha, i)
+// holds R = rA_k rb_k contiguous values; its indices are decoded once per
+// row, and the threads run along the row (matrix rank fastest), so the core
+// reads of neighbouring lanes are contiguous, the vector-core reads are
+// shared and the store is coalesced.  Rows shorter than the block share it.
+// The work is n multiply-adds per 8-byte store: HBM-bound on the output.
+// ---------------------------------------------------------------------------
+
+struct CmvArgs {
+  const double* G;       // [ra0][m][n][ra1]
+  const double* B;       // nvec cores [rb0][n][rb1]
+  double* C;             // nvec cores [rb0][ra0][m][rb1][ra1]
+  int64_t nvec;
+  int32_t ra0, ra1, rb0, rb1, m, n;
+};
+
+__global__ void __launch_bounds__(256) compressed_matvec_kernel(const CmvArgs args) {
+  (void)args;
+  const CmvArgs& a = kernarg<CmvArgs>();
+  const int R = a.ra1 * a.rb1;
+  const int rpb = (R >= 256) ? 1 : 256 / R;                 // rows per block pass
+  const int rl = (R >= 256) ? 0 : (int)threadIdx.x / R;      // this thread's row in the pass
+  const int q0 = (R >= 256) ? (int)threadIdx.x : (int)threadIdx.x % R;
+  const int qs = (R >= 256) ? 256 : R;
+  const int64_t rows = a.nvec * a.rb0 * a.ra0 * a.m;
+  const int64_t bsz = (int64_t)a.rb0 * a.n * a.rb1;
+  if (rl >= rpb) return;
+  for (int64_t row0 = (int64_t)blockIdx.x * rpb; row0 < rows; row0 += (int64_t)gridDim.x * rpb) {
+    const int64_t row = row0 + rl;
+    if (row >= rows) continue;
+    int64_t t = row;
+    const int i = (int)(t % a.m); t /= a.m;
+    const int al = (int)(t % a.ra0); t /= a.ra0;
+    const int be = (int)(t % a.rb0); t /= a.rb0;
+    const double* g = a.G + ((int64_t)al * a.m + i) * a.n * a.ra1;
+    const double* b = a.B + t * bsz + (int64_t)be * a.n * a.rb1;
+    double* out = a.C + row * R;
+    for (int q = q0; q < R; q += qs) {
+      const int ap = q % a.ra1, bp = q / a.ra1;
+      double s = 0.0;
+      for (int j = 0; j < a.n; ++j) s = fma(g[j * a.ra1 + ap], b[j * a.rb1 + bp], s);
+      out[q] = s;
+    }
+  }
+}
+
+// The same product when n <= kCmvMaxN, n rb1 <= kCmvLds and ra1 <= 256 (the
+// octree operators): a block takes one vector-core slice b[v][beta] into LDS
+// and kCmvRows output rows (alpha, i) of it; a thread keeps the n core
+// values G[alpha][i][.][alpha'] in registers and produces the rb1 outputs of
+// its alpha' (one global load per output instead of 2n).  Same summation
+// order as compressed_matvec_kernel, so the results are identical.
+constexpr int kCmvMaxN = 16;
+constexpr int kCmvLds = 4096;
+constexpr int kCmvRows = 64;
+
+__global__ void __launch_bounds__(256) compressed_matvec_lds_kernel(const CmvArgs args) {
+  (void)args;
+  const CmvArgs& a = kernarg<CmvArgs>();
+  __shared__ double bs[kCmvLds];
+  const int n = a.n, ra1 = a.ra1, rb1 = a.rb1;
+  const int nrow = a.ra0 * a.m;
+  const int nchunk = (nrow + kCmvRows - 1) / kCmvRows;
+  const int64_t nblk = a.nvec * a.rb0 * nchunk;
+  const int64_t R = (int64_t)ra1 * rb1;
+  const int64_t bsz = (int64_t)a.rb0 * n * rb1;
+  const int rpp = 256 / ra1;                       // rows in flight per pass
+  const int rl = (int)threadIdx.x / ra1, ap = (int)threadIdx.x % ra1;
+  for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+    const int64_t vb = blk / nchunk;               // v * rb0 + beta
+    const int chunk = (int)(blk - vb * nchunk);
+    const int64_t v = vb / a.rb0;
+    const int be = (int)(vb - v * a.rb0);
+    __syncthreads();                               // the previous slice is no longer read
+    const double* b = a.B + v * bsz + (int64_t)be * n * rb1;
+    for (int e = threadIdx.x; e < n * rb1; e += 256) bs[e] = b[e];
+    __syncthreads();
+    if (rl < rpp) {
+      const int r1 = min(nrow, (chunk + 1) * kCmvRows);
+      for (int r = chunk * kCmvRows + rl; r < r1; r += rpp) {
+        const double* g = a.G + (int64_t)r * n * ra1 + ap;   // r = alpha m + i
+        double gr[kCmvMaxN];
+#pragma unroll
+        for (int j = 0; j < kCmvMaxN; ++j) gr[j] = (j < n) ? g[j * ra1] : 0.0;
+        double* out = a.C + (vb * nrow + r) * R + ap;
+        for (int bp = 0; bp < rb1; ++bp) {
+          double s = 0.0;
+#pragma unroll
+          for (int j = 0; j < kCmvMaxN; ++j)
+            if (j < n) s = fma(gr[j], bs[j * rb1 + bp], s);
+          out[(int64_t)bp * ra1] = s;
+        }
+      }
+    }
+  }
+}
+
 }  // namespace qtt

@@ -485,6 +485,7 @@ struct CoreDev {
   int Rpad;           // rows of Mv
   int RpadT;          // rows of Mt
   int tuned_t;        // shape id in the rank-slowest sweep, -1 = heuristic
+  double* g64 = nullptr;  // FP64 core as given, [r_in][m][n][r_out] (compressed products)
 };
 
 struct qtt_matrix_s {
@@ -1237,6 +1238,7 @@ qtt_status_t qtt_matrix_load(int32_t d, const int64_t* ranks, const int64_t* m, 
     c.valu = nullptr;
     c.valu1 = nullptr;
     c.valut = nullptr;
+    c.g64 = nullptr;
     c.Rpad = 0;
     c.RpadT = 0;
     c.tuned_t = -1;
@@ -1332,6 +1334,24 @@ qtt_status_t qtt_matrix_load(int32_t d, const int64_t* ranks, const int64_t* m, 
       }
     }
   }
+  // FP64 cores as given (the compressed matrix-vector product reads them)
+  if (dtypes & QTT_FP64) {
+    for (int k = 0; k < d; ++k) {
+      CoreDev& c = A->core[k];
+      const size_t nel = (size_t)c.r_in * c.m * c.n * c.r_out;
+      void* dptr = nullptr;
+      if (hipMalloc(&dptr, std::max<size_t>(nel * 8, 256)) != hipSuccess) {
+        qtt_matrix_free(A);
+        return fail(QTT_ERR_OUT_OF_MEMORY, "hipMalloc for the FP64 copy of core %d failed", k);
+      }
+      c.g64 = static_cast<double*>(dptr);
+      hipError_t er = hipMemcpy(dptr, cores[k], nel * 8, hipMemcpyHostToDevice);
+      if (er != hipSuccess) {
+        qtt_matrix_free(A);
+        return fail(QTT_ERR_DEVICE, "hipMemcpy of core %d failed: %s", k, hipGetErrorString(er));
+      }
+    }
+  }
   // FP64 copy for the rank-slowest sweep: Mt[(a * RpadT + row) * 8 + j] = M_k(row, a + r_{k-1} j)
   if (dtypes & QTT_FP64) {
     bool ok = true;
@@ -1378,6 +1398,7 @@ qtt_status_t qtt_matrix_free(qtt_matrix_t A) {
     if (c.valu) (void)hipFree(c.valu);
     if (c.valu1) (void)hipFree(c.valu1);
     if (c.valut) (void)hipFree(c.valut);
+    if (c.g64) (void)hipFree(c.g64);
   }
   delete A;
   return QTT_OK;
@@ -2196,6 +2217,69 @@ qtt_status_t qtt_solve_fgmres(qtt_matrix_t A, qtt_matrix_t Ainv, qtt_dtype_t inv
   for (int64_t c = 0; c < nrhs; ++c) above += (relv[c] > rtol);
   HIP_TRY(hipStreamSynchronize(st));
   if (above > 0) return fail(QTT_ERR_NOT_CONVERGED, "%lld columns above rtol after %d steps", (long long)above, M);
+  return QTT_OK;
+}
+
+// --------------------------------------------------------------------------- compressed product
+
+qtt_status_t qtt_matvec_compressed(qtt_matrix_t A, int64_t nvec, const int64_t* rb, const double* const* B,
+                                   double* const* C, void* stream) {
+  if (!valid_handle(A)) return fail(QTT_ERR_INVALID_ARG, "null handle");
+  int dt;
+  qtt_status_t s = check_dtype(A, QTT_FP64, &dt);
+  if (s != QTT_OK) return s;
+  if (A->has_diag) return fail(QTT_ERR_INVALID_ARG, "an operator with diagonals has no compressed product here");
+  if (nvec < 0) return fail(QTT_ERR_INVALID_ARG, "nvec < 0");
+  if (nvec == 0) return QTT_OK;
+  if (!rb || !B || !C) return fail(QTT_ERR_INVALID_ARG, "null rank or core array");
+  const int d = A->d;
+  if (rb[0] != 1 || rb[d] != 1) return fail(QTT_ERR_SHAPE, "vector ranks must start and end with 1");
+  std::vector<std::pair<const void*, size_t>> ins, outs;
+  for (int k = 0; k < d; ++k) {
+    if (rb[k + 1] < 1 || rb[k + 1] * A->core[k].r_out > (1 << 24))
+      return fail(QTT_ERR_SHAPE, "vector rank %d out of range", k + 1);
+    if (!B[k] || !C[k]) return fail(QTT_ERR_INVALID_ARG, "core %d pointer is null", k);
+    const CoreDev& c = A->core[k];
+    const size_t ib = (size_t)nvec * rb[k] * c.n * rb[k + 1] * 8;
+    const size_t ob = (size_t)nvec * rb[k] * c.r_in * c.m * rb[k + 1] * c.r_out * 8;
+    ins.push_back({B[k], ib});
+    outs.push_back({C[k], ob});
+  }
+  for (size_t i = 0; i < outs.size(); ++i) {
+    for (auto& x : ins)
+      if (overlaps(outs[i].first, outs[i].second, x.first, x.second)) return fail(QTT_ERR_INVALID_ARG, "output core %zu overlaps an input core", i);
+    for (size_t j = 0; j < i; ++j)
+      if (overlaps(outs[i].first, outs[i].second, outs[j].first, outs[j].second)) return fail(QTT_ERR_INVALID_ARG, "output cores %zu and %zu overlap", j, i);
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  for (int k = 0; k < d; ++k) {
+    const CoreDev& c = A->core[k];
+    CmvArgs ca;
+    ca.G = c.g64;
+    ca.B = B[k];
+    ca.C = C[k];
+    ca.nvec = nvec;
+    ca.ra0 = c.r_in;
+    ca.ra1 = c.r_out;
+    ca.rb0 = (int32_t)rb[k];
+    ca.rb1 = (int32_t)rb[k + 1];
+    ca.m = c.m;
+    ca.n = c.n;
+    void* args[] = {&ca};
+    if (c.n <= kCmvMaxN && c.n * rb[k + 1] <= kCmvLds && c.r_out <= 256) {
+      const int64_t nchunk = ((int64_t)c.r_in * c.m + kCmvRows - 1) / kCmvRows;
+      const int64_t blocks = std::min<int64_t>(1 << 18, std::max<int64_t>(1, nvec * rb[k] * nchunk));
+      HIP_TRY(hipLaunchKernel(reinterpret_cast<const void*>(&compressed_matvec_lds_kernel),
+                              dim3((unsigned)blocks), dim3(256), args, 0, st));
+      continue;
+    }
+    const int64_t rows = (int64_t)nvec * rb[k] * c.r_in * c.m;
+    const int64_t R = rb[k + 1] * c.r_out;
+    const int64_t rpb = (R >= 256) ? 1 : 256 / R;
+    const int64_t blocks = std::min<int64_t>(1 << 18, std::max<int64_t>(1, (rows + rpb - 1) / rpb));
+    HIP_TRY(hipLaunchKernel(reinterpret_cast<const void*>(&compressed_matvec_kernel), dim3((unsigned)blocks),
+                            dim3(256), args, 0, st));
+  }
   return QTT_OK;
 }
 

@@ -56,6 +56,7 @@ def _load():
         "qtt_matrix_load": [I32, PI64, PI64, PI64, PP, U32, PP],
         "qtt_matrix_free": [P],
         "qtt_matrix_set_diagonals": [P, D, P, P],
+        "qtt_matvec_compressed": [P, I64, PI64, PP, PP, P],
         "qtt_matrix_info": [P, ctypes.POINTER(I32), PI64, PI64, PI64, ctypes.POINTER(U32)],
         "qtt_workspace_bytes": [P, I32, I64, ctypes.POINTER(SZ)],
         "qtt_apply": [P, I32, I64, P, I64, P, I64, P, SZ, P],
@@ -87,7 +88,7 @@ _lib = _load()
 # Names the C ABI exports (include/qtt.h); the tests check each is present.
 EXPORTED = ["qtt_matrix_load", "qtt_matrix_free", "qtt_matrix_set_diagonals", "qtt_matrix_info", "qtt_workspace_bytes",
             "qtt_apply", "qtt_apply_batched", "qtt_autotune", "qtt_solve_workspace_bytes",
-            "qtt_solve", "qtt_fgmres_workspace_bytes", "qtt_solve_fgmres", "qtt_status_string", "qtt_last_error", "qtt_set_shape", "qtt_list_shapes",
+            "qtt_matvec_compressed", "qtt_solve", "qtt_fgmres_workspace_bytes", "qtt_solve_fgmres", "qtt_status_string", "qtt_last_error", "qtt_set_shape", "qtt_list_shapes",
             "qtt_timing_enable",
             "qtt_timing_reset", "qtt_timing_read", "qtt_timing_read_shape"]
 
@@ -320,6 +321,28 @@ def qtt_solve_fgmres(A, Ainv, inv_compute, F, Sigma=None, rtol=1e-8, max_iter=30
     else:
         _check(st, allow=(QTT_ERR_NOT_CONVERGED, QTT_ERR_NONFINITE))
     return Sigma, [(c.iters, c.rel_residual) for c in info], st
+
+
+def qtt_matvec_compressed(A, Bcores, Ccores=None, stream=None):
+    """Cores of c = A b for a batch of TT vectors (section 4.2).  Bcores[k]:
+    contiguous FP64 CUDA tensor (nvec, rb_k, n_k, rb_{k+1}).  Returns the list
+    of (nvec, rA_k rb_k, m_k, rA_{k+1} rb_{k+1}) tensors (the merged index is
+    alpha + rA beta)."""
+    d = len(Bcores)
+    nvec = Bcores[0].shape[0]
+    rb = [1] + [int(B.shape[3]) for B in Bcores]
+    for k, B in enumerate(Bcores):
+        if (not B.is_cuda or B.dtype != torch.float64 or not B.is_contiguous() or B.dim() != 4
+                or B.shape[0] != nvec or B.shape[1] != rb[k] or B.shape[2] != A.n[k]):
+            raise ValueError(f"vector core {k} must be a contiguous FP64 CUDA tensor (nvec, rb_k, n_k, rb_k+1)")
+    if Ccores is None:
+        Ccores = [torch.empty((nvec, A.ranks[k] * rb[k], A.m[k], A.ranks[k + 1] * rb[k + 1]),
+                              dtype=torch.float64, device=Bcores[0].device) for k in range(d)]
+    rbh = (ctypes.c_int64 * (d + 1))(*rb)
+    bp = (ctypes.c_void_p * d)(*[B.data_ptr() for B in Bcores])
+    cp = (ctypes.c_void_p * d)(*[C.data_ptr() for C in Ccores])
+    _check(_lib.qtt_matvec_compressed(A.handle, int(nvec), rbh, bp, cp, _stream(stream)))
+    return Ccores
 
 
 def qtt_set_shape(A, compute, core, shape):

@@ -414,3 +414,29 @@ def test_fused_pairs_any_rank(Q, dtype, base):
     assert np.all(np.linalg.norm(res, axis=0) <= 1e-8 * np.linalg.norm(F, axis=0) * 1.0001)
     A.free()
     Ai.free()
+
+
+@pytest.mark.slow
+def test_apply_and_solve_L8_maximum_size(Q):
+    """The largest operator of the serving trace: L=8 (N=16,777,216), ranks
+    [1,24,32,32,32,32,32,24,1] (three fused pairs, a single interior core,
+    the last core).  FP64 apply of two vectors against the oracle (first
+    column, normwise and elementwise), and a refined solve with the BF16
+    inverse whose residual the oracle recomputes (second column)."""
+    ranks = [1, 24, 32, 32, 32, 32, 32, 24, 1]
+    Ac, Aic = I.perturbed_identity_pair(ranks, [8] * 8, seed=51, eps=0.1)
+    X = I.rhs(8 ** 8, 2, seed=52)
+    A = Q.qtt_matrix_load(Ac, dtypes=("fp64",))
+    Ai = Q.qtt_matrix_load(Aic, dtypes=("bf16",))
+    Xd = Q.to_block(X)
+    Y = Q.qtt_apply(A, "fp64", Xd).cpu().numpy()
+    ref = O.qtt_apply_alg2(Ac, X[:, :1])
+    assert colrel(Y[:, :1], ref) <= 1e-12 and elementwise_ok(Y[:, :1], ref, 1e-12)
+    del Y, ref
+    Sig, info, st = Q.qtt_solve(A, Ai, "bf16", Xd, rtol=1e-8)
+    s1 = Sig[:, 1].cpu().numpy()
+    r = X[:, 1] - O.qtt_apply_alg2(Ac, s1[:, None])[:, 0]
+    assert np.linalg.norm(r) <= 1e-8 * np.linalg.norm(X[:, 1]) * 1.0001
+    assert info[1][1] == pytest.approx(np.linalg.norm(r) / np.linalg.norm(X[:, 1]), rel=1e-3)
+    A.free()
+    Ai.free()
