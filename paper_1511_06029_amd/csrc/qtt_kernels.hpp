@@ -51,6 +51,11 @@ __device__ __host__ inline uint16_t f32_to_bf16_rne(float f) {
   return (uint16_t)(u >> 16);
 }
 
+// The same rounding in device code on the hardware converter
+// (v_cvt_pk_bf16_f32): identical bits to f32_to_bf16_rne for every finite
+// value and infinity; a NaN stays a quiet NaN (its payload may differ).
+__device__ inline uint16_t bf16_rne_dev(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
+
 template <class Tc> struct Mfma;
 
 template <> struct Mfma<double> {
@@ -99,8 +104,8 @@ template <> struct Mfma<bf16_tag> {
     return __builtin_bit_cast(v8bf, *reinterpret_cast<const v4u*>(p));
   }
   __device__ static frag zero_frag() { return __builtin_bit_cast(v8bf, v4u{0u, 0u, 0u, 0u}); }
-  __device__ static elem from_double(double x) { return f32_to_bf16_rne((float)x); }
-  __device__ static elem from_acc(accel x) { return f32_to_bf16_rne(x); }
+  __device__ static elem from_double(double x) { return bf16_rne_dev((float)x); }
+  __device__ static elem from_acc(accel x) { return bf16_rne_dev(x); }
 };
 
 // A contiguous run of vectors with its own pointers: used by the first core
@@ -2514,8 +2519,8 @@ template <> struct SmallK<bf16_tag> {
   static constexpr int KS = 32, E = 8, TQ = 32;
   __device__ static float from_bits(uint16_t b) { return __builtin_bit_cast(float, (uint32_t)b << 16); }
   __device__ static acc load_core(const void* M, int64_t i) { return from_bits(reinterpret_cast<const uint16_t*>(M)[i]); }
-  __device__ static acc round_in(double x) { return from_bits(f32_to_bf16_rne((float)x)); }
-  __device__ static out to_out(acc v) { return f32_to_bf16_rne(v); }
+  __device__ static acc round_in(double x) { return from_bits(bf16_rne_dev((float)x)); }
+  __device__ static out to_out(acc v) { return bf16_rne_dev(v); }
 };
 
 template <class Tc>
