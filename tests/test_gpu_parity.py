@@ -440,3 +440,37 @@ def test_apply_and_solve_L8_maximum_size(Q):
     assert info[1][1] == pytest.approx(np.linalg.norm(r) / np.linalg.norm(X[:, 1]), rel=1e-3)
     A.free()
     Ai.free()
+
+
+def _bf16_rne(x):
+    """Round-to-nearest-even of float32(x) to BF16, by integer arithmetic on
+    the float32 bits (ties to even), returned as FP64."""
+    u = np.asarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def test_bf16_rounding_bitwise_through_identity(Q):
+    """A BF16 identity operator rounds its input once (to BF16, nearest even)
+    and carries it exactly, so its output equals that rounding bit for bit:
+    exact ties with even and odd upper bits, values just below and above a
+    tie, the largest finite BF16 range, and random values.  (Infinities are
+    left out: the identity core's zeros would turn them into NaN; so are
+    subnormals, which the matrix cores may flush.)"""
+    g = I.rng(961)
+    hi = (g.integers(0x0080, 0x7F7F, 4096).astype(np.uint32) | (g.integers(0, 2, 4096).astype(np.uint32) << 15)) << 16
+    ties = (hi | 0x8000).view(np.float32)
+    near = (hi | 0x7FFF).view(np.float32)
+    above = (hi | 0x8001).view(np.float32)
+    edge = np.array([3.38e38, -3.38e38, 1.0, -1.0, 0.0], dtype=np.float32)
+    rnd = g.standard_normal(4096).astype(np.float32)
+    vals = np.concatenate([ties, near, above, edge, rnd])
+    N = 512
+    n_col = len(vals) // N
+    X = vals[: N * n_col].astype(np.float64).reshape(N, n_col, order="F")
+    A = Q.qtt_matrix_load(I.identity_qtt([8] * 3), dtypes=("bf16",))
+    Y = Q.qtt_apply(A, "bf16", Q.to_block(X)).cpu().numpy()
+    E = _bf16_rne(X)
+    assert np.all(np.isfinite(E))
+    assert np.array_equal(Y, E)
+    A.free()
