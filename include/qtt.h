@@ -255,6 +255,18 @@ qtt_status_t qtt_solve_fgmres(qtt_matrix_t A, qtt_matrix_t Ainv, qtt_dtype_t inv
 qtt_status_t qtt_matvec_compressed(qtt_matrix_t A, int64_t nvec, const int64_t* rb,
                                    const double* const* B, double* const* C, void* stream);
 
+/* qtt_solve_fgmres with §5.2's product-form preconditioner: the compressed
+ * inverse is the product of two QTT matrices, Ainv = M Y (the inversion
+ * solves A M Y = I for Y with an easily inverted M), applied as two chained
+ * sweeps, z_j = M (Y v_j), both in inv_compute.  Y v_j is staged in the slot
+ * of v_{j+1}, so no memory is added: the workspace is the larger of
+ * qtt_fgmres_workspace_bytes for M and for Y.  M and Y must both be given
+ * (QTT_ERR_INVALID_ARG otherwise); everything else as qtt_solve_fgmres. */
+qtt_status_t qtt_solve_fgmres_product(qtt_matrix_t A, qtt_matrix_t M, qtt_matrix_t Y, qtt_dtype_t inv_compute,
+                                      int64_t nrhs, const double* F, int64_t ldf, double* Sigma, int64_t lds,
+                                      double rtol, int32_t max_iter, void* ws, size_t ws_bytes,
+                                      void* stream, qtt_solve_col_t* info);
+
 const char* qtt_status_string(qtt_status_t s);
 const char* qtt_last_error(void);
 

@@ -1981,22 +1981,28 @@ qtt_status_t combine(const KryChunk& ch, double* out, int64_t ldo, const double*
 
 extern "C" {
 
-qtt_status_t qtt_solve_fgmres(qtt_matrix_t A, qtt_matrix_t Ainv, qtt_dtype_t inv_compute, int64_t nrhs,
-                              const double* F, int64_t ldf, double* Sigma, int64_t lds, double rtol,
-                              int32_t max_iter, void* ws, size_t ws_bytes, void* stream,
-                              qtt_solve_col_t* info) {
-  if (!valid_handle(A) || (Ainv && !valid_handle(Ainv))) return fail(QTT_ERR_INVALID_ARG, "null handle");
+// Flexible GMRES with the preconditioner z = Ainv (Y v) (Y may be NULL: z =
+// Ainv v; Ainv NULL: z = v).
+static qtt_status_t fgmres_impl(qtt_matrix_t A, qtt_matrix_t Ainv, qtt_matrix_t Y, qtt_dtype_t inv_compute,
+                                int64_t nrhs, const double* F, int64_t ldf, double* Sigma, int64_t lds,
+                                double rtol, int32_t max_iter, void* ws, size_t ws_bytes, void* stream,
+                                qtt_solve_col_t* info) {
+  if (!valid_handle(A) || (Ainv && !valid_handle(Ainv)) || (Y && !valid_handle(Y)))
+    return fail(QTT_ERR_INVALID_ARG, "null handle");
   int dti = -1, dta;
   qtt_status_t s = check_dtype(A, QTT_FP64, &dta);
   if (s != QTT_OK) return s;
-  if (Ainv) {
-    s = check_dtype(Ainv, inv_compute, &dti);
+  for (qtt_matrix_t P : {Ainv, Y}) {
+    if (!P) continue;
+    s = check_dtype(P, inv_compute, &dti);
     if (s != QTT_OK) return s;
-    if (A->d != Ainv->d) return fail(QTT_ERR_SHAPE, "A and Ainv have different core counts");
+    if (A->d != P->d) return fail(QTT_ERR_SHAPE, "A and the preconditioner have different core counts");
+    for (int k = 0; k < A->d; ++k)
+      if (P->m[k] != A->m[k] || P->n[k] != A->n[k])
+        return fail(QTT_ERR_SHAPE, "solve needs square, identical modes (core %d)", k);
   }
   for (int k = 0; k < A->d; ++k)
-    if (A->m[k] != A->n[k] || (Ainv && (Ainv->m[k] != A->m[k] || Ainv->n[k] != A->n[k])))
-      return fail(QTT_ERR_SHAPE, "solve needs square, identical modes (core %d)", k);
+    if (A->m[k] != A->n[k]) return fail(QTT_ERR_SHAPE, "solve needs square, identical modes (core %d)", k);
   if (nrhs < 0 || max_iter < 1 || !(rtol >= 0)) return fail(QTT_ERR_INVALID_ARG, "bad nrhs, max_iter or rtol");
   if (nrhs == 0) return QTT_OK;
   if (!F || !Sigma || !ws) return fail(QTT_ERR_INVALID_ARG, "null F, Sigma or workspace");
@@ -2008,8 +2014,9 @@ qtt_status_t qtt_solve_fgmres(qtt_matrix_t A, qtt_matrix_t Ainv, qtt_dtype_t inv
   const size_t extra = fgmres_extra_bytes(A, pre, nrhs, max_iter);
   size_t need1 = 0, tmp = 0;
   qtt_workspace_bytes(A, QTT_FP64, 1, &need1);
-  if (pre) {
-    qtt_workspace_bytes(Ainv, inv_compute, 1, &tmp);
+  for (qtt_matrix_t P : {Ainv, Y}) {
+    if (!P) continue;
+    qtt_workspace_bytes(P, inv_compute, 1, &tmp);
     need1 = std::max(need1, tmp);
   }
   if (ws_bytes < extra + need1)
@@ -2125,10 +2132,17 @@ qtt_status_t qtt_solve_fgmres(qtt_matrix_t A, qtt_matrix_t Ainv, qtt_dtype_t inv
     double* Vj = V + j * bstride;
     double* Zj = Z + j * bstride;
     double* W = V + (j + 1) * bstride;
-    std::vector<Block> bi, ba;
+    std::vector<Block> bi, ba, by;
     for (auto& r : runs) {
-      bi.push_back({Vj + r.first * N, Zj + r.first * N, nullptr, N, N, 0, r.second});
+      // with a product preconditioner, Y v_j goes to the w slot first (A z_j
+      // overwrites it afterwards)
+      by.push_back({Vj + r.first * N, W + r.first * N, nullptr, N, N, 0, r.second});
+      bi.push_back({(Y ? W : Vj) + r.first * N, Zj + r.first * N, nullptr, N, N, 0, r.second});
       ba.push_back({Zj + r.first * N, W + r.first * N, nullptr, N, N, 0, r.second});
+    }
+    if (Y) {
+      s = run_blocks(Y, dti, by, aws, aws_bytes, 1.0, st);
+      if (s != QTT_OK) return s;
     }
     if (pre) {
       s = run_blocks(Ainv, dti, bi, aws, aws_bytes, 1.0, st);
@@ -2218,6 +2232,23 @@ qtt_status_t qtt_solve_fgmres(qtt_matrix_t A, qtt_matrix_t Ainv, qtt_dtype_t inv
   HIP_TRY(hipStreamSynchronize(st));
   if (above > 0) return fail(QTT_ERR_NOT_CONVERGED, "%lld columns above rtol after %d steps", (long long)above, M);
   return QTT_OK;
+}
+
+qtt_status_t qtt_solve_fgmres(qtt_matrix_t A, qtt_matrix_t Ainv, qtt_dtype_t inv_compute, int64_t nrhs,
+                              const double* F, int64_t ldf, double* Sigma, int64_t lds, double rtol,
+                              int32_t max_iter, void* ws, size_t ws_bytes, void* stream,
+                              qtt_solve_col_t* info) {
+  return fgmres_impl(A, Ainv, nullptr, inv_compute, nrhs, F, ldf, Sigma, lds, rtol, max_iter, ws, ws_bytes,
+                     stream, info);
+}
+
+qtt_status_t qtt_solve_fgmres_product(qtt_matrix_t A, qtt_matrix_t M, qtt_matrix_t Y, qtt_dtype_t inv_compute,
+                                      int64_t nrhs, const double* F, int64_t ldf, double* Sigma, int64_t lds,
+                                      double rtol, int32_t max_iter, void* ws, size_t ws_bytes, void* stream,
+                                      qtt_solve_col_t* info) {
+  if (!M || !Y) return fail(QTT_ERR_INVALID_ARG, "the product preconditioner needs both M and Y");
+  return fgmres_impl(A, M, Y, inv_compute, nrhs, F, ldf, Sigma, lds, rtol, max_iter, ws, ws_bytes, stream,
+                     info);
 }
 
 // --------------------------------------------------------------------------- compressed product

@@ -66,6 +66,8 @@ def _load():
         "qtt_solve": [P, P, I32, I64, P, I64, P, I64, D, I32, P, SZ, P, ctypes.POINTER(_SolveCol)],
         "qtt_fgmres_workspace_bytes": [P, P, I32, I64, I32, ctypes.POINTER(SZ)],
         "qtt_solve_fgmres": [P, P, I32, I64, P, I64, P, I64, D, I32, P, SZ, P, ctypes.POINTER(_SolveCol)],
+        "qtt_solve_fgmres_product": [P, P, P, I32, I64, P, I64, P, I64, D, I32, P, SZ, P,
+                                     ctypes.POINTER(_SolveCol)],
         "qtt_set_shape": [P, I32, I32, I32],
         "qtt_list_shapes": [I32, ctypes.POINTER(I32), I32, ctypes.POINTER(I32)],
         "qtt_timing_enable": [I32],
@@ -88,7 +90,7 @@ _lib = _load()
 # Names the C ABI exports (include/qtt.h); the tests check each is present.
 EXPORTED = ["qtt_matrix_load", "qtt_matrix_free", "qtt_matrix_set_diagonals", "qtt_matrix_info", "qtt_workspace_bytes",
             "qtt_apply", "qtt_apply_batched", "qtt_autotune", "qtt_solve_workspace_bytes",
-            "qtt_matvec_compressed", "qtt_solve", "qtt_fgmres_workspace_bytes", "qtt_solve_fgmres", "qtt_status_string", "qtt_last_error", "qtt_set_shape", "qtt_list_shapes",
+            "qtt_matvec_compressed", "qtt_solve", "qtt_fgmres_workspace_bytes", "qtt_solve_fgmres", "qtt_solve_fgmres_product", "qtt_status_string", "qtt_last_error", "qtt_set_shape", "qtt_list_shapes",
             "qtt_timing_enable",
             "qtt_timing_reset", "qtt_timing_read", "qtt_timing_read_shape"]
 
@@ -343,6 +345,28 @@ def qtt_matvec_compressed(A, Bcores, Ccores=None, stream=None):
     cp = (ctypes.c_void_p * d)(*[C.data_ptr() for C in Ccores])
     _check(_lib.qtt_matvec_compressed(A.handle, int(nvec), rbh, bp, cp, _stream(stream)))
     return Ccores
+
+
+def qtt_solve_fgmres_product(A, M, Y, inv_compute, F, Sigma=None, rtol=1e-8, max_iter=30, ws=None,
+                             stream=None, raise_on_fail=True):
+    """Flexible GMRES with the product preconditioner z = M (Y v); returns
+    (Sigma, info, status)."""
+    fp, n, k, ldf = _col_major(F, "F")
+    if Sigma is None:
+        Sigma = empty_block(n, k, F.device) if F.dim() == 2 else torch.empty(n, dtype=torch.float64, device=F.device)
+    sp, _, _, lds = _col_major(Sigma, "Sigma")
+    if ws is None:
+        ws = workspace(max(qtt_fgmres_workspace_bytes(A, M, inv_compute, k, max_iter),
+                           qtt_fgmres_workspace_bytes(A, Y, inv_compute, k, max_iter)), F.device)
+    info = (_SolveCol * k)()
+    st = _lib.qtt_solve_fgmres_product(A.handle, M.handle, Y.handle, _dtype(inv_compute), k, fp, ldf, sp, lds,
+                                       float(rtol), int(max_iter), ws.data_ptr(),
+                                       ws.numel() * ws.element_size(), _stream(stream), info)
+    if raise_on_fail:
+        _check(st)
+    else:
+        _check(st, allow=(QTT_ERR_NOT_CONVERGED, QTT_ERR_NONFINITE))
+    return Sigma, [(c.iters, c.rel_residual) for c in info], st
 
 
 def qtt_set_shape(A, compute, core, shape):

@@ -189,3 +189,35 @@ def test_fgmres_L7_full_size(Q):
     assert max(c[0] for c in info) <= max(c[0] for c in rinfo)
     A.free()
     Ai.free()
+
+
+@pytest.mark.parametrize("inv", ["fp64", "bf16"])
+def test_fgmres_product_preconditioner(Q, inv):
+    """Section 5.2's product form Ainv = M Y, applied as two chained QTT
+    sweeps: M is the diagonal-free first-order inverse, Y a second
+    perturbed-identity factor (ranks 4).  FP64: the oracle's FGMRES with the
+    preconditioner v -> M (Y v) takes the same steps and finds the same
+    solution; BF16: the oracle's residual reaches 1e-8."""
+    Ac, Mc = I.perturbed_identity_pair([1, 6, 8, 6, 1], [8] * 4, seed=81)
+    Yc, _ = I.perturbed_identity_pair([1, 4, 4, 4, 1], [8] * 4, seed=951, eps=0.05)
+    F = I.rhs(4096, 3, seed=952)
+    apA = lambda v: O.qtt_apply_alg2(Ac, v[:, None])[:, 0]
+    apP = lambda v: O.qtt_apply_alg2(Mc, O.qtt_apply_alg2(Yc, v[:, None]))[:, 0]
+    Xo, ho, ito = O.fgmres_solve(apA, apP, F, rtol=1e-8, max_iter=30)
+    A = Q.qtt_matrix_load(Ac, dtypes=("fp64",))
+    M = Q.qtt_matrix_load(Mc, dtypes=(inv,))
+    Y = Q.qtt_matrix_load(Yc, dtypes=(inv,))
+    Sig, info, st = Q.qtt_solve_fgmres_product(A, M, Y, inv, Q.to_block(F), rtol=1e-8, max_iter=30)
+    S = Sig.cpu().numpy()
+    assert max(true_rel(Ac, F, S)) <= 1e-8 * 1.0001
+    if inv == "fp64":
+        assert [c[0] for c in info] == ito
+        assert colrel(S, Xo) <= 1e-10
+    else:
+        assert max(c[0] for c in info) <= max(ito) + 2
+    # both factors are required
+    st = Q.lib().qtt_solve_fgmres_product(A.handle, M.handle, None, Q.DTYPES[inv], 3, None, 4096, None,
+                                          4096, 1e-8, 30, None, 0, None, None)
+    assert st == 1
+    for h in (A, M, Y):
+        h.free()
