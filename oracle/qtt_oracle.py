@@ -16,14 +16,26 @@ equations in complex geometries", arXiv:1511.06029):
   with dummy ranks r_0 = r_d = 1.
 * QTT matrix over the product tree -- section 3 (tensorized matrix
   A_T(b_1..b_d) with b_k = (i_k, j_k)); a core is G_k(a_{k-1}, i_k, j_k, a_k).
-* matrix by full vector -- section 4.2, Algorithm 2 (alg:TT-matvec).
+* matrix by full vector -- the product Algorithm 2 (section 4.2,
+  alg:TT-matvec) computes, contracted here core by core from the TT formula.
 * matrix by compressed vector -- section 4.2 (QTT compressed matrix-vector
   product): the cores of c = A b are the contractions over j_k of A's and
   b's cores, with the rank pairs merged (ranks multiply).
-* TT-SVD -- section 2.2, Algorithm 1 (alg:TT-dec).
+* TT-SVD -- section 2.3, Algorithm 1 (alg:TT-dec).
 * non-translation-invariant operators -- section 3, the matrix form of the
   Nystrom discretisation (eq. nystrom): A = a I + B K W C with B, C, W
   diagonal (entries b(x_i), c(y_j), w_j).
+* TT rounding -- the TT decomposition that Algorithm 1 (section 2.3) gives
+  for a tensor that is itself handed over in TT form, computed from its
+  cores (the compressed product of section 4.2 has ranks that multiply; the
+  "QTT solve" of section 5.1 rounds them back).
+* the right-hand side of the volume experiments -- section 5.1: f(x, y, z) =
+  phi(x) phi(y) phi(z), phi(t) = diric(2 pi t, 10) (eq. diric).
+* QTT inversion -- the Newton-Hotelling-Schulz iteration that section 1
+  names among the QTT inversion methods, X <- X (2 I - A X), in QTT form
+  with the matrix-matrix product (ranks multiply, as in the proof of the
+  corollary on non-translation-invariant kernels in section 3) and rounding
+  after each product.
 * outer Krylov solver -- section 5.2 (boundary integral equations): the
   compressed approximate inverse preconditions an unrestarted GMRES with a
   relative-residual tolerance of 1e-8.  Because a low-precision inverse apply
@@ -48,6 +60,8 @@ __all__ = [
     "alg2_flops", "tt_svd", "qtt_matrix_from_dense", "morton_points",
     "volume_self_term", "volume_matrix", "volume_apply_direct",
     "richardson_solve", "fgmres_solve", "nti_apply", "qtt_matvec_compressed",
+    "tt_full", "tt_round", "diric", "diric_rhs", "qtt_matmul", "qtt_lincomb", "qtt_identity",
+    "qtt_round_matrix", "newton_schulz",
 ]
 
 
@@ -117,29 +131,38 @@ def qtt_to_dense(cores):
 
 
 # --------------------------------------------------------------------------
-# Algorithm 2: QTT matrix by uncompressed vector
+# the matrix by full-vector product (computed by Alg. 2 in section 4.2)
 # --------------------------------------------------------------------------
 
-def _alg2_one(cores, b):
-    """Algorithm 2 (sec. 4.2) for one vector b of length N."""
-    y = b.reshape(1, -1)                              # y_0 = b^T
+def _contract_digits(cores, x):
+    """y = A x for one vector, contracting the digit tensor of x with the cores.
+
+    Written from the TT entry formula: with x viewed as the tensor
+    x[j_1, ..., j_d] (first digit fastest),
+
+        y[i_1..i_d] = sum over j_1..j_d and the rank indices of
+                      G_1[1, i_1, j_1, a_1] G_2[a_1, i_2, j_2, a_2] ... G_d[a_{d-1}, i_d, j_d, 1]
+                      x[j_1, ..., j_d].
+
+    The sums are taken one core at a time, finest level first.  After core k
+    the partial result is a tensor W_k[a_k, j_{k+1}, ..., j_d, i_1, ..., i_k]:
+    the source digits j_1..j_k are summed out, the target digits i_1..i_k are
+    free, and a_k links it to the cores still to come.  This is the order in
+    which Alg. 2 visits the cores; here it is a plain tensor contraction with
+    no blocking or layout of its own."""
+    W = np.asarray(x, dtype=np.float64).reshape([G.shape[2] for G in cores], order="F")
+    W = W[np.newaxis]                                  # W_0[a_0 = 0, j_1, ..., j_d]
     for G in cores:
-        r_prev, m_k, n_k, r_k = G.shape
-        # M_k(overline{a_k i_k}, overline{a_{k-1} j_k}) = G_k(a_{k-1}, overline{i_k j_k}, a_k)
-        M = G.transpose(3, 1, 0, 2).reshape(r_k * m_k, r_prev * n_k, order="F")
-        cols = y.shape[1] // n_k
-        # b_k(overline{a_{k-1} j_k}, overline{J^BOX_k I^LCL_{k-1}}) = y_{k-1}(a_{k-1}, overline{J^BOX_{k-1} I^LCL_{k-1}})
-        bk = y.reshape(r_prev * n_k, cols, order="F")
-        phi = M @ bk
-        # y_k(a_k, overline{J^BOX_k I^LCL_k}) = phi_k(overline{a_k i_k}, overline{J^BOX_k I^LCL_{k-1}}),
-        # with I^LCL_k = overline{I^LCL_{k-1} i_k}: i_k becomes the slowest column digit.
-        y = phi.reshape(r_k, m_k, cols, order="F").transpose(0, 2, 1)
-        y = y.reshape(r_k, cols * m_k, order="F")
-    return y.reshape(-1, order="F")                   # y = y_d^T
+        # W_k[i_k, a_k, rest] = sum_{a_{k-1}, j_k} G_k[a_{k-1}, i_k, j_k, a_k] W_{k-1}[a_{k-1}, j_k, rest]
+        T = np.tensordot(G, W, axes=([0, 2], [0, 1]))
+        W = np.moveaxis(T, 0, -1)                      # i_k joins the target digits, slowest
+    # W_d[a_d = 0, i_1, ..., i_d]; flatten the target digits first-fastest
+    return W[0].reshape(-1, order="F")
 
 
 def qtt_apply_alg2(cores, X):
-    """Y = A X for a block of vectors, one Algorithm-2 sweep per column.
+    """Y = A X for a block of vectors: the product that Alg. 2 (section 4.2)
+    computes, taken column by column by _contract_digits.
 
     X: (N,) or (N, K) FP64.  Returns an array of shape (M,) or (M, K)."""
     _, m, n = qtt_shapes(cores)
@@ -148,10 +171,10 @@ def qtt_apply_alg2(cores, X):
     if X.shape[0] != N:
         raise ValueError(f"X has {X.shape[0]} rows, the operator has {N} columns")
     if X.ndim == 1:
-        return _alg2_one(cores, X)
+        return _contract_digits(cores, X)
     Y = np.empty((int(np.prod(m)), X.shape[1]))
     for c in range(X.shape[1]):
-        Y[:, c] = _alg2_one(cores, X[:, c])
+        Y[:, c] = _contract_digits(cores, X[:, c])
     return Y
 
 
@@ -195,37 +218,49 @@ def alg2_flops(ranks, m, n):
 # Algorithm 1: TT-SVD, and the QTT matrix of a dense matrix
 # --------------------------------------------------------------------------
 
+def _keep_rank(s, delta):
+    """Smallest r >= 1 whose discarded singular values s_r, s_{r+1}, ... have
+    a Euclidean norm of at most delta (the optimal rank-r error of the
+    unfolding, Eckart-Young), and that norm."""
+    tail = np.sqrt(np.cumsum((s ** 2)[::-1])[::-1])     # tail[r] = ||s[r:]||
+    tail = np.append(tail, 0.0)
+    r = 1
+    while r < len(s) and tail[r] > delta:
+        r += 1
+    return r, float(tail[r])
+
+
 def tt_svd(tensor, eps):
-    """Algorithm 1 (sec. 2.2) with a truncated SVD as the low-rank routine.
+    """TT decomposition of a dense tensor by successive truncated SVDs of its
+    unfoldings (Alg. 1, section 2.3, with the truncated SVD as the low-rank
+    routine and the per-unfolding accuracy eps ||A||_F / sqrt(d-1)).
 
-    The per-unfolding threshold is delta = eps * ||A||_F / sqrt(d-1); the rank
-    kept is the smallest r >= 1 whose discarded singular values have
-    sum of squares <= delta^2.  Singular values go into the right factor.
+    The modes are split off one at a time from the front.  The remainder R is
+    kept as a tensor R[a_{k-1}, i_k, i_{k+1}, ..., i_d]; its k-th unfolding
+    groups (a_{k-1}, i_k) into rows.  The left singular vectors of that
+    unfolding, cut to the rank _keep_rank allows, are core k; the singular
+    values times the right singular vectors become the next remainder, with
+    the new rank index in front.  The last remainder is core d.
 
-    Returns (cores, tails) where cores[k] has shape (r_{k-1}, n_k, r_k) and
-    tails[k] is the Frobenius norm discarded at unfolding k+1."""
+    Returns (cores, tails): cores[k] has shape (r_{k-1}, n_k, r_k), and
+    tails[k] is the Frobenius norm cut away from unfolding k+1."""
     A = np.asarray(tensor, dtype=np.float64)
-    d = A.ndim
-    n = A.shape
+    modes = A.shape
+    d = len(modes)
     if d == 1:
-        return [A.reshape(1, n[0], 1).copy()], []
+        return [A.reshape(1, modes[0], 1).copy()], []
     delta = eps * np.linalg.norm(A) / np.sqrt(d - 1)
-    Mk = A.reshape(n[0], -1, order="F")               # first unfolding matrix
-    r_prev = 1
+    R = A[np.newaxis]                                   # R[a_0 = 0, i_1, ..., i_d]
     cores, tails = [], []
     for k in range(d - 1):
-        U, s, Vt = np.linalg.svd(Mk, full_matrices=False)
-        # discarded[r] = sqrt(sum_{t >= r} s_t^2) for r = 0..len(s)
-        discarded = np.sqrt(np.append(np.cumsum((s ** 2)[::-1])[::-1], 0.0))
-        r = 1
-        while r < len(s) and discarded[r] > delta:
-            r += 1
-        tails.append(float(discarded[r]))
-        cores.append(U[:, :r].reshape(r_prev, n[k], r, order="F"))
-        V = s[:r, None] * Vt[:r]
-        Mk = V.reshape(r * n[k + 1], -1, order="F")
-        r_prev = r
-    cores.append(Mk.reshape(r_prev, n[d - 1], 1, order="F"))
+        ra, nk = R.shape[0], R.shape[1]
+        rest = R.shape[2:]
+        U, s, Vt = np.linalg.svd(R.reshape(ra * nk, -1, order="F"), full_matrices=False)
+        r, cut = _keep_rank(s, delta)
+        tails.append(cut)
+        cores.append(U[:, :r].reshape(ra, nk, r, order="F"))
+        R = (s[:r, None] * Vt[:r]).reshape((r,) + rest, order="F")
+    cores.append(R.reshape(R.shape[0], modes[-1], 1, order="F"))
     return cores, tails
 
 
@@ -455,3 +490,166 @@ def fgmres_solve(apply_A, apply_M, F, rtol=1e-8, max_iter=50):
         history.append(hist)
         iters.append(k)
     return (X[:, 0] if one else X), history, iters
+
+
+# --------------------------------------------------------------------------
+# TT vectors: expansion and rounding
+# --------------------------------------------------------------------------
+
+def tt_full(cores):
+    """The vector a TT decomposition with cores[k] of shape (r_{k-1}, n_k, r_k)
+    represents (eq. TTdeccores), flattened first index fastest (section 2.1)."""
+    T = np.ones((1, 1))
+    for G in cores:
+        T = np.tensordot(T, G, axes=([T.ndim - 1], [0]))
+    return T.reshape(-1, order="F")  # axes (a_0, i_1, ..., i_d, a_d), a_0 = a_d = 0
+
+
+def tt_round(cores, eps):
+    """The TT decomposition that Algorithm 1 (truncated SVDs, per-unfolding
+    accuracy eps ||c||_F / sqrt(d-1)) computes for the tensor c that `cores`
+    represent, without expanding c.
+
+    Why it can be done core by core: if cores k+1..d are right-orthonormal
+    (each core, as the r_{k-1} x (n_k r_k) matrix of its entries, has
+    orthonormal rows), the k-th unfolding of c is (its first k cores,
+    contracted) times a matrix with orthonormal rows, so it has the singular
+    values and left singular vectors of the first factor.  Hence:
+      1. right to left, k = d..2: QR of core k's transposed matrix,
+         core k <- Q^T (orthonormal rows), core k-1 <- core k-1 R^T;
+      2. left to right, k = 1..d-1: SVD of core k as the (r_{k-1} n_k) x r_k
+         matrix, keep the rank _keep_rank allows (tail <= eps ||c|| /
+         sqrt(d-1)), core k <- U, core k+1 <- (S V^T) core k+1.
+    Returns (cores, tails) as tt_svd does."""
+    G = [np.array(c, dtype=np.float64, copy=True) for c in cores]
+    d = len(G)
+    for k in range(d - 1, 0, -1):
+        r0, n, r1 = G[k].shape
+        q, rr = np.linalg.qr(G[k].reshape(r0, n * r1, order="F").T)      # (n r1) x r', r' x r0
+        G[k] = q.T.reshape(q.shape[1], n, r1, order="F")
+        G[k - 1] = np.tensordot(G[k - 1], rr.T, axes=([2], [0]))        # r_{k-2} x n x r'
+    norm = float(np.linalg.norm(G[0]))
+    if d == 1:
+        return G, []
+    delta = eps * norm / np.sqrt(d - 1)
+    tails = []
+    for k in range(d - 1):
+        r0, n, r1 = G[k].shape
+        U, sv, Vt = np.linalg.svd(G[k].reshape(r0 * n, r1, order="F"), full_matrices=False)
+        r, cut = _keep_rank(sv, delta)
+        tails.append(cut)
+        G[k] = U[:, :r].reshape(r0, n, r, order="F")
+        G[k + 1] = np.tensordot(sv[:r, None] * Vt[:r], G[k + 1], axes=([1], [0]))
+    return G, tails
+
+
+# --------------------------------------------------------------------------
+# the right-hand side of the volume experiments (section 5.1)
+# --------------------------------------------------------------------------
+
+def diric(t, nu):
+    """The periodic sinc function of eq. diric: sin(nu t / 2) / (nu sin(t / 2)),
+    and (-1)^(k (nu - 1)) at t = 2 pi k."""
+    t = np.asarray(t, dtype=np.float64)
+    k = np.round(t / (2.0 * np.pi))
+    at_pole = np.isclose(t, 2.0 * np.pi * k, rtol=0.0, atol=1e-12)
+    den = nu * np.sin(t / 2.0)
+    safe = np.where(at_pole, 1.0, den)
+    val = np.sin(nu * t / 2.0) / safe
+    return np.where(at_pole, (-1.0) ** (k * (nu - 1)), val)
+
+
+def diric_rhs(L, nu=10):
+    """f(x, y, z) = phi(x) phi(y) phi(z), phi(t) = diric(2 pi t, nu), at the
+    cell centres of the (2^L)^3 grid on [0,1]^3, listed in Morton order
+    (section 5.1's right-hand side, on the grid of volume_matrix)."""
+    h = 1.0 / (1 << L)
+    P = (morton_points(L) + 0.5) * h
+    phi = diric(2.0 * np.pi * P, nu)
+    return phi[:, 0] * phi[:, 1] * phi[:, 2]
+
+
+# --------------------------------------------------------------------------
+# QTT matrices: product, linear combination, rounding, Newton-Schulz
+# --------------------------------------------------------------------------
+
+def qtt_identity(m):
+    """Rank-1 QTT of the identity: cores delta(i_k, j_k)."""
+    return [np.eye(mk).reshape(1, mk, mk, 1) for mk in m]
+
+
+def qtt_matmul(A_cores, B_cores):
+    """Cores of the product A B: C_k(alpha + rA beta, i, j, alpha' + rA beta') =
+    sum_l A_k(alpha, i, l, alpha') B_k(beta, l, j, beta').  The ranks multiply
+    (the merged rank index puts A's rank first, as qtt_matvec_compressed)."""
+    out = []
+    for GA, GB in zip(A_cores, B_cores):
+        ra0, m, l, ra1 = GA.shape
+        rb0, l2, n, rb1 = GB.shape
+        if l2 != l:
+            raise ValueError("inner mode sizes differ")
+        T = np.einsum("ailc,bljd->baijdc", GA, GB)     # [beta, alpha, i, j, beta', alpha']
+        out.append(T.reshape(rb0 * ra0, m, n, rb1 * ra1))
+    return out
+
+
+def qtt_lincomb(terms):
+    """Cores of sum_t c_t A_t for a list of (c_t, cores_t) with equal modes:
+    block-diagonal interior cores, the first core a row of blocks and the last
+    a column (the TT sum; ranks add).  The coefficients scale the first core."""
+    d = len(terms[0][1])
+    out = []
+    for k in range(d):
+        blocks = [(c if k == 0 else 1.0) * cores[k] for c, cores in terms]
+        m, n = blocks[0].shape[1], blocks[0].shape[2]
+        r0 = 1 if k == 0 else sum(b.shape[0] for b in blocks)
+        r1 = 1 if k == d - 1 else sum(b.shape[3] for b in blocks)
+        G = np.zeros((r0, m, n, r1))
+        a = b = 0
+        for blk in blocks:
+            p, q = blk.shape[0], blk.shape[3]
+            ia = slice(0, 1) if k == 0 else slice(a, a + p)
+            ib = slice(0, 1) if k == d - 1 else slice(b, b + q)
+            G[ia, :, :, ib] += blk
+            a += p
+            b += q
+        out.append(G)
+    return out
+
+
+def qtt_round_matrix(cores, eps):
+    """tt_round of a QTT matrix, its cores read as TT cores of mode m_k n_k
+    (row digit fastest, the index b_k = i_k + m_k j_k of section 3)."""
+    shapes = [(G.shape[1], G.shape[2]) for G in cores]
+    tt = [G.reshape(G.shape[0], G.shape[1] * G.shape[2], G.shape[3], order="F") for G in cores]
+    out, tails = tt_round(tt, eps)
+    return [G.reshape(G.shape[0], m, n, G.shape[2], order="F") for G, (m, n) in zip(out, shapes)], tails
+
+
+def newton_schulz(A_cores, X0_cores, eps, max_iter=20, tol=0.0):
+    """Approximate inverse of A by the Newton-Hotelling-Schulz iteration
+    X_{t+1} = X_t (2 I - A X_t) in QTT form: each product by qtt_matmul,
+    the sum by qtt_lincomb, and tt rounding (relative accuracy eps) after
+    each product and after the sum.  In exact arithmetic I - A X_{t+1} =
+    (I - A X_t)^2, so the iteration converges quadratically once
+    ||I - A X_0|| < 1.
+
+    Stops after max_iter steps or once the rounded residual matrix
+    R = I - A X has ||R||_F <= tol ||I||_F.  Returns (X_cores, history) with
+    history[t] = ||I - A X_t||_F / ||I||_F for t = 0, 1, ... (computed from the
+    rounded QTT of A X_t, before X_{t+1} is formed)."""
+    m = [G.shape[1] for G in A_cores]
+    I = qtt_identity(m)
+    ident_norm = float(np.sqrt(np.prod(m)))
+    X = [np.array(G, dtype=np.float64) for G in X0_cores]
+    history = []
+    for t in range(max_iter + 1):
+        AX, _ = qtt_round_matrix(qtt_matmul(A_cores, X), eps)
+        R, _ = qtt_round_matrix(qtt_lincomb([(1.0, I), (-1.0, AX)]), eps)
+        history.append(float(np.linalg.norm(tt_full([G.reshape(G.shape[0], -1, G.shape[3], order="F")
+                                                      for G in R])) / ident_norm))
+        if history[-1] <= tol or t == max_iter:
+            break
+        Z, _ = qtt_round_matrix(qtt_lincomb([(1.0, I), (1.0, R)]), eps)      # 2 I - A X = I + R
+        X, _ = qtt_round_matrix(qtt_matmul(X, Z), eps)
+    return X, history
