@@ -144,7 +144,7 @@ qtt_status_t qtt_apply_batched(qtt_matrix_t A, qtt_dtype_t compute, int32_t nblo
  * kernel configuration is timed on each core (outputs written to scratch in
  * ws), and the fastest is kept in the handle and in a process-wide table
  * keyed by (dtype, core shape).  For FP64 the whole sweep is then timed
- * core by core, with fused core pairs and in the rank-slowest mode, and the
+ * core by core and with fused core pairs, and the
  * fastest of the three is kept.  X/Y are used as in qtt_apply and hold A X
  * on return.  Synchronises the stream. */
 qtt_status_t qtt_autotune(qtt_matrix_t A, qtt_dtype_t compute, int64_t nrhs,
@@ -155,12 +155,8 @@ qtt_status_t qtt_autotune(qtt_matrix_t A, qtt_dtype_t compute, int64_t nrhs,
  * configuration id (as chosen by qtt_autotune), -1 restores the default
  * choice.  A configuration that cannot serve the core (wrong dtype, shape
  * restrictions, misaligned operands) falls back to the default at launch.
- * core = -1 selects a whole-sweep mode instead (FP64 only): shape 50 runs
- * every FP64 sweep on the vector ALUs with the intermediates stored rank
- * index slowest (needs every mode size 8, else QTT_ERR_SHAPE; ids 50..56
- * then pick that sweep's per-core configuration), -1 returns to the
- * standard sweep.  core = -2 (FP64, FP32) switches fused core pairs off
- * (shape 0) or on (shape 1): with pairs on, which is the default, two
+ * core = -2 (FP64, FP32) switches fused core pairs off (shape 0) or on
+ * (shape 1): with pairs on, which is the default, two
  * consecutive cores k, k + 1 with r_k in 17..32 and m_k = n_{k+1} = 8, core
  * k + 1 not the last, run as one kernel that keeps the tile's intermediate
  * y_k on chip (Algorithm 2 applied two cores at a time).  Pinning a
@@ -194,8 +190,11 @@ qtt_status_t qtt_solve_workspace_bytes(qtt_matrix_t A, qtt_matrix_t Ainv, qtt_dt
  *   F         device FP64, N x nrhs, stride ldf.  Sigma: device FP64, stride lds.
  *   info      host array of nrhs entries (may be NULL).
  * Synchronises the stream once per pass to read the nrhs residual norms.
- * Returns QTT_ERR_NOT_CONVERGED (Sigma holds the last iterate) or
- * QTT_ERR_NONFINITE when a residual norm is not finite. */
+ * Columns never mix, so a column whose F or residual norm is not finite
+ * (NaN or Inf) is set aside (its info holds that norm; a column with a
+ * non-finite F is not written) while the others are solved; the call then
+ * returns QTT_ERR_NONFINITE.  Otherwise QTT_ERR_NOT_CONVERGED when a column is
+ * above rtol after max_iter passes (Sigma holds the last iterate). */
 qtt_status_t qtt_solve(qtt_matrix_t A, qtt_matrix_t Ainv, qtt_dtype_t inv_compute, int64_t nrhs,
                        const double* F, int64_t ldf, double* Sigma, int64_t lds,
                        double rtol, int32_t max_iter, void* ws, size_t ws_bytes,
@@ -225,9 +224,11 @@ qtt_status_t qtt_fgmres_workspace_bytes(qtt_matrix_t A, qtt_matrix_t Ainv, qtt_d
  *             estimate |g_{k+1}| / ||F_c|| of the rotated Hessenberg system,
  *             which equals the true relative residual up to FP64 rounding of
  *             the Arnoldi relation (A applied in FP64).
- * A zero column of F gives a zero column of Sigma in no steps.  Synchronises
- * the stream once per step.  Returns QTT_ERR_NOT_CONVERGED after max_iter
- * steps (Sigma holds each column's minimal-residual iterate),
+ * A zero column of F gives a zero column of Sigma in no steps; a column of F
+ * that is not finite is skipped (not written, its info holds the norm) while
+ * the others are solved, and the call returns QTT_ERR_NONFINITE.
+ * Synchronises the stream once per step.  Returns QTT_ERR_NOT_CONVERGED
+ * after max_iter steps (Sigma holds each column's minimal-residual iterate),
  * QTT_ERR_NONFINITE for a non-finite norm or a singular Hessenberg matrix,
  * QTT_ERR_WORKSPACE below qtt_fgmres_workspace_bytes' fixed part plus the
  * one-vector apply workspace. */

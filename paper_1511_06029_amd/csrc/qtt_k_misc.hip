@@ -1,0 +1,34 @@
+// FP64 vector-ALU core-step kernels and the short-contraction first-core kernel.
+#define QTT_KERNEL_TEMPLATES_ONLY
+#include "qtt_registry.hpp"
+
+namespace qtt {
+
+// (id, waves, rows per wave, columns per lane, input group size)
+#define QTT_VALU_SHAPES(X)   \
+  X(40, 8, 24, 1, 8)         \
+  X(41, 4, 24, 2, 8)         \
+  X(42, 4, 32, 1, 8)         \
+  X(43, 4, 16, 1, 8)         \
+  X(44, 8, 16, 1, 8)         \
+  X(45, 1, 8, 4, 8)          \
+  X(46, 2, 8, 2, 8)          \
+  X(47, 1, 8, 2, 8)          \
+  X(48, 4, 16, 1, 1)
+
+void add_valu_kernels(std::vector<ValuCfg>& v) {
+#define QTT_ADDV(id, nw, rw, cpl, nj) \
+  v.push_back({id, nw, rw, cpl, nj, reinterpret_cast<const void*>(&core_step_valu64_kernel<nw, rw, cpl, nj>), 0});
+  QTT_VALU_SHAPES(QTT_ADDV)
+#undef QTT_ADDV
+}
+
+const void* smallk_kernel(int dt) {
+  switch (dt) {
+    case 0: return reinterpret_cast<const void*>(&core_step_smallk_kernel<double>);
+    case 1: return reinterpret_cast<const void*>(&core_step_smallk_kernel<float>);
+    default: return reinterpret_cast<const void*>(&core_step_smallk_kernel<bf16_tag>);
+  }
+}
+
+}  // namespace qtt

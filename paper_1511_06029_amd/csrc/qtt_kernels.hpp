@@ -56,6 +56,27 @@ __device__ __host__ inline uint16_t f32_to_bf16_rne(float f) {
 // value and infinity; a NaN stays a quiet NaN (its payload may differ).
 __device__ inline uint16_t bf16_rne_dev(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 
+// FP64 to FP32 rounded to odd: the FP32 value next to x toward zero, with its
+// last significand bit set when the conversion is inexact.  FP32 carries 16
+// more significand bits than BF16, so rounding this value to BF16 (nearest,
+// ties to even) gives the nearest-even BF16 of x itself: one rounding, not
+// two (Boldo and Melquiond, "Emulation of FMA and correctly rounded sums:
+// proved algorithms using rounding to odd", IEEE Trans. Comput. 57, 2008).
+// Infinities, NaNs and exactly representable values pass unchanged; finite
+// values beyond the FP32 range become FLT_MAX (odd), which rounds to
+// infinity in BF16 as x does.
+__device__ __host__ inline float f64_to_f32_odd(double x) {
+  const float f = (float)x;
+  const double back = (double)f;
+  if (back == x || !(x - x == 0.0)) return f;      // exact, or Inf / NaN
+  uint32_t u = __builtin_bit_cast(uint32_t, f);
+  if ((back < 0 ? -back : back) > (x < 0 ? -x : x)) u -= 1;   // toward zero
+  return __builtin_bit_cast(float, u | 1u);
+}
+
+__device__ __host__ inline uint16_t f64_to_bf16_rne(double x) { return f32_to_bf16_rne(f64_to_f32_odd(x)); }
+__device__ inline uint16_t bf16_rne_dev_f64(double x) { return bf16_rne_dev(f64_to_f32_odd(x)); }
+
 template <class Tc> struct Mfma;
 
 template <> struct Mfma<double> {
@@ -104,13 +125,16 @@ template <> struct Mfma<bf16_tag> {
     return __builtin_bit_cast(v8bf, *reinterpret_cast<const v4u*>(p));
   }
   __device__ static frag zero_frag() { return __builtin_bit_cast(v8bf, v4u{0u, 0u, 0u, 0u}); }
-  __device__ static elem from_double(double x) { return bf16_rne_dev((float)x); }
+  __device__ static elem from_double(double x) { return bf16_rne_dev_f64(x); }
   __device__ static elem from_acc(accel x) { return bf16_rne_dev(x); }
 };
 
 // A contiguous run of vectors with its own pointers: used by the first core
 // (reads x) and the last core (writes y = z + alpha * (A x), z optional).
-constexpr int kMaxSeg = 24;
+// A launch reads its segments from a table in device memory (the head of the
+// caller's workspace), sorted by rhs_begin; up to kMaxSeg per launch.
+constexpr int kMaxSeg = 4096;
+constexpr int kSegChunk = 32;   // segments one table-writing launch carries
 struct Segment {
   const double* x;
   double* y;
@@ -139,7 +163,7 @@ struct StepArgs {
   int32_t nseg;
   int32_t M_bytes;       // bytes of the fragment array M (range of buffer loads), 0 if not needed
   double alpha;
-  Segment seg[kMaxSeg];
+  const Segment* seg;    // device table of nseg segments
 };
 
 // Kernel arguments are read in place from the kernarg segment: indexing the
@@ -150,12 +174,27 @@ __device__ inline const T& kernarg() {
   return *(const T*)(__builtin_amdgcn_kernarg_segment_ptr());
 }
 
+// The segment holding vector rhs: the last one whose rhs_begin <= rhs
+// (binary search over the sorted table).
 template <class Args>
 __device__ inline int find_seg(const Args& a, int64_t rhs) {
-  int s = 0;
-  for (int t = 1; t < a.nseg; ++t) s = (a.seg[t].rhs_begin <= rhs) ? t : s;
-  return s;
+  int lo = 0, hi = a.nseg - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (a.seg[mid].rhs_begin <= rhs) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
 }
+
+// Copies up to kSegChunk segments carried in the kernel arguments into the
+// device table (one launch per chunk; the table then serves every kernel of
+// the sweep, and graph capture records these launches with their arguments).
+struct SegWriteArgs {
+  Segment* dst;
+  int32_t n;
+  Segment seg[kSegChunk];
+};
 
 // Tin: element type the input is read in (double for the first core).
 // VEC: 16-byte input loads (host guarantees alignment and K_in % (16/sizeof(Tin)) == 0).
@@ -341,246 +380,6 @@ core_step_kernel(const StepArgs args) {
         }
       }
     }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Pipelined core step: both operands staged in LDS.
-//
-// The workgroup streams (tile, chunk) pairs: a chunk is KC contraction
-// indices of the input columns of one tile plus the matching KC columns of
-// the tile's core rows.  Global loads run two chunks ahead of the matrix
-// cores (into registers), each chunk is written to one of two LDS stages,
-// and one barrier per chunk separates reuse of a stage.  Fragments for step
-// s+1 are read from LDS while step s runs on the matrix cores.  The core
-// fragments are copied unchanged (the loader already stores them in
-// fragment order), so every LDS read is 64 lanes x E contiguous elements.
-// ---------------------------------------------------------------------------
-template <class Tc, class Tin, int WAVES_R, int WAVES_C, int WR, int WC, int KC,
-          bool ROWS_ON_LANES, bool VEC>
-__global__ void __launch_bounds__(64 * WAVES_R * WAVES_C)
-core_step_pipe_kernel(const StepArgs args) {
-  (void)args;
-  const StepArgs& a = kernarg<StepArgs>();
-  using MF = Mfma<Tc>;
-  using elem = typename MF::elem;
-  using frag = typename MF::frag;
-  using acc_t = typename MF::acc;
-  constexpr int NT = 64 * WAVES_R * WAVES_C;
-  constexpr int TC = 16 * WC * WAVES_C;
-  constexpr int TR = 16 * WR * WAVES_R;
-  constexpr int E = MF::E, KSTEP = MF::KSTEP;
-  constexpr int SPC = KC / KSTEP;
-  static_assert(KC % KSTEP == 0, "chunk must hold whole steps");
-  constexpr int VE = VEC ? (int)(16 / sizeof(Tin)) : 1;
-  static_assert(KC % VE == 0, "chunk must hold whole loads");
-  constexpr int VPC = KC / VE;
-  constexpr int NLA = (TC * VPC + NT - 1) / NT;                  // input loads per thread
-  constexpr int BV_PER_RB = SPC * 64 * E * (int)sizeof(elem) / 16;   // 16-byte core loads per row block
-  constexpr int NLB = ((TR / 16) * BV_PER_RB + NT - 1) / NT;     // core loads per thread
-  constexpr int A_ELEMS = (TC / 16) * SPC * 64 * E;
-  constexpr int B_ELEMS = (TR / 16) * SPC * 64 * E;
-  constexpr int STAGE = A_ELEMS + B_ELEMS;
-  using ld_t = typename std::conditional<VEC, v4u, Tin>::type;
-
-  __shared__ __attribute__((aligned(16))) elem lds[2 * STAGE];
-
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
-  const int wr = wave % WAVES_R;
-  const int wc = wave / WAVES_R;
-  const elem* __restrict__ Mf = reinterpret_cast<const elem*>(a.M);
-  const int Kpad = a.Ksteps * KSTEP;
-  const int nch = (Kpad + KC - 1) / KC;
-
-  const int64_t my_tiles = (a.n_tiles > (int64_t)blockIdx.x)
-                               ? (a.n_tiles - 1 - (int64_t)blockIdx.x) / gridDim.x + 1 : 0;
-  const int64_t total_it = my_tiles * nch;
-  if (total_it == 0) return;
-
-  ld_t sa[NLA];
-  v4u sb[NLB];
-
-  // ---- global -> registers for iteration it ----
-  auto gload = [&](int64_t it) {
-    const int64_t tile = blockIdx.x + (it / nch) * (int64_t)gridDim.x;
-    const int ch = (int)(it % nch);
-    const int kc0 = ch * KC;
-    const int rt = (int)(tile % a.n_row_tiles);
-    const int64_t col0 = (tile / a.n_row_tiles) * (int64_t)TC;
-#pragma unroll
-    for (int t = 0; t < NLA; ++t) {
-      const int idx = tid + t * NT;
-      const int c = idx / VPC;
-      const int kap = kc0 + (idx % VPC) * VE;
-      const int64_t g = col0 + c;
-      sa[t] = ld_t{};
-      if (idx < TC * VPC && g < a.ncols && kap < a.K_in) {
-        const int64_t rhs = g / a.C;
-        const int64_t q = g - rhs * a.C;
-        const Tin* p;
-        if (a.in_table) {
-          const Segment& sg = a.seg[find_seg(a, rhs)];
-          p = reinterpret_cast<const Tin*>(sg.x) + (rhs - sg.rhs_begin) * sg.ldx + q * a.K_in;
-        } else {
-          p = reinterpret_cast<const Tin*>(a.in) + rhs * a.in_stride + q * a.K_in;
-        }
-        sa[t] = *reinterpret_cast<const ld_t*>(p + kap);
-      }
-    }
-    const int s0 = kc0 / KSTEP;
-    const int nsteps = min(SPC, a.Ksteps - s0);
-    const int valid_v = nsteps * 64 * E * (int)sizeof(elem) / 16;   // loads per row block holding real steps
-#pragma unroll
-    for (int t = 0; t < NLB; ++t) {
-      const int idx = tid + t * NT;
-      const int rb = idx / BV_PER_RB;
-      const int v = idx % BV_PER_RB;
-      const int rbg = rt * (TR / 16) + rb;
-      sb[t] = v4u{0u, 0u, 0u, 0u};
-      if (idx < (TR / 16) * BV_PER_RB && rbg < a.nRB && v < valid_v) {
-        const elem* p = Mf + ((int64_t)rbg * a.Ksteps + s0) * 64 * E;
-        sb[t] = reinterpret_cast<const v4u*>(p)[v];
-      }
-    }
-  };
-  // ---- registers -> LDS stage ----
-  auto lstore = [&](int stage, int64_t it) {
-    const int ch = (int)(it % nch);
-    const int kc0 = ch * KC;
-    elem* A = lds + stage * STAGE;
-    elem* B = A + A_ELEMS;
-#pragma unroll
-    for (int t = 0; t < NLA; ++t) {
-      const int idx = tid + t * NT;
-      if (idx < TC * VPC) {
-        const int c = idx / VPC;
-        const int kl0 = (idx % VPC) * VE;
-        const int cb = c >> 4, cl = c & 15;
-        const Tin* v = reinterpret_cast<const Tin*>(&sa[t]);
-        if constexpr (VE == E && std::is_same<Tin, elem>::value) {
-          // one 16-byte fragment slot
-          const int s = kl0 / KSTEP, gq = (kl0 % KSTEP) / E;
-          *reinterpret_cast<ld_t*>(&A[((cb * SPC + s) * 64 + cl + 16 * gq) * E]) = sa[t];
-        } else {
-#pragma unroll
-          for (int e = 0; e < VE; ++e) {
-            const int kl = kl0 + e;
-            const int s = kl / KSTEP, gq = (kl % KSTEP) / E, ee = kl % E;
-            elem val;
-            if constexpr (std::is_same<Tin, double>::value) val = MF::from_double(v[e]);
-            else val = *reinterpret_cast<const elem*>(&v[e]);
-            A[((cb * SPC + s) * 64 + cl + 16 * gq) * E + ee] = val;
-          }
-        }
-      }
-    }
-    (void)kc0;
-#pragma unroll
-    for (int t = 0; t < NLB; ++t) {
-      const int idx = tid + t * NT;
-      if (idx < (TR / 16) * BV_PER_RB) {
-        const int rb = idx / BV_PER_RB;
-        const int v = idx % BV_PER_RB;
-        reinterpret_cast<v4u*>(B + rb * SPC * 64 * E)[v] = sb[t];
-      }
-    }
-  };
-
-  acc_t acc[WR][WC];
-  gload(0);
-  lstore(0, 0);
-  __syncthreads();
-  if (total_it > 1) gload(1);
-
-  for (int64_t it = 0; it < total_it; ++it) {
-    const int ch = (int)(it % nch);
-    if (ch == 0) {
-#pragma unroll
-      for (int i = 0; i < WR; ++i)
-#pragma unroll
-        for (int j = 0; j < WC; ++j) acc[i][j] = acc_t{};
-    }
-    const elem* A = lds + (it & 1) * STAGE;
-    const elem* B = A + A_ELEMS;
-    const int nsteps = min(SPC, a.Ksteps - ch * SPC);
-    auto step = [&](int s) {
-      frag bf[WR], af[WC];
-#pragma unroll
-      for (int i = 0; i < WR; ++i)
-        bf[i] = MF::load_frag(&B[(((wr * WR + i) * SPC + s) * 64 + lane) * E]);
-#pragma unroll
-      for (int j = 0; j < WC; ++j)
-        af[j] = MF::load_frag(&A[(((wc * WC + j) * SPC + s) * 64 + lane) * E]);
-#pragma unroll
-      for (int i = 0; i < WR; ++i)
-#pragma unroll
-        for (int j = 0; j < WC; ++j)
-          acc[i][j] = ROWS_ON_LANES ? MF::mma(af[j], bf[i], acc[i][j])
-                                    : MF::mma(bf[i], af[j], acc[i][j]);
-    };
-    if (nsteps == SPC) {
-#pragma unroll
-      for (int s = 0; s < SPC; ++s) step(s);
-    } else {
-      for (int s = 0; s < nsteps; ++s) step(s);
-    }
-
-    if (ch == nch - 1) {
-      // ---- epilogue of this tile ----
-      const int64_t tile = blockIdx.x + (it / nch) * (int64_t)gridDim.x;
-      const int rt = (int)(tile % a.n_row_tiles);
-      const int64_t col0 = (tile / a.n_row_tiles) * (int64_t)TC;
-      const int64_t rhs0 = col0 / a.C;
-      const int64_t q0 = col0 - rhs0 * a.C;
-      const bool one_rhs = (q0 + TC <= a.C);
-      const Segment* s0p = a.out_table ? &a.seg[find_seg(a, rhs0)] : nullptr;
-#pragma unroll
-      for (int i = 0; i < WR; ++i) {
-#pragma unroll
-        for (int j = 0; j < WC; ++j) {
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            int row, cit;
-            if (ROWS_ON_LANES) {
-              cit = (wc * WC + j) * 16 + MF::acc_line(lane, v);
-              row = rt * TR + (wr * WR + i) * 16 + (lane & 15);
-            } else {
-              row = rt * TR + (wr * WR + i) * 16 + MF::acc_line(lane, v);
-              cit = (wc * WC + j) * 16 + (lane & 15);
-            }
-            const int64_t g = col0 + cit;
-            if (g >= a.ncols || row >= a.R_out) continue;
-            int64_t rhs, q;
-            const Segment* sp = s0p;
-            if (one_rhs) {
-              rhs = rhs0;
-              q = q0 + cit;
-            } else {
-              rhs = g / a.C;
-              q = g - rhs * a.C;
-              if (a.out_table) sp = &a.seg[find_seg(a, rhs)];
-            }
-            const int ar = row % a.r_out;
-            const int ir = row / a.r_out;
-            const int64_t off = ar + (int64_t)a.r_out * (q + a.C * ir);
-            const auto val = acc[i][j][v];
-            if (a.out_table) {
-              const int64_t vr = rhs - sp->rhs_begin;
-              double res = a.alpha * (double)val;
-              if (sp->z != nullptr) res += sp->z[vr * sp->ldz + off];
-              sp->y[vr * sp->ldy + off] = res;
-            } else {
-              reinterpret_cast<elem*>(a.out)[rhs * a.out_stride + off] = MF::from_acc(val);
-            }
-          }
-        }
-      }
-    }
-    if (it + 1 < total_it) lstore((int)((it + 1) & 1), it + 1);
-    __syncthreads();
-    if (it + 2 < total_it) gload(it + 2);
   }
 }
 
@@ -1071,7 +870,7 @@ struct PairArgs {
   int32_t MA_bytes, MB_bytes;
   int32_t nseg;          // FIRST: input columns come from seg[].x
   int32_t ra;            // boundary rank r_k (the RA = 32 kernels take 17..32)
-  Segment seg[kMaxSeg];
+  const Segment* seg;    // device table of nseg segments
 };
 
 template <int RA, int WRB, bool FIRST, int KCA, int PF, bool PAD = false>
@@ -1535,7 +1334,7 @@ struct ValuArgs {
   int32_t n_row_tiles;
   int32_t in_table, out_table, nseg;
   double alpha;
-  Segment seg[kMaxSeg];
+  const Segment* seg;    // device table of nseg segments
 };
 
 template <int NW, int RW, int CPL, int G>
@@ -1652,6 +1451,7 @@ __global__ void __launch_bounds__(64 * NW) core_step_valu64_kernel(const ValuArg
 // contiguous), then copied out with 16-byte stores.
 // Requirements checked by the host: K_in % 8 == 0, C_k % 64 == 0.
 // ---------------------------------------------------------------------------
+#ifndef QTT_KERNEL_TEMPLATES_ONLY  // non-template kernels: compiled in the runtime unit only
 __global__ void __launch_bounds__(256) core_step_bf16_resident_kernel(const StepArgs args) {
   (void)args;
   const StepArgs& a = kernarg<StepArgs>();
@@ -1797,6 +1597,7 @@ __global__ void __launch_bounds__(256) core_step_bf16_resident_kernel(const Step
     if (t + 2 < my) gload(t + 2);
   }
 }
+#endif  // QTT_KERNEL_TEMPLATES_ONLY
 
 // ---------------------------------------------------------------------------
 // Same computation with the input tiles moved by direct global-to-LDS loads
@@ -1982,499 +1783,6 @@ __global__ void __launch_bounds__(256, TCB == 2 ? 2 : 1) core_step_bf16_dma_kern
 }
 
 // ---------------------------------------------------------------------------
-// FP64 interior core step, both operands moved by direct global-to-LDS loads.
-//
-// Tile: 256 rows x 64 columns, 4 waves of 64 x 64 (16 accumulator blocks).
-// The contraction runs in chunks of 16 indices (4 steps).  A chunk's core
-// fragments (16 row blocks x 4 steps, contiguous 2 KB per row block in the
-// fragment-ordered core) are copied with 16-byte loads, 1 KB per instruction;
-// its input fragments with 8-byte loads, one 512-byte fragment per
-// instruction (lane l: column l mod 16, contraction index 4 s + l div 16).
-// Three LDS stages keep two chunks in flight.  Waits count only the copies
-// issued after the awaited chunk: the output stores issued in between make
-// such a wait stricter, never weaker.  Input indices past K_in and columns past
-// the last tile column read finite data of the same operand (their core
-// values, or their outputs, are never used).
-// Requirements checked by the host: interior core (packed input and output),
-// R_out <= 256 with R_out % 64 == 0, C % 64 == 0.
-// ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) core_step_f64_dma_kernel(const StepArgs args) {
-  (void)args;
-  const StepArgs& a = kernarg<StepArgs>();
-  using MF = Mfma<double>;
-  constexpr int WR = 4, WC = 4, TR = 256, TC = 64, SPC = 4, KC = 16;
-  constexpr int A_EL = (TC / 16) * SPC * 64;       // 1024 doubles = 8 KB
-  constexpr int B_EL = (TR / 16) * SPC * 64;       // 4096 doubles = 32 KB
-  constexpr int DMA_B = (TR / 16) * SPC * 64 * 8 / 1024 / 4;   // 1 KB copies per wave (8)
-  constexpr int DMA_A = (TC / 16) * SPC * 2 / 4;                // 256 B gathers per wave (8)
-  constexpr int PER = DMA_A + DMA_B;                            // copies per wave per chunk
-  __shared__ __attribute__((aligned(1024))) double sA0[A_EL];
-  __shared__ __attribute__((aligned(1024))) double sA1[A_EL];
-  __shared__ __attribute__((aligned(1024))) double sA2[A_EL];
-  __shared__ __attribute__((aligned(1024))) double sB0[B_EL];
-  __shared__ __attribute__((aligned(1024))) double sB1[B_EL];
-  __shared__ __attribute__((aligned(1024))) double sB2[B_EL];
-
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int Ks = a.Ksteps;
-  const int nch = (Ks + SPC - 1) / SPC;
-  const double* __restrict__ Mf = reinterpret_cast<const double*>(a.M);
-  const double* __restrict__ in = reinterpret_cast<const double*>(a.in);
-  double* __restrict__ out = reinterpret_cast<double*>(a.out);
-  const int64_t ntiles = a.ncols / TC;
-  const int64_t my = (ntiles > (int64_t)blockIdx.x) ? (ntiles - 1 - (int64_t)blockIdx.x) / gridDim.x + 1 : 0;
-  const int64_t total = my * nch;
-  if (total == 0) return;
-
-  auto stageA = [&](int64_t it) -> double* { const int m = (int)(it % 3); return m == 0 ? sA0 : (m == 1 ? sA1 : sA2); };
-  auto stageB = [&](int64_t it) -> double* { const int m = (int)(it % 3); return m == 0 ? sB0 : (m == 1 ? sB1 : sB2); };
-  auto dma = [&](int64_t it) {
-    const int64_t col0 = (blockIdx.x + (it / nch) * (int64_t)gridDim.x) * TC;
-    const int ch = (int)(it % nch);
-    double* A = stageA(it);
-    double* B = stageB(it);
-    // core: row block rb, steps s0..s0+3 are 2 KB contiguous -> two 1 KB copies
-    const int s0 = min(ch * SPC, Ks - SPC >= 0 ? Ks - SPC : 0);
-#pragma unroll
-    for (int u = 0; u < DMA_B; ++u) {
-      const int f = wave * DMA_B + u;                 // 0..31
-      const int rb = f >> 1, half = f & 1;
-      const double* src = Mf + (((int64_t)rb * Ks + s0) * 64) + half * 128 + lane * 2;
-      __builtin_amdgcn_global_load_lds((const void*)src, (lds_void*)(B + rb * SPC * 64 + half * 128), 16, 0, 0);
-    }
-    // input: fragment (cb, s) holds, for MFMA lane d, column col0 + 16 cb + d % 16
-    // and index 4 s + d / 16.  A 4-byte copy fills half a fragment: lane l
-    // fetches half (l % 2) of fragment double 32 h + l / 2.
-#pragma unroll
-    for (int u = 0; u < DMA_A; ++u) {
-      const int f = wave * DMA_A + u;                 // 0..31
-      const int frag_id = f >> 1, h = f & 1;
-      const int cb = frag_id / SPC, s = frag_id % SPC;
-      const int d = 32 * h + (lane >> 1);
-      const int64_t col = col0 + cb * 16 + (d & 15);
-      const int kap = min(ch * KC + 4 * s + (d >> 4), a.K_in - 1);
-      const int64_t rhs = col / a.C;
-      const int64_t q = col - rhs * a.C;
-      const char* src = reinterpret_cast<const char*>(in + rhs * a.in_stride + q * a.K_in + kap) + 4 * (lane & 1);
-      __builtin_amdgcn_global_load_lds((const void*)src, (lds_void*)(A + (cb * SPC + s) * 64 + 32 * h), 4, 0, 0);
-    }
-  };
-
-  dma(0);
-  if (total > 1) dma(1);
-  if (total > 2) dma(2);
-  v4d acc[WR][WC];
-  for (int64_t it = 0; it < total; ++it) {
-    const int ch = (int)(it % nch);
-    const int nd = (int)(min(total - 1, it + 2) - it);   // copies issued after chunk it
-    wait_vmcnt_dispatch<2 * PER>(nd * PER);
-    __syncthreads();
-    if (ch == 0) {
-#pragma unroll
-      for (int i = 0; i < WR; ++i)
-#pragma unroll
-        for (int j = 0; j < WC; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
-    }
-    const double* A = stageA(it);
-    const double* B = stageB(it);
-    // the last chunk may start before ch * SPC when Ks is not a multiple of SPC
-    const int s_first = ch * SPC;
-    const int s0 = min(s_first, Ks - SPC >= 0 ? Ks - SPC : 0);
-    const int sk = s_first - s0;                     // steps of this chunk already done
-    const int nsteps = min(SPC, Ks - s_first);
-#pragma unroll
-    for (int s = 0; s < SPC; ++s) {
-      if (s < nsteps) {
-        const int sb = s + sk;
-        double bf[WR], af[WC];
-#pragma unroll
-        for (int i = 0; i < WR; ++i) bf[i] = B[((wave * WR + i) * SPC + sb) * 64 + lane];
-#pragma unroll
-        for (int j = 0; j < WC; ++j) af[j] = A[(j * SPC + s) * 64 + lane];
-#pragma unroll
-        for (int i = 0; i < WR; ++i)
-#pragma unroll
-          for (int j = 0; j < WC; ++j) acc[i][j] = MF::mma(af[j], bf[i], acc[i][j]);
-      }
-    }
-    if (ch == nch - 1 && wave * 64 < a.R_out) {
-      const int64_t col0 = (blockIdx.x + (it / nch) * (int64_t)gridDim.x) * TC;
-      const int64_t rhs = col0 / a.C;
-      const int64_t q0 = col0 - rhs * a.C;
-      double* dst = out + rhs * a.out_stride;
-#pragma unroll
-      for (int i = 0; i < WR; ++i) {
-        const int row = (wave * WR + i) * 16 + (lane & 15);
-        const int ir = row / a.r_out, ar = row - ir * a.r_out;
-        const int64_t rbase = ar + (int64_t)a.r_out * (q0 + a.C * ir);
-#pragma unroll
-        for (int j = 0; j < WC; ++j)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int cit = j * 16 + MF::acc_line(lane, v);
-            dst[rbase + (int64_t)a.r_out * cit] = acc[i][j][v];
-          }
-      }
-    }
-    __syncthreads();                                 // stage it % 3 is free again
-    if (it + 3 < total) dma(it + 3);
-  }
-}
-
-// ---------------------------------------------------------------------------
-// FP64 sweep on the vector ALUs in the rank-slowest layout.
-//
-// In this mode every intermediate of the FP64 sweep is stored with the rank
-// index slowest: y_k(a, col) at a * ncol_k + col, col = j_{k+1} + n_{k+1} q
-// in Algorithm 2's column order (for r = 1 this is X or Y itself).  Core k then
-// reads, for lane column q and rank a, its n_k values at a * n_k C_k + n_k q
-// + j (16-byte loads, consecutive lanes 64 bytes apart), and writes output
-// row (a', i) of column q at a' * m_k C_k + q + C_k i (consecutive lanes,
-// consecutive addresses).
-// Core values are wave-uniform scalar operands: the rows of rank a are read
-// in groups of two rows (two 64-byte scalar loads), the next group requested
-// before the current one is used; a scheduling barrier keeps the compiler
-// from sinking those loads to the end of the group.
-// Core order: Mt[(a * Rpad + row) * n + j] = M_k(row, a + r_{k-1} j).
-// ---------------------------------------------------------------------------
-template <int NW, int RW, int CPL>
-__global__ void __launch_bounds__(64 * NW) core_step_valu64t_kernel(const ValuArgs args) {
-  (void)args;
-  const ValuArgs& a = kernarg<ValuArgs>();
-  constexpr int NJ = 8;                       // mode size n_k (host checks)
-  static_assert(RW % 2 == 0, "rows in pairs");
-  const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  constexpr int TCOL = 64 * CPL;
-  const int r_in = a.K_in / NJ;
-  const int64_t nC = (int64_t)NJ * a.C;
-  const int m = a.R_out / a.r_out;
-  const int64_t mC = (int64_t)m * a.C;
-  for (int64_t tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
-    const int rt = (int)(tile % a.n_row_tiles);
-    const int64_t col0 = (tile / a.n_row_tiles) * TCOL;
-    const int row0 = rt * NW * RW + wave * RW;
-    const double* xin[CPL];
-    double* yout[CPL];
-    const double* zin[CPL];
-    bool ok[CPL];
-#pragma unroll
-    for (int c = 0; c < CPL; ++c) {
-      const int64_t g = col0 + lane + 64 * c;
-      ok[c] = g < a.ncols;
-      const int64_t gg = ok[c] ? g : 0;
-      const int64_t rhs = gg / a.C;
-      const int64_t q = gg - rhs * a.C;
-      if (a.in_table) {
-        const Segment& sg = a.seg[find_seg(a, rhs)];
-        xin[c] = sg.x + (rhs - sg.rhs_begin) * sg.ldx + (int64_t)NJ * q;
-      } else {
-        xin[c] = a.in + rhs * a.in_stride + (int64_t)NJ * q;
-      }
-      if (a.out_table) {
-        const Segment& sg = a.seg[find_seg(a, rhs)];
-        yout[c] = sg.y + (rhs - sg.rhs_begin) * sg.ldy + q;
-        zin[c] = sg.z ? sg.z + (rhs - sg.rhs_begin) * sg.ldz + q : nullptr;
-      } else {
-        yout[c] = a.out + rhs * a.out_stride + q;
-        zin[c] = nullptr;
-      }
-    }
-    double acc[RW][CPL];
-#pragma unroll
-    for (int r = 0; r < RW; ++r)
-#pragma unroll
-      for (int c = 0; c < CPL; ++c) acc[r][c] = 0.0;
-    double x[CPL][NJ];
-    auto load_x = [&](int al) {
-#pragma unroll
-      for (int c = 0; c < CPL; ++c) {
-        const double* p = static_cast<const double*>(__builtin_assume_aligned(xin[c] + (int64_t)al * nC, 16));
-#pragma unroll
-        for (int j = 0; j < NJ; ++j) x[c][j] = p[j];
-        if (!ok[c]) {
-#pragma unroll
-          for (int j = 0; j < NJ; ++j) x[c][j] = 0.0;
-        }
-      }
-    };
-    load_x(0);
-    for (int al = 0; al < r_in; ++al) {
-      double xc[CPL][NJ];
-#pragma unroll
-      for (int c = 0; c < CPL; ++c)
-#pragma unroll
-        for (int j = 0; j < NJ; ++j) xc[c][j] = x[c][j];
-      if (al + 1 < r_in) load_x(al + 1);
-      const cdouble* mrow = (const cdouble*)a.M + ((int64_t)al * a.Rpad + row0) * NJ;
-      double mc[2][NJ], mn[2][NJ];
-#pragma unroll
-      for (int h = 0; h < 2; ++h)
-#pragma unroll
-        for (int j = 0; j < NJ; ++j) mc[h][j] = mrow[h * NJ + j];
-#pragma unroll
-      for (int r = 0; r < RW; r += 2) {
-        // scalar loads return out of order, so a wait covers every load in
-        // flight: wait for the current group first, then request the next
-        __builtin_amdgcn_s_waitcnt(0xC07F);        // lgkmcnt(0) only
-        __builtin_amdgcn_sched_barrier(0);
-        if (r + 2 < RW) {
-#pragma unroll
-          for (int h = 0; h < 2; ++h)
-#pragma unroll
-            for (int j = 0; j < NJ; ++j) mn[h][j] = mrow[(r + 2 + h) * NJ + j];
-        }
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int h = 0; h < 2; ++h)
-#pragma unroll
-          for (int j = 0; j < NJ; ++j)
-#pragma unroll
-            for (int c = 0; c < CPL; ++c) acc[r + h][c] = fma(mc[h][j], xc[c][j], acc[r + h][c]);
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int h = 0; h < 2; ++h)
-#pragma unroll
-          for (int j = 0; j < NJ; ++j) mc[h][j] = mn[h][j];
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < RW; ++r) {
-      const int row = row0 + r;
-      if (row >= a.R_out) break;
-      const int ap = row % a.r_out, ir = row / a.r_out;
-      const int64_t off = (int64_t)ap * mC + (int64_t)a.C * ir;
-#pragma unroll
-      for (int c = 0; c < CPL; ++c) {
-        if (!ok[c]) continue;
-        if (a.out_table) {
-          double v = a.alpha * acc[r][c];
-          if (zin[c]) v += zin[c][off];
-          yout[c][off] = v;
-        } else {
-          yout[c][off] = acc[r][c];
-        }
-      }
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// FP64 core step on the 4x4x4 matrix instruction with both operands in LDS.
-//
-// Same product and operand mapping as core_step_f64q_kernel.  Vector-memory
-// operations complete in issue order, so a kernel that waits on core loads
-// every step also waits on every older input load and output store.  Here
-// every vector-memory wait is at a chunk boundary.
-//  * The core fragments of a chunk (the workgroup's TR / 16 row blocks, SPC
-//    steps) are copied into LDS by direct global-to-LDS loads of 16 bytes per
-//    lane, i.e. two consecutive step fragments of one row block per load.
-//  * The input columns of a chunk are loaded into registers and written to
-//    LDS in the 16-value-run layout (kQGS).
-//  * Both are issued for chunk it + 1 when chunk it starts, into the other of
-//    two LDS stages, and waited for (vmcnt 0) when chunk it ends.
-//  * The output stores of a finished tile are issued after those loads, at
-//    the start of the next chunk, so that a whole chunk of matrix work
-//    separates them from the next wait.
-// Requires an even number of steps Ks (the copies move step pairs).
-// ---------------------------------------------------------------------------
-template <int WR, int WQ, int KC, int MIN_WAVES = 1>
-__global__ void __launch_bounds__(256, MIN_WAVES)
-core_step_f64ql_kernel(const StepArgs args) {
-  (void)args;
-  const StepArgs& a = kernarg<StepArgs>();
-  constexpr int NT = 256;
-  constexpr int TC = 4 * WQ;
-  constexpr int TR = 16 * WR * 4;
-  constexpr int SPC = KC / 4;
-  static_assert(KC % 8 == 0, "chunk must hold an even number of steps");
-  constexpr int VPC = KC / 2;  // 16-byte input loads per column and chunk
-  constexpr int NLA = (TC * VPC + NT - 1) / NT;
-  constexpr int CORE_ELEMS = (TR / 16) * SPC * 64;
-  constexpr int IN_ELEMS = (TC / 4) * SPC * kQGS;
-  constexpr int STAGE = CORE_ELEMS + IN_ELEMS;
-  constexpr int NPAIR = (TR / 16) * (SPC / 2);  // core copies per chunk
-
-  __shared__ __attribute__((aligned(16))) double lds[2 * STAGE];
-
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wr = tid >> 6;
-  const double* __restrict__ Mf = reinterpret_cast<const double*>(a.M);
-  const int Ks = a.Ksteps;
-  const int nch = (Ks * 4 + KC - 1) / KC;
-  const int rd = 4 * (lane & 3) + (lane >> 4);
-
-  const int64_t my_tiles = (a.n_tiles > (int64_t)blockIdx.x)
-                               ? (a.n_tiles - 1 - (int64_t)blockIdx.x) / gridDim.x + 1 : 0;
-  const int64_t total_it = my_tiles * nch;
-  if (total_it == 0) return;
-
-  v4u sa[NLA];
-  auto gload = [&](int64_t it) {
-    const int64_t tile = blockIdx.x + (it / nch) * (int64_t)gridDim.x;
-    const int kc0 = (int)(it % nch) * KC;
-    const int64_t col0 = (tile / a.n_row_tiles) * (int64_t)TC;
-#pragma unroll
-    for (int t = 0; t < NLA; ++t) {
-      const int idx = tid + t * NT;
-      const int c = idx / VPC;
-      const int kap = kc0 + (idx % VPC) * 2;
-      const int64_t g = col0 + c;
-      sa[t] = v4u{};
-      if (idx < TC * VPC && g < a.ncols && kap < a.K_in) {
-        const int64_t rhs = g / a.C;
-        const int64_t q = g - rhs * a.C;
-        const double* p;
-        if (a.in_table) {
-          const Segment& sg = a.seg[find_seg(a, rhs)];
-          p = reinterpret_cast<const double*>(sg.x) + (rhs - sg.rhs_begin) * sg.ldx + q * a.K_in;
-        } else {
-          p = reinterpret_cast<const double*>(a.in) + rhs * a.in_stride + q * a.K_in;
-        }
-        sa[t] = *reinterpret_cast<const v4u*>(p + kap);
-      }
-    }
-  };
-  auto lstore = [&](int stage) {
-    double* A = lds + stage * STAGE + CORE_ELEMS;
-#pragma unroll
-    for (int t = 0; t < NLA; ++t) {
-      const int idx = tid + t * NT;
-      if (idx < TC * VPC) {
-        const int c = idx / VPC;
-        const int kl0 = (idx % VPC) * 2;
-        *reinterpret_cast<v4u*>(&A[((c >> 2) * SPC + (kl0 >> 2)) * kQGS + 4 * (c & 3) + (kl0 & 3)]) = sa[t];
-      }
-    }
-  };
-  // core copies of chunk it: unit u = (row block rbl, step pair p), four waves
-  // share the units; a copy moves fragments (rb, s0 + 2 p) and (rb, s0 + 2 p + 1)
-  auto cload = [&](int64_t it, int stage) {
-    const int64_t tile = blockIdx.x + (it / nch) * (int64_t)gridDim.x;
-    const int rt = (int)(tile % a.n_row_tiles);
-    const int s0 = (int)(it % nch) * SPC;
-    const int ns = min(SPC, Ks - s0);
-    double* B = lds + stage * STAGE;
-#pragma unroll
-    for (int u0 = 0; u0 < NPAIR; u0 += 4) {
-      const int u = u0 + wr;
-      const int rbl = u / (SPC / 2), p = u % (SPC / 2);
-      if (u < NPAIR && 2 * p < ns) {
-        const double* src = Mf + ((int64_t)(rt * (TR / 16) + rbl) * Ks + s0 + 2 * p) * 64 + 2 * lane;
-        __builtin_amdgcn_global_load_lds((const void*)src, (lds_void*)(B + (rbl * SPC + 2 * p) * 64), 16, 0, 0);
-      }
-    }
-  };
-
-  double acc[WR][WQ];
-  auto epilogue = [&](int64_t it) {
-    const int64_t tile = blockIdx.x + (it / nch) * (int64_t)gridDim.x;
-    const int rt = (int)(tile % a.n_row_tiles);
-    const int64_t col0 = (tile / a.n_row_tiles) * (int64_t)TC;
-    const int64_t rhs0 = col0 / a.C;
-    const int64_t q0 = col0 - rhs0 * a.C;
-    const bool one_rhs = (q0 + TC <= a.C);
-    const Segment* s0p = a.out_table ? &a.seg[find_seg(a, rhs0)] : nullptr;
-#pragma unroll
-    for (int i = 0; i < WR; ++i) {
-      const int row = rt * TR + (wr * WR + i) * 16 + (lane & 15);
-      const int ar = row % a.r_out;
-      const int ir = row / a.r_out;
-#pragma unroll
-      for (int j = 0; j < WQ; ++j) {
-        const int cit = j * 4 + (lane >> 4);
-        const int64_t g = col0 + cit;
-        if (g >= a.ncols || row >= a.R_out) continue;
-        int64_t rhs, q;
-        const Segment* sp = s0p;
-        if (one_rhs) {
-          rhs = rhs0;
-          q = q0 + cit;
-        } else {
-          rhs = g / a.C;
-          q = g - rhs * a.C;
-          if (a.out_table) sp = &a.seg[find_seg(a, rhs)];
-        }
-        const int64_t off = ar + (int64_t)a.r_out * (q + a.C * ir);
-        const double val = acc[i][j];
-        if (a.out_table) {
-          const int64_t vr = rhs - sp->rhs_begin;
-          double res = a.alpha * val;
-          if (sp->z != nullptr) res += sp->z[vr * sp->ldz + off];
-          sp->y[vr * sp->ldy + off] = res;
-        } else {
-          reinterpret_cast<double*>(a.out)[rhs * a.out_stride + off] = val;
-        }
-      }
-    }
-  };
-
-  cload(0, 0);
-  gload(0);
-  wait_vmcnt<0>();
-  lstore(0);
-  __syncthreads();
-#pragma unroll
-  for (int i = 0; i < WR; ++i)
-#pragma unroll
-    for (int j = 0; j < WQ; ++j) acc[i][j] = 0.0;
-
-  for (int64_t it = 0; it < total_it; ++it) {
-    if (it + 1 < total_it) {
-      cload(it + 1, (int)((it + 1) & 1));
-      gload(it + 1);
-    }
-    const int ch = (int)(it % nch);
-    if (it > 0 && ch == 0) {
-      epilogue(it - 1);
-#pragma unroll
-      for (int i = 0; i < WR; ++i)
-#pragma unroll
-        for (int j = 0; j < WQ; ++j) acc[i][j] = 0.0;
-    }
-    const double* S = lds + (it & 1) * STAGE;
-    const int nsteps = min(SPC, Ks - ch * SPC);
-    auto lread = [&](double (&af)[WQ], double (&bc)[WR], int s) {
-#pragma unroll
-      for (int i = 0; i < WR; ++i) bc[i] = S[((wr * WR + i) * SPC + s) * 64 + lane];
-#pragma unroll
-      for (int j = 0; j < WQ; ++j) af[j] = S[CORE_ELEMS + (j * SPC + s) * kQGS + rd];
-    };
-    auto mma = [&](const double (&af)[WQ], const double (&bc)[WR]) {
-#pragma unroll
-      for (int i = 0; i < WR; ++i)
-#pragma unroll
-        for (int j = 0; j < WQ; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f64_4x4x4f64(af[j], bc[i], acc[i][j], 0, 0, 0);
-    };
-    if (nsteps == SPC) {
-      double af[2][WQ], bc[2][WR];
-      lread(af[0], bc[0], 0);
-#pragma unroll
-      for (int s = 0; s < SPC; ++s) {
-        if (s + 1 < SPC) lread(af[(s + 1) & 1], bc[(s + 1) & 1], s + 1);
-        mma(af[s & 1], bc[s & 1]);
-      }
-    } else {
-      for (int s = 0; s < nsteps; ++s) {
-        double af[WQ], bc[WR];
-        lread(af, bc, s);
-        mma(af, bc);
-      }
-    }
-    if (it + 1 < total_it) {
-      wait_vmcnt<0>();
-      lstore((int)((it + 1) & 1));
-    }
-    __syncthreads();
-  }
-  epilogue(total_it - 1);
-}
-
-// ---------------------------------------------------------------------------
 // First core step with a short contraction (K_in = n_1 <= 16) on the vector
 // ALUs, any compute dtype.
 //
@@ -2519,7 +1827,7 @@ template <> struct SmallK<bf16_tag> {
   static constexpr int KS = 32, E = 8, TQ = 32;
   __device__ static float from_bits(uint16_t b) { return __builtin_bit_cast(float, (uint32_t)b << 16); }
   __device__ static acc load_core(const void* M, int64_t i) { return from_bits(reinterpret_cast<const uint16_t*>(M)[i]); }
-  __device__ static acc round_in(double x) { return from_bits(bf16_rne_dev((float)x)); }
+  __device__ static acc round_in(double x) { return from_bits(bf16_rne_dev_f64(x)); }
   __device__ static out to_out(acc v) { return bf16_rne_dev(v); }
 };
 
@@ -2615,91 +1923,12 @@ __global__ void __launch_bounds__(256) core_step_smallk_kernel(const StepArgs ar
   }
 }
 
-// ---------------------------------------------------------------------------
-// Last core step of a BF16 sweep (r_d = 1, R_out = m_d <= 8) on the vector
-// ALUs with FP32 accumulation.
-//
-// The product is at most 8 x K_in with K_in up to 256: too few rows for a
-// matrix instruction, and the step is bound by reading the K_in BF16 values
-// of every column.  Four lanes share a column, each contracting a quarter of
-// it with 16-byte loads (8 BF16 values); the core, decoded once per workgroup
-// from its fragment buffer (the same values as the matrix-core kernels),
-// sits in LDS as Ms[k][row] and is read as two 16-byte broadcasts per
-// contraction index; a butterfly over the four lanes completes the sums, and
-// the four lanes write the FP64 output Y = Z + alpha (A X) (rows h, h + 4 for
-// lane h), which is the step's fused epilogue.
-// Requirements checked by the host: last core of a BF16 sweep (input packed,
-// output through the segment table), R_out <= 8, K_in % 32 == 0, K_in <= 256.
-// ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) core_step_lastk_bf16_kernel(const StepArgs args) {
+#ifndef QTT_KERNEL_TEMPLATES_ONLY  // non-template kernels: compiled in the runtime unit only
+__global__ void __launch_bounds__(64) seg_write_kernel(const SegWriteArgs args) {
   (void)args;
-  const StepArgs& a = kernarg<StepArgs>();
-  constexpr int NT = 256, MAXK = 256, RP = 8, CPB = NT / 4;   // columns per workgroup pass
-  __shared__ __attribute__((aligned(16))) float Ms[MAXK * RP];
-  const int tid = threadIdx.x;
-  const int K = a.K_in, R = a.R_out, Ks = a.Ksteps;
-  const uint16_t* __restrict__ Mf = reinterpret_cast<const uint16_t*>(a.M);
-  for (int idx = tid; idx < K * RP; idx += NT) {
-    const int k = idx / RP, row = idx - k * RP;
-    float v = 0.f;
-    if (row < R) {
-      const int l = (row & 15) + 16 * ((k & 31) >> 3);
-      const uint16_t b = Mf[(((int64_t)(row >> 4) * Ks + (k >> 5)) * 64 + l) * 8 + (k & 7)];
-      v = __builtin_bit_cast(float, (uint32_t)b << 16);
-    }
-    Ms[idx] = v;
-  }
-  __syncthreads();
-  const int h = tid & 3;
-  const int kq = K / 4;                            // contraction indices per lane (multiple of 8)
-  const uint16_t* __restrict__ in = reinterpret_cast<const uint16_t*>(a.in);
-  for (int64_t g = (int64_t)blockIdx.x * CPB + (tid >> 2); g < a.ncols; g += (int64_t)gridDim.x * CPB) {
-    const int64_t rhs = g / a.C;
-    const int64_t q = g - rhs * a.C;
-    const v4u* src = reinterpret_cast<const v4u*>(in + rhs * a.in_stride + q * K + h * kq);
-    float acc[RP];
-#pragma unroll
-    for (int r = 0; r < RP; ++r) acc[r] = 0.f;
-    for (int v = 0; v < kq / 8; ++v) {
-      const v4u x8 = src[v];
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const uint32_t w = x8[e >> 1];
-        const float xv = __builtin_bit_cast(float, (e & 1) ? (w & 0xffff0000u) : (w << 16));
-        const int k = h * kq + 8 * v + e;
-        const v4f m0 = *reinterpret_cast<const v4f*>(&Ms[k * RP]);
-        const v4f m1 = *reinterpret_cast<const v4f*>(&Ms[k * RP + 4]);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          acc[r] = fmaf(m0[r], xv, acc[r]);
-          acc[r + 4] = fmaf(m1[r], xv, acc[r + 4]);
-        }
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < RP; ++r) {
-      acc[r] += __shfl_xor(acc[r], 1);
-      acc[r] += __shfl_xor(acc[r], 2);
-    }
-    // row = i_d (r_d = 1): output q + C_d i_d
-    const Segment& sg = a.seg[find_seg(a, rhs)];
-    const int64_t vr = rhs - sg.rhs_begin;
-    // lane h writes rows h and h + 4 (selected without indexing registers)
-    float sel[2] = {acc[0], acc[4]};
-    if (h == 1) { sel[0] = acc[1]; sel[1] = acc[5]; }
-    if (h == 2) { sel[0] = acc[2]; sel[1] = acc[6]; }
-    if (h == 3) { sel[0] = acc[3]; sel[1] = acc[7]; }
-#pragma unroll
-    for (int r2 = 0; r2 < 2; ++r2) {
-      const int row = h + 4 * r2;
-      if (row < R) {
-        const int64_t off = q + a.C * row;
-        double res = a.alpha * (double)sel[r2];
-        if (sg.z != nullptr) res += sg.z[vr * sg.ldz + off];
-        sg.y[vr * sg.ldy + off] = res;
-      }
-    }
-  }
+  const SegWriteArgs& a = kernarg<SegWriteArgs>();
+  const int t = threadIdx.x;
+  if (t < a.n) a.dst[t] = a.seg[t];
 }
 
 // ---------------------------------------------------------------------------
@@ -2707,12 +1936,13 @@ __global__ void __launch_bounds__(256) core_step_lastk_bf16_kernel(const StepArg
 // summation order depends only on the column length, never on the batch).
 // ---------------------------------------------------------------------------
 constexpr int kNormBlocks = 64;
+constexpr int kNormCols = 24;      // columns per norm launch
 constexpr int kNormThreads = 256;
 
 struct NormArgs {
-  const double* R[kMaxSeg];
-  int64_t ld[kMaxSeg];
-  int64_t col_begin[kMaxSeg];
+  const double* R[kNormCols];
+  int64_t ld[kNormCols];
+  int64_t col_begin[kNormCols];
   int32_t nseg;
   int32_t ncol;
   int64_t N;
@@ -2892,7 +2122,7 @@ __global__ void __launch_bounds__(kKryThreads) combine_kernel(const CombineArgs 
 // ---------------------------------------------------------------------------
 
 struct DiagArgs {
-  Segment seg[kMaxSeg];
+  const Segment* seg;    // device table of nseg segments
   int32_t nseg;
   int64_t ncol;          // vectors in the launch
   int64_t rows;          // length of the columns handled (N before, M after)
@@ -2901,11 +2131,7 @@ struct DiagArgs {
   double a, alpha;       // after only
 };
 
-__device__ inline int diag_segment(const DiagArgs& a, int64_t t) {
-  int s = 0;
-  for (int q = 1; q < a.nseg; ++q) s = (a.seg[q].rhs_begin <= t) ? q : s;
-  return s;
-}
+__device__ inline int diag_segment(const DiagArgs& a, int64_t t) { return find_seg(a, t); }
 
 __global__ void __launch_bounds__(256) diag_in_kernel(const DiagArgs args) {
   (void)args;
@@ -3037,5 +2263,7 @@ __global__ void __launch_bounds__(256) compressed_matvec_lds_kernel(const CmvArg
     }
   }
 }
+
+#endif  // QTT_KERNEL_TEMPLATES_ONLY
 
 }  // namespace qtt

@@ -24,6 +24,7 @@
 
 #include "qtt.h"
 #include "qtt_kernels.hpp"
+#include "qtt_registry.hpp"
 
 using namespace qtt;
 
@@ -67,147 +68,12 @@ static const int kFragE[3] = {1, 1, 8};
 // ---------------------------------------------------------------------------
 // kernel registry
 // ---------------------------------------------------------------------------
-typedef void (*step_fn)(const StepArgs);
-
-struct KernelCfg {
-  int dt;          // 0 fp64, 1 fp32, 2 bf16
-  bool in_f64;     // reads FP64 input (first core)
-  bool vec;        // 16-byte input loads
-  int TR, TC, KC, NT;
-  int id;          // configuration id within the dtype (tile shape)
-  const void* fn;  // kernel symbol
-  int occ;         // resident blocks per CU, 0 = not yet queried
-  int kind;        // 0 single-operand LDS, 1 pipelined, 2 streamed, 3 4x4x4 streamed, 4 4x4x4 LDS-fed
-};
-
-template <class Tc, class Tin, int WRW, int WCW, int WR, int WC, int KC, bool ROL, bool VEC, int KIND,
-          int MINW = 1, int PF = 1, bool AHEAD = true>
-static KernelCfg make_cfg(int dt, bool in_f64, int id) {
-  KernelCfg k;
-  k.dt = dt;
-  k.in_f64 = in_f64;
-  k.vec = VEC;
-  k.TR = 16 * WR * WRW;
-  k.TC = (KIND >= 3 ? 4 : 16) * WC * WCW;
-  k.KC = KC;
-  k.NT = 64 * WRW * WCW;
-  k.id = id;
-  k.kind = KIND;
-  if constexpr (KIND == 4) {
-    static_assert(std::is_same<Tc, double>::value && std::is_same<Tin, double>::value && WRW == 4 && WCW == 1,
-                  "the LDS-fed 4x4x4 kernel is FP64 only, four waves along rows");
-    k.fn = reinterpret_cast<const void*>(&core_step_f64ql_kernel<WR, WC, KC, MINW>);
-  } else if constexpr (KIND == 3) {
-    static_assert(std::is_same<Tc, double>::value && std::is_same<Tin, double>::value,
-                  "the 4x4x4 kernel is FP64 only");
-    k.fn = reinterpret_cast<const void*>(&core_step_f64q_kernel<WRW, WCW, WR, WC, KC, PF, MINW, AHEAD>);
-  } else if constexpr (KIND == 2)
-    k.fn = reinterpret_cast<const void*>(&core_step_stream_kernel<Tc, Tin, WRW, WCW, WR, WC, KC, ROL, VEC, MINW>);
-  else if constexpr (KIND == 1)
-    k.fn = reinterpret_cast<const void*>(&core_step_pipe_kernel<Tc, Tin, WRW, WCW, WR, WC, KC, ROL, VEC>);
-  else
-    k.fn = reinterpret_cast<const void*>(&core_step_kernel<Tc, Tin, WRW, WCW, WR, WC, KC, ROL, VEC>);
-  k.occ = 0;
-  return k;
-}
-
-// Tile shapes: (id, waves along rows, waves along columns, row blocks per
-// wave, column blocks per wave, rows on lanes).  Ids below 10 use the
-// single-operand-LDS kernel, ids from 10 the pipelined two-operand kernel.
-#define QTT_SHAPES_V1(X)     \
-  X(0, 4, 1, 4, 4, true)     \
-  X(1, 4, 1, 3, 4, true)     \
-  X(2, 1, 4, 1, 4, false)    \
-  X(5, 4, 1, 4, 2, true)     \
-  X(6, 2, 2, 2, 2, true)
-#define QTT_SHAPES_V2(X)     \
-  X(10, 4, 1, 4, 4, true)    \
-  X(11, 4, 1, 4, 2, true)    \
-  X(13, 1, 4, 1, 4, false)
-#define QTT_SHAPES_V3(X)     \
-  X(20, 4, 1, 4, 4, true)    \
-  X(21, 4, 1, 4, 2, true)    \
-  X(22, 4, 1, 3, 4, true)    \
-  X(23, 1, 4, 1, 4, false)   \
-  X(24, 2, 2, 4, 4, true)    \
-  X(25, 4, 1, 2, 4, true)    \
-  X(26, 4, 1, 4, 1, true)    \
-  X(27, 1, 4, 1, 2, false)
-// FP64 shapes on the 4x4x4 instruction (ids from 60): (id, waves along rows,
-// waves along columns, row blocks per wave, 4-column groups per wave, chunk
-// length KC, core prefetch depth in steps, minimum resident waves per SIMD).
-// They serve a core only when its step count is a multiple of KC / 4.
-#define QTT_SHAPES_Q(X)             \
-  X(60, 4, 1, 4, 8, 32, 2, 2)       \
-  X(61, 4, 1, 4, 8, 32, 4, 2)       \
-  X(62, 4, 1, 4, 8, 32, 8, 2)       \
-  X(63, 4, 1, 3, 8, 32, 2, 2)       \
-  X(64, 4, 1, 3, 8, 32, 4, 2)       \
-  X(65, 4, 1, 4, 4, 32, 4, 2)       \
-  X(66, 4, 1, 4, 4, 32, 8, 2)       \
-  X(67, 4, 1, 3, 8, 8, 2, 2)        \
-  X(68, 4, 1, 4, 8, 8, 2, 2)        \
-  X(69, 2, 2, 4, 4, 32, 4, 2)
-// the same without reading input fragments a step ahead (ids from 75)
-#define QTT_SHAPES_QN(X)            \
-  X(75, 4, 1, 4, 8, 32, 4, 2)       \
-  X(76, 4, 1, 4, 8, 32, 8, 2)       \
-  X(77, 4, 1, 3, 8, 32, 4, 2)       \
-  X(78, 4, 1, 4, 6, 32, 4, 2)       \
-  X(79, 4, 1, 4, 6, 32, 8, 2)
-// FP64 shapes on the 4x4x4 instruction with both operands in LDS (ids from
-// 70): (id, row blocks per wave, 4-column groups per wave, chunk length KC,
-// minimum resident waves per SIMD); four waves along rows.
-#define QTT_SHAPES_QL(X)     \
-  X(70, 4, 8, 16, 2)         \
-  X(71, 4, 4, 16, 2)         \
-  X(72, 3, 8, 16, 2)         \
-  X(73, 4, 8, 8, 2)          \
-  X(74, 2, 8, 32, 2)
-static const int kGenericShape = 6;
-static const int kSmallK = 34;   // first core with a short contraction (vector ALUs)
-static const int kLastK = 35;    // BF16 last core with at most 8 rows (vector ALUs)
-
-template <class Tc, class Tin, int KC1, int KC2>
-static void add_family(std::vector<KernelCfg>& v, int dt, bool in_f64) {
-#define QTT_ADD1(id, a, b, c, d, rol) v.push_back(make_cfg<Tc, Tin, a, b, c, d, KC1, rol, true, 0>(dt, in_f64, id));
-#define QTT_ADD2(id, a, b, c, d, rol) v.push_back(make_cfg<Tc, Tin, a, b, c, d, KC2, rol, true, 1>(dt, in_f64, id));
-#define QTT_ADD3(id, a, b, c, d, rol) v.push_back(make_cfg<Tc, Tin, a, b, c, d, KC1, rol, true, 2>(dt, in_f64, id));
-  QTT_SHAPES_V1(QTT_ADD1)
-  QTT_SHAPES_V2(QTT_ADD2)
-  QTT_SHAPES_V3(QTT_ADD3)
-  // streamed shapes held to 3 resident waves per SIMD (fewer registers each)
-  v.push_back(make_cfg<Tc, Tin, 4, 1, 4, 2, KC1, true, true, 2, 3>(dt, in_f64, 28));
-  v.push_back(make_cfg<Tc, Tin, 4, 1, 2, 4, KC1, true, true, 2, 3>(dt, in_f64, 29));
-  if constexpr (std::is_same<Tc, double>::value) {
-#define QTT_ADDQ(id, a, b, c, d, kc, pf, mw) \
-    v.push_back(make_cfg<Tc, Tin, a, b, c, d, kc, true, true, 3, mw, pf>(dt, in_f64, id));
-    QTT_SHAPES_Q(QTT_ADDQ)
-#undef QTT_ADDQ
-#define QTT_ADDQN(id, a, b, c, d, kc, pf, mw) \
-    v.push_back(make_cfg<Tc, Tin, a, b, c, d, kc, true, true, 3, mw, pf, false>(dt, in_f64, id));
-    QTT_SHAPES_QN(QTT_ADDQN)
-#undef QTT_ADDQN
-#define QTT_ADDQL(id, c, d, kc, mw) \
-    v.push_back(make_cfg<Tc, Tin, 4, 1, c, d, kc, true, true, 4, mw>(dt, in_f64, id));
-    QTT_SHAPES_QL(QTT_ADDQL)
-#undef QTT_ADDQL
-  }
-#undef QTT_ADD1
-#undef QTT_ADD2
-#undef QTT_ADD3
-  // scalar-load fallback for shapes whose columns are not 16-byte aligned
-  v.push_back(make_cfg<Tc, Tin, 2, 2, 2, 2, KC1, true, false, 0>(dt, in_f64, kGenericShape));
-}
-
 static std::vector<KernelCfg>& registry() {
   static std::vector<KernelCfg> reg = [] {
     std::vector<KernelCfg> v;
-    add_family<double, double, 32, 16>(v, 0, true);
-    add_family<float, float, 32, 32>(v, 1, false);
-    add_family<float, double, 32, 32>(v, 1, true);
-    add_family<bf16_tag, uint16_t, 128, 64>(v, 2, false);
-    add_family<bf16_tag, double, 32, 64>(v, 2, true);   // first core: K_in = n_1 is small
+    add_kernels_f64(v);
+    add_kernels_f32(v);
+    add_kernels_bf16(v);
     return v;
   }();
   return reg;
@@ -238,70 +104,13 @@ static std::vector<int> shape_ids(int dt, bool in_f64) {
   return ids;
 }
 
-// FP64 vector-ALU kernels: (id, waves, rows per wave, columns per lane, input group size).
-struct ValuCfg {
-  int id, NW, RW, CPL, G;
-  const void* fn;
-  int occ;
-};
-#define QTT_VALU_SHAPES(X)   \
-  X(40, 8, 24, 1, 8)         \
-  X(41, 4, 24, 2, 8)         \
-  X(42, 4, 32, 1, 8)         \
-  X(43, 4, 16, 1, 8)         \
-  X(44, 8, 16, 1, 8)         \
-  X(45, 1, 8, 4, 8)          \
-  X(46, 2, 8, 2, 8)          \
-  X(47, 1, 8, 2, 8)          \
-  X(48, 4, 16, 1, 1)
-static const int kValuGeneric = 48;
-
 static std::vector<ValuCfg>& valu_registry() {
   static std::vector<ValuCfg> reg = [] {
     std::vector<ValuCfg> v;
-#define QTT_ADDV(id, nw, rw, cpl, nj) \
-    v.push_back({id, nw, rw, cpl, nj, reinterpret_cast<const void*>(&core_step_valu64_kernel<nw, rw, cpl, nj>), 0});
-    QTT_VALU_SHAPES(QTT_ADDV)
-#undef QTT_ADDV
+    add_valu_kernels(v);
     return v;
   }();
   return reg;
-}
-
-// FP64 sweeps in the rank-slowest layout (vector ALUs, n_k = 8): ids 50..
-#define QTT_VALUT_SHAPES(X)  \
-  X(50, 4, 32, 1)            \
-  X(51, 8, 32, 1)            \
-  X(52, 4, 16, 2)            \
-  X(53, 8, 16, 2)            \
-  X(54, 4, 8, 4)             \
-  X(55, 1, 8, 4)             \
-  X(56, 2, 8, 2)
-static std::vector<ValuCfg>& valut_registry() {
-  static std::vector<ValuCfg> reg = [] {
-    std::vector<ValuCfg> v;
-#define QTT_ADDVT(id, nw, rw, cpl) \
-    v.push_back({id, nw, rw, cpl, 8, reinterpret_cast<const void*>(&core_step_valu64t_kernel<nw, rw, cpl>), 0});
-    QTT_VALUT_SHAPES(QTT_ADDVT)
-#undef QTT_ADDVT
-    return v;
-  }();
-  return reg;
-}
-static ValuCfg* find_valut(int id) {
-  for (auto& k : valut_registry())
-    if (k.id == id) return &k;
-  return nullptr;
-}
-
-// Rows of the rank-slowest copy: every tile height of that registry divides it.
-static int valut_padded_rows(int R_out) {
-  int pad = R_out;
-  for (auto& k : valut_registry()) {
-    const int t = k.NW * k.RW;
-    pad = std::max(pad, (R_out + t - 1) / t * t);
-  }
-  return pad;
 }
 
 static ValuCfg* find_valu(int id) {
@@ -349,7 +158,7 @@ static KernelCfg* bf16_dma_cfg() {
   static KernelCfg k = [] {
     KernelCfg c = *bf16_resident_cfg();
     c.id = kBf16Dma;
-    c.fn = reinterpret_cast<const void*>(&core_step_bf16_dma_kernel<4>);
+    c.fn = bf16_dma_kernel(4);
     c.occ = 0;
     c.kind = -1;
     return c;
@@ -361,7 +170,7 @@ static KernelCfg* bf16_dma32_cfg() {
     KernelCfg c = *bf16_resident_cfg();
     c.id = kBf16Dma32;
     c.TC = 32;
-    c.fn = reinterpret_cast<const void*>(&core_step_bf16_dma_kernel<2>);
+    c.fn = bf16_dma_kernel(2);
     c.occ = 0;
     c.kind = -1;
     return c;
@@ -375,9 +184,7 @@ static KernelCfg* smallk_cfg(int dt) {
   static KernelCfg k[3] = {};
   static std::once_flag once;
   std::call_once(once, [] {
-    const void* fns[3] = {reinterpret_cast<const void*>(&core_step_smallk_kernel<double>),
-                          reinterpret_cast<const void*>(&core_step_smallk_kernel<float>),
-                          reinterpret_cast<const void*>(&core_step_smallk_kernel<bf16_tag>)};
+    const void* fns[3] = {smallk_kernel(0), smallk_kernel(1), smallk_kernel(2)};
     const int tq[3] = {SmallK<double>::TQ, SmallK<float>::TQ, SmallK<bf16_tag>::TQ};
     for (int t = 0; t < 3; ++t) {
       k[t].dt = t;
@@ -394,47 +201,6 @@ static KernelCfg* smallk_cfg(int dt) {
     }
   });
   return &k[dt];
-}
-
-// BF16 last core on the vector ALUs (shape id 35).
-static KernelCfg* lastk_cfg() {
-  static KernelCfg k = [] {
-    KernelCfg c;
-    c.dt = 2;
-    c.in_f64 = false;
-    c.vec = true;
-    c.TR = 256;
-    c.TC = 64;
-    c.KC = 32;
-    c.NT = 256;
-    c.id = kLastK;
-    c.fn = reinterpret_cast<const void*>(&core_step_lastk_bf16_kernel);
-    c.occ = 0;
-    c.kind = -1;
-    return c;
-  }();
-  return &k;
-}
-
-// FP64 interior kernel fed by direct global-to-LDS loads (shape id 32).
-static const int kF64Dma = 32;
-static KernelCfg* f64_dma_cfg() {
-  static KernelCfg k = [] {
-    KernelCfg c;
-    c.dt = 0;
-    c.in_f64 = true;
-    c.vec = true;
-    c.TR = 256;
-    c.TC = 64;
-    c.KC = 16;
-    c.NT = 256;
-    c.id = kF64Dma;
-    c.fn = reinterpret_cast<const void*>(&core_step_f64_dma_kernel);
-    c.occ = 0;
-    c.kind = -1;
-    return c;
-  }();
-  return &k;
 }
 
 static int num_cus() {
@@ -481,10 +247,7 @@ struct CoreDev {
   int tuned[3];       // tuned shape id per dtype, -1 = heuristic
   double* valu;       // FP64 vector-ALU copy Mv, input groups of 8 (when K_in % 8 == 0)
   double* valu1;      // FP64 vector-ALU copy Mv, groups of 1
-  double* valut;      // FP64 copy for the rank-slowest sweep (n_k = 8), Mt
   int Rpad;           // rows of Mv
-  int RpadT;          // rows of Mt
-  int tuned_t;        // shape id in the rank-slowest sweep, -1 = heuristic
   double* g64 = nullptr;  // FP64 core as given, [r_in][m][n][r_out] (compressed products)
 };
 
@@ -496,8 +259,6 @@ struct qtt_matrix_s {
   int device = 0;
   std::vector<CoreDev> core;
   int64_t max_inter = 0;  // largest y_k (k < d) per vector, elements
-  bool fp64_t = false;    // FP64 sweeps in the rank-slowest layout on the vector ALUs
-  bool fp64_t_ok = false; // every mode size is 8, so the mode is available
   bool fp64_pair = true;  // FP64 sweeps fuse interior core pairs where the pair kernel applies
   bool fp32_pair = true;  // the same for FP32 sweeps
   // a I + diag(b) K diag(wc) (non-translation-invariant operator); device
@@ -569,7 +330,10 @@ static thread_local bool g_timing = false;
 static thread_local std::vector<TimedLaunch> g_timed;
 static std::atomic<int> g_timing_env{-1};
 
+static thread_local bool g_timing_off = false;   // set while an entry point must not create events
+
 static bool timing_on() {
+  if (g_timing_off) return false;
   if (g_timing) return true;
   int e = g_timing_env.load();
   if (e < 0) {
@@ -590,7 +354,8 @@ static void record_timing(TimedLaunch& tl, const qtt_matrix_s* A, int k, int dt,
                           const Segment* segs, int nseg, int shape);
 
 static qtt_status_t launch_valu(const qtt_matrix_s* A, int k, int64_t nrhs, const Segment* segs, int nseg,
-                                const void* in_packed, void* out_packed, double alpha, int id, hipStream_t st) {
+                                const Segment* dsegs, const void* in_packed, void* out_packed, double alpha, int id,
+                                hipStream_t st) {
   const CoreDev& c = A->core[k];
   const bool first = (k == 0), last = (k == A->d - 1);
   ValuCfg* vc = find_valu(id);
@@ -624,62 +389,7 @@ static qtt_status_t launch_valu(const qtt_matrix_s* A, int k, int64_t nrhs, cons
   a.out_table = last ? 1 : 0;
   a.nseg = nseg;
   a.alpha = alpha;
-  for (int s = 0; s < nseg; ++s) a.seg[s] = segs[s];
-  const int nt = 64 * vc->NW;
-  const int64_t resident = (int64_t)occupancy_fn(vc->fn, nt, &vc->occ) * num_cus();
-  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(a.n_tiles, resident));
-  TimedLaunch tl;
-  const bool timed = timing_on();
-  if (timed) {
-    HIP_TRY(hipEventCreate(&tl.a));
-    HIP_TRY(hipEventCreate(&tl.b));
-    HIP_TRY(hipEventRecord(tl.a, st));
-  }
-  void* args[] = {&a};
-  HIP_TRY(hipLaunchKernel(vc->fn, dim3(grid), dim3(nt), args, 0, st));
-  if (timed) {
-    HIP_TRY(hipEventRecord(tl.b, st));
-    record_timing(tl, A, k, 0, a.ncols, segs, nseg, vc->id);
-  }
-  return QTT_OK;
-}
-
-static int heuristic_valut(const CoreDev& c) {
-  if (c.R_out <= 8) return 55;
-  if (c.R_out <= 16) return 56;
-  if (c.R_out <= 64) return 54;
-  return 52;
-}
-
-// One core of the rank-slowest FP64 sweep.
-static qtt_status_t launch_valut(const qtt_matrix_s* A, int k, int64_t nrhs, const Segment* segs, int nseg,
-                                 const void* in_packed, void* out_packed, double alpha, hipStream_t st) {
-  const CoreDev& c = A->core[k];
-  const bool first = (k == 0), last = (k == A->d - 1);
-  ValuCfg* vc = find_valut(c.tuned_t >= 0 ? c.tuned_t : heuristic_valut(c));
-  if (!vc) vc = find_valut(heuristic_valut(c));
-  ValuArgs a;
-  memset(&a, 0, sizeof(a));
-  a.M = c.valut;
-  a.in = static_cast<const double*>(in_packed);
-  a.out = static_cast<double*>(out_packed);
-  a.in_stride = c.C * c.K_in;
-  a.out_stride = c.out_len;
-  a.C = c.C;
-  a.ncols = c.C * nrhs;
-  a.R_out = c.R_out;
-  a.Rpad = c.RpadT;
-  a.K_in = c.K_in;
-  a.r_out = c.r_out;
-  const int trows = vc->NW * vc->RW;
-  a.n_row_tiles = (c.R_out + trows - 1) / trows;
-  const int64_t col_tiles = (a.ncols + 64 * vc->CPL - 1) / (64 * vc->CPL);
-  a.n_tiles = col_tiles * a.n_row_tiles;
-  a.in_table = first ? 1 : 0;
-  a.out_table = last ? 1 : 0;
-  a.nseg = nseg;
-  a.alpha = alpha;
-  for (int s = 0; s < nseg; ++s) a.seg[s] = segs[s];
+  a.seg = dsegs;
   const int nt = 64 * vc->NW;
   const int64_t resident = (int64_t)occupancy_fn(vc->fn, nt, &vc->occ) * num_cus();
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(a.n_tiles, resident));
@@ -719,8 +429,10 @@ static void record_timing(TimedLaunch& tl, const qtt_matrix_s* A, int k, int dt,
   g_timed.push_back(tl);
 }
 
+// segs: the host copy of the launch's segments (alignment checks, timing);
+// dsegs: the same table in device memory, which the kernels read.
 static qtt_status_t launch_step(const qtt_matrix_s* A, int k, int dt, int64_t nrhs,
-                                const Segment* segs, int nseg, const void* in_packed,
+                                const Segment* segs, int nseg, const Segment* dsegs, const void* in_packed,
                                 void* out_packed, double alpha, hipStream_t st) {
   const CoreDev& c = A->core[k];
   const bool first = (k == 0), last = (k == A->d - 1);
@@ -743,7 +455,7 @@ static qtt_status_t launch_step(const qtt_matrix_s* A, int k, int dt, int64_t nr
     shape = (it != g_tuned.end()) ? it->second : heuristic_shape(c.R_out, c.K_in, dt);
   }
   if (dt == 0 && is_valu_shape(shape))
-    return launch_valu(A, k, nrhs, segs, nseg, in_packed, out_packed, alpha, shape, st);
+    return launch_valu(A, k, nrhs, segs, nseg, dsegs, in_packed, out_packed, alpha, shape, st);
   // the resident BF16 kernel serves interior cores that fit it
   const bool resident_ok = dt == 2 && !first && !last && c.R_out <= 256 && c.K_in <= 256 &&
                            c.K_in % 8 == 0 && c.C % 64 == 0 && vec &&
@@ -751,27 +463,16 @@ static qtt_status_t launch_step(const qtt_matrix_s* A, int k, int dt, int64_t nr
   const bool dma_ok = resident_ok && c.Ksteps[2] <= 8 && c.R_out % 32 == 0;
   if (shape == kBf16Dma32 && !(dma_ok && c.R_out % 64 == 0)) shape = kBf16Dma;
   if (shape == kBf16Dma && !dma_ok) shape = kBf16Resident;
-  const bool f64dma_ok = dt == 0 && !first && !last && c.R_out <= 256 && c.R_out % 64 == 0 &&
-                         c.C % 64 == 0 && c.Ksteps[0] >= 4;
-  if (shape == kF64Dma && !f64dma_ok) shape = 21;
   // the 4x4x4 kernels address the fragment array with 32-bit buffer offsets
   const int64_t m_bytes =
       (int64_t)padded_row_blocks(c.nRB) * c.Ksteps[dt] * 64 * kFragE[dt] * kElemBytes[dt];
-
-  // the LDS-fed ones copy step pairs
-  if (shape >= 70 && shape < 75 && c.Ksteps[dt] % 2 != 0) shape = 60;
   if (shape == kBf16Resident && !resident_ok) shape = heuristic_shape(c.R_out, c.K_in, 1);
   const int tq = smallk_cfg(dt)->TC;
   const bool smallk_ok = first && !last && vec && c.K_in <= 16 && c.K_in % 2 == 0 && c.R_out <= 256 &&
                          c.r_out % 4 == 0 && c.C % tq == 0 && (c.r_out * tq * kElemBytes[dt]) % 16 == 0 &&
                          reinterpret_cast<uintptr_t>(out_packed) % 16 == 0;
   if (shape == kSmallK && !smallk_ok) shape = (dt == 0) ? 67 : 26;   // first-core matrix-core kernels
-  const bool lastk_ok = dt == 2 && last && !first && c.R_out <= 8 && c.K_in % 32 == 0 && c.K_in <= 256 &&
-                        reinterpret_cast<uintptr_t>(in_packed) % 16 == 0;
-  if (shape == kLastK && !lastk_ok) shape = 2;
   KernelCfg* kc = (shape == kSmallK) ? smallk_cfg(dt)
-                  : (shape == kLastK) ? lastk_cfg()
-                  : (shape == kF64Dma) ? f64_dma_cfg()
                   : (shape == kBf16Dma) ? bf16_dma_cfg()
                   : (shape == kBf16Dma32) ? bf16_dma32_cfg()
                   : (shape == kBf16Resident) ? bf16_resident_cfg()
@@ -804,7 +505,7 @@ static qtt_status_t launch_step(const qtt_matrix_s* A, int k, int dt, int64_t nr
   a.nseg = nseg;
   a.M_bytes = (int32_t)std::min<int64_t>(m_bytes, INT32_MAX);
   a.alpha = alpha;
-  for (int s = 0; s < nseg; ++s) a.seg[s] = segs[s];
+  a.seg = dsegs;
 
   const int64_t resident = (int64_t)occupancy(kc) * num_cus();
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(a.n_tiles, resident));
@@ -830,6 +531,27 @@ static qtt_status_t launch_step(const qtt_matrix_s* A, int k, int dt, int64_t nr
 // ---------------------------------------------------------------------------
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Every apply workspace starts with two segment tables of kMaxSeg entries:
+// the sweep's and the diagonal passes' (the two are live at the same time).
+static constexpr size_t kSegTableBytes = 2 * kMaxSeg * sizeof(Segment);
+static Segment* sweep_table(void* ws) { return static_cast<Segment*>(ws); }
+static Segment* diag_table(void* ws) { return static_cast<Segment*>(ws) + kMaxSeg; }
+static void* sweep_buffers(void* ws) { return static_cast<char*>(ws) + kSegTableBytes; }
+
+// Write nseg host segments into a device table (captured with the sweep).
+static qtt_status_t write_segments(const Segment* segs, int nseg, Segment* table, hipStream_t st) {
+  for (int s0 = 0; s0 < nseg; s0 += kSegChunk) {
+    SegWriteArgs wa;
+    memset(&wa, 0, sizeof(wa));
+    wa.dst = table + s0;
+    wa.n = std::min(kSegChunk, nseg - s0);
+    for (int t = 0; t < wa.n; ++t) wa.seg[t] = segs[s0 + t];
+    void* args[] = {&wa};
+    HIP_TRY(hipLaunchKernel(reinterpret_cast<const void*>(&seg_write_kernel), dim3(1), dim3(64), args, 0, st));
+  }
+  return QTT_OK;
+}
+
 static size_t wave_buffer_bytes(const qtt_matrix_s* A, int dt, int64_t nrhs) {
   return align256((size_t)A->max_inter * kElemBytes[dt] * (size_t)nrhs);
 }
@@ -843,14 +565,15 @@ static size_t diag_scratch_bytes(const qtt_matrix_s* A, int64_t nrhs) {
 // workspace of one wave of nrhs vectors: the sweep's two buffers, then the
 // diagonal scratch
 static size_t wave_total_bytes(const qtt_matrix_s* A, int dt, int64_t nrhs) {
-  return (A->d > 1 ? 2 * wave_buffer_bytes(A, dt, nrhs) : 0) + diag_scratch_bytes(A, nrhs);
+  return kSegTableBytes + (A->d > 1 ? 2 * wave_buffer_bytes(A, dt, nrhs) : 0) + diag_scratch_bytes(A, nrhs);
 }
 
 static int64_t wave_capacity(const qtt_matrix_s* A, int dt, size_t ws_bytes) {
   const size_t per = (A->d > 1 ? 2 * (size_t)A->max_inter * kElemBytes[dt] : 0)
                      + (A->has_diag ? (size_t)(A->rows + A->cols) * 8 : 0);
+  if (ws_bytes < kSegTableBytes) return 0;
   if (per == 0) return INT64_MAX;
-  int64_t w = (int64_t)(ws_bytes / per);
+  int64_t w = (int64_t)((ws_bytes - kSegTableBytes) / per);
   while (w > 0 && wave_total_bytes(A, dt, w) > ws_bytes) --w;
   return w;
 }
@@ -880,19 +603,8 @@ static bool pair_ok(const qtt_matrix_s* A, int dt, int k, const Segment* segs, i
       if (reinterpret_cast<uintptr_t>(segs[s].x) % 16 != 0 || segs[s].ldx % 2 != 0) return false;
   return true;
 }
-// RA = 24 and 32 exact; "RA = 33" stands for the padded 256-row kernel
-template <int RA, int WRB, bool FIRST>
-static const void* pair_fn() {
-  constexpr int R = RA > 32 ? 32 : RA;
-  return reinterpret_cast<const void*>(&core_pair_f64q_kernel<R, WRB, FIRST, FIRST ? 8 : 32, 4, (RA > 32)>);
-}
-template <int RA, int WRB, bool FIRST>
-static const void* pair32_fn() {
-  constexpr int R = RA > 32 ? 32 : RA;
-  return reinterpret_cast<const void*>(&core_pair_f32_kernel<R, WRB, FIRST, FIRST ? 8 : 32, 4, (RA > 32)>);
-}
 static qtt_status_t launch_pair(const qtt_matrix_s* A, int dt, int k, int64_t nrhs, const Segment* segs,
-                                int nseg, const void* in, void* out, hipStream_t st) {
+                                int nseg, const Segment* dsegs, const void* in, void* out, hipStream_t st) {
   const CoreDev& x = A->core[k];
   const CoreDev& y = A->core[k + 1];
   const bool first = (k == 0);
@@ -916,19 +628,18 @@ static qtt_status_t launch_pair(const qtt_matrix_s* A, int dt, int k, int64_t nr
   a.MB_bytes = (int32_t)frag_bytes(y, dt);
   a.nseg = first ? nseg : 0;
   a.ra = x.r_out;
-  for (int s = 0; s < a.nseg; ++s) a.seg[s] = segs[s];
+  a.seg = dsegs;
   // instantiation: rank of the fused boundary, rows of step k + 1, first core
   // index: 12 dt + 6 first + 2 (0: rank 24, 1: rank 32, 2: padded 17..32) + (rows of core k + 1 > 192)
   static int occ[24] = {};
-  static const void* fns[24] = {
-      pair_fn<24, 3, false>(),   pair_fn<24, 4, false>(),   pair_fn<32, 3, false>(),   pair_fn<32, 4, false>(),
-      pair_fn<33, 3, false>(),   pair_fn<33, 4, false>(),
-      pair_fn<24, 3, true>(),    pair_fn<24, 4, true>(),    pair_fn<32, 3, true>(),    pair_fn<32, 4, true>(),
-      pair_fn<33, 3, true>(),    pair_fn<33, 4, true>(),
-      pair32_fn<24, 3, false>(), pair32_fn<24, 4, false>(), pair32_fn<32, 3, false>(), pair32_fn<32, 4, false>(),
-      pair32_fn<33, 3, false>(), pair32_fn<33, 4, false>(),
-      pair32_fn<24, 3, true>(),  pair32_fn<24, 4, true>(),  pair32_fn<32, 3, true>(),  pair32_fn<32, 4, true>(),
-      pair32_fn<33, 3, true>(),  pair32_fn<33, 4, true>()};
+  static const void* fns[24] = {};
+  static std::once_flag fns_once;
+  std::call_once(fns_once, [] {
+    for (int i = 0; i < 12; ++i) {
+      fns[i] = pair_f64_kernel(i);
+      fns[12 + i] = pair_f32_kernel(i);
+    }
+  });
   const int rk = (x.r_out == 24) ? 0 : (x.r_out == 32 ? 1 : 2);
   const int f = (dt == 1 ? 12 : 0) + (first ? 6 : 0) + 2 * rk + (y.R_out > 192 ? 1 : 0);
   // timing id: exact rank 24, else the 256-row kernels (exact or padded)
@@ -956,38 +667,25 @@ static qtt_status_t launch_pair(const qtt_matrix_s* A, int dt, int k, int64_t nr
   return QTT_OK;
 }
 
-// Whether X allows the rank-slowest sweep (16-byte aligned columns).
-static bool tsweep_usable_mode_free(const qtt_matrix_s* A, const double* X, int64_t ldx) {
-  (void)A;
-  return reinterpret_cast<uintptr_t>(X) % 16 == 0 && ldx % 2 == 0;
-}
-
-// The rank-slowest FP64 sweep reads X with 16-byte loads per lane column.
-static bool tsweep_usable(const qtt_matrix_s* A, int dt, const Segment* segs, int nseg) {
-  if (dt != 0 || !A->fp64_t || !A->fp64_t_ok) return false;
-  for (int s = 0; s < nseg; ++s)
-    if (reinterpret_cast<uintptr_t>(segs[s].x) % 16 != 0 || segs[s].ldx % 2 != 0) return false;
-  return true;
-}
-
 static qtt_status_t sweep(const qtt_matrix_s* A, int dt, int64_t nrhs, const Segment* segs, int nseg,
                           void* ws, double alpha, hipStream_t st) {
-  void* buf[2] = {ws, nullptr};
-  if (A->d > 1) buf[1] = static_cast<char*>(ws) + wave_buffer_bytes(A, dt, nrhs);
-  const bool tsw = tsweep_usable(A, dt, segs, nseg);
+  Segment* dsegs = sweep_table(ws);
+  qtt_status_t s0 = write_segments(segs, nseg, dsegs, st);
+  if (s0 != QTT_OK) return s0;
+  void* buf[2] = {sweep_buffers(ws), nullptr};
+  if (A->d > 1) buf[1] = static_cast<char*>(buf[0]) + wave_buffer_bytes(A, dt, nrhs);
   int cur = 0;  // buffer holding the latest intermediate (core 0 writes buf[0])
   for (int k = 0; k < A->d;) {
     const void* in = (k == 0) ? nullptr : buf[cur];
-    if (!tsw && pair_ok(A, dt, k, segs, nseg)) {
-      qtt_status_t s = launch_pair(A, dt, k, nrhs, segs, nseg, in, buf[cur ^ 1], st);
+    if (pair_ok(A, dt, k, segs, nseg)) {
+      qtt_status_t s = launch_pair(A, dt, k, nrhs, segs, nseg, dsegs, in, buf[cur ^ 1], st);
       if (s != QTT_OK) return s;
       cur ^= 1;
       k += 2;
       continue;
     }
     void* out = (k == A->d - 1) ? nullptr : (k == 0 ? buf[0] : buf[cur ^ 1]);
-    qtt_status_t s = tsw ? launch_valut(A, k, nrhs, segs, nseg, in, out, alpha, st)
-                         : launch_step(A, k, dt, nrhs, segs, nseg, in, out, alpha, st);
+    qtt_status_t s = launch_step(A, k, dt, nrhs, segs, nseg, dsegs, in, out, alpha, st);
     if (s != QTT_OK) return s;
     if (k > 0) cur ^= 1;
     ++k;
@@ -1062,13 +760,17 @@ static qtt_status_t sweep_graph(const qtt_matrix_s* A, int dt, int64_t nrhs, con
 // The scratch sits after the sweep buffers of a full wave (cap vectors), so
 // it never overlaps the buffers of this wave.
 static qtt_status_t diag_sweep(const qtt_matrix_s* A, int dt, int64_t nrhs, int64_t cap,
-                               const std::vector<Segment>& segs, void* ws, double alpha, hipStream_t st) {
-  char* base = static_cast<char*>(ws) + (A->d > 1 ? 2 * wave_buffer_bytes(A, dt, cap) : 0);
+                               const std::vector<Segment>& segs, void* ws, double alpha, hipStream_t st,
+                               bool use_graph) {
+  char* base = static_cast<char*>(sweep_buffers(ws)) + (A->d > 1 ? 2 * wave_buffer_bytes(A, dt, cap) : 0);
   double* S1 = reinterpret_cast<double*>(base);
   double* S2 = reinterpret_cast<double*>(base + align256((size_t)A->cols * 8 * cap));
   DiagArgs da;
   memset(&da, 0, sizeof(da));
-  for (size_t i = 0; i < segs.size(); ++i) da.seg[i] = segs[i];
+  Segment* dtab = diag_table(ws);
+  qtt_status_t sw = write_segments(segs.data(), (int)segs.size(), dtab, st);
+  if (sw != QTT_OK) return sw;
+  da.seg = dtab;
   da.nseg = (int32_t)segs.size();
   da.ncol = nrhs;
   auto grid = [&](int64_t rows) {
@@ -1088,7 +790,8 @@ static qtt_status_t diag_sweep(const qtt_matrix_s* A, int dt, int64_t nrhs, int6
   one.ldy = A->rows;
   one.ldz = 0;
   one.rhs_begin = 0;
-  qtt_status_t s = sweep_graph(A, dt, nrhs, &one, 1, ws, 1.0, st);
+  qtt_status_t s = use_graph ? sweep_graph(A, dt, nrhs, &one, 1, ws, 1.0, st)
+                             : sweep(A, dt, nrhs, &one, 1, ws, 1.0, st);
   if (s != QTT_OK) return s;
   da.rows = A->rows;
   da.d = A->diag_b;
@@ -1108,9 +811,11 @@ struct Block {
 };
 
 // Run y = z + alpha * A x over blocks, in waves bounded by the workspace and
-// by the segment-table size.
+// by the segment-table size.  use_graph = false launches every sweep directly
+// (no graph capture or instantiation, which allocate).
 static qtt_status_t run_blocks(const qtt_matrix_s* A, int dt, const std::vector<Block>& blocks,
-                               void* ws, size_t ws_bytes, double alpha, hipStream_t st) {
+                               void* ws, size_t ws_bytes, double alpha, hipStream_t st,
+                               bool use_graph = true) {
   int64_t total = 0;
   for (auto& b : blocks) total += b.width;
   if (total == 0) return QTT_OK;
@@ -1123,8 +828,9 @@ static qtt_status_t run_blocks(const qtt_matrix_s* A, int dt, const std::vector<
   int64_t in_wave = 0;
   auto flush = [&]() -> qtt_status_t {
     if (in_wave == 0) return QTT_OK;
-    qtt_status_t s = A->has_diag ? diag_sweep(A, dt, in_wave, cap, segs, ws, alpha, st)
-                                 : sweep_graph(A, dt, in_wave, segs.data(), (int)segs.size(), ws, alpha, st);
+    qtt_status_t s = A->has_diag ? diag_sweep(A, dt, in_wave, cap, segs, ws, alpha, st, use_graph)
+                     : use_graph ? sweep_graph(A, dt, in_wave, segs.data(), (int)segs.size(), ws, alpha, st)
+                                 : sweep(A, dt, in_wave, segs.data(), (int)segs.size(), ws, alpha, st);
     segs.clear();
     in_wave = 0;
     return s;
@@ -1237,11 +943,8 @@ qtt_status_t qtt_matrix_load(int32_t d, const int64_t* ranks, const int64_t* m, 
     for (int t = 0; t < 3; ++t) { c.frag[t] = nullptr; c.Ksteps[t] = 0; c.tuned[t] = -1; }
     c.valu = nullptr;
     c.valu1 = nullptr;
-    c.valut = nullptr;
     c.g64 = nullptr;
     c.Rpad = 0;
-    c.RpadT = 0;
-    c.tuned_t = -1;
     if (k < d - 1) A->max_inter = std::max(A->max_inter, c.out_len);
   }
 
@@ -1294,7 +997,7 @@ qtt_status_t qtt_matrix_load(int32_t d, const int64_t* ranks, const int64_t* m, 
         e = hipMemcpy(dptr, f.data(), bytes, hipMemcpyHostToDevice);
       } else {
         std::vector<uint16_t> b(nel);
-        for (size_t i = 0; i < nel; ++i) b[i] = f32_to_bf16_rne((float)h[i]);
+        for (size_t i = 0; i < nel; ++i) b[i] = f64_to_bf16_rne(h[i]);
         e = hipMemcpy(dptr, b.data(), bytes, hipMemcpyHostToDevice);
       }
       if (e != hipSuccess) {
@@ -1352,36 +1055,6 @@ qtt_status_t qtt_matrix_load(int32_t d, const int64_t* ranks, const int64_t* m, 
       }
     }
   }
-  // FP64 copy for the rank-slowest sweep: Mt[(a * RpadT + row) * 8 + j] = M_k(row, a + r_{k-1} j)
-  if (dtypes & QTT_FP64) {
-    bool ok = true;
-    for (int k = 0; k < d; ++k) ok = ok && m[k] == 8 && n[k] == 8;
-    A->fp64_t_ok = ok;
-    for (int k = 0; k < d && ok; ++k) {
-      CoreDev& c = A->core[k];
-      const double* G = cores[k];
-      c.RpadT = valut_padded_rows(c.R_out);
-      const size_t nel = (size_t)c.r_in * c.RpadT * 8;
-      std::vector<double> h(nel, 0.0);
-      for (int ap = 0; ap < c.r_in; ++ap)
-        for (int row = 0; row < c.R_out; ++row)
-          for (int jk = 0; jk < 8; ++jk) {
-            const int ak = row % c.r_out, ik = row / c.r_out;
-            h[((size_t)ap * c.RpadT + row) * 8 + jk] = G[(((size_t)ap * c.m + ik) * c.n + jk) * c.r_out + ak];
-          }
-      void* dptr = nullptr;
-      if (hipMalloc(&dptr, std::max<size_t>(nel * 8, 256)) != hipSuccess) {
-        qtt_matrix_free(A);
-        return fail(QTT_ERR_OUT_OF_MEMORY, "hipMalloc for the rank-slowest copy of core %d failed", k);
-      }
-      c.valut = static_cast<double*>(dptr);
-      hipError_t er = hipMemcpy(dptr, h.data(), nel * 8, hipMemcpyHostToDevice);
-      if (er != hipSuccess) {
-        qtt_matrix_free(A);
-        return fail(QTT_ERR_DEVICE, "hipMemcpy of core %d failed: %s", k, hipGetErrorString(er));
-      }
-    }
-  }
   *out = A;
   return QTT_OK;
 }
@@ -1397,7 +1070,6 @@ qtt_status_t qtt_matrix_free(qtt_matrix_t A) {
       if (c.frag[t]) (void)hipFree(c.frag[t]);
     if (c.valu) (void)hipFree(c.valu);
     if (c.valu1) (void)hipFree(c.valu1);
-    if (c.valut) (void)hipFree(c.valut);
     if (c.g64) (void)hipFree(c.g64);
   }
   delete A;
@@ -1520,7 +1192,11 @@ qtt_status_t qtt_autotune(qtt_matrix_t A, qtt_dtype_t compute, int64_t nrhs, con
   const int64_t w = std::min<int64_t>(nrhs, cap);
   Segment sg;
   sg.x = X; sg.y = Y; sg.z = nullptr; sg.ldx = ldx; sg.ldy = ldy; sg.ldz = 0; sg.rhs_begin = 0;
-  void* buf[2] = {ws, (A->d > 1) ? static_cast<char*>(ws) + wave_buffer_bytes(A, dt, w) : nullptr};
+  void* b0 = sweep_buffers(ws);
+  void* buf[2] = {b0, (A->d > 1) ? static_cast<char*>(b0) + wave_buffer_bytes(A, dt, w) : nullptr};
+  Segment* dsegs = sweep_table(ws);
+  s = write_segments(&sg, 1, dsegs, st);
+  if (s != QTT_OK) return s;
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
@@ -1539,9 +1215,7 @@ qtt_status_t qtt_autotune(qtt_matrix_t A, qtt_dtype_t compute, int64_t nrhs, con
       ids.push_back(kBf16Dma);
       ids.push_back(kBf16Dma32);
     }
-    if (dt == 0 && k > 0 && k < A->d - 1) ids.push_back(kF64Dma);
     if (k == 0 && A->d > 1) ids.push_back(kSmallK);
-    if (dt == 2 && k == A->d - 1 && k > 0) ids.push_back(kLastK);
     if (dt == 0)
       for (auto& vc : valu_registry())
         if (vc.G == 1 || c.K_in % vc.G == 0) ids.push_back(vc.id);
@@ -1550,7 +1224,7 @@ qtt_status_t qtt_autotune(qtt_matrix_t A, qtt_dtype_t compute, int64_t nrhs, con
       for (int rep = 0; rep < 2; ++rep) {           // warm-up + timed
         HIP_TRY(hipEventRecord(e0, st));
         for (int it = 0; it < 3; ++it) {
-          s = launch_step(A, k, dt, w, &sg, 1, in, out, 1.0, st);
+          s = launch_step(A, k, dt, w, &sg, 1, dsegs, in, out, 1.0, st);
           if (s != QTT_OK) { g_timing = was_timing; return s; }
         }
         HIP_TRY(hipEventRecord(e1, st));
@@ -1567,58 +1241,7 @@ qtt_status_t qtt_autotune(qtt_matrix_t A, qtt_dtype_t compute, int64_t nrhs, con
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tuned[std::make_tuple(dt, c.R_out, c.K_in, c.r_out, c.C)] = best_id;
   }
-  // FP64: also tune the rank-slowest vector-ALU sweep, then keep whichever
-  // whole sweep is faster
-  if (dt == 0 && A->fp64_t_ok && tsweep_usable_mode_free(A, X, ldx)) {
-    const bool was_t = A->fp64_t;
-    for (int k = 0; k < A->d; ++k) {
-      CoreDev& c = A->core[k];
-      const void* in = (k == 0) ? nullptr : buf[(k - 1) & 1];
-      void* out = (k == A->d - 1) ? nullptr : buf[k & 1];
-      float best = 1e30f;
-      int best_id = -1;
-      for (auto& vc : valut_registry()) {
-        c.tuned_t = vc.id;
-        for (int rep = 0; rep < 2; ++rep) {
-          HIP_TRY(hipEventRecord(e0, st));
-          for (int it = 0; it < 3; ++it) {
-            s = launch_valut(A, k, w, &sg, 1, in, out, 1.0, st);
-            if (s != QTT_OK) { g_timing = was_timing; return s; }
-          }
-          HIP_TRY(hipEventRecord(e1, st));
-        }
-        HIP_TRY(hipEventSynchronize(e1));
-        float ms = 0;
-        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-        if (tune_log())
-          fprintf(stderr, "qtt_autotune dtype 0 core %d (%d x %d, %lld cols) shape %d: %.4f ms\n", k,
-                  c.R_out, c.K_in, (long long)(c.C * w), vc.id, ms / 3);
-        if (ms < best) { best = ms; best_id = vc.id; }
-      }
-      c.tuned_t = best_id;
-    }
-    float ms_mode[3] = {0, 0, 0};
-    for (int mode = 0; mode < 3; ++mode) {
-      A->fp64_t = (mode == 2);
-      A->fp64_pair = (mode == 1);
-      for (int rep = 0; rep < 2; ++rep) {
-        HIP_TRY(hipEventRecord(e0, st));
-        for (int it = 0; it < 2; ++it) {
-          s = sweep(A, dt, w, &sg, 1, ws, 1.0, st);
-          if (s != QTT_OK) { g_timing = was_timing; A->fp64_t = was_t; return s; }
-        }
-        HIP_TRY(hipEventRecord(e1, st));
-      }
-      HIP_TRY(hipEventSynchronize(e1));
-      HIP_TRY(hipEventElapsedTime(&ms_mode[mode], e0, e1));
-    }
-    const int best = (ms_mode[1] < ms_mode[0]) ? (ms_mode[2] < ms_mode[1] ? 2 : 1) : (ms_mode[2] < ms_mode[0] ? 2 : 0);
-    A->fp64_t = (best == 2);
-    A->fp64_pair = (best == 1);
-    if (tune_log())
-      fprintf(stderr, "qtt_autotune dtype 0 whole sweep: standard %.4f ms, fused pairs %.4f ms, rank-slowest %.4f ms\n",
-              ms_mode[0] / 2, ms_mode[1] / 2, ms_mode[2] / 2);
-  } else if (dt <= 1) {
+  if (dt <= 1) {
     // fused pairs against the standard sweep
     bool& pair = (dt == 0) ? A->fp64_pair : A->fp32_pair;
     float ms_mode[2] = {0, 0};
@@ -1651,19 +1274,14 @@ qtt_status_t qtt_autotune(qtt_matrix_t A, qtt_dtype_t compute, int64_t nrhs, con
   return QTT_OK;
 }
 
-static const int kTSweepMode = 50;
-
 qtt_status_t qtt_list_shapes(qtt_dtype_t compute, int32_t* ids, int32_t cap, int32_t* count) {
   const int dt = dt_index(compute);
   if (dt < 0 || !count || (cap > 0 && !ids)) return fail(QTT_ERR_INVALID_ARG, "bad arguments");
   std::vector<int> v = shape_ids(dt, dt == 0);
   v.push_back(kSmallK);
-  if (dt == 2) { v.push_back(kBf16Resident); v.push_back(kBf16Dma); v.push_back(kBf16Dma32); v.push_back(kLastK); }
-  if (dt == 0) {
-    v.push_back(kF64Dma);
+  if (dt == 2) { v.push_back(kBf16Resident); v.push_back(kBf16Dma); v.push_back(kBf16Dma32); }
+  if (dt == 0)
     for (auto& vc : valu_registry()) v.push_back(vc.id);
-    for (auto& vc : valut_registry()) v.push_back(vc.id);
-  }
   *count = (int32_t)v.size();
   for (int i = 0; i < (int)v.size() && i < cap; ++i) ids[i] = v[i];
   return QTT_OK;
@@ -1680,20 +1298,7 @@ qtt_status_t qtt_set_shape(qtt_matrix_t A, qtt_dtype_t compute, int32_t core, in
     drop_graphs(A);
     return QTT_OK;
   }
-  if (core == -1) {               // whole-sweep mode (FP64): rank-slowest layout on/off
-    if (dt != 0 || (shape != -1 && shape != kTSweepMode)) return fail(QTT_ERR_INVALID_ARG, "core -1 takes shape %d or -1 (FP64)", kTSweepMode);
-    if (shape == kTSweepMode && !A->fp64_t_ok) return fail(QTT_ERR_SHAPE, "the rank-slowest sweep needs every mode size to be 8");
-    A->fp64_t = (shape == kTSweepMode);
-    drop_graphs(A);
-    return QTT_OK;
-  }
   if (core < 0 || core >= A->d) return fail(QTT_ERR_INVALID_ARG, "core %d out of range", core);
-  if (dt == 0 && shape >= 50 && shape < 60) {
-    if (!find_valut(shape)) return fail(QTT_ERR_INVALID_ARG, "unknown shape %d", shape);
-    A->core[core].tuned_t = shape;
-    drop_graphs(A);
-    return QTT_OK;
-  }
   if (shape != -1) {
     int32_t ids[128], n = 0;
     qtt_list_shapes(compute, ids, 128, &n);
@@ -1736,13 +1341,13 @@ qtt_status_t qtt_solve_workspace_bytes(qtt_matrix_t A, qtt_matrix_t Ainv, qtt_dt
 static qtt_status_t column_norms(const std::vector<const double*>& cols, const std::vector<int64_t>& lds_,
                                  int64_t N, double* partial, double* dnorm, std::vector<double>& host,
                                  hipStream_t st) {
-  // one launch per kMaxSeg columns (each column is its own segment)
+  // one launch per kNormCols columns (each column is its own segment)
   const int ncol = (int)cols.size();
   host.assign(ncol, 0.0);
-  for (int c0 = 0; c0 < ncol; c0 += kMaxSeg) {
+  for (int c0 = 0; c0 < ncol; c0 += kNormCols) {
     NormArgs na;
     memset(&na, 0, sizeof(na));
-    const int nc = std::min(kMaxSeg, ncol - c0);
+    const int nc = std::min(kNormCols, ncol - c0);
     for (int t = 0; t < nc; ++t) {
       na.R[t] = cols[c0 + t];
       na.ld[t] = lds_[c0 + t];
@@ -1814,13 +1419,20 @@ qtt_status_t qtt_solve(qtt_matrix_t A, qtt_matrix_t Ainv, qtt_dtype_t inv_comput
   std::vector<double> fn, rn;
   s = column_norms(fcols, fld, N, partial, dnorm, fn, st);
   if (s != QTT_OK) return s;
-  for (int64_t c = 0; c < nrhs; ++c) {
-    if (!std::isfinite(fn[c])) return fail(QTT_ERR_NONFINITE, "column %lld of F is not finite", (long long)c);
-    if (info) { info[c].iters = 0; info[c].rel_residual = (fn[c] > 0) ? 1.0 : 0.0; }
-  }
-  // columns still iterating; a converged column is frozen
+  // columns still iterating; a converged column is frozen, and so is a column
+  // whose F or residual is not finite (the others go on: columns never mix)
   std::vector<char> active(nrhs, 1);
   int64_t n_active = nrhs;
+  int64_t first_bad = -1;
+  for (int64_t c = 0; c < nrhs; ++c) {
+    if (info) { info[c].iters = 0; info[c].rel_residual = (fn[c] > 0) ? 1.0 : 0.0; }
+    if (!std::isfinite(fn[c])) {
+      if (info) info[c].rel_residual = fn[c];
+      if (first_bad < 0) first_bad = c;
+      active[c] = 0;
+      --n_active;
+    }
+  }
   std::vector<int> iters(nrhs, 0);
   for (int it = 1; it <= max_iter && n_active > 0; ++it) {
     // runs of consecutive active columns
@@ -1856,10 +1468,17 @@ qtt_status_t qtt_solve(qtt_matrix_t A, qtt_matrix_t Ainv, qtt_dtype_t inv_comput
       iters[c] = it;
       const double rel = (fn[c] > 0) ? rn[t] / fn[c] : rn[t];
       if (info) { info[c].iters = it; info[c].rel_residual = rel; }
-      if (!std::isfinite(rel)) return fail(QTT_ERR_NONFINITE, "residual of column %lld is not finite", (long long)c);
+      if (!std::isfinite(rel)) {
+        if (first_bad < 0) first_bad = c;
+        active[c] = 0;
+        --n_active;
+        continue;
+      }
       if (rel <= rtol) { active[c] = 0; --n_active; }
     }
   }
+  if (first_bad >= 0)
+    return fail(QTT_ERR_NONFINITE, "column %lld: F or its residual is not finite", (long long)first_bad);
   if (n_active > 0) return fail(QTT_ERR_NOT_CONVERGED, "%lld columns above rtol after %d passes", (long long)n_active, max_iter);
   return QTT_OK;
 }
@@ -2063,9 +1682,14 @@ static qtt_status_t fgmres_impl(qtt_matrix_t A, qtt_matrix_t Ainv, qtt_matrix_t 
   if (s != QTT_OK) return s;
   std::vector<int64_t> act, zero;
   std::vector<double> relv(nrhs, 0.0);
+  int64_t first_bad = -1;   // columns whose F is not finite are skipped (Sigma not written)
   for (int64_t c = 0; c < nrhs; ++c) {
-    if (!std::isfinite(beta[c])) return fail(QTT_ERR_NONFINITE, "column %lld of F is not finite", (long long)c);
     if (info) { info[c].iters = 0; info[c].rel_residual = 0.0; }
+    if (!std::isfinite(beta[c])) {
+      if (info) info[c].rel_residual = beta[c];
+      if (first_bad < 0) first_bad = c;
+      continue;
+    }
     (beta[c] > 0 ? act : zero).push_back(c);
   }
   // zero right-hand sides: sigma = 0
@@ -2230,6 +1854,7 @@ static qtt_status_t fgmres_impl(qtt_matrix_t A, qtt_matrix_t Ainv, qtt_matrix_t 
   int64_t above = 0;
   for (int64_t c = 0; c < nrhs; ++c) above += (relv[c] > rtol);
   HIP_TRY(hipStreamSynchronize(st));
+  if (first_bad >= 0) return fail(QTT_ERR_NONFINITE, "column %lld of F is not finite", (long long)first_bad);
   if (above > 0) return fail(QTT_ERR_NOT_CONVERGED, "%lld columns above rtol after %d steps", (long long)above, M);
   return QTT_OK;
 }

@@ -12,6 +12,7 @@ raises if it has not been built (``python -m paper_1511_06029_amd.build_lib``).
 from __future__ import annotations
 
 import ctypes
+import functools
 import os
 
 import numpy as np
@@ -109,6 +110,19 @@ def _dtype(compute):
     if isinstance(compute, str):
         return DTYPES[compute]
     return int(compute)
+
+
+def _on_stream(fn):
+    """Run a wrapper with its stream argument resolved and made torch's
+    current stream, so that the temporaries it allocates (workspaces, and
+    outputs it creates) belong to the stream the library enqueues on: the
+    caching allocator then reuses their memory only behind that work."""
+    @functools.wraps(fn)
+    def wrapper(*args, stream=None, **kw):
+        s = torch.cuda.current_stream() if stream is None else stream
+        with torch.cuda.stream(s):
+            return fn(*args, stream=s, **kw)
+    return wrapper
 
 
 def _stream(stream):
@@ -232,6 +246,7 @@ def workspace(nbytes, device="cuda"):
     return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
 
 
+@_on_stream
 def qtt_apply(A, compute, X, Y=None, ws=None, stream=None):
     """Y = A X; returns Y (allocated column-major when not given)."""
     xp, n, k, ldx = _col_major(X, "X")
@@ -247,6 +262,7 @@ def qtt_apply(A, compute, X, Y=None, ws=None, stream=None):
     return Y
 
 
+@_on_stream
 def qtt_apply_batched(A, compute, Xs, Ys=None, ws=None, stream=None):
     """Y_b = A X_b for a list of uneven column-major blocks; returns the list Ys."""
     nb = len(Xs)
@@ -269,6 +285,7 @@ def qtt_apply_batched(A, compute, Xs, Ys=None, ws=None, stream=None):
     return Ys
 
 
+@_on_stream
 def qtt_autotune(A, compute, X, Y, ws, stream=None):
     xp, n, k, ldx = _col_major(X, "X")
     yp, m, _, ldy = _col_major(Y, "Y")
@@ -276,6 +293,7 @@ def qtt_autotune(A, compute, X, Y, ws, stream=None):
                              ws.numel() * ws.element_size(), _stream(stream)))
 
 
+@_on_stream
 def qtt_solve(A, Ainv, inv_compute, F, Sigma=None, rtol=1e-8, max_iter=50, ws=None, stream=None,
               raise_on_fail=True):
     """Refined solve A Sigma = F; returns (Sigma, info, status) with info a list of
@@ -303,6 +321,7 @@ def qtt_fgmres_workspace_bytes(A, Ainv, inv_compute, nrhs, max_iter):
     return n.value
 
 
+@_on_stream
 def qtt_solve_fgmres(A, Ainv, inv_compute, F, Sigma=None, rtol=1e-8, max_iter=30, ws=None, stream=None,
                      raise_on_fail=True):
     """Flexible GMRES solve A Sigma = F, Ainv (or None) the right
@@ -325,6 +344,7 @@ def qtt_solve_fgmres(A, Ainv, inv_compute, F, Sigma=None, rtol=1e-8, max_iter=30
     return Sigma, [(c.iters, c.rel_residual) for c in info], st
 
 
+@_on_stream
 def qtt_matvec_compressed(A, Bcores, Ccores=None, stream=None):
     """Cores of c = A b for a batch of TT vectors (section 4.2).  Bcores[k]:
     contiguous FP64 CUDA tensor (nvec, rb_k, n_k, rb_{k+1}).  Returns the list
@@ -347,6 +367,7 @@ def qtt_matvec_compressed(A, Bcores, Ccores=None, stream=None):
     return Ccores
 
 
+@_on_stream
 def qtt_solve_fgmres_product(A, M, Y, inv_compute, F, Sigma=None, rtol=1e-8, max_iter=30, ws=None,
                              stream=None, raise_on_fail=True):
     """Flexible GMRES with the product preconditioner z = M (Y v); returns

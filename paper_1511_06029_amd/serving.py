@@ -190,6 +190,7 @@ class SolveServer:
         for A, Ai in self.ops.values():
             A.free()
             Ai.free()
+        self.arena = None            # the budget's device memory goes back to torch
 
     # ------------------------------------------------------------ scheduling
     def _take_batch(self):
@@ -240,6 +241,12 @@ class SolveServer:
                     r.status, r.done, r.admitted, r.batch_id = -2, t, t_adm, bid
                     r.error = repr(e)
             finally:
+                # nothing queued on the slot stream may still use the region
+                # when it goes back to the arena (also after a failed batch)
+                try:
+                    stream.synchronize()
+                except Exception:
+                    pass
                 with self._lock:
                     self.arena.release(*region)
                     self._in_use -= region[1]
@@ -323,11 +330,60 @@ def summarize(requests):
             "iters_max": max((c[0] for r in requests for c in r.info), default=0)}
 
 
+def serving_operators(n_ops=12, levels=(5, 6, 7, 8), seed=51):
+    """The serving workload's resident operators: {name: (A_cores, Ainv_cores)}
+    and their descriptions (L, ranks)."""
+    from . import inputs as I
+    descs = I.serving_operators(n_ops, levels=levels, seed=seed)
+    operators = {}
+    for t, dsc in enumerate(descs):
+        A, Ai = I.perturbed_identity_pair(dsc["ranks"], [8] * dsc["L"], seed=dsc["seed"], eps=0.1)
+        operators[f"op{t}"] = (A, Ai)
+    return operators, descs
+
+
+def serving_trace(server, descs, n_requests, rate, seed=51, k_max=16, device="cuda"):
+    """Run a seeded Poisson trace on a server: request i picks an operator and
+    k in [1, k_max] from a seeded generator; its right-hand sides are drawn
+    N(0,1) on the device from a seeded torch generator.  Returns the summary
+    of summarize(), plus per-L latency percentiles and the largest relative
+    residual ||F - A Sigma|| / ||F|| recomputed by a separate FP64 apply."""
+    from . import inputs as I
+    g = I.rng(seed + 1)
+    arrivals = I.poisson_arrivals(n_requests, rate, seed=seed + 2)
+    tg = torch.Generator(device=device).manual_seed(seed * 7919)
+    reqs = []
+    for i in range(n_requests):
+        t = int(g.integers(len(descs)))
+        k = int(g.integers(1, k_max + 1))
+        N = 8 ** descs[t]["L"]
+        F = torch.randn((k, N), generator=tg, device=device, dtype=torch.float64).t()
+        reqs.append(Request(rid=i, op=f"op{t}", F=F, arrival=float(arrivals[i])))
+    torch.cuda.synchronize()
+    stats = server.run_trace(reqs)
+    by_L = {}
+    for r in reqs:
+        by_L.setdefault(descs[int(r.op[2:])]["L"], []).append(r.latency * 1e3)
+    stats["latency_by_L_ms"] = {str(L): {"requests": len(v), "p50": float(np.percentile(v, 50)),
+                                         "p99": float(np.percentile(v, 99))}
+                                for L, v in sorted(by_L.items())}
+    worst = 0.0
+    for r in reqs:
+        if r.Sigma is None:
+            continue
+        A, _ = server.ops[r.op]
+        AS = Q.qtt_apply(A, "fp64", r.Sigma.reshape(A.rows, -1))
+        res = (r.F.reshape(A.rows, -1) - AS).norm(dim=0) / r.F.reshape(A.rows, -1).norm(dim=0)
+        worst = max(worst, float(res.max()))
+        r.Sigma = None
+    stats["max_rel_residual_recomputed"] = worst
+    return stats
+
+
 def _main():
     """Serving benchmark: a seeded Poisson trace over resident operators."""
     import argparse
     import json
-    from . import inputs as I
     p = argparse.ArgumentParser()
     p.add_argument("--requests", type=int, default=48)
     p.add_argument("--rate", type=float, default=200.0)
@@ -339,24 +395,10 @@ def _main():
     p.add_argument("--seed", type=int, default=51)
     args = p.parse_args()
     levels = tuple(int(x) for x in args.levels.split(","))
-    descs = I.serving_operators(args.ops, levels=levels, seed=args.seed)
-    operators = {}
-    for t, dsc in enumerate(descs):
-        A, Ai = I.perturbed_identity_pair(dsc["ranks"], [8] * dsc["L"], seed=dsc["seed"], eps=0.1)
-        operators[f"op{t}"] = (A, Ai)
+    operators, descs = serving_operators(args.ops, levels=levels, seed=args.seed)
     srv = SolveServer(operators, inv_dtype=args.inv, budget_bytes=int(args.budget_gb * 1e9),
                       n_slots=args.slots)
-    g = I.rng(args.seed + 1)
-    arrivals = I.poisson_arrivals(args.requests, args.rate, seed=args.seed + 2)
-    reqs = []
-    for i in range(args.requests):
-        t = int(g.integers(args.ops))
-        k = int(g.integers(1, 17))
-        N = 8 ** descs[t]["L"]
-        F = Q.to_block(I.rhs(N, k, seed=args.seed * 7919 + i))
-        reqs.append(Request(rid=i, op=f"op{t}", F=F, arrival=float(arrivals[i])))
-    torch.cuda.synchronize()
-    stats = srv.run_trace(reqs)
+    stats = serving_trace(srv, descs, args.requests, args.rate, seed=args.seed)
     srv.close()
     stats.update({"workload": "serving: Poisson trace over resident QTT operators",
                   "operators": [{"L": d["L"], "r": d["ranks"][1]} for d in descs],

@@ -50,24 +50,62 @@ def test_graph_replays_follow_new_data(Q):
     A.free()
 
 
+def _wave_capacity(Q, A, dtype, ws_bytes):
+    """Vectors per wave: the largest w with qtt_workspace_bytes(w) <= ws_bytes
+    (the rule the library applies to a caller's workspace)."""
+    lo, hi = 1, 1
+    while Q.qtt_workspace_bytes(A, dtype, hi * 2) <= ws_bytes:
+        hi *= 2
+    hi *= 2
+    while lo < hi - 1:
+        mid = (lo + hi) // 2
+        if Q.qtt_workspace_bytes(A, dtype, mid) <= ws_bytes:
+            lo = mid
+        else:
+            hi = mid
+    return lo
+
+
 @pytest.mark.slow
 def test_batched_uneven_L7_fp32(Q):
     """64 blocks of widths drawn from {1,2,4,8,16,32} against the L=7 operator in
-    FP32, through one apply_batched call; sampled columns checked by the oracle."""
+    FP32, through one apply_batched call.  Every column is compared with the
+    FP64 apply of the same column (itself pinned to the oracle), and the first
+    and last column of every workspace wave are checked by the oracle."""
     w = I.WORKLOADS["batched_L7"]
     Ac, _ = I.perturbed_identity_pair(w["ranks"], [8] * 7, seed=w["core_seed"])
     widths = I.uneven_widths(w["nblocks"], seed=w["width_seed"])
-    A = Q.qtt_matrix_load(Ac, dtypes=("fp32",))
+    A = Q.qtt_matrix_load(Ac, dtypes=("fp32", "fp64"))
     N = 8 ** 7
     g = torch.Generator(device="cuda").manual_seed(w["rhs_seed"])
     Xs = [torch.randn((wd, N), generator=g, device="cuda", dtype=torch.float64).t() for wd in widths]
-    ws = Q.workspace(min(Q.qtt_workspace_bytes(A, "fp32", sum(widths)), 64 * 2 ** 30))
+    ws_bytes = min(Q.qtt_workspace_bytes(A, "fp32", sum(widths)), 64 * 2 ** 30)
+    ws = Q.workspace(ws_bytes)
     Ys = Q.qtt_apply_batched(A, "fp32", Xs, ws=ws)
     torch.cuda.synchronize()
-    for b, c in ((0, 0), (len(widths) - 1, widths[-1] - 1), (int(np.argmax(widths)), 3)):
+    del ws
+    # every column against the FP64 sweep
+    ws64 = Q.workspace(Q.qtt_workspace_bytes(A, "fp64", 32))
+    worst = 0.0
+    for b, (X, Y) in enumerate(zip(Xs, Ys)):
+        R = Q.qtt_apply(A, "fp64", X, ws=ws64)
+        err = ((Y - R).norm(dim=0) / R.norm(dim=0)).max().item()
+        worst = max(worst, err)
+        assert err < 1e-5, (b, err)
+    del ws64
+    # the oracle on the first and last column of each wave
+    cap = _wave_capacity(Q, A, "fp32", ws_bytes)
+    total = sum(widths)
+    starts = np.cumsum([0] + widths)
+    cols = sorted({g0 for g0 in range(0, total, cap)} | {min(g0 + cap, total) - 1 for g0 in range(0, total, cap)})
+    print(f"{len(widths)} blocks, {total} vectors, {cap} per wave; FP32 vs FP64 worst {worst:.2e}; "
+          f"oracle on columns {cols}")
+    for gcol in cols:
+        b = int(np.searchsorted(starts, gcol, side="right") - 1)
+        c = gcol - int(starts[b])
         x = Xs[b][:, c].cpu().numpy()
         ref = O.qtt_apply_alg2(Ac, x)
-        assert rel(Ys[b][:, c].cpu().numpy(), ref) < 1e-5
+        assert rel(Ys[b][:, c].cpu().numpy(), ref) < 1e-5, (gcol, b, c)
     A.free()
 
 
@@ -113,6 +151,50 @@ def test_server_alone_equals_mix(Q):
         Ac = ops[r.op][0]
         res = F - O.qtt_apply_alg2(Ac, m.Sigma.cpu().numpy().reshape(F.shape))
         assert np.all(np.linalg.norm(res, axis=0) <= 1e-8 * np.linalg.norm(F, axis=0) * 1.0001)
+    srv.close()
+
+
+@pytest.mark.slow
+def test_server_alone_equals_mix_serving_shapes(Q):
+    """The serving workload's operator shapes (mode 8, L = 5, 6 and 7, ranks
+    between 16 and 32, requests of 1 to 16 vectors): every result of a mixed
+    run with three slots is bitwise the result of the same request served
+    alone, and the oracle's FP64 residual of each is <= 1e-8 (L = 5 and 6:
+    every column; L = 7: the first column of each request)."""
+    from paper_1511_06029_amd.serving import Request, SolveServer
+    shapes = (("L5r17", 5, 17), ("L6r29", 6, 29), ("L7r24", 7, 24))
+    ops = {name: I.perturbed_identity_pair([1] + [r] * (L - 1) + [1], [8] * L, seed=740 + t)
+           for t, (name, L, r) in enumerate(shapes)}
+    g = I.rng(77)
+    spec = []
+    for i in range(10):
+        name, L, _ = shapes[int(g.integers(3))]
+        spec.append((i, name, I.rhs(8 ** L, int(g.integers(1, 17)), seed=760 + i)))
+
+    def make():
+        return [Request(rid=i, op=op, F=Q.to_block(F)) for i, op, F in spec]
+
+    srv = SolveServer(ops, inv_dtype="bf16", budget_bytes=60 * 10 ** 9, n_slots=3)
+    mixed = make()
+    torch.cuda.synchronize()
+    stats = srv.run_trace(mixed, realtime=False)
+    srv.close()
+    assert stats["all_converged"]
+    assert stats["batches"] < len(mixed)
+    srv = SolveServer(ops, inv_dtype="bf16", budget_bytes=60 * 10 ** 9, n_slots=1)
+    for r in make():
+        torch.cuda.synchronize()
+        srv.run_trace([r], realtime=False)
+        m = mixed[r.rid]
+        assert np.array_equal(r.Sigma.cpu().numpy(), m.Sigma.cpu().numpy()), r.rid
+        F = spec[r.rid][2]
+        S = m.Sigma.cpu().numpy().reshape(F.shape)
+        cols = [0] if F.shape[0] == 8 ** 7 else list(range(F.shape[1]))
+        Ac = ops[r.op][0]
+        res = F[:, cols] - O.qtt_apply_alg2(Ac, S[:, cols])
+        assert np.all(np.linalg.norm(res, axis=0) <= 1e-8 * np.linalg.norm(F[:, cols], axis=0) * 1.0001), r.rid
+        r.Sigma = None
+        m.Sigma = None
     srv.close()
 
 
