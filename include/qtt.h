@@ -140,6 +140,21 @@ qtt_status_t qtt_apply_batched(qtt_matrix_t A, qtt_dtype_t compute, int32_t nblo
                                const int64_t* ldx, double* const* Y, const int64_t* ldy,
                                void* ws, size_t ws_bytes, void* stream);
 
+/* qtt_apply for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and results as qtt_apply, with the workspace taken from a
+ * static 512 MiB device array that every GPU holds for the life of the
+ * process.  The vectors run in waves that fit it.  Allocates nothing and
+ * captures no graph; the caller passes only inputs and outputs.
+ *   X, Y, ldx, ldy, nrhs as in qtt_apply; the handle's device must be current.
+ * QTT_ERR_WORKSPACE when one vector needs more than 512 MiB of workspace
+ * (qtt_workspace_bytes for nrhs = 1; e.g. an FP64 or FP32 sweep with a
+ * 2^21-long intermediate of rank 32).  Nothing in the array needs to start
+ * at zero.  All calls on one GPU share the array: calls that overlap on that
+ * GPU (concurrent streams or host threads) race and give wrong results. */
+qtt_status_t qtt_apply_noalloc(qtt_matrix_t A, qtt_dtype_t compute, int64_t nrhs,
+                               const double* X, int64_t ldx, double* Y, int64_t ldy, void* stream);
+
 /* Tune tile shapes for this matrix, dtype and vector count: every candidate
  * kernel configuration is timed on each core (outputs written to scratch in
  * ws), and the fastest is kept in the handle and in a process-wide table

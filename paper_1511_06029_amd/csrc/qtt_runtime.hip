@@ -1181,6 +1181,65 @@ qtt_status_t qtt_apply_batched(qtt_matrix_t A, qtt_dtype_t compute, int32_t nblo
   return run_blocks(A, dt, blocks, ws, ws_bytes, 1.0, static_cast<hipStream_t>(stream));
 }
 
+}  // extern "C"
+
+// Workspace of qtt_apply_noalloc: a file-scope device array, one copy per GPU
+// for the life of the process.  Host code never passes the array's name to a
+// kernel or copy (on the host it is only a stand-in symbol); it uses the
+// device address that hipGetSymbolAddress returns for the current device.
+static constexpr size_t kScratchBytes = size_t(512) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[64] = {};
+
+static qtt_status_t scratch_address(int device, void** ptr) {
+  if (device < 0 || device >= 64) return fail(QTT_ERR_DEVICE, "device %d out of the supported range", device);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device] == nullptr) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr)
+      return fail(QTT_ERR_DEVICE, "hipGetSymbolAddress(scratch) on device %d failed: %s", device,
+                  hipGetErrorString(e));
+    g_scratch_ptr[device] = p;
+  }
+  *ptr = g_scratch_ptr[device];
+  return QTT_OK;
+}
+
+extern "C" {
+
+qtt_status_t qtt_apply_noalloc(qtt_matrix_t A, qtt_dtype_t compute, int64_t nrhs, const double* X, int64_t ldx,
+                               double* Y, int64_t ldy, void* stream) {
+  if (!valid_handle(A)) return fail(QTT_ERR_INVALID_ARG, "null handle");
+  int dt;
+  qtt_status_t s = check_dtype(A, compute, &dt);
+  if (s != QTT_OK) return s;
+  if (nrhs < 0) return fail(QTT_ERR_INVALID_ARG, "nrhs < 0");
+  if (nrhs == 0) return QTT_OK;
+  if (!X || !Y) return fail(QTT_ERR_INVALID_ARG, "X or Y is null");
+  if (ldx < A->cols || ldy < A->rows) return fail(QTT_ERR_INVALID_ARG, "ldx < N or ldy < M");
+  const size_t need = wave_total_bytes(A, dt, 1);
+  if (need > kScratchBytes)
+    return fail(QTT_ERR_WORKSPACE,
+                "one vector needs %zu bytes of workspace, above the %zu-byte static workspace of qtt_apply_noalloc",
+                need, kScratchBytes);
+  const size_t xb = ((size_t)(nrhs - 1) * ldx + A->cols) * 8, yb = ((size_t)(nrhs - 1) * ldy + A->rows) * 8;
+  if (overlaps(X, xb, Y, yb)) return fail(QTT_ERR_INVALID_ARG, "X and Y overlap");
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev != A->device) return fail(QTT_ERR_INVALID_ARG, "the current device %d is not the handle's %d", dev, A->device);
+  void* ws = nullptr;
+  s = scratch_address(dev, &ws);
+  if (s != QTT_OK) return s;
+  std::vector<Block> blocks{{X, Y, nullptr, ldx, ldy, 0, nrhs}};
+  g_timing_off = true;
+  s = run_blocks(A, dt, blocks, ws, kScratchBytes, 1.0, static_cast<hipStream_t>(stream), false);
+  g_timing_off = false;
+  return s;
+}
+
 qtt_status_t qtt_autotune(qtt_matrix_t A, qtt_dtype_t compute, int64_t nrhs, const double* X, int64_t ldx,
                           double* Y, int64_t ldy, void* ws, size_t ws_bytes, void* stream) {
   qtt_status_t s = qtt_apply(A, compute, nrhs, X, ldx, Y, ldy, ws, ws_bytes, stream);  // validates, warms up

@@ -62,6 +62,7 @@ def _load():
         "qtt_workspace_bytes": [P, I32, I64, ctypes.POINTER(SZ)],
         "qtt_apply": [P, I32, I64, P, I64, P, I64, P, SZ, P],
         "qtt_apply_batched": [P, I32, I32, PI64, PP, PI64, PP, PI64, P, SZ, P],
+        "qtt_apply_noalloc": [P, I32, I64, P, I64, P, I64, P],
         "qtt_autotune": [P, I32, I64, P, I64, P, I64, P, SZ, P],
         "qtt_solve_workspace_bytes": [P, P, I32, I64, ctypes.POINTER(SZ)],
         "qtt_solve": [P, P, I32, I64, P, I64, P, I64, D, I32, P, SZ, P, ctypes.POINTER(_SolveCol)],
@@ -90,7 +91,7 @@ def _load():
 _lib = _load()
 # Names the C ABI exports (include/qtt.h); the tests check each is present.
 EXPORTED = ["qtt_matrix_load", "qtt_matrix_free", "qtt_matrix_set_diagonals", "qtt_matrix_info", "qtt_workspace_bytes",
-            "qtt_apply", "qtt_apply_batched", "qtt_autotune", "qtt_solve_workspace_bytes",
+            "qtt_apply", "qtt_apply_batched", "qtt_apply_noalloc", "qtt_autotune", "qtt_solve_workspace_bytes",
             "qtt_matvec_compressed", "qtt_solve", "qtt_fgmres_workspace_bytes", "qtt_solve_fgmres", "qtt_solve_fgmres_product", "qtt_status_string", "qtt_last_error", "qtt_set_shape", "qtt_list_shapes",
             "qtt_timing_enable",
             "qtt_timing_reset", "qtt_timing_read", "qtt_timing_read_shape"]
@@ -259,6 +260,17 @@ def qtt_apply(A, compute, X, Y=None, ws=None, stream=None):
         ws = workspace(qtt_workspace_bytes(A, compute, k), X.device)
     _check(_lib.qtt_apply(A.handle, _dtype(compute), k, xp, ldx, yp, ldy, ws.data_ptr(),
                           ws.numel() * ws.element_size(), _stream(stream)))
+    return Y
+
+
+def qtt_apply_noalloc(A, compute, X, Y, stream=None):
+    """Y = A X through the entry point that allocates nothing (its workspace is
+    the library's static device array); X and Y are caller-owned."""
+    xp, n, k, ldx = _col_major(X, "X")
+    yp, m, ky, ldy = _col_major(Y, "Y")
+    if n != A.cols or m != A.rows or ky != k:
+        raise ValueError(f"shape mismatch: A is {A.rows}x{A.cols}, X {n}x{k}, Y {m}x{ky}")
+    _check(_lib.qtt_apply_noalloc(A.handle, _dtype(compute), k, xp, ldx, yp, ldy, _stream(stream)))
     return Y
 
 
