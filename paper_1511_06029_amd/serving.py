@@ -368,11 +368,14 @@ def serving_trace(server, descs, n_requests, rate, seed=51, k_max=16, device="cu
                                          "p99": float(np.percentile(v, 99))}
                                 for L, v in sorted(by_L.items())}
     worst = 0.0
+    # one workspace of the one-vector size of the largest operator: the
+    # recomputation runs in waves of single vectors beside the arena
+    ws = Q.workspace(max(Q.qtt_workspace_bytes(A, "fp64", 1) for A, _ in server.ops.values()), device)
     for r in reqs:
         if r.Sigma is None:
             continue
         A, _ = server.ops[r.op]
-        AS = Q.qtt_apply(A, "fp64", r.Sigma.reshape(A.rows, -1))
+        AS = Q.qtt_apply(A, "fp64", r.Sigma.reshape(A.rows, -1), ws=ws)
         res = (r.F.reshape(A.rows, -1) - AS).norm(dim=0) / r.F.reshape(A.rows, -1).norm(dim=0)
         worst = max(worst, float(res.max()))
         r.Sigma = None
