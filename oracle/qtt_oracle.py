@@ -10,7 +10,7 @@ equations in complex geometries", arXiv:1511.06029):
 
 * index convention -- section 2.1 (Nomenclature): multi-indices are flattened
   in Matlab order, so ``i = i_1 + m_1*(i_2 + m_2*(i_3 + ...))``; the first
-  index is the fastest.  Core 1 is the finest tree level (section 2.3,
+  index is the fastest.  Core 1 is the finest tree level (section 2.4,
   hierarchical tensorization: levels are numbered from the finest).
 * TT format -- section 2.2, Definition of the TT decomposition (eq. TTdeccores),
   with dummy ranks r_0 = r_d = 1.
@@ -28,15 +28,15 @@ equations in complex geometries", arXiv:1511.06029):
 * TT rounding -- the TT decomposition that Algorithm 1 (section 2.3) gives
   for a tensor that is itself handed over in TT form, computed from its
   cores (the compressed product of section 4.2 has ranks that multiply; the
-  "QTT solve" of section 5.1 rounds them back).
-* the right-hand side of the volume experiments -- section 5.1: f(x, y, z) =
+  "QTT solve" of section 5.2 rounds them back).
+* the right-hand side of the volume experiments -- section 5.2: f(x, y, z) =
   phi(x) phi(y) phi(z), phi(t) = diric(2 pi t, 10) (eq. diric).
-* QTT inversion -- the Newton-Hotelling-Schulz iteration that section 1
+* QTT inversion -- the Newton-Hotelling-Schulz iteration that section 1.3
   names among the QTT inversion methods, X <- X (2 I - A X), in QTT form
   with the matrix-matrix product (ranks multiply, as in the proof of the
   corollary on non-translation-invariant kernels in section 3) and rounding
   after each product.
-* outer Krylov solver -- section 5.2 (boundary integral equations): the
+* outer Krylov solver -- section 5.3 (boundary integral equations): the
   compressed approximate inverse preconditions an unrestarted GMRES with a
   relative-residual tolerance of 1e-8.  Because a low-precision inverse apply
   is linear only up to rounding, the solver here is the flexible variant
@@ -285,14 +285,14 @@ def qtt_matrix_from_dense(A, m, n, eps):
 
 
 # --------------------------------------------------------------------------
-# the volume operator of the numerical experiments (sec. 5.1)
+# the volume operator of the numerical experiments (sec. 5.2)
 # --------------------------------------------------------------------------
 
 def morton_points(L):
     """Integer cell coordinates (ix, iy, iz) of a (2^L)^3 grid listed in
     octree (Morton) order: point index i = sum_k i_k 8^{k-1}, where the level-k
     octant digit is i_k = 4 z_bit + 2 y_bit + x_bit of bit k-1 of each
-    coordinate (level 1 = finest, sec. 2.3; ordering of sec. 5.1)."""
+    coordinate (level 1 = finest, sec. 2.4; ordering of sec. 5.2)."""
     side = 1 << L
     N = side ** 3
     idx = np.arange(N, dtype=np.int64)
@@ -310,7 +310,7 @@ def morton_points(L):
 def volume_self_term(h, sub=8):
     """Diagonal self term: midpoint rule with sub^3 sub-cells for the integral
     of 1/(4 pi |x - y|) over the cell centred at x (no sub-cell midpoint hits
-    the singularity).  Used in place of the punctured trapezoid of sec. 5.1."""
+    the singularity).  Used in place of the punctured trapezoid of sec. 5.2."""
     t = (np.arange(sub) + 0.5) / sub - 0.5
     u = np.stack(np.meshgrid(t, t, t, indexing="ij"), axis=-1).reshape(-1, 3)
     return float(np.sum((h / sub) ** 3 / (4.0 * np.pi * h * np.linalg.norm(u, axis=1))))
@@ -413,12 +413,12 @@ def richardson_solve(A_cores, Ainv_cores, F, rtol=1e-8, max_iter=50):
 
 
 # --------------------------------------------------------------------------
-# the outer Krylov solver: flexible GMRES, right preconditioner (sec. 5.2)
+# the outer Krylov solver: flexible GMRES, right preconditioner (sec. 5.3)
 # --------------------------------------------------------------------------
 
 def fgmres_solve(apply_A, apply_M, F, rtol=1e-8, max_iter=50):
     """sigma with A sigma = F by unrestarted flexible GMRES, one column at a
-    time, as section 5.2 uses GMRES (no restart, relative-residual tolerance)
+    time, as section 5.3 uses GMRES (no restart, relative-residual tolerance)
     with the compressed inverse as right preconditioner.
 
     The steps are Saad's FGMRES (SIAM J. Sci. Comput. 14, 1993), written out
@@ -505,7 +505,7 @@ def tt_full(cores):
     return T.reshape(-1, order="F")  # axes (a_0, i_1, ..., i_d, a_d), a_0 = a_d = 0
 
 
-def tt_round(cores, eps):
+def tt_round(cores, eps, floor=0.0):
     """The TT decomposition that Algorithm 1 (truncated SVDs, per-unfolding
     accuracy eps ||c||_F / sqrt(d-1)) computes for the tensor c that `cores`
     represent, without expanding c.
@@ -520,6 +520,8 @@ def tt_round(cores, eps):
       2. left to right, k = 1..d-1: SVD of core k as the (r_{k-1} n_k) x r_k
          matrix, keep the rank _keep_rank allows (tail <= eps ||c|| /
          sqrt(d-1)), core k <- U, core k+1 <- (S V^T) core k+1.
+    floor > 0 replaces eps ||c|| by max(eps ||c||, floor): an absolute
+    accuracy for a tensor whose own norm is not the scale that matters.
     Returns (cores, tails) as tt_svd does."""
     G = [np.array(c, dtype=np.float64, copy=True) for c in cores]
     d = len(G)
@@ -531,7 +533,7 @@ def tt_round(cores, eps):
     norm = float(np.linalg.norm(G[0]))
     if d == 1:
         return G, []
-    delta = eps * norm / np.sqrt(d - 1)
+    delta = max(eps * norm, floor) / np.sqrt(d - 1)
     tails = []
     for k in range(d - 1):
         r0, n, r1 = G[k].shape
@@ -544,7 +546,7 @@ def tt_round(cores, eps):
 
 
 # --------------------------------------------------------------------------
-# the right-hand side of the volume experiments (section 5.1)
+# the right-hand side of the volume experiments (section 5.2)
 # --------------------------------------------------------------------------
 
 def diric(t, nu):
@@ -562,7 +564,7 @@ def diric(t, nu):
 def diric_rhs(L, nu=10):
     """f(x, y, z) = phi(x) phi(y) phi(z), phi(t) = diric(2 pi t, nu), at the
     cell centres of the (2^L)^3 grid on [0,1]^3, listed in Morton order
-    (section 5.1's right-hand side, on the grid of volume_matrix)."""
+    (section 5.2's right-hand side, on the grid of volume_matrix)."""
     h = 1.0 / (1 << L)
     P = (morton_points(L) + 0.5) * h
     phi = diric(2.0 * np.pi * P, nu)
@@ -617,22 +619,31 @@ def qtt_lincomb(terms):
     return out
 
 
-def qtt_round_matrix(cores, eps):
+def qtt_round_matrix(cores, eps, floor=0.0):
     """tt_round of a QTT matrix, its cores read as TT cores of mode m_k n_k
     (row digit fastest, the index b_k = i_k + m_k j_k of section 3)."""
     shapes = [(G.shape[1], G.shape[2]) for G in cores]
     tt = [G.reshape(G.shape[0], G.shape[1] * G.shape[2], G.shape[3], order="F") for G in cores]
-    out, tails = tt_round(tt, eps)
+    out, tails = tt_round(tt, eps, floor)
     return [G.reshape(G.shape[0], m, n, G.shape[2], order="F") for G, (m, n) in zip(out, shapes)], tails
 
 
-def newton_schulz(A_cores, X0_cores, eps, max_iter=20, tol=0.0):
+def newton_schulz(A_cores, X0_cores, eps, max_iter=20, tol=0.0, theta=0.0):
     """Approximate inverse of A by the Newton-Hotelling-Schulz iteration
     X_{t+1} = X_t (2 I - A X_t) in QTT form: each product by qtt_matmul,
     the sum by qtt_lincomb, and tt rounding (relative accuracy eps) after
-    each product and after the sum.  In exact arithmetic I - A X_{t+1} =
-    (I - A X_t)^2, so the iteration converges quadratically once
-    ||I - A X_0|| < 1.
+    each product and after the sum.  The residual R = I - A X is rounded to
+    accuracy eps ||I||_F (the scale X's accuracy is measured on), not eps
+    ||R||: once X is good, R is mostly the rounding noise of the previous
+    steps, whose rank relative to its own norm is not bounded.  In exact
+    arithmetic I - A X_{t+1} = (I - A X_t)^2, so the iteration converges
+    quadratically once ||I - A X_0|| < 1.
+
+    theta > 0 rounds the next iterate (and 2 I - A X) to the accuracy
+    max(eps, theta h_t^2) instead of eps, h_t = ||R_t||_F / ||I||_F: the
+    next iterate is within about h_t^2 of the inverse, so more accuracy buys
+    only rank (an early iterate has high ranks at a tight eps that the
+    inverse itself does not need).
 
     Stops after max_iter steps or once the rounded residual matrix
     R = I - A X has ||R||_F <= tol ||I||_F.  Returns (X_cores, history) with
@@ -645,11 +656,12 @@ def newton_schulz(A_cores, X0_cores, eps, max_iter=20, tol=0.0):
     history = []
     for t in range(max_iter + 1):
         AX, _ = qtt_round_matrix(qtt_matmul(A_cores, X), eps)
-        R, _ = qtt_round_matrix(qtt_lincomb([(1.0, I), (-1.0, AX)]), eps)
+        R, _ = qtt_round_matrix(qtt_lincomb([(1.0, I), (-1.0, AX)]), eps, floor=eps * ident_norm)
         history.append(float(np.linalg.norm(tt_full([G.reshape(G.shape[0], -1, G.shape[3], order="F")
                                                       for G in R])) / ident_norm))
         if history[-1] <= tol or t == max_iter:
             break
-        Z, _ = qtt_round_matrix(qtt_lincomb([(1.0, I), (1.0, R)]), eps)      # 2 I - A X = I + R
-        X, _ = qtt_round_matrix(qtt_matmul(X, Z), eps)
+        tau = max(eps, theta * history[-1] ** 2)
+        Z, _ = qtt_round_matrix(qtt_lincomb([(1.0, I), (1.0, R)]), tau)      # 2 I - A X = I + R
+        X, _ = qtt_round_matrix(qtt_matmul(X, Z), tau)
     return X, history

@@ -1,4 +1,4 @@
-"""Pins of the oracle's TT rounding, the section 5.1 right-hand side, the QTT
+"""Pins of the oracle's TT rounding, the section 5.2 right-hand side, the QTT
 matrix product and sum, and the Newton-Hotelling-Schulz inversion, against
 facts that do not come from those functions: the dense TT-SVD (itself pinned
 to Eckart-Young), exact rank recovery, the rounding error bound, the
@@ -75,6 +75,25 @@ def test_round_equals_dense_ttsvd_and_bound(eps):
     err = np.linalg.norm(w - v)
     assert err <= eps * np.linalg.norm(v) * (1 + 1e-12)
     assert err <= np.sqrt(np.sum(np.square(tails))) * (1 + 1e-9) + 1e-14 * np.linalg.norm(v)
+
+
+def test_round_floor_is_absolute_accuracy():
+    """With a floor, the rounding accuracy is max(eps ||c||, floor): a small
+    tensor rounded against a larger absolute scale keeps fewer ranks and
+    stays within the floor."""
+    big = _rand_tt([1, 3, 3, 3, 1], [4, 3, 4, 3], seed=13)
+    small = _rand_tt([1, 2, 4, 2, 1], [4, 3, 4, 3], seed=14, scale=0.05)
+    c = _tt_sum(big, small)
+    c[0] = c[0] * 1e-3                                  # ||c|| is about 1e-3 of the scale below
+    v = O.tt_full(c)
+    scale = 1e3 * np.linalg.norm(v)
+    r_rel, _ = O.tt_round(c, 1e-6)
+    r_abs, _ = O.tt_round(c, 1e-6, floor=1e-3 * scale)
+    assert np.linalg.norm(O.tt_full(r_abs) - v) <= 1e-3 * scale * (1 + 1e-12)
+    assert sum(G.shape[2] for G in r_abs) < sum(G.shape[2] for G in r_rel)
+    # a floor below eps ||c|| changes nothing
+    r_low, _ = O.tt_round(c, 1e-6, floor=1e-12 * np.linalg.norm(v))
+    assert [G.shape for G in r_low] == [G.shape for G in r_rel]
 
 
 def test_round_two_cores_is_truncated_svd():
@@ -179,3 +198,18 @@ def test_newton_schulz_truncated_accuracy():
     R = np.eye(A.shape[0]) - A @ O.qtt_to_dense(X)
     assert np.linalg.norm(R) / np.sqrt(A.shape[0]) <= 1e-6
     assert hist[-1] <= 1e-6
+
+
+def test_newton_schulz_adaptive_rounding():
+    """theta > 0 rounds early iterates coarser (accuracy theta h_t^2): the
+    same final accuracy as the plain rule, never larger ranks at the end, and
+    the residual still squares until it reaches the rounding level."""
+    Ac, Aic = I.perturbed_identity_pair([1, 3, 4, 4, 3, 1], [2] * 5, seed=15)
+    X1, h1 = O.newton_schulz(Ac, Aic, 1e-9, max_iter=6)
+    X2, h2 = O.newton_schulz(Ac, Aic, 1e-9, max_iter=6, theta=0.1)
+    A = O.qtt_to_dense(Ac)
+    Ainv = np.linalg.inv(A)
+    for X in (X1, X2):
+        assert np.linalg.norm(O.qtt_to_dense(X) - Ainv) <= 1e-7 * np.linalg.norm(Ainv)
+    assert max(G.shape[3] for G in X2) <= max(G.shape[3] for G in X1)
+    assert h2[-1] <= 1e-7 and h2[1] <= 2 * np.sqrt(32) * h2[0] ** 2
