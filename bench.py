@@ -32,8 +32,12 @@ PEAK_FP64_TFLOPS = 78.6      # MI355X dense FP64 (matrix and vector)
 PEAK_FP32_TFLOPS = 157.3
 PEAK_BF16_TFLOPS = 2500.0
 PEAK_HBM_GBS = 8000.0
-# the sources whose hash the committed HBM-traffic figures are tied to
-KERNEL_SOURCES = ("paper_1511_06029_amd/csrc/qtt_kernels.hpp", "paper_1511_06029_amd/csrc/qtt_runtime.hip")
+# the sources whose hash the committed HBM-traffic figures are tied to: every
+# file the library is built from
+def kernel_sources():
+    import glob
+    csrc = os.path.join(ROOT, "paper_1511_06029_amd", "csrc")
+    return sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.hpp")))
 
 
 def parse():
@@ -56,6 +60,8 @@ def parse():
     p.add_argument("--no-serving", action="store_true",
                    help="skip the serving traces (BF16 and FP64 inverses, and the lower arrival rate)")
     p.add_argument("--serving-requests", type=int, default=32)
+    p.add_argument("--no-tt", action="store_true",
+                   help="skip the TT-format legs (compressed 'QTT solve' and Newton-Schulz inversion)")
     p.add_argument("--copy-probe", action="store_true",
                    help="only run a device copy of known size (HBM counter calibration)")
     p.add_argument("--variants", default="bf16,fp64,fp32",
@@ -201,6 +207,8 @@ def main():
     batched = None if args.no_batched else batched_run(Q, torch)
 
     serving = None if args.no_serving else serving_run(Q, torch, args.serving_requests)
+    qtt_solve_c = None if args.no_tt else qtt_solve_compressed_run(Q, torch, Aic)
+    ns = None if args.no_tt else newton_schulz_run(Q, torch, A, Ai, F, K, rtol, args)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -245,6 +253,8 @@ def main():
         "compressed_matvec_L7": cmv,
         "batched_uneven_L7": batched,
         "serving": serving,
+        "qtt_solve_compressed_L7": qtt_solve_c,
+        "newton_schulz_inverse_L7": ns,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
@@ -311,7 +321,7 @@ def nti_run(Q, torch, Ac, F, K, N, reps=10):
 
 def fgmres_run(Q, torch, A, Ai, inv, F, K, N, rtol, args, max_iter=12):
     """The same solve by flexible GMRES (the compressed inverse as right
-    preconditioner, section 5.2's outer solver): RHS/s, steps, and the true
+    preconditioner, section 5.3's outer solver): RHS/s, steps, and the true
     relative residual recomputed by an FP64 apply outside the timed region."""
     ws = Q.workspace(Q.qtt_fgmres_workspace_bytes(A, Ai, inv, K, max_iter))
     Sig = Q.empty_block(N, K)
@@ -345,8 +355,8 @@ def measured_traffic(dtype, shape):
     import hashlib
     path = os.path.join(ROOT, "profiles", "hbm_traffic_refine_L7.json")
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        h.update(open(os.path.join(ROOT, f), "rb").read())
+    for f in kernel_sources():
+        h.update(open(f, "rb").read())
     try:
         rec = json.load(open(path))
         b = rec["bytes_per_launch"][f"{dtype} shape {shape}"]
@@ -468,6 +478,100 @@ def serving_run(Q, torch, n_requests):
     torch.cuda.empty_cache()
     out["bf16_inverse_knee"] = dict(_round_stats(st), rate_per_s=rate)
     return out
+
+
+def qtt_solve_compressed_run(Q, torch, Aic, eps=1e-4, reps=3):
+    """The "QTT solve" of section 5.2 at L=7 on the GPU: compress the right-hand
+    side f = phi(x) phi(y) phi(z), phi(t) = diric(2 pi t, 10), into TT form,
+    take the compressed product with the compressed inverse (ranks multiply),
+    round the product; each step timed (median of reps), and the result
+    compared with the full-vector apply of the inverse to f."""
+    L = 7
+    N = 8 ** L
+    side = 1 << L
+    # f on the cell centres in octree order (octant digit 4z + 2y + x per level)
+    idx = np.arange(N, dtype=np.int64)
+    coord = [np.zeros(N, dtype=np.int64) for _ in range(3)]
+    for k in range(L):
+        dig = (idx >> (3 * k)) & 7
+        for a in range(3):
+            coord[a] |= ((dig >> a) & 1) << k
+    t = 2 * np.pi * (np.stack(coord, axis=1) + 0.5) / side
+    with np.errstate(divide="ignore", invalid="ignore"):
+        phi = np.sin(10 * t / 2) / (10 * np.sin(t / 2))     # no cell centre hits t = 2 pi k
+    f = torch.from_numpy(np.ascontiguousarray(phi[:, 0] * phi[:, 1] * phi[:, 2])).cuda()
+    Ai = Q.qtt_matrix_load(Aic, dtypes=("fp64",))
+    times = {"compress_ms": [], "product_ms": [], "round_ms": []}
+    out = None
+    for rep in range(reps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fc, fr, _ = Q.qtt_tt_compress(f, [8] * L, eps, seed=3)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        C = Q.qtt_matvec_compressed(Ai, [G[None].contiguous() for G in fc])
+        prod = [Cc[0].contiguous() for Cc in C]
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        cores, ranks, st = Q.qtt_tt_round(prod, eps, seed=4, raise_on_cap=False)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        if rep > 0:
+            times["compress_ms"].append((t1 - t0) * 1e3)
+            times["product_ms"].append((t2 - t1) * 1e3)
+            times["round_ms"].append((t3 - t2) * 1e3)
+        out = (fr, [1] + [int(P.shape[2]) for P in prod], ranks, st, cores)
+    fr, pr, ranks, st, cores = out
+    # expand the rounded TT on the device and compare with Ainv f (full-vector sweep)
+    v = cores[0].reshape(8, -1)
+    for G in cores[1:]:
+        v = (v @ G.reshape(G.shape[0], -1)).reshape(-1, G.shape[2])
+    v = v.reshape(-1)
+    # the expansion's index is i_1 fastest only after reordering: v was built
+    # with i_1 slowest, so reverse the digit order
+    v = v.reshape([8] * L).permute(*reversed(range(L))).reshape(-1)
+    y = Q.qtt_apply(Ai, "fp64", f.reshape(N, 1))[:, 0]
+    err = float((v - y).norm() / y.norm())
+    Ai.free()
+    med = {k: round(float(np.median(x)), 2) for k, x in times.items()}
+    return {"eps": eps, "rhs_ranks": fr, "product_ranks": pr, "rounded_ranks": ranks,
+            "rank_cap_reached": st == 9, **med,
+            "total_ms": round(sum(med.values()), 2),
+            "rel_error_vs_full_apply": err,
+            "config": "L=7 (N=2097152), diric RHS (section 5.2), inverse ranks [1,24,32,32,32,32,24,1]; "
+                      "compress, compressed product, round, each at relative accuracy eps"}
+
+
+def newton_schulz_run(Q, torch, A, Ai0, F, K, rtol, args, rank_cap=32, eps=1e-10, max_iter=6):
+    """QTT inversion on the GPU (Newton-Hotelling-Schulz from the first-order
+    inverse, every rounding held to the inverse's ranks, at most rank_cap): its
+    time, the residual history ||I - A X|| / ||I||, and the refined solve of the
+    headline workload with it (BF16 and FP64 inverse) against the first-order
+    inverse."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    X, hist, steps, st = Q.qtt_invert_newton_schulz(A, Ai0, eps, max_rank=rank_cap, max_iter=max_iter,
+                                                    theta=0.1, seed=5, dtypes=("fp64", "bf16", "fp32"),
+                                                    raise_on_cap=False)
+    torch.cuda.synchronize()
+    t_inv = time.perf_counter() - t0
+    res = {"seconds": round(t_inv, 2), "steps": steps, "history": [float(f"{h:.3e}") for h in hist],
+           "ranks": X.ranks, "rank_cap": rank_cap, "eps": eps}
+    ws = Q.workspace(max(Q.qtt_solve_workspace_bytes(A, X, v, K) for v in ("bf16", "fp32", "fp64")))
+    Sig = Q.empty_block(F.shape[0], K)
+    for v in ("bf16", "fp32", "fp64"):
+        for _ in range(2):
+            Q.qtt_solve(A, X, v, F, Sig, rtol=rtol, ws=ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(max(3, args.steps // 4)):
+            _, info, _ = Q.qtt_solve(A, X, v, F, Sig, rtol=rtol, ws=ws)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / max(3, args.steps // 4)
+        res[f"solve_{v}"] = {"rhs_per_s": round(K / dt, 3), "passes": max(c[0] for c in info),
+                             "max_rel_residual": max(c[1] for c in info)}
+    X.free()
+    return res
 
 
 def _round_stats(st):

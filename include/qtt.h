@@ -65,7 +65,8 @@ typedef enum {
   QTT_ERR_NOT_CONVERGED = 5, /* qtt_solve reached max_iter above rtol */
   QTT_ERR_NONFINITE = 6,     /* qtt_solve met a NaN or Inf residual */
   QTT_ERR_WORKSPACE = 7,     /* workspace smaller than the one-vector minimum */
-  QTT_ERR_DTYPE = 8          /* the handle holds no device copy in this dtype */
+  QTT_ERR_DTYPE = 8,         /* the handle holds no device copy in this dtype */
+  QTT_ERR_RANK = 9           /* a TT rounding needed ranks above max_rank (result kept at max_rank) */
 } qtt_status_t;
 
 /* Load a QTT matrix onto the current HIP device.
@@ -109,6 +110,10 @@ qtt_status_t qtt_matrix_set_diagonals(qtt_matrix_t A, double a, const double* b,
 /* Shape of a loaded matrix; any output pointer may be NULL. */
 qtt_status_t qtt_matrix_info(qtt_matrix_t A, int32_t* d, int64_t* rows, int64_t* cols,
                              int64_t* max_rank, uint32_t* dtypes);
+
+/* Ranks (d + 1 values) and row and column mode sizes (d values each) of a
+ * loaded matrix; any output pointer may be NULL. */
+qtt_status_t qtt_matrix_shape(qtt_matrix_t A, int64_t* ranks, int64_t* m, int64_t* n);
 
 /* Device bytes of workspace that let qtt_apply / qtt_apply_batched run nrhs
  * vectors in one sweep: two ping-pong buffers of the largest intermediate
@@ -223,7 +228,7 @@ qtt_status_t qtt_fgmres_workspace_bytes(qtt_matrix_t A, qtt_matrix_t Ainv, qtt_d
                                         int64_t nrhs, int32_t max_iter, size_t* bytes);
 
 /* Solve A sigma = F by unrestarted flexible GMRES with the compressed
- * inverse as right preconditioner, as section 5.2 uses GMRES (relative
+ * inverse as right preconditioner, as section 5.3 uses GMRES (relative
  * residual tolerance, no restart) around the QTT approximate inverse.  Each
  * column c runs its own Krylov space; all active columns share every apply:
  *   z_j = Ainv v_j (inv_compute), w = A z_j (FP64), two passes of classical
@@ -271,7 +276,7 @@ qtt_status_t qtt_solve_fgmres(qtt_matrix_t A, qtt_matrix_t Ainv, qtt_dtype_t inv
 qtt_status_t qtt_matvec_compressed(qtt_matrix_t A, int64_t nvec, const int64_t* rb,
                                    const double* const* B, double* const* C, void* stream);
 
-/* qtt_solve_fgmres with §5.2's product-form preconditioner: the compressed
+/* qtt_solve_fgmres with section 4.1's product-form preconditioner: the compressed
  * inverse is the product of two QTT matrices, Ainv = M Y (the inversion
  * solves A M Y = I for Y with an easily inverted M), applied as two chained
  * sweeps, z_j = M (Y v_j), both in inv_compute.  Y v_j is staged in the slot
@@ -282,6 +287,73 @@ qtt_status_t qtt_solve_fgmres_product(qtt_matrix_t A, qtt_matrix_t M, qtt_matrix
                                       int64_t nrhs, const double* F, int64_t ldf, double* Sigma, int64_t lds,
                                       double rtol, int32_t max_iter, void* ws, size_t ws_bytes,
                                       void* stream, qtt_solve_col_t* info);
+
+/* ------------------------------------------------------------------------
+ * Tensors in TT form.  A TT tensor (eq. TTdeccores, section 2.2) with d cores
+ * has ranks r_0..r_d (r_0 = r_d = 1) and modes n_1..n_d; core k is a device
+ * FP64 array [r_{k-1}][n_k][r_k], C row-major, and the entries, first index
+ * fastest (section 2.1), are
+ *     c(i_1, ..., i_d) = G_1(:, i_1, :) G_2(:, i_2, :) ... G_d(:, i_d, :).
+ * A QTT matrix core [r][m][n][r'] is the TT core of mode m n (j fastest).
+ * These calls allocate device scratch of their own and synchronise the
+ * stream before returning (ranks are decided on the host).
+ * ------------------------------------------------------------------------ */
+
+/* TT rounding: the TT decomposition that Algorithm 1 (section 2.3: truncated
+ * SVDs of the unfoldings, each to accuracy eps ||c||_F / sqrt(d - 1), so the
+ * result c' has ||c - c'||_F <= eps ||c||_F up to the sketch's error) gives
+ * for the tensor c that the input cores represent, computed from the cores:
+ * a randomized range finder with Gaussian sketch cores (Philox4x32-10
+ * normals from seed), then a right-to-left truncation with the rank rule of
+ * Algorithm 1.  The sketch rank grows from 32 up to max_rank (1..128) while a
+ * kept rank comes within an eighth of it.
+ *   ranks, n     the input's ranks (d + 1) and modes (d), host arrays.
+ *   cores        d device pointers to the input cores (not modified).
+ *   out          d device pointers; out[k] must hold
+ *                min(max_rank, ranks[k]) n_k min(max_rank, ranks[k+1]) values.
+ *   out_ranks    host, d + 1 values: the ranks of the result.
+ * The result's cores 2..d have orthonormal rows (as r_{k-1} x n_k r_k
+ * matrices); core 1 carries the norm.  QTT_ERR_RANK when max_rank was
+ * reached while the tolerance asked for more (the result is then the best
+ * found at max_rank). */
+qtt_status_t qtt_tt_round(int32_t d, const int64_t* n, const int64_t* ranks, const double* const* cores,
+                          double eps, int32_t max_rank, uint64_t seed, double* const* out, int64_t* out_ranks,
+                          void* stream);
+
+/* Compression of a full vector x (device FP64, prod n_k values, first digit
+ * fastest) into TT form to relative accuracy eps: Algorithm 1 with a
+ * randomized low-rank routine (Gaussian sketch of each unfolding's columns,
+ * thin QR), then the same truncation as qtt_tt_round.  The "compress" step of
+ * section 5.2's "QTT solve".  out / out_ranks as in qtt_tt_round. */
+qtt_status_t qtt_tt_compress(int32_t d, const int64_t* n, const double* x, double eps, int32_t max_rank,
+                             uint64_t seed, double* const* out, int64_t* out_ranks, void* stream);
+
+/* Read back the FP64 cores of a handle (as loaded): host_cores[k] receives
+ * r_{k-1} m_k n_k r_k values, [r_{k-1}][m_k][n_k][r_k].  QTT_ERR_DTYPE when
+ * the handle has no FP64 copy.  Synchronous. */
+qtt_status_t qtt_matrix_cores(qtt_matrix_t A, double* const* host_cores);
+
+/* QTT inversion by the Newton-Hotelling-Schulz iteration (named in section 1.3
+ * among the QTT inversion methods): from X_0 (the handle X0), repeat
+ *     R_t = round(I - round(A X_t)),   X_{t+1} = round(X_t round(I + R_t)),
+ * every product in QTT form (ranks multiply) and every round a qtt_tt_round
+ * to relative accuracy eps with ranks up to max_rank, except R_t's, whose
+ * accuracy is eps ||I||_F (the scale of X's error, not R_t's own norm).
+ * I - A X_{t+1} =
+ * (I - A X_t)^2 before rounding, so the residual squares each step once
+ * ||I - A X_0|| < 1.  theta > 0 rounds I + R_t and X_{t+1} to accuracy
+ * max(eps, theta h_t^2), h_t = ||R_t||_F / ||I||_F (X_{t+1} is within about
+ * h_t^2 of the inverse; early iterates then keep the ranks the inverse
+ * needs, not the higher ones a tight eps would give them); theta = 0 rounds
+ * everything at eps.  Stops when h_t <= tol or after max_iter steps.  A and X0 need FP64 copies and square, identical modes.
+ *   Xinv     receives a new handle with device copies in dtypes (free it
+ *            with qtt_matrix_free).
+ *   history  host, max_iter + 1 values or NULL: ||R_t||_F / ||I||_F.
+ *   steps    host or NULL: the number of updates done.
+ * QTT_ERR_RANK if some rounding hit max_rank (Xinv is still returned). */
+qtt_status_t qtt_invert_newton_schulz(qtt_matrix_t A, qtt_matrix_t X0, double eps, int32_t max_rank,
+                                      int32_t max_iter, double tol, double theta, uint64_t seed, uint32_t dtypes,
+                                      qtt_matrix_t* Xinv, double* history, int32_t* steps, void* stream);
 
 const char* qtt_status_string(qtt_status_t s);
 const char* qtt_last_error(void);

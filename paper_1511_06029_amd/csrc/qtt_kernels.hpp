@@ -1983,7 +1983,7 @@ __global__ void colnorm_final_kernel(const double* partial, int ncol, double* ou
 }
 
 // ---------------------------------------------------------------------------
-// Vector kernels of the flexible GMRES outer solver (section 5.2 uses the
+// Vector kernels of the flexible GMRES outer solver (section 5.3 uses the
 // compressed inverse as the preconditioner of an unrestarted GMRES).  Every
 // vector is an FP64 column of N values; column c of basis vector i lies at
 // basis + i * bstride + c * N.  The work per call is a few passes over N x K

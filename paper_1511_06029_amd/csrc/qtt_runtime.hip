@@ -25,15 +25,16 @@
 #include "qtt.h"
 #include "qtt_kernels.hpp"
 #include "qtt_registry.hpp"
+#include "qtt_internal.hpp"
 
 using namespace qtt;
 
 // ---------------------------------------------------------------------------
 // errors
 // ---------------------------------------------------------------------------
-static thread_local std::string g_last_error;
+thread_local std::string g_last_error;
 
-static qtt_status_t fail(qtt_status_t s, const char* fmt, ...) {
+qtt_status_t qtt::fail(qtt_status_t s, const char* fmt, ...) {
   char buf[512];
   va_list ap;
   va_start(ap, fmt);
@@ -42,13 +43,6 @@ static qtt_status_t fail(qtt_status_t s, const char* fmt, ...) {
   g_last_error = buf;
   return s;
 }
-
-#define HIP_TRY(expr)                                                              \
-  do {                                                                             \
-    hipError_t e_ = (expr);                                                        \
-    if (e_ != hipSuccess)                                                          \
-      return fail(QTT_ERR_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
-  } while (0)
 
 // ---------------------------------------------------------------------------
 // dtype helpers
@@ -234,52 +228,8 @@ static int occupancy(KernelCfg* k) {
 }
 
 // ---------------------------------------------------------------------------
-// the matrix handle
+// the handle's graph cache
 // ---------------------------------------------------------------------------
-struct CoreDev {
-  int r_in, r_out, m, n;
-  int R_out, K_in;
-  int64_t C;          // columns of b_k per vector
-  int64_t out_len;    // elements of y_k per vector
-  int nRB;
-  int Ksteps[3];
-  void* frag[3];
-  int tuned[3];       // tuned shape id per dtype, -1 = heuristic
-  double* valu;       // FP64 vector-ALU copy Mv, input groups of 8 (when K_in % 8 == 0)
-  double* valu1;      // FP64 vector-ALU copy Mv, groups of 1
-  int Rpad;           // rows of Mv
-  double* g64 = nullptr;  // FP64 core as given, [r_in][m][n][r_out] (compressed products)
-};
-
-struct qtt_matrix_s {
-  int d = 0;
-  std::vector<int64_t> ranks, m, n;
-  int64_t rows = 0, cols = 0, max_rank = 0;
-  uint32_t dtypes = 0;
-  int device = 0;
-  std::vector<CoreDev> core;
-  int64_t max_inter = 0;  // largest y_k (k < d) per vector, elements
-  bool fp64_pair = true;  // FP64 sweeps fuse interior core pairs where the pair kernel applies
-  bool fp32_pair = true;  // the same for FP32 sweeps
-  // a I + diag(b) K diag(wc) (non-translation-invariant operator); device
-  // arrays of rows / cols values, NULL = ones
-  bool has_diag = false;
-  double diag_a = 0.0;
-  double* diag_b = nullptr;
-  double* diag_wc = nullptr;
-  // captured sweeps: a sweep with the same dtype, vectors, pointers, workspace
-  // and alpha replays its graph instead of launching d kernels
-  struct Graph {
-    std::string key;
-    hipGraph_t graph;
-    hipGraphExec_t exec;
-  };
-  mutable std::mutex graph_mu;
-  mutable std::vector<Graph> graphs;   // most recent last
-  mutable hipStream_t cap_stream = nullptr;
-  mutable uint64_t tune_gen = 0;       // bumped when tile choices change
-};
-
 static const size_t kMaxGraphs = 48;
 
 static void drop_graphs(const qtt_matrix_s* A) {
@@ -888,6 +838,7 @@ const char* qtt_status_string(qtt_status_t s) {
     case QTT_ERR_NONFINITE: return "non-finite residual";
     case QTT_ERR_WORKSPACE: return "workspace too small";
     case QTT_ERR_DTYPE: return "dtype not loaded";
+    case QTT_ERR_RANK: return "rank cap reached";
   }
   return "unknown status";
 }
@@ -1119,6 +1070,16 @@ qtt_status_t qtt_matrix_info(qtt_matrix_t A, int32_t* d, int64_t* rows, int64_t*
   if (cols) *cols = A->cols;
   if (max_rank) *max_rank = A->max_rank;
   if (dtypes) *dtypes = A->dtypes;
+  return QTT_OK;
+}
+
+qtt_status_t qtt_matrix_shape(qtt_matrix_t A, int64_t* ranks, int64_t* m, int64_t* n) {
+  if (!valid_handle(A)) return fail(QTT_ERR_INVALID_ARG, "null handle");
+  for (int k = 0; k <= A->d && ranks; ++k) ranks[k] = A->ranks[k];
+  for (int k = 0; k < A->d; ++k) {
+    if (m) m[k] = A->m[k];
+    if (n) n[k] = A->n[k];
+  }
   return QTT_OK;
 }
 

@@ -72,6 +72,12 @@ def _load():
                                      ctypes.POINTER(_SolveCol)],
         "qtt_set_shape": [P, I32, I32, I32],
         "qtt_list_shapes": [I32, ctypes.POINTER(I32), I32, ctypes.POINTER(I32)],
+        "qtt_tt_round": [I32, PI64, PI64, PP, D, I32, ctypes.c_uint64, PP, PI64, P],
+        "qtt_tt_compress": [I32, PI64, P, D, I32, ctypes.c_uint64, PP, PI64, P],
+        "qtt_matrix_cores": [P, PP],
+        "qtt_matrix_shape": [P, PI64, PI64, PI64],
+        "qtt_invert_newton_schulz": [P, P, D, I32, I32, D, D, ctypes.c_uint64, U32, PP, ctypes.POINTER(D),
+                                     ctypes.POINTER(I32), P],
         "qtt_timing_enable": [I32],
         "qtt_timing_reset": [],
         "qtt_timing_read": [I32, I32, PI64, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(D)],
@@ -93,6 +99,7 @@ _lib = _load()
 EXPORTED = ["qtt_matrix_load", "qtt_matrix_free", "qtt_matrix_set_diagonals", "qtt_matrix_info", "qtt_workspace_bytes",
             "qtt_apply", "qtt_apply_batched", "qtt_apply_noalloc", "qtt_autotune", "qtt_solve_workspace_bytes",
             "qtt_matvec_compressed", "qtt_solve", "qtt_fgmres_workspace_bytes", "qtt_solve_fgmres", "qtt_solve_fgmres_product", "qtt_status_string", "qtt_last_error", "qtt_set_shape", "qtt_list_shapes",
+            "qtt_tt_round", "qtt_tt_compress", "qtt_matrix_cores", "qtt_matrix_shape", "qtt_invert_newton_schulz",
             "qtt_timing_enable",
             "qtt_timing_reset", "qtt_timing_read", "qtt_timing_read_shape"]
 
@@ -185,6 +192,18 @@ class QttMatrix:
             self.free()
         except Exception:
             pass
+
+    @classmethod
+    def _from_handle(cls, h):
+        """Wrap a handle the library created (shapes read back from it)."""
+        hv = ctypes.c_void_p(h)
+        d = ctypes.c_int32()
+        _check(_lib.qtt_matrix_info(hv, ctypes.byref(d), None, None, None, None))
+        r = (ctypes.c_int64 * (d.value + 1))()
+        m = (ctypes.c_int64 * d.value)()
+        n = (ctypes.c_int64 * d.value)()
+        _check(_lib.qtt_matrix_shape(hv, r, m, n))
+        return cls(hv, (list(r), list(m), list(n)))
 
 
 def qtt_matrix_load(cores, dtypes=("fp64",)):
@@ -435,3 +454,91 @@ def qtt_timing_read_shape(compute, shape):
     _check(_lib.qtt_timing_read_shape(_dtype(compute), int(shape), ctypes.byref(n), ctypes.byref(ms),
                                       ctypes.byref(fl), ctypes.byref(by)))
     return {"launches": n.value, "ms": ms.value, "flops": fl.value, "bytes": by.value}
+
+
+# ---------------------------------------------------------------- TT form
+
+QTT_ERR_RANK = 9
+
+
+def _tt_out(n, ranks_cap, device):
+    """Output cores with room for ranks up to ranks_cap (d + 1 values)."""
+    return [torch.empty(int(ranks_cap[k] * n[k] * ranks_cap[k + 1]), dtype=torch.float64, device=device)
+            for k in range(len(n))]
+
+
+def _tt_result(bufs, n, ranks):
+    return [bufs[k][: ranks[k] * n[k] * ranks[k + 1]].view(ranks[k], n[k], ranks[k + 1]) for k in range(len(n))]
+
+
+@_on_stream
+def qtt_tt_round(cores, eps, max_rank=128, seed=1, stream=None, raise_on_cap=True):
+    """Round a TT tensor given as a list of (r_{k-1}, n_k, r_k) FP64 CUDA
+    tensors; returns (cores, ranks, status)."""
+    d = len(cores)
+    n = [int(c.shape[1]) for c in cores]
+    ranks = [int(cores[0].shape[0])] + [int(c.shape[2]) for c in cores]
+    for c in cores:
+        if not c.is_cuda or c.dtype != torch.float64 or not c.is_contiguous():
+            raise TypeError("TT cores must be contiguous FP64 CUDA tensors")
+    cap = [1] + [min(max_rank, r) for r in ranks[1:-1]] + [1]
+    out = _tt_out(n, cap, cores[0].device)
+    nn = (ctypes.c_int64 * d)(*n)
+    rr = (ctypes.c_int64 * (d + 1))(*ranks)
+    cin = (ctypes.c_void_p * d)(*[c.data_ptr() for c in cores])
+    cout = (ctypes.c_void_p * d)(*[o.data_ptr() for o in out])
+    ro = (ctypes.c_int64 * (d + 1))()
+    st = _lib.qtt_tt_round(d, nn, rr, cin, float(eps), int(max_rank), int(seed), cout, ro, _stream(stream))
+    _check(st, allow=() if raise_on_cap else (QTT_ERR_RANK,))
+    r = list(ro)
+    return _tt_result(out, n, r), r, st
+
+
+@_on_stream
+def qtt_tt_compress(x, n, eps, max_rank=128, seed=1, stream=None, raise_on_cap=True):
+    """TT form of a full FP64 CUDA vector x (length prod n, first digit
+    fastest); returns (cores, ranks, status)."""
+    d = len(n)
+    if not x.is_cuda or x.dtype != torch.float64 or not x.is_contiguous() or x.numel() != int(np.prod(n)):
+        raise ValueError("x must be a contiguous FP64 CUDA vector of length prod(n)")
+    cap = [1]
+    left = 1
+    for k in range(d - 1):
+        left *= n[k]
+        cap.append(min(max_rank, left))
+    cap.append(1)
+    out = _tt_out(n, cap, x.device)
+    nn = (ctypes.c_int64 * d)(*n)
+    cout = (ctypes.c_void_p * d)(*[o.data_ptr() for o in out])
+    ro = (ctypes.c_int64 * (d + 1))()
+    st = _lib.qtt_tt_compress(d, nn, x.data_ptr(), float(eps), int(max_rank), int(seed), cout, ro, _stream(stream))
+    _check(st, allow=() if raise_on_cap else (QTT_ERR_RANK,))
+    r = list(ro)
+    return _tt_result(out, n, r), r, st
+
+
+def qtt_matrix_cores(A):
+    """The handle's FP64 cores as host numpy arrays (r, m, n, r')."""
+    out = [np.empty((A.ranks[k], A.m[k], A.n[k], A.ranks[k + 1])) for k in range(A.d)]
+    ptrs = (ctypes.c_void_p * A.d)(*[o.ctypes.data for o in out])
+    _check(_lib.qtt_matrix_cores(A.handle, ptrs))
+    return out
+
+
+@_on_stream
+def qtt_invert_newton_schulz(A, X0, eps, max_rank=128, max_iter=12, tol=0.0, theta=0.0, seed=1,
+                             dtypes=("fp64",), stream=None, raise_on_cap=True):
+    """Newton-Hotelling-Schulz inverse of A from X0; returns (handle,
+    history, steps, status)."""
+    flags = 0
+    for t in dtypes:
+        flags |= DTYPES[t]
+    out = ctypes.c_void_p()
+    hist = (ctypes.c_double * (max_iter + 1))()
+    steps = ctypes.c_int32()
+    st = _lib.qtt_invert_newton_schulz(A.handle, X0.handle, float(eps), int(max_rank), int(max_iter), float(tol),
+                                       float(theta), int(seed), flags, ctypes.byref(out), hist, ctypes.byref(steps),
+                                       _stream(stream))
+    _check(st, allow=() if raise_on_cap else (QTT_ERR_RANK,))
+    X = QttMatrix._from_handle(out.value)
+    return X, list(hist)[: steps.value + 1], steps.value, st

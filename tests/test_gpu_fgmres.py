@@ -1,5 +1,5 @@
 """GPU parity of the flexible GMRES outer solver (qtt_solve_fgmres) against
-the oracle's FGMRES (section 5.2: GMRES around the compressed inverse,
+the oracle's FGMRES (section 5.3: GMRES around the compressed inverse,
 relative-residual tolerance, no restart).
 
 With an FP64 preconditioner both sides run the same algorithm in FP64, so the
@@ -193,7 +193,7 @@ def test_fgmres_L7_full_size(Q):
 
 @pytest.mark.parametrize("inv", ["fp64", "bf16"])
 def test_fgmres_product_preconditioner(Q, inv):
-    """Section 5.2's product form Ainv = M Y, applied as two chained QTT
+    """Section 4.1's product form Ainv = M Y, applied as two chained QTT
     sweeps: M is the diagonal-free first-order inverse, Y a second
     perturbed-identity factor (ranks 4).  FP64: the oracle's FGMRES with the
     preconditioner v -> M (Y v) takes the same steps and finds the same

@@ -116,7 +116,7 @@ def test_nti_solve(Q, solver):
 
 
 def test_nti_volume_gaussians(Q):
-    """The section 5.1 non-translation-invariant volume test: the kernel part
+    """The section 5.2.2 non-translation-invariant volume test: the kernel part
     of the L=4 volume operator in QTT, b(x) = c(x) = 1 + exp(-|x - x0|^2)
     around the cube centre, a = 1."""
     L, N = 4, 4096

@@ -287,7 +287,7 @@ def test_richardson_volume_L4(volume_L4):
     assert _rel(X, ref) < 1e-8
 
 
-# ---------------------------------------------------------------- FGMRES (sec. 5.2)
+# ---------------------------------------------------------------- FGMRES (sec. 5.3)
 
 def _dense_problem(n, seed, shift=3.0):
     g = I.rng(seed)
@@ -440,7 +440,7 @@ def test_nti_apply_matches_assembled_qtt():
 
 @pytest.mark.slow
 def test_nti_volume_gaussians_vs_direct(volume_L4):
-    """The non-translation-invariant volume test of section 5.1: b(x) =
+    """The non-translation-invariant volume test of section 5.2.2: b(x) =
     1 + exp(-|x - x0|^2), c(y) likewise, around the cube centre; the kernel
     part (A - I of the volume operator, weights included) in QTT.  Against
     direct summation from the coordinates, within the TT-SVD error bound."""
