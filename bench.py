@@ -2,18 +2,22 @@
 """Benchmark: refined QTT-inverse solve on one MI355X.
 
 Workload (one "step"): solve A sigma = F for K = 8 right-hand sides at L = 7
-(N = 8^7 = 2,097,152), ranks [1,24,32,32,32,32,24,1], to relative residual
-1e-8 by iterative refinement with the compressed inverse: sigma += Ainv r in
-BF16 (FP32 accumulation), r = F - A sigma in FP64.  The same refinement with
-Ainv applied in FP64 ("plain FP64") is timed beside it, and the FP32 inverse
-as a third variant.  Operators are the seeded synthetic pair (A = perturbed
-identity, Ainv = its first-order inverse); F is seeded N(0,1); everything is
+(N = 8^7 = 2,097,152), A of ranks [1,24,32,32,32,32,24,1], to relative
+residual 1e-8 by iterative refinement with the compressed inverse:
+sigma += Ainv r in BF16 (FP32 accumulation), r = F - A sigma in FP64.  The
+compressed inverse (ranks <= 32) is computed in the untimed setup on the GPU
+by Newton-Hotelling-Schulz from the first-order inverse of the seeded
+operator pair.  The same refinement with Ainv applied in FP64 ("plain FP64")
+is timed beside it, and the FP32 inverse as a third variant; the first-order
+inverse is timed too, for comparison.  F is seeded N(0,1); everything is
 resident in HBM before timing starts.
 
 Prints ONE JSON line.  Extra keys beyond the driver contract: latency
 percentiles, the plain-FP64 and FP32-inverse runs, the roofline of the
-dominant kernel (the FP64 interior core step of the residual apply) and of
-the BF16 core step, and the CPU oracle baseline.
+dominant kernel (the FP64 core pair of the residual apply) and of the BF16
+core step, the flexible-GMRES solve, the operator with diagonals, the
+compressed product, uneven batching, serving traces, the compressed "QTT
+solve", and the CPU oracle baseline.
 """
 from __future__ import annotations
 
@@ -33,11 +37,13 @@ PEAK_FP32_TFLOPS = 157.3
 PEAK_BF16_TFLOPS = 2500.0
 PEAK_HBM_GBS = 8000.0
 # the sources whose hash the committed HBM-traffic figures are tied to: every
-# file the library is built from
+# file the sweep's kernels and their launches are built from (the TT-format
+# operations, qtt_tt*, are not part of a sweep)
 def kernel_sources():
     import glob
     csrc = os.path.join(ROOT, "paper_1511_06029_amd", "csrc")
-    return sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.hpp")))
+    files = glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.hpp"))
+    return sorted(f for f in files if not os.path.basename(f).startswith("qtt_tt"))
 
 
 def parse():
@@ -64,6 +70,8 @@ def parse():
                    help="skip the TT-format legs (compressed 'QTT solve' and Newton-Schulz inversion)")
     p.add_argument("--copy-probe", action="store_true",
                    help="only run a device copy of known size (HBM counter calibration)")
+    p.add_argument("--first-order-inverse", action="store_true",
+                   help="solve with the first-order inverse instead of the Newton-Schulz one")
     p.add_argument("--variants", default="bf16,fp64,fp32",
                    help="inverse dtypes to time; the first is the reported value")
     return p.parse_args()
@@ -101,8 +109,25 @@ def main():
     variants = [v.strip() for v in args.variants.split(",") if v.strip()]
 
     A = Q.qtt_matrix_load(Ac, dtypes=("fp64",))
-    Ai = Q.qtt_matrix_load(Aic, dtypes=tuple(sorted(set(variants) | {"fp64"})))
+    inv_dtypes = tuple(sorted(set(variants) | {"fp64"}))
+    Ai0 = Q.qtt_matrix_load(Aic, dtypes=inv_dtypes)
     F = Q.to_block(F_h)
+    # setup (untimed): the compressed inverse at the operator's ranks (<= 32),
+    # computed on the GPU by Newton-Hotelling-Schulz from the first-order
+    # inverse; the headline solves use it
+    torch.cuda.synchronize()
+    t_inv = time.perf_counter()
+    if args.first_order_inverse:
+        Ai, inv_info = Ai0, {"method": "first-order inverse (identity minus the perturbation)"}
+    else:
+        Ai, hist, ns_steps, _ = Q.qtt_invert_newton_schulz(A, Ai0, 1e-10, max_rank=32, max_iter=6, theta=0.1,
+                                                           seed=5, dtypes=inv_dtypes, raise_on_cap=False)
+        torch.cuda.synchronize()
+        inv_info = {"method": "Newton-Hotelling-Schulz on the GPU from the first-order inverse, ranks held at "
+                              "<= 32 (qtt_invert_newton_schulz, eps 1e-10, theta 0.1)",
+                    "seconds": round(time.perf_counter() - t_inv, 2), "steps": ns_steps,
+                    "residual_history": [float(f"{h:.3e}") for h in hist], "ranks": Ai.ranks}
+    Aic = Q.qtt_matrix_cores(Ai)
     Sig = Q.empty_block(N, K)
     ws_bytes = max(Q.qtt_solve_workspace_bytes(A, Ai, v, K) for v in variants)
     ws = Q.workspace(ws_bytes)
@@ -166,6 +191,26 @@ def main():
     head = variants[0]
     r0 = results[head]
 
+    # continuity: the same solves with the first-order inverse (the previous
+    # headline inverse), fewer steps
+    first_order = None
+    if not args.first_order_inverse:
+        first_order = {}
+        for v in ("bf16", "fp64"):
+            if v not in inv_dtypes:
+                continue
+            for _ in range(2):
+                Q.qtt_solve(A, Ai0, v, F, Sig, rtol=rtol, ws=ws, stream=stream)
+            torch.cuda.synchronize()
+            n_fo = max(3, args.steps // 4)
+            t0 = time.perf_counter()
+            for _ in range(n_fo):
+                _, info, _ = Q.qtt_solve(A, Ai0, v, F, Sig, rtol=rtol, ws=ws, stream=stream)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / n_fo
+            first_order[v] = {"rhs_per_s": round(K / dt, 3), "passes": max(c[0] for c in info),
+                              "max_rel_residual": max(c[1] for c in info)}
+
     def dominant(dt):
         """The kernel configuration that carries the most flops of dtype dt."""
         cand = [(r["flops"], sh, r) for (d, sh), r in r0["shapes"].items() if d == dt and r["launches"]]
@@ -208,7 +253,7 @@ def main():
 
     serving = None if args.no_serving else serving_run(Q, torch, args.serving_requests)
     qtt_solve_c = None if args.no_tt else qtt_solve_compressed_run(Q, torch, Aic)
-    ns = None if args.no_tt else newton_schulz_run(Q, torch, A, Ai, F, K, rtol, args)
+    ns = inv_info
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -233,7 +278,8 @@ def main():
         "dtype": f"{head}+f64",
         "data": "synthetic",
         "config": {"workload": "refine_L7: refined QTT-inverse solve, L=7 (N=2097152), mode 8x8, "
-                               "ranks [1,24,32,32,32,32,24,1], K=8 RHS per step, rtol 1e-8",
+                               "A ranks [1,24,32,32,32,32,24,1], inverse ranks <= 32 (computed on the GPU), "
+                               "K=8 RHS per step, rtol 1e-8",
                    "inverse_dtype": head, "residual_dtype": "fp64", "rhs_per_step": K,
                    "N": N, "L": L, "ranks": ranks},
         "latency_ms": {"p50": round(r0["p50_ms"], 3), "p99": round(r0["p99_ms"], 3)},
@@ -254,12 +300,15 @@ def main():
         "batched_uneven_L7": batched,
         "serving": serving,
         "qtt_solve_compressed_L7": qtt_solve_c,
-        "newton_schulz_inverse_L7": ns,
+        "inverse": ns,
+        "first_order_inverse": first_order,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
     A.free()
     Ai.free()
+    if Ai is not Ai0:
+        Ai0.free()
 
 
 def compressed_run(Q, torch, Ac, nvec=64, rank=8, reps=20):
@@ -480,7 +529,7 @@ def serving_run(Q, torch, n_requests):
     return out
 
 
-def qtt_solve_compressed_run(Q, torch, Aic, eps=1e-4, reps=3):
+def qtt_solve_compressed_run(Q, torch, Aic, eps=1e-4, eps_round=1e-3, reps=3):
     """The "QTT solve" of section 5.2 at L=7 on the GPU: compress the right-hand
     side f = phi(x) phi(y) phi(z), phi(t) = diric(2 pi t, 10), into TT form,
     take the compressed product with the compressed inverse (ranks multiply),
@@ -513,7 +562,7 @@ def qtt_solve_compressed_run(Q, torch, Aic, eps=1e-4, reps=3):
         prod = [Cc[0].contiguous() for Cc in C]
         torch.cuda.synchronize()
         t2 = time.perf_counter()
-        cores, ranks, st = Q.qtt_tt_round(prod, eps, seed=4, raise_on_cap=False)
+        cores, ranks, st = Q.qtt_tt_round(prod, eps_round, seed=4, raise_on_cap=False)
         torch.cuda.synchronize()
         t3 = time.perf_counter()
         if rep > 0:
@@ -534,44 +583,12 @@ def qtt_solve_compressed_run(Q, torch, Aic, eps=1e-4, reps=3):
     err = float((v - y).norm() / y.norm())
     Ai.free()
     med = {k: round(float(np.median(x)), 2) for k, x in times.items()}
-    return {"eps": eps, "rhs_ranks": fr, "product_ranks": pr, "rounded_ranks": ranks,
+    return {"eps_compress": eps, "eps_round": eps_round, "rhs_ranks": fr, "product_ranks": pr, "rounded_ranks": ranks,
             "rank_cap_reached": st == 9, **med,
             "total_ms": round(sum(med.values()), 2),
             "rel_error_vs_full_apply": err,
             "config": "L=7 (N=2097152), diric RHS (section 5.2), inverse ranks [1,24,32,32,32,32,24,1]; "
-                      "compress, compressed product, round, each at relative accuracy eps"}
-
-
-def newton_schulz_run(Q, torch, A, Ai0, F, K, rtol, args, rank_cap=32, eps=1e-10, max_iter=6):
-    """QTT inversion on the GPU (Newton-Hotelling-Schulz from the first-order
-    inverse, every rounding held to the inverse's ranks, at most rank_cap): its
-    time, the residual history ||I - A X|| / ||I||, and the refined solve of the
-    headline workload with it (BF16 and FP64 inverse) against the first-order
-    inverse."""
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    X, hist, steps, st = Q.qtt_invert_newton_schulz(A, Ai0, eps, max_rank=rank_cap, max_iter=max_iter,
-                                                    theta=0.1, seed=5, dtypes=("fp64", "bf16", "fp32"),
-                                                    raise_on_cap=False)
-    torch.cuda.synchronize()
-    t_inv = time.perf_counter() - t0
-    res = {"seconds": round(t_inv, 2), "steps": steps, "history": [float(f"{h:.3e}") for h in hist],
-           "ranks": X.ranks, "rank_cap": rank_cap, "eps": eps}
-    ws = Q.workspace(max(Q.qtt_solve_workspace_bytes(A, X, v, K) for v in ("bf16", "fp32", "fp64")))
-    Sig = Q.empty_block(F.shape[0], K)
-    for v in ("bf16", "fp32", "fp64"):
-        for _ in range(2):
-            Q.qtt_solve(A, X, v, F, Sig, rtol=rtol, ws=ws)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(max(3, args.steps // 4)):
-            _, info, _ = Q.qtt_solve(A, X, v, F, Sig, rtol=rtol, ws=ws)
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / max(3, args.steps // 4)
-        res[f"solve_{v}"] = {"rhs_per_s": round(K / dt, 3), "passes": max(c[0] for c in info),
-                             "max_rel_residual": max(c[1] for c in info)}
-    X.free()
-    return res
+                      "compress (eps_compress), compressed product, round (eps_round)"}
 
 
 def _round_stats(st):

@@ -99,6 +99,22 @@ unsigned grid_for(int64_t work, int64_t per_block = 256) {
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>((work + per_block - 1) / per_block, 65535));
 }
 
+#define QTT_CHECK(expr)                 \
+  do {                                  \
+    qtt_status_t s_ = (expr);           \
+    if (s_ != QTT_OK) return s_;        \
+  } while (0)
+
+const void* gemm_fn(bool ta, bool tb) {
+  return ta ? (tb ? reinterpret_cast<const void*>(&gemm_kernel<true, true>)
+                  : reinterpret_cast<const void*>(&gemm_kernel<true, false>))
+            : (tb ? reinterpret_cast<const void*>(&gemm_kernel<false, true>)
+                  : reinterpret_cast<const void*>(&gemm_kernel<false, false>));
+}
+
+// C = alpha op(A) op(B) + beta C (see gemm_kernel).  Products with few output
+// tiles and a long contraction are split over the contraction (partial
+// products in scratch, then summed in split order) so that they fill the GPU.
 qtt_status_t gemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
                   const double* B, int64_t ldb, double beta, double* C, int64_t ldc, hipStream_t st) {
   if (M <= 0 || N <= 0) return QTT_OK;
@@ -118,12 +134,28 @@ qtt_status_t gemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alph
   g.tiles_n = (N + kGemmT - 1) / kGemmT;
   const int64_t tiles = ((M + kGemmT - 1) / kGemmT) * g.tiles_n;
   if (tiles > INT32_MAX) return fail(QTT_ERR_SHAPE, "product of %lld x %lld too large", (long long)M, (long long)N);
-  const void* fn = ta ? (tb ? reinterpret_cast<const void*>(&gemm_kernel<true, true>)
-                            : reinterpret_cast<const void*>(&gemm_kernel<true, false>))
-                      : (tb ? reinterpret_cast<const void*>(&gemm_kernel<false, true>)
-                            : reinterpret_cast<const void*>(&gemm_kernel<false, false>));
+  int64_t splits = 1;
+  if (tiles < 512 && K >= 4096) splits = std::min<int64_t>({(1024 + tiles - 1) / tiles, K / 1024, 256});
+  if (splits <= 1) {
+    void* args[] = {&g};
+    HIP_TRY(hipLaunchKernel(gemm_fn(ta, tb), dim3((unsigned)tiles, 1), dim3(256), args, 0, st));
+    return QTT_OK;
+  }
+  DBuf P;
+  QTT_CHECK(dalloc(P, splits * M * N));
+  g.C = P.p;
+  g.ldc = N;
+  g.sC = M * N;
+  g.beta = 0.0;
+  g.ksplit = ((K + splits - 1) / splits + kGemmK - 1) / kGemmK * kGemmK;
+  splits = (K + g.ksplit - 1) / g.ksplit;
   void* args[] = {&g};
-  HIP_TRY(hipLaunchKernel(fn, dim3((unsigned)tiles, 1), dim3(256), args, 0, st));
+  HIP_TRY(hipLaunchKernel(gemm_fn(ta, tb), dim3((unsigned)tiles, (unsigned)splits), dim3(256), args, 0, st));
+  SplitSumArgs ss{P.p, C, M, N, ldc, splits, beta};
+  void* args2[] = {&ss};
+  HIP_TRY(hipLaunchKernel(reinterpret_cast<const void*>(&split_sum_kernel), dim3(grid_for(M * N)), dim3(256), args2,
+                          0, st));
+  HIP_TRY(hipStreamSynchronize(st));       // P is freed on return
   return QTT_OK;
 }
 
@@ -162,11 +194,6 @@ qtt_status_t launch1d(const void* fn, Args a, int64_t work, hipStream_t st) {
   return QTT_OK;
 }
 
-#define QTT_CHECK(expr)                 \
-  do {                                  \
-    qtt_status_t s_ = (expr);           \
-    if (s_ != QTT_OK) return s_;        \
-  } while (0)
 
 // Smallest r >= 1 whose discarded singular values s_r, s_{r+1}, ... (sorted
 // descending) have Euclidean norm <= delta (Algorithm 1's rank rule).

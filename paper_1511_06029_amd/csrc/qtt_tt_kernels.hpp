@@ -39,6 +39,8 @@ struct GemmArgs {
   int64_t lda, ldb, ldc;
   int64_t sA, sB, sC;
   int64_t tiles_n;      // column tiles (N / 64 rounded up)
+  int64_t ksplit;       // > 0: split of the contraction blockIdx.y works on
+                        // (indices [y ksplit, min(K, (y + 1) ksplit)), C + y sC)
   double alpha, beta;
 };
 
@@ -54,13 +56,15 @@ __global__ void __launch_bounds__(256) gemm_kernel(const GemmArgs a) {
   const double* A = a.A + (int64_t)blockIdx.y * a.sA;
   const double* B = a.B + (int64_t)blockIdx.y * a.sB;
   double* C = a.C + (int64_t)blockIdx.y * a.sC;
+  const int64_t kbeg = a.ksplit > 0 ? (int64_t)blockIdx.y * a.ksplit : 0;
+  const int64_t kend = a.ksplit > 0 ? (kbeg + a.ksplit < a.K ? kbeg + a.ksplit : a.K) : a.K;
   const int ty = tid >> 4, tx = tid & 15;   // rows 4 ty .. 4 ty + 3, columns 4 tx .. 4 tx + 3
   double acc[4][4];
 #pragma unroll
   for (int r = 0; r < 4; ++r)
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[r][c] = 0.0;
-  for (int64_t k0 = 0; k0 < a.K; k0 += kGemmK) {
+  for (int64_t k0 = kbeg; k0 < kend; k0 += kGemmK) {
     // A tile: 64 rows x 16 contraction indices, 4 values per thread
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
@@ -69,7 +73,7 @@ __global__ void __launch_bounds__(256) gemm_kernel(const GemmArgs a) {
       else { i = tid >> 2; kk = (tid & 3) * 4 + e; }         // consecutive k along memory
       const int64_t gi = m0 + i, gk = k0 + kk;
       double v = 0.0;
-      if (gi < a.M && gk < a.K) v = TA ? A[gk * a.lda + gi] : A[gi * a.lda + gk];
+      if (gi < a.M && gk < kend) v = TA ? A[gk * a.lda + gi] : A[gi * a.lda + gk];
       As[kk][i] = v;
     }
     // B tile: 16 contraction indices x 64 columns
@@ -80,7 +84,7 @@ __global__ void __launch_bounds__(256) gemm_kernel(const GemmArgs a) {
       else { kk = tid >> 4; j = (tid & 15) * 4 + e; }
       const int64_t gj = n0 + j, gk = k0 + kk;
       double v = 0.0;
-      if (gj < a.N && gk < a.K) v = TB ? B[gj * a.ldb + gk] : B[gk * a.ldb + gj];
+      if (gj < a.N && gk < kend) v = TB ? B[gj * a.ldb + gk] : B[gk * a.ldb + gj];
       Bs[kk][j] = v;
     }
     __syncthreads();
@@ -109,6 +113,25 @@ __global__ void __launch_bounds__(256) gemm_kernel(const GemmArgs a) {
       double* p = C + gi * a.ldc + gj;
       *p = a.beta == 0.0 ? a.alpha * acc[r][c] : a.alpha * acc[r][c] + a.beta * *p;
     }
+  }
+}
+
+// C[i ldc + j] = sum_s P[s][i N + j] + beta C[i ldc + j]: the partial products
+// of a split contraction, added in split order.
+struct SplitSumArgs {
+  const double* P;
+  double* C;
+  int64_t M, N, ldc, splits;
+  double beta;
+};
+
+__global__ void __launch_bounds__(256) split_sum_kernel(const SplitSumArgs a) {
+  const int64_t MN = a.M * a.N;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < MN; e += (int64_t)gridDim.x * 256) {
+    double t = 0.0;
+    for (int64_t s2 = 0; s2 < a.splits; ++s2) t += a.P[s2 * MN + e];
+    double* c = a.C + (e / a.N) * a.ldc + e % a.N;
+    *c = a.beta == 0.0 ? t : t + a.beta * *c;
   }
 }
 
