@@ -237,9 +237,10 @@ def main():
         if lo is not None:
             gbs = lo["bytes"] / lo["ms"] * 1e-6
             tfs = lo["flops"] / lo["ms"] * 1e-9
-            _, klo = measured_traffic(head, shlo)
+            tlo, klo = measured_traffic(head, shlo)
             roof_lo = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                        "frac": round(gbs / PEAK_HBM_GBS, 4), "tflops": round(tfs, 2),
+                       "traffic": (None if (tlo is None or args.tune) else tlo),
                        "kernel": (f"{head} core step, configuration {shlo}" + (f" ({klo})" if klo else "")
                                   + ", the one carrying most of the inverse apply's flops"),
                        "launches": lo["launches"], "avg_launch_ms": round(lo["ms"] / lo["launches"], 4)}
