@@ -27,6 +27,7 @@ const void* smallk_kernel(int dt) {
   switch (dt) {
     case 0: return reinterpret_cast<const void*>(&core_step_smallk_kernel<double>);
     case 1: return reinterpret_cast<const void*>(&core_step_smallk_kernel<float>);
+    case 3: return reinterpret_cast<const void*>(&core_step_smallk_bf16_kernel<8>);
     default: return reinterpret_cast<const void*>(&core_step_smallk_kernel<bf16_tag>);
   }
 }

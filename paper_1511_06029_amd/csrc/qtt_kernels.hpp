@@ -220,7 +220,13 @@ core_step_kernel(const StepArgs args) {
   constexpr int NLOAD = (TC * VPC + NT - 1) / NT;
   using ld_t = typename std::conditional<VEC, v4u, Tin>::type;
 
-  __shared__ __attribute__((aligned(16))) elem lds[(TC / 16) * SPC * 64 * E];
+  // Fragment (column block, step) blocks of 64 lanes x E elements.  For
+  // BF16, 16 bytes of padding after each 16-lane group move the 16 lanes
+  // that store one column's chunk (4 steps x 4 groups, 256 bytes apart
+  // unpadded) onto distinct banks; the fragment reads stay contiguous.
+  constexpr int PADQ = std::is_same<Tc, bf16_tag>::value ? E : 0;
+  constexpr int BLK = 64 * E + 4 * PADQ;
+  __shared__ __attribute__((aligned(16))) elem lds[(TC / 16) * SPC * BLK];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -289,7 +295,7 @@ core_step_kernel(const StepArgs args) {
             elem val;
             if constexpr (std::is_same<Tin, double>::value) val = MF::from_double(v[e]);
             else val = *reinterpret_cast<const elem*>(&v[e]);
-            lds[((cb * SPC + s) * 64 + cl + 16 * gq) * E + ee] = val;
+            lds[(cb * SPC + s) * BLK + (cl + 16 * gq) * E + gq * PADQ + ee] = val;
           }
         }
       }
@@ -317,7 +323,7 @@ core_step_kernel(const StepArgs args) {
         frag af[WC];
 #pragma unroll
         for (int j = 0; j < WC; ++j)
-          af[j] = MF::load_frag(&lds[(((wc * WC + j) * SPC + s) * 64 + lane) * E]);
+          af[j] = MF::load_frag(&lds[((wc * WC + j) * SPC + s) * BLK + lane * E + (lane >> 4) * PADQ]);
 #pragma unroll
         for (int i = 0; i < WR; ++i)
 #pragma unroll
@@ -848,7 +854,12 @@ core_step_f64q_kernel(const StepArgs args) {
 // alias the start of the LDS tile), from the packed intermediate or, with
 // FIRST, from the caller's FP64 vectors through the segment table (core 0);
 // both steps take core fragments through buffer resources with a ring of
-// prefetched steps.  Step k + 1 covers 64 WRB rows.
+// prefetched steps.  Step k + 1 covers 64 WRB rows.  With PIPE, each step
+// reads the next step's input fragments from LDS while its own matrix
+// instructions run, and the core-fragment and input prefetches past the end
+// are clamped re-reads instead of branches, so that a whole chunk is one
+// block the compiler can schedule across steps (4% faster for the interior
+// pairs at r = 32; results bitwise those of the plain schedule).
 // Requirements checked by the host: the conditions above, R_out(k + 1) <=
 // 64 WRB, step counts multiples of the chunk (step k) and of 8 (step k + 1),
 // C_k % 32 == 0, K_in(k) even with 16-byte aligned columns, both fragment
@@ -873,7 +884,7 @@ struct PairArgs {
   const Segment* seg;    // device table of nseg segments
 };
 
-template <int RA, int WRB, bool FIRST, int KCA, int PF, bool PAD = false>
+template <int RA, int WRB, bool FIRST, int KCA, int PF, bool PAD = false, bool PIPE = false>
 __global__ void __launch_bounds__(256, 2) core_pair_f64q_kernel(const PairArgs args) {
   (void)args;
   const PairArgs& a = kernarg<PairArgs>();
@@ -917,7 +928,14 @@ __global__ void __launch_bounds__(256, 2) core_pair_f64q_kernel(const PairArgs a
       const int kap = kc0 + (idx % VPC) * 2;
       const int64_t g = col0 + c;
       sa[t] = v4u{};
-      if (idx < TC * VPC && g < a.ncols && kap < a.K_inA) {
+      // PIPE, not FIRST: idx and g are in range by construction (TC * VPC a
+      // multiple of NT; the host requires C % 32 == 0, so every column of a
+      // tile below n_tiles exists); the contraction index may pass K_in
+      // where the core's steps were padded
+      const bool inside = (PIPE && !FIRST && (TC * VPC) % NT == 0)
+                              ? (kap < a.K_inA)
+                              : (idx < TC * VPC && g < a.ncols && kap < a.K_inA);
+      if (inside) {
         const int64_t rhs = g / a.C;
         const int64_t q = g - rhs * a.C;
         const double* p;
@@ -983,17 +1001,39 @@ __global__ void __launch_bounds__(256, 2) core_pair_f64q_kernel(const PairArgs a
       __syncthreads();
       for (int ch = 0; ch < nchA; ++ch) {
         const double* S = lds + (ch & 1) * A_ELEMS;
+        double afn[WQ];
+        if constexpr (PIPE) {
+#pragma unroll
+          for (int j = 0; j < WQ; ++j) afn[j] = S[(j * SPA) * kQGS + rd];
+        }
 #pragma unroll
         for (int s = 0; s < SPA; ++s) {
           double af[WQ];
+          if constexpr (PIPE) {
+            // the next step's input fragments are read while this step's
+            // instructions run; core fragments past the end are re-reads
+            // of the last step (clamped: no branch in the chunk)
 #pragma unroll
-          for (int j = 0; j < WQ; ++j) af[j] = S[(j * SPA + s) * kQGS + rd];
+            for (int j = 0; j < WQ; ++j) af[j] = afn[j];
+            if (s + 1 < SPA) {
+#pragma unroll
+              for (int j = 0; j < WQ; ++j) afn[j] = S[(j * SPA + s + 1) * kQGS + rd];
+            }
+          } else {
+#pragma unroll
+            for (int j = 0; j < WQ; ++j) af[j] = S[(j * SPA + s) * kQGS + rd];
+          }
           double bc[WRA];
 #pragma unroll
           for (int i = 0; i < WRA; ++i) bc[i] = ring[s % PFA][i];
           const int gs = ch * SPA + s + PFA;
-          if (gs < a.KsA) loadA(ring[s % PFA], gs);
-          if (s == 0 && ch + 1 < nchA) gload(tile, ch + 1);
+          if constexpr (PIPE) {
+            loadA(ring[s % PFA], gs < a.KsA ? gs : a.KsA - 1);
+            if (s == 0) gload(tile, ch + 1 < nchA ? ch + 1 : ch);
+          } else {
+            if (gs < a.KsA) loadA(ring[s % PFA], gs);
+            if (s == 0 && ch + 1 < nchA) gload(tile, ch + 1);
+          }
 #pragma unroll
           for (int i = 0; i < WRA; ++i)
 #pragma unroll
@@ -1040,17 +1080,31 @@ __global__ void __launch_bounds__(256, 2) core_pair_f64q_kernel(const PairArgs a
 #pragma unroll
       for (int j = 0; j < WQ; ++j) acc[i][j] = 0.0;
     __syncthreads();
+    double bfn[WQ];
+    if constexpr (PIPE) {
+#pragma unroll
+      for (int j = 0; j < WQ; ++j) bfn[j] = lds[(j * KSB) * kQGS + rd];
+    }
     for (int c8 = 0; c8 < ksb / SPB; ++c8) {
 #pragma unroll
       for (int s = 0; s < SPB; ++s) {
         const int gs = c8 * SPB + s;
         double af[WQ];
+        if constexpr (PIPE) {
+          const int gn = gs + 1 < ksb ? gs + 1 : ksb - 1;
 #pragma unroll
-        for (int j = 0; j < WQ; ++j) af[j] = lds[(j * KSB + gs) * kQGS + rd];
+          for (int j = 0; j < WQ; ++j) af[j] = bfn[j];
+#pragma unroll
+          for (int j = 0; j < WQ; ++j) bfn[j] = lds[(j * KSB + gn) * kQGS + rd];
+        } else {
+#pragma unroll
+          for (int j = 0; j < WQ; ++j) af[j] = lds[(j * KSB + gs) * kQGS + rd];
+        }
         double bc[WRB];
 #pragma unroll
         for (int i = 0; i < WRB; ++i) bc[i] = ring[s % PF][i];
-        if (gs + PF < ksb) loadB(ring[s % PF], gs + PF);
+        if constexpr (PIPE) loadB(ring[s % PF], gs + PF < ksb ? gs + PF : ksb - 1);
+        else if (gs + PF < ksb) loadB(ring[s % PF], gs + PF);
 #pragma unroll
         for (int i = 0; i < WRB; ++i)
 #pragma unroll
@@ -1919,6 +1973,103 @@ __global__ void __launch_bounds__(256) core_step_smallk_kernel(const StepArgs ar
     for (int idx = tid; idx < m * per_i; idx += NT) {
       const int ir = idx / per_i, v = idx - ir * per_i;
       reinterpret_cast<v4u*>(dst + (int64_t)r * a.C * ir)[v] = reinterpret_cast<const v4u*>(st + ir * (r * TQ))[v];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The first BF16 core with K_in <= 8 (r_0 = 1), rows held in registers.
+//
+// Thread (wave w, lane l): row quad aq = l mod 8 (rows 4 aq .. 4 aq + 3 of an
+// i_1 block; active when 4 aq < r_1) and column offset qq = l div 8, for the
+// two blocks i_1 = 2 w, 2 w + 1.  A tile is 64 columns; the thread computes
+// columns qq + 8 t, t = 0..7, of both blocks.  Each output is the FMA chain
+// over k = 0 .. K_in - 1 in order on the BF16-rounded input (the chain of
+// core_step_smallk_kernel, so the two agree bitwise).  Its four rows leave as
+// one 8-byte store: with r_1 = 32, the 8 columns x 8 row quads of a wave are
+// one contiguous 512-byte run of y_1, and no output passes through LDS.  The
+// input is staged in LDS as rounded floats, two buffers (one barrier a tile).
+// Requirements checked by the host: first core, not the last, K_in <= 8,
+// r_1 % 4 == 0, r_1 <= 32, m_1 = R_out / r_1 <= 8, C_1 % 64 == 0, FP64
+// input columns 16-byte aligned with an even K_in, output 16-byte aligned.
+// ---------------------------------------------------------------------------
+template <int MAXK>
+__global__ void __launch_bounds__(256) core_step_smallk_bf16_kernel(const StepArgs args) {
+  (void)args;
+  const StepArgs& a = kernarg<StepArgs>();
+  using S = SmallK<bf16_tag>;
+  constexpr int TQ = 64;
+  __shared__ __attribute__((aligned(16))) float xs[2][TQ * MAXK];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int K = a.K_in, r = a.r_out, m = a.R_out / a.r_out;
+  const int Ks = a.Ksteps;
+  const int aq = lane & 7, qq = lane >> 3;
+  const bool act = 4 * aq < r;
+  float Mr[2][4][MAXK];
+#pragma unroll
+  for (int ii = 0; ii < 2; ++ii)
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+      for (int k = 0; k < MAXK; ++k) {
+        const int i = 2 * w + ii, row = r * i + 4 * aq + e;
+        const int l = (row & 15) + 16 * ((k % S::KS) / S::E);
+        Mr[ii][e][k] = (act && i < m && k < K)
+                           ? S::load_core(a.M, (((int64_t)(row >> 4) * Ks + k / S::KS) * 64 + l) * S::E + k % S::E)
+                           : 0.f;
+      }
+  const int64_t ntiles = a.n_tiles;
+  const int nvec = TQ * K / 2;                      // 16-byte input loads per tile
+  v4u pre = v4u{};
+  auto gload = [&](int64_t tile) {
+    const int64_t col0 = tile * TQ;
+    const int64_t rhs = col0 / a.C;
+    const int64_t q0 = col0 - rhs * a.C;
+    const Segment& sg = a.seg[find_seg(a, rhs)];
+    const v4u* src = reinterpret_cast<const v4u*>(reinterpret_cast<const double*>(sg.x) +
+                                                  (rhs - sg.rhs_begin) * sg.ldx + q0 * K);
+    if (tid < nvec) pre = src[tid];
+  };
+  if ((int64_t)blockIdx.x < ntiles) gload(blockIdx.x);
+  int buf = 0;
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x, buf ^= 1) {
+    // the buffer was last read two tiles ago, before the previous barrier
+    if (tid < nvec) {
+      typedef double v2d __attribute__((ext_vector_type(2)));
+      const v2d d = __builtin_bit_cast(v2d, pre);
+      xs[buf][2 * tid] = S::round_in(d[0]);
+      xs[buf][2 * tid + 1] = S::round_in(d[1]);
+    }
+    __syncthreads();
+    if (tile + gridDim.x < ntiles) gload(tile + gridDim.x);
+    const int64_t col0 = tile * TQ;
+    const int64_t rhs = col0 / a.C;
+    const int64_t q0 = col0 - rhs * a.C;
+    uint16_t* dst = reinterpret_cast<uint16_t*>(a.out) + rhs * a.out_stride + (int64_t)r * q0 + 4 * aq;
+    const float* X = xs[buf];
+#pragma unroll 2
+    for (int t = 0; t < TQ / 8; ++t) {
+      const int q = qq + 8 * t;
+      float xv[MAXK];
+#pragma unroll
+      for (int k = 0; k < MAXK; ++k) xv[k] = (k < K) ? X[q * K + k] : 0.f;
+#pragma unroll
+      for (int ii = 0; ii < 2; ++ii) {
+        const int i = 2 * w + ii;
+        if (!act || i >= m) continue;
+        float v[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int k = 0; k < MAXK; ++k) {
+          if (k < K) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v[e] = fma(Mr[ii][e][k], xv[k], v[e]);
+          }
+        }
+        uint2 o;
+        o.x = (uint32_t)S::to_out(v[0]) | ((uint32_t)S::to_out(v[1]) << 16);
+        o.y = (uint32_t)S::to_out(v[2]) | ((uint32_t)S::to_out(v[3]) << 16);
+        *reinterpret_cast<uint2*>(dst + (int64_t)r * (q + a.C * i)) = o;
+      }
     }
   }
 }

@@ -43,7 +43,8 @@ const void* bf16_dma_kernel(int tcb);
 // 6 first + 2 (0: rank 24, 1: rank 32, 2: padded 17..32) + (rows of core k + 1 > 192)
 const void* pair_f64_kernel(int f);
 const void* pair_f32_kernel(int f);
-// FP64 vector-ALU kernels and the short-contraction first core (qtt_k_misc.hip)
+// FP64 vector-ALU kernels and the short-contraction first core (qtt_k_misc.hip;
+// smallk_kernel(3): the BF16 first core with rows in registers)
 void add_valu_kernels(std::vector<ValuCfg>& v);
 const void* smallk_kernel(int dt);
 

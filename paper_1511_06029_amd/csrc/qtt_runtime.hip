@@ -197,6 +197,27 @@ static KernelCfg* smallk_cfg(int dt) {
   return &k[dt];
 }
 
+// The BF16 first core with rows in registers (core_step_smallk_bf16_kernel):
+// also configuration 34, 64-column tiles.
+static KernelCfg* smallk_rows_cfg() {
+  static KernelCfg k = [] {
+    KernelCfg c = {};
+    c.dt = 2;
+    c.in_f64 = true;
+    c.vec = true;
+    c.TR = 256;
+    c.TC = 64;
+    c.KC = 8;
+    c.NT = 256;
+    c.id = kSmallK;
+    c.fn = smallk_kernel(3);
+    c.occ = 0;
+    c.kind = -1;
+    return c;
+  }();
+  return &k;
+}
+
 static int num_cus() {
   static int n = [] {
     int dev = 0, cus = 0;
@@ -422,7 +443,10 @@ static qtt_status_t launch_step(const qtt_matrix_s* A, int k, int dt, int64_t nr
                          c.r_out % 4 == 0 && c.C % tq == 0 && (c.r_out * tq * kElemBytes[dt]) % 16 == 0 &&
                          reinterpret_cast<uintptr_t>(out_packed) % 16 == 0;
   if (shape == kSmallK && !smallk_ok) shape = (dt == 0) ? 67 : 26;   // first-core matrix-core kernels
-  KernelCfg* kc = (shape == kSmallK) ? smallk_cfg(dt)
+  const bool smallk_rows = shape == kSmallK && dt == 2 && c.K_in <= 8 && c.r_out <= 32 &&
+                           c.R_out / c.r_out <= 8 && c.C % 64 == 0;
+  KernelCfg* kc = smallk_rows ? smallk_rows_cfg()
+                  : (shape == kSmallK) ? smallk_cfg(dt)
                   : (shape == kBf16Dma) ? bf16_dma_cfg()
                   : (shape == kBf16Dma32) ? bf16_dma32_cfg()
                   : (shape == kBf16Resident) ? bf16_resident_cfg()
