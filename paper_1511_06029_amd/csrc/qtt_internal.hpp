@@ -65,6 +65,7 @@ struct qtt_matrix_s {
     std::string key;
     hipGraph_t graph;
     hipGraphExec_t exec;
+    hipEvent_t done;   // recorded after each launch: waited on before destruction
   };
   mutable std::mutex graph_mu;
   mutable std::vector<Graph> graphs;   // most recent last

@@ -4,21 +4,22 @@
 
 namespace qtt {
 
-// (id, waves, rows per wave, columns per lane, input group size)
+// (id, waves, rows per wave, columns per lane, input group size, groups per load)
 #define QTT_VALU_SHAPES(X)   \
-  X(40, 8, 24, 1, 8)         \
-  X(41, 4, 24, 2, 8)         \
-  X(42, 4, 32, 1, 8)         \
-  X(43, 4, 16, 1, 8)         \
-  X(44, 8, 16, 1, 8)         \
-  X(45, 1, 8, 4, 8)          \
-  X(46, 2, 8, 2, 8)          \
-  X(47, 1, 8, 2, 8)          \
-  X(48, 4, 16, 1, 1)
+  X(40, 8, 24, 1, 8, 1)      \
+  X(41, 4, 24, 2, 8, 1)      \
+  X(42, 4, 32, 1, 8, 1)      \
+  X(43, 4, 16, 1, 8, 1)      \
+  X(44, 8, 16, 1, 8, 1)      \
+  X(45, 1, 8, 4, 8, 1)       \
+  X(46, 2, 8, 2, 8, 1)       \
+  X(47, 1, 8, 2, 8, 1)       \
+  X(48, 4, 16, 1, 1, 1)      \
+  X(49, 1, 8, 2, 8, 2)
 
 void add_valu_kernels(std::vector<ValuCfg>& v) {
-#define QTT_ADDV(id, nw, rw, cpl, nj) \
-  v.push_back({id, nw, rw, cpl, nj, reinterpret_cast<const void*>(&core_step_valu64_kernel<nw, rw, cpl, nj>), 0});
+#define QTT_ADDV(id, nw, rw, cpl, nj, lg) \
+  v.push_back({id, nw, rw, cpl, nj, lg, reinterpret_cast<const void*>(&core_step_valu64_kernel<nw, rw, cpl, nj, lg>), 0});
   QTT_VALU_SHAPES(QTT_ADDV)
 #undef QTT_ADDV
 }

@@ -1391,7 +1391,11 @@ struct ValuArgs {
   const Segment* seg;    // device table of nseg segments
 };
 
-template <int NW, int RW, int CPL, int G>
+// LG > 1: each step loads LG consecutive groups of a column at once (LG G
+// values, 128 bytes for G = 8, LG = 2: whole cache lines, so a line is never
+// read in halves far apart in time); the FMA chain is unchanged (K_in % (G LG)
+// == 0 is checked by the host).
+template <int NW, int RW, int CPL, int G, int LG = 1>
 __global__ void __launch_bounds__(64 * NW) core_step_valu64_kernel(const ValuArgs args) {
   (void)args;
   const ValuArgs& a = kernarg<ValuArgs>();
@@ -1399,7 +1403,7 @@ __global__ void __launch_bounds__(64 * NW) core_step_valu64_kernel(const ValuArg
   // wave index made provably uniform, so core addresses go through scalar loads
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   constexpr int TCOL = 64 * CPL;
-  const int ngroups = a.K_in / G;
+  const int ngroups = a.K_in / (G * LG);
   for (int64_t tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
     const int rt = (int)(tile % a.n_row_tiles);
     const int64_t col0 = (tile / a.n_row_tiles) * TCOL;
@@ -1437,37 +1441,41 @@ __global__ void __launch_bounds__(64 * NW) core_step_valu64_kernel(const ValuArg
 #pragma unroll
       for (int c = 0; c < CPL; ++c) acc[r][c] = 0.0;
 
-    double x[CPL][G];
+    constexpr int GL = G * LG;
+    double x[CPL][GL];
     auto load_x = [&](int gi) {
 #pragma unroll
       for (int c = 0; c < CPL; ++c) {
-        const double* p = xin[c] + (int64_t)gi * G;
+        const double* p = xin[c] + (int64_t)gi * GL;
         if constexpr (G > 1) p = static_cast<const double*>(__builtin_assume_aligned(p, 16));
 #pragma unroll
-        for (int e = 0; e < G; ++e) x[c][e] = p[e];
+        for (int e = 0; e < GL; ++e) x[c][e] = p[e];
         if (!ok[c]) {
 #pragma unroll
-          for (int e = 0; e < G; ++e) x[c][e] = 0.0;
+          for (int e = 0; e < GL; ++e) x[c][e] = 0.0;
         }
       }
     };
     load_x(0);
     for (int gi = 0; gi < ngroups; ++gi) {
-      double xc[CPL][G];
+      double xc[CPL][GL];
 #pragma unroll
       for (int c = 0; c < CPL; ++c)
 #pragma unroll
-        for (int e = 0; e < G; ++e) xc[c][e] = x[c][e];
+        for (int e = 0; e < GL; ++e) xc[c][e] = x[c][e];
       if (gi + 1 < ngroups) load_x(gi + 1);
-      const cdouble* mrow = (const cdouble*)a.M + ((int64_t)gi * a.Rpad + row0) * G;
 #pragma unroll
-      for (int r = 0; r < RW; ++r)
+      for (int lg = 0; lg < LG; ++lg) {
+        const cdouble* mrow = (const cdouble*)a.M + ((int64_t)(gi * LG + lg) * a.Rpad + row0) * G;
 #pragma unroll
-        for (int e = 0; e < G; ++e) {
-          const double mv = mrow[r * G + e];
+        for (int r = 0; r < RW; ++r)
 #pragma unroll
-          for (int c = 0; c < CPL; ++c) acc[r][c] = fma(mv, xc[c][e], acc[r][c]);
-        }
+          for (int e = 0; e < G; ++e) {
+            const double mv = mrow[r * G + e];
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) acc[r][c] = fma(mv, xc[c][lg * G + e], acc[r][c]);
+          }
+      }
     }
 #pragma unroll
     for (int r = 0; r < RW; ++r) {

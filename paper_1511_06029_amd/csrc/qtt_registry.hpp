@@ -22,9 +22,10 @@ struct KernelCfg {
   int kind;        // 0 single-operand LDS, 2 streamed, 3 4x4x4 streamed
 };
 
-// FP64 vector-ALU kernels: (id, waves, rows per wave, columns per lane, input group size).
+// FP64 vector-ALU kernels: (id, waves, rows per wave, columns per lane, input group size,
+// groups loaded per step).
 struct ValuCfg {
-  int id, NW, RW, CPL, G;
+  int id, NW, RW, CPL, G, LG;
   const void* fn;
   int occ;
 };

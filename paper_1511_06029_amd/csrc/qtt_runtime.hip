@@ -253,12 +253,19 @@ static int occupancy(KernelCfg* k) {
 // ---------------------------------------------------------------------------
 static const size_t kMaxGraphs = 48;
 
+// Destroys a cached graph once its last launch (on whatever stream) is done.
+static void destroy_graph(const qtt_matrix_s::Graph& g) {
+  if (g.done) {
+    (void)hipEventSynchronize(g.done);
+    (void)hipEventDestroy(g.done);
+  }
+  (void)hipGraphExecDestroy(g.exec);
+  (void)hipGraphDestroy(g.graph);
+}
+
 static void drop_graphs(const qtt_matrix_s* A) {
   std::lock_guard<std::mutex> lk(A->graph_mu);
-  for (auto& g : A->graphs) {
-    (void)hipGraphExecDestroy(g.exec);
-    (void)hipGraphDestroy(g.graph);
-  }
+  for (auto& g : A->graphs) destroy_graph(g);
   A->graphs.clear();
   ++A->tune_gen;
 }
@@ -270,6 +277,9 @@ static bool valid_handle(qtt_matrix_t A) { return A != nullptr && A->d > 0; }
 // hence its bits) are the same whatever batch it is part of.
 static std::mutex g_tune_mu;
 static std::map<std::tuple<int, int, int, int, int64_t>, int> g_tuned;
+// bumped on every change of g_tuned: part of every graph key, so that no
+// handle replays a sweep captured with configurations that changed since
+static std::atomic<int64_t> g_tune_gen{0};
 
 static bool tune_log() {
   const char* s = getenv("QTT_TUNE_LOG");
@@ -278,7 +288,7 @@ static bool tune_log() {
 
 // Untuned defaults, from tuning runs on MI355X at L = 7, r = 32.
 static int heuristic_shape(int R_out, int K_in, int dt) {
-  if (R_out <= 16) return dt == 0 ? 47 : 2;      // last core (r_d = 1)
+  if (R_out <= 16) return dt == 0 ? 49 : 2;      // last core (r_d = 1; 49 needs K_in % 16 == 0, else 47)
   if (dt == 0 && R_out > 64) {                   // FP64: 4x4x4 matrix instruction
     if (K_in <= 16) return 67;                   // short chunks for the first core
     return R_out <= 192 ? 63 : 75;
@@ -338,6 +348,7 @@ static qtt_status_t launch_valu(const qtt_matrix_s* A, int k, int64_t nrhs, cons
   } else {
     aligned = aligned && (reinterpret_cast<uintptr_t>(in_packed) % 16 == 0);
   }
+  if (vc && c.K_in % (vc->G * vc->LG) != 0) vc = find_valu(47);
   if (!vc || (vc->G == 8 && !aligned)) vc = find_valu(kValuGeneric);
   ValuArgs a;
   memset(&a, 0, sizeof(a));
@@ -689,6 +700,8 @@ static qtt_status_t sweep_graph(const qtt_matrix_s* A, int dt, int64_t nrhs, con
   put(&alpha, sizeof alpha);
   put(&ws, sizeof ws);
   put(&A->tune_gen, sizeof A->tune_gen);
+  const int64_t gen = g_tune_gen.load();
+  put(&gen, sizeof gen);
   for (int i = 0; i < nseg; ++i) put(&segs[i], sizeof(Segment));
   std::lock_guard<std::mutex> lk(A->graph_mu);
   for (size_t i = 0; i < A->graphs.size(); ++i) {
@@ -697,6 +710,7 @@ static qtt_status_t sweep_graph(const qtt_matrix_s* A, int dt, int64_t nrhs, con
       A->graphs.erase(A->graphs.begin() + i);
       A->graphs.push_back(g);
       HIP_TRY(hipGraphLaunch(g.exec, st));
+      HIP_TRY(hipEventRecord(g.done, st));
       return QTT_OK;
     }
   }
@@ -720,12 +734,18 @@ static qtt_status_t sweep_graph(const qtt_matrix_s* A, int dt, int64_t nrhs, con
     (void)hipGraphDestroy(graph);
     return fail(QTT_ERR_DEVICE, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
   }
+  hipEvent_t done = nullptr;
+  e = hipEventCreateWithFlags(&done, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+    return fail(QTT_ERR_DEVICE, "hipEventCreate failed: %s", hipGetErrorString(e));
+  }
   if (A->graphs.size() >= kMaxGraphs) {
-    (void)hipGraphExecDestroy(A->graphs.front().exec);
-    (void)hipGraphDestroy(A->graphs.front().graph);
+    destroy_graph(A->graphs.front());
     A->graphs.erase(A->graphs.begin());
   }
-  A->graphs.push_back({key, graph, exec});
+  A->graphs.push_back({key, graph, exec, done});
   return QTT_OK;
 }
 
@@ -1284,6 +1304,7 @@ qtt_status_t qtt_autotune(qtt_matrix_t A, qtt_dtype_t compute, int64_t nrhs, con
     c.tuned[dt] = best_id;
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tuned[std::make_tuple(dt, c.R_out, c.K_in, c.r_out, c.C)] = best_id;
+    ++g_tune_gen;
   }
   if (dt <= 1) {
     // fused pairs against the standard sweep

@@ -374,8 +374,9 @@ def test_timing_by_configuration(Q):
         assert all(r["ms"] > 0 for r in used.values())
         if dt == "fp64":
             # fused pairs (0, 1): first core, r_1 = 24, 256 rows next; (2, 3): r_3 = 32,
-            # 192 rows next; then the last core on the vector ALUs
-            assert set(used) == {90 + 4 + 0 + 1, 90 + 0 + 2 + 0, 47}, used.keys()
+            # 192 rows next; then the last core on the vector ALUs (K_in = 192: the
+            # whole-line configuration 49)
+            assert set(used) == {90 + 4 + 0 + 1, 90 + 0 + 2 + 0, 49}, used.keys()
             assert sum(r["launches"] for r in used.values()) == 3
         else:
             assert 34 in used and sum(r["launches"] for r in used.values()) == len(ranks) - 1, used.keys()
