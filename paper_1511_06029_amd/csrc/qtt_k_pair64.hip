@@ -6,14 +6,11 @@
 namespace qtt {
 
 namespace {
-// RA = 24 and 32 exact; "RA = 33" stands for the padded 256-row kernel.  The
-// pairs after the first core run the pipelined schedule (PIPE): the short
-// first-core step gains nothing from it and the first pair keeps the plain one.
+// RA = 24 and 32 exact; "RA = 33" stands for the padded 256-row kernel.
 template <int RA, int WRB, bool FIRST>
 const void* fn() {
   constexpr int R = RA > 32 ? 32 : RA;
-  return reinterpret_cast<const void*>(
-      &core_pair_f64q_kernel<R, WRB, FIRST, FIRST ? 8 : 32, 4, (RA > 32), !FIRST>);
+  return reinterpret_cast<const void*>(&core_pair_f64_kernel<R, WRB, FIRST, FIRST ? 8 : 32, 4, (RA > 32)>);
 }
 }  // namespace
 

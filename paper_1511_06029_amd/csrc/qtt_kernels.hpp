@@ -837,8 +837,8 @@ core_step_f64q_kernel(const StepArgs args) {
 }
 
 // ---------------------------------------------------------------------------
-// Two consecutive FP64 core steps k, k + 1 in one pass over a column tile,
-// on the 4x4x4 matrix instruction: the tile's intermediate y_k stays on chip.
+// Two consecutive FP64 core steps k, k + 1 in one pass over a column tile:
+// the tile's intermediate y_k stays on chip.
 //
 // For cores with r_k = RA (24 or 32; with PAD, the RA = 32 kernel takes any
 // r_k from 17 to 32, padded) and m_k = n_{k+1} = 8.  A tile is 32
@@ -846,20 +846,32 @@ core_step_f64q_kernel(const StepArgs args) {
 // gives phi_k(a_k + RA i_k, j_{k+1} + 8 Q) for all 8 RA rows.  By the row
 // separation of step k and the reshape into b_{k+1} (Algorithm 2), these are
 // exactly the 32 complete columns q' = Q + (C_k / 8) i_k of b_{k+1}, with
-// contraction index a_k + RA j_{k+1}.  They are written to LDS in the input
-// layout of the 4x4x4 kernels (column c' = (Q - Q0) + 4 i_k, all 2 RA steps:
-// at most 80 KB, which still lets two workgroups share a CU), and step k + 1
-// runs from there with no input traffic and no barriers.  Step k streams its
-// input like core_step_f64q_kernel (chunks of KCA / 4 steps, two stages that
-// alias the start of the LDS tile), from the packed intermediate or, with
-// FIRST, from the caller's FP64 vectors through the segment table (core 0);
-// both steps take core fragments through buffer resources with a ring of
-// prefetched steps.  Step k + 1 covers 64 WRB rows.  With PIPE, each step
-// reads the next step's input fragments from LDS while its own matrix
-// instructions run, and the core-fragment and input prefetches past the end
-// are clamped re-reads instead of branches, so that a whole chunk is one
-// block the compiler can schedule across steps (4% faster for the interior
-// pairs at r = 32; results bitwise those of the plain schedule).
+// contraction index a_k + RA j_{k+1}.  They are written to LDS (column
+// c' = (Q - Q0) + 4 i_k, all 2 RA steps: 64 KB at RA = 32, so two workgroups
+// share a CU), and step k + 1 runs from there with no input traffic and no
+// barriers.  Step k streams its input in chunks of KCA / 4 steps through two
+// LDS stages that alias the start of the tile, from the packed intermediate
+// or, with FIRST, from the caller's FP64 vectors through the segment table
+// (core 0); both steps take core fragments through buffer resources with a
+// ring of PF prefetched steps.  Step k + 1 covers 64 WRB rows.
+//
+// Both steps run on v_mfma_f64_16x16x4f64.  One instruction takes 16 tile
+// columns (A operand, lane l: column l mod 16, contraction index l div 16)
+// against 16 core rows (B operand, lane l: row 16 rb + l mod 16, contraction
+// index 4 s + l div 16, the fragment order of the core arrays), so one step
+// of a wave is 2 input fragments x WR core fragments -> 2 WR instructions of
+// 2048 flops; accumulator lane l, element v holds D(tile column
+// (l div 16) + 4 v, core row l mod 16).  Each step reads the next step's
+// input fragments from LDS while its own instructions run, and prefetches
+// past the end are clamped re-reads instead of branches, so that a whole
+// chunk is one block the compiler can schedule across steps.
+//
+// LDS holds, per 16-column block and step, a 4 x 16 block (contraction
+// index, column) whose column is XOR-swizzled with (4 step + contraction
+// index) mod 16 (pm_pos): each fragment read is a permutation inside every
+// 16-lane group (conflict-free), and the stores of one column's consecutive
+// contraction indices fall on distinct banks.
+//
 // Requirements checked by the host: the conditions above, R_out(k + 1) <=
 // 64 WRB, step counts multiples of the chunk (step k) and of 8 (step k + 1),
 // C_k % 32 == 0, K_in(k) even with 16-byte aligned columns, both fragment
@@ -884,32 +896,40 @@ struct PairArgs {
   const Segment* seg;    // device table of nseg segments
 };
 
-template <int RA, int WRB, bool FIRST, int KCA, int PF, bool PAD = false, bool PIPE = false>
-__global__ void __launch_bounds__(256, 2) core_pair_f64q_kernel(const PairArgs args) {
+// LDS position of (tile column c, contraction index kap) in a tile of
+// `steps` steps per 16-column block.
+__device__ inline int pm_pos(int c, int kap, int steps) {
+  const int s = kap >> 2, k4 = kap & 3;
+  return (((c >> 4) * steps + s) * 4 + k4) * 16 + ((c & 15) ^ ((4 * s + k4) & 15));
+}
+
+template <int RA, int WRB, bool FIRST, int KCA, int PF, bool PAD = false>
+__global__ void __launch_bounds__(256, 2) core_pair_f64_kernel(const PairArgs args) {
   (void)args;
   const PairArgs& a = kernarg<PairArgs>();
-  constexpr int NT = 256, WQ = 8, TC = 32, SPB = 8;
-  constexpr int WRA = RA / 8;                      // row blocks per wave in step k (8 RA rows)
+  constexpr int NT = 256, TC = 32, CB = TC / 16, SPB = 8;
+  constexpr int WRA = RA / 8;                      // 16-row blocks per wave in step k (8 RA rows)
   constexpr int SPA = KCA / 4, VPC = KCA / 2;
   constexpr int PFA = PF < SPA ? PF : SPA;
   constexpr int NLA = (TC * VPC + NT - 1) / NT;
-  constexpr int A_ELEMS = (TC / 4) * SPA * kQGS;   // one staging stage of step k
+  constexpr int A_ELEMS = CB * SPA * 64;           // one staging stage of step k
   constexpr int KSB = 2 * RA;                      // LDS steps of step k + 1 (K_in <= 8 RA)
-  constexpr int X_ELEMS = (TC / 4) * KSB * kQGS;   // b_{k+1} tile
+  constexpr int X_ELEMS = CB * KSB * 64;           // b_{k+1} tile
   static_assert(RA == 24 || RA == 32, "rank of the fused boundary");
   static_assert(!PAD || RA == 32, "padded ranks use the 256-row kernel");
-  static_assert(SPA % PFA == 0 && SPB % PF == 0 && KSB % SPB == 0, "whole prefetch rounds");
+  static_assert(SPA % PFA == 0 && SPB % PF == 0 && KSB % SPB == 0 && SPB % 4 == 0, "whole prefetch rounds");
   static_assert(2 * A_ELEMS <= X_ELEMS, "stages alias the tile");
   __shared__ __attribute__((aligned(16))) double lds[X_ELEMS];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wr = tid >> 6;
-  const int rd = 4 * (lane & 3) + (lane >> 4);
+  const int k4l = lane >> 4, cl = lane & 15;
+  // fragment read offset inside a (column block, step) block, by step mod 4
+  int sw[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) sw[t] = 16 * k4l + (cl ^ (4 * t + k4l));
   const int nchA = a.KsA / SPA;
-  // the boundary rank: RA itself, or (PAD) any ra in 17..32 with step k's
-  // rows padded to 8 RA (zero fragment rows) and step k + 1's contraction to
-  // a.KsB steps (zero core steps past 8 ra, zero LDS values there)
   const int ra = PAD ? a.ra : RA;
   const int kin_b = 8 * ra;
   const int ksb = PAD ? a.KsB : KSB;
@@ -928,11 +948,11 @@ __global__ void __launch_bounds__(256, 2) core_pair_f64q_kernel(const PairArgs a
       const int kap = kc0 + (idx % VPC) * 2;
       const int64_t g = col0 + c;
       sa[t] = v4u{};
-      // PIPE, not FIRST: idx and g are in range by construction (TC * VPC a
+      // not FIRST: idx and g are in range by construction (TC * VPC a
       // multiple of NT; the host requires C % 32 == 0, so every column of a
       // tile below n_tiles exists); the contraction index may pass K_in
       // where the core's steps were padded
-      const bool inside = (PIPE && !FIRST && (TC * VPC) % NT == 0)
+      const bool inside = (!FIRST && (TC * VPC) % NT == 0)
                               ? (kap < a.K_inA)
                               : (idx < TC * VPC && g < a.ncols && kap < a.K_inA);
       if (inside) {
@@ -957,7 +977,10 @@ __global__ void __launch_bounds__(256, 2) core_pair_f64q_kernel(const PairArgs a
       if (idx < TC * VPC) {
         const int c = idx / VPC;
         const int kl0 = (idx % VPC) * 2;
-        *reinterpret_cast<v4u*>(&S[((c >> 2) * SPA + (kl0 >> 2)) * kQGS + 4 * (c & 3) + (kl0 & 3)]) = sa[t];
+        typedef double v2d __attribute__((ext_vector_type(2)));
+        const v2d v = __builtin_bit_cast(v2d, sa[t]);
+        S[pm_pos(c, kl0, SPA)] = v[0];
+        S[pm_pos(c, kl0 + 1, SPA)] = v[1];
       }
     }
   };
@@ -988,7 +1011,7 @@ __global__ void __launch_bounds__(256, 2) core_pair_f64q_kernel(const PairArgs a
     const int64_t tile = blockIdx.x + t * (int64_t)gridDim.x;
     // ---- step k: input streamed in chunks of SPA steps ----
     {
-      double acc[WRA][WQ];
+      v4d acc[WRA][CB];
       double ring[PFA][WRA];
       __syncthreads();                             // the previous tile's step k + 1 is done with lds
       lstore(0);
@@ -997,48 +1020,33 @@ __global__ void __launch_bounds__(256, 2) core_pair_f64q_kernel(const PairArgs a
 #pragma unroll
       for (int i = 0; i < WRA; ++i)
 #pragma unroll
-        for (int j = 0; j < WQ; ++j) acc[i][j] = 0.0;
+        for (int j = 0; j < CB; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
       __syncthreads();
       for (int ch = 0; ch < nchA; ++ch) {
         const double* S = lds + (ch & 1) * A_ELEMS;
-        double afn[WQ];
-        if constexpr (PIPE) {
+        double afn[CB];
 #pragma unroll
-          for (int j = 0; j < WQ; ++j) afn[j] = S[(j * SPA) * kQGS + rd];
-        }
+        for (int j = 0; j < CB; ++j) afn[j] = S[(j * SPA) * 64 + sw[0]];
 #pragma unroll
         for (int s = 0; s < SPA; ++s) {
-          double af[WQ];
-          if constexpr (PIPE) {
-            // the next step's input fragments are read while this step's
-            // instructions run; core fragments past the end are re-reads
-            // of the last step (clamped: no branch in the chunk)
+          double af[CB];
 #pragma unroll
-            for (int j = 0; j < WQ; ++j) af[j] = afn[j];
-            if (s + 1 < SPA) {
+          for (int j = 0; j < CB; ++j) af[j] = afn[j];
+          if (s + 1 < SPA) {
 #pragma unroll
-              for (int j = 0; j < WQ; ++j) afn[j] = S[(j * SPA + s + 1) * kQGS + rd];
-            }
-          } else {
-#pragma unroll
-            for (int j = 0; j < WQ; ++j) af[j] = S[(j * SPA + s) * kQGS + rd];
+            for (int j = 0; j < CB; ++j) afn[j] = S[(j * SPA + s + 1) * 64 + sw[(s + 1) & 3]];
           }
           double bc[WRA];
 #pragma unroll
           for (int i = 0; i < WRA; ++i) bc[i] = ring[s % PFA][i];
           const int gs = ch * SPA + s + PFA;
-          if constexpr (PIPE) {
-            loadA(ring[s % PFA], gs < a.KsA ? gs : a.KsA - 1);
-            if (s == 0) gload(tile, ch + 1 < nchA ? ch + 1 : ch);
-          } else {
-            if (gs < a.KsA) loadA(ring[s % PFA], gs);
-            if (s == 0 && ch + 1 < nchA) gload(tile, ch + 1);
-          }
+          loadA(ring[s % PFA], gs < a.KsA ? gs : a.KsA - 1);
+          if (s == 0) gload(tile, ch + 1 < nchA ? ch + 1 : ch);
 #pragma unroll
           for (int i = 0; i < WRA; ++i)
 #pragma unroll
-            for (int j = 0; j < WQ; ++j)
-              acc[i][j] = __builtin_amdgcn_mfma_f64_4x4x4f64(af[j], bc[i], acc[i][j], 0, 0, 0);
+            for (int j = 0; j < CB; ++j)
+              acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[j], bc[i], acc[i][j], 0, 0, 0);
         }
         if (ch + 1 < nchA) {
           lstore((ch + 1) & 1);
@@ -1049,15 +1057,16 @@ __global__ void __launch_bounds__(256, 2) core_pair_f64q_kernel(const PairArgs a
       __syncthreads();                             // every wave is done with the stages
 #pragma unroll
       for (int i = 0; i < WRA; ++i) {
-        const int row = 16 * (WRA * wr + i) + (lane & 15);   // a_k + ra i_k
+        const int row = 16 * (WRA * wr + i) + cl;            // a_k + ra i_k
         if (row < kin_b) {
           const int ak = row % ra, ik = row / ra;
 #pragma unroll
-          for (int j = 0; j < WQ; ++j) {
-            const int col = 4 * j + (lane >> 4);             // j_{k+1} + 8 (Q - Q0)
-            const int kap = ak + ra * (col & 7);
-            lds[(ik * KSB + (kap >> 2)) * kQGS + 4 * (col >> 3) + (kap & 3)] = acc[i][j];
-          }
+          for (int j = 0; j < CB; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int ql = 16 * j + k4l + 4 * v;           // j_{k+1} + 8 (Q - Q0)
+              lds[pm_pos((ql >> 3) + 4 * ik, ak + ra * (ql & 7), KSB)] = acc[i][j][v];
+            }
         }
       }
       // contraction indices 8 ra .. 4 KsB of every column: zeros
@@ -1065,12 +1074,12 @@ __global__ void __launch_bounds__(256, 2) core_pair_f64q_kernel(const PairArgs a
         const int pad = 4 * a.KsB - kin_b;
         for (int e = tid; e < TC * pad; e += NT) {
           const int c = e / pad, kap = kin_b + (e - c * pad);
-          lds[((c >> 2) * KSB + (kap >> 2)) * kQGS + 4 * (c & 3) + (kap & 3)] = 0.0;
+          lds[pm_pos(c, kap, KSB)] = 0.0;
         }
       }
     }
     // ---- step k + 1 from LDS ----
-    double acc[WRB][WQ];
+    v4d acc[WRB][CB];
     double ring[PF][WRB];
 #pragma unroll
     for (int p = 0; p < PF; ++p) loadB(ring[p], p);
@@ -1078,38 +1087,30 @@ __global__ void __launch_bounds__(256, 2) core_pair_f64q_kernel(const PairArgs a
 #pragma unroll
     for (int i = 0; i < WRB; ++i)
 #pragma unroll
-      for (int j = 0; j < WQ; ++j) acc[i][j] = 0.0;
+      for (int j = 0; j < CB; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
     __syncthreads();
-    double bfn[WQ];
-    if constexpr (PIPE) {
+    double bfn[CB];
 #pragma unroll
-      for (int j = 0; j < WQ; ++j) bfn[j] = lds[(j * KSB) * kQGS + rd];
-    }
+    for (int j = 0; j < CB; ++j) bfn[j] = lds[(j * KSB) * 64 + sw[0]];
     for (int c8 = 0; c8 < ksb / SPB; ++c8) {
 #pragma unroll
       for (int s = 0; s < SPB; ++s) {
         const int gs = c8 * SPB + s;
-        double af[WQ];
-        if constexpr (PIPE) {
-          const int gn = gs + 1 < ksb ? gs + 1 : ksb - 1;
+        const int gn = gs + 1 < ksb ? gs + 1 : ksb - 1;
+        double af[CB];
 #pragma unroll
-          for (int j = 0; j < WQ; ++j) af[j] = bfn[j];
+        for (int j = 0; j < CB; ++j) af[j] = bfn[j];
 #pragma unroll
-          for (int j = 0; j < WQ; ++j) bfn[j] = lds[(j * KSB + gn) * kQGS + rd];
-        } else {
-#pragma unroll
-          for (int j = 0; j < WQ; ++j) af[j] = lds[(j * KSB + gs) * kQGS + rd];
-        }
+        for (int j = 0; j < CB; ++j) bfn[j] = lds[(j * KSB + gn) * 64 + sw[(s + 1) & 3]];
         double bc[WRB];
 #pragma unroll
         for (int i = 0; i < WRB; ++i) bc[i] = ring[s % PF][i];
-        if constexpr (PIPE) loadB(ring[s % PF], gs + PF < ksb ? gs + PF : ksb - 1);
-        else if (gs + PF < ksb) loadB(ring[s % PF], gs + PF);
+        loadB(ring[s % PF], gs + PF < ksb ? gs + PF : ksb - 1);
 #pragma unroll
         for (int i = 0; i < WRB; ++i)
 #pragma unroll
-          for (int j = 0; j < WQ; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f64_4x4x4f64(af[j], bc[i], acc[i][j], 0, 0, 0);
+          for (int j = 0; j < CB; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[j], bc[i], acc[i][j], 0, 0, 0);
       }
     }
     // ---- y_{k+1}(a', q' + C i_{k+1}) with q' = Q + (C / 8) i_k ----
@@ -1119,20 +1120,23 @@ __global__ void __launch_bounds__(256, 2) core_pair_f64q_kernel(const PairArgs a
     double* dst = a.out + rhs * a.out_stride;
 #pragma unroll
     for (int i = 0; i < WRB; ++i) {
-      const int row = 16 * (WRB * wr + i) + (lane & 15);
+      const int row = 16 * (WRB * wr + i) + cl;
       if (row >= a.R_outB) continue;
       const int ar = row % a.r_outB, ir = row / a.r_outB;
 #pragma unroll
-      for (int j = 0; j < WQ; ++j) {
-        const int64_t qp = Q0 + (lane >> 4) + (a.C / 8) * j;    // column c' = (Q - Q0) + 4 i_k, i_k = j
-        dst[ar + (int64_t)a.r_outB * (qp + a.C * ir)] = acc[i][j];
-      }
+      for (int j = 0; j < CB; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          // tile column c' = 16 j + k4l + 4 v = (Q - Q0) + 4 i_k
+          const int64_t qp = Q0 + k4l + (a.C / 8) * (4 * j + v);
+          dst[ar + (int64_t)a.r_outB * (qp + a.C * ir)] = acc[i][j][v];
+        }
     }
   }
 }
 
 // ---------------------------------------------------------------------------
-// The fused pair of core steps k, k + 1 (see core_pair_f64q_kernel) for the
+// The fused pair of core steps k, k + 1 (see core_pair_f64_kernel) for the
 // FP32 sweep, on v_mfma_f32_16x16x4f32 with FP32 accumulation.
 //
 // Operands as in the streamed FP32 kernels with rows on lanes: the input

@@ -563,7 +563,7 @@ static int64_t wave_capacity(const qtt_matrix_s* A, int dt, size_t ws_bytes) {
   return w;
 }
 
-// Fused FP64 pair (core k, core k + 1), see core_pair_f64q_kernel.
+// Fused FP64 pair (core k, core k + 1), see core_pair_f64_kernel.
 // configuration ids reported by the launch timing: 90 + 4 (first core) +
 // 2 (r_k != 24: the padded rank-32 kernel) + (R_out(k + 1) > 192), one per
 // kernel instantiation
