@@ -939,34 +939,30 @@ __global__ void __launch_bounds__(256, 2) core_pair_f64_kernel(const PairArgs ar
 
   v4u sa[NLA];
   auto gload = [&](int64_t tile, int ch) {
+    // a tile lies in one vector (C % 32 == 0): its vector, and for FIRST its
+    // segment, are wave-uniform (scalar loads)
     const int64_t col0 = tile * TC;
+    const int64_t rhs = col0 / a.C;
+    const int64_t q0 = col0 - rhs * a.C;
+    const double* base;
+    if constexpr (FIRST) {
+      const Segment& sg = a.seg[find_seg(a, rhs)];
+      base = sg.x + (rhs - sg.rhs_begin) * sg.ldx;
+    } else {
+      base = a.in + rhs * a.in_stride;
+    }
     const int kc0 = ch * KCA;
 #pragma unroll
     for (int t = 0; t < NLA; ++t) {
       const int idx = tid + t * NT;
       const int c = idx / VPC;
       const int kap = kc0 + (idx % VPC) * 2;
-      const int64_t g = col0 + c;
       sa[t] = v4u{};
-      // not FIRST: idx and g are in range by construction (TC * VPC a
-      // multiple of NT; the host requires C % 32 == 0, so every column of a
-      // tile below n_tiles exists); the contraction index may pass K_in
-      // where the core's steps were padded
-      const bool inside = (!FIRST && (TC * VPC) % NT == 0)
-                              ? (kap < a.K_inA)
-                              : (idx < TC * VPC && g < a.ncols && kap < a.K_inA);
-      if (inside) {
-        const int64_t rhs = g / a.C;
-        const int64_t q = g - rhs * a.C;
-        const double* p;
-        if constexpr (FIRST) {
-          const Segment& sg = a.seg[find_seg(a, rhs)];
-          p = sg.x + (rhs - sg.rhs_begin) * sg.ldx + q * a.K_inA;
-        } else {
-          p = a.in + rhs * a.in_stride + q * a.K_inA;
-        }
-        sa[t] = *reinterpret_cast<const v4u*>(p + kap);
-      }
+      // idx is in range by construction when TC * VPC is a multiple of NT,
+      // and every column of a tile below n_tiles exists; the contraction
+      // index may pass K_in where the core's steps were padded
+      const bool inside = ((TC * VPC) % NT == 0 || idx < TC * VPC) && kap < a.K_inA;
+      if (inside) sa[t] = *reinterpret_cast<const v4u*>(base + (q0 + c) * a.K_inA + kap);
     }
   };
   auto lstore = [&](int stage) {
@@ -1990,6 +1986,153 @@ __global__ void __launch_bounds__(256) core_step_smallk_kernel(const StepArgs ar
 }
 
 // ---------------------------------------------------------------------------
+// The last BF16 core (R_out = m_d r_d <= 16) streamed through registers: no
+// LDS and no barriers.  Every wave walks its own tiles of 16 columns.  The B
+// operand of v_mfma_f32_16x16x32_bf16 (lane l: column l mod 16, contraction
+// indices 32 s + 8 (l div 16) .. +7) is loaded straight from the packed
+// intermediate, 16 bytes a lane and step, two tiles ahead; the core is held as
+// A fragments for every step (rows past R_out are zero).  Accumulator row
+// 4 (l div 16) + v, column l mod 16 goes out through the segment table as
+// z + alpha acc.  The steps accumulate in order, as in the chunked kernels;
+// steps past Ksteps add zero core values times finite data.
+// Requirements checked by the host: last core, R_out <= 16, K_in % 8 == 0,
+// Ksteps <= KS, C_d % 16 == 0, 16-byte aligned input.
+// ---------------------------------------------------------------------------
+template <int KS>
+__global__ void __launch_bounds__(256) core_step_bf16_last_kernel(const StepArgs args) {
+  (void)args;
+  const StepArgs& a = kernarg<StepArgs>();
+  using MF = Mfma<bf16_tag>;
+  const int lane = threadIdx.x & 63;
+  // wave index made provably uniform: tile, vector and segment lookups then
+  // go through scalar loads, which do not wait on the vector-load counter
+  const int64_t gw = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t nw = (int64_t)gridDim.x * 4;
+  const int Ks = a.Ksteps;
+  const uint16_t* __restrict__ Mf = reinterpret_cast<const uint16_t*>(a.M);
+  const uint16_t* __restrict__ in = reinterpret_cast<const uint16_t*>(a.in);
+  v8bf mf[KS];
+#pragma unroll
+  for (int s = 0; s < KS; ++s)
+    mf[s] = (s < Ks) ? MF::load_frag(Mf + ((int64_t)s * 64 + lane) * 8) : MF::zero_frag();
+  const int64_t ntiles = a.ncols / 16;
+  const int cl = lane & 15, kq = 8 * (lane >> 4);
+  // indices past K_in (a partial last step) read the column's last 8 values
+  // again: finite data of the same column, multiplied by zero core values
+  const int kmax = a.K_in - 8;
+  // every step is loaded and multiplied (steps past Ks: zero core values
+  // times finite data), so the hot loop has no branch on Ks
+  auto load = [&](v4u (&b)[KS], int64_t t) {
+    const uint16_t* p = in + (t * 16 + cl) * (int64_t)a.K_in;
+#pragma unroll
+    for (int s = 0; s < KS; ++s) b[s] = *reinterpret_cast<const v4u*>(p + min(32 * s + kq, kmax));
+  };
+  // A tile's input and z are fetched two tiles ahead (three buffers); vector
+  // loads complete in issue order, so a tile's data has arrived once at most
+  // the two later fetches and the stores since are outstanding.  The segment
+  // of the current vector is cached in scalar registers: a table lookup (a
+  // scalar load, which must wait for the wave's earlier stores) happens only
+  // when a tile starts a new vector.
+  // y and z are device memory: global-address-space pointers, so their
+  // accesses are global (vector counter only), not flat instructions
+  typedef __attribute__((address_space(1))) double gdouble;
+  int64_t cur_rhs = -1;
+  gdouble* ybase = nullptr;
+  const gdouble* zbase = nullptr;
+  auto segment = [&](int64_t rhs) {
+    if (rhs != cur_rhs) {
+      const Segment& sg = a.seg[find_seg(a, rhs)];
+      const int64_t vr = rhs - sg.rhs_begin;
+      ybase = (gdouble*)(sg.y + vr * sg.ldy);
+      zbase = sg.z ? (const gdouble*)(sg.z + vr * sg.ldz) : nullptr;
+      cur_rhs = rhs;
+    }
+  };
+  // one tile in flight: its input steps, z values, output base and z flag
+  struct Tile {
+    v4u b[KS];
+    double z[4];
+    gdouble* y;
+    bool hz;
+  };
+  auto fetch = [&](Tile& u, int64_t t) {
+    const int64_t col0 = t * 16;
+    const int64_t rhs = col0 / a.C;
+    const int64_t q = col0 - rhs * a.C + cl;
+    segment(rhs);
+    u.y = ybase + (int64_t)a.r_out * q;
+    u.hz = (zbase != nullptr);
+    // the same number of loads on every path (so that the compiler's count
+    // of outstanding loads stays exact): without z, the output's own entries
+    // are read and ignored; rows past R_out read row R_out - 1 again
+    const gdouble* zq = (u.hz ? zbase : ybase) + (int64_t)a.r_out * q;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = min(4 * (lane >> 4) + v, a.R_out - 1);
+      const int ir = row / a.r_out, ar = row - ir * a.r_out;
+      u.z[v] = zq[ar + (int64_t)a.r_out * a.C * ir];
+    }
+    load(u.b, t);
+  };
+  auto finish = [&](const Tile& u) {
+    v4f acc = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < KS; ++s) acc = MF::mma(mf[s], __builtin_bit_cast(v8bf, u.b[s]), acc);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = 4 * (lane >> 4) + v;
+      if (row < a.R_out) {
+        const int ir = row / a.r_out, ar = row - ir * a.r_out;
+        double res = a.alpha * (double)acc[v];
+        if (u.hz) res += u.z[v];
+        u.y[ar + (int64_t)a.r_out * a.C * ir] = res;
+      }
+    }
+  };
+  if (gw >= ntiles) return;
+  const int64_t my = (ntiles - 1 - gw) / nw + 1;   // tiles of this wave: gw + i nw
+  auto tile = [&](int64_t i) { return gw + i * nw; };
+  Tile u0, u1, u2;
+  if (my < 3) {
+    fetch(u0, tile(0));
+    if (my > 1) fetch(u1, tile(1));
+    finish(u0);
+    if (my > 1) finish(u1);
+    return;
+  }
+  fetch(u0, tile(0));
+  fetch(u1, tile(1));
+  int64_t i = 0;
+  // steady state, no branch around a vector load: tile i in u0, i + 1 in u1
+  for (; i + 4 < my; i += 3) {
+    fetch(u2, tile(i + 2));
+    finish(u0);
+    fetch(u0, tile(i + 3));
+    finish(u1);
+    fetch(u1, tile(i + 4));
+    finish(u2);
+  }
+  // 2 to 4 tiles left, the first two fetched
+  const int64_t left = my - i;
+  if (left == 2) {
+    finish(u0);
+    finish(u1);
+  } else if (left == 3) {
+    fetch(u2, tile(i + 2));
+    finish(u0);
+    finish(u1);
+    finish(u2);
+  } else {
+    fetch(u2, tile(i + 2));
+    finish(u0);
+    fetch(u0, tile(i + 3));
+    finish(u1);
+    finish(u2);
+    finish(u0);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // The first BF16 core with K_in <= 8 (r_0 = 1), rows held in registers.
 //
 // Thread (wave w, lane l): row quad aq = l mod 8 (rows 4 aq .. 4 aq + 3 of an
@@ -2017,6 +2160,9 @@ __global__ void __launch_bounds__(256) core_step_smallk_bf16_kernel(const StepAr
   const int Ks = a.Ksteps;
   const int aq = lane & 7, qq = lane >> 3;
   const bool act = 4 * aq < r;
+  // the core: every load issued unconditionally (indices clamped into the
+  // core), then the values outside it replaced by zeros, so that the loads
+  // overlap instead of each waiting for the previous one
   float Mr[2][4][MAXK];
 #pragma unroll
   for (int ii = 0; ii < 2; ++ii)
@@ -2024,22 +2170,40 @@ __global__ void __launch_bounds__(256) core_step_smallk_bf16_kernel(const StepAr
     for (int e = 0; e < 4; ++e)
 #pragma unroll
       for (int k = 0; k < MAXK; ++k) {
-        const int i = 2 * w + ii, row = r * i + 4 * aq + e;
-        const int l = (row & 15) + 16 * ((k % S::KS) / S::E);
-        Mr[ii][e][k] = (act && i < m && k < K)
-                           ? S::load_core(a.M, (((int64_t)(row >> 4) * Ks + k / S::KS) * 64 + l) * S::E + k % S::E)
-                           : 0.f;
+        const int i = 2 * w + ii;
+        const int row = min(r * i + 4 * aq + e, a.R_out - 1), kc = min(k, K - 1);
+        const int l = (row & 15) + 16 * ((kc % S::KS) / S::E);
+        Mr[ii][e][k] = S::load_core(a.M, (((int64_t)(row >> 4) * Ks + kc / S::KS) * 64 + l) * S::E + kc % S::E);
       }
+#pragma unroll
+  for (int ii = 0; ii < 2; ++ii)
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+      for (int k = 0; k < MAXK; ++k)
+        if (!(act && 2 * w + ii < m && k < K)) Mr[ii][e][k] = 0.f;
   const int64_t ntiles = a.n_tiles;
   const int nvec = TQ * K / 2;                      // 16-byte input loads per tile
   v4u pre = v4u{};
+  // with one segment (a single block of vectors) its fields are read once,
+  // here, before any barrier: inside the loop a table read could not use the
+  // scalar cache and would wait for every outstanding vector access
+  const bool one_seg = (a.nseg == 1);
+  const double* x0 = a.seg[0].x;
+  const int64_t ldx0 = a.seg[0].ldx;
   auto gload = [&](int64_t tile) {
     const int64_t col0 = tile * TQ;
     const int64_t rhs = col0 / a.C;
     const int64_t q0 = col0 - rhs * a.C;
-    const Segment& sg = a.seg[find_seg(a, rhs)];
-    const v4u* src = reinterpret_cast<const v4u*>(reinterpret_cast<const double*>(sg.x) +
-                                                  (rhs - sg.rhs_begin) * sg.ldx + q0 * K);
+    const double* xv;
+    if (one_seg) {
+      xv = x0 + rhs * ldx0;
+    } else {
+      const Segment& sg = a.seg[find_seg(a, rhs)];
+      xv = sg.x + (rhs - sg.rhs_begin) * sg.ldx;
+    }
+    typedef __attribute__((address_space(1))) const v4u gv4u;
+    const gv4u* src = (const gv4u*)(xv + q0 * K);
     if (tid < nvec) pre = src[tid];
   };
   if ((int64_t)blockIdx.x < ntiles) gload(blockIdx.x);
@@ -2059,7 +2223,9 @@ __global__ void __launch_bounds__(256) core_step_smallk_bf16_kernel(const StepAr
     const int64_t q0 = col0 - rhs * a.C;
     uint16_t* dst = reinterpret_cast<uint16_t*>(a.out) + rhs * a.out_stride + (int64_t)r * q0 + 4 * aq;
     const float* X = xs[buf];
-#pragma unroll 2
+    // fully unrolled: a known number of stores per tile, so the wait before
+    // the next tile's staging is counted exactly, not a full drain
+#pragma unroll
     for (int t = 0; t < TQ / 8; ++t) {
       const int q = qq + 8 * t;
       float xv[MAXK];

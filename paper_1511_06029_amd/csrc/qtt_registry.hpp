@@ -38,8 +38,9 @@ constexpr int kValuGeneric = 48;   // vector-ALU kernel without input groups
 void add_kernels_f64(std::vector<KernelCfg>& v);
 void add_kernels_f32(std::vector<KernelCfg>& v);
 void add_kernels_bf16(std::vector<KernelCfg>& v);
-// core_step_bf16_dma_kernel<tcb>, tcb = 2 or 4 (qtt_k_bf16.hip)
+// core_step_bf16_dma_kernel<tcb>, tcb = 2 or 4, and core_step_bf16_last_kernel (qtt_k_bf16.hip)
 const void* bf16_dma_kernel(int tcb);
+const void* bf16_last_kernel();
 // fused core pairs (qtt_k_pair64.hip, qtt_k_pair32.hip); index
 // 6 first + 2 (0: rank 24, 1: rank 32, 2: padded 17..32) + (rows of core k + 1 > 192)
 const void* pair_f64_kernel(int f);

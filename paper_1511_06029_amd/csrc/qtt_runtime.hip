@@ -159,6 +159,22 @@ static KernelCfg* bf16_dma_cfg() {
   }();
   return &k;
 }
+// The last BF16 core streamed through registers (shape id 35).
+static const int kBf16Last = 35;
+static KernelCfg* bf16_last_cfg() {
+  static KernelCfg k = [] {
+    KernelCfg c = *bf16_resident_cfg();
+    c.id = kBf16Last;
+    c.TR = 16;
+    c.TC = 16;
+    c.KC = 256;
+    c.fn = bf16_last_kernel();
+    c.occ = 0;
+    c.kind = -1;
+    return c;
+  }();
+  return &k;
+}
 static KernelCfg* bf16_dma32_cfg() {
   static KernelCfg k = [] {
     KernelCfg c = *bf16_resident_cfg();
@@ -288,7 +304,8 @@ static bool tune_log() {
 
 // Untuned defaults, from tuning runs on MI355X at L = 7, r = 32.
 static int heuristic_shape(int R_out, int K_in, int dt) {
-  if (R_out <= 16) return dt == 0 ? 49 : 2;      // last core (r_d = 1; 49 needs K_in % 16 == 0, else 47)
+  if (R_out <= 16) return dt == 0 ? 49 : (dt == 2 ? kBf16Last : 2);   // last core (r_d = 1; 49 needs
+                                                 // K_in % 16 == 0, else 47; 35 falls back to 2)
   if (dt == 0 && R_out > 64) {                   // FP64: 4x4x4 matrix instruction
     if (K_in <= 16) return 67;                   // short chunks for the first core
     return R_out <= 192 ? 63 : 75;
@@ -449,6 +466,9 @@ static qtt_status_t launch_step(const qtt_matrix_s* A, int k, int dt, int64_t nr
   const int64_t m_bytes =
       (int64_t)padded_row_blocks(c.nRB) * c.Ksteps[dt] * 64 * kFragE[dt] * kElemBytes[dt];
   if (shape == kBf16Resident && !resident_ok) shape = heuristic_shape(c.R_out, c.K_in, 1);
+  const bool last_ok = dt == 2 && last && !first && c.R_out <= 16 && c.K_in % 8 == 0 && c.Ksteps[2] <= 8 &&
+                       c.C % 16 == 0 && vec && reinterpret_cast<uintptr_t>(in_packed) % 16 == 0;
+  if (shape == kBf16Last && !last_ok) shape = 2;
   const int tq = smallk_cfg(dt)->TC;
   const bool smallk_ok = first && !last && vec && c.K_in <= 16 && c.K_in % 2 == 0 && c.R_out <= 256 &&
                          c.r_out % 4 == 0 && c.C % tq == 0 && (c.r_out * tq * kElemBytes[dt]) % 16 == 0 &&
@@ -458,6 +478,7 @@ static qtt_status_t launch_step(const qtt_matrix_s* A, int k, int dt, int64_t nr
                            c.R_out / c.r_out <= 8 && c.C % 64 == 0;
   KernelCfg* kc = smallk_rows ? smallk_rows_cfg()
                   : (shape == kSmallK) ? smallk_cfg(dt)
+                  : (shape == kBf16Last) ? bf16_last_cfg()
                   : (shape == kBf16Dma) ? bf16_dma_cfg()
                   : (shape == kBf16Dma32) ? bf16_dma32_cfg()
                   : (shape == kBf16Resident) ? bf16_resident_cfg()
@@ -1280,6 +1301,7 @@ qtt_status_t qtt_autotune(qtt_matrix_t A, qtt_dtype_t compute, int64_t nrhs, con
       ids.push_back(kBf16Dma32);
     }
     if (k == 0 && A->d > 1) ids.push_back(kSmallK);
+    if (dt == 2 && k == A->d - 1 && k > 0) ids.push_back(kBf16Last);
     if (dt == 0)
       for (auto& vc : valu_registry())
         if (vc.G == 1 || c.K_in % vc.G == 0) ids.push_back(vc.id);
@@ -1344,7 +1366,12 @@ qtt_status_t qtt_list_shapes(qtt_dtype_t compute, int32_t* ids, int32_t cap, int
   if (dt < 0 || !count || (cap > 0 && !ids)) return fail(QTT_ERR_INVALID_ARG, "bad arguments");
   std::vector<int> v = shape_ids(dt, dt == 0);
   v.push_back(kSmallK);
-  if (dt == 2) { v.push_back(kBf16Resident); v.push_back(kBf16Dma); v.push_back(kBf16Dma32); }
+  if (dt == 2) {
+    v.push_back(kBf16Resident);
+    v.push_back(kBf16Dma);
+    v.push_back(kBf16Dma32);
+    v.push_back(kBf16Last);
+  }
   if (dt == 0)
     for (auto& vc : valu_registry()) v.push_back(vc.id);
   *count = (int32_t)v.size();
