@@ -1408,31 +1408,64 @@ __global__ void __launch_bounds__(64 * NW) core_step_valu64_kernel(const ValuArg
     const int rt = (int)(tile % a.n_row_tiles);
     const int64_t col0 = (tile / a.n_row_tiles) * TCOL;
     const int row0 = rt * NW * RW + wave * RW;          // wave-uniform
-    const double* xin[CPL];
-    double* yout[CPL];
-    const double* zin[CPL];
+    // x, y and z are device memory: global-address-space pointers, so their
+    // accesses are global (vector counter only), not flat instructions that
+    // the scalar loads of the core would also wait for
+    typedef __attribute__((address_space(1))) double gdouble;
+    const gdouble* xin[CPL];
+    gdouble* yout[CPL];
+    const gdouble* zin[CPL];
     bool ok[CPL];
-#pragma unroll
-    for (int c = 0; c < CPL; ++c) {
-      const int64_t g = col0 + lane + 64 * c;
-      ok[c] = g < a.ncols;
-      const int64_t gg = ok[c] ? g : 0;
-      const int64_t rhs = gg / a.C;
-      const int64_t q = gg - rhs * a.C;
+    const int64_t rhs0 = col0 / a.C;
+    if (col0 + TCOL <= (rhs0 + 1) * a.C && col0 + TCOL <= a.ncols) {
+      // the whole tile in one vector: its vector and segment are wave-uniform
+      const double* xb;
+      double* yb;
+      const double* zb = nullptr;
       if (a.in_table) {
-        const Segment& sg = a.seg[find_seg(a, rhs)];
-        xin[c] = sg.x + (rhs - sg.rhs_begin) * sg.ldx + q * a.K_in;
+        const Segment& sg = a.seg[find_seg(a, rhs0)];
+        xb = sg.x + (rhs0 - sg.rhs_begin) * sg.ldx;
       } else {
-        xin[c] = a.in + rhs * a.in_stride + q * a.K_in;
+        xb = a.in + rhs0 * a.in_stride;
       }
-      const int64_t qo = (int64_t)a.r_out * q;
       if (a.out_table) {
-        const Segment& sg = a.seg[find_seg(a, rhs)];
-        yout[c] = sg.y + (rhs - sg.rhs_begin) * sg.ldy + qo;
-        zin[c] = sg.z ? sg.z + (rhs - sg.rhs_begin) * sg.ldz + qo : nullptr;
+        const Segment& sg = a.seg[find_seg(a, rhs0)];
+        yb = sg.y + (rhs0 - sg.rhs_begin) * sg.ldy;
+        if (sg.z) zb = sg.z + (rhs0 - sg.rhs_begin) * sg.ldz;
       } else {
-        yout[c] = a.out + rhs * a.out_stride + qo;
-        zin[c] = nullptr;
+        yb = a.out + rhs0 * a.out_stride;
+      }
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) {
+        const int64_t q = col0 - rhs0 * a.C + lane + 64 * c;
+        ok[c] = true;
+        xin[c] = (const gdouble*)(xb + q * a.K_in);
+        yout[c] = (gdouble*)(yb + (int64_t)a.r_out * q);
+        zin[c] = zb ? (const gdouble*)(zb + (int64_t)a.r_out * q) : nullptr;
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) {
+        const int64_t g = col0 + lane + 64 * c;
+        ok[c] = g < a.ncols;
+        const int64_t gg = ok[c] ? g : 0;
+        const int64_t rhs = gg / a.C;
+        const int64_t q = gg - rhs * a.C;
+        if (a.in_table) {
+          const Segment& sg = a.seg[find_seg(a, rhs)];
+          xin[c] = (const gdouble*)(sg.x + (rhs - sg.rhs_begin) * sg.ldx + q * a.K_in);
+        } else {
+          xin[c] = (const gdouble*)(a.in + rhs * a.in_stride + q * a.K_in);
+        }
+        const int64_t qo = (int64_t)a.r_out * q;
+        if (a.out_table) {
+          const Segment& sg = a.seg[find_seg(a, rhs)];
+          yout[c] = (gdouble*)(sg.y + (rhs - sg.rhs_begin) * sg.ldy + qo);
+          zin[c] = sg.z ? (const gdouble*)(sg.z + (rhs - sg.rhs_begin) * sg.ldz + qo) : nullptr;
+        } else {
+          yout[c] = (gdouble*)(a.out + rhs * a.out_stride + qo);
+          zin[c] = nullptr;
+        }
       }
     }
     double acc[RW][CPL];
@@ -1446,8 +1479,7 @@ __global__ void __launch_bounds__(64 * NW) core_step_valu64_kernel(const ValuArg
     auto load_x = [&](int gi) {
 #pragma unroll
       for (int c = 0; c < CPL; ++c) {
-        const double* p = xin[c] + (int64_t)gi * GL;
-        if constexpr (G > 1) p = static_cast<const double*>(__builtin_assume_aligned(p, 16));
+        const gdouble* p = xin[c] + (int64_t)gi * GL;
 #pragma unroll
         for (int e = 0; e < GL; ++e) x[c][e] = p[e];
         if (!ok[c]) {
@@ -1477,22 +1509,38 @@ __global__ void __launch_bounds__(64 * NW) core_step_valu64_kernel(const ValuArg
           }
       }
     }
+    // every z value of the tile is loaded before any is used, so the loads
+    // overlap instead of each waiting for the one before
+    double zv[RW][CPL];
 #pragma unroll
     for (int r = 0; r < RW; ++r) {
-      const int row = row0 + r;
-      if (row >= a.R_out) break;
+      const int row = min(row0 + r, a.R_out - 1);
       const int ap = row % a.r_out, ir = row / a.r_out;
       const int64_t off = ap + (int64_t)a.r_out * a.C * ir;
 #pragma unroll
+      for (int c = 0; c < CPL; ++c) zv[r][c] = (a.out_table && ok[c] && zin[c]) ? zin[c][off] : 0.0;
+    }
+    // results first, then the stores with no load or branch on a lane's
+    // data between them (a store never waits for an earlier one)
+#pragma unroll
+    for (int r = 0; r < RW; ++r)
+#pragma unroll
       for (int c = 0; c < CPL; ++c) {
-        if (!ok[c]) continue;
         if (a.out_table) {
           double v = a.alpha * acc[r][c];
-          if (zin[c]) v += zin[c][off];
-          yout[c][off] = v;
-        } else {
-          yout[c][off] = acc[r][c];
+          if (zin[c]) v += zv[r][c];
+          acc[r][c] = v;
         }
+      }
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+      const int row = row0 + r;
+      if (row < a.R_out) {
+        const int ap = row % a.r_out, ir = row / a.r_out;
+        const int64_t off = ap + (int64_t)a.r_out * a.C * ir;
+#pragma unroll
+        for (int c = 0; c < CPL; ++c)
+          if (ok[c]) yout[c][off] = acc[r][c];
       }
     }
   }
