@@ -2111,14 +2111,18 @@ __global__ void __launch_bounds__(256) core_step_bf16_last_kernel(const StepArgs
     u.y = ybase + (int64_t)a.r_out * q;
     u.hz = (zbase != nullptr);
     // the same number of loads on every path (so that the compiler's count
-    // of outstanding loads stays exact): without z, the output's own entries
-    // are read and ignored; rows past R_out read row R_out - 1 again
-    const gdouble* zq = (u.hz ? zbase : ybase) + (int64_t)a.r_out * q;
+    // of outstanding loads stays exact): without z, the first 8 bytes of the
+    // lane's own input column are read and ignored (a cache hit: the column
+    // is loaded just after); rows past R_out read row R_out - 1 again
+    typedef __attribute__((address_space(1))) const double gcdouble;
+    gcdouble* zq = u.hz ? zbase + (int64_t)a.r_out * q : (gcdouble*)(in + (t * 16 + cl) * (int64_t)a.K_in);
+    const int64_t zs = u.hz ? (int64_t)a.r_out * a.C : 0;
+    const int zr = u.hz ? 1 : 0;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int row = min(4 * (lane >> 4) + v, a.R_out - 1);
       const int ir = row / a.r_out, ar = row - ir * a.r_out;
-      u.z[v] = zq[ar + (int64_t)a.r_out * a.C * ir];
+      u.z[v] = zq[zr * ar + zs * ir];
     }
     load(u.b, t);
   };
