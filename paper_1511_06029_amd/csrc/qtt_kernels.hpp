@@ -1002,6 +1002,22 @@ __global__ void __launch_bounds__(256, 2) core_pair_f64_kernel(const PairArgs ar
       dst[i] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rB, voB[i], soff, 0));
   };
 
+  // HOLD (the first core's pair, not padded): the first PFA steps of core k
+  // (all of them: K_in = 8 is 2 steps) and the first PF steps of core k + 1
+  // are the same for every tile; they are loaded once and copied into the
+  // rings at the start of each step, so that no step of these short tiles
+  // starts by waiting for core fragments.  The padded 256-row kernel would
+  // spill, and holding the first steps of core k + 1 in the other pairs
+  // measured no gain.
+  constexpr bool HOLD = FIRST && !PAD;
+  constexpr int HB = HOLD ? PF : 0;
+  double holdA[HOLD ? PFA : 1][WRA], holdB[HB > 0 ? HB : 1][WRB];
+  if constexpr (HOLD) {
+#pragma unroll
+    for (int p = 0; p < PFA; ++p) loadA(holdA[p], p);
+  }
+#pragma unroll
+  for (int p = 0; p < HB; ++p) loadB(holdB[p], p);
   gload(blockIdx.x, 0);
   for (int64_t t = 0; t < my_tiles; ++t) {
     const int64_t tile = blockIdx.x + t * (int64_t)gridDim.x;
@@ -1012,7 +1028,14 @@ __global__ void __launch_bounds__(256, 2) core_pair_f64_kernel(const PairArgs ar
       __syncthreads();                             // the previous tile's step k + 1 is done with lds
       lstore(0);
 #pragma unroll
-      for (int p = 0; p < PFA; ++p) loadA(ring[p], p);
+      for (int p = 0; p < PFA; ++p) {
+        if constexpr (HOLD) {
+#pragma unroll
+          for (int i = 0; i < WRA; ++i) ring[p][i] = holdA[p][i];
+        } else {
+          loadA(ring[p], p);
+        }
+      }
 #pragma unroll
       for (int i = 0; i < WRA; ++i)
 #pragma unroll
@@ -1078,7 +1101,14 @@ __global__ void __launch_bounds__(256, 2) core_pair_f64_kernel(const PairArgs ar
     v4d acc[WRB][CB];
     double ring[PF][WRB];
 #pragma unroll
-    for (int p = 0; p < PF; ++p) loadB(ring[p], p);
+    for (int p = 0; p < PF; ++p) {
+      if (p < HB) {
+#pragma unroll
+        for (int i = 0; i < WRB; ++i) ring[p][i] = holdB[p][i];
+      } else {
+        loadB(ring[p], p);
+      }
+    }
     if (t + 1 < my_tiles) gload(tile + gridDim.x, 0);
 #pragma unroll
     for (int i = 0; i < WRB; ++i)
