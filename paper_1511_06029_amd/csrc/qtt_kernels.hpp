@@ -1018,6 +1018,18 @@ __global__ void __launch_bounds__(256, 2) core_pair_f64_kernel(const PairArgs ar
   }
 #pragma unroll
   for (int p = 0; p < HB; ++p) loadB(holdB[p], p);
+  // Otherwise the first PFA steps of core k are loaded at the end of the
+  // previous tile's step k + 1, before its output stores: loads and stores
+  // complete in issue order, so fragments loaded after the stores could not
+  // be used before every store had completed.  (Live only across the
+  // epilogue, where the ring of core k + 1 is dead; not in the padded
+  // kernels, which would spill.)
+  constexpr bool NEXTA = !HOLD && !PAD;
+  double nextA[NEXTA ? PFA : 1][WRA];
+  if constexpr (NEXTA) {
+#pragma unroll
+    for (int p = 0; p < PFA; ++p) loadA(nextA[p], p);
+  }
   gload(blockIdx.x, 0);
   for (int64_t t = 0; t < my_tiles; ++t) {
     const int64_t tile = blockIdx.x + t * (int64_t)gridDim.x;
@@ -1032,6 +1044,9 @@ __global__ void __launch_bounds__(256, 2) core_pair_f64_kernel(const PairArgs ar
         if constexpr (HOLD) {
 #pragma unroll
           for (int i = 0; i < WRA; ++i) ring[p][i] = holdA[p][i];
+        } else if constexpr (NEXTA) {
+#pragma unroll
+          for (int i = 0; i < WRA; ++i) ring[p][i] = nextA[p][i];
         } else {
           loadA(ring[p], p);
         }
@@ -1137,6 +1152,12 @@ __global__ void __launch_bounds__(256, 2) core_pair_f64_kernel(const PairArgs ar
 #pragma unroll
           for (int j = 0; j < CB; ++j)
             acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[j], bc[i], acc[i][j], 0, 0, 0);
+      }
+    }
+    if constexpr (NEXTA) {
+      if (t + 1 < my_tiles) {
+#pragma unroll
+        for (int p = 0; p < PFA; ++p) loadA(nextA[p], p);
       }
     }
     // ---- y_{k+1}(a', q' + C i_{k+1}) with q' = Q + (C / 8) i_k ----
