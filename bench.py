@@ -109,7 +109,7 @@ def main():
     variants = [v.strip() for v in args.variants.split(",") if v.strip()]
 
     A = Q.qtt_matrix_load(Ac, dtypes=("fp64",))
-    inv_dtypes = tuple(sorted(set(variants) | {"fp64"}))
+    inv_dtypes = tuple(sorted({DT(v) for v in variants} | {"fp64"}))
     Ai0 = Q.qtt_matrix_load(Aic, dtypes=inv_dtypes)
     F = Q.to_block(F_h)
     # setup (untimed): the compressed inverse at the operator's ranks (<= 32),
@@ -128,8 +128,16 @@ def main():
                     "seconds": round(time.perf_counter() - t_inv, 2), "steps": ns_steps,
                     "residual_history": [float(f"{h:.3e}") for h in hist], "ranks": Ai.ranks}
     Aic = Q.qtt_matrix_cores(Ai)
+    # each variant's inverse handle and compute dtype; fp32s is a second FP32
+    # handle of the same inverse with the split-product configuration pinned on
+    # its interior cores
+    inv_h = {v: (Ai, v) for v in variants + ["fp64"]}
+    if "fp32s" in variants:
+        Ais = Q.qtt_matrix_load(Aic, dtypes=("fp32",))
+        Q.qtt_use_split_products(Ais)
+        inv_h["fp32s"] = (Ais, "fp32")
     Sig = Q.empty_block(N, K)
-    ws_bytes = max(Q.qtt_solve_workspace_bytes(A, Ai, v, K) for v in variants)
+    ws_bytes = max(Q.qtt_solve_workspace_bytes(A, inv_h[v][0], inv_h[v][1], K) for v in variants)
     ws = Q.workspace(ws_bytes)
     stream = torch.cuda.current_stream()
 
@@ -137,17 +145,19 @@ def main():
     if args.tune and not args.no_tune:
         Yt = Q.empty_block(N, K)
         aws = Q.workspace(max(Q.qtt_workspace_bytes(A, "fp64", K),
-                              *[Q.qtt_workspace_bytes(Ai, v, K) for v in variants]))
+                              *[Q.qtt_workspace_bytes(Ai, DT(v), K) for v in variants]))
         Q.qtt_autotune(A, "fp64", F, Yt, aws)
         for v in variants:
-            Q.qtt_autotune(Ai, v, F, Yt, aws)
+            if v != "fp32s":          # pinned configuration: not tuned
+                Q.qtt_autotune(Ai, v, F, Yt, aws)
         del Yt, aws
         torch.cuda.synchronize()
 
     results = {}
     for v in variants:
+        Ah, dv = inv_h[v]
         for _ in range(args.warmup):
-            Q.qtt_solve(A, Ai, v, F, Sig, rtol=rtol, ws=ws, stream=stream)
+            Q.qtt_solve(A, Ah, dv, F, Sig, rtol=rtol, ws=ws, stream=stream)
         torch.cuda.synchronize()
         # the timed solves replay each sweep from its captured graph (one
         # hipGraphLaunch per sweep); no per-launch events in this region
@@ -157,7 +167,7 @@ def main():
         t0 = time.perf_counter()
         for _ in range(args.steps):
             s0 = time.perf_counter()
-            _, info, _ = Q.qtt_solve(A, Ai, v, F, Sig, rtol=rtol, ws=ws, stream=stream)
+            _, info, _ = Q.qtt_solve(A, Ah, dv, F, Sig, rtol=rtol, ws=ws, stream=stream)
             lat.append((time.perf_counter() - s0) * 1e3)
             infos.append(info)
         torch.cuda.synchronize()
@@ -169,12 +179,13 @@ def main():
             Q.qtt_timing_reset()
             Q.qtt_timing_enable(True)
             for _ in range(max(2, min(args.steps, 5))):
-                Q.qtt_solve(A, Ai, v, F, Sig, rtol=rtol, ws=ws, stream=stream)
+                Q.qtt_solve(A, Ah, dv, F, Sig, rtol=rtol, ws=ws, stream=stream)
             torch.cuda.synchronize()
             Q.qtt_timing_enable(False)
-            kt = {(dt, pos): Q.qtt_timing_read(dt, pos) for dt in ("fp64", v) for pos in (0, 1, 2)}
+            kt = {(dt, pos): Q.qtt_timing_read(dt, pos) for dt in ("fp64", dv) for pos in (0, 1, 2)}
             ks = {(dt, sh): Q.qtt_timing_read_shape(dt, sh)
-                  for dt in ("fp64", v) for sh in Q.qtt_list_shapes(dt) + Q.PAIR_SHAPES}
+                  for dt in ("fp64", dv)
+                  for sh in Q.qtt_list_shapes(dt) + Q.PAIR_SHAPES + ([Q.F32_SPLIT] if dt == "fp32" else [])}
             Q.qtt_timing_reset()
         elapsed = t1 - t0
         if v == variants[0]:
@@ -233,11 +244,11 @@ def main():
                 "achieved_hbm_GBs": round(f64["bytes"] / f64["ms"] * 1e-6, 1)}
     roof_lo = None
     if head != "fp64":
-        shlo, lo = dominant(head)
+        shlo, lo = dominant(DT(head))
         if lo is not None:
             gbs = lo["bytes"] / lo["ms"] * 1e-6
             tfs = lo["flops"] / lo["ms"] * 1e-9
-            tlo, klo = measured_traffic(head, shlo)
+            tlo, klo = measured_traffic(DT(head), shlo)
             roof_lo = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                        "frac": round(gbs / PEAK_HBM_GBS, 4), "tflops": round(tfs, 2),
                        "traffic": (None if (tlo is None or args.tune) else tlo),
@@ -245,7 +256,7 @@ def main():
                                   + ", the one carrying most of the inverse apply's flops"),
                        "launches": lo["launches"], "avg_launch_ms": round(lo["ms"] / lo["launches"], 4)}
 
-    fg = None if args.no_fgmres else fgmres_run(Q, torch, A, Ai, head, F, K, N, rtol, args)
+    fg = None if args.no_fgmres else fgmres_run(Q, torch, A, inv_h[head][0], inv_h[head][1], F, K, N, rtol, args)
 
     nti = None if args.no_nti else nti_run(Q, torch, Ac, F, K, N)
     cmv = None if args.no_compressed else compressed_run(Q, torch, Ac)
@@ -261,8 +272,8 @@ def main():
         # one standalone inverse apply of the first right-hand side per dtype
         inv_applies = {}
         f0 = F[:, :1].contiguous()
-        for dt in sorted(set(variants) | {"fp64"}):
-            inv_applies[dt] = Q.qtt_apply(Ai, dt, f0)[:, 0].cpu().numpy().copy()
+        for v in sorted(set(variants) | {"fp64"}):
+            inv_applies[v] = Q.qtt_apply(inv_h[v][0], inv_h[v][1], f0)[:, 0].cpu().numpy().copy()
         cpu = cpu_baseline(Ac, Aic, F_h[:, :1], r0["passes"], sigma0, head, inv_applies)
 
     line = {
@@ -395,6 +406,11 @@ def fgmres_run(Q, torch, A, Ai, inv, F, K, N, rtol, args, max_iter=12):
             "p50_ms": round(percentile(lat, 50), 3), "p99_ms": round(percentile(lat, 99), 3),
             "steps": max(c[0] for c in info), "max_rel_residual_estimate": max(c[1] for c in info),
             "max_rel_residual_true": true}
+
+
+def DT(variant):
+    """Compute dtype of a solve variant: fp32s is FP32 with split-operand products."""
+    return "fp32" if variant == "fp32s" else variant
 
 
 def measured_traffic(dtype, shape):

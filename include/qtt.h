@@ -183,7 +183,19 @@ qtt_status_t qtt_autotune(qtt_matrix_t A, qtt_dtype_t compute, int64_t nrhs,
  * configuration on a core (shape != -1) switches that dtype's pairs off, so that the
  * pinned configuration is the one that runs.  Returns QTT_ERR_INVALID_ARG
  * for an unknown id or core index.  Used by the tests to run every kernel
- * variant, and to replay a tuning result. */
+ * variant, and to replay a tuning result.
+ *
+ * Configuration 38 (QTT_FP32 only, interior cores; never chosen by default,
+ * by qtt_autotune or listed by qtt_list_shapes) forms each FP32 product on
+ * the BF16 matrix instruction from split operands: every FP32 core value and
+ * input value v is written bf16(v) + bf16(v - bf16(v)) and the product
+ * M b as M_hi b_hi + M_hi b_lo + M_lo b_hi with FP32 accumulation.  Cores,
+ * intermediates and accumulation stay FP32; the error of each product term
+ * is at most about 3 * 2^-16 of its size instead of 2^-24, for about a fifth of the
+ * FP32 matrix-instruction time.  It serves cores with K_in <= 256,
+ * K_in % 8 == 0, r_k m_k a multiple of 64 up to 256, r_k % 4 == 0 and
+ * C_k % 32 == 0 (the handle builds the split copy at load for every FP32
+ * core with K_in <= 256, K_in % 8 == 0); other cores keep the default. */
 qtt_status_t qtt_set_shape(qtt_matrix_t A, qtt_dtype_t compute, int32_t core, int32_t shape);
 
 /* Ids of the configurations available for a dtype (up to cap written to

@@ -41,6 +41,11 @@ struct CoreDev {
   double* valu1;      // FP64 vector-ALU copy Mv, groups of 1
   int Rpad;           // rows of Mv
   double* g64 = nullptr;  // FP64 core as given, [r_in][m][n][r_out] (compressed products)
+  // FP32 core split into BF16 hi and lo fragment arrays (hi, then lo, each in
+  // the BF16 fragment layout with fsplit_ks steps), for K_in <= 256, K_in % 8 == 0
+  void* fsplit = nullptr;
+  int fsplit_ks = 0;
+  int32_t fsplit_half = 0;  // bytes of one of the two arrays
 };
 
 struct qtt_matrix_s {

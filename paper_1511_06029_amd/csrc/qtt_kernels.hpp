@@ -1944,6 +1944,204 @@ __global__ void __launch_bounds__(256, TCB == 2 ? 2 : 1) core_step_bf16_dma_kern
 }
 
 // ---------------------------------------------------------------------------
+// FP32 interior core step with each product formed on the BF16 matrix
+// instruction from a two-term split of both operands.
+//
+// An FP32 value v is written v_hi + v_lo + e with v_hi = bf16(v) and
+// v_lo = bf16(v - v_hi) (nearest even, unit roundoff 2^-8; v - v_hi is exact
+// in FP32), so |e| <= 2^-16 |v|.  The product is M b ~ M_hi b_hi + M_hi b_lo
+// + M_lo b_hi, accumulated in FP32: the omitted M_lo b_lo and the two
+// remainders leave each term's error below about 3 * 2^-16 of its size
+// (typically near 2^-19; FP32 products: 2^-24),
+// and the three BF16 products cost about a fifth of the FP32 matrix
+// instruction's time for the same product (16x16x32 BF16 at 16 times the
+// 16x16x4 FP32 rate).  Inputs and outputs stay FP32 in memory.
+//
+// Workgroup of 8 waves, 32-column tiles; wave w holds the hi and lo core
+// fragments of row blocks 2w and 2w + 1 (256 rows) for all 8 steps in
+// registers.  A tile's operand buffer in LDS has 16 blocks of 2 KB (column
+// block cb, step s: 1 KB of hi fragment, then 1 KB of lo).  Lane l of wave w
+// reads, for each of blocks 2w and 2w + 1, the 32 contiguous bytes of its
+// fragment slot (column 16 cb + l mod 16, step offsets 8 (l div 16) .. + 7)
+// into registers two tiles ahead, splits them and writes its hi and lo
+// slots.  Every lane issues the same loads and stores in every tile (tile
+// indices past the end are clamped, the stores per lane are the template
+// constant SPT = R_out / 64), so the compiler's counter waits stay exact and
+// two tiles of loads stay in flight.  Results are staged in LDS laid out as
+// in memory (run a + r_k q of r_k TC values per i_k) and leave as 16-byte
+// stores.  Host requirements: interior core, K_in <= 256, K_in % 8 == 0,
+// R_out = 64 SPT, r_k % 4 == 0, C % 32 == 0, 16-byte aligned input and output.
+// ---------------------------------------------------------------------------
+__device__ inline uint32_t bf16x2_bits(float a, float b) {
+  return (uint32_t)bf16_rne_dev(a) | ((uint32_t)bf16_rne_dev(b) << 16);
+}
+
+template <int SPT>
+__global__ void __launch_bounds__(512, 2) core_step_f32_split_kernel(const StepArgs args) {
+  (void)args;
+  const StepArgs& a = kernarg<StepArgs>();
+  using MF = Mfma<bf16_tag>;
+  constexpr int NW = 8, WR = 2, TCB = 2, TC = 16 * TCB, KS = 8, NT = 64 * NW;
+  constexpr int BLK_F = 512;                       // floats per (column block, step) block
+  typedef __attribute__((address_space(1))) const v4f gv4f;
+  __shared__ __attribute__((aligned(1024))) float lin[TCB * KS * BLK_F];
+  __shared__ __attribute__((aligned(16))) float lout[TC * 256];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int Ks = a.Ksteps;                         // host guarantees Ks <= KS
+  const uint16_t* __restrict__ Mh = reinterpret_cast<const uint16_t*>(a.M);
+  const uint16_t* __restrict__ Ml = reinterpret_cast<const uint16_t*>(static_cast<const char*>(a.M) + a.M_bytes);
+  float* __restrict__ out = reinterpret_cast<float*>(a.out);
+
+  v8bf mh[WR][KS], ml[WR][KS];
+#pragma unroll
+  for (int i = 0; i < WR; ++i) {
+    const int rbg = wave * WR + i;
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      mh[i][s] = MF::zero_frag();
+      ml[i][s] = MF::zero_frag();
+      if (rbg < a.nRB && s < Ks) {
+        const int64_t o = (((int64_t)rbg * Ks + s) * 64 + lane) * 8;
+        mh[i][s] = MF::load_frag(Mh + o);
+        ml[i][s] = MF::load_frag(Ml + o);
+      }
+    }
+  }
+  wait_vmcnt<0>();
+  const int64_t ntiles = a.ncols / TC;
+  const int64_t my = (ntiles > (int64_t)blockIdx.x) ? (ntiles - 1 - (int64_t)blockIdx.x) / gridDim.x + 1 : 0;
+  if (my == 0) return;
+  const bool has_rows = wave * WR < a.nRB;
+
+  // this lane's slot in blocks 2w and 2w + 1: column 16 cb + cl, offsets 8 g ..
+  const int g = lane >> 4, cl = lane & 15;
+  int64_t src[2];
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    const int blk = 2 * wave + b, cb = blk / KS, s = blk % KS;
+    src[b] = (int64_t)(cb * 16 + cl) * a.K_in + min(32 * s + 8 * g, a.K_in - 8);
+  }
+  gv4f* in = (gv4f*)a.in;
+  auto load = [&](int64_t t, v4f (&x)[2][2]) {
+    t = min(t, my - 1);                            // clamped: the same loads in every tile
+    const int64_t col0 = (blockIdx.x + t * (int64_t)gridDim.x) * TC;
+    gv4f* base = (gv4f*)((__attribute__((address_space(1))) const float*)in + col0 * a.K_in);
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      gv4f* p = (gv4f*)((__attribute__((address_space(1))) const float*)base + src[b]);
+      x[b][0] = p[0];
+      x[b][1] = p[1];
+    }
+  };
+  auto split = [&](const v4f (&x)[2][2]) {
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      float* blk = lin + (2 * wave + b) * BLK_F;
+      v4u hi, lo;
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        const float x0 = x[b][p >> 1][2 * (p & 1)], x1 = x[b][p >> 1][2 * (p & 1) + 1];
+        hi[p] = bf16x2_bits(x0, x1);
+        lo[p] = bf16x2_bits(x0 - __builtin_bit_cast(float, hi[p] << 16),
+                            x1 - __builtin_bit_cast(float, hi[p] & 0xffff0000u));
+      }
+      *reinterpret_cast<v4u*>(blk + 4 * lane) = hi;
+      *reinterpret_cast<v4u*>(blk + 256 + 4 * lane) = lo;
+    }
+  };
+
+  const int rows_out = a.R_out;                    // = 64 SPT
+  const int r = a.r_out;                           // host: r % 4 == 0
+  const int spq = r / 4;                           // 16-byte slots per column of one i_k run
+  const int swm = (spq == 2 || spq == 4 || spq == 8) ? spq - 1 : 0;
+  // one tile: its input (in x) is split into the operand buffer, whose last
+  // readers (the previous tile's matrix work) are behind the previous tile's
+  // second barrier; x is then refilled with tile t + 2
+  auto tile = [&](int64_t t, v4f (&x)[2][2]) {
+    split(x);
+    load(t + 2, x);
+    __syncthreads();
+    if (has_rows) {
+      v4f acc[WR][TCB];
+#pragma unroll
+      for (int i = 0; i < WR; ++i)
+#pragma unroll
+        for (int j = 0; j < TCB; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        if (s < Ks) {
+          v8bf ah[TCB], al[TCB];
+#pragma unroll
+          for (int j = 0; j < TCB; ++j) {
+            const float* blk = lin + (j * KS + s) * BLK_F;
+            ah[j] = __builtin_bit_cast(v8bf, *reinterpret_cast<const v4u*>(blk + 4 * lane));
+            al[j] = __builtin_bit_cast(v8bf, *reinterpret_cast<const v4u*>(blk + 256 + 4 * lane));
+          }
+#pragma unroll
+          for (int i = 0; i < WR; ++i)
+#pragma unroll
+            for (int j = 0; j < TCB; ++j) {
+              acc[i][j] = MF::mma(ml[i][s], ah[j], acc[i][j]);
+              acc[i][j] = MF::mma(mh[i][s], al[j], acc[i][j]);
+              acc[i][j] = MF::mma(mh[i][s], ah[j], acc[i][j]);
+            }
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < WR; ++i) {
+        const int row0 = (wave * WR + i) * 16 + 4 * (lane >> 4);
+        if (row0 < rows_out) {                       // rows_out % 64 == 0: all four rows exist
+          const int ir = row0 / r, ar = row0 - ir * r;
+#pragma unroll
+          for (int j = 0; j < TCB; ++j) {
+            const int q = j * 16 + (lane & 15);
+            const int slot = q * spq + ((ar >> 2) ^ (q & swm));
+            *reinterpret_cast<v4f*>(&lout[ir * (r * TC) + 4 * slot]) = acc[i][j];
+          }
+        }
+      }
+    }
+    __syncthreads();
+    const int64_t col0 = (blockIdx.x + t * (int64_t)gridDim.x) * TC;
+    const int64_t rhs = col0 / a.C;
+    const int64_t q0 = col0 - rhs * a.C;
+    float* dst = out + rhs * a.out_stride + (int64_t)r * q0;
+    const int per_i = r * TC / 4;
+#pragma unroll
+    for (int u = 0; u < SPT; ++u) {
+      const int idx = tid + u * NT;
+      const int ir = idx / per_i;
+      const int v = idx - ir * per_i;
+      const int q = v / spq, w = v - q * spq;
+      const int vp = q * spq + (w ^ (q & swm));
+      reinterpret_cast<v4f*>(dst + (int64_t)r * a.C * ir)[v] =
+          *reinterpret_cast<const v4f*>(&lout[ir * (r * TC) + 4 * vp]);
+    }
+    // the next tile writes lout after its first barrier, which every lane
+    // reaches only after these reads
+  };
+  // the first two tiles are peeled so that the loop is entered with the
+  // same operations outstanding as on its back edge (the compiler's wait at
+  // the loop head serves both)
+  v4f xa[2][2], xb[2][2];
+  load(0, xa);
+  load(1, xb);
+  tile(0, xa);
+  if (my > 1) {
+    tile(1, xb);
+    int64_t t = 2;
+    for (; t + 1 < my; t += 2) {
+      tile(t, xa);
+      tile(t + 1, xb);
+    }
+    if (t < my) tile(t, xa);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // First core step with a short contraction (K_in = n_1 <= 16) on the vector
 // ALUs, any compute dtype.
 //

@@ -41,6 +41,9 @@ void add_kernels_bf16(std::vector<KernelCfg>& v);
 // core_step_bf16_dma_kernel<tcb>, tcb = 2 or 4, and core_step_bf16_last_kernel (qtt_k_bf16.hip)
 const void* bf16_dma_kernel(int tcb);
 const void* bf16_last_kernel();
+// core_step_f32_split_kernel<spt>: FP32 interior step from split BF16 products,
+// R_out = 64 spt, spt = 1..4 (qtt_k_f32.hip)
+const void* f32_split_kernel(int spt);
 // fused core pairs (qtt_k_pair64.hip, qtt_k_pair32.hip); index
 // 6 first + 2 (0: rank 24, 1: rank 32, 2: padded 17..32) + (rows of core k + 1 > 192)
 const void* pair_f64_kernel(int f);

@@ -188,6 +188,33 @@ static KernelCfg* bf16_dma32_cfg() {
   return &k;
 }
 
+// FP32 interior cores with the products formed from split BF16 operands
+// (shape id 38, core_step_f32_split_kernel): never chosen by the heuristic
+// or the autotuner (its rounding error is up to about 3 * 2^-16 per product
+// term against 2^-24), only
+// when pinned with qtt_set_shape.  One instantiation per R_out / 64.
+static const int kF32Split = 38;
+static KernelCfg* f32_split_cfg(int spt) {
+  static KernelCfg k[4] = {};
+  static std::once_flag once;
+  std::call_once(once, [] {
+    for (int i = 0; i < 4; ++i) {
+      k[i].dt = 1;
+      k[i].in_f64 = false;
+      k[i].vec = true;
+      k[i].TR = 256;
+      k[i].TC = 32;
+      k[i].KC = 256;
+      k[i].NT = 512;
+      k[i].id = kF32Split;
+      k[i].fn = f32_split_kernel(i + 1);
+      k[i].occ = 0;
+      k[i].kind = -1;
+    }
+  });
+  return &k[spt - 1];
+}
+
 // First core with a short contraction on the vector ALUs (shape id 34), one
 // instantiation per compute dtype.
 static KernelCfg* smallk_cfg(int dt) {
@@ -469,6 +496,11 @@ static qtt_status_t launch_step(const qtt_matrix_s* A, int k, int dt, int64_t nr
   const bool last_ok = dt == 2 && last && !first && c.R_out <= 16 && c.K_in % 8 == 0 && c.Ksteps[2] <= 8 &&
                        c.C % 16 == 0 && vec && reinterpret_cast<uintptr_t>(in_packed) % 16 == 0;
   if (shape == kBf16Last && !last_ok) shape = 2;
+  const bool split_ok = dt == 1 && !first && !last && c.fsplit != nullptr && c.fsplit_ks <= 8 &&
+                        c.R_out % 64 == 0 && c.R_out <= 256 && c.r_out % 4 == 0 && c.K_in % 8 == 0 &&
+                        c.C % 32 == 0 && reinterpret_cast<uintptr_t>(in_packed) % 16 == 0 &&
+                        reinterpret_cast<uintptr_t>(out_packed) % 16 == 0;
+  if (shape == kF32Split && !split_ok) shape = heuristic_shape(c.R_out, c.K_in, dt);
   const int tq = smallk_cfg(dt)->TC;
   const bool smallk_ok = first && !last && vec && c.K_in <= 16 && c.K_in % 2 == 0 && c.R_out <= 256 &&
                          c.r_out % 4 == 0 && c.C % tq == 0 && (c.r_out * tq * kElemBytes[dt]) % 16 == 0 &&
@@ -477,6 +509,7 @@ static qtt_status_t launch_step(const qtt_matrix_s* A, int k, int dt, int64_t nr
   const bool smallk_rows = shape == kSmallK && dt == 2 && c.K_in <= 8 && c.r_out <= 32 &&
                            c.R_out / c.r_out <= 8 && c.C % 64 == 0;
   KernelCfg* kc = smallk_rows ? smallk_rows_cfg()
+                  : (shape == kF32Split) ? f32_split_cfg(c.R_out / 64)
                   : (shape == kSmallK) ? smallk_cfg(dt)
                   : (shape == kBf16Last) ? bf16_last_cfg()
                   : (shape == kBf16Dma) ? bf16_dma_cfg()
@@ -512,6 +545,11 @@ static qtt_status_t launch_step(const qtt_matrix_s* A, int k, int dt, int64_t nr
   a.M_bytes = (int32_t)std::min<int64_t>(m_bytes, INT32_MAX);
   a.alpha = alpha;
   a.seg = dsegs;
+  if (shape == kF32Split) {       // hi and lo fragment arrays, BF16 steps
+    a.M = c.fsplit;
+    a.Ksteps = c.fsplit_ks;
+    a.M_bytes = c.fsplit_half;
+  }
 
   const int64_t resident = (int64_t)occupancy(kc) * num_cus();
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(a.n_tiles, resident));
@@ -1022,6 +1060,48 @@ qtt_status_t qtt_matrix_load(int32_t d, const int64_t* ranks, const int64_t* m, 
       }
     }
   }
+  // FP32 cores split for configuration kF32Split: v = (float) M_k(row, kap),
+  // hi = bf16(v), lo = bf16(v - hi), each array in the BF16 fragment layout
+  if (dtypes & QTT_FP32) {
+    for (int k = 0; k < d; ++k) {
+      CoreDev& c = A->core[k];
+      if (c.K_in > 256 || c.K_in % 8 != 0) continue;
+      const double* G = cores[k];
+      const int KS = kKstep[2], E = kFragE[2];
+      const int Ksteps = (c.K_in + KS - 1) / KS;
+      const size_t nel = (size_t)padded_row_blocks(c.nRB) * Ksteps * 64 * E;
+      std::vector<uint16_t> b(2 * nel, 0);
+      for (int rb = 0; rb < c.nRB; ++rb)
+        for (int s = 0; s < Ksteps; ++s)
+          for (int l = 0; l < 64; ++l)
+            for (int e = 0; e < E; ++e) {
+              const int row = 16 * rb + (l & 15);
+              const int kap = KS * s + E * (l >> 4) + e;
+              if (row >= c.R_out || kap >= c.K_in) continue;
+              const int ak = row % c.r_out, ik = row / c.r_out;
+              const int ap = kap % c.r_in, jk = kap / c.r_in;
+              const float v = (float)G[(((size_t)ap * c.m + ik) * c.n + jk) * c.r_out + ak];
+              const uint16_t hi = f32_to_bf16_rne(v);
+              const float hv = __builtin_bit_cast(float, (uint32_t)hi << 16);
+              const size_t at = (((size_t)rb * Ksteps + s) * 64 + l) * E + e;
+              b[at] = hi;
+              b[nel + at] = f32_to_bf16_rne(v - hv);
+            }
+      void* dptr = nullptr;
+      if (hipMalloc(&dptr, std::max<size_t>(2 * nel * 2, 256)) != hipSuccess) {
+        qtt_matrix_free(A);
+        return fail(QTT_ERR_OUT_OF_MEMORY, "hipMalloc for the split FP32 copy of core %d failed", k);
+      }
+      c.fsplit = dptr;
+      c.fsplit_ks = Ksteps;
+      c.fsplit_half = (int32_t)(nel * 2);
+      hipError_t er = hipMemcpy(dptr, b.data(), 2 * nel * 2, hipMemcpyHostToDevice);
+      if (er != hipSuccess) {
+        qtt_matrix_free(A);
+        return fail(QTT_ERR_DEVICE, "hipMemcpy of core %d failed: %s", k, hipGetErrorString(er));
+      }
+    }
+  }
   // FP64 vector-ALU copies: Mv[(g * Rpad + row) * G + e] = M_k(row, G g + e)
   if (dtypes & QTT_FP64) {
     for (int k = 0; k < d; ++k) {
@@ -1087,6 +1167,7 @@ qtt_status_t qtt_matrix_free(qtt_matrix_t A) {
     if (c.valu) (void)hipFree(c.valu);
     if (c.valu1) (void)hipFree(c.valu1);
     if (c.g64) (void)hipFree(c.g64);
+    if (c.fsplit) (void)hipFree(c.fsplit);
   }
   delete A;
   return QTT_OK;
@@ -1391,7 +1472,7 @@ qtt_status_t qtt_set_shape(qtt_matrix_t A, qtt_dtype_t compute, int32_t core, in
     return QTT_OK;
   }
   if (core < 0 || core >= A->d) return fail(QTT_ERR_INVALID_ARG, "core %d out of range", core);
-  if (shape != -1) {
+  if (shape != -1 && !(dt == 1 && shape == kF32Split)) {
     int32_t ids[128], n = 0;
     qtt_list_shapes(compute, ids, 128, &n);
     bool found = false;

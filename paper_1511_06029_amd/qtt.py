@@ -28,6 +28,8 @@ DTYPES = {"fp64": QTT_FP64, "fp32": QTT_FP32, "bf16": QTT_BF16}
 # FP64 90.., FP32 100.. (+ 4 first core + 2 padded rank-32 kernel + rows of
 # the second core above 192)
 PAIR_SHAPES = list(range(90, 98)) + list(range(100, 108))
+# FP32 interior cores with products formed from split BF16 operands (pinned only)
+F32_SPLIT = 38
 
 QTT_OK = 0
 QTT_ERR_NOT_CONVERGED = 5
@@ -423,6 +425,15 @@ def qtt_solve_fgmres_product(A, M, Y, inv_compute, F, Sigma=None, rtol=1e-8, max
 
 def qtt_set_shape(A, compute, core, shape):
     _check(_lib.qtt_set_shape(A.handle, _dtype(compute), int(core), int(shape)))
+
+
+def qtt_use_split_products(A, on=True):
+    """Pin (on) or unpin the FP32 split-operand configuration on every interior
+    core of A; cores it cannot serve keep the default kernels at launch."""
+    for k in range(1, A.d - 1):
+        qtt_set_shape(A, "fp32", k, F32_SPLIT if on else -1)
+    if not on:
+        qtt_set_shape(A, "fp32", -2, 1)     # pinning switched the FP32 pairs off
 
 
 def qtt_list_shapes(compute):

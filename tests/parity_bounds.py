@@ -12,19 +12,27 @@ of these is a relative perturbation of one factor of the product of the cores
 where |A| is the QTT matrix with cores |G_k| (the magnitude of every term of
 the sum that defines A(i, j)) and |X| the entrywise magnitude.  The oracle
 applies |A| to |X| in FP64.  A small absolute floor covers FP32 underflow.
+
+"fp32s" is the FP32 sweep with products formed from split BF16 operands
+(v = bf16(v) + bf16(v - bf16(v)) + e, |e| <= 2^-16 |v|, the product of the
+two lo parts omitted): each product term is off by at most
+(1 + 2^-24)^2 (1 + 2^-16)^2 - 1 + 2^-16 (1 + 2^-8)^2 < 4 * 2^-16 of its
+size, covered by two factors (1 + 2^-15) per core; its three matrix
+instructions per contraction index triple the FP32 additions.
 """
 import numpy as np
 
 from oracle import qtt_oracle as O
 
-UNIT = {"fp32": 2.0 ** -24, "bf16": 2.0 ** -8}
+UNIT = {"fp32": 2.0 ** -24, "bf16": 2.0 ** -8, "fp32s": 2.0 ** -15}
+ACC_TERMS = {"fp32": 1, "bf16": 1, "fp32s": 3}
 U_ACC = 2.0 ** -24
 
 
 def growth(cores, dtype):
     d = len(cores)
     kin = sum(G.shape[0] * G.shape[2] for G in cores)
-    return (1.0 + UNIT[dtype]) ** (2 * d) * (1.0 + U_ACC) ** kin - 1.0
+    return (1.0 + UNIT[dtype]) ** (2 * d) * (1.0 + U_ACC) ** (ACC_TERMS[dtype] * kin) - 1.0
 
 
 def magnitude(cores, X):

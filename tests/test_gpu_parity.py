@@ -25,7 +25,7 @@ import qtt_structures as S
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp64": 1e-12, "fp32": 1e-5, "bf16": 3e-2}
+TOL = {"fp64": 1e-12, "fp32": 1e-5, "bf16": 3e-2, "fp32s": 1e-4}
 
 
 @pytest.fixture(scope="module")
@@ -342,6 +342,65 @@ def test_every_kernel_configuration(Q, dtype):
                 assert B.elementwise_ratio(Y.cpu().numpy(), ref, cores, X, dtype, mag) <= 1.0, (ranks, shape)
                 assert B.blockwise_rel(Y.cpu().numpy(), ref) <= TOL[dtype], (ranks, shape)
         A.free()
+
+
+def test_fp32_split_products(Q):
+    """FP32 sweeps with the split-operand configuration pinned on the interior
+    cores, against the oracle: element-wise within the split's rounding bound,
+    block-wise within 1e-4.  The cases cover 256, 192, 128 and 64 rows (all
+    four store counts), K_in of 104 (a partial last step), 128, 192 and 256, a
+    core it cannot serve (r_k = 13: the default kernels run there), one to
+    four tiles per workgroup (one or two peeled tiles, the loop, its odd tail), and
+    the launch timing shows which cores ran it."""
+    cases = [([1, 24, 32, 32, 24, 1], 7, 3), ([1, 16, 32, 16, 1], 2, 2), ([1, 8, 13, 8, 1], 3, 1),
+             ([1, 24, 32, 24, 1], 24, 2)]
+    for ranks, K, n_split in cases:
+        L = len(ranks) - 1
+        cores = I.gaussian_qtt(ranks, [8] * L, seed=41 + L + K)
+        X = I.rhs(8 ** L, K, seed=42 + L + K)
+        ref = O.qtt_apply_alg2(cores, X)
+        A = Q.qtt_matrix_load(cores, dtypes=("fp32",))
+        Q.qtt_use_split_products(A)
+        Xd = Q.to_block(X)
+        Q.qtt_apply(A, "fp32", Xd)
+        torch.cuda.synchronize()
+        Q.qtt_timing_reset()
+        Q.qtt_timing_enable(True)
+        Y = Q.qtt_apply(A, "fp32", Xd)
+        torch.cuda.synchronize()
+        Q.qtt_timing_enable(False)
+        ran = Q.qtt_timing_read_shape("fp32", Q.F32_SPLIT)["launches"]
+        Q.qtt_timing_reset()
+        assert ran == n_split, (ranks, ran)
+        check_reduced(Y.cpu().numpy(), ref, cores, X, "fp32s", f"split {ranks} K={K}")
+        # unpinned: the default FP32 kernels again, at FP32's own bound
+        Q.qtt_use_split_products(A, False)
+        Y = Q.qtt_apply(A, "fp32", Xd)
+        torch.cuda.synchronize()
+        check_reduced(Y.cpu().numpy(), ref, cores, X, "fp32", f"unpinned {ranks} K={K}")
+        A.free()
+
+
+@pytest.mark.slow
+def test_refine_L7_split_fp32_inverse(Q):
+    """The refined solve at full size with the FP32 inverse applied by split
+    BF16 products (the launch configuration of the benchmark's fp32s leg):
+    three passes, and the oracle recomputes the relative residual of two
+    sampled columns."""
+    w = I.WORKLOADS["refine_L7"]
+    Ac, Aic = I.perturbed_identity_pair(w["ranks"], [8] * 7, seed=w["core_seed"], eps=w["eps"])
+    F = I.rhs(8 ** 7, w["K"], seed=w["rhs_seed"])
+    A = Q.qtt_matrix_load(Ac, dtypes=("fp64",))
+    Ai = Q.qtt_matrix_load(Aic, dtypes=("fp32",))
+    Q.qtt_use_split_products(Ai)
+    Sig, info, st = Q.qtt_solve(A, Ai, "fp32", Q.to_block(F), rtol=w["rtol"])
+    print("split fp32 inverse passes", [c[0] for c in info], "residuals", [c[1] for c in info])
+    Sh = Sig.cpu().numpy()
+    for c in (0, w["K"] - 1):
+        r = F[:, c] - O.qtt_apply_alg2(Ac, Sh[:, c])
+        assert np.linalg.norm(r) <= 1e-8 * np.linalg.norm(F[:, c]) * 1.0001
+    A.free()
+    Ai.free()
 
 
 def test_timing_by_configuration(Q):
