@@ -72,8 +72,9 @@ def parse():
                    help="only run a device copy of known size (HBM counter calibration)")
     p.add_argument("--first-order-inverse", action="store_true",
                    help="solve with the first-order inverse instead of the Newton-Schulz one")
-    p.add_argument("--variants", default="bf16,fp64,fp32",
-                   help="inverse dtypes to time; the first is the reported value")
+    p.add_argument("--variants", default="fp32s,bf16,fp64,fp32",
+                   help="inverse dtypes to time (fp32s: FP32 cores, products from split BF16 "
+                        "operands); the first is the reported value")
     return p.parse_args()
 
 
@@ -292,7 +293,8 @@ def main():
         "config": {"workload": "refine_L7: refined QTT-inverse solve, L=7 (N=2097152), mode 8x8, "
                                "A ranks [1,24,32,32,32,32,24,1], inverse ranks <= 32 (computed on the GPU), "
                                "K=8 RHS per step, rtol 1e-8",
-                   "inverse_dtype": head, "residual_dtype": "fp64", "rhs_per_step": K,
+                   "inverse_dtype": head, "inverse_arithmetic": INV_ARITH.get(head, head),
+                   "residual_dtype": "fp64", "rhs_per_step": K,
                    "N": N, "L": L, "ranks": ranks},
         "latency_ms": {"p50": round(r0["p50_ms"], 3), "p99": round(r0["p99_ms"], 3)},
         "launch_path": "timed solves replay each sweep from its captured hipGraph; the roofline "
@@ -406,6 +408,15 @@ def fgmres_run(Q, torch, A, Ai, inv, F, K, N, rtol, args, max_iter=12):
             "p50_ms": round(percentile(lat, 50), 3), "p99_ms": round(percentile(lat, 99), 3),
             "steps": max(c[0] for c in info), "max_rel_residual_estimate": max(c[1] for c in info),
             "max_rel_residual_true": true}
+
+
+INV_ARITH = {
+    "fp32s": "FP32 cores and intermediates; each FP32 product formed from split BF16 operands "
+             "(hi + lo, three BF16 matrix instructions), FP32 accumulation",
+    "fp32": "FP32 cores and intermediates, FP32 matrix instructions",
+    "bf16": "BF16 cores and intermediates, FP32 accumulation",
+    "fp64": "FP64 throughout",
+}
 
 
 def DT(variant):

@@ -39,6 +39,7 @@ struct CoreDev {
   int tuned[3];       // tuned shape id per dtype, -1 = heuristic
   double* valu;       // FP64 vector-ALU copy Mv, input groups of 8 (when K_in % 8 == 0)
   double* valu1;      // FP64 vector-ALU copy Mv, groups of 1
+  float* valu32 = nullptr;  // FP32 vector-ALU copy Mv, groups of 8 (last core, K_in % 32 == 0)
   int Rpad;           // rows of Mv
   double* g64 = nullptr;  // FP64 core as given, [r_in][m][n][r_out] (compressed products)
   // FP32 core split into BF16 hi and lo fragment arrays (hi, then lo, each in

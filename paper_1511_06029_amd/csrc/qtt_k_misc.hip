@@ -1,4 +1,5 @@
-// FP64 vector-ALU core-step kernels and the short-contraction first-core kernel.
+// FP64 vector-ALU core-step kernels, the FP32 vector-ALU last core and the
+// short-contraction first-core kernels.
 #define QTT_KERNEL_TEMPLATES_ONLY
 #include "qtt_registry.hpp"
 
@@ -24,11 +25,18 @@ void add_valu_kernels(std::vector<ValuCfg>& v) {
 #undef QTT_ADDV
 }
 
+// FP32 last core: one wave of 8 rows, 2 columns per lane, 128-byte loads
+// (4 groups of 8 values)
+ValuCfg valu32_last_cfg() {
+  return {39, 1, 8, 2, 8, 4, reinterpret_cast<const void*>(&core_step_valu32_last_kernel<8, 2, 32>), 0};
+}
+
 const void* smallk_kernel(int dt) {
   switch (dt) {
     case 0: return reinterpret_cast<const void*>(&core_step_smallk_kernel<double>);
     case 1: return reinterpret_cast<const void*>(&core_step_smallk_kernel<float>);
-    case 3: return reinterpret_cast<const void*>(&core_step_smallk_bf16_kernel<8>);
+    case 3: return reinterpret_cast<const void*>(&core_step_smallk_rows_kernel<bf16_tag, 8>);
+    case 4: return reinterpret_cast<const void*>(&core_step_smallk_rows_kernel<float, 8>);
     default: return reinterpret_cast<const void*>(&core_step_smallk_kernel<bf16_tag>);
   }
 }

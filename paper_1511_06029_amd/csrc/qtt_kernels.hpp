@@ -1598,6 +1598,112 @@ __global__ void __launch_bounds__(64 * NW) core_step_valu64_kernel(const ValuArg
 }
 
 // ---------------------------------------------------------------------------
+// The FP32 last core (R_out = m_d r_d small, packed FP32 input, FP64 output
+// z + alpha acc through the segment table) on the vector ALUs.  A wave owns
+// RW consecutive rows and 64 CPL consecutive columns of one vector; lane l
+// takes columns l + 64 c.  Each output is the FP32 FMA chain over k = 0 ..
+// K_in - 1 in order, with core values from the FP32 copy Mv (groups of 8,
+// read through the scalar cache: wave-uniform addresses) and the input read
+// GL values (GL / 8 groups, whole 128-byte lines for GL = 32) a step ahead.
+// Host requirements: last core, K_in % GL == 0, C_d % (64 CPL) == 0,
+// 16-byte aligned input.
+// ---------------------------------------------------------------------------
+template <int RW, int CPL, int GL>
+__global__ void __launch_bounds__(64) core_step_valu32_last_kernel(const ValuArgs args) {
+  (void)args;
+  const ValuArgs& a = kernarg<ValuArgs>();
+  const int lane = threadIdx.x & 63;
+  constexpr int TCOL = 64 * CPL, G = 8, LG = GL / G;
+  typedef __attribute__((address_space(1))) const float gcfloat;
+  typedef __attribute__((address_space(1))) double gdouble;
+  typedef __attribute__((address_space(1))) const double gcdouble;
+  typedef __attribute__((address_space(4))) const float cfloat;
+  const int ngroups = a.K_in / GL;
+  for (int64_t tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
+    const int rt = (int)(tile % a.n_row_tiles);
+    const int64_t col0 = (tile / a.n_row_tiles) * TCOL;
+    const int row0 = rt * RW;
+    const int64_t rhs0 = col0 / a.C;                 // the tile lies in one vector
+    const Segment& sg = a.seg[find_seg(a, rhs0)];
+    gdouble* yb = (gdouble*)(sg.y + (rhs0 - sg.rhs_begin) * sg.ldy);
+    gcdouble* zb = sg.z ? (gcdouble*)(sg.z + (rhs0 - sg.rhs_begin) * sg.ldz) : nullptr;
+    gcfloat* xb = (gcfloat*)(reinterpret_cast<const float*>(a.in) + rhs0 * a.in_stride);
+    int64_t q[CPL];
+    gcfloat* xin[CPL];
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+      q[c] = col0 - rhs0 * a.C + lane + 64 * c;
+      xin[c] = xb + q[c] * a.K_in;
+    }
+    float acc[RW][CPL];
+#pragma unroll
+    for (int r = 0; r < RW; ++r)
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) acc[r][c] = 0.f;
+    float x[CPL][GL];
+    auto load_x = [&](int gi) {
+#pragma unroll
+      for (int c = 0; c < CPL; ++c)
+#pragma unroll
+        for (int e = 0; e < GL; ++e) x[c][e] = xin[c][(int64_t)gi * GL + e];
+    };
+    load_x(0);
+    for (int gi = 0; gi < ngroups; ++gi) {
+      float xc[CPL][GL];
+#pragma unroll
+      for (int c = 0; c < CPL; ++c)
+#pragma unroll
+        for (int e = 0; e < GL; ++e) xc[c][e] = x[c][e];
+      if (gi + 1 < ngroups) load_x(gi + 1);
+#pragma unroll
+      for (int lg = 0; lg < LG; ++lg) {
+        cfloat* mrow = (cfloat*)reinterpret_cast<const float*>(a.M) + ((int64_t)(gi * LG + lg) * a.Rpad + row0) * G;
+#pragma unroll
+        for (int r = 0; r < RW; ++r)
+#pragma unroll
+          for (int e = 0; e < G; ++e) {
+            const float mv = mrow[r * G + e];
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) acc[r][c] = fmaf(mv, xc[c][lg * G + e], acc[r][c]);
+          }
+      }
+    }
+    // every z value is loaded before any output is formed; the stores then
+    // follow with no branch between them when all RW rows exist (a result
+    // formed inside a per-row branch would wait there for all earlier stores)
+    int64_t off[RW];
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+      const int row = min(row0 + r, a.R_out - 1);
+      const int ap = row % a.r_out, ir = row / a.r_out;
+      off[r] = ap + (int64_t)a.r_out * a.C * ir;
+    }
+    double res[RW][CPL];
+#pragma unroll
+    for (int r = 0; r < RW; ++r)
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) res[r][c] = zb ? zb[off[r] + (int64_t)a.r_out * q[c]] : 0.0;
+#pragma unroll
+    for (int r = 0; r < RW; ++r)
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) res[r][c] += a.alpha * (double)acc[r][c];
+    if (row0 + RW <= a.R_out) {
+#pragma unroll
+      for (int r = 0; r < RW; ++r)
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) yb[off[r] + (int64_t)a.r_out * q[c]] = res[r][c];
+    } else {
+#pragma unroll
+      for (int r = 0; r < RW; ++r)
+        if (row0 + r < a.R_out) {
+#pragma unroll
+          for (int c = 0; c < CPL; ++c) yb[off[r] + (int64_t)a.r_out * q[c]] = res[r][c];
+        }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // BF16 interior core step with the core resident in registers.
 //
 // For the interior cores of the BF16 sweep (R_out = r_k m_k <= 256 and
@@ -2434,7 +2540,8 @@ __global__ void __launch_bounds__(256) core_step_bf16_last_kernel(const StepArgs
 }
 
 // ---------------------------------------------------------------------------
-// The first BF16 core with K_in <= 8 (r_0 = 1), rows held in registers.
+// The first core with K_in <= 8 (r_0 = 1), rows held in registers, for the
+// BF16 and FP32 compute types (Tc = bf16_tag, float).
 //
 // Thread (wave w, lane l): row quad aq = l mod 8 (rows 4 aq .. 4 aq + 3 of an
 // i_1 block; active when 4 aq < r_1) and column offset qq = l div 8, for the
@@ -2442,18 +2549,20 @@ __global__ void __launch_bounds__(256) core_step_bf16_last_kernel(const StepArgs
 // columns qq + 8 t, t = 0..7, of both blocks.  Each output is the FMA chain
 // over k = 0 .. K_in - 1 in order on the BF16-rounded input (the chain of
 // core_step_smallk_kernel, so the two agree bitwise).  Its four rows leave as
-// one 8-byte store: with r_1 = 32, the 8 columns x 8 row quads of a wave are
-// one contiguous 512-byte run of y_1, and no output passes through LDS.  The
-// input is staged in LDS as rounded floats, two buffers (one barrier a tile).
+// one 8-byte (BF16) or 16-byte (FP32) store: with r_1 = 32, the 8 columns x 8
+// row quads of a wave are one contiguous run of y_1, and no output passes
+// through LDS.  The input is staged in LDS as rounded floats, two buffers
+// (one barrier a tile).
 // Requirements checked by the host: first core, not the last, K_in <= 8,
 // r_1 % 4 == 0, r_1 <= 32, m_1 = R_out / r_1 <= 8, C_1 % 64 == 0, FP64
 // input columns 16-byte aligned with an even K_in, output 16-byte aligned.
 // ---------------------------------------------------------------------------
-template <int MAXK>
-__global__ void __launch_bounds__(256) core_step_smallk_bf16_kernel(const StepArgs args) {
+template <class Tc, int MAXK>
+__global__ void __launch_bounds__(256) core_step_smallk_rows_kernel(const StepArgs args) {
   (void)args;
   const StepArgs& a = kernarg<StepArgs>();
-  using S = SmallK<bf16_tag>;
+  using S = SmallK<Tc>;
+  using out_t = typename S::out;
   constexpr int TQ = 64;
   __shared__ __attribute__((aligned(16))) float xs[2][TQ * MAXK];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -2522,7 +2631,7 @@ __global__ void __launch_bounds__(256) core_step_smallk_bf16_kernel(const StepAr
     const int64_t col0 = tile * TQ;
     const int64_t rhs = col0 / a.C;
     const int64_t q0 = col0 - rhs * a.C;
-    uint16_t* dst = reinterpret_cast<uint16_t*>(a.out) + rhs * a.out_stride + (int64_t)r * q0 + 4 * aq;
+    out_t* dst = reinterpret_cast<out_t*>(a.out) + rhs * a.out_stride + (int64_t)r * q0 + 4 * aq;
     const float* X = xs[buf];
     // fully unrolled: a known number of stores per tile, so the wait before
     // the next tile's staging is counted exactly, not a full drain
@@ -2544,10 +2653,14 @@ __global__ void __launch_bounds__(256) core_step_smallk_bf16_kernel(const StepAr
             for (int e = 0; e < 4; ++e) v[e] = fma(Mr[ii][e][k], xv[k], v[e]);
           }
         }
-        uint2 o;
-        o.x = (uint32_t)S::to_out(v[0]) | ((uint32_t)S::to_out(v[1]) << 16);
-        o.y = (uint32_t)S::to_out(v[2]) | ((uint32_t)S::to_out(v[3]) << 16);
-        *reinterpret_cast<uint2*>(dst + (int64_t)r * (q + a.C * i)) = o;
+        if constexpr (sizeof(out_t) == 2) {
+          uint2 o;
+          o.x = (uint32_t)S::to_out(v[0]) | ((uint32_t)S::to_out(v[1]) << 16);
+          o.y = (uint32_t)S::to_out(v[2]) | ((uint32_t)S::to_out(v[3]) << 16);
+          *reinterpret_cast<uint2*>(dst + (int64_t)r * (q + a.C * i)) = o;
+        } else {
+          *reinterpret_cast<v4f*>(dst + (int64_t)r * (q + a.C * i)) = v4f{v[0], v[1], v[2], v[3]};
+        }
       }
     }
   }

@@ -49,8 +49,11 @@ const void* f32_split_kernel(int spt);
 const void* pair_f64_kernel(int f);
 const void* pair_f32_kernel(int f);
 // FP64 vector-ALU kernels and the short-contraction first core (qtt_k_misc.hip;
-// smallk_kernel(3): the BF16 first core with rows in registers)
+// smallk_kernel(3), smallk_kernel(4): the BF16 and FP32 first cores with rows
+// in registers)
 void add_valu_kernels(std::vector<ValuCfg>& v);
+// the FP32 last core on the vector ALUs (core_step_valu32_kernel), id 39
+ValuCfg valu32_last_cfg();
 const void* smallk_kernel(int dt);
 
 }  // namespace qtt

@@ -194,6 +194,8 @@ static KernelCfg* bf16_dma32_cfg() {
 // term against 2^-24), only
 // when pinned with qtt_set_shape.  One instantiation per R_out / 64.
 static const int kF32Split = 38;
+// FP32 last core on the vector ALUs (the FP32 default for R_out <= 16)
+static const int kValu32 = 39;
 static KernelCfg* f32_split_cfg(int spt) {
   static KernelCfg k[4] = {};
   static std::once_flag once;
@@ -240,25 +242,27 @@ static KernelCfg* smallk_cfg(int dt) {
   return &k[dt];
 }
 
-// The BF16 first core with rows in registers (core_step_smallk_bf16_kernel):
-// also configuration 34, 64-column tiles.
-static KernelCfg* smallk_rows_cfg() {
-  static KernelCfg k = [] {
-    KernelCfg c = {};
-    c.dt = 2;
-    c.in_f64 = true;
-    c.vec = true;
-    c.TR = 256;
-    c.TC = 64;
-    c.KC = 8;
-    c.NT = 256;
-    c.id = kSmallK;
-    c.fn = smallk_kernel(3);
-    c.occ = 0;
-    c.kind = -1;
-    return c;
-  }();
-  return &k;
+// The BF16 and FP32 first cores with rows in registers
+// (core_step_smallk_rows_kernel): also configuration 34, 64-column tiles.
+static KernelCfg* smallk_rows_cfg(int dt) {
+  static KernelCfg k[2] = {};
+  static std::once_flag once;
+  std::call_once(once, [] {
+    for (int i = 0; i < 2; ++i) {
+      k[i].dt = i == 0 ? 2 : 1;
+      k[i].in_f64 = true;
+      k[i].vec = true;
+      k[i].TR = 256;
+      k[i].TC = 64;
+      k[i].KC = 8;
+      k[i].NT = 256;
+      k[i].id = kSmallK;
+      k[i].fn = smallk_kernel(i == 0 ? 3 : 4);
+      k[i].occ = 0;
+      k[i].kind = -1;
+    }
+  });
+  return &k[dt == 2 ? 0 : 1];
 }
 
 static int num_cus() {
@@ -331,8 +335,8 @@ static bool tune_log() {
 
 // Untuned defaults, from tuning runs on MI355X at L = 7, r = 32.
 static int heuristic_shape(int R_out, int K_in, int dt) {
-  if (R_out <= 16) return dt == 0 ? 49 : (dt == 2 ? kBf16Last : 2);   // last core (r_d = 1; 49 needs
-                                                 // K_in % 16 == 0, else 47; 35 falls back to 2)
+  if (R_out <= 16) return dt == 0 ? 49 : (dt == 2 ? kBf16Last : kValu32);   // last core (r_d = 1; 49
+                                                 // needs K_in % 16 == 0, else 47; 35 and 39 fall back to 2)
   if (dt == 0 && R_out > 64) {                   // FP64: 4x4x4 matrix instruction
     if (K_in <= 16) return 67;                   // short chunks for the first core
     return R_out <= 192 ? 63 : 75;
@@ -372,18 +376,25 @@ static bool timing_on() {
 // ---------------------------------------------------------------------------
 // launching one core step
 // ---------------------------------------------------------------------------
-// FP64 vector-ALU shape ids are 40..48; anything else is a matrix-core shape.
+// FP64 vector-ALU shape ids are 40..49; anything else is a matrix-core shape.
 static bool is_valu_shape(int id) { return id >= 40 && id < 50; }
+// The FP32 last core on the vector ALUs (core_step_valu32_kernel, id kValu32).
+static ValuCfg* valu32_cfg() {
+  static ValuCfg k = valu32_last_cfg();
+  return &k;
+}
 
 static void record_timing(TimedLaunch& tl, const qtt_matrix_s* A, int k, int dt, int64_t ncols,
                           const Segment* segs, int nseg, int shape);
 
-static qtt_status_t launch_valu(const qtt_matrix_s* A, int k, int64_t nrhs, const Segment* segs, int nseg,
+// dt 0: the FP64 vector-ALU configurations (id 40..49); dt 1: the FP32 last
+// core (kValu32; the caller checks its requirements).
+static qtt_status_t launch_valu(const qtt_matrix_s* A, int k, int dt, int64_t nrhs, const Segment* segs, int nseg,
                                 const Segment* dsegs, const void* in_packed, void* out_packed, double alpha, int id,
                                 hipStream_t st) {
   const CoreDev& c = A->core[k];
   const bool first = (k == 0), last = (k == A->d - 1);
-  ValuCfg* vc = find_valu(id);
+  ValuCfg* vc = (dt == 1) ? valu32_cfg() : find_valu(id);
   // grouped kernels read each lane's inputs as aligned 16-byte vectors
   bool aligned = (c.K_in % 8) == 0 && c.valu != nullptr;
   if (first) {
@@ -392,11 +403,11 @@ static qtt_status_t launch_valu(const qtt_matrix_s* A, int k, int64_t nrhs, cons
   } else {
     aligned = aligned && (reinterpret_cast<uintptr_t>(in_packed) % 16 == 0);
   }
-  if (vc && c.K_in % (vc->G * vc->LG) != 0) vc = find_valu(47);
-  if (!vc || (vc->G == 8 && !aligned)) vc = find_valu(kValuGeneric);
+  if (dt == 0 && vc && c.K_in % (vc->G * vc->LG) != 0) vc = find_valu(47);
+  if (dt == 0 && (!vc || (vc->G == 8 && !aligned))) vc = find_valu(kValuGeneric);
   ValuArgs a;
   memset(&a, 0, sizeof(a));
-  a.M = (vc->G == 8) ? c.valu : c.valu1;
+  a.M = (dt == 1) ? reinterpret_cast<const double*>(c.valu32) : (vc->G == 8) ? c.valu : c.valu1;
   a.in = static_cast<const double*>(in_packed);
   a.out = static_cast<double*>(out_packed);
   a.in_stride = c.C * c.K_in;
@@ -430,7 +441,7 @@ static qtt_status_t launch_valu(const qtt_matrix_s* A, int k, int64_t nrhs, cons
   HIP_TRY(hipLaunchKernel(vc->fn, dim3(grid), dim3(nt), args, 0, st));
   if (timed) {
     HIP_TRY(hipEventRecord(tl.b, st));
-    record_timing(tl, A, k, 0, a.ncols, segs, nseg, vc->id);
+    record_timing(tl, A, k, dt, a.ncols, segs, nseg, vc->id);
   }
   return QTT_OK;
 }
@@ -481,7 +492,7 @@ static qtt_status_t launch_step(const qtt_matrix_s* A, int k, int dt, int64_t nr
     shape = (it != g_tuned.end()) ? it->second : heuristic_shape(c.R_out, c.K_in, dt);
   }
   if (dt == 0 && is_valu_shape(shape))
-    return launch_valu(A, k, nrhs, segs, nseg, dsegs, in_packed, out_packed, alpha, shape, st);
+    return launch_valu(A, k, 0, nrhs, segs, nseg, dsegs, in_packed, out_packed, alpha, shape, st);
   // the resident BF16 kernel serves interior cores that fit it
   const bool resident_ok = dt == 2 && !first && !last && c.R_out <= 256 && c.K_in <= 256 &&
                            c.K_in % 8 == 0 && c.C % 64 == 0 && vec &&
@@ -493,22 +504,29 @@ static qtt_status_t launch_step(const qtt_matrix_s* A, int k, int dt, int64_t nr
   const int64_t m_bytes =
       (int64_t)padded_row_blocks(c.nRB) * c.Ksteps[dt] * 64 * kFragE[dt] * kElemBytes[dt];
   if (shape == kBf16Resident && !resident_ok) shape = heuristic_shape(c.R_out, c.K_in, 1);
-  const bool last_ok = dt == 2 && last && !first && c.R_out <= 16 && c.K_in % 8 == 0 && c.Ksteps[2] <= 8 &&
-                       c.C % 16 == 0 && vec && reinterpret_cast<uintptr_t>(in_packed) % 16 == 0;
-  if (shape == kBf16Last && !last_ok) shape = 2;
   const bool split_ok = dt == 1 && !first && !last && c.fsplit != nullptr && c.fsplit_ks <= 8 &&
                         c.R_out % 64 == 0 && c.R_out <= 256 && c.r_out % 4 == 0 && c.K_in % 8 == 0 &&
                         c.C % 32 == 0 && reinterpret_cast<uintptr_t>(in_packed) % 16 == 0 &&
                         reinterpret_cast<uintptr_t>(out_packed) % 16 == 0;
   if (shape == kF32Split && !split_ok) shape = heuristic_shape(c.R_out, c.K_in, dt);
+  // (after the fallbacks above, which can name it)
+  if (shape == kValu32) {
+    if (dt == 1 && last && !first && c.valu32 != nullptr && c.K_in % 32 == 0 && c.C % 128 == 0 &&
+        reinterpret_cast<uintptr_t>(in_packed) % 16 == 0)
+      return launch_valu(A, k, 1, nrhs, segs, nseg, dsegs, in_packed, out_packed, alpha, shape, st);
+    shape = 2;
+  }
+  const bool last_ok = dt == 2 && last && !first && c.R_out <= 16 && c.K_in % 8 == 0 && c.Ksteps[2] <= 8 &&
+                       c.C % 16 == 0 && vec && reinterpret_cast<uintptr_t>(in_packed) % 16 == 0;
+  if (shape == kBf16Last && !last_ok) shape = 2;
   const int tq = smallk_cfg(dt)->TC;
   const bool smallk_ok = first && !last && vec && c.K_in <= 16 && c.K_in % 2 == 0 && c.R_out <= 256 &&
                          c.r_out % 4 == 0 && c.C % tq == 0 && (c.r_out * tq * kElemBytes[dt]) % 16 == 0 &&
                          reinterpret_cast<uintptr_t>(out_packed) % 16 == 0;
   if (shape == kSmallK && !smallk_ok) shape = (dt == 0) ? 67 : 26;   // first-core matrix-core kernels
-  const bool smallk_rows = shape == kSmallK && dt == 2 && c.K_in <= 8 && c.r_out <= 32 &&
+  const bool smallk_rows = shape == kSmallK && (dt == 2 || dt == 1) && c.K_in <= 8 && c.r_out <= 32 &&
                            c.R_out / c.r_out <= 8 && c.C % 64 == 0;
-  KernelCfg* kc = smallk_rows ? smallk_rows_cfg()
+  KernelCfg* kc = smallk_rows ? smallk_rows_cfg(dt)
                   : (shape == kF32Split) ? f32_split_cfg(c.R_out / 64)
                   : (shape == kSmallK) ? smallk_cfg(dt)
                   : (shape == kBf16Last) ? bf16_last_cfg()
@@ -1102,6 +1120,35 @@ qtt_status_t qtt_matrix_load(int32_t d, const int64_t* ranks, const int64_t* m, 
       }
     }
   }
+  // FP32 vector-ALU copy of the last core (groups of 8), values (float) M_d
+  if ((dtypes & QTT_FP32) && d > 1) {
+    CoreDev& c = A->core[d - 1];
+    const double* G = cores[d - 1];
+    if (c.K_in % 32 == 0) {
+      const int Rpad = valu_padded_rows(c.R_out);
+      const size_t nel = (size_t)c.K_in * Rpad;
+      std::vector<float> h(nel, 0.f);
+      for (int row = 0; row < c.R_out; ++row)
+        for (int kap = 0; kap < c.K_in; ++kap) {
+          const int ak = row % c.r_out, ik = row / c.r_out;
+          const int ap = kap % c.r_in, jk = kap / c.r_in;
+          h[((size_t)(kap / 8) * Rpad + row) * 8 + kap % 8] =
+              (float)G[(((size_t)ap * c.m + ik) * c.n + jk) * c.r_out + ak];
+        }
+      void* dptr = nullptr;
+      if (hipMalloc(&dptr, std::max<size_t>(nel * 4, 256)) != hipSuccess) {
+        qtt_matrix_free(A);
+        return fail(QTT_ERR_OUT_OF_MEMORY, "hipMalloc for the FP32 vector-ALU copy of core %d failed", d - 1);
+      }
+      c.valu32 = static_cast<float*>(dptr);
+      c.Rpad = Rpad;
+      hipError_t er = hipMemcpy(dptr, h.data(), nel * 4, hipMemcpyHostToDevice);
+      if (er != hipSuccess) {
+        qtt_matrix_free(A);
+        return fail(QTT_ERR_DEVICE, "hipMemcpy of core %d failed: %s", d - 1, hipGetErrorString(er));
+      }
+    }
+  }
   // FP64 vector-ALU copies: Mv[(g * Rpad + row) * G + e] = M_k(row, G g + e)
   if (dtypes & QTT_FP64) {
     for (int k = 0; k < d; ++k) {
@@ -1168,6 +1215,7 @@ qtt_status_t qtt_matrix_free(qtt_matrix_t A) {
     if (c.valu1) (void)hipFree(c.valu1);
     if (c.g64) (void)hipFree(c.g64);
     if (c.fsplit) (void)hipFree(c.fsplit);
+    if (c.valu32) (void)hipFree(c.valu32);
   }
   delete A;
   return QTT_OK;
@@ -1383,6 +1431,7 @@ qtt_status_t qtt_autotune(qtt_matrix_t A, qtt_dtype_t compute, int64_t nrhs, con
     }
     if (k == 0 && A->d > 1) ids.push_back(kSmallK);
     if (dt == 2 && k == A->d - 1 && k > 0) ids.push_back(kBf16Last);
+    if (dt == 1 && k == A->d - 1 && k > 0) ids.push_back(kValu32);
     if (dt == 0)
       for (auto& vc : valu_registry())
         if (vc.G == 1 || c.K_in % vc.G == 0) ids.push_back(vc.id);
@@ -1453,6 +1502,7 @@ qtt_status_t qtt_list_shapes(qtt_dtype_t compute, int32_t* ids, int32_t cap, int
     v.push_back(kBf16Dma32);
     v.push_back(kBf16Last);
   }
+  if (dt == 1) v.push_back(kValu32);
   if (dt == 0)
     for (auto& vc : valu_registry()) v.push_back(vc.id);
   *count = (int32_t)v.size();

@@ -373,6 +373,13 @@ def test_fp32_split_products(Q):
         Q.qtt_timing_reset()
         assert ran == n_split, (ranks, ran)
         check_reduced(Y.cpu().numpy(), ref, cores, X, "fp32s", f"split {ranks} K={K}")
+        # pinned on the first and last cores too, which it cannot serve: the
+        # defaults run there
+        Q.qtt_set_shape(A, "fp32", 0, Q.F32_SPLIT)
+        Q.qtt_set_shape(A, "fp32", L - 1, Q.F32_SPLIT)
+        Y = Q.qtt_apply(A, "fp32", Xd)
+        torch.cuda.synchronize()
+        check_reduced(Y.cpu().numpy(), ref, cores, X, "fp32s", f"split, all cores pinned, {ranks} K={K}")
         # unpinned: the default FP32 kernels again, at FP32's own bound
         Q.qtt_use_split_products(A, False)
         Y = Q.qtt_apply(A, "fp32", Xd)
