@@ -257,7 +257,8 @@ def main():
                                   + ", the one carrying most of the inverse apply's flops"),
                        "launches": lo["launches"], "avg_launch_ms": round(lo["ms"] / lo["launches"], 4)}
 
-    fg = None if args.no_fgmres else fgmres_run(Q, torch, A, inv_h[head][0], inv_h[head][1], F, K, N, rtol, args)
+    fg = None if args.no_fgmres else fgmres_run(Q, torch, A, inv_h[head][0], inv_h[head][1], F, K, N, rtol, args,
+                                                label=head)
 
     nti = None if args.no_nti else nti_run(Q, torch, Ac, F, K, N)
     cmv = None if args.no_compressed else compressed_run(Q, torch, Ac)
@@ -382,7 +383,7 @@ def nti_run(Q, torch, Ac, F, K, N, reps=10):
     return out
 
 
-def fgmres_run(Q, torch, A, Ai, inv, F, K, N, rtol, args, max_iter=12):
+def fgmres_run(Q, torch, A, Ai, inv, F, K, N, rtol, args, max_iter=12, label=None):
     """The same solve by flexible GMRES (the compressed inverse as right
     preconditioner, section 5.3's outer solver): RHS/s, steps, and the true
     relative residual recomputed by an FP64 apply outside the timed region."""
@@ -403,7 +404,7 @@ def fgmres_run(Q, torch, A, Ai, inv, F, K, N, rtol, args, max_iter=12):
     del ws
     AS = Q.qtt_apply(A, "fp64", Sig)
     true = ((F - AS).norm(dim=0) / F.norm(dim=0)).max().item()
-    return {"inverse_dtype": inv, "rhs_per_s": round(K * args.steps / el, 3),
+    return {"inverse_dtype": label or inv, "rhs_per_s": round(K * args.steps / el, 3),
             "ms_per_step": round(1e3 * el / args.steps, 3),
             "p50_ms": round(percentile(lat, 50), 3), "p99_ms": round(percentile(lat, 99), 3),
             "steps": max(c[0] for c in info), "max_rel_residual_estimate": max(c[1] for c in info),
