@@ -388,6 +388,33 @@ def test_fp32_split_products(Q):
         A.free()
 
 
+def test_fp32_split_batched_uneven(Q):
+    """The split-product configuration on uneven blocks (several segments for
+    the first and last cores, one or several workspace waves), each block
+    against the oracle within the split's bound, and a block's bits the same
+    alone and in the batch."""
+    ranks = [1, 24, 32, 32, 24, 1]
+    cores = I.gaussian_qtt(ranks, [8] * 5, seed=51)
+    widths = [1, 4, 2, 0, 7, 1, 3]
+    A = Q.qtt_matrix_load(cores, dtypes=("fp32",))
+    Q.qtt_use_split_products(A)
+    Xs_h = [I.rhs(8 ** 5, w, seed=60 + b) for b, w in enumerate(widths)]
+    Xs = [Q.to_block(x) if x.shape[1] else Q.empty_block(8 ** 5, 0) for x in Xs_h]
+    total = sum(widths)
+    for ws_n in (total, 3):
+        ws = Q.workspace(Q.qtt_workspace_bytes(A, "fp32", ws_n))
+        Ys = Q.qtt_apply_batched(A, "fp32", Xs, ws=ws)
+        torch.cuda.synchronize()
+        for b, (x, y) in enumerate(zip(Xs_h, Ys)):
+            if x.shape[1]:
+                check_reduced(y.cpu().numpy(), O.qtt_apply_alg2(cores, x), cores, x, "fp32s",
+                              f"split batched block {b} (workspace {ws_n} vectors)")
+    alone = Q.qtt_apply(A, "fp32", Xs[4])
+    torch.cuda.synchronize()
+    assert np.array_equal(alone.cpu().numpy(), Ys[4].cpu().numpy())
+    A.free()
+
+
 @pytest.mark.slow
 def test_refine_L7_split_fp32_inverse(Q):
     """The reported solve in the benchmark's launch configuration: L=7, K=8,
