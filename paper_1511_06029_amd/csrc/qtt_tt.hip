@@ -20,8 +20,11 @@
 //      core k <- diag(1/s) U_r^T B, core k-1 <- core k-1 U_r diag(s).
 // When a kept rank comes close to its sketch rank (so the sketch may have
 // missed part of the range) the sketch rank is doubled, up to max_rank.
-// Every product is an FP64 GEMM (gemm_kernel); the small factorizations run
-// one per workgroup (qr_thin_kernel, jacobi_svd_kernel).  The stream is
+// Every product is an FP64 GEMM (gemm_kernel); the QR factorizations are
+// tall-skinny Householder QRs over row blocks held in LDS (qr_block_lds_kernel,
+// qr_combine_kernel; one workgroup through global memory, qr_thin_kernel,
+// where the blocks do not fit), the SVDs one per workgroup
+// (jacobi_svd_kernel).  The stream is
 // synchronised once per core of stage 2 (the kept rank is chosen on the host).
 #include <hip/hip_runtime.h>
 
@@ -171,28 +174,77 @@ qtt_status_t gaussian(double* out, int64_t count, uint64_t seed, uint32_t stream
   return QTT_OK;
 }
 
-// Thin Q of the m x n matrix Z (overwritten), m >= n.
-qtt_status_t qr_thin(double* Z, int64_t m, int64_t n, double* Q, hipStream_t st) {
-  if (m < n || n > 256) return fail(QTT_ERR_SHAPE, "QR of %lld x %lld", (long long)m, (long long)n);
-  QrArgs a;
-  memset(&a, 0, sizeof(a));
-  a.A = Z;
-  a.Q = Q;
-  a.m = m;
-  a.n = n;
-  a.lda = n;
-  a.ldq = n;
-  void* args[] = {&a};
-  HIP_TRY(hipLaunchKernel(reinterpret_cast<const void*>(&qr_thin_kernel), dim3(1), dim3(256), args, 0, st));
-  return QTT_OK;
-}
-
 template <class Args>
 qtt_status_t launch1d(const void* fn, Args a, int64_t work, hipStream_t st) {
   void* args[] = {&a};
   HIP_TRY(hipLaunchKernel(fn, dim3(grid_for(work)), dim3(256), args, 0, st));
   return QTT_OK;
 }
+
+// Thin QR of the m x n matrix Z (overwritten, row-major), m >= n: Q (m x n)
+// and, when R is not null, R (n x n).  Tall-skinny Householder QR when the
+// blocks fit in LDS (n <= 64, m a multiple of 64): row blocks of B rows
+// (a multiple of 64, so every block has at least n rows) are factored one
+// per workgroup, their stacked R_b factored by one more workgroup, and
+// Q = blockdiag(Q_b) Q2, R = R2.  Otherwise one workgroup factors Z through
+// global memory (qr_thin_kernel).
+static const size_t kQrLdsBytes = 150 * 1024;
+static int64_t qr_block_rows(int64_t n) { return (int64_t)(kQrLdsBytes / (8 * (size_t)(n + 1))) / 64 * 64; }
+
+static qtt_status_t qr_tall(double* Z, int64_t m, int64_t n, double* Q, double* R, hipStream_t st) {
+  if (m < n || n > 256 || n < 1) return fail(QTT_ERR_SHAPE, "QR of %lld x %lld", (long long)m, (long long)n);
+  const int64_t B = qr_block_rows(n);
+  const int64_t nb = (m + B - 1) / B;
+  const bool lds = n <= 64 && m % 64 == 0 && B >= 64 && B >= n &&
+                   (nb == 1 || (size_t)(nb * n) * (n + 1) * 8 <= kQrLdsBytes);
+  if (!lds) {
+    QrArgs a;
+    memset(&a, 0, sizeof(a));
+    a.A = Z;
+    a.Q = Q;
+    a.R = R;
+    a.m = m;
+    a.n = n;
+    a.lda = n;
+    a.ldq = n;
+    void* args[] = {&a};
+    HIP_TRY(hipLaunchKernel(reinterpret_cast<const void*>(&qr_thin_kernel), dim3(1), dim3(256), args, 0, st));
+    return QTT_OK;
+  }
+  static bool attr = false;
+  if (!attr) {
+    HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&qr_block_lds_kernel),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kQrLdsBytes));
+    attr = true;
+  }
+  const void* fn = reinterpret_cast<const void*>(&qr_block_lds_kernel);
+  if (nb == 1) {
+    QrBlkArgs a{Z, Q, R, m, (int32_t)n, (int32_t)m};
+    void* args[] = {&a};
+    HIP_TRY(hipLaunchKernel(fn, dim3(1), dim3(256), args, (size_t)m * (n + 1) * 8, st));
+    return QTT_OK;
+  }
+  DBuf Q1, Rs, Q2;
+  QTT_CHECK(dalloc(Q1, m * n));
+  QTT_CHECK(dalloc(Rs, nb * n * n));
+  QTT_CHECK(dalloc(Q2, nb * n * n));
+  QrBlkArgs a1{Z, Q1.p, Rs.p, m, (int32_t)n, (int32_t)B};
+  void* args1[] = {&a1};
+  HIP_TRY(hipLaunchKernel(fn, dim3((unsigned)nb), dim3(256), args1, (size_t)B * (n + 1) * 8, st));
+  QrBlkArgs a2{Rs.p, Q2.p, R, nb * n, (int32_t)n, (int32_t)(nb * n)};
+  void* args2[] = {&a2};
+  HIP_TRY(hipLaunchKernel(fn, dim3(1), dim3(256), args2, (size_t)(nb * n) * (n + 1) * 8, st));
+  QrCombineArgs c{Q1.p, Q2.p, Q, m, (int32_t)n, (int32_t)B};
+  QTT_CHECK(launch1d(reinterpret_cast<const void*>(&qr_combine_kernel), c, m * n, st));
+  HIP_TRY(hipStreamSynchronize(st));       // the temporaries are freed on return
+  return QTT_OK;
+}
+
+// Thin Q of the m x n matrix Z (overwritten), m >= n.
+qtt_status_t qr_thin(double* Z, int64_t m, int64_t n, double* Q, hipStream_t st) {
+  return qr_tall(Z, m, n, Q, nullptr, st);
+}
+
 
 
 // Smallest r >= 1 whose discarded singular values s_r, s_{r+1}, ... (sorted
@@ -221,17 +273,7 @@ qtt_status_t left_svd(const double* B, int64_t lr, int64_t cols, DBuf& U, DBuf& 
     QTT_CHECK(launch1d(reinterpret_cast<const void*>(&transpose_kernel), ta, cols * lr, st));
     QTT_CHECK(dalloc(Qb, cols * lr));
     QTT_CHECK(dalloc(R, lr * lr));
-    QrArgs qa;
-    memset(&qa, 0, sizeof(qa));
-    qa.A = Bt.p;
-    qa.Q = Qb.p;
-    qa.R = R.p;
-    qa.m = cols;
-    qa.n = lr;
-    qa.lda = lr;
-    qa.ldq = lr;
-    void* args[] = {&qa};
-    HIP_TRY(hipLaunchKernel(reinterpret_cast<const void*>(&qr_thin_kernel), dim3(1), dim3(256), args, 0, st));
+    QTT_CHECK(qr_tall(Bt.p, cols, lr, Qb.p, R.p, st));
     QTT_CHECK(dalloc(Mb, lr * lr));
     TransposeArgs tr{R.p, Mb.p, 1, lr, lr};          // M = R^T
     QTT_CHECK(launch1d(reinterpret_cast<const void*>(&transpose_kernel), tr, lr * lr, st));

@@ -10,6 +10,9 @@
 //                        Shaw, SC'11) with the Box-Muller transform;
 //   * qr_thin_kernel     Householder QR of one m x n matrix (m >= n) per
 //                        workgroup, giving the thin Q;
+//   * qr_block_lds_kernel, qr_combine_kernel  the same QR as a tall-skinny
+//                        QR: row blocks factored in LDS, one per workgroup,
+//                        then their stacked R factors, Q recombined;
 //   * jacobi_svd_kernel  singular values and left singular vectors of one
 //                        m x c matrix (c <= m <= 128) per workgroup,
 //                        one-sided Jacobi in round-robin order, in LDS;
@@ -209,6 +212,149 @@ __device__ inline double block_sum256(double v, double* red) {
   const double s = red[0] + red[1] + red[2] + red[3];
   __syncthreads();
   return s;
+}
+
+// ---------------------------------------------------------------------------
+// Householder QR of one row block per workgroup with the block in LDS
+// (rows x (n + 1) doubles, n <= 64): the same reflectors as qr_thin_kernel
+// (x0 - alpha, alpha = -sign(x0) ||x||), R_b (n x n) written out, then the
+// thin Q_b formed in place by accumulating the reflectors from the last to
+// the first (column j of Q is H_0 .. H_j e_j).  Block b holds rows
+// [b B, min(m, (b + 1) B)); every block has at least n rows (host).  Used
+// for both levels of the tall-skinny QR: the blocks of Z, then the stacked
+// R_b (one block).
+// ---------------------------------------------------------------------------
+struct QrBlkArgs {
+  const double* A;     // m x n, row-major (leading dimension n)
+  double* Q;           // m x n, the same rows
+  double* R;           // (blocks) x n x n, block b at b n n; may be null
+  int64_t m;
+  int32_t n, B;
+};
+
+__global__ void __launch_bounds__(256) qr_block_lds_kernel(const QrBlkArgs a) {
+  extern __shared__ double As[];
+  __shared__ double red[4];
+  __shared__ double beta_s[64];
+  __shared__ double alpha_s[64];
+  __shared__ double part[256];
+  __shared__ double w[64];
+  const int tid = threadIdx.x;
+  const int n = a.n, ld = n + 1;
+  const int64_t r0 = (int64_t)blockIdx.x * a.B;
+  const int mb = (int)((a.m - r0 < a.B) ? a.m - r0 : a.B);
+  for (int e = tid; e < mb * n; e += 256) {
+    const int i = e / n, c = e - (e / n) * n;
+    As[i * ld + c] = a.A[(r0 + i) * n + c];
+  }
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    double ss = 0.0;
+    for (int i = j + tid; i < mb; i += 256) ss += As[i * ld + j] * As[i * ld + j];
+    const double s = block_sum256(ss, red);
+    const double x0 = As[j * ld + j];
+    const double nrm = sqrt(s);
+    const double alpha = (x0 >= 0.0) ? -nrm : nrm;
+    const double v0 = x0 - alpha;
+    const double vn2 = s - x0 * x0 + v0 * v0;
+    const double beta = (vn2 > 0.0) ? 2.0 / vn2 : 0.0;
+    __syncthreads();
+    if (tid == 0) {
+      As[j * ld + j] = v0;
+      beta_s[j] = beta;
+      alpha_s[j] = (vn2 > 0.0) ? alpha : x0;
+    }
+    __syncthreads();
+    const int nc = n - 1 - j;
+    if (nc > 0 && beta != 0.0) {
+      // w_c = v^T A[j:, c], row groups of the 256 threads per column
+      const int Gc = 256 / nc, g = tid / nc, cl = tid - (tid / nc) * nc;
+      double acc = 0.0;
+      if (g < Gc)
+        for (int i = j + g; i < mb; i += Gc) acc += As[i * ld + j] * As[i * ld + j + 1 + cl];
+      part[tid] = acc;
+      __syncthreads();
+      if (tid < nc) {
+        double t = 0.0;
+        for (int q = 0; q < Gc; ++q) t += part[q * nc + tid];
+        w[tid] = t;
+      }
+      __syncthreads();
+      for (int e = tid; e < (mb - j) * nc; e += 256) {
+        const int i = j + e / nc, c2 = e - (e / nc) * nc;
+        As[i * ld + j + 1 + c2] -= beta * As[i * ld + j] * w[c2];
+      }
+      __syncthreads();
+    }
+  }
+  if (a.R) {
+    double* R = a.R + (int64_t)blockIdx.x * n * n;
+    for (int e = tid; e < n * n; e += 256) {
+      const int i = e / n, c = e - (e / n) * n;
+      R[e] = (c > i) ? As[i * ld + c] : (c == i ? alpha_s[i] : 0.0);
+    }
+  }
+  __syncthreads();
+  // Q in place, from the last reflector to the first: the columns c > j
+  // already hold H_{j+1} .. H_{n-1} e_c (zero in rows <= j); H_j is applied
+  // to them with v still in column j, which then becomes H_j e_j
+  for (int j = n - 1; j >= 0; --j) {
+    const double beta = beta_s[j];
+    const double v0 = As[j * ld + j];
+    const int nc = n - 1 - j;
+    if (nc > 0 && beta != 0.0) {
+      const int Gc = 256 / nc, g = tid / nc, cl = tid - (tid / nc) * nc;
+      double acc = 0.0;
+      if (g < Gc)
+        for (int i = j + g; i < mb; i += Gc) acc += (i == j ? v0 : As[i * ld + j]) * As[i * ld + j + 1 + cl];
+      part[tid] = acc;
+      __syncthreads();
+      if (tid < nc) {
+        double t = 0.0;
+        for (int q = 0; q < Gc; ++q) t += part[q * nc + tid];
+        w[tid] = t;
+      }
+      __syncthreads();
+      for (int e = tid; e < (mb - j) * nc; e += 256) {
+        const int i = j + e / nc, c2 = e - (e / nc) * nc;
+        As[i * ld + j + 1 + c2] -= beta * (i == j ? v0 : As[i * ld + j]) * w[c2];
+      }
+      __syncthreads();
+    }
+    for (int i = tid; i < mb; i += 256) {
+      const double vi = As[i * ld + j];
+      As[i * ld + j] = (i < j) ? 0.0 : (i == j ? 1.0 - beta * v0 * v0 : -beta * v0 * vi);
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < mb * n; e += 256) {
+    const int i = e / n, c = e - (e / n) * n;
+    a.Q[(r0 + i) * n + c] = As[i * ld + c];
+  }
+}
+
+// Q = blockdiag(Q_1, .., Q_nb) Q2 for the tall-skinny QR: row i of block
+// b = i div B times rows b n .. b n + n - 1 of Q2.
+struct QrCombineArgs {
+  const double* Q1;    // m x n
+  const double* Q2;    // nb n x n
+  double* Q;           // m x n
+  int64_t m;
+  int32_t n, B;
+};
+
+__global__ void __launch_bounds__(256) qr_combine_kernel(const QrCombineArgs a) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= a.m * a.n) return;
+  const int n = a.n;
+  const int64_t i = e / n;
+  const int c = (int)(e - i * n);
+  const int64_t b = i / a.B;
+  const double* q1 = a.Q1 + i * n;
+  const double* q2 = a.Q2 + b * n * n + c;
+  double t = 0.0;
+  for (int k = 0; k < n; ++k) t += q1[k] * q2[(int64_t)k * n];
+  a.Q[e] = t;
 }
 
 __global__ void __launch_bounds__(256) qr_thin_kernel(const QrArgs a) {
