@@ -290,14 +290,21 @@ def test_error_paths(Q):
     Ai.free()
 
 
-@pytest.mark.parametrize("inv", ["fp64", "bf16"])
+@pytest.mark.parametrize("inv", ["fp64", "bf16", "fp32s"])
 def test_nonfinite_rhs_reported(Q, inv):
     """A NaN or an infinity in one column of F makes its residual norm
     non-finite: qtt_solve and qtt_solve_fgmres return QTT_ERR_NONFINITE (6)
-    instead of iterating, and the finite columns are still solved."""
+    instead of iterating, and the finite columns are still solved.  fp32s:
+    the FP32 inverse with split-product cores (core 2 here; an infinity
+    splits into a NaN low part, still non-finite)."""
     Ac, Aic = I.perturbed_identity_pair([1, 6, 8, 6, 1], [8] * 4, seed=95)
     A = Q.qtt_matrix_load(Ac, dtypes=("fp64",))
-    Ai = Q.qtt_matrix_load(Aic, dtypes=("fp64", "bf16"))
+    if inv == "fp32s":
+        Ai = Q.qtt_matrix_load(Aic, dtypes=("fp32",))
+        Q.qtt_use_split_products(Ai)
+        inv = "fp32"
+    else:
+        Ai = Q.qtt_matrix_load(Aic, dtypes=("fp64", "bf16"))
     for bad in (np.nan, np.inf):
         F = I.rhs(4096, 3, seed=96)
         F[17, 1] = bad
