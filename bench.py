@@ -110,7 +110,7 @@ def main():
     variants = [v.strip() for v in args.variants.split(",") if v.strip()]
 
     A = Q.qtt_matrix_load(Ac, dtypes=("fp64",))
-    inv_dtypes = tuple(sorted({DT(v) for v in variants} | {"fp64"}))
+    inv_dtypes = tuple(sorted({DT(v) for v in variants} | {"fp64"} | ({"bf16"} if "sched" in variants else set())))
     Ai0 = Q.qtt_matrix_load(Aic, dtypes=inv_dtypes)
     F = Q.to_block(F_h)
     # setup (untimed): the compressed inverse at the operator's ranks (<= 32),
@@ -133,12 +133,15 @@ def main():
     # handle of the same inverse with the split-product configuration pinned on
     # its interior cores
     inv_h = {v: (Ai, v) for v in variants + ["fp64"]}
-    if "fp32s" in variants:
+    if "fp32s" in variants or "sched" in variants:
         Ais = Q.qtt_matrix_load(Aic, dtypes=("fp32",))
         Q.qtt_use_split_products(Ais)
         inv_h["fp32s"] = (Ais, "fp32")
+        inv_h["sched"] = (Ais, "fp32")     # its later passes; the first applies Ai's BF16 copy
     Sig = Q.empty_block(N, K)
     ws_bytes = max(Q.qtt_solve_workspace_bytes(A, inv_h[v][0], inv_h[v][1], K) for v in variants)
+    if "sched" in variants:
+        ws_bytes = max(ws_bytes, Q.qtt_solve_workspace_bytes(A, Ai, "bf16", K))
     ws = Q.workspace(ws_bytes)
     stream = torch.cuda.current_stream()
 
@@ -149,16 +152,25 @@ def main():
                               *[Q.qtt_workspace_bytes(Ai, DT(v), K) for v in variants]))
         Q.qtt_autotune(A, "fp64", F, Yt, aws)
         for v in variants:
-            if v != "fp32s":          # pinned configuration: not tuned
+            if v not in ("fp32s", "sched"):          # pinned configuration: not tuned
                 Q.qtt_autotune(Ai, v, F, Yt, aws)
         del Yt, aws
         torch.cuda.synchronize()
 
+    def solver(v):
+        """One refined solve of variant v (sched: the inverse's BF16 copy in the
+        first pass, the split-product FP32 copy after it)."""
+        Ah, dv = inv_h[v]
+        if v == "sched":
+            return lambda: Q.qtt_solve_schedule(A, Ai, "bf16", 1, Ah, dv, F, Sig, rtol=rtol, ws=ws, stream=stream)
+        return lambda: Q.qtt_solve(A, Ah, dv, F, Sig, rtol=rtol, ws=ws, stream=stream)
+
     results = {}
     for v in variants:
         Ah, dv = inv_h[v]
+        solve = solver(v)
         for _ in range(args.warmup):
-            Q.qtt_solve(A, Ah, dv, F, Sig, rtol=rtol, ws=ws, stream=stream)
+            solve()
         torch.cuda.synchronize()
         # the timed solves replay each sweep from its captured graph (one
         # hipGraphLaunch per sweep); no per-launch events in this region
@@ -168,7 +180,7 @@ def main():
         t0 = time.perf_counter()
         for _ in range(args.steps):
             s0 = time.perf_counter()
-            _, info, _ = Q.qtt_solve(A, Ah, dv, F, Sig, rtol=rtol, ws=ws, stream=stream)
+            _, info, _ = solve()
             lat.append((time.perf_counter() - s0) * 1e3)
             infos.append(info)
         torch.cuda.synchronize()
@@ -180,7 +192,7 @@ def main():
             Q.qtt_timing_reset()
             Q.qtt_timing_enable(True)
             for _ in range(max(2, min(args.steps, 5))):
-                Q.qtt_solve(A, Ah, dv, F, Sig, rtol=rtol, ws=ws, stream=stream)
+                solve()
             torch.cuda.synchronize()
             Q.qtt_timing_enable(False)
             kt = {(dt, pos): Q.qtt_timing_read(dt, pos) for dt in ("fp64", dv) for pos in (0, 1, 2)}
@@ -258,7 +270,7 @@ def main():
                        "launches": lo["launches"], "avg_launch_ms": round(lo["ms"] / lo["launches"], 4)}
 
     fg = None if args.no_fgmres else fgmres_run(Q, torch, A, inv_h[head][0], inv_h[head][1], F, K, N, rtol, args,
-                                                label=head)
+                                                label="fp32s" if head == "sched" else head)
 
     nti = None if args.no_nti else nti_run(Q, torch, Ac, F, K, N)
     cmv = None if args.no_compressed else compressed_run(Q, torch, Ac)
@@ -414,6 +426,8 @@ def fgmres_run(Q, torch, A, Ai, inv, F, K, N, rtol, args, max_iter=12, label=Non
 INV_ARITH = {
     "fp32s": "FP32 cores and intermediates; each FP32 product formed from split BF16 operands "
              "(hi + lo, three BF16 matrix instructions), FP32 accumulation",
+    "sched": "first pass: the inverse's BF16 copy (BF16 cores and intermediates, FP32 accumulation); "
+             "later passes: its FP32 copy with split-BF16 products (as fp32s)",
     "fp32": "FP32 cores and intermediates, FP32 matrix instructions",
     "bf16": "BF16 cores and intermediates, FP32 accumulation",
     "fp64": "FP64 throughout",
@@ -421,8 +435,9 @@ INV_ARITH = {
 
 
 def DT(variant):
-    """Compute dtype of a solve variant: fp32s is FP32 with split-operand products."""
-    return "fp32" if variant == "fp32s" else variant
+    """Compute dtype of a solve variant's main inverse: fp32s (and sched after
+    its first pass) is FP32 with split-operand products."""
+    return "fp32" if variant in ("fp32s", "sched") else variant
 
 
 def measured_traffic(dtype, shape):

@@ -232,6 +232,23 @@ qtt_status_t qtt_solve(qtt_matrix_t A, qtt_matrix_t Ainv, qtt_dtype_t inv_comput
                        double rtol, int32_t max_iter, void* ws, size_t ws_bytes,
                        void* stream, qtt_solve_col_t* info);
 
+/* qtt_solve with a schedule of inverse applies: passes 1 .. first_passes
+ * apply Ainv_first in first_compute, the later passes Ainv in inv_compute
+ * (the refinement of section 5 with the compressed inverse applied at two
+ * precisions: each pass contracts the error by that pass's apply, so a
+ * cheaper first pass costs one factor of its own contraction).  The residual,
+ * the stopping rule, the column handling and the return values are those of
+ * qtt_solve; first_passes = 0 is qtt_solve with Ainv.  Ainv_first and Ainv
+ * may be the same handle (two device copies) or two handles of the same
+ * matrix.  The workspace must hold what qtt_solve_workspace_bytes returns for
+ * either inverse (the larger of the two).  QTT_ERR_INVALID_ARG for
+ * first_passes < 0. */
+qtt_status_t qtt_solve_schedule(qtt_matrix_t A, qtt_matrix_t Ainv_first, qtt_dtype_t first_compute,
+                                int32_t first_passes, qtt_matrix_t Ainv, qtt_dtype_t inv_compute,
+                                int64_t nrhs, const double* F, int64_t ldf, double* Sigma, int64_t lds,
+                                double rtol, int32_t max_iter, void* ws, size_t ws_bytes,
+                                void* stream, qtt_solve_col_t* info);
+
 /* Device bytes of workspace for qtt_solve_fgmres: max_iter + 1 Krylov blocks
  * V and, with a preconditioner, max_iter preconditioned blocks Z (each
  * N x nrhs FP64), small coefficient buffers, and the apply workspace.

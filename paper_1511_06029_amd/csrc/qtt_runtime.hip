@@ -1595,19 +1595,27 @@ static qtt_status_t column_norms(const std::vector<const double*>& cols, const s
   return QTT_OK;
 }
 
-qtt_status_t qtt_solve(qtt_matrix_t A, qtt_matrix_t Ainv, qtt_dtype_t inv_compute, int64_t nrhs,
-                       const double* F, int64_t ldf, double* Sigma, int64_t lds, double rtol,
-                       int32_t max_iter, void* ws, size_t ws_bytes, void* stream, qtt_solve_col_t* info) {
-  if (!valid_handle(A) || !valid_handle(Ainv)) return fail(QTT_ERR_INVALID_ARG, "null handle");
-  int dti, dta;
+// The refined solve; the first `first_passes` passes apply Ainv1 in its
+// compute dtype (Ainv1 == Ainv and first_passes == 0 for qtt_solve).
+static qtt_status_t solve_impl(qtt_matrix_t A, qtt_matrix_t Ainv1, qtt_dtype_t compute1, int32_t first_passes,
+                               qtt_matrix_t Ainv, qtt_dtype_t inv_compute, int64_t nrhs,
+                               const double* F, int64_t ldf, double* Sigma, int64_t lds, double rtol,
+                               int32_t max_iter, void* ws, size_t ws_bytes, void* stream, qtt_solve_col_t* info) {
+  if (!valid_handle(A) || !valid_handle(Ainv) || !valid_handle(Ainv1)) return fail(QTT_ERR_INVALID_ARG, "null handle");
+  if (first_passes < 0) return fail(QTT_ERR_INVALID_ARG, "first_passes < 0");
+  int dti, dta, dt1;
   qtt_status_t s = check_dtype(Ainv, inv_compute, &dti);
+  if (s != QTT_OK) return s;
+  s = check_dtype(Ainv1, compute1, &dt1);
   if (s != QTT_OK) return s;
   s = check_dtype(A, QTT_FP64, &dta);
   if (s != QTT_OK) return s;
-  if (A->d != Ainv->d) return fail(QTT_ERR_SHAPE, "A and Ainv have different core counts");
-  for (int k = 0; k < A->d; ++k)
-    if (A->m[k] != A->n[k] || Ainv->m[k] != A->m[k] || Ainv->n[k] != A->n[k])
-      return fail(QTT_ERR_SHAPE, "solve needs square, identical modes (core %d)", k);
+  for (qtt_matrix_t Ai : {Ainv, Ainv1}) {
+    if (A->d != Ai->d) return fail(QTT_ERR_SHAPE, "A and Ainv have different core counts");
+    for (int k = 0; k < A->d; ++k)
+      if (A->m[k] != A->n[k] || Ai->m[k] != A->m[k] || Ai->n[k] != A->n[k])
+        return fail(QTT_ERR_SHAPE, "solve needs square, identical modes (core %d)", k);
+  }
   if (nrhs < 0 || max_iter < 1 || !(rtol >= 0)) return fail(QTT_ERR_INVALID_ARG, "bad nrhs, max_iter or rtol");
   if (nrhs == 0) return QTT_OK;
   if (!F || !Sigma || !ws) return fail(QTT_ERR_INVALID_ARG, "null F, Sigma or workspace");
@@ -1621,6 +1629,10 @@ qtt_status_t qtt_solve(qtt_matrix_t A, qtt_matrix_t Ainv, qtt_dtype_t inv_comput
   qtt_workspace_bytes(A, QTT_FP64, 1, &need1);
   qtt_workspace_bytes(Ainv, inv_compute, 1, &tmp);
   need1 = std::max(need1, tmp);
+  if (first_passes > 0) {
+    qtt_workspace_bytes(Ainv1, compute1, 1, &tmp);
+    need1 = std::max(need1, tmp);
+  }
   if (ws_bytes < extra + need1)
     return fail(QTT_ERR_WORKSPACE, "solve workspace %zu < minimum %zu", ws_bytes, extra + need1);
   if (overlaps(ws, ws_bytes, F, fb) || overlaps(ws, ws_bytes, Sigma, sb))
@@ -1675,7 +1687,8 @@ qtt_status_t qtt_solve(qtt_matrix_t A, qtt_matrix_t Ainv, qtt_dtype_t inv_comput
       // r = F - A sigma, residual fused into A's last core
       ba.push_back({Sigma + r.first * lds, R + r.first * N, F + r.first * ldf, lds, N, ldf, r.second});
     }
-    s = run_blocks(Ainv, dti, bi, aws, aws_bytes, 1.0, st);
+    s = (it <= first_passes) ? run_blocks(Ainv1, dt1, bi, aws, aws_bytes, 1.0, st)
+                             : run_blocks(Ainv, dti, bi, aws, aws_bytes, 1.0, st);
     if (s != QTT_OK) return s;
     s = run_blocks(A, dta, ba, aws, aws_bytes, -1.0, st);
     if (s != QTT_OK) return s;
@@ -1704,6 +1717,21 @@ qtt_status_t qtt_solve(qtt_matrix_t A, qtt_matrix_t Ainv, qtt_dtype_t inv_comput
     return fail(QTT_ERR_NONFINITE, "column %lld: F or its residual is not finite", (long long)first_bad);
   if (n_active > 0) return fail(QTT_ERR_NOT_CONVERGED, "%lld columns above rtol after %d passes", (long long)n_active, max_iter);
   return QTT_OK;
+}
+
+qtt_status_t qtt_solve(qtt_matrix_t A, qtt_matrix_t Ainv, qtt_dtype_t inv_compute, int64_t nrhs,
+                       const double* F, int64_t ldf, double* Sigma, int64_t lds, double rtol,
+                       int32_t max_iter, void* ws, size_t ws_bytes, void* stream, qtt_solve_col_t* info) {
+  return solve_impl(A, Ainv, inv_compute, 0, Ainv, inv_compute, nrhs, F, ldf, Sigma, lds, rtol, max_iter, ws,
+                    ws_bytes, stream, info);
+}
+
+qtt_status_t qtt_solve_schedule(qtt_matrix_t A, qtt_matrix_t Ainv_first, qtt_dtype_t first_compute,
+                                int32_t first_passes, qtt_matrix_t Ainv, qtt_dtype_t inv_compute, int64_t nrhs,
+                                const double* F, int64_t ldf, double* Sigma, int64_t lds, double rtol,
+                                int32_t max_iter, void* ws, size_t ws_bytes, void* stream, qtt_solve_col_t* info) {
+  return solve_impl(A, Ainv_first, first_compute, first_passes, Ainv, inv_compute, nrhs, F, ldf, Sigma, lds, rtol,
+                    max_iter, ws, ws_bytes, stream, info);
 }
 
 // --------------------------------------------------------------------------- flexible GMRES

@@ -68,6 +68,8 @@ def _load():
         "qtt_autotune": [P, I32, I64, P, I64, P, I64, P, SZ, P],
         "qtt_solve_workspace_bytes": [P, P, I32, I64, ctypes.POINTER(SZ)],
         "qtt_solve": [P, P, I32, I64, P, I64, P, I64, D, I32, P, SZ, P, ctypes.POINTER(_SolveCol)],
+        "qtt_solve_schedule": [P, P, I32, I32, P, I32, I64, P, I64, P, I64, D, I32, P, SZ, P,
+                               ctypes.POINTER(_SolveCol)],
         "qtt_fgmres_workspace_bytes": [P, P, I32, I64, I32, ctypes.POINTER(SZ)],
         "qtt_solve_fgmres": [P, P, I32, I64, P, I64, P, I64, D, I32, P, SZ, P, ctypes.POINTER(_SolveCol)],
         "qtt_solve_fgmres_product": [P, P, P, I32, I64, P, I64, P, I64, D, I32, P, SZ, P,
@@ -100,7 +102,7 @@ _lib = _load()
 # Names the C ABI exports (include/qtt.h); the tests check each is present.
 EXPORTED = ["qtt_matrix_load", "qtt_matrix_free", "qtt_matrix_set_diagonals", "qtt_matrix_info", "qtt_workspace_bytes",
             "qtt_apply", "qtt_apply_batched", "qtt_apply_noalloc", "qtt_autotune", "qtt_solve_workspace_bytes",
-            "qtt_matvec_compressed", "qtt_solve", "qtt_fgmres_workspace_bytes", "qtt_solve_fgmres", "qtt_solve_fgmres_product", "qtt_status_string", "qtt_last_error", "qtt_set_shape", "qtt_list_shapes",
+            "qtt_matvec_compressed", "qtt_solve", "qtt_solve_schedule", "qtt_fgmres_workspace_bytes", "qtt_solve_fgmres", "qtt_solve_fgmres_product", "qtt_status_string", "qtt_last_error", "qtt_set_shape", "qtt_list_shapes",
             "qtt_tt_round", "qtt_tt_compress", "qtt_matrix_cores", "qtt_matrix_shape", "qtt_invert_newton_schulz",
             "qtt_timing_enable",
             "qtt_timing_reset", "qtt_timing_read", "qtt_timing_read_shape"]
@@ -340,6 +342,30 @@ def qtt_solve(A, Ainv, inv_compute, F, Sigma=None, rtol=1e-8, max_iter=50, ws=No
     info = (_SolveCol * k)()
     st = _lib.qtt_solve(A.handle, Ainv.handle, _dtype(inv_compute), k, fp, ldf, sp, lds, float(rtol),
                         int(max_iter), ws.data_ptr(), ws.numel() * ws.element_size(), _stream(stream), info)
+    if raise_on_fail:
+        _check(st)
+    else:
+        _check(st, allow=(QTT_ERR_NOT_CONVERGED, QTT_ERR_NONFINITE))
+    return Sigma, [(c.iters, c.rel_residual) for c in info], st
+
+
+@_on_stream
+def qtt_solve_schedule(A, Ainv_first, first_compute, first_passes, Ainv, inv_compute, F, Sigma=None, rtol=1e-8,
+                       max_iter=50, ws=None, stream=None, raise_on_fail=True):
+    """qtt_solve whose first `first_passes` passes apply Ainv_first in
+    first_compute and the later ones Ainv in inv_compute; returns (Sigma,
+    info, status) as qtt_solve."""
+    fp, n, k, ldf = _col_major(F, "F")
+    if Sigma is None:
+        Sigma = empty_block(n, k, F.device) if F.dim() == 2 else torch.empty(n, dtype=torch.float64, device=F.device)
+    sp, _, _, lds = _col_major(Sigma, "Sigma")
+    if ws is None:
+        ws = workspace(max(qtt_solve_workspace_bytes(A, Ainv, inv_compute, k),
+                           qtt_solve_workspace_bytes(A, Ainv_first, first_compute, k)), F.device)
+    info = (_SolveCol * k)()
+    st = _lib.qtt_solve_schedule(A.handle, Ainv_first.handle, _dtype(first_compute), int(first_passes), Ainv.handle,
+                                 _dtype(inv_compute), k, fp, ldf, sp, lds, float(rtol), int(max_iter), ws.data_ptr(),
+                                 ws.numel() * ws.element_size(), _stream(stream), info)
     if raise_on_fail:
         _check(st)
     else:

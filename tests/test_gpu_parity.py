@@ -422,6 +422,33 @@ def test_fp32_split_batched_uneven(Q):
     A.free()
 
 
+def test_solve_schedule(Q):
+    """qtt_solve_schedule: with no first passes it is qtt_solve (same bits);
+    a BF16 first pass and split-product FP32 passes after it converge to the
+    tolerance, the residual recomputed by the oracle; a negative pass count
+    is rejected."""
+    Ac, Aic = I.perturbed_identity_pair([1, 8, 16, 16, 8, 1], [8] * 5, seed=97)
+    F = I.rhs(8 ** 5, 3, seed=98)
+    A = Q.qtt_matrix_load(Ac, dtypes=("fp64",))
+    Ai = Q.qtt_matrix_load(Aic, dtypes=("bf16", "fp32"))
+    Ais = Q.qtt_matrix_load(Aic, dtypes=("fp32",))
+    Q.qtt_use_split_products(Ais)
+    Fd = Q.to_block(F)
+    S0, info0, _ = Q.qtt_solve(A, Ais, "fp32", Fd, rtol=1e-8)
+    S1, info1, _ = Q.qtt_solve_schedule(A, Ai, "bf16", 0, Ais, "fp32", Fd, rtol=1e-8)
+    assert np.array_equal(S0.cpu().numpy(), S1.cpu().numpy()) and info0 == info1
+    S2, info2, _ = Q.qtt_solve_schedule(A, Ai, "bf16", 1, Ais, "fp32", Fd, rtol=1e-8)
+    print("schedule passes", [c[0] for c in info2], "split only", [c[0] for c in info0])
+    Sh = S2.cpu().numpy()
+    for c in range(3):
+        r = F[:, c] - O.qtt_apply_alg2(Ac, Sh[:, c])
+        assert np.linalg.norm(r) <= 1e-8 * np.linalg.norm(F[:, c]) * 1.0001
+    with pytest.raises(Q.QttError):
+        Q.qtt_solve_schedule(A, Ai, "bf16", -1, Ais, "fp32", Fd, rtol=1e-8)
+    for h in (A, Ai, Ais):
+        h.free()
+
+
 @pytest.mark.slow
 def test_refine_L7_split_fp32_inverse(Q):
     """The reported solve in the benchmark's launch configuration: L=7, K=8,
@@ -430,14 +457,16 @@ def test_refine_L7_split_fp32_inverse(Q):
     copy applied with the split-product configuration on every interior core.
     Three passes; the oracle recomputes the relative residual of two sampled
     columns, and one inverse apply is checked element by element against the
-    oracle's apply of the same cores within the split's rounding bound."""
+    oracle's apply of the same cores within the split's rounding bound.  The
+    schedule with the inverse's BF16 copy in the first pass also takes three
+    passes."""
     w = I.WORKLOADS["refine_L7"]
     Ac, Aic = I.perturbed_identity_pair(w["ranks"], [8] * 7, seed=w["core_seed"], eps=w["eps"])
     F = I.rhs(8 ** 7, w["K"], seed=w["rhs_seed"])
     A = Q.qtt_matrix_load(Ac, dtypes=("fp64",))
-    Ai0 = Q.qtt_matrix_load(Aic, dtypes=("fp64", "fp32"))
+    Ai0 = Q.qtt_matrix_load(Aic, dtypes=("fp64", "fp32", "bf16"))
     Ai, hist, steps, _ = Q.qtt_invert_newton_schulz(A, Ai0, 1e-10, max_rank=32, max_iter=6, theta=0.1, seed=5,
-                                                     dtypes=("fp64", "fp32"), raise_on_cap=False)
+                                                     dtypes=("fp64", "fp32", "bf16"), raise_on_cap=False)
     cores = Q.qtt_matrix_cores(Ai)
     Ais = Q.qtt_matrix_load(cores, dtypes=("fp32",))
     Q.qtt_use_split_products(Ais)
@@ -452,6 +481,14 @@ def test_refine_L7_split_fp32_inverse(Q):
     torch.cuda.synchronize()
     ref = O.qtt_apply_alg2(cores, F[:, :1])
     check_reduced(Y.cpu().numpy(), ref, cores, F[:, :1], "fp32s", "split inverse apply, L=7")
+    # the schedule with the BF16 copy of the same inverse in the first pass
+    Sig, info, st = Q.qtt_solve_schedule(A, Ai, "bf16", 1, Ais, "fp32", Q.to_block(F), rtol=w["rtol"])
+    print("schedule passes", [c[0] for c in info], "residuals", [c[1] for c in info])
+    assert [c[0] for c in info] == [3] * w["K"]
+    Sh = Sig.cpu().numpy()
+    for c in (0, w["K"] - 1):
+        r = F[:, c] - O.qtt_apply_alg2(Ac, Sh[:, c])
+        assert np.linalg.norm(r) <= 1e-8 * np.linalg.norm(F[:, c]) * 1.0001
     for h in (A, Ai0, Ai, Ais):
         h.free()
 
