@@ -1056,6 +1056,12 @@ __global__ void __launch_bounds__(256, 2) core_pair_f64_kernel(const PairArgs ar
 #pragma unroll
         for (int j = 0; j < CB; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
       __syncthreads();
+      // Issue priority by phase: the two waves of a SIMD belong to different
+      // work-groups, so one is often in another phase of its tile than the
+      // other.  The barrier-free step k + 1 outranks step k, and both outrank
+      // the output stores and staging at the tile's end, so the matrix pipe
+      // is fed first (about 1% on the pairs; the results do not change).
+      __builtin_amdgcn_s_setprio(1);
       for (int ch = 0; ch < nchA; ++ch) {
         const double* S = lds + (ch & 1) * A_ELEMS;
         double afn[CB];
@@ -1130,6 +1136,7 @@ __global__ void __launch_bounds__(256, 2) core_pair_f64_kernel(const PairArgs ar
 #pragma unroll
       for (int j = 0; j < CB; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
     __syncthreads();
+    __builtin_amdgcn_s_setprio(2);
     double bfn[CB];
 #pragma unroll
     for (int j = 0; j < CB; ++j) bfn[j] = lds[(j * KSB) * 64 + sw[0]];
@@ -1154,6 +1161,7 @@ __global__ void __launch_bounds__(256, 2) core_pair_f64_kernel(const PairArgs ar
             acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[j], bc[i], acc[i][j], 0, 0, 0);
       }
     }
+    __builtin_amdgcn_s_setprio(0);
     if constexpr (NEXTA) {
       if (t + 1 < my_tiles) {
 #pragma unroll
