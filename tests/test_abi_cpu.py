@@ -44,3 +44,14 @@ def test_binding_loads_and_matches_header():
     m = (ctypes.c_int64 * 1)(8)
     st = qtt.lib().qtt_matrix_load(1, r, m, m, (ctypes.c_void_p * 1)(None), 1, ctypes.byref(h))
     assert st == 2 and b"boundary" in qtt.lib().qtt_last_error()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libqtt.so not built")
+def test_solve_schedule_argument_errors():
+    """qtt_solve_schedule rejects null handles before any device work (the
+    pass-count check needs valid handles and runs on the GPU tests)."""
+    import torch  # noqa: F401
+    from paper_1511_06029_amd import qtt
+    L = qtt.lib()
+    st = L.qtt_solve_schedule(None, None, 1, 1, None, 1, 1, None, 1, None, 1, 1e-8, 4, None, 0, None, None)
+    assert st == 1 and b"null handle" in L.qtt_last_error()    # QTT_ERR_INVALID_ARG
