@@ -423,10 +423,12 @@ def test_fp32_split_batched_uneven(Q):
 
 
 def test_solve_schedule(Q):
-    """qtt_solve_schedule: with no first passes it is qtt_solve (same bits);
-    a BF16 first pass and split-product FP32 passes after it converge to the
-    tolerance, the residual recomputed by the oracle; a negative pass count
-    is rejected."""
+    """qtt_solve_schedule: with no first passes it is qtt_solve with the
+    second inverse, and with more first passes than the solve needs it is
+    qtt_solve with the first (same bits either way); a BF16 first pass and
+    split-product (or plain, from the same handle) FP32 passes after it
+    converge to the tolerance, the residual recomputed by the oracle; a
+    negative pass count is rejected."""
     Ac, Aic = I.perturbed_identity_pair([1, 8, 16, 16, 8, 1], [8] * 5, seed=97)
     F = I.rhs(8 ** 5, 3, seed=98)
     A = Q.qtt_matrix_load(Ac, dtypes=("fp64",))
@@ -442,6 +444,16 @@ def test_solve_schedule(Q):
     Sh = S2.cpu().numpy()
     for c in range(3):
         r = F[:, c] - O.qtt_apply_alg2(Ac, Sh[:, c])
+        assert np.linalg.norm(r) <= 1e-8 * np.linalg.norm(F[:, c]) * 1.0001
+    # every pass within the first ones: qtt_solve with the first inverse
+    S3, info3, _ = Q.qtt_solve(A, Ai, "bf16", Fd, rtol=1e-8)
+    S4, info4, _ = Q.qtt_solve_schedule(A, Ai, "bf16", 50, Ais, "fp32", Fd, rtol=1e-8)
+    assert np.array_equal(S3.cpu().numpy(), S4.cpu().numpy()) and info3 == info4
+    # one handle holding both copies, plain FP32 arithmetic after the first pass
+    S5, info5, _ = Q.qtt_solve_schedule(A, Ai, "bf16", 1, Ai, "fp32", Fd, rtol=1e-8)
+    S5h = S5.cpu().numpy()
+    for c in range(3):
+        r = F[:, c] - O.qtt_apply_alg2(Ac, S5h[:, c])
         assert np.linalg.norm(r) <= 1e-8 * np.linalg.norm(F[:, c]) * 1.0001
     with pytest.raises(Q.QttError):
         Q.qtt_solve_schedule(A, Ai, "bf16", -1, Ais, "fp32", Fd, rtol=1e-8)
