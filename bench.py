@@ -72,9 +72,10 @@ def parse():
                    help="only run a device copy of known size (HBM counter calibration)")
     p.add_argument("--first-order-inverse", action="store_true",
                    help="solve with the first-order inverse instead of the Newton-Schulz one")
-    p.add_argument("--variants", default="sched,fp32s,bf16,fp64,fp32",
+    p.add_argument("--variants", default="mixed,sched,fp32s,bf16,fp64,fp32",
                    help="inverse dtypes to time (fp32s: FP32 cores, products from split BF16 "
-                        "operands; sched: the BF16 copy in the first pass, fp32s after it); "
+                        "operands; sched: the BF16 copy in the first pass, fp32s after it; mixed: "
+                        "sched, with the residual updated by A's split FP32 copy below 1e-5); "
                         "the first is the reported value")
     return p.parse_args()
 
@@ -111,7 +112,8 @@ def main():
     variants = [v.strip() for v in args.variants.split(",") if v.strip()]
 
     A = Q.qtt_matrix_load(Ac, dtypes=("fp64",))
-    inv_dtypes = tuple(sorted({DT(v) for v in variants} | {"fp64"} | ({"bf16"} if "sched" in variants else set())))
+    scheduled = [v for v in variants if v in ("sched", "mixed")]
+    inv_dtypes = tuple(sorted({DT(v) for v in variants} | {"fp64"} | ({"bf16"} if scheduled else set())))
     Ai0 = Q.qtt_matrix_load(Aic, dtypes=inv_dtypes)
     F = Q.to_block(F_h)
     # setup (untimed): the compressed inverse at the operator's ranks (<= 32),
@@ -134,15 +136,30 @@ def main():
     # handle of the same inverse with the split-product configuration pinned on
     # its interior cores
     inv_h = {v: (Ai, v) for v in variants + ["fp64"]}
-    if "fp32s" in variants or "sched" in variants:
+    if "fp32s" in variants or scheduled:
         Ais = Q.qtt_matrix_load(Aic, dtypes=("fp32",))
         Q.qtt_use_split_products(Ais)
-        inv_h["fp32s"] = (Ais, "fp32")
-        inv_h["sched"] = (Ais, "fp32")     # its later passes; the first applies Ai's BF16 copy
+        for v in ("fp32s", "sched", "mixed"):
+            inv_h[v] = (Ais, "fp32")       # sched, mixed: their later passes (the first applies Ai's BF16 copy)
+    # mixed: A's own split-product FP32 copy updates the residual (r -= A dx)
+    # in the passes that start below 1e-5 of ||F|| (about 2e-11 of ||F|| off
+    # the true residual at that size; the true residuals are recomputed in
+    # FP64 after the timed solves)
+    As = None
+    if "mixed" in variants:
+        As = Q.qtt_matrix_load(Ac, dtypes=("fp32",))
+        Q.qtt_use_split_products(As)
+
+    def schedule(v):
+        if v == "sched":
+            return dict(first=Ai, first_compute="bf16", first_passes=1)
+        if v == "mixed":
+            return dict(first=Ai, first_compute="bf16", first_passes=1, A_lo=As, lo_compute="fp32", lo_below=1e-5)
+        return {}
+
     Sig = Q.empty_block(N, K)
-    ws_bytes = max(Q.qtt_solve_workspace_bytes(A, inv_h[v][0], inv_h[v][1], K) for v in variants)
-    if "sched" in variants:
-        ws_bytes = max(ws_bytes, Q.qtt_solve_workspace_bytes(A, Ai, "bf16", K))
+    ws_bytes = max(Q.qtt_solve_schedule_workspace_bytes(A, inv_h[v][0], inv_h[v][1], K, **schedule(v))
+                   for v in variants)
     ws = Q.workspace(ws_bytes)
     stream = torch.cuda.current_stream()
 
@@ -153,17 +170,19 @@ def main():
                               *[Q.qtt_workspace_bytes(Ai, DT(v), K) for v in variants]))
         Q.qtt_autotune(A, "fp64", F, Yt, aws)
         for v in variants:
-            if v not in ("fp32s", "sched"):          # pinned configuration: not tuned
+            if v not in ("fp32s", "sched", "mixed"):          # pinned configuration: not tuned
                 Q.qtt_autotune(Ai, v, F, Yt, aws)
         del Yt, aws
         torch.cuda.synchronize()
 
     def solver(v):
         """One refined solve of variant v (sched: the inverse's BF16 copy in the
-        first pass, the split-product FP32 copy after it)."""
+        first pass, the split-product FP32 copy after it; mixed: sched with the
+        late residual updates by A's split-product copy)."""
         Ah, dv = inv_h[v]
-        if v == "sched":
-            return lambda: Q.qtt_solve_schedule(A, Ai, "bf16", 1, Ah, dv, F, Sig, rtol=rtol, ws=ws, stream=stream)
+        if v in ("sched", "mixed"):
+            sc = schedule(v)
+            return lambda: Q.qtt_solve_schedule(A, Ah, dv, F, Sig, rtol=rtol, ws=ws, stream=stream, **sc)
         return lambda: Q.qtt_solve(A, Ah, dv, F, Sig, rtol=rtol, ws=ws, stream=stream)
 
     results = {}
@@ -192,7 +211,7 @@ def main():
             # with HIP events around every launch (direct launches, no graphs)
             Q.qtt_timing_reset()
             Q.qtt_timing_enable(True)
-            for _ in range(max(2, min(args.steps, 5))):
+            for _ in range(max(2, min(args.steps, 8))):
                 solve()
             torch.cuda.synchronize()
             Q.qtt_timing_enable(False)
@@ -206,9 +225,13 @@ def main():
             sigma0 = Sig[:, 0].cpu().numpy().copy()   # the headline solve's first solution
         iters = max(c[0] for c in infos[-1])
         worst = max(c[1] for inf in infos for c in inf)
+        # untimed: the last solve's true residuals, A applied in FP64
+        Rt = F - Q.qtt_apply(A, "fp64", Sig)
+        true = float((torch.linalg.vector_norm(Rt, dim=0) / torch.linalg.vector_norm(F, dim=0)).max())
+        del Rt
         results[v] = {"rhs_per_s": K * args.steps / elapsed, "ms_per_step": 1e3 * elapsed / args.steps,
                       "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99),
-                      "passes": iters, "max_rel_residual": worst}
+                      "passes": iters, "max_rel_residual": worst, "max_rel_residual_true": true}
         if timing:
             results[v]["kernels"] = kt
             results[v]["shapes"] = ks
@@ -265,14 +288,18 @@ def main():
             tlo, klo = measured_traffic(DT(head), shlo)
             roof_lo = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                        "frac": round(gbs / PEAK_HBM_GBS, 4), "tflops": round(tfs, 2),
-                       "traffic": (None if (tlo is None or args.tune) else tlo),
-                       "kernel": (f"{'fp32s' if head == 'sched' else head} core step, configuration {shlo}"
+                       # mixed: the configuration's launches include those of
+                       # A's split copy, while the counters cover the inverse's
+                       "traffic": (None if (tlo is None or args.tune or head == "mixed") else tlo),
+                       "kernel": (f"{'fp32s' if head in ('sched', 'mixed') else head} core step, configuration {shlo}"
                                   + (f" ({klo})" if klo else "")
-                                  + ", the one carrying most of the inverse apply's flops"),
+                                  + (", the one carrying most of the split-product applies' flops (the inverse's "
+                                     "and, in the late residual updates, A's)" if head == "mixed" else
+                                     ", the one carrying most of the inverse apply's flops")),
                        "launches": lo["launches"], "avg_launch_ms": round(lo["ms"] / lo["launches"], 4)}
 
     fg = None if args.no_fgmres else fgmres_run(Q, torch, A, inv_h[head][0], inv_h[head][1], F, K, N, rtol, args,
-                                                label="fp32s" if head == "sched" else head)
+                                                label="fp32s" if head in ("sched", "mixed") else head)
 
     nti = None if args.no_nti else nti_run(Q, torch, Ac, F, K, N)
     cmv = None if args.no_compressed else compressed_run(Q, torch, Ac)
@@ -303,19 +330,21 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": ("bf16,fp32s" if head == "sched" else head) + "+f64",
+        "dtype": ("bf16,fp32s" if head in ("sched", "mixed") else head) + "+f64",
         "data": "synthetic",
         "config": {"workload": "refine_L7: refined QTT-inverse solve, L=7 (N=2097152), mode 8x8, "
                                "A ranks [1,24,32,32,32,32,24,1], inverse ranks <= 32 (computed on the GPU), "
                                "K=8 RHS per step, rtol 1e-8",
                    "inverse_dtype": head, "inverse_arithmetic": INV_ARITH.get(head, head),
-                   "residual_dtype": "fp64", "rhs_per_step": K,
+                   "residual_dtype": ("fp64; below 1e-5 ||F||: updated with A's split-product FP32 copy, "
+                                      "FP64 accumulation" if head == "mixed" else "fp64"), "rhs_per_step": K,
                    "N": N, "L": L, "ranks": ranks},
         "latency_ms": {"p50": round(r0["p50_ms"], 3), "p99": round(r0["p99_ms"], 3)},
         "launch_path": "timed solves replay each sweep from its captured hipGraph; the roofline "
                        "figures come from a separate run with HIP events around every launch",
         "passes": r0["passes"],
         "max_rel_residual": r0["max_rel_residual"],
+        "max_rel_residual_true": r0["max_rel_residual_true"],
         "variants": {v: {k: (float(f"{x:.5g}") if isinstance(x, float) else x) for k, x in r.items()
                          if k not in ("kernels", "shapes")}
                      for v, r in results.items()},
@@ -430,6 +459,8 @@ INV_ARITH = {
              "(hi + lo, three BF16 matrix instructions), FP32 accumulation",
     "sched": "first pass: the inverse's BF16 copy (BF16 cores and intermediates, FP32 accumulation); "
              "later passes: its FP32 copy with split-BF16 products (as fp32s)",
+    "mixed": "the inverse as in sched; residual r = F - A sigma in FP64 in the passes that start above "
+             "1e-5 ||F||, r -= A dx with A's split-product FP32 copy (FP64 update) in the others",
     "fp32": "FP32 cores and intermediates, FP32 matrix instructions",
     "bf16": "BF16 cores and intermediates, FP32 accumulation",
     "fp64": "FP64 throughout",
@@ -437,9 +468,9 @@ INV_ARITH = {
 
 
 def DT(variant):
-    """Compute dtype of a solve variant's main inverse: fp32s (and sched after
-    its first pass) is FP32 with split-operand products."""
-    return "fp32" if variant in ("fp32s", "sched") else variant
+    """Compute dtype of a solve variant's main inverse: fp32s (and sched and
+    mixed after their first pass) is FP32 with split-operand products."""
+    return "fp32" if variant in ("fp32s", "sched", "mixed") else variant
 
 
 def measured_traffic(dtype, shape):

@@ -232,22 +232,51 @@ qtt_status_t qtt_solve(qtt_matrix_t A, qtt_matrix_t Ainv, qtt_dtype_t inv_comput
                        double rtol, int32_t max_iter, void* ws, size_t ws_bytes,
                        void* stream, qtt_solve_col_t* info);
 
-/* qtt_solve with a schedule of inverse applies: passes 1 .. first_passes
- * apply Ainv_first in first_compute, the later passes Ainv in inv_compute
- * (the refinement of section 5 with the compressed inverse applied at two
- * precisions: each pass contracts the error by that pass's apply, so a
- * cheaper first pass costs one factor of its own contraction).  The residual,
- * the stopping rule, the column handling and the return values are those of
- * qtt_solve; first_passes = 0 is qtt_solve with Ainv.  Ainv_first and Ainv
- * may be the same handle (two device copies) or two handles of the same
- * matrix.  The workspace must hold what qtt_solve_workspace_bytes returns for
- * either inverse (the larger of the two).  QTT_ERR_INVALID_ARG for
- * first_passes < 0. */
-qtt_status_t qtt_solve_schedule(qtt_matrix_t A, qtt_matrix_t Ainv_first, qtt_dtype_t first_compute,
-                                int32_t first_passes, qtt_matrix_t Ainv, qtt_dtype_t inv_compute,
-                                int64_t nrhs, const double* F, int64_t ldf, double* Sigma, int64_t lds,
-                                double rtol, int32_t max_iter, void* ws, size_t ws_bytes,
-                                void* stream, qtt_solve_col_t* info);
+/* The schedule of a refined solve (qtt_solve_schedule).  Refinement as
+ * section 5 uses it fixes no precision per pass; each pass multiplies the
+ * error by the contraction of its own inverse apply, so a cheaper apply
+ * costs only its own factor, in the pass where it runs.
+ *   inv_first, first_compute, first_passes
+ *       passes 1 .. first_passes apply inv_first in first_compute, the later
+ *       ones Ainv in inv_compute (first_passes = 0: inv_first is ignored and
+ *       may be NULL).
+ *   A_lo, lo_compute, lo_below
+ *       a pass that starts with ||r_c|| <= lo_below ||F_c|| in every column
+ *       still iterating keeps its correction dx = Ainv r apart and updates
+ *       the residual as r -= A_lo dx (A_lo applied in lo_compute, the update
+ *       fused into A_lo's last core and accumulated in FP64) instead of
+ *       recomputing r = F - A sigma with A in FP64.  The computed residual
+ *       then differs from the true one by the error of A_lo's apply on dx,
+ *       about u_lo ||A|| ||dx||, and ||dx|| is about ||Ainv|| lo_below ||F_c||:
+ *       choose lo_below <= 0.01 rtol / u_lo (u_lo the relative error of one
+ *       A_lo apply).  A_lo = NULL: every residual is recomputed in FP64.
+ *       A_lo holds the same operator as A (same modes); the library does not
+ *       check its values. */
+typedef struct {
+  qtt_matrix_t inv_first;
+  qtt_dtype_t first_compute;
+  int32_t first_passes;
+  qtt_matrix_t A_lo;
+  qtt_dtype_t lo_compute;
+  double lo_below;
+} qtt_schedule_t;
+
+/* Device bytes of workspace for qtt_solve_schedule: qtt_solve's, with the
+ * apply workspace of every handle the schedule names, plus an N x nrhs FP64
+ * correction block when A_lo is given.  sched may be NULL (qtt_solve's). */
+qtt_status_t qtt_solve_schedule_workspace_bytes(qtt_matrix_t A, qtt_matrix_t Ainv, qtt_dtype_t inv_compute,
+                                                const qtt_schedule_t* sched, int64_t nrhs, size_t* bytes);
+
+/* qtt_solve with a schedule (qtt_schedule_t); sched = NULL, or one with
+ * first_passes = 0 and A_lo = NULL, is qtt_solve with Ainv.  The stopping
+ * rule, the column handling and the return values are those of qtt_solve;
+ * info's rel_residual is the computed residual (updated with A_lo in the
+ * passes that do so).  QTT_ERR_INVALID_ARG for first_passes < 0, a NULL
+ * inv_first with first_passes > 0, or lo_below < 0 or not finite. */
+qtt_status_t qtt_solve_schedule(qtt_matrix_t A, qtt_matrix_t Ainv, qtt_dtype_t inv_compute,
+                                const qtt_schedule_t* sched, int64_t nrhs, const double* F, int64_t ldf,
+                                double* Sigma, int64_t lds, double rtol, int32_t max_iter, void* ws,
+                                size_t ws_bytes, void* stream, qtt_solve_col_t* info);
 
 /* Device bytes of workspace for qtt_solve_fgmres: max_iter + 1 Krylov blocks
  * V and, with a preconditioner, max_iter preconditioned blocks Z (each

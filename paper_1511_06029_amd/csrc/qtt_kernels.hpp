@@ -2861,6 +2861,25 @@ __global__ void __launch_bounds__(kKryThreads) combine_kernel(const CombineArgs 
   }
 }
 
+// y_c += x_c for the columns of one run of consecutive vectors (blockIdx.y
+// is the column within the run): the refined solve's sigma += dx when the
+// correction dx is kept apart for a residual update.
+struct AddColsArgs {
+  double* y;
+  const double* x;
+  int64_t ldy, ldx;      // elements between consecutive columns
+  int64_t N;             // rows
+};
+
+__global__ void __launch_bounds__(256) add_cols_kernel(const AddColsArgs args) {
+  (void)args;
+  const AddColsArgs& a = kernarg<AddColsArgs>();
+  double* y = a.y + (int64_t)blockIdx.y * a.ldy;
+  const double* x = a.x + (int64_t)blockIdx.y * a.ldx;
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < a.N; r += stride) y[r] += x[r];
+}
+
 // ---------------------------------------------------------------------------
 // Non-translation-invariant operators A = a I + B K W C (section 3, the
 // matrix form of the Nystrom discretisation): B = diag(b), W C = diag(wc),

@@ -1595,27 +1595,91 @@ static qtt_status_t column_norms(const std::vector<const double*>& cols, const s
   return QTT_OK;
 }
 
-// The refined solve; the first `first_passes` passes apply Ainv1 in its
-// compute dtype (Ainv1 == Ainv and first_passes == 0 for qtt_solve).
-static qtt_status_t solve_impl(qtt_matrix_t A, qtt_matrix_t Ainv1, qtt_dtype_t compute1, int32_t first_passes,
-                               qtt_matrix_t Ainv, qtt_dtype_t inv_compute, int64_t nrhs,
-                               const double* F, int64_t ldf, double* Sigma, int64_t lds, double rtol,
+// Checks of a solve's schedule against A (NULL sched: qtt_solve's).
+static qtt_status_t check_schedule(const qtt_matrix_s* A, const qtt_schedule_t* sc, int* dt1, int* dtl) {
+  if (!sc) return QTT_OK;
+  if (sc->first_passes < 0) return fail(QTT_ERR_INVALID_ARG, "first_passes < 0");
+  if (!(sc->lo_below >= 0) || !std::isfinite(sc->lo_below))
+    return fail(QTT_ERR_INVALID_ARG, "lo_below must be finite and >= 0");
+  qtt_status_t s;
+  if (sc->first_passes > 0) {
+    if (!valid_handle(sc->inv_first)) return fail(QTT_ERR_INVALID_ARG, "null inv_first with first_passes > 0");
+    s = check_dtype(sc->inv_first, sc->first_compute, dt1);
+    if (s != QTT_OK) return s;
+  }
+  if (sc->A_lo) {
+    if (!valid_handle(sc->A_lo)) return fail(QTT_ERR_INVALID_ARG, "invalid A_lo");
+    s = check_dtype(sc->A_lo, sc->lo_compute, dtl);
+    if (s != QTT_OK) return s;
+  }
+  for (const qtt_matrix_s* M : {sc->first_passes > 0 ? sc->inv_first : nullptr, sc->A_lo}) {
+    if (!M) continue;
+    if (A->d != M->d) return fail(QTT_ERR_SHAPE, "schedule handle with a different core count");
+    for (int k = 0; k < A->d; ++k)
+      if (M->m[k] != A->m[k] || M->n[k] != A->n[k])
+        return fail(QTT_ERR_SHAPE, "schedule handle with different modes (core %d)", k);
+  }
+  return QTT_OK;
+}
+
+// Apply workspace (per vector) of every handle a solve uses, and the bytes
+// of the correction block.
+static size_t schedule_apply_bytes(qtt_matrix_t A, qtt_matrix_t Ainv, qtt_dtype_t inv_compute,
+                                   const qtt_schedule_t* sc, int64_t k) {
+  size_t need = 0, tmp = 0;
+  qtt_workspace_bytes(A, QTT_FP64, k, &need);
+  qtt_workspace_bytes(Ainv, inv_compute, k, &tmp);
+  need = std::max(need, tmp);
+  if (sc && sc->first_passes > 0) {
+    qtt_workspace_bytes(sc->inv_first, sc->first_compute, k, &tmp);
+    need = std::max(need, tmp);
+  }
+  if (sc && sc->A_lo) {
+    qtt_workspace_bytes(sc->A_lo, sc->lo_compute, k, &tmp);
+    need = std::max(need, tmp);
+  }
+  return need;
+}
+
+static size_t correction_bytes(const qtt_matrix_s* A, const qtt_schedule_t* sc, int64_t nrhs) {
+  return (sc && sc->A_lo) ? align256((size_t)A->rows * nrhs * 8) : 0;
+}
+
+// y_c += x_c for the columns of each block (one launch per block).
+static qtt_status_t add_cols(const std::vector<Block>& blocks, int64_t N, hipStream_t st) {
+  for (const Block& b : blocks) {
+    AddColsArgs aa;
+    aa.y = b.y;
+    aa.x = b.x;
+    aa.ldy = b.ldy;
+    aa.ldx = b.ldx;
+    aa.N = N;
+    const int64_t bx = std::min<int64_t>(1024, (N + 255) / 256);
+    void* args[] = {&aa};
+    HIP_TRY(hipLaunchKernel(reinterpret_cast<const void*>(&add_cols_kernel), dim3((unsigned)bx, (unsigned)b.width),
+                            dim3(256), args, 0, st));
+  }
+  return QTT_OK;
+}
+
+// The refined solve with an optional schedule (NULL: qtt_solve).
+static qtt_status_t solve_impl(qtt_matrix_t A, qtt_matrix_t Ainv, qtt_dtype_t inv_compute, const qtt_schedule_t* sc,
+                               int64_t nrhs, const double* F, int64_t ldf, double* Sigma, int64_t lds, double rtol,
                                int32_t max_iter, void* ws, size_t ws_bytes, void* stream, qtt_solve_col_t* info) {
-  if (!valid_handle(A) || !valid_handle(Ainv) || !valid_handle(Ainv1)) return fail(QTT_ERR_INVALID_ARG, "null handle");
-  if (first_passes < 0) return fail(QTT_ERR_INVALID_ARG, "first_passes < 0");
-  int dti, dta, dt1;
+  if (!valid_handle(A) || !valid_handle(Ainv)) return fail(QTT_ERR_INVALID_ARG, "null handle");
+  int dti, dta, dt1 = -1, dtl = -1;
   qtt_status_t s = check_dtype(Ainv, inv_compute, &dti);
-  if (s != QTT_OK) return s;
-  s = check_dtype(Ainv1, compute1, &dt1);
   if (s != QTT_OK) return s;
   s = check_dtype(A, QTT_FP64, &dta);
   if (s != QTT_OK) return s;
-  for (qtt_matrix_t Ai : {Ainv, Ainv1}) {
-    if (A->d != Ai->d) return fail(QTT_ERR_SHAPE, "A and Ainv have different core counts");
-    for (int k = 0; k < A->d; ++k)
-      if (A->m[k] != A->n[k] || Ai->m[k] != A->m[k] || Ai->n[k] != A->n[k])
-        return fail(QTT_ERR_SHAPE, "solve needs square, identical modes (core %d)", k);
-  }
+  if (A->d != Ainv->d) return fail(QTT_ERR_SHAPE, "A and Ainv have different core counts");
+  for (int k = 0; k < A->d; ++k)
+    if (A->m[k] != A->n[k] || Ainv->m[k] != A->m[k] || Ainv->n[k] != A->n[k])
+      return fail(QTT_ERR_SHAPE, "solve needs square, identical modes (core %d)", k);
+  s = check_schedule(A, sc, &dt1, &dtl);
+  if (s != QTT_OK) return s;
+  const int32_t first_passes = sc ? sc->first_passes : 0;
+  const qtt_matrix_s* A_lo = sc ? sc->A_lo : nullptr;
   if (nrhs < 0 || max_iter < 1 || !(rtol >= 0)) return fail(QTT_ERR_INVALID_ARG, "bad nrhs, max_iter or rtol");
   if (nrhs == 0) return QTT_OK;
   if (!F || !Sigma || !ws) return fail(QTT_ERR_INVALID_ARG, "null F, Sigma or workspace");
@@ -1623,16 +1687,10 @@ static qtt_status_t solve_impl(qtt_matrix_t A, qtt_matrix_t Ainv1, qtt_dtype_t c
   if (ldf < N || lds < N) return fail(QTT_ERR_INVALID_ARG, "ldf or lds < N");
   const size_t fb = ((size_t)(nrhs - 1) * ldf + N) * 8, sb = ((size_t)(nrhs - 1) * lds + N) * 8;
   if (overlaps(F, fb, Sigma, sb)) return fail(QTT_ERR_INVALID_ARG, "F and Sigma overlap");
-  // carve the workspace: [R | partial | norms | apply workspace]
-  const size_t extra = solve_extra_bytes(A, nrhs);
-  size_t need1 = 0, tmp = 0;
-  qtt_workspace_bytes(A, QTT_FP64, 1, &need1);
-  qtt_workspace_bytes(Ainv, inv_compute, 1, &tmp);
-  need1 = std::max(need1, tmp);
-  if (first_passes > 0) {
-    qtt_workspace_bytes(Ainv1, compute1, 1, &tmp);
-    need1 = std::max(need1, tmp);
-  }
+  // carve the workspace: [R | D (with A_lo) | partial | norms | apply workspace]
+  const size_t dbytes = correction_bytes(A, sc, nrhs);
+  const size_t extra = solve_extra_bytes(A, nrhs) + dbytes;
+  const size_t need1 = schedule_apply_bytes(A, Ainv, inv_compute, sc, 1);
   if (ws_bytes < extra + need1)
     return fail(QTT_ERR_WORKSPACE, "solve workspace %zu < minimum %zu", ws_bytes, extra + need1);
   if (overlaps(ws, ws_bytes, F, fb) || overlaps(ws, ws_bytes, Sigma, sb))
@@ -1640,6 +1698,8 @@ static qtt_status_t solve_impl(qtt_matrix_t A, qtt_matrix_t Ainv1, qtt_dtype_t c
   char* p = static_cast<char*>(ws);
   double* R = reinterpret_cast<double*>(p);
   p += align256((size_t)N * nrhs * 8);
+  double* D = dbytes ? reinterpret_cast<double*>(p) : nullptr;
+  p += dbytes;
   double* partial = reinterpret_cast<double*>(p);
   p += align256((size_t)nrhs * kNormBlocks * 8);
   double* dnorm = reinterpret_cast<double*>(p);
@@ -1657,10 +1717,12 @@ static qtt_status_t solve_impl(qtt_matrix_t A, qtt_matrix_t Ainv1, qtt_dtype_t c
   // columns still iterating; a converged column is frozen, and so is a column
   // whose F or residual is not finite (the others go on: columns never mix)
   std::vector<char> active(nrhs, 1);
+  std::vector<double> rel(nrhs, 1.0);          // relative residual before the next pass
   int64_t n_active = nrhs;
   int64_t first_bad = -1;
   for (int64_t c = 0; c < nrhs; ++c) {
     if (info) { info[c].iters = 0; info[c].rel_residual = (fn[c] > 0) ? 1.0 : 0.0; }
+    if (!(fn[c] > 0)) rel[c] = 0.0;
     if (!std::isfinite(fn[c])) {
       if (info) info[c].rel_residual = fn[c];
       if (first_bad < 0) first_bad = c;
@@ -1668,29 +1730,49 @@ static qtt_status_t solve_impl(qtt_matrix_t A, qtt_matrix_t Ainv1, qtt_dtype_t c
       --n_active;
     }
   }
-  std::vector<int> iters(nrhs, 0);
   for (int it = 1; it <= max_iter && n_active > 0; ++it) {
     // runs of consecutive active columns
     std::vector<std::pair<int64_t, int64_t>> runs;
+    double worst = 0.0;
     for (int64_t c = 0; c < nrhs;) {
       if (!active[c]) { ++c; continue; }
       int64_t e = c;
-      while (e < nrhs && active[e]) ++e;
+      while (e < nrhs && active[e]) { worst = std::max(worst, rel[e]); ++e; }
       runs.push_back({c, e - c});
       c = e;
     }
-    // sigma += Ainv r  (first pass: sigma = Ainv F)
-    std::vector<Block> bi, ba;
+    const bool use_first = it <= first_passes;
+    const qtt_matrix_s* Ai = use_first ? sc->inv_first : Ainv;
+    const int dtv = use_first ? dt1 : dti;
+    // residual update with A_lo when every active column starts below lo_below
+    const bool lo = A_lo && worst <= sc->lo_below;
+    std::vector<Block> bi, ba, bd;
     for (auto& r : runs) {
-      if (it == 1) bi.push_back({F + r.first * ldf, Sigma + r.first * lds, nullptr, ldf, lds, 0, r.second});
-      else bi.push_back({R + r.first * N, Sigma + r.first * lds, Sigma + r.first * lds, N, lds, lds, r.second});
-      // r = F - A sigma, residual fused into A's last core
-      ba.push_back({Sigma + r.first * lds, R + r.first * N, F + r.first * ldf, lds, N, ldf, r.second});
+      const int64_t c0 = r.first, w = r.second;
+      if (!lo) {
+        // sigma += Ainv r  (first pass: sigma = Ainv F); r = F - A sigma,
+        // the residual fused into A's last core
+        if (it == 1) bi.push_back({F + c0 * ldf, Sigma + c0 * lds, nullptr, ldf, lds, 0, w});
+        else bi.push_back({R + c0 * N, Sigma + c0 * lds, Sigma + c0 * lds, N, lds, lds, w});
+        ba.push_back({Sigma + c0 * lds, R + c0 * N, F + c0 * ldf, lds, N, ldf, w});
+      } else if (it == 1) {
+        // sigma = dx = Ainv F; r = F - A_lo sigma
+        bi.push_back({F + c0 * ldf, Sigma + c0 * lds, nullptr, ldf, lds, 0, w});
+        ba.push_back({Sigma + c0 * lds, R + c0 * N, F + c0 * ldf, lds, N, ldf, w});
+      } else {
+        // dx = Ainv r; sigma += dx; r -= A_lo dx
+        bi.push_back({R + c0 * N, D + c0 * N, nullptr, N, N, 0, w});
+        bd.push_back({D + c0 * N, Sigma + c0 * lds, nullptr, N, lds, 0, w});
+        ba.push_back({D + c0 * N, R + c0 * N, R + c0 * N, N, N, N, w});
+      }
     }
-    s = (it <= first_passes) ? run_blocks(Ainv1, dt1, bi, aws, aws_bytes, 1.0, st)
-                             : run_blocks(Ainv, dti, bi, aws, aws_bytes, 1.0, st);
+    s = run_blocks(Ai, dtv, bi, aws, aws_bytes, 1.0, st);
     if (s != QTT_OK) return s;
-    s = run_blocks(A, dta, ba, aws, aws_bytes, -1.0, st);
+    if (!bd.empty()) {
+      s = add_cols(bd, N, st);
+      if (s != QTT_OK) return s;
+    }
+    s = lo ? run_blocks(A_lo, dtl, ba, aws, aws_bytes, -1.0, st) : run_blocks(A, dta, ba, aws, aws_bytes, -1.0, st);
     if (s != QTT_OK) return s;
     std::vector<const double*> rc;
     std::vector<int64_t> rld;
@@ -1701,16 +1783,16 @@ static qtt_status_t solve_impl(qtt_matrix_t A, qtt_matrix_t Ainv1, qtt_dtype_t c
     if (s != QTT_OK) return s;
     for (size_t t = 0; t < idx.size(); ++t) {
       const int64_t c = idx[t];
-      iters[c] = it;
-      const double rel = (fn[c] > 0) ? rn[t] / fn[c] : rn[t];
-      if (info) { info[c].iters = it; info[c].rel_residual = rel; }
-      if (!std::isfinite(rel)) {
+      const double rr = (fn[c] > 0) ? rn[t] / fn[c] : rn[t];
+      rel[c] = rr;
+      if (info) { info[c].iters = it; info[c].rel_residual = rr; }
+      if (!std::isfinite(rr)) {
         if (first_bad < 0) first_bad = c;
         active[c] = 0;
         --n_active;
         continue;
       }
-      if (rel <= rtol) { active[c] = 0; --n_active; }
+      if (rr <= rtol) { active[c] = 0; --n_active; }
     }
   }
   if (first_bad >= 0)
@@ -1722,16 +1804,32 @@ static qtt_status_t solve_impl(qtt_matrix_t A, qtt_matrix_t Ainv1, qtt_dtype_t c
 qtt_status_t qtt_solve(qtt_matrix_t A, qtt_matrix_t Ainv, qtt_dtype_t inv_compute, int64_t nrhs,
                        const double* F, int64_t ldf, double* Sigma, int64_t lds, double rtol,
                        int32_t max_iter, void* ws, size_t ws_bytes, void* stream, qtt_solve_col_t* info) {
-  return solve_impl(A, Ainv, inv_compute, 0, Ainv, inv_compute, nrhs, F, ldf, Sigma, lds, rtol, max_iter, ws,
-                    ws_bytes, stream, info);
+  return solve_impl(A, Ainv, inv_compute, nullptr, nrhs, F, ldf, Sigma, lds, rtol, max_iter, ws, ws_bytes, stream,
+                    info);
 }
 
-qtt_status_t qtt_solve_schedule(qtt_matrix_t A, qtt_matrix_t Ainv_first, qtt_dtype_t first_compute,
-                                int32_t first_passes, qtt_matrix_t Ainv, qtt_dtype_t inv_compute, int64_t nrhs,
-                                const double* F, int64_t ldf, double* Sigma, int64_t lds, double rtol,
-                                int32_t max_iter, void* ws, size_t ws_bytes, void* stream, qtt_solve_col_t* info) {
-  return solve_impl(A, Ainv_first, first_compute, first_passes, Ainv, inv_compute, nrhs, F, ldf, Sigma, lds, rtol,
-                    max_iter, ws, ws_bytes, stream, info);
+qtt_status_t qtt_solve_schedule_workspace_bytes(qtt_matrix_t A, qtt_matrix_t Ainv, qtt_dtype_t inv_compute,
+                                                const qtt_schedule_t* sched, int64_t nrhs, size_t* bytes) {
+  if (!valid_handle(A) || !valid_handle(Ainv) || !bytes) return fail(QTT_ERR_INVALID_ARG, "null handle or output");
+  int dt, dt1, dtl;
+  qtt_status_t s = check_dtype(Ainv, inv_compute, &dt);
+  if (s != QTT_OK) return s;
+  s = check_dtype(A, QTT_FP64, &dt);
+  if (s != QTT_OK) return s;
+  s = check_schedule(A, sched, &dt1, &dtl);
+  if (s != QTT_OK) return s;
+  const int64_t k = std::max<int64_t>(nrhs, 1);
+  *bytes = schedule_apply_bytes(A, Ainv, inv_compute, sched, k) + solve_extra_bytes(A, k) +
+           correction_bytes(A, sched, k);
+  return QTT_OK;
+}
+
+qtt_status_t qtt_solve_schedule(qtt_matrix_t A, qtt_matrix_t Ainv, qtt_dtype_t inv_compute,
+                                const qtt_schedule_t* sched, int64_t nrhs, const double* F, int64_t ldf,
+                                double* Sigma, int64_t lds, double rtol, int32_t max_iter, void* ws,
+                                size_t ws_bytes, void* stream, qtt_solve_col_t* info) {
+  return solve_impl(A, Ainv, inv_compute, sched, nrhs, F, ldf, Sigma, lds, rtol, max_iter, ws, ws_bytes, stream,
+                    info);
 }
 
 // --------------------------------------------------------------------------- flexible GMRES

@@ -46,6 +46,12 @@ class _SolveCol(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("rel_residual", ctypes.c_double)]
 
 
+class _Schedule(ctypes.Structure):
+    """qtt_schedule_t."""
+    _fields_ = [("inv_first", ctypes.c_void_p), ("first_compute", ctypes.c_int32), ("first_passes", ctypes.c_int32),
+                ("A_lo", ctypes.c_void_p), ("lo_compute", ctypes.c_int32), ("lo_below", ctypes.c_double)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with "
@@ -68,8 +74,9 @@ def _load():
         "qtt_autotune": [P, I32, I64, P, I64, P, I64, P, SZ, P],
         "qtt_solve_workspace_bytes": [P, P, I32, I64, ctypes.POINTER(SZ)],
         "qtt_solve": [P, P, I32, I64, P, I64, P, I64, D, I32, P, SZ, P, ctypes.POINTER(_SolveCol)],
-        "qtt_solve_schedule": [P, P, I32, I32, P, I32, I64, P, I64, P, I64, D, I32, P, SZ, P,
+        "qtt_solve_schedule": [P, P, I32, ctypes.POINTER(_Schedule), I64, P, I64, P, I64, D, I32, P, SZ, P,
                                ctypes.POINTER(_SolveCol)],
+        "qtt_solve_schedule_workspace_bytes": [P, P, I32, ctypes.POINTER(_Schedule), I64, ctypes.POINTER(SZ)],
         "qtt_fgmres_workspace_bytes": [P, P, I32, I64, I32, ctypes.POINTER(SZ)],
         "qtt_solve_fgmres": [P, P, I32, I64, P, I64, P, I64, D, I32, P, SZ, P, ctypes.POINTER(_SolveCol)],
         "qtt_solve_fgmres_product": [P, P, P, I32, I64, P, I64, P, I64, D, I32, P, SZ, P,
@@ -102,7 +109,7 @@ _lib = _load()
 # Names the C ABI exports (include/qtt.h); the tests check each is present.
 EXPORTED = ["qtt_matrix_load", "qtt_matrix_free", "qtt_matrix_set_diagonals", "qtt_matrix_info", "qtt_workspace_bytes",
             "qtt_apply", "qtt_apply_batched", "qtt_apply_noalloc", "qtt_autotune", "qtt_solve_workspace_bytes",
-            "qtt_matvec_compressed", "qtt_solve", "qtt_solve_schedule", "qtt_fgmres_workspace_bytes", "qtt_solve_fgmres", "qtt_solve_fgmres_product", "qtt_status_string", "qtt_last_error", "qtt_set_shape", "qtt_list_shapes",
+            "qtt_matvec_compressed", "qtt_solve", "qtt_solve_schedule", "qtt_solve_schedule_workspace_bytes", "qtt_fgmres_workspace_bytes", "qtt_solve_fgmres", "qtt_solve_fgmres_product", "qtt_status_string", "qtt_last_error", "qtt_set_shape", "qtt_list_shapes",
             "qtt_tt_round", "qtt_tt_compress", "qtt_matrix_cores", "qtt_matrix_shape", "qtt_invert_newton_schulz",
             "qtt_timing_enable",
             "qtt_timing_reset", "qtt_timing_read", "qtt_timing_read_shape"]
@@ -349,23 +356,42 @@ def qtt_solve(A, Ainv, inv_compute, F, Sigma=None, rtol=1e-8, max_iter=50, ws=No
     return Sigma, [(c.iters, c.rel_residual) for c in info], st
 
 
+def _schedule(first, first_compute, first_passes, A_lo, lo_compute, lo_below):
+    return _Schedule(first.handle if first is not None else None, _dtype(first_compute or "fp64"), int(first_passes),
+                     A_lo.handle if A_lo is not None else None, _dtype(lo_compute or "fp64"), float(lo_below))
+
+
+def qtt_solve_schedule_workspace_bytes(A, Ainv, inv_compute, nrhs, first=None, first_compute=None, first_passes=0,
+                                       A_lo=None, lo_compute=None, lo_below=0.0):
+    b = ctypes.c_size_t()
+    sc = _schedule(first, first_compute, first_passes, A_lo, lo_compute, lo_below)
+    _check(_lib.qtt_solve_schedule_workspace_bytes(A.handle, Ainv.handle, _dtype(inv_compute), ctypes.byref(sc),
+                                                   int(nrhs), ctypes.byref(b)))
+    return b.value
+
+
 @_on_stream
-def qtt_solve_schedule(A, Ainv_first, first_compute, first_passes, Ainv, inv_compute, F, Sigma=None, rtol=1e-8,
-                       max_iter=50, ws=None, stream=None, raise_on_fail=True):
-    """qtt_solve whose first `first_passes` passes apply Ainv_first in
-    first_compute and the later ones Ainv in inv_compute; returns (Sigma,
-    info, status) as qtt_solve."""
+def qtt_solve_schedule(A, Ainv, inv_compute, F, Sigma=None, rtol=1e-8, max_iter=50, ws=None, stream=None,
+                       first=None, first_compute=None, first_passes=0, A_lo=None, lo_compute=None, lo_below=0.0,
+                       raise_on_fail=True):
+    """qtt_solve with a schedule: passes 1 .. first_passes apply `first` in
+    first_compute (the later ones Ainv in inv_compute), and a pass starting
+    with every active column's relative residual <= lo_below updates the
+    residual as r -= A_lo dx (A_lo in lo_compute) instead of recomputing it
+    in FP64.  Returns (Sigma, info, status) as qtt_solve; info holds the
+    computed residuals."""
     fp, n, k, ldf = _col_major(F, "F")
     if Sigma is None:
         Sigma = empty_block(n, k, F.device) if F.dim() == 2 else torch.empty(n, dtype=torch.float64, device=F.device)
     sp, _, _, lds = _col_major(Sigma, "Sigma")
+    sc = _schedule(first, first_compute, first_passes, A_lo, lo_compute, lo_below)
     if ws is None:
-        ws = workspace(max(qtt_solve_workspace_bytes(A, Ainv, inv_compute, k),
-                           qtt_solve_workspace_bytes(A, Ainv_first, first_compute, k)), F.device)
+        ws = workspace(qtt_solve_schedule_workspace_bytes(A, Ainv, inv_compute, k, first, first_compute,
+                                                          first_passes, A_lo, lo_compute, lo_below), F.device)
     info = (_SolveCol * k)()
-    st = _lib.qtt_solve_schedule(A.handle, Ainv_first.handle, _dtype(first_compute), int(first_passes), Ainv.handle,
-                                 _dtype(inv_compute), k, fp, ldf, sp, lds, float(rtol), int(max_iter), ws.data_ptr(),
-                                 ws.numel() * ws.element_size(), _stream(stream), info)
+    st = _lib.qtt_solve_schedule(A.handle, Ainv.handle, _dtype(inv_compute), ctypes.byref(sc), k, fp, ldf, sp, lds,
+                                 float(rtol), int(max_iter), ws.data_ptr(), ws.numel() * ws.element_size(),
+                                 _stream(stream), info)
     if raise_on_fail:
         _check(st)
     else:

@@ -53,5 +53,26 @@ def test_solve_schedule_argument_errors():
     import torch  # noqa: F401
     from paper_1511_06029_amd import qtt
     L = qtt.lib()
-    st = L.qtt_solve_schedule(None, None, 1, 1, None, 1, 1, None, 1, None, 1, 1e-8, 4, None, 0, None, None)
+    st = L.qtt_solve_schedule(None, None, 1, None, 1, None, 1, None, 1, 1e-8, 4, None, 0, None, None)
     assert st == 1 and b"null handle" in L.qtt_last_error()    # QTT_ERR_INVALID_ARG
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libqtt.so not built")
+def test_schedule_struct_layout(tmp_path):
+    """The binding's qtt_schedule_t has the C layout the header gives it
+    (size and field offsets as compiled by gcc)."""
+    import ctypes
+    import torch  # noqa: F401
+    from paper_1511_06029_amd import qtt
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stddef.h>\n#include <stdio.h>\n#include "qtt.h"\n'
+                   'int main(void) { printf("%zu %zu %zu %zu %zu %zu %zu", sizeof(qtt_schedule_t), '
+                   'offsetof(qtt_schedule_t, inv_first), offsetof(qtt_schedule_t, first_compute), '
+                   'offsetof(qtt_schedule_t, first_passes), offsetof(qtt_schedule_t, A_lo), '
+                   'offsetof(qtt_schedule_t, lo_compute), offsetof(qtt_schedule_t, lo_below)); return 0; }\n')
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)], check=True)
+    c = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    S = qtt._Schedule
+    py = [ctypes.sizeof(S)] + [getattr(S, f).offset for f, _ in S._fields_]
+    assert c == py, (c, py)

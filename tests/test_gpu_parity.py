@@ -423,41 +423,67 @@ def test_fp32_split_batched_uneven(Q):
 
 
 def test_solve_schedule(Q):
-    """qtt_solve_schedule: with no first passes it is qtt_solve with the
-    second inverse, and with more first passes than the solve needs it is
-    qtt_solve with the first (same bits either way); a BF16 first pass and
-    split-product (or plain, from the same handle) FP32 passes after it
-    converge to the tolerance, the residual recomputed by the oracle; a
-    negative pass count is rejected."""
+    """qtt_solve_schedule.  With no schedule it is qtt_solve, and with more
+    first passes than the solve needs it is qtt_solve with the first inverse
+    (same bits either way).  A BF16 first pass and split-product (or plain,
+    from the same handle) FP32 passes after it converge to the tolerance,
+    the residual recomputed by the oracle.  Residual updates with a split
+    FP32 copy of A in the late passes: the computed residual stays within
+    1e-10 of the true one (recomputed in FP64), lo_below = 0 changes no bit,
+    and a first pass with the update gives qtt_solve's first iterate.  Bad
+    schedules are rejected."""
     Ac, Aic = I.perturbed_identity_pair([1, 8, 16, 16, 8, 1], [8] * 5, seed=97)
     F = I.rhs(8 ** 5, 3, seed=98)
     A = Q.qtt_matrix_load(Ac, dtypes=("fp64",))
+    As = Q.qtt_matrix_load(Ac, dtypes=("fp32",))
+    Q.qtt_use_split_products(As)
     Ai = Q.qtt_matrix_load(Aic, dtypes=("bf16", "fp32"))
     Ais = Q.qtt_matrix_load(Aic, dtypes=("fp32",))
     Q.qtt_use_split_products(Ais)
     Fd = Q.to_block(F)
+    Fn = np.linalg.norm(F, axis=0)
+
+    def true_rel(S):
+        Sh = S.cpu().numpy()
+        return np.array([np.linalg.norm(F[:, c] - O.qtt_apply_alg2(Ac, Sh[:, c])) / Fn[c] for c in range(3)])
+
     S0, info0, _ = Q.qtt_solve(A, Ais, "fp32", Fd, rtol=1e-8)
-    S1, info1, _ = Q.qtt_solve_schedule(A, Ai, "bf16", 0, Ais, "fp32", Fd, rtol=1e-8)
+    S1, info1, _ = Q.qtt_solve_schedule(A, Ais, "fp32", Fd, rtol=1e-8)
     assert np.array_equal(S0.cpu().numpy(), S1.cpu().numpy()) and info0 == info1
-    S2, info2, _ = Q.qtt_solve_schedule(A, Ai, "bf16", 1, Ais, "fp32", Fd, rtol=1e-8)
+    S2, info2, _ = Q.qtt_solve_schedule(A, Ais, "fp32", Fd, rtol=1e-8, first=Ai, first_compute="bf16",
+                                        first_passes=1)
     print("schedule passes", [c[0] for c in info2], "split only", [c[0] for c in info0])
-    Sh = S2.cpu().numpy()
-    for c in range(3):
-        r = F[:, c] - O.qtt_apply_alg2(Ac, Sh[:, c])
-        assert np.linalg.norm(r) <= 1e-8 * np.linalg.norm(F[:, c]) * 1.0001
+    assert np.all(true_rel(S2) <= 1e-8 * 1.0001)
     # every pass within the first ones: qtt_solve with the first inverse
     S3, info3, _ = Q.qtt_solve(A, Ai, "bf16", Fd, rtol=1e-8)
-    S4, info4, _ = Q.qtt_solve_schedule(A, Ai, "bf16", 50, Ais, "fp32", Fd, rtol=1e-8)
+    S4, info4, _ = Q.qtt_solve_schedule(A, Ais, "fp32", Fd, rtol=1e-8, first=Ai, first_compute="bf16",
+                                        first_passes=50)
     assert np.array_equal(S3.cpu().numpy(), S4.cpu().numpy()) and info3 == info4
     # one handle holding both copies, plain FP32 arithmetic after the first pass
-    S5, info5, _ = Q.qtt_solve_schedule(A, Ai, "bf16", 1, Ai, "fp32", Fd, rtol=1e-8)
-    S5h = S5.cpu().numpy()
-    for c in range(3):
-        r = F[:, c] - O.qtt_apply_alg2(Ac, S5h[:, c])
-        assert np.linalg.norm(r) <= 1e-8 * np.linalg.norm(F[:, c]) * 1.0001
-    with pytest.raises(Q.QttError):
-        Q.qtt_solve_schedule(A, Ai, "bf16", -1, Ais, "fp32", Fd, rtol=1e-8)
-    for h in (A, Ai, Ais):
+    S5, _, _ = Q.qtt_solve_schedule(A, Ai, "fp32", Fd, rtol=1e-8, first=Ai, first_compute="bf16", first_passes=1)
+    assert np.all(true_rel(S5) <= 1e-8 * 1.0001)
+    # residual updates with A's split FP32 copy once every column is below 1e-5
+    sched = dict(first=Ai, first_compute="bf16", first_passes=1, A_lo=As, lo_compute="fp32")
+    S6, info6, _ = Q.qtt_solve_schedule(A, Ais, "fp32", Fd, rtol=1e-8, lo_below=1e-5, **sched)
+    t6 = true_rel(S6)
+    print("updated residuals", [c for c in info6], "true", t6)
+    assert np.all(np.abs(t6 - np.array([c[1] for c in info6])) <= 1e-10)
+    assert np.all(t6 <= 1e-8 * 1.0001)
+    assert [c[0] for c in info6] == [c[0] for c in info2]
+    S7, info7, _ = Q.qtt_solve_schedule(A, Ais, "fp32", Fd, rtol=1e-8, lo_below=0.0, **sched)
+    assert np.array_equal(S7.cpu().numpy(), S2.cpu().numpy()) and info7 == info2
+    # the update from the first pass on: sigma_1 = Ainv F as qtt_solve's, and
+    # the computed residual within the split apply's error of the true one
+    S8, info8, _ = Q.qtt_solve_schedule(A, Ais, "fp32", Fd, rtol=1e-8, max_iter=1, lo_below=2.0, A_lo=As,
+                                        lo_compute="fp32", raise_on_fail=False)
+    S9, info9, _ = Q.qtt_solve(A, Ais, "fp32", Fd, rtol=1e-8, max_iter=1, raise_on_fail=False)
+    assert np.array_equal(S8.cpu().numpy(), S9.cpu().numpy())
+    assert np.all(np.abs(np.array([c[1] for c in info8]) - np.array([c[1] for c in info9])) <= 1e-4)
+    for bad in (dict(first_passes=-1, first=Ai, first_compute="bf16"), dict(first_passes=1),
+                dict(A_lo=As, lo_compute="fp32", lo_below=-1.0), dict(A_lo=As, lo_compute="bf16", lo_below=1e-5)):
+        with pytest.raises(Q.QttError):
+            Q.qtt_solve_schedule(A, Ais, "fp32", Fd, rtol=1e-8, ws=Q.workspace(1 << 30), **bad)
+    for h in (A, As, Ai, Ais):
         h.free()
 
 
@@ -471,7 +497,9 @@ def test_refine_L7_split_fp32_inverse(Q):
     columns, and one inverse apply is checked element by element against the
     oracle's apply of the same cores within the split's rounding bound.  The
     schedule with the inverse's BF16 copy in the first pass also takes three
-    passes."""
+    passes, with and without residual updates by A's split FP32 copy in the
+    late passes; every column's true residual (FP64 apply) is within 1e-10 of
+    the computed one and below the tolerance."""
     w = I.WORKLOADS["refine_L7"]
     Ac, Aic = I.perturbed_identity_pair(w["ranks"], [8] * 7, seed=w["core_seed"], eps=w["eps"])
     F = I.rhs(8 ** 7, w["K"], seed=w["rhs_seed"])
@@ -493,15 +521,28 @@ def test_refine_L7_split_fp32_inverse(Q):
     torch.cuda.synchronize()
     ref = O.qtt_apply_alg2(cores, F[:, :1])
     check_reduced(Y.cpu().numpy(), ref, cores, F[:, :1], "fp32s", "split inverse apply, L=7")
-    # the schedule with the BF16 copy of the same inverse in the first pass
-    Sig, info, st = Q.qtt_solve_schedule(A, Ai, "bf16", 1, Ais, "fp32", Q.to_block(F), rtol=w["rtol"])
-    print("schedule passes", [c[0] for c in info], "residuals", [c[1] for c in info])
-    assert [c[0] for c in info] == [3] * w["K"]
-    Sh = Sig.cpu().numpy()
-    for c in (0, w["K"] - 1):
-        r = F[:, c] - O.qtt_apply_alg2(Ac, Sh[:, c])
-        assert np.linalg.norm(r) <= 1e-8 * np.linalg.norm(F[:, c]) * 1.0001
-    for h in (A, Ai0, Ai, Ais):
+    # the schedule with the BF16 copy of the same inverse in the first pass,
+    # then also with the residual updated by A's split FP32 copy once every
+    # column is below 1e-5 (the benchmark's call)
+    As = Q.qtt_matrix_load(Ac, dtypes=("fp32",))
+    Q.qtt_use_split_products(As)
+    Fd = Q.to_block(F)
+    for lo in (None, As):
+        Sig, info, st = Q.qtt_solve_schedule(A, Ais, "fp32", Fd, rtol=w["rtol"], first=Ai, first_compute="bf16",
+                                             first_passes=1, A_lo=lo, lo_compute="fp32", lo_below=1e-5)
+        print("schedule passes", [c[0] for c in info], "residuals", [c[1] for c in info])
+        assert [c[0] for c in info] == [3] * w["K"]
+        # the true residual of every column, A applied in FP64 on the GPU
+        R = Fd - Q.qtt_apply(A, "fp64", Sig)
+        true = (torch.linalg.vector_norm(R, dim=0) / torch.linalg.vector_norm(Fd, dim=0)).cpu().numpy()
+        print("true residuals", true)
+        assert np.all(np.abs(true - np.array([c[1] for c in info])) <= 1e-10)
+        assert np.all(true <= 1e-8 * 1.0001)
+        Sh = Sig.cpu().numpy()
+        for c in (0, w["K"] - 1):
+            r = F[:, c] - O.qtt_apply_alg2(Ac, Sh[:, c])
+            assert np.linalg.norm(r) <= 1e-8 * np.linalg.norm(F[:, c]) * 1.0001
+    for h in (A, As, Ai0, Ai, Ais):
         h.free()
 
 
