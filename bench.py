@@ -345,6 +345,9 @@ def main():
         "passes": r0["passes"],
         "max_rel_residual": r0["max_rel_residual"],
         "max_rel_residual_true": r0["max_rel_residual_true"],
+        # the value stands only if every column of the reported solve meets
+        # rtol by its true residual (A applied in FP64 to the returned sigma)
+        "true_residual_meets_rtol": bool(r0["max_rel_residual_true"] <= rtol),
         "variants": {v: {k: (float(f"{x:.5g}") if isinstance(x, float) else x) for k, x in r.items()
                          if k not in ("kernels", "shapes")}
                      for v, r in results.items()},
