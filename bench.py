@@ -580,23 +580,30 @@ def batched_run(Q, torch):
 def serving_run(Q, torch, n_requests):
     """The serving workload: 12 resident operators (L in {5,6,7,8}, ranks 16-32),
     a seeded Poisson trace at 200 requests/s with 1-16 vectors each, a 200 GB
-    arena, three slots.  Run with the BF16 inverse (FP64 residuals) and with
-    the FP64 inverse (plain FP64), same operators and trace; then the BF16
-    server again at about 70% of its measured capacity (the knee)."""
+    arena, three slots.  Run with the BF16 inverse (FP64 residuals), with
+    the BF16 inverse and the late residual updates by an FP32 copy of A
+    (columns that start a pass below 1e-4 of their right-hand side), and
+    with the FP64 inverse (plain FP64), same operators and trace; then the
+    BF16 server again at about 70% of its measured capacity (the knee)."""
     from paper_1511_06029_amd import serving as SV
     torch.cuda.empty_cache()      # the arena takes 200 GB: return the earlier legs' cached blocks
     ops, descs = SV.serving_operators()
     out = {"operators": [{"L": d["L"], "r": d["ranks"][1]} for d in descs], "requests": n_requests,
            "slots": 3, "budget_gb": 200}
-    for inv in ("bf16", "fp64"):
-        srv = SV.SolveServer(ops, inv_dtype=inv, budget_bytes=200 * 10 ** 9, n_slots=3)
+    for key, inv, kw in (("bf16_inverse_200_per_s", "bf16", {}),
+                         ("bf16_inverse_fp32_residual_updates_200_per_s", "bf16",
+                          dict(residual_lo="fp32", lo_below=1e-4)),
+                         ("fp64_inverse_200_per_s", "fp64", {})):
+        srv = SV.SolveServer(ops, inv_dtype=inv, budget_bytes=200 * 10 ** 9, n_slots=3, **kw)
         st = SV.serving_trace(srv, descs, n_requests, 200.0, seed=51)
         srv.close()
         del srv
         torch.cuda.empty_cache()
-        out[f"{inv}_inverse_200_per_s"] = _round_stats(st)
+        out[key] = _round_stats(st)
     b, f = out["bf16_inverse_200_per_s"], out["fp64_inverse_200_per_s"]
     out["served_speedup_vs_plain_fp64"] = round(b["rhs_per_s"] / f["rhs_per_s"], 3)
+    out["served_speedup_with_residual_updates"] = round(
+        out["bf16_inverse_fp32_residual_updates_200_per_s"]["rhs_per_s"] / f["rhs_per_s"], 3)
     # knee: about 70% of the saturated BF16 capacity, in requests per second
     mean_k = 8.5
     rate = round(0.7 * b["rhs_per_s"] / mean_k, 2)

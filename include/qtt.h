@@ -241,11 +241,14 @@ qtt_status_t qtt_solve(qtt_matrix_t A, qtt_matrix_t Ainv, qtt_dtype_t inv_comput
  *       ones Ainv in inv_compute (first_passes = 0: inv_first is ignored and
  *       may be NULL).
  *   A_lo, lo_compute, lo_below
- *       a pass that starts with ||r_c|| <= lo_below ||F_c|| in every column
- *       still iterating keeps its correction dx = Ainv r apart and updates
- *       the residual as r -= A_lo dx (A_lo applied in lo_compute, the update
- *       fused into A_lo's last core and accumulated in FP64) instead of
- *       recomputing r = F - A sigma with A in FP64.  The computed residual
+ *       a column that starts a pass with ||r_c|| <= lo_below ||F_c|| keeps
+ *       its correction dx = Ainv r apart and updates its residual as
+ *       r -= A_lo dx (A_lo applied in lo_compute, the update fused into
+ *       A_lo's last core and accumulated in FP64) instead of recomputing
+ *       r = F - A sigma with A in FP64.  The choice is made per column, so a
+ *       column's arithmetic does not depend on the other columns of the
+ *       call (in a pass, the columns of each route form their own sweeps of
+ *       A or A_lo; the inverse sweep is shared).  The computed residual
  *       then differs from the true one by the error of A_lo's apply on dx,
  *       about u_lo ||A|| ||dx||, and ||dx|| is about ||Ainv|| lo_below ||F_c||:
  *       choose lo_below <= 0.01 rtol / u_lo (u_lo the relative error of one

@@ -1731,25 +1731,26 @@ static qtt_status_t solve_impl(qtt_matrix_t A, qtt_matrix_t Ainv, qtt_dtype_t in
     }
   }
   for (int it = 1; it <= max_iter && n_active > 0; ++it) {
-    // runs of consecutive active columns
+    // runs of consecutive active columns with the same residual route: a
+    // column that starts the pass at or below lo_below updates its residual
+    // with A_lo (decided per column, so a column's arithmetic does not
+    // depend on the other columns of the call)
+    auto lo_col = [&](int64_t c) { return A_lo != nullptr && rel[c] <= sc->lo_below; };
     std::vector<std::pair<int64_t, int64_t>> runs;
-    double worst = 0.0;
     for (int64_t c = 0; c < nrhs;) {
       if (!active[c]) { ++c; continue; }
       int64_t e = c;
-      while (e < nrhs && active[e]) { worst = std::max(worst, rel[e]); ++e; }
+      while (e < nrhs && active[e] && lo_col(e) == lo_col(c)) ++e;
       runs.push_back({c, e - c});
       c = e;
     }
     const bool use_first = it <= first_passes;
     const qtt_matrix_s* Ai = use_first ? sc->inv_first : Ainv;
     const int dtv = use_first ? dt1 : dti;
-    // residual update with A_lo when every active column starts below lo_below
-    const bool lo = A_lo && worst <= sc->lo_below;
-    std::vector<Block> bi, ba, bd;
+    std::vector<Block> bi, ba, bl, bd;
     for (auto& r : runs) {
       const int64_t c0 = r.first, w = r.second;
-      if (!lo) {
+      if (!lo_col(c0)) {
         // sigma += Ainv r  (first pass: sigma = Ainv F); r = F - A sigma,
         // the residual fused into A's last core
         if (it == 1) bi.push_back({F + c0 * ldf, Sigma + c0 * lds, nullptr, ldf, lds, 0, w});
@@ -1758,12 +1759,12 @@ static qtt_status_t solve_impl(qtt_matrix_t A, qtt_matrix_t Ainv, qtt_dtype_t in
       } else if (it == 1) {
         // sigma = dx = Ainv F; r = F - A_lo sigma
         bi.push_back({F + c0 * ldf, Sigma + c0 * lds, nullptr, ldf, lds, 0, w});
-        ba.push_back({Sigma + c0 * lds, R + c0 * N, F + c0 * ldf, lds, N, ldf, w});
+        bl.push_back({Sigma + c0 * lds, R + c0 * N, F + c0 * ldf, lds, N, ldf, w});
       } else {
         // dx = Ainv r; sigma += dx; r -= A_lo dx
         bi.push_back({R + c0 * N, D + c0 * N, nullptr, N, N, 0, w});
         bd.push_back({D + c0 * N, Sigma + c0 * lds, nullptr, N, lds, 0, w});
-        ba.push_back({D + c0 * N, R + c0 * N, R + c0 * N, N, N, N, w});
+        bl.push_back({D + c0 * N, R + c0 * N, R + c0 * N, N, N, N, w});
       }
     }
     s = run_blocks(Ai, dtv, bi, aws, aws_bytes, 1.0, st);
@@ -1772,8 +1773,12 @@ static qtt_status_t solve_impl(qtt_matrix_t A, qtt_matrix_t Ainv, qtt_dtype_t in
       s = add_cols(bd, N, st);
       if (s != QTT_OK) return s;
     }
-    s = lo ? run_blocks(A_lo, dtl, ba, aws, aws_bytes, -1.0, st) : run_blocks(A, dta, ba, aws, aws_bytes, -1.0, st);
+    s = run_blocks(A, dta, ba, aws, aws_bytes, -1.0, st);          // no-op without blocks
     if (s != QTT_OK) return s;
+    if (!bl.empty()) {
+      s = run_blocks(A_lo, dtl, bl, aws, aws_bytes, -1.0, st);
+      if (s != QTT_OK) return s;
+    }
     std::vector<const double*> rc;
     std::vector<int64_t> rld;
     std::vector<int64_t> idx;

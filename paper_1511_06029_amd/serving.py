@@ -130,21 +130,31 @@ class SolveServer:
     operators: {name: (A_cores, Ainv_cores)} host FP64 cores.
     budget_bytes: device memory the batches in flight may hold together
         (solve workspace + batch right-hand sides + solutions).
+    residual_lo, lo_below: with a dtype ("fp32"), each operator also keeps
+        a copy of A in it, and a request column that starts a refinement
+        pass at or below lo_below of its right-hand side's norm updates its
+        residual with that copy (r -= A_lo dx, qtt_solve_schedule) instead
+        of recomputing it in FP64; choose lo_below <= 0.01 rtol / u_lo.
     """
 
     def __init__(self, operators, inv_dtype="bf16", budget_bytes=200 * 10 ** 9, n_slots=3,
-                 rtol=1e-8, max_iter=50, max_batch_rhs=64, device="cuda"):
+                 rtol=1e-8, max_iter=50, max_batch_rhs=64, device="cuda", residual_lo=None, lo_below=0.0):
         self.inv_dtype = inv_dtype
+        self.residual_lo = residual_lo
+        self.lo_below = float(lo_below)
         self.budget = int(budget_bytes)
         self.rtol = rtol
         self.max_iter = max_iter
         self.max_batch_rhs = max_batch_rhs
         self.device = torch.device(device)
         self.ops = {}
+        self.lo = {}
         for name, (Ac, Aic) in operators.items():
             A = Q.qtt_matrix_load(Ac, dtypes=("fp64",))
             Ai = Q.qtt_matrix_load(Aic, dtypes=(inv_dtype,))
             self.ops[name] = (A, Ai)
+            if residual_lo is not None:
+                self.lo[name] = Q.qtt_matrix_load(Ac, dtypes=(residual_lo,))
         self.n_slots = n_slots
         self.arena = Arena(self.budget, self.device)
         self._lock = threading.Condition()
@@ -190,6 +200,8 @@ class SolveServer:
         for A, Ai in self.ops.values():
             A.free()
             Ai.free()
+        for A_lo in self.lo.values():
+            A_lo.free()
         self.arena = None            # the budget's device memory goes back to torch
 
     # ------------------------------------------------------------ scheduling
@@ -215,9 +227,14 @@ class SolveServer:
         """Bytes of one batch as carved from the arena (each part aligned)."""
         A, Ai = self.ops[op]
         al = Arena.ALIGN
-        ws = Q.qtt_solve_workspace_bytes(A, Ai, self.inv_dtype, k)
+        ws = Q.qtt_solve_schedule_workspace_bytes(A, Ai, self.inv_dtype, k, **self._schedule(op))
         blk = (A.rows * k * 8 + al - 1) // al * al
         return (ws + al - 1) // al * al + 2 * blk
+
+    def _schedule(self, op):
+        if self.residual_lo is None:
+            return {}
+        return dict(A_lo=self.lo[op], lo_compute=self.residual_lo, lo_below=self.lo_below)
 
     def _worker(self, slot):
         stream = torch.cuda.Stream(device=self.device)
@@ -258,7 +275,8 @@ class SolveServer:
         N = A.rows
         al = Arena.ALIGN
         off0, _ = region
-        ws_n = (Q.qtt_solve_workspace_bytes(A, Ai, self.inv_dtype, k) + al - 1) // al * al
+        ws_n = (Q.qtt_solve_schedule_workspace_bytes(A, Ai, self.inv_dtype, k, **self._schedule(op))
+                + al - 1) // al * al
         blk = (N * k * 8 + al - 1) // al * al
         ws = self.arena.bytes(off0, ws_n)
         Fb = self.arena.block(off0 + ws_n, N, k)
@@ -269,8 +287,8 @@ class SolveServer:
             for r in reqs:
                 Fb[:, c:c + r.k].copy_(r.F.reshape(N, r.k))
                 c += r.k
-        _, info, st = Q.qtt_solve(A, Ai, self.inv_dtype, Fb, Sb, rtol=self.rtol, max_iter=self.max_iter,
-                                  ws=ws, stream=stream, raise_on_fail=False)
+        _, info, st = Q.qtt_solve_schedule(A, Ai, self.inv_dtype, Fb, Sb, rtol=self.rtol, max_iter=self.max_iter,
+                                           ws=ws, stream=stream, raise_on_fail=False, **self._schedule(op))
         with torch.cuda.stream(stream):
             outs = []
             c = 0

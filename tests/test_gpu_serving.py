@@ -118,8 +118,14 @@ def _ops():
     return ops
 
 
-def test_server_alone_equals_mix(Q):
+@pytest.mark.parametrize("lo", [None, "fp32"])
+def test_server_alone_equals_mix(Q, lo):
+    """Every result of a mixed run is bitwise the same request served alone,
+    and the oracle's FP64 residual of each column is <= 1e-8; also with the
+    late residual updates by an FP32 copy of A (decided per column, so the
+    mix cannot change a column's route)."""
     from paper_1511_06029_amd.serving import Request, SolveServer
+    kw = dict(residual_lo=lo, lo_below=1e-4) if lo else {}
     ops = _ops()
     g = I.rng(5)
     spec = []
@@ -133,7 +139,7 @@ def test_server_alone_equals_mix(Q):
         return [Request(rid=i, op=op, F=Q.to_block(F)) for i, op, F in spec]
 
     # mixed: everything waiting at once, two slots
-    srv = SolveServer(ops, inv_dtype="bf16", budget_bytes=2 * 10 ** 9, n_slots=2)
+    srv = SolveServer(ops, inv_dtype="bf16", budget_bytes=2 * 10 ** 9, n_slots=2, **kw)
     mixed = make()
     torch.cuda.synchronize()
     stats = srv.run_trace(mixed, realtime=False)
@@ -141,7 +147,7 @@ def test_server_alone_equals_mix(Q):
     assert stats["all_converged"]
     assert stats["batches"] < len(mixed)          # requests were coalesced
     # alone: one slot, one request at a time
-    srv = SolveServer(ops, inv_dtype="bf16", budget_bytes=2 * 10 ** 9, n_slots=1)
+    srv = SolveServer(ops, inv_dtype="bf16", budget_bytes=2 * 10 ** 9, n_slots=1, **kw)
     for r in make():
         torch.cuda.synchronize()
         srv.run_trace([r], realtime=False)
