@@ -299,7 +299,7 @@ def main():
                        "launches": lo["launches"], "avg_launch_ms": round(lo["ms"] / lo["launches"], 4)}
 
     fg = None if args.no_fgmres else fgmres_run(Q, torch, A, inv_h[head][0], inv_h[head][1], F, K, N, rtol, args,
-                                                label="fp32s" if head in ("sched", "mixed") else head)
+                                                label=head, sched=schedule(head))
 
     nti = None if args.no_nti else nti_run(Q, torch, Ac, F, K, N)
     cmv = None if args.no_compressed else compressed_run(Q, torch, Ac)
@@ -429,21 +429,28 @@ def nti_run(Q, torch, Ac, F, K, N, reps=10):
     return out
 
 
-def fgmres_run(Q, torch, A, Ai, inv, F, K, N, rtol, args, max_iter=12, label=None):
+def fgmres_run(Q, torch, A, Ai, inv, F, K, N, rtol, args, max_iter=12, label=None, sched=None):
     """The same solve by flexible GMRES (the compressed inverse as right
     preconditioner, section 5.3's outer solver): RHS/s, steps, and the true
-    relative residual recomputed by an FP64 apply outside the timed region."""
-    ws = Q.workspace(Q.qtt_fgmres_workspace_bytes(A, Ai, inv, K, max_iter))
+    relative residual recomputed by an FP64 apply outside the timed region.
+    sched: the schedule of qtt_solve_fgmres_schedule (first steps'
+    preconditioner, w = A_lo z_j below lo_below), or None."""
+    sc = sched or {}
+    ws = Q.workspace(Q.qtt_fgmres_schedule_workspace_bytes(A, Ai, inv, K, max_iter, **sc))
     Sig = Q.empty_block(N, K)
     stream = torch.cuda.current_stream()
+
+    def solve():
+        return Q.qtt_solve_fgmres_schedule(A, Ai, inv, F, Sig, rtol=rtol, max_iter=max_iter, ws=ws, stream=stream,
+                                           **sc)
     for _ in range(max(args.warmup, 1)):
-        Q.qtt_solve_fgmres(A, Ai, inv, F, Sig, rtol=rtol, max_iter=max_iter, ws=ws, stream=stream)
+        solve()
     torch.cuda.synchronize()
     lat, info = [], None
     t0 = time.perf_counter()
     for _ in range(args.steps):
         s0 = time.perf_counter()
-        _, info, _ = Q.qtt_solve_fgmres(A, Ai, inv, F, Sig, rtol=rtol, max_iter=max_iter, ws=ws, stream=stream)
+        _, info, _ = solve()
         lat.append((time.perf_counter() - s0) * 1e3)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0

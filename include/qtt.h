@@ -318,6 +318,24 @@ qtt_status_t qtt_solve_fgmres(qtt_matrix_t A, qtt_matrix_t Ainv, qtt_dtype_t inv
                               double rtol, int32_t max_iter, void* ws, size_t ws_bytes,
                               void* stream, qtt_solve_col_t* info);
 
+/* qtt_solve_fgmres with a schedule (qtt_schedule_t).  Steps 1 ..
+ * first_passes are preconditioned with inv_first in first_compute (the
+ * flexible method allows a different preconditioner per step; needs Ainv),
+ * and a column whose residual estimate before a step is at or below
+ * lo_below forms that step's w = A_lo z_j (lo_compute) instead of A z_j in
+ * FP64, decided per column.  Step j's basis vector enters the solution with
+ * a weight about the residual before the step, so the true residual moves
+ * by about u_lo ||A|| times that residual: choose lo_below <= 0.01 rtol /
+ * u_lo.  info holds the residual estimates of the rotations.  sched = NULL
+ * is qtt_solve_fgmres. */
+qtt_status_t qtt_fgmres_schedule_workspace_bytes(qtt_matrix_t A, qtt_matrix_t Ainv, qtt_dtype_t inv_compute,
+                                                 const qtt_schedule_t* sched, int64_t nrhs, int32_t max_iter,
+                                                 size_t* bytes);
+qtt_status_t qtt_solve_fgmres_schedule(qtt_matrix_t A, qtt_matrix_t Ainv, qtt_dtype_t inv_compute,
+                                       const qtt_schedule_t* sched, int64_t nrhs, const double* F, int64_t ldf,
+                                       double* Sigma, int64_t lds, double rtol, int32_t max_iter, void* ws,
+                                       size_t ws_bytes, void* stream, qtt_solve_col_t* info);
+
 /* Compressed matrix-vector product (section 4.2): for vectors b given in
  * TT form, the cores of c = A b,
  *   c_k(alpha + rA_{k-1} beta, i, alpha' + rA_k beta')

@@ -1959,12 +1959,17 @@ extern "C" {
 static qtt_status_t fgmres_impl(qtt_matrix_t A, qtt_matrix_t Ainv, qtt_matrix_t Y, qtt_dtype_t inv_compute,
                                 int64_t nrhs, const double* F, int64_t ldf, double* Sigma, int64_t lds,
                                 double rtol, int32_t max_iter, void* ws, size_t ws_bytes, void* stream,
-                                qtt_solve_col_t* info) {
+                                qtt_solve_col_t* info, const qtt_schedule_t* sc = nullptr) {
   if (!valid_handle(A) || (Ainv && !valid_handle(Ainv)) || (Y && !valid_handle(Y)))
     return fail(QTT_ERR_INVALID_ARG, "null handle");
-  int dti = -1, dta;
+  int dti = -1, dta, dt1 = -1, dtl = -1;
   qtt_status_t s = check_dtype(A, QTT_FP64, &dta);
   if (s != QTT_OK) return s;
+  s = check_schedule(A, sc, &dt1, &dtl);
+  if (s != QTT_OK) return s;
+  if (sc && sc->first_passes > 0 && !Ainv)
+    return fail(QTT_ERR_INVALID_ARG, "first_passes > 0 needs a preconditioner");
+  const qtt_matrix_s* A_lo = sc ? sc->A_lo : nullptr;
   for (qtt_matrix_t P : {Ainv, Y}) {
     if (!P) continue;
     s = check_dtype(P, inv_compute, &dti);
@@ -1990,6 +1995,14 @@ static qtt_status_t fgmres_impl(qtt_matrix_t A, qtt_matrix_t Ainv, qtt_matrix_t 
   for (qtt_matrix_t P : {Ainv, Y}) {
     if (!P) continue;
     qtt_workspace_bytes(P, inv_compute, 1, &tmp);
+    need1 = std::max(need1, tmp);
+  }
+  if (sc && sc->first_passes > 0) {
+    qtt_workspace_bytes(sc->inv_first, sc->first_compute, 1, &tmp);
+    need1 = std::max(need1, tmp);
+  }
+  if (A_lo) {
+    qtt_workspace_bytes(sc->A_lo, sc->lo_compute, 1, &tmp);
     need1 = std::max(need1, tmp);
   }
   if (ws_bytes < extra + need1)
@@ -2036,6 +2049,7 @@ static qtt_status_t fgmres_impl(qtt_matrix_t A, qtt_matrix_t Ainv, qtt_matrix_t 
   if (s != QTT_OK) return s;
   std::vector<int64_t> act, zero;
   std::vector<double> relv(nrhs, 0.0);
+  std::vector<double> est(nrhs, 1.0);     // residual estimate before the next step (A_lo routing)
   int64_t first_bad = -1;   // columns whose F is not finite are skipped (Sigma not written)
   for (int64_t c = 0; c < nrhs; ++c) {
     if (info) { info[c].iters = 0; info[c].rel_residual = 0.0; }
@@ -2099,35 +2113,44 @@ static qtt_status_t fgmres_impl(qtt_matrix_t A, qtt_matrix_t Ainv, qtt_matrix_t 
   };
 
   for (int j = 0; j < M && !act.empty(); ++j) {
-    // z_j = Ainv v_j, w = A z_j (w is stored as v_{j+1})
+    // z_j = Ainv v_j, w = A z_j (w is stored as v_{j+1}); a column whose
+    // residual estimate is at or below the schedule's lo_below forms
+    // w = A_lo z_j (decided per column)
+    auto lo_col = [&](int64_t c) { return A_lo != nullptr && est[c] <= sc->lo_below; };
     std::vector<std::pair<int64_t, int64_t>> runs;
     for (size_t t = 0; t < act.size();) {
       size_t e = t + 1;
-      while (e < act.size() && act[e] == act[e - 1] + 1) ++e;
+      while (e < act.size() && act[e] == act[e - 1] + 1 && lo_col(act[e]) == lo_col(act[t])) ++e;
       runs.push_back({act[t], (int64_t)(e - t)});
       t = e;
     }
     double* Vj = V + j * bstride;
     double* Zj = Z + j * bstride;
     double* W = V + (j + 1) * bstride;
-    std::vector<Block> bi, ba, by;
+    std::vector<Block> bi, ba, bl, by;
     for (auto& r : runs) {
       // with a product preconditioner, Y v_j goes to the w slot first (A z_j
       // overwrites it afterwards)
       by.push_back({Vj + r.first * N, W + r.first * N, nullptr, N, N, 0, r.second});
       bi.push_back({(Y ? W : Vj) + r.first * N, Zj + r.first * N, nullptr, N, N, 0, r.second});
-      ba.push_back({Zj + r.first * N, W + r.first * N, nullptr, N, N, 0, r.second});
+      (lo_col(r.first) ? bl : ba).push_back({Zj + r.first * N, W + r.first * N, nullptr, N, N, 0, r.second});
     }
     if (Y) {
       s = run_blocks(Y, dti, by, aws, aws_bytes, 1.0, st);
       if (s != QTT_OK) return s;
     }
     if (pre) {
-      s = run_blocks(Ainv, dti, bi, aws, aws_bytes, 1.0, st);
+      const bool first = sc && j < sc->first_passes;
+      s = first ? run_blocks(sc->inv_first, dt1, bi, aws, aws_bytes, 1.0, st)
+                : run_blocks(Ainv, dti, bi, aws, aws_bytes, 1.0, st);
       if (s != QTT_OK) return s;
     }
-    s = run_blocks(A, dta, ba, aws, aws_bytes, 1.0, st);
+    s = run_blocks(A, dta, ba, aws, aws_bytes, 1.0, st);          // no-op without blocks
     if (s != QTT_OK) return s;
+    if (!bl.empty()) {
+      s = run_blocks(A_lo, dtl, bl, aws, aws_bytes, 1.0, st);
+      if (s != QTT_OK) return s;
+    }
     // classical Gram-Schmidt, twice: h = V^T w, w -= V h
     const int nb = j + 1;
     auto chs = chunk_columns(act);
@@ -2181,6 +2204,7 @@ static qtt_status_t fgmres_impl(qtt_matrix_t A, qtt_matrix_t Ainv, qtt_matrix_t 
         gc[j] = cc[j] * gc[j];
         const double rel = std::fabs(gc[j + 1]) / beta[c];
         relv[c] = rel;
+        est[c] = rel;
         if (info) { info[c].iters = j + 1; info[c].rel_residual = rel; }
         if (rel <= rtol || hn == 0.0 || j + 1 == M) done.push_back(c);
         else { keep.push_back(c); keep_scale.push_back(1.0 / hn); }
@@ -2219,6 +2243,44 @@ qtt_status_t qtt_solve_fgmres(qtt_matrix_t A, qtt_matrix_t Ainv, qtt_dtype_t inv
                               qtt_solve_col_t* info) {
   return fgmres_impl(A, Ainv, nullptr, inv_compute, nrhs, F, ldf, Sigma, lds, rtol, max_iter, ws, ws_bytes,
                      stream, info);
+}
+
+qtt_status_t qtt_fgmres_schedule_workspace_bytes(qtt_matrix_t A, qtt_matrix_t Ainv, qtt_dtype_t inv_compute,
+                                                 const qtt_schedule_t* sched, int64_t nrhs, int32_t max_iter,
+                                                 size_t* bytes) {
+  qtt_status_t s = qtt_fgmres_workspace_bytes(A, Ainv, inv_compute, nrhs, max_iter, bytes);
+  if (s != QTT_OK) return s;
+  int dt1, dtl;
+  s = check_schedule(A, sched, &dt1, &dtl);
+  if (s != QTT_OK) return s;
+  if (!sched) return QTT_OK;
+  const int64_t k = std::max<int64_t>(nrhs, 1);
+  size_t wa = 0, tmp = 0;
+  qtt_workspace_bytes(A, QTT_FP64, k, &wa);
+  size_t wmax = wa;
+  if (Ainv) {
+    qtt_workspace_bytes(Ainv, inv_compute, k, &tmp);
+    wmax = std::max(wmax, tmp);
+  }
+  size_t wsched = wmax;
+  if (sched->first_passes > 0) {
+    qtt_workspace_bytes(sched->inv_first, sched->first_compute, k, &tmp);
+    wsched = std::max(wsched, tmp);
+  }
+  if (sched->A_lo) {
+    qtt_workspace_bytes(sched->A_lo, sched->lo_compute, k, &tmp);
+    wsched = std::max(wsched, tmp);
+  }
+  *bytes += wsched - wmax;
+  return QTT_OK;
+}
+
+qtt_status_t qtt_solve_fgmres_schedule(qtt_matrix_t A, qtt_matrix_t Ainv, qtt_dtype_t inv_compute,
+                                       const qtt_schedule_t* sched, int64_t nrhs, const double* F, int64_t ldf,
+                                       double* Sigma, int64_t lds, double rtol, int32_t max_iter, void* ws,
+                                       size_t ws_bytes, void* stream, qtt_solve_col_t* info) {
+  return fgmres_impl(A, Ainv, nullptr, inv_compute, nrhs, F, ldf, Sigma, lds, rtol, max_iter, ws, ws_bytes,
+                     stream, info, sched);
 }
 
 qtt_status_t qtt_solve_fgmres_product(qtt_matrix_t A, qtt_matrix_t M, qtt_matrix_t Y, qtt_dtype_t inv_compute,

@@ -81,6 +81,9 @@ def _load():
         "qtt_solve_fgmres": [P, P, I32, I64, P, I64, P, I64, D, I32, P, SZ, P, ctypes.POINTER(_SolveCol)],
         "qtt_solve_fgmres_product": [P, P, P, I32, I64, P, I64, P, I64, D, I32, P, SZ, P,
                                      ctypes.POINTER(_SolveCol)],
+        "qtt_fgmres_schedule_workspace_bytes": [P, P, I32, ctypes.POINTER(_Schedule), I64, I32, ctypes.POINTER(SZ)],
+        "qtt_solve_fgmres_schedule": [P, P, I32, ctypes.POINTER(_Schedule), I64, P, I64, P, I64, D, I32, P, SZ, P,
+                                      ctypes.POINTER(_SolveCol)],
         "qtt_set_shape": [P, I32, I32, I32],
         "qtt_list_shapes": [I32, ctypes.POINTER(I32), I32, ctypes.POINTER(I32)],
         "qtt_tt_round": [I32, PI64, PI64, PP, D, I32, ctypes.c_uint64, PP, PI64, P],
@@ -109,7 +112,7 @@ _lib = _load()
 # Names the C ABI exports (include/qtt.h); the tests check each is present.
 EXPORTED = ["qtt_matrix_load", "qtt_matrix_free", "qtt_matrix_set_diagonals", "qtt_matrix_info", "qtt_workspace_bytes",
             "qtt_apply", "qtt_apply_batched", "qtt_apply_noalloc", "qtt_autotune", "qtt_solve_workspace_bytes",
-            "qtt_matvec_compressed", "qtt_solve", "qtt_solve_schedule", "qtt_solve_schedule_workspace_bytes", "qtt_fgmres_workspace_bytes", "qtt_solve_fgmres", "qtt_solve_fgmres_product", "qtt_status_string", "qtt_last_error", "qtt_set_shape", "qtt_list_shapes",
+            "qtt_matvec_compressed", "qtt_solve", "qtt_solve_schedule", "qtt_solve_schedule_workspace_bytes", "qtt_fgmres_workspace_bytes", "qtt_solve_fgmres", "qtt_solve_fgmres_product", "qtt_fgmres_schedule_workspace_bytes", "qtt_solve_fgmres_schedule", "qtt_status_string", "qtt_last_error", "qtt_set_shape", "qtt_list_shapes",
             "qtt_tt_round", "qtt_tt_compress", "qtt_matrix_cores", "qtt_matrix_shape", "qtt_invert_newton_schulz",
             "qtt_timing_enable",
             "qtt_timing_reset", "qtt_timing_read", "qtt_timing_read_shape"]
@@ -422,6 +425,43 @@ def qtt_solve_fgmres(A, Ainv, inv_compute, F, Sigma=None, rtol=1e-8, max_iter=30
     st = _lib.qtt_solve_fgmres(A.handle, Ainv.handle if Ainv is not None else None, _dtype(inv_compute), k,
                                fp, ldf, sp, lds, float(rtol), int(max_iter), ws.data_ptr(),
                                ws.numel() * ws.element_size(), _stream(stream), info)
+    if raise_on_fail:
+        _check(st)
+    else:
+        _check(st, allow=(QTT_ERR_NOT_CONVERGED, QTT_ERR_NONFINITE))
+    return Sigma, [(c.iters, c.rel_residual) for c in info], st
+
+
+def qtt_fgmres_schedule_workspace_bytes(A, Ainv, inv_compute, nrhs, max_iter, first=None, first_compute=None,
+                                        first_passes=0, A_lo=None, lo_compute=None, lo_below=0.0):
+    n = ctypes.c_size_t()
+    sc = _schedule(first, first_compute, first_passes, A_lo, lo_compute, lo_below)
+    _check(_lib.qtt_fgmres_schedule_workspace_bytes(A.handle, Ainv.handle if Ainv is not None else None,
+                                                    _dtype(inv_compute), ctypes.byref(sc), int(nrhs),
+                                                    int(max_iter), ctypes.byref(n)))
+    return n.value
+
+
+@_on_stream
+def qtt_solve_fgmres_schedule(A, Ainv, inv_compute, F, Sigma=None, rtol=1e-8, max_iter=30, ws=None, stream=None,
+                              first=None, first_compute=None, first_passes=0, A_lo=None, lo_compute=None,
+                              lo_below=0.0, raise_on_fail=True):
+    """qtt_solve_fgmres with a schedule: steps 1 .. first_passes
+    preconditioned with `first` (first_compute), and w = A_lo z_j (lo_compute)
+    for a column whose residual estimate before the step is <= lo_below.
+    Returns (Sigma, info, status) as qtt_solve_fgmres."""
+    fp, n, k, ldf = _col_major(F, "F")
+    if Sigma is None:
+        Sigma = empty_block(n, k, F.device) if F.dim() == 2 else torch.empty(n, dtype=torch.float64, device=F.device)
+    sp, _, _, lds = _col_major(Sigma, "Sigma")
+    sc = _schedule(first, first_compute, first_passes, A_lo, lo_compute, lo_below)
+    if ws is None:
+        ws = workspace(qtt_fgmres_schedule_workspace_bytes(A, Ainv, inv_compute, k, max_iter, first, first_compute,
+                                                           first_passes, A_lo, lo_compute, lo_below), F.device)
+    info = (_SolveCol * k)()
+    st = _lib.qtt_solve_fgmres_schedule(A.handle, Ainv.handle if Ainv is not None else None, _dtype(inv_compute),
+                                        ctypes.byref(sc), k, fp, ldf, sp, lds, float(rtol), int(max_iter),
+                                        ws.data_ptr(), ws.numel() * ws.element_size(), _stream(stream), info)
     if raise_on_fail:
         _check(st)
     else:

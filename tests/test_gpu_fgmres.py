@@ -221,3 +221,40 @@ def test_fgmres_product_preconditioner(Q, inv):
     assert st == 1
     for h in (A, M, Y):
         h.free()
+
+
+def test_fgmres_schedule(Q):
+    """qtt_solve_fgmres_schedule: with no schedule, or with A_lo but
+    lo_below = 0, it is qtt_solve_fgmres (same bits).  With the BF16 inverse
+    preconditioning the first step, the split FP32 one after it, and
+    w = A_lo z_j by A's split FP32 copy once a column's estimate is below
+    1e-5: the oracle's residual of every column is below 1e-8 and within
+    1e-10 of the estimate.  first_passes without a preconditioner is
+    rejected."""
+    Ac, Aic = I.perturbed_identity_pair([1, 8, 16, 16, 8, 1], [8] * 5, seed=97)
+    F = I.rhs(8 ** 5, 3, seed=98)
+    A = Q.qtt_matrix_load(Ac, dtypes=("fp64",))
+    As = Q.qtt_matrix_load(Ac, dtypes=("fp32",))
+    Q.qtt_use_split_products(As)
+    Ai = Q.qtt_matrix_load(Aic, dtypes=("bf16",))
+    Ais = Q.qtt_matrix_load(Aic, dtypes=("fp32",))
+    Q.qtt_use_split_products(Ais)
+    Fd = Q.to_block(F)
+    S0, info0, _ = Q.qtt_solve_fgmres(A, Ais, "fp32", Fd, rtol=1e-8)
+    S1, info1, _ = Q.qtt_solve_fgmres_schedule(A, Ais, "fp32", Fd, rtol=1e-8)
+    assert np.array_equal(S0.cpu().numpy(), S1.cpu().numpy()) and info0 == info1
+    S2, info2, _ = Q.qtt_solve_fgmres_schedule(A, Ais, "fp32", Fd, rtol=1e-8, A_lo=As, lo_compute="fp32",
+                                               lo_below=0.0)
+    assert np.array_equal(S0.cpu().numpy(), S2.cpu().numpy()) and info0 == info2
+    S3, info3, _ = Q.qtt_solve_fgmres_schedule(A, Ais, "fp32", Fd, rtol=1e-8, first=Ai, first_compute="bf16",
+                                               first_passes=1, A_lo=As, lo_compute="fp32", lo_below=1e-5)
+    t3 = np.array(true_rel(Ac, F, S3.cpu().numpy()))
+    print("fgmres schedule steps", [c[0] for c in info3], "plain", [c[0] for c in info0], "true", t3,
+          "estimates", [c[1] for c in info3])
+    assert np.all(t3 <= 1e-8 * 1.0001)
+    assert np.all(np.abs(t3 - np.array([c[1] for c in info3])) <= 1e-10)
+    with pytest.raises(Q.QttError):
+        Q.qtt_solve_fgmres_schedule(A, None, "fp32", Fd, rtol=1e-8, first=Ai, first_compute="bf16",
+                                    first_passes=1)
+    for h in (A, As, Ai, Ais):
+        h.free()
