@@ -321,6 +321,31 @@ def test_nonfinite_rhs_reported(Q, inv):
     Ai.free()
 
 
+def test_nonfinite_rhs_reported_scheduled(Q):
+    """The scheduled solvers (BF16 inverse in the first pass or step, FP32
+    after it, late residual updates by an FP32 copy of A) report a NaN or an
+    infinity in one column as QTT_ERR_NONFINITE and still solve the finite
+    columns to the tolerance (the oracle recomputes their residuals)."""
+    Ac, Aic = I.perturbed_identity_pair([1, 6, 8, 6, 1], [8] * 4, seed=95)
+    A = Q.qtt_matrix_load(Ac, dtypes=("fp64",))
+    Alo = Q.qtt_matrix_load(Ac, dtypes=("fp32",))
+    Ai = Q.qtt_matrix_load(Aic, dtypes=("fp32", "bf16"))
+    sched = dict(first=Ai, first_compute="bf16", first_passes=1, A_lo=Alo, lo_compute="fp32", lo_below=1e-4)
+    for bad in (np.nan, np.inf):
+        F = I.rhs(4096, 3, seed=96)
+        F[17, 1] = bad
+        for solve in (Q.qtt_solve_schedule, Q.qtt_solve_fgmres_schedule):
+            Sig, info, st = solve(A, Ai, "fp32", Q.to_block(F), rtol=1e-8, raise_on_fail=False, **sched)
+            assert st == 6, (bad, st, solve.__name__)
+            assert not np.isfinite(info[1][1])
+            S = Sig.cpu().numpy()
+            for c in (0, 2):
+                res = F[:, c] - O.qtt_apply_alg2(Ac, S[:, c])
+                assert np.linalg.norm(res) <= 1e-8 * np.linalg.norm(F[:, c]) * 1.0001, (bad, c, solve.__name__)
+    for h in (A, Alo, Ai):
+        h.free()
+
+
 @pytest.mark.parametrize("dtype", ["fp64", "fp32", "bf16"])
 def test_every_kernel_configuration(Q, dtype):
     """Pin each kernel configuration on every core in turn (a configuration
